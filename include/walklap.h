@@ -1,0 +1,214 @@
+/*
+ * walklap.h -- C ABI of the MI355X walk-Laplacian library.
+ *
+ * The library evaluates, on one GPU, matrix functions of the walk generating
+ * functions of Arrigo & Durastante, "Walk based Laplacians for modeling
+ * diffusion on complex networks" (arXiv 2601.11338):
+ *
+ *   phi(A, c) = sum_k c_k q_k(A)                       (Sec. 3.2, Prop. "whe-we-converge")
+ *   q_0 = I, q_1 = A, q_2 = A^2 - mu D,
+ *   q_{k+1} = A q_k + mu (mu I - D) q_{k-1}            (eq. qrec; mu = 0: all walks,
+ *                                                        mu = 1: nonbacktracking, eq. Br)
+ *   w = phi 1              (walk degree / total communicability, Sec. 3.1)
+ *   L = diag(w) - phi      (eq. f-laplacian, eq. weighted_laplacian)
+ *   exp(-t L) U0           (diffusion, eq. diffusion_on_G_with_downweighted_walk)
+ *   diag / trace estimates (Sec. 4.4, Alg. 1)
+ *
+ * with weights c_k = alpha^k (resolvent) or beta^k / k! (exponential), c_0 = 1.
+ *
+ * Conventions for every entry point:
+ *  - Returns a wl_status; WL_OK = 0.  On failure a message is available from
+ *    wl_last_error() (thread-local, valid until the next call on the thread).
+ *    Arguments are validated before anything is enqueued; on a validation
+ *    error nothing has been launched and no output has been written.
+ *  - Pointers named d_* are DEVICE pointers on the context's device, owned by
+ *    the caller, and must stay valid until the call returns (calls that return
+ *    host scalars synchronise the context stream; the others are enqueued on
+ *    it and complete in stream order).  Pointers without d_ are host memory.
+ *  - Dense blocks are ROW-MAJOR n x b (the b values of one node contiguous),
+ *    element type given by the precision of the object (float for WL_FP32,
+ *    double for WL_FP64), base address 16-byte aligned.
+ *  - Handles are created and destroyed by the library; destroying a context
+ *    does not destroy graphs or operators made from it (destroy those first).
+ *  - Workspace (Krylov bases, recurrence buffers, reduction partials) is
+ *    allocated by the library on the device and kept in the operator or graph
+ *    for reuse; WL_ENOMEM if it cannot be allocated.
+ */
+#ifndef WALKLAP_H
+#define WALKLAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WL_OK = 0,
+  WL_EINVAL = 1,        /* invalid argument (null pointer, bad size, malformed graph) */
+  WL_ERANGE = 2,        /* parameter outside the convergence region (alpha * rho(Z_mu) >= 1),
+                           or a size beyond the supported range (nnz >= 2^31) */
+  WL_ENOMEM = 3,        /* device allocation failed */
+  WL_EDEVICE = 4,       /* HIP runtime error, or no usable device */
+  WL_ENOTSPD = 5,       /* an operator that must be positive definite is not */
+  WL_ENOCONV = 6,       /* an iteration did not reach its tolerance */
+  WL_ENUMERIC = 7,      /* NaN or Inf in a result */
+  WL_EUNSUPPORTED = 8,  /* valid request this build does not handle */
+  WL_EINTERNAL = 9
+} wl_status;
+
+typedef enum { WL_F_RESOLVENT = 0, WL_F_EXP = 1 } wl_func;
+typedef enum { WL_FP32 = 4, WL_FP64 = 8 } wl_prec;
+typedef enum {
+  WL_M_AUTO = 0,        /* exponential: recurrence; resolvent: block Lanczos on A_mu */
+  WL_M_RECURRENCE = 1,  /* truncated series by the fused three-term recurrence (exponential) */
+  WL_M_LANCZOS = 2      /* block Lanczos (mu = 0: on A; resolvent: on A_mu(alpha)) */
+} wl_method;
+typedef enum { WL_PROBE_GAUSS = 0, WL_PROBE_RADEMACHER = 1 } wl_probe_law;
+typedef enum { WL_EST_HUTCHINSON = 0, WL_EST_BKS = 1, WL_EST_XNYS = 2 } wl_estimator;
+
+/* Graph flags */
+#define WL_GRAPH_COPY 1u      /* library copies the CSR arrays (else it borrows them) */
+#define WL_GRAPH_VALIDATE 2u  /* check sortedness, range, loops, duplicates, symmetry on device */
+
+typedef struct wl_ctx wl_ctx;
+typedef struct wl_graph wl_graph;
+typedef struct wl_op wl_op;
+typedef struct wl_mlp wl_mlp;
+
+/* Operator description.
+ *   mu          backtrack downweighting in [0, 1]; each backtracking step of a walk is
+ *               weighted by theta = 1 - mu (Sec. 3.2).  mu = 0 all walks, mu = 1 NBT.
+ *   func        WL_F_RESOLVENT (c_k = param^k) or WL_F_EXP (c_k = param^k / k!).
+ *   param       alpha (resolvent; must satisfy alpha * rho(Z_mu) < 1, Prop. "whe-we-converge"
+ *               and its remark) or beta (exponential; inverse temperature, Sec. 4.1.2).
+ *   prec        WL_FP32 or WL_FP64: element type of vectors; all Krylov / recurrence
+ *               coefficients and inner products are accumulated in double.
+ *   krylov_dim  recurrence degree (exponential) or number of block Lanczos steps;
+ *               0 = choose from tol.
+ *   tol         relative accuracy target used when krylov_dim = 0 (tail bound of the
+ *               series, or Lanczos a-posteriori estimate).
+ *   method      wl_method.
+ *   reorth      0: three-term recurrence only; 1: second local Gram-Schmidt pass
+ *               against the two previous blocks; 2: full reorthogonalisation.
+ *   rho_hint    if > 0, rho(Z_mu) supplied by the caller (skips its computation);
+ *               used to validate alpha.                                               */
+typedef struct wl_op_desc {
+  double mu;
+  int32_t func;
+  double param;
+  int32_t prec;
+  int32_t krylov_dim;
+  double tol;
+  int32_t method;
+  int32_t reorth;
+  double rho_hint;
+} wl_op_desc;
+
+/* ---------------------------------------------------------------- errors / version */
+const char* wl_last_error(void);
+const char* wl_status_string(wl_status s);
+int32_t wl_version(void);
+
+/* ---------------------------------------------------------------- context
+ * device: HIP device ordinal.  stream: a hipStream_t to enqueue on (NULL = the null
+ * stream).  The context never destroys a caller's stream.                          */
+wl_status wl_ctx_create(int32_t device, void* stream, wl_ctx** out);
+wl_status wl_ctx_set_stream(wl_ctx* ctx, void* stream);
+wl_status wl_ctx_synchronize(wl_ctx* ctx);
+wl_status wl_ctx_destroy(wl_ctx* ctx);
+
+/* ---------------------------------------------------------------- graph (Sec. 2)
+ * A simple undirected unweighted graph as symmetric CSR: d_rowptr (n+1 int32),
+ * d_colidx (nnz int32), columns strictly increasing within a row, no self loops,
+ * every edge stored in both directions (Definition "adjacency"; simple graphs,
+ * Sec. 2).  nnz must be < 2^31 (WL_ERANGE).  With WL_GRAPH_VALIDATE the structure
+ * is checked on the device (WL_EINVAL with the first violation).  Degrees
+ * d = A 1 are computed on the device.  The row split used by the SpMM kernels
+ * (rows above a degree threshold handled by whole workgroups) is built here.    */
+wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_rowptr,
+                          const int32_t* d_colidx, uint32_t flags, wl_graph** out);
+wl_status wl_graph_info(const wl_graph* g, int64_t* n, int64_t* nnz, int32_t* max_degree);
+wl_status wl_graph_destroy(wl_graph* g);
+
+/* Y = A X for a row-major n x b block (b >= 1), element type by prec.  The raw
+ * sparse product every Krylov step is built on (Sec. 4.1).                     */
+wl_status wl_spmm(wl_graph* g, int32_t prec, const void* d_X, void* d_Y, int32_t b);
+
+/* Choose the SpMM launch shape (lanes per row, long-row threshold) for (prec, b)
+ * by timing candidates on this graph; the choice is kept in the graph.  Without
+ * it a heuristic from the mean degree is used.  Enqueues and synchronises.     */
+wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b);
+
+/* Largest adjacency eigenvalue lambda_max(A) = rho(A) by Lanczos (double).  Used
+ * for beta ~ 1/rho(A) (Sec. 4.1.2).  tol: relative.                              */
+wl_status wl_lambda_max(wl_graph* g, double tol, double* out);
+
+/* rho(Z_mu) of the 2n x 2n linearisation Z = [[O, I], [mu (mu I - D), A]]
+ * (eq. Zdef).  mu = 0 returns lambda_max(A).  For mu > 0 it is the reciprocal of
+ * the smallest t > 0 at which A_mu(t) = (1 - mu^2 t^2) I - t A + t^2 mu D becomes
+ * singular; located by bracketing + bisection on the smallest Lanczos Ritz value
+ * of A_mu(t).  tol: relative.                                                     */
+wl_status wl_spectral_radius(wl_graph* g, double mu, double tol, double* rho);
+
+/* ---------------------------------------------------------------- operator */
+wl_status wl_op_create(wl_graph* g, const wl_op_desc* desc, wl_op** out);
+wl_status wl_op_destroy(wl_op* op);
+
+/* w = phi 1 (n values): total communicability t(f) (Sec. 3.1) and the diagonal of
+ * the walk Laplacian's degree part (eq. weighted_laplacian).  Includes c_0 = 1.
+ * Cached in the operator after the first call.                                   */
+wl_status wl_fdeg(wl_op* op, void* d_w);
+
+/* Y = phi X (n x b).                                                              */
+wl_status wl_apply_phi(wl_op* op, const void* d_X, void* d_Y, int32_t b);
+
+/* Y = L X = w * X - phi X (eq. f-laplacian / eq. weighted_laplacian), never
+ * forming L (Sec. 4.1).                                                           */
+wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b);
+
+/* Y_i = exp(-t_i L) U0 for i < nt (eq. diffusion_on_G_with_downweighted_walk; L is
+ * symmetric so the row-vector form is the transpose).  One block Lanczos basis of
+ * dimension outer_dim on L serves every t_i (as the parfor of Alg. 1 shares one
+ * basis).  d_Y: host array of nt device pointers, each n x b.  err_est (host, nt,
+ * may be NULL): a-posteriori estimate || B_K E_K^T exp(-t T) E_1 R_0 ||_F.        */
+wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt,
+                  void* const* d_Y, int32_t outer_dim, double* err_est);
+
+/* ---------------------------------------------------------------- probes
+ * Fill an n x M row-major block with Philox4x32-10 probes (Salmon et al., SC'11):
+ * element (i, j) is word e mod 4 of Philox(counter (q lo, q hi, stream, 0),
+ * key (seed lo, seed hi)), e = i*M + j, q = e div 4.  Rademacher 1 - 2 (word>>31);
+ * Gaussian by Box-Muller on word pairs (0,1), (2,3), u = (word + 1/2) 2^-32,
+ * evaluated in double.  These are the "iid isotropic" probes of Alg. 1.          */
+wl_status wl_probes(wl_ctx* ctx, int32_t prec, int32_t law, uint64_t seed, uint32_t stream,
+                    int64_t n, int32_t M, void* d_out);
+
+/* ---------------------------------------------------------------- estimators (Sec. 4.4)
+ * Given the probe block Omega (n x M) and Y = F Omega for a symmetric F:
+ *   WL_EST_HUTCHINSON  d_i = (1/M) sum_j Omega_ij Y_ij
+ *   WL_EST_BKS         d_i = sum_j Omega_ij Y_ij / sum_j Omega_ij^2
+ *   WL_EST_XNYS        leave-one-out Nystrom estimator: for each j the Nystrom
+ *                      approximation from the other probes, corrected by probe j,
+ *                      averaged over j (F must be positive semidefinite).
+ * d_diag (n, prec) receives the diagonal estimate; trace / trace_err (host, may be
+ * NULL) the trace estimate and its error estimate (std over j / sqrt M; for the
+ * Hutchinson/BKS laws the same statistic of the per-probe traces).  rcond: the
+ * Nystrom core pseudo-inverse drops eigenvalues below rcond * largest.
+ * d_cv (n, prec, may be NULL): control variate g for the diagonal:
+ *   d_i = g_i + (1/M) sum_j Omega_ij (Y_ij - g_i Omega_ij)   (Hutchinson only).   */
+wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, int32_t M,
+                      const void* d_Omega, const void* d_Y, const void* d_cv, double rcond,
+                      void* d_diag, double* trace, double* trace_err);
+
+/* Convenience: diag phi (target 0) or diag exp(-t L) (target 1) estimated from M
+ * probes drawn by wl_probes(seed, law).  d_diag n values.                         */
+wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t seed,
+                      int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
+                      void* d_diag, double* trace, double* trace_err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WALKLAP_H */

@@ -1,0 +1,245 @@
+"""MI355X walk-based Laplacians: Python binding of libwalklap.so.
+
+Every computation runs in the HIP library; this module only marshals pointers
+and sizes.  torch supplies device memory and the stream (the library enqueues
+on ``torch.cuda.current_stream()`` of the context's device).  There is no CPU
+fallback: if the library is missing or no GPU is present, calls raise.
+"""
+
+import ctypes as C
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    WL_EST_BKS,
+    WL_EST_HUTCHINSON,
+    WL_EST_XNYS,
+    WL_F_EXP,
+    WL_F_RESOLVENT,
+    WL_FP32,
+    WL_FP64,
+    WL_M_AUTO,
+    WL_M_LANCZOS,
+    WL_M_RECURRENCE,
+    WL_PROBE_GAUSS,
+    WL_PROBE_RADEMACHER,
+    WLError,
+    check,
+    load,
+)
+
+FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP}
+METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS}
+ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS}
+LAWS = {"gauss": WL_PROBE_GAUSS, "gaussian": WL_PROBE_GAUSS, "rademacher": WL_PROBE_RADEMACHER}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _prec_of(dtype):
+    torch = _torch()
+    if dtype == torch.float32:
+        return WL_FP32
+    if dtype == torch.float64:
+        return WL_FP64
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _dtype_of(prec):
+    torch = _torch()
+    return torch.float32 if prec == WL_FP32 else torch.float64
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+class Context:
+    """A device and the stream the library enqueues on."""
+
+    def __init__(self, device=0, stream=None):
+        torch = _torch()
+        lib = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.handle = C.c_void_p()
+        check(lib.wl_ctx_create(device, C.c_void_p(stream), C.byref(self.handle)))
+
+    def synchronize(self):
+        check(load().wl_ctx_synchronize(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_ctx_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_device(self):
+        return _torch().device("cuda", self.device)
+
+
+class Graph:
+    """Symmetric unweighted CSR graph resident on the device (int32 rowptr / colidx)."""
+
+    def __init__(self, ctx, rowptr, colidx, n=None, copy=False, validate=False):
+        torch = _torch()
+        dev = ctx.torch_device
+        self.ctx = ctx
+        self.rowptr = torch.as_tensor(rowptr).to(device=dev, dtype=torch.int32).contiguous()
+        self.colidx = torch.as_tensor(colidx).to(device=dev, dtype=torch.int32).contiguous()
+        self.n = int(self.rowptr.numel() - 1) if n is None else int(n)
+        self.nnz = int(self.colidx.numel())
+        flags = (_lib.WL_GRAPH_COPY if copy else 0) | (_lib.WL_GRAPH_VALIDATE if validate else 0)
+        self.handle = C.c_void_p()
+        check(load().wl_graph_create(ctx.handle, self.n, self.nnz, _ptr(self.rowptr), _ptr(self.colidx), flags,
+                                     C.byref(self.handle)))
+        if copy:
+            self.rowptr = self.colidx = None
+
+    def info(self):
+        n, nnz, md = C.c_int64(), C.c_int64(), C.c_int32()
+        check(load().wl_graph_info(self.handle, C.byref(n), C.byref(nnz), C.byref(md)))
+        return n.value, nnz.value, md.value
+
+    def spmm(self, X, Y=None):
+        torch = _torch()
+        X = X.contiguous()
+        b = X.shape[1] if X.dim() == 2 else 1
+        if Y is None:
+            Y = torch.empty_like(X)
+        check(load().wl_spmm(self.handle, _prec_of(X.dtype), _ptr(X), _ptr(Y), b))
+        return Y
+
+    def autotune(self, dtype, b):
+        check(load().wl_autotune(self.handle, _prec_of(dtype), b))
+
+    def lambda_max(self, tol=1e-12):
+        out = C.c_double()
+        check(load().wl_lambda_max(self.handle, tol, C.byref(out)))
+        return out.value
+
+    def spectral_radius(self, mu, tol=1e-10):
+        out = C.c_double()
+        check(load().wl_spectral_radius(self.handle, float(mu), tol, C.byref(out)))
+        return out.value
+
+    def features(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n, 8), dtype=torch.float32, device=self.ctx.torch_device)
+        check(load().wl_features(self.handle, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """phi(A, c) and its walk Laplacian for one (mu, f, parameter) choice."""
+
+    def __init__(self, graph, mu, func, param, dtype=None, krylov_dim=0, tol=0.0, method="auto", reorth=1,
+                 rho_hint=0.0):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        self.graph = graph
+        self.dtype = dtype
+        d = _lib.OpDesc(mu=float(mu), func=FUNCS[func] if isinstance(func, str) else int(func), param=float(param),
+                        prec=_prec_of(dtype), krylov_dim=int(krylov_dim), tol=float(tol),
+                        method=METHODS[method] if isinstance(method, str) else int(method), reorth=int(reorth),
+                        rho_hint=float(rho_hint))
+        self.desc = d
+        self.handle = C.c_void_p()
+        check(load().wl_op_create(graph.handle, C.byref(d), C.byref(self.handle)))
+
+    def _empty(self, *shape):
+        return _torch().empty(shape, dtype=self.dtype, device=self.graph.ctx.torch_device)
+
+    def fdeg(self, out=None):
+        out = self._empty(self.graph.n) if out is None else out
+        check(load().wl_fdeg(self.handle, _ptr(out)))
+        return out
+
+    def _block(self, X):
+        X = X.to(self.dtype).contiguous()
+        if X.dim() == 1:
+            X = X.view(-1, 1)
+        return X
+
+    def apply_phi(self, X, out=None):
+        X = self._block(X)
+        out = _torch().empty_like(X) if out is None else out
+        check(load().wl_apply_phi(self.handle, _ptr(X), _ptr(out), X.shape[1]))
+        return out
+
+    def apply_L(self, X, out=None):
+        X = self._block(X)
+        out = _torch().empty_like(X) if out is None else out
+        check(load().wl_apply_L(self.handle, _ptr(X), _ptr(out), X.shape[1]))
+        return out
+
+    def expv(self, U0, ts, outer_dim=30, outs=None):
+        U0 = self._block(U0)
+        ts = [float(t) for t in ts]
+        torch = _torch()
+        outs = [torch.empty_like(U0) for _ in ts] if outs is None else outs
+        tarr = (C.c_double * len(ts))(*ts)
+        parr = (C.c_void_p * len(ts))(*[o.data_ptr() for o in outs])
+        err = (C.c_double * len(ts))()
+        check(load().wl_expv(self.handle, _ptr(U0), U0.shape[1], tarr, len(ts), parr, int(outer_dim), err))
+        return outs, list(err)
+
+    def diag_est(self, M, seed, target="phi", t=0.0, law="gauss", estimator="hutchinson", cv=None, outer_dim=30):
+        out = self._empty(self.graph.n)
+        tr, te = C.c_double(), C.c_double()
+        check(load().wl_diag_est(self.handle, 0 if target == "phi" else 1, float(t), int(M), int(seed), LAWS[law],
+                                 ESTIMATORS[estimator], _ptr(cv), int(outer_dim), _ptr(out), C.byref(tr),
+                                 C.byref(te)))
+        return out, tr.value, te.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_op_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probes(ctx, n, M, seed, law="gauss", dtype=None, stream=0):
+    torch = _torch()
+    dtype = dtype or torch.float32
+    out = torch.empty((n, M), dtype=dtype, device=ctx.torch_device)
+    check(load().wl_probes(ctx.handle, _prec_of(dtype), LAWS[law], int(seed), int(stream), n, M, _ptr(out)))
+    return out
+
+
+def estimate(ctx, Omega, Y, estimator="hutchinson", cv=None, rcond=1e-10, want_diag=True):
+    torch = _torch()
+    Omega = Omega.contiguous()
+    Y = Y.contiguous()
+    n, M = Omega.shape
+    diag = torch.empty(n, dtype=Omega.dtype, device=Omega.device) if want_diag else None
+    tr, te = C.c_double(), C.c_double()
+    check(load().wl_estimate(ctx.handle, _prec_of(Omega.dtype), ESTIMATORS[estimator], n, M, _ptr(Omega), _ptr(Y),
+                             _ptr(cv), float(rcond), _ptr(diag), C.byref(tr), C.byref(te)))
+    return diag, tr.value, te.value

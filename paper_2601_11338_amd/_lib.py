@@ -1,0 +1,104 @@
+"""ctypes declarations for libwalklap.so (include/walklap.h).  Marshalling only."""
+
+import ctypes as C
+import os
+
+LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwalklap.so")
+
+WL_OK, WL_EINVAL, WL_ERANGE, WL_ENOMEM, WL_EDEVICE, WL_ENOTSPD, WL_ENOCONV, WL_ENUMERIC, WL_EUNSUPPORTED = range(9)
+WL_F_RESOLVENT, WL_F_EXP = 0, 1
+WL_FP32, WL_FP64 = 4, 8
+WL_M_AUTO, WL_M_RECURRENCE, WL_M_LANCZOS = 0, 1, 2
+WL_PROBE_GAUSS, WL_PROBE_RADEMACHER = 0, 1
+WL_EST_HUTCHINSON, WL_EST_BKS, WL_EST_XNYS = 0, 1, 2
+WL_GRAPH_COPY, WL_GRAPH_VALIDATE = 1, 2
+
+STATUS_NAMES = {
+    WL_OK: "WL_OK", WL_EINVAL: "WL_EINVAL", WL_ERANGE: "WL_ERANGE", WL_ENOMEM: "WL_ENOMEM",
+    WL_EDEVICE: "WL_EDEVICE", WL_ENOTSPD: "WL_ENOTSPD", WL_ENOCONV: "WL_ENOCONV",
+    WL_ENUMERIC: "WL_ENUMERIC", WL_EUNSUPPORTED: "WL_EUNSUPPORTED",
+}
+
+
+class OpDesc(C.Structure):
+    _fields_ = [
+        ("mu", C.c_double),
+        ("func", C.c_int32),
+        ("param", C.c_double),
+        ("prec", C.c_int32),
+        ("krylov_dim", C.c_int32),
+        ("tol", C.c_double),
+        ("method", C.c_int32),
+        ("reorth", C.c_int32),
+        ("rho_hint", C.c_double),
+    ]
+
+
+vp = C.c_void_p
+i32, i64, u32, u64, f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+pd = C.POINTER(C.c_double)
+
+SIGNATURES = {
+    "wl_last_error": (C.c_char_p, []),
+    "wl_status_string": (C.c_char_p, [C.c_int]),
+    "wl_version": (i32, []),
+    "wl_ctx_create": (C.c_int, [i32, vp, C.POINTER(vp)]),
+    "wl_ctx_set_stream": (C.c_int, [vp, vp]),
+    "wl_ctx_synchronize": (C.c_int, [vp]),
+    "wl_ctx_destroy": (C.c_int, [vp]),
+    "wl_graph_create": (C.c_int, [vp, i64, i64, vp, vp, u32, C.POINTER(vp)]),
+    "wl_graph_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
+    "wl_graph_destroy": (C.c_int, [vp]),
+    "wl_spmm": (C.c_int, [vp, i32, vp, vp, i32]),
+    "wl_autotune": (C.c_int, [vp, i32, i32]),
+    "wl_lambda_max": (C.c_int, [vp, f64, pd]),
+    "wl_spectral_radius": (C.c_int, [vp, f64, f64, pd]),
+    "wl_op_create": (C.c_int, [vp, C.POINTER(OpDesc), C.POINTER(vp)]),
+    "wl_op_destroy": (C.c_int, [vp]),
+    "wl_fdeg": (C.c_int, [vp, vp]),
+    "wl_apply_phi": (C.c_int, [vp, vp, vp, i32]),
+    "wl_apply_L": (C.c_int, [vp, vp, vp, i32]),
+    "wl_expv": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd]),
+    "wl_probes": (C.c_int, [vp, i32, i32, u64, u32, i64, i32, vp]),
+    "wl_estimate": (C.c_int, [vp, i32, i32, i64, i32, vp, vp, vp, f64, vp, pd, pd]),
+    "wl_diag_est": (C.c_int, [vp, i32, f64, i32, u64, i32, i32, vp, i32, vp, pd, pd]),
+    "wl_features": (C.c_int, [vp, vp]),
+    "wl_mlp_create": (C.c_int, [vp, vp, C.POINTER(vp)]),
+    "wl_mlp_destroy": (C.c_int, [vp]),
+    "wl_mlp_get_params": (C.c_int, [vp, vp]),
+    "wl_mlp_forward": (C.c_int, [vp, vp, i64, vp]),
+    "wl_mlp_loss_grad": (C.c_int, [vp, vp, vp, i64, pd, vp]),
+    "wl_mlp_train_step": (C.c_int, [vp, vp, vp, i64, f64, pd]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libwalklap.so; raises if it is not built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with `python -m paper_2601_11338_amd.build`")
+    lib = C.CDLL(LIBPATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class WLError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+def check(status):
+    if status != WL_OK:
+        msg = load().wl_last_error()
+        raise WLError(status, msg.decode() if msg else "")

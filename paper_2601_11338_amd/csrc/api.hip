@@ -1,0 +1,1077 @@
+// C ABI of the walk-Laplacian library and the Krylov drivers behind it.
+//
+// Drivers (all vector work on the device; only b x b blocks and the projected
+// matrix cross to the host):
+//  * fused recurrence: phi X = sum_k c_k q_k(A) X with q from eq. qrec, scaled as
+//    P_k = s^k q_k X (s = alpha or beta) so that |P_k| stays O(1):
+//      P_1 = s A P_0,  P_2 = s A P_1 - s^2 mu D P_0,
+//      P_{k+1} = s A P_k + s^2 mu (mu I - D) P_{k-1}   (k >= 2),
+//    S = sum_k (c_k / s^k) P_k accumulated in the SpMM epilogue, one launch per
+//    degree (Prop. "whe-we-converge": the recurrence is the Taylor series of f_1
+//    on the linearisation Z applied to [q_1; q_2]);
+//  * block Lanczos (Sec. 4.1) on a symmetric operator, block CholQR2 with
+//    deflation, local or full reorthogonalisation, three-term subtraction fused
+//    into the SpMM epilogue.  The resolvent uses the deformed Laplacian
+//    A_mu(alpha) = (1 - mu^2 alpha^2) I - alpha A + alpha^2 mu D, for which
+//    phi = (1 - mu^2 alpha^2) A_mu(alpha)^{-1} (eq. deformed, extended to all mu as
+//    the remark after Prop. "CGworks" states), so phi X = (1 - mu^2 a^2) V T^{-1} E_1 R_0;
+//  * diffusion: outer block Lanczos on the walk Laplacian with inner phi products,
+//    exp(-t T) from one eigendecomposition for every t (Alg. 1 shares one basis
+//    across its parfor over t).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "wl_internal.h"
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[1024] = "";
+
+void wl_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename T>
+constexpr int prec_of() {
+  return sizeof(T) == 4 ? WL_FP32 : WL_FP64;
+}
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// deflation thresholds on squared norms (Gram pivots)
+template <typename T>
+double defl_tol() {
+  return sizeof(T) == 4 ? 1e-10 : 1e-24;
+}
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+int lanes_for(int prec, int b) {
+  const int vw = prec == WL_FP32 ? 4 : 2;
+  if (b % vw == 0) {
+    int l = b / vw;
+    if (l >= 16) return 16;
+    return next_pow2(l);
+  }
+  return b == 1 ? 1 : std::min(16, next_pow2(b));
+}
+
+SpmmShape shape_for(wl_graph* g, int prec, int b) {
+  auto it = g->tuned.find(prec * 1000 + std::min(b, 999));
+  if (it != g->tuned.end()) return it->second;
+  SpmmShape s;
+  const int lpn = lanes_for(prec, b);
+  int ns = next_pow2(std::max(1, (int)std::ceil(g->mean_deg))) / 2;
+  if (ns < 1) ns = 1;
+  int G = std::max(4, std::min(64, lpn * ns));
+  s.G = G;
+  s.long_thr = std::max(g->long_min_thr, 32 * (G / lpn));
+  return s;
+}
+
+template <typename T>
+T* tptr(const DevBuf& b, size_t off_elems = 0) {
+  return b.as<T>() + off_elems;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wl_last_error(void) { return g_err; }
+
+const char* wl_status_string(wl_status s) {
+  switch (s) {
+    case WL_OK: return "ok";
+    case WL_EINVAL: return "invalid argument";
+    case WL_ERANGE: return "out of range";
+    case WL_ENOMEM: return "out of device memory";
+    case WL_EDEVICE: return "device error";
+    case WL_ENOTSPD: return "operator not positive definite";
+    case WL_ENOCONV: return "no convergence";
+    case WL_ENUMERIC: return "non-finite result";
+    case WL_EUNSUPPORTED: return "unsupported";
+    default: return "internal error";
+  }
+}
+
+int32_t wl_version(void) { return 100; }
+
+// ------------------------------------------------------------------ context
+wl_status wl_ctx_create(int32_t device, void* stream, wl_ctx** out) {
+  WL_CHECK(out != nullptr, WL_EINVAL, "wl_ctx_create: out is null");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  WL_CHECK(e == hipSuccess && count > 0, WL_EDEVICE, "wl_ctx_create: no HIP device available");
+  WL_CHECK(device >= 0 && device < count, WL_EINVAL, "wl_ctx_create: device %d out of range [0,%d)", device, count);
+  DeviceGuard dg(device);
+  WL_HIP(hipFree(nullptr));
+  auto* c = new wl_ctx;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  *out = c;
+  return WL_OK;
+}
+
+wl_status wl_ctx_set_stream(wl_ctx* ctx, void* stream) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_ctx_set_stream: ctx is null");
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return WL_OK;
+}
+
+wl_status wl_ctx_synchronize(wl_ctx* ctx) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_ctx_synchronize: ctx is null");
+  DeviceGuard dg(ctx->device);
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
+wl_status wl_ctx_destroy(wl_ctx* ctx) {
+  if (!ctx) return WL_OK;
+  {
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->partials.release();
+    ctx->scratch.release();
+  }
+  delete ctx;
+  return WL_OK;
+}
+
+// ------------------------------------------------------------------ graph
+wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_colidx,
+                          uint32_t flags, wl_graph** out) {
+  WL_CHECK(ctx && out, WL_EINVAL, "wl_graph_create: null ctx or out");
+  *out = nullptr;
+  WL_CHECK(n >= 0 && nnz >= 0, WL_EINVAL, "wl_graph_create: negative size");
+  WL_CHECK(n < (1ll << 31) - 1, WL_ERANGE, "wl_graph_create: n must be < 2^31 - 1");
+  WL_CHECK(nnz < (1ll << 31), WL_ERANGE, "wl_graph_create: nnz must be < 2^31 (int32 CSR)");
+  WL_CHECK(d_rowptr != nullptr, WL_EINVAL, "wl_graph_create: rowptr is null");
+  WL_CHECK(nnz == 0 || d_colidx != nullptr, WL_EINVAL, "wl_graph_create: colidx is null");
+  WL_CHECK((flags & ~(WL_GRAPH_COPY | WL_GRAPH_VALIDATE)) == 0, WL_EINVAL, "wl_graph_create: unknown flags");
+  DeviceGuard dg(ctx->device);
+  auto* g = new wl_graph;
+  g->ctx = ctx;
+  g->n = n;
+  g->nnz = nnz;
+  auto fail = [&](wl_status s) {
+    delete g;
+    return s;
+  };
+  if (flags & WL_GRAPH_COPY) {
+    wl_status s = g->own_rowptr.ensure((size_t)(n + 1) * 4);
+    if (s != WL_OK) return fail(s);
+    s = g->own_colidx.ensure((size_t)std::max<int64_t>(nnz, 1) * 4);
+    if (s != WL_OK) return fail(s);
+    if (hipMemcpyAsync(g->own_rowptr.p, d_rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, ctx->stream) !=
+            hipSuccess ||
+        (nnz > 0 && hipMemcpyAsync(g->own_colidx.p, d_colidx, (size_t)nnz * 4, hipMemcpyDeviceToDevice,
+                                   ctx->stream) != hipSuccess)) {
+      wl_set_error("wl_graph_create: copying the CSR arrays failed");
+      return fail(WL_EDEVICE);
+    }
+    g->rowptr = g->own_rowptr.as<int32_t>();
+    g->colidx = g->own_colidx.as<int32_t>();
+  } else {
+    g->rowptr = d_rowptr;
+    g->colidx = d_colidx;
+  }
+  // host copy of rowptr: structural checks that protect every kernel, degree stats,
+  // and the decreasing-degree list of long rows
+  std::vector<int32_t> h(n + 1);
+  if (hipMemcpyAsync(h.data(), g->rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    wl_set_error("wl_graph_create: reading rowptr failed (is it a device pointer?)");
+    return fail(WL_EDEVICE);
+  }
+  if (h[0] != 0 || (int64_t)h[n] != nnz) {
+    wl_set_error("wl_graph_create: rowptr[0] must be 0 and rowptr[n] must equal nnz (got %d, %d)", h[0], h[n]);
+    return fail(WL_EINVAL);
+  }
+  int32_t maxd = 0;
+  std::vector<std::pair<int32_t, int32_t>> longs;
+  for (int64_t r = 0; r < n; ++r) {
+    const int32_t d = h[r + 1] - h[r];
+    if (d < 0) {
+      wl_set_error("wl_graph_create: rowptr decreases at row %lld", (long long)r);
+      return fail(WL_EINVAL);
+    }
+    maxd = std::max(maxd, d);
+    if (d > g->long_min_thr) longs.emplace_back(d, (int32_t)r);
+  }
+  g->max_deg = maxd;
+  g->mean_deg = n > 0 ? (double)nnz / (double)n : 0.0;
+  std::sort(longs.begin(), longs.end(), [](const auto& a, const auto& b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  });
+  {
+    std::vector<int32_t> rows(longs.size());
+    g->h_long_deg.resize(longs.size());
+    for (size_t i = 0; i < longs.size(); ++i) {
+      rows[i] = longs[i].second;
+      g->h_long_deg[i] = longs[i].first;
+    }
+    wl_status s = g->long_rows.ensure(std::max<size_t>(rows.size(), 1) * 4);
+    if (s != WL_OK) return fail(s);
+    if (!rows.empty() &&
+        hipMemcpy(g->long_rows.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      wl_set_error("wl_graph_create: upload of the long-row list failed");
+      return fail(WL_EDEVICE);
+    }
+  }
+  // column range always; full structure (order, loops, symmetry) on request
+  if (n > 0) {
+    DevBuf flagsbuf;
+    wl_status s = flagsbuf.ensure(8 * 4);
+    if (s != WL_OK) return fail(s);
+    if (hipMemsetAsync(flagsbuf.p, 0, 8 * 4, ctx->stream) != hipSuccess) return fail(WL_EDEVICE);
+    s = launch_validate(g, flagsbuf.as<int32_t>());
+    if (s != WL_OK) return fail(s);
+    int32_t hf[8];
+    if (hipMemcpyAsync(hf, flagsbuf.p, sizeof(hf), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(WL_EDEVICE);
+    if (hf[0] || hf[1]) {
+      wl_set_error("wl_graph_create: column index out of range or malformed rowptr");
+      return fail(WL_EINVAL);
+    }
+    if (flags & WL_GRAPH_VALIDATE) {
+      if (hf[2]) {
+        wl_set_error("wl_graph_create: self loop (graphs must be simple)");
+        return fail(WL_EINVAL);
+      }
+      if (hf[3]) {
+        wl_set_error("wl_graph_create: columns not strictly increasing (unsorted or duplicate edge)");
+        return fail(WL_EINVAL);
+      }
+      if (hf[4]) {
+        wl_set_error("wl_graph_create: adjacency not symmetric");
+        return fail(WL_EINVAL);
+      }
+    }
+  }
+  wl_status s = g->degf.ensure(std::max<int64_t>(n, 1) * 4);
+  if (s == WL_OK) s = g->degd.ensure(std::max<int64_t>(n, 1) * 8);
+  if (s == WL_OK) s = launch_degrees<float>(g, g->degf.as<float>());
+  if (s == WL_OK) s = launch_degrees<double>(g, g->degd.as<double>());
+  if (s != WL_OK) return fail(s);
+  *out = g;
+  return WL_OK;
+}
+
+wl_status wl_graph_info(const wl_graph* g, int64_t* n, int64_t* nnz, int32_t* max_degree) {
+  WL_CHECK(g, WL_EINVAL, "wl_graph_info: graph is null");
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (max_degree) *max_degree = g->max_deg;
+  return WL_OK;
+}
+
+wl_status wl_graph_destroy(wl_graph* g) {
+  if (!g) return WL_OK;
+  DeviceGuard dg(g->ctx->device);
+  (void)hipStreamSynchronize(g->ctx->stream);
+  delete g;
+  return WL_OK;
+}
+
+wl_status wl_spmm(wl_graph* g, int32_t prec, const void* d_X, void* d_Y, int32_t b) {
+  WL_CHECK(g, WL_EINVAL, "wl_spmm: graph is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_spmm: prec must be WL_FP32 or WL_FP64");
+  WL_CHECK(b >= 1, WL_EINVAL, "wl_spmm: b must be >= 1");
+  WL_CHECK(g->n == 0 || (d_X && d_Y), WL_EINVAL, "wl_spmm: null block");
+  WL_CHECK(d_X != d_Y || g->n == 0, WL_EINVAL, "wl_spmm: X and Y must not alias");
+  DeviceGuard dg(g->ctx->device);
+  const SpmmShape sh = shape_for(g, prec, b);
+  if (prec == WL_FP32) {
+    EpiArgs<float> ep;
+    return launch_spmm<float>(g, (const float*)d_X, (float*)d_Y, b, ep, sh);
+  }
+  EpiArgs<double> ep;
+  return launch_spmm<double>(g, (const double*)d_X, (double*)d_Y, b, ep, sh);
+}
+
+wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b) {
+  WL_CHECK(g, WL_EINVAL, "wl_autotune: graph is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_autotune: bad prec");
+  WL_CHECK(b >= 1 && b <= 4096, WL_EINVAL, "wl_autotune: b out of range");
+  if (g->n == 0) return WL_OK;
+  DeviceGuard dg(g->ctx->device);
+  const size_t es = prec == WL_FP32 ? 4 : 8;
+  DevBuf X, Y;
+  WL_TRY(X.ensure((size_t)g->n * b * es));
+  WL_TRY(Y.ensure((size_t)g->n * b * es));
+  hipStream_t st = g->ctx->stream;
+  if (prec == WL_FP32)
+    WL_TRY(launch_fill<float>(g->ctx, g->n * b, 1.0f, X.as<float>()));
+  else
+    WL_TRY(launch_fill<double>(g->ctx, g->n * b, 1.0, X.as<double>()));
+  const int lpn = lanes_for(prec, b);
+  std::vector<SpmmShape> cands;
+  for (int G = std::max(4, lpn); G <= 64; G <<= 1) {
+    for (int mult : {8, 32, 128}) {
+      SpmmShape s;
+      s.G = G;
+      s.long_thr = std::max(g->long_min_thr, mult * (G / lpn));
+      cands.push_back(s);
+    }
+  }
+  hipEvent_t e0, e1;
+  WL_HIP(hipEventCreate(&e0));
+  WL_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  SpmmShape bests = shape_for(g, prec, b);
+  for (const auto& s : cands) {
+    auto run = [&]() -> wl_status {
+      if (prec == WL_FP32) {
+        EpiArgs<float> ep;
+        return launch_spmm<float>(g, X.as<float>(), Y.as<float>(), b, ep, s);
+      }
+      EpiArgs<double> ep;
+      return launch_spmm<double>(g, X.as<double>(), Y.as<double>(), b, ep, s);
+    };
+    WL_TRY(run());  // warm
+    WL_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 5; ++r) WL_TRY(run());
+    WL_HIP(hipEventRecord(e1, st));
+    WL_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    WL_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bests = s;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g->tuned[prec * 1000 + std::min(b, 999)] = bests;
+  return WL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ block Lanczos core
+namespace {
+
+// Operator applied by the Lanczos driver to block V (n x b), result into W, with the
+// three-term subtraction W -= Vprev Bprev^T fused when possible.
+template <typename T>
+struct LanczosOp {
+  int kind = 0;  // 0: a*A + (b0 + b1 d) I (one SpMM); 1: walk Laplacian of an operator
+  double a = 1.0, b0 = 0.0, b1 = 0.0;
+  wl_op* inner = nullptr;  // kind 1
+};
+
+template <typename T>
+wl_status apply_lanczos_op(wl_graph* g, const LanczosOp<T>& L, const T* V, T* W, int b, const T* Vprev,
+                           const double* Bprev, double* scratch) {
+  if (L.kind == 0) {
+    EpiArgs<T> ep;
+    ep.a = L.a;
+    if (L.b0 != 0.0 || L.b1 != 0.0) {
+      ep.Z = V;
+      ep.b0 = L.b0;
+      ep.b1 = L.b1;
+    }
+    if (Vprev) {
+      ep.Z2 = Vprev;
+      ep.C = Bprev;
+      ep.transC = 1;
+    }
+    return launch_spmm<T>(g, V, W, b, ep, shape_for(g, prec_of<T>(), b));
+  }
+  // walk Laplacian: W = w (.) V - phi V, then the three-term subtraction
+  wl_op* op = L.inner;
+  WL_TRY(phi_apply_impl<T>(op, V, W, b, op->w.as<T>(), V));
+  if (Vprev) {
+    WL_TRY(launch_dtranspose(g->ctx, b, Bprev, scratch));
+    WL_TRY(launch_update<T>(g->ctx, g->n, Vprev, b, 0, 1, scratch, W, 1.0, nullptr, -1.0, W, b, nullptr));
+  }
+  return WL_OK;
+}
+
+// Device-resident layout of the small matrices of one Lanczos run.
+struct SmallLayout {
+  int b, K;
+  size_t bb;
+  size_t A(int j) const { return (size_t)j * bb; }              // K blocks
+  size_t B(int j) const { return (size_t)(K + j) * bb; }        // K blocks
+  size_t R0() const { return (size_t)(2 * K) * bb; }
+  size_t G() const { return (size_t)(2 * K + 1) * bb; }
+  size_t R1() const { return (size_t)(2 * K + 2) * bb; }
+  size_t Ri1() const { return (size_t)(2 * K + 3) * bb; }
+  size_t R2() const { return (size_t)(2 * K + 4) * bb; }
+  size_t Ri2() const { return (size_t)(2 * K + 5) * bb; }
+  size_t P() const { return (size_t)(2 * K + 6) * bb; }         // up to (K+1) blocks
+  size_t total() const { return (size_t)(3 * K + 8) * bb; }
+};
+
+// Runs K block Lanczos steps from X (n x b).  basis must hold (K+1) blocks, Wb one
+// block.  On return the host arrays hold A_j (K blocks), B_j (K blocks; B_{K-1}
+// is the residual coupling), R0 (X = V_0 R0).
+// ring = true keeps only three basis blocks (slot j mod 3) and needs reorth = 0.
+template <typename T>
+wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, int K, int reorth, T* basis, T* Wb,
+                        DevBuf& small, std::vector<double>& hA, std::vector<double>& hB, std::vector<double>& hR0,
+                        int* K_eff, bool ring = false) {
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  const int64_t blk = n * b;
+  SmallLayout Ly{b, K, (size_t)b * b};
+  WL_TRY(small.ensure(Ly.total() * sizeof(double)));
+  double* S = small.as<double>();
+  const double tol = defl_tol<T>();
+  // V_0 R0 = X by CholQR2
+  WL_TRY(launch_gram<T>(ctx, n, X, b, 0, 1, X, b, S + Ly.G()));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr));
+  WL_TRY(launch_update<T>(ctx, n, X, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, basis, b, S + Ly.G()));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                     S + Ly.R0()));
+  WL_TRY(launch_update<T>(ctx, n, basis, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, basis, b, nullptr));
+  if (ring) reorth = 0;
+  auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
+  for (int j = 0; j < K; ++j) {
+    T* Vj = slot(j);
+    const T* Vp = j > 0 ? slot(j - 1) : nullptr;
+    WL_TRY(apply_lanczos_op<T>(g, L, Vj, Wb, b, Vp, j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.P()));
+    // A_j = V_j^T W ; W -= V_j A_j
+    WL_TRY(launch_gram<T>(ctx, n, Vj, b, 0, 1, Wb, b, S + Ly.A(j)));
+    const bool second = reorth >= 1;
+    WL_TRY(launch_update<T>(ctx, n, Vj, b, 0, 1, S + Ly.A(j), Wb, 1.0, nullptr, -1.0, Wb, b,
+                            second ? nullptr : S + Ly.G()));
+    if (second) {
+      const int lo = reorth >= 2 ? 0 : std::max(0, j - 1);
+      const int nb = j - lo + 1;
+      const T* Vlo = basis + (size_t)lo * blk;
+      WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nb, Wb, b, S + Ly.P()));
+      WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nb, S + Ly.P(), Wb, 1.0, nullptr, -1.0, Wb, b, S + Ly.G()));
+      WL_TRY(launch_dadd(ctx, b * b, S + Ly.P() + (size_t)(nb - 1) * b * b, S + Ly.A(j)));
+    }
+    // W = V_{j+1} B_j by CholQR2
+    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, S + Ly.A(j), j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.R1(),
+                       S + Ly.Ri1(), nullptr, nullptr));
+    if (j + 1 == K) {
+      WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
+      break;
+    }
+    T* Vn = slot(j + 1);
+    WL_TRY(launch_update<T>(ctx, n, Wb, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G()));
+    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                       S + Ly.B(j)));
+    WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
+  }
+  hA.assign((size_t)K * b * b, 0.0);
+  hB.assign((size_t)K * b * b, 0.0);
+  hR0.assign((size_t)b * b, 0.0);
+  WL_HIP(hipMemcpyAsync(hA.data(), S + Ly.A(0), hA.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipMemcpyAsync(hB.data(), S + Ly.B(0), hB.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipMemcpyAsync(hR0.data(), S + Ly.R0(), hR0.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  // effective dimension: stop after the first block whose coupling vanished entirely
+  int Ke = K;
+  for (int j = 0; j + 1 < K; ++j) {
+    double s = 0.0;
+    for (int e = 0; e < b * b; ++e) s += hB[(size_t)j * b * b + e] * hB[(size_t)j * b * b + e];
+    if (s == 0.0) {
+      Ke = j + 1;
+      break;
+    }
+  }
+  *K_eff = Ke;
+  for (double v : hA)
+    if (!is_finite(v)) {
+      wl_set_error("block Lanczos produced non-finite coefficients");
+      return WL_ENUMERIC;
+    }
+  return WL_OK;
+}
+
+// Assemble the (K b) x (K b) block tridiagonal T.
+std::vector<double> assemble_T(int K, int b, const std::vector<double>& hA, const std::vector<double>& hB) {
+  const int m = K * b;
+  std::vector<double> T((size_t)m * m, 0.0);
+  for (int j = 0; j < K; ++j) {
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c) {
+        T[(size_t)(j * b + r) * m + j * b + c] = hA[(size_t)j * b * b + r * b + c];
+        if (j + 1 < K) {
+          const double v = hB[(size_t)j * b * b + r * b + c];  // T_{j+1, j}
+          T[(size_t)((j + 1) * b + r) * m + j * b + c] = v;
+          T[(size_t)(j * b + c) * m + (j + 1) * b + r] = v;
+        }
+      }
+  }
+  return T;
+}
+
+// F = f(T) E_1 R0 via the eigendecomposition of T (m = K b), f applied to eigenvalues.
+template <typename Fn>
+int coeffs_by_eig(int K, int b, const std::vector<double>& hA, const std::vector<double>& hB,
+                  const std::vector<double>& hR0, Fn f, std::vector<double>& F, std::vector<double>* lam_out,
+                  std::vector<double>* U_out) {
+  const int m = K * b;
+  std::vector<double> T = assemble_T(K, b, hA, hB);
+  std::vector<double> lam(m), U((size_t)m * m);
+  if (dense_syev(m, T.data(), lam.data(), U.data())) return 1;
+  // W = U^T E_1 R0  (m x b): rows of U restricted to the first b
+  std::vector<double> Wt((size_t)m * b, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int c = 0; c < b; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < b; ++k) s += U[(size_t)k * m + i] * hR0[(size_t)k * b + c];
+      Wt[(size_t)i * b + c] = s * f(lam[i]);
+    }
+  F.assign((size_t)m * b, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int i = 0; i < m; ++i) {
+      const double u = U[(size_t)r * m + i];
+      if (u == 0.0) continue;
+      for (int c = 0; c < b; ++c) F[(size_t)r * b + c] += u * Wt[(size_t)i * b + c];
+    }
+  if (lam_out) *lam_out = lam;
+  if (U_out) *U_out = U;
+  return 0;
+}
+
+template <typename T>
+wl_status recombine(wl_graph* g, const T* basis, int b, int K, const std::vector<double>& F, DevBuf& coef,
+                    const T* wv, const T* Xw, T* Y) {
+  WL_TRY(coef.ensure(F.size() * sizeof(double)));
+  WL_HIP(hipMemcpyAsync(coef.p, F.data(), F.size() * 8, hipMemcpyHostToDevice, g->ctx->stream));
+  WL_HIP(hipStreamSynchronize(g->ctx->stream));
+  if (wv)
+    return launch_update<T>(g->ctx, g->n, basis, b, g->n * b, K, coef.as<double>(), Xw, 0.0, wv, -1.0, Y, b, nullptr);
+  return launch_update<T>(g->ctx, g->n, basis, b, g->n * b, K, coef.as<double>(), nullptr, 0.0, nullptr, 1.0, Y, b,
+                          nullptr);
+}
+
+// phi X through the fused recurrence.
+template <typename T>
+wl_status phi_recurrence(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  const double mu = op->d.mu, s = op->d.param;
+  const int K = op->K;
+  WL_TRY(op->bufA.ensure((size_t)n * b * sizeof(T)));
+  WL_TRY(op->bufB.ensure((size_t)n * b * sizeof(T)));
+  T* A = op->bufA.as<T>();
+  T* B = op->bufB.as<T>();
+  const SpmmShape sh = shape_for(g, prec_of<T>(), b);
+  // weights omega_k = c_k / s^k
+  auto omega = [&](int k) {
+    if (op->d.func == WL_F_RESOLVENT) return 1.0;
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f /= i;
+    return f;
+  };
+  if (K == 0) {
+    // phi = c_0 I
+    if (wv) return launch_axpby_rows<T>(g->ctx, n, b, wv, Xw, -1.0, X, Y);
+    return launch_axpby_rows<T>(g->ctx, n, b, nullptr, X, 0.0, X, Y);
+  }
+  // step 1: P_1 = s A X ; S = X + omega_1 P_1
+  {
+    EpiArgs<T> ep;
+    ep.a = s;
+    ep.Sin = X;
+    ep.Sout = Y;
+    ep.s0 = 1.0;
+    ep.sc = omega(1);
+    if (K == 1) {
+      ep.wv = wv;
+      ep.Xw = Xw;
+    }
+    WL_TRY(launch_spmm<T>(g, X, K == 1 ? nullptr : A, b, ep, sh));
+  }
+  const T* Pm2 = X;  // P_{k-2}
+  T* Pm1 = A;        // P_{k-1}
+  T* spare = B;
+  for (int k = 2; k <= K; ++k) {
+    EpiArgs<T> ep;
+    ep.a = s;
+    ep.Z = Pm2;
+    ep.b0 = (k == 2) ? 0.0 : s * s * mu * mu;
+    ep.b1 = -s * s * mu;
+    ep.Sin = Y;
+    ep.Sout = Y;
+    ep.s0 = 1.0;
+    ep.sc = omega(k);
+    const bool last = k == K;
+    if (last) {
+      ep.wv = wv;
+      ep.Xw = Xw;
+    }
+    // P_k overwrites the buffer of P_{k-2} (row r of P_{k-2} is read and row r of
+    // P_k written by the same lanes); P_0 = X is never overwritten.
+    T* out = (k == 2) ? spare : const_cast<T*>(Pm2);
+    if (mu == 0.0) ep.Z = nullptr;
+    WL_TRY(launch_spmm<T>(g, Pm1, last ? nullptr : out, b, ep, sh));
+    Pm2 = Pm1;
+    Pm1 = out;
+  }
+  return WL_OK;
+}
+
+template <typename T>
+wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  const int K = op->K;
+  const double mu = op->d.mu, p = op->d.param;
+  LanczosOp<T> L;
+  double scale = 1.0;
+  if (op->d.func == WL_F_RESOLVENT) {
+    // A_mu(alpha) = (1 - mu^2 a^2) I - a A + a^2 mu D
+    L.a = -p;
+    L.b0 = 1.0 - mu * mu * p * p;
+    L.b1 = p * p * mu;
+    scale = 1.0 - mu * mu * p * p;
+  } else {
+    L.a = 1.0;  // mu = 0: phi = exp(beta A)
+  }
+  WL_TRY(op->basis.ensure((size_t)(K + 1) * n * b * sizeof(T)));
+  WL_TRY(op->wbuf.ensure((size_t)n * b * sizeof(T)));
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<T>(g, L, X, b, K, op->d.reorth, op->basis.as<T>(), op->wbuf.as<T>(), op->small, hA, hB, hR0,
+                          &Ke));
+  std::vector<double> F;
+  if (op->d.func == WL_F_RESOLVENT) {
+    // F = scale * T^{-1} E_1 R0
+    std::vector<double> rhs((size_t)Ke * b * b, 0.0), sol((size_t)Ke * b * b);
+    for (int r = 0; r < b; ++r)
+      for (int c = 0; c < b; ++c) rhs[(size_t)r * b + c] = hR0[(size_t)r * b + c];
+    bool ok = block_tridiag_solve(Ke, b, hA.data(), hB.data(), rhs.data(), b, sol.data()) == 0;
+    if (ok) {
+      F.resize(sol.size());
+      for (size_t i = 0; i < sol.size(); ++i) F[i] = scale * sol[i];
+    } else {
+      // deflated (singular) projection: pseudo-inverse through the eigendecomposition
+      std::vector<double> lam;
+      double lmax = 0.0;
+      {
+        std::vector<double> Tm = assemble_T(Ke, b, hA, hB);
+        std::vector<double> l(Ke * b), U((size_t)Ke * b * Ke * b);
+        if (dense_syev(Ke * b, Tm.data(), l.data(), U.data())) {
+          wl_set_error("eigendecomposition of the projected matrix failed");
+          return WL_ENOCONV;
+        }
+        for (double v : l) lmax = std::max(lmax, std::fabs(v));
+        if (l[0] < -1e-6 * lmax) {
+          wl_set_error("deformed Laplacian not positive definite on the Krylov space (alpha too large?)");
+          return WL_ENOTSPD;
+        }
+      }
+      const double cut = 1e-12 * lmax;
+      if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return x > cut ? scale / x : 0.0; }, F, nullptr,
+                        nullptr)) {
+        wl_set_error("eigendecomposition of the projected matrix failed");
+        return WL_ENOCONV;
+      }
+    }
+  } else {
+    if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return std::exp(p * x); }, F, nullptr, nullptr)) {
+      wl_set_error("eigendecomposition of the projected matrix failed");
+      return WL_ENOCONV;
+    }
+  }
+  return recombine<T>(g, op->basis.as<T>(), b, Ke, F, op->coef, wv, Xw, Y);
+}
+
+}  // namespace
+
+template <typename T>
+wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
+  if (op->g->n == 0) return WL_OK;
+  if (op->d.method == WL_M_LANCZOS) return phi_lanczos<T>(op, X, Y, b, wv, Xw);
+  return phi_recurrence<T>(op, X, Y, b, wv, Xw);
+}
+
+template wl_status phi_apply_impl<float>(wl_op*, const float*, float*, int, const float*, const float*);
+template wl_status phi_apply_impl<double>(wl_op*, const double*, double*, int, const double*, const double*);
+
+template <typename T>
+wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* const* Y, int outer_dim,
+                    double* err_est) {
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(outer_dim, std::max<int64_t>(1, (n + b - 1) / b)));
+  WL_TRY(op->outer_basis.ensure((size_t)(K + 1) * n * b * sizeof(T)));
+  WL_TRY(op->outer_w.ensure((size_t)n * b * sizeof(T)));
+  LanczosOp<T> L;
+  L.kind = 1;
+  L.inner = op;
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<T>(g, L, U0, b, K, op->d.reorth, op->outer_basis.as<T>(), op->outer_w.as<T>(),
+                          op->outer_small, hA, hB, hR0, &Ke));
+  const int m = Ke * b;
+  std::vector<double> Tm = assemble_T(Ke, b, hA, hB);
+  std::vector<double> lam(m), U((size_t)m * m);
+  if (dense_syev(m, Tm.data(), lam.data(), U.data())) {
+    wl_set_error("eigendecomposition of the projected Laplacian failed");
+    return WL_ENOCONV;
+  }
+  // U^T E_1 R0
+  std::vector<double> W0((size_t)m * b, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int c = 0; c < b; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < b; ++k) s += U[(size_t)k * m + i] * hR0[(size_t)k * b + c];
+      W0[(size_t)i * b + c] = s;
+    }
+  for (int it = 0; it < nt; ++it) {
+    std::vector<double> F((size_t)m * b, 0.0);
+    for (int r = 0; r < m; ++r)
+      for (int i = 0; i < m; ++i) {
+        const double u = U[(size_t)r * m + i] * std::exp(-t[it] * lam[i]);
+        if (u == 0.0) continue;
+        for (int c = 0; c < b; ++c) F[(size_t)r * b + c] += u * W0[(size_t)i * b + c];
+      }
+    if (err_est) {
+      // || B_{K-1} F_last ||_F with F_last the last block row of F
+      double e2 = 0.0;
+      if (Ke == K) {
+        const double* Bl = &hB[(size_t)(K - 1) * b * b];
+        for (int r = 0; r < b; ++r)
+          for (int c = 0; c < b; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < b; ++k) s += Bl[(size_t)r * b + k] * F[(size_t)((K - 1) * b + k) * b + c];
+            e2 += s * s;
+          }
+      }
+      err_est[it] = std::sqrt(e2);
+    }
+    WL_TRY(recombine<T>(g, op->outer_basis.as<T>(), b, Ke, F, op->outer_coef, nullptr, nullptr, Y[it]));
+    if (it + 1 < nt) WL_HIP(hipStreamSynchronize(g->ctx->stream));  // coefficient buffer is reused
+  }
+  return WL_OK;
+}
+
+template wl_status expv_impl<float>(wl_op*, const float*, int, const double*, int, float* const*, int, double*);
+template wl_status expv_impl<double>(wl_op*, const double*, int, const double*, int, double* const*, int, double*);
+
+// ------------------------------------------------------------------ spectral scale
+// kind 0: A; kind 1: A_mu(t).  Runs `steps` single-vector Lanczos steps from 1 and
+// returns the extreme Ritz values.
+wl_status lanczos_extreme(wl_graph* g, int kind, double mu, double t, int steps, double* lo, double* hi) {
+  const int64_t n = g->n;
+  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(steps, n));
+  LanczosOp<double> L;
+  if (kind == 1) {
+    L.a = -t;
+    L.b0 = 1.0 - mu * mu * t * t;
+    L.b1 = t * t * mu;
+  }
+  WL_TRY(g->tmp.ensure((size_t)4 * n * sizeof(double) + 256));
+  double* basis = g->tmp.as<double>();
+  double* W = basis + (size_t)3 * n;
+  DevBuf ones, small;
+  WL_TRY(ones.ensure((size_t)n * sizeof(double)));
+  WL_TRY(launch_fill<double>(g->ctx, n, 1.0, ones.as<double>()));
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<double>(g, L, ones.as<double>(), 1, K, 0, basis, W, small, hA, hB, hR0, &Ke, true));
+  std::vector<double> a(Ke), bb(std::max(1, Ke - 1)), lam(Ke);
+  for (int j = 0; j < Ke; ++j) a[j] = hA[j];
+  for (int j = 0; j + 1 < Ke; ++j) bb[j] = hB[j];
+  if (tridiag_eigvals(Ke, a.data(), bb.data(), lam.data())) {
+    wl_set_error("tridiagonal eigenvalues did not converge");
+    return WL_ENOCONV;
+  }
+  *lo = *std::min_element(lam.begin(), lam.end());
+  *hi = *std::max_element(lam.begin(), lam.end());
+  return WL_OK;
+}
+
+extern "C" {
+
+wl_status wl_lambda_max(wl_graph* g, double tol, double* out) {
+  WL_CHECK(g && out, WL_EINVAL, "wl_lambda_max: null argument");
+  WL_CHECK(tol >= 0 && is_finite(tol), WL_EINVAL, "wl_lambda_max: bad tol");
+  if (g->n == 0 || g->nnz == 0) {
+    *out = 0.0;
+    return WL_OK;
+  }
+  if (g->lam_max > 0) {
+    *out = g->lam_max;
+    return WL_OK;
+  }
+  DeviceGuard dg(g->ctx->device);
+  if (tol == 0) tol = 1e-12;
+  double prev = -1, lo, hi = 0;
+  for (int steps = 60; steps <= 960; steps *= 2) {
+    WL_TRY(lanczos_extreme(g, 0, 0.0, 0.0, steps, &lo, &hi));
+    if (prev > 0 && std::fabs(hi - prev) <= tol * hi) break;
+    if (steps >= g->n) break;
+    prev = hi;
+  }
+  g->lam_max = hi;
+  *out = hi;
+  return WL_OK;
+}
+
+wl_status wl_spectral_radius(wl_graph* g, double mu, double tol, double* rho) {
+  WL_CHECK(g && rho, WL_EINVAL, "wl_spectral_radius: null argument");
+  WL_CHECK(mu >= 0.0 && mu <= 1.0, WL_EINVAL, "wl_spectral_radius: mu must lie in [0, 1]");
+  WL_CHECK(tol >= 0 && is_finite(tol), WL_EINVAL, "wl_spectral_radius: bad tol");
+  if (tol == 0) tol = 1e-10;
+  double lam;
+  WL_TRY(wl_lambda_max(g, 1e-12, &lam));
+  if (mu == 0.0 || lam == 0.0) {
+    *rho = lam;
+    return WL_OK;
+  }
+  auto it = g->rho_cache.find(mu);
+  if (it != g->rho_cache.end()) {
+    *rho = it->second;
+    return WL_OK;
+  }
+  DeviceGuard dg(g->ctx->device);
+  const int steps = (int)std::min<int64_t>(g->n, 200);
+  // f(t) = smallest Ritz value of A_mu(t); the first zero of f is 1 / rho(Z_mu)
+  auto f = [&](double t, double* v) -> wl_status {
+    double lo, hi, prev = 1e300;
+    for (int s = steps; s <= 1600; s *= 2) {
+      WL_TRY(lanczos_extreme(g, 1, mu, t, s, &lo, &hi));
+      if (std::fabs(lo - prev) <= 1e-13 * std::max(1.0, std::fabs(hi)) || s >= g->n) break;
+      prev = lo;
+    }
+    *v = lo;
+    return WL_OK;
+  };
+  double tlo = 0.0, flo = 1.0, thi = 1.0 / lam, fhi;
+  WL_TRY(f(thi, &fhi));
+  int guard = 0;
+  while (fhi > 0) {
+    tlo = thi;
+    flo = fhi;
+    thi *= 1.05;
+    WL_TRY(f(thi, &fhi));
+    if (++guard > 400) {
+      wl_set_error("wl_spectral_radius: no sign change of the deformed Laplacian's smallest eigenvalue");
+      return WL_ENOCONV;
+    }
+  }
+  // Illinois false position on [tlo, thi]
+  int side = 0;
+  for (int iter = 0; iter < 200 && (thi - tlo) > tol * thi * 0.25; ++iter) {
+    double tm = (tlo * fhi - thi * flo) / (fhi - flo);
+    if (!(tm > tlo && tm < thi)) tm = 0.5 * (tlo + thi);
+    double fm;
+    WL_TRY(f(tm, &fm));
+    if (fm > 0) {
+      tlo = tm;
+      flo = fm;
+      if (side == 1) fhi *= 0.5;
+      side = 1;
+    } else {
+      thi = tm;
+      fhi = fm;
+      if (side == -1) flo *= 0.5;
+      side = -1;
+    }
+  }
+  const double r = 2.0 / (tlo + thi);
+  g->rho_cache[mu] = r;
+  *rho = r;
+  return WL_OK;
+}
+
+// ------------------------------------------------------------------ operator
+wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
+  WL_CHECK(g && d && out, WL_EINVAL, "wl_op_create: null argument");
+  *out = nullptr;
+  WL_CHECK(d->mu >= 0.0 && d->mu <= 1.0, WL_EINVAL, "wl_op_create: mu must lie in [0, 1]");
+  WL_CHECK(d->func == WL_F_RESOLVENT || d->func == WL_F_EXP, WL_EINVAL, "wl_op_create: unknown func");
+  WL_CHECK(is_finite(d->param) && d->param > 0.0, WL_EINVAL, "wl_op_create: param (alpha or beta) must be > 0");
+  WL_CHECK(d->prec == WL_FP32 || d->prec == WL_FP64, WL_EINVAL, "wl_op_create: prec must be WL_FP32 or WL_FP64");
+  WL_CHECK(d->krylov_dim >= 0 && d->krylov_dim <= 2000, WL_EINVAL, "wl_op_create: krylov_dim out of range");
+  WL_CHECK(is_finite(d->tol) && d->tol >= 0.0, WL_EINVAL, "wl_op_create: bad tol");
+  WL_CHECK(d->method >= WL_M_AUTO && d->method <= WL_M_LANCZOS, WL_EINVAL, "wl_op_create: unknown method");
+  WL_CHECK(d->reorth >= 0 && d->reorth <= 2, WL_EINVAL, "wl_op_create: reorth must be 0, 1 or 2");
+  int method = d->method;
+  if (method == WL_M_AUTO) method = d->func == WL_F_EXP ? WL_M_RECURRENCE : WL_M_LANCZOS;
+  WL_CHECK(!(method == WL_M_LANCZOS && d->func == WL_F_EXP && d->mu != 0.0), WL_EUNSUPPORTED,
+           "wl_op_create: exponential weights with mu > 0 are not a function of one symmetric n x n matrix; "
+           "use the recurrence");
+  WL_CHECK(!(method == WL_M_RECURRENCE && d->func == WL_F_RESOLVENT && d->krylov_dim == 0), WL_EINVAL,
+           "wl_op_create: the truncated resolvent series needs an explicit krylov_dim");
+  DeviceGuard dg(g->ctx->device);
+  double rho = 0.0;
+  if (d->func == WL_F_RESOLVENT) {
+    if (d->rho_hint > 0)
+      rho = d->rho_hint;
+    else
+      WL_TRY(wl_spectral_radius(g, d->mu, 1e-10, &rho));
+    WL_CHECK(d->param * rho < 1.0, WL_ERANGE,
+             "wl_op_create: alpha * rho(Z_mu) = %.6g >= 1: the series does not converge", d->param * rho);
+  }
+  int K = d->krylov_dim;
+  if (K == 0) {
+    const double tol = d->tol > 0 ? d->tol : 1e-12;
+    if (d->func == WL_F_EXP) {
+      double lam;
+      WL_TRY(wl_lambda_max(g, 1e-10, &lam));
+      // smallest K with sum_{k>K} (beta lam)^k / k! <= tol * e^{beta lam}
+      const double x = d->param * lam;
+      double term = 1.0, tail = std::exp(x) - 1.0;
+      K = 0;
+      while (tail > tol * std::exp(x) && K < 2000) {
+        ++K;
+        term *= x / K;
+        tail -= term;
+      }
+    } else {
+      // conjugate-gradient style bound with a spectral-interval estimate of A_mu(alpha)
+      double lam;
+      WL_TRY(wl_lambda_max(g, 1e-10, &lam));
+      const double a = d->param, mu = d->mu;
+      const double top = 1.0 + a * lam + a * a * mu * g->max_deg;
+      const double bot = std::max(1.0 - a * rho, 1e-6);
+      const double kappa = top / bot;
+      K = (int)std::ceil(0.5 * std::sqrt(kappa) * std::log(2.0 / tol)) + 2;
+      K = std::min(K, 2000);
+    }
+  }
+  auto* op = new wl_op;
+  op->g = g;
+  op->d = *d;
+  op->d.method = method;
+  op->rho = rho;
+  op->K = K;
+  *out = op;
+  return WL_OK;
+}
+
+wl_status wl_op_destroy(wl_op* op) {
+  if (!op) return WL_OK;
+  DeviceGuard dg(op->g->ctx->device);
+  (void)hipStreamSynchronize(op->g->ctx->stream);
+  delete op;
+  return WL_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename T>
+wl_status ensure_w(wl_op* op) {
+  if (op->w_valid) return WL_OK;
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  WL_TRY(op->w.ensure(std::max<int64_t>(n, 1) * sizeof(T)));
+  DevBuf ones;
+  WL_TRY(ones.ensure(std::max<int64_t>(n, 1) * sizeof(T)));
+  WL_TRY(launch_fill<T>(g->ctx, n, T(1), ones.as<T>()));
+  WL_TRY(phi_apply_impl<T>(op, ones.as<T>(), op->w.as<T>(), 1, nullptr, nullptr));
+  WL_HIP(hipStreamSynchronize(g->ctx->stream));  // ones is freed on return
+  op->w_valid = true;
+  return WL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+wl_status wl_fdeg(wl_op* op, void* d_w) {
+  WL_CHECK(op, WL_EINVAL, "wl_fdeg: op is null");
+  WL_CHECK(op->g->n == 0 || d_w, WL_EINVAL, "wl_fdeg: output is null");
+  DeviceGuard dg(op->g->ctx->device);
+  const size_t es = op->d.prec == WL_FP32 ? 4 : 8;
+  if (op->d.prec == WL_FP32)
+    WL_TRY(ensure_w<float>(op));
+  else
+    WL_TRY(ensure_w<double>(op));
+  if (op->g->n > 0)
+    WL_HIP(hipMemcpyAsync(d_w, op->w.p, (size_t)op->g->n * es, hipMemcpyDeviceToDevice, op->g->ctx->stream));
+  return WL_OK;
+}
+
+static wl_status check_block(wl_op* op, const void* X, const void* Y, int32_t b, const char* who) {
+  WL_CHECK(op, WL_EINVAL, "%s: op is null", who);
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "%s: b must lie in [1, 64]", who);
+  WL_CHECK(op->g->n == 0 || (X && Y), WL_EINVAL, "%s: null block", who);
+  WL_CHECK(X != Y || op->g->n == 0, WL_EINVAL, "%s: X and Y must not alias", who);
+  const size_t es = op->d.prec == WL_FP32 ? 4 : 8;
+  WL_CHECK((reinterpret_cast<uintptr_t>(X) % es) == 0 && (reinterpret_cast<uintptr_t>(Y) % es) == 0, WL_EINVAL,
+           "%s: misaligned block", who);
+  return WL_OK;
+}
+
+wl_status wl_apply_phi(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
+  WL_TRY(check_block(op, d_X, d_Y, b, "wl_apply_phi"));
+  DeviceGuard dg(op->g->ctx->device);
+  if (op->d.prec == WL_FP32) return phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, nullptr, nullptr);
+  return phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, nullptr, nullptr);
+}
+
+wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
+  WL_TRY(check_block(op, d_X, d_Y, b, "wl_apply_L"));
+  DeviceGuard dg(op->g->ctx->device);
+  if (op->d.prec == WL_FP32) {
+    WL_TRY(ensure_w<float>(op));
+    return phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, op->w.as<float>(), (const float*)d_X);
+  }
+  WL_TRY(ensure_w<double>(op));
+  return phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, op->w.as<double>(), (const double*)d_X);
+}
+
+wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
+                  int32_t outer_dim, double* err_est) {
+  WL_CHECK(op, WL_EINVAL, "wl_expv: op is null");
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_expv: b must lie in [1, 64]");
+  WL_CHECK(nt >= 1 && t && d_Y, WL_EINVAL, "wl_expv: need nt >= 1 times and outputs");
+  WL_CHECK(outer_dim >= 1 && outer_dim <= 1000, WL_EINVAL, "wl_expv: outer_dim out of range");
+  WL_CHECK(op->g->n == 0 || d_U0, WL_EINVAL, "wl_expv: U0 is null");
+  for (int i = 0; i < nt; ++i) {
+    WL_CHECK(is_finite(t[i]) && t[i] >= 0, WL_EINVAL, "wl_expv: times must be finite and >= 0");
+    WL_CHECK(op->g->n == 0 || (d_Y[i] && d_Y[i] != d_U0), WL_EINVAL, "wl_expv: bad output pointer %d", i);
+  }
+  if (op->g->n == 0) return WL_OK;
+  DeviceGuard dg(op->g->ctx->device);
+  if (op->d.prec == WL_FP32) {
+    WL_TRY(ensure_w<float>(op));
+    return expv_impl<float>(op, (const float*)d_U0, b, t, nt, (float* const*)d_Y, outer_dim, err_est);
+  }
+  WL_TRY(ensure_w<double>(op));
+  return expv_impl<double>(op, (const double*)d_U0, b, t, nt, (double* const*)d_Y, outer_dim, err_est);
+}
+
+wl_status wl_probes(wl_ctx* ctx, int32_t prec, int32_t law, uint64_t seed, uint32_t stream, int64_t n, int32_t M,
+                    void* d_out) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_probes: ctx is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_probes: bad prec");
+  WL_CHECK(law == WL_PROBE_GAUSS || law == WL_PROBE_RADEMACHER, WL_EINVAL, "wl_probes: bad law");
+  WL_CHECK(n >= 0 && M >= 1, WL_EINVAL, "wl_probes: bad size");
+  WL_CHECK(n == 0 || d_out, WL_EINVAL, "wl_probes: output is null");
+  DeviceGuard dg(ctx->device);
+  if (prec == WL_FP32) return launch_probes<float>(ctx, law, seed, stream, n, M, (float*)d_out);
+  return launch_probes<double>(ctx, law, seed, stream, n, M, (double*)d_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,705 @@
+// Tall-skinny block kernels for the Krylov drivers and estimators (gfx950).
+//
+//  * gram:    X^T Y for n x B blocks (B <= 64), double accumulation.  Each
+//             workgroup stages 32-row tiles of both operands in LDS (coalesced
+//             loads of contiguous rows) and every thread owns entries (i, j) of
+//             the B x B result; per-workgroup partials are reduced by a second
+//             kernel in a fixed order, so results are bitwise reproducible.
+//  * update:  Out = w (.) Yin + beta * sum_k X_k C_k, one thread per row: the row
+//             segment of X_k is loaded with vector loads into registers and C_k
+//             (B x B) is broadcast from LDS; optionally the Gram of the result is
+//             accumulated in the same pass (block CholQR needs W^T W right after
+//             W is formed).
+//  * chol:    Cholesky with deflation of a B x B Gram and the inverse of its
+//             factor, one workgroup (column-parallel).
+//  * probes:  Philox4x32-10 (Salmon et al., SC'11) Rademacher / Gaussian blocks.
+//  * small helpers: fills, scaled row sums, degree vector, CSR validation.
+#include "wl_internal.h"
+
+namespace {
+
+constexpr int GRAM_TR = 32;  // rows per LDS tile in the Gram kernel
+
+template <int B>
+__global__ __launch_bounds__(256) void k_gram_partial(int64_t n, const float* __restrict__ Xf,
+                                                      const double* __restrict__ Xd, int ldx, int64_t sX,
+                                                      const float* __restrict__ Yf, const double* __restrict__ Yd,
+                                                      int ldy, int bx, int by, double* __restrict__ partials) {
+  constexpr int E = B * B;
+  constexpr int QE = E >= 256 ? E / 256 : 1;
+  __shared__ double sx[GRAM_TR * B];
+  __shared__ double sy[GRAM_TR * B];
+  __shared__ double sred[256];
+  const int tid = threadIdx.x;
+  const int64_t xoff = (int64_t)blockIdx.y * sX;
+  double acc[QE];
+#pragma unroll
+  for (int q = 0; q < QE; ++q) acc[q] = 0.0;
+  // entries-per-thread layout for E < 256: P row phases
+  constexpr int P = E >= 256 ? 1 : 256 / E;
+  const int e_small = tid % E;
+  const int p_small = tid / E;
+  const int64_t ntiles = (n + GRAM_TR - 1) / GRAM_TR;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row0 = t * GRAM_TR;
+    for (int idx = tid; idx < GRAM_TR * B; idx += 256) {
+      const int r = idx / B, c = idx % B;
+      const int64_t row = row0 + r;
+      double xv = 0.0, yv = 0.0;
+      if (row < n) {
+        if (c < bx) xv = Xf ? (double)Xf[xoff + row * ldx + c] : Xd[xoff + row * ldx + c];
+        if (c < by) yv = Yf ? (double)Yf[row * ldy + c] : Yd[row * ldy + c];
+      }
+      sx[idx] = xv;
+      sy[idx] = yv;
+    }
+    __syncthreads();
+    if constexpr (E >= 256) {
+#pragma unroll
+      for (int q = 0; q < QE; ++q) {
+        const int e = tid + q * 256;
+        const int i = e / B, j = e % B;
+        double s = acc[q];
+#pragma unroll 8
+        for (int r = 0; r < GRAM_TR; ++r) s += sx[r * B + i] * sy[r * B + j];
+        acc[q] = s;
+      }
+    } else {
+      if (p_small < P) {
+        const int i = e_small / B, j = e_small % B;
+        double s = acc[0];
+        for (int r = p_small; r < GRAM_TR; r += P) s += sx[r * B + i] * sy[r * B + j];
+        acc[0] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double* out = partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * E;
+  if constexpr (E >= 256) {
+#pragma unroll
+    for (int q = 0; q < QE; ++q) out[tid + q * 256] = acc[q];
+  } else {
+    sred[tid] = (p_small < P) ? acc[0] : 0.0;
+    __syncthreads();
+    if (tid < E) {
+      double s = 0.0;
+      for (int p = 0; p < P; ++p) s += sred[tid + p * E];
+      out[tid] = s;
+    }
+  }
+}
+
+// out[(k*bx + i)*by + j] = sum over partial blocks (fixed order)
+__global__ void k_gram_finalize(const double* __restrict__ partials, int nparts, int B, int bx, int by,
+                                double* __restrict__ out) {
+  const int E = B * B;
+  const int k = blockIdx.y;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+    const int i = e / B, j = e % B;
+    if (i >= bx || j >= by) continue;
+    const double* p = partials + (int64_t)k * nparts * E + e;
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += p[(int64_t)q * E];
+    out[((int64_t)k * bx + i) * by + j] = s;
+  }
+}
+
+template <typename T, int B>
+struct RowVec {
+  T v[B];
+};
+
+// Out[r,:] = (wv ? wv[r] : alpha) * Yin[r,:] + beta * sum_k X_k[r,0:bx] C_k,  C_k = C[k*bx:(k+1)*bx, 0:by]
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_update(int64_t n, const T* X, int ldx, int64_t sX, int nblk,
+                                                int bx, const double* __restrict__ C, const T* Yin, int ldy,
+                                                double alpha, const T* __restrict__ wv, double beta, T* Out,
+                                                int by, double* __restrict__ gram_partials) {
+  // rows of the result staged per chunk for the fused Gram (keeps LDS <= 64 KiB)
+  constexpr int CHR = (256 * (B + 1) * (int)sizeof(T) <= 65536) ? 256 : 65536 / ((B + 1) * (int)sizeof(T)) / 64 * 64;
+  __shared__ T sC[B * B];
+  __shared__ T sO[CHR * (B + 1)];
+  const int tid = threadIdx.x;
+  const T tb = (T)beta;
+  constexpr int E = B * B;
+  constexpr int QE = E >= 256 ? E / 256 : 1;
+  double gacc[QE];
+#pragma unroll
+  for (int q = 0; q < QE; ++q) gacc[q] = 0.0;
+  constexpr int P = E >= 256 ? 1 : 256 / E;
+  const int64_t ntiles = (n + 255) / 256;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row = t * 256 + tid;
+    const bool ok = row < n;
+    T acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = T(0);
+    for (int k = 0; k < nblk; ++k) {
+      __syncthreads();
+      for (int e = tid; e < B * B; e += 256) {
+        const int i = e / B, j = e % B;
+        sC[e] = (i < bx && j < by) ? (T)C[((int64_t)k * bx + i) * by + j] : T(0);
+      }
+      __syncthreads();
+      if (ok) {
+        const T* xr = X + (int64_t)k * sX + row * ldx;
+        T xv[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) xv[i] = (i < bx) ? xr[i] : T(0);
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+          for (int j = 0; j < B; ++j) acc[j] += xv[i] * sC[i * B + j];
+      }
+    }
+    if (ok) {
+      const T sc = wv ? wv[row] : (T)alpha;
+      T* orow = Out + row * ldy;
+      const T* yrow = Yin ? Yin + row * ldy : nullptr;
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        if (j < by) {
+          T o = tb * acc[j];
+          if (yrow) o += sc * yrow[j];
+          orow[j] = o;
+          acc[j] = o;
+        }
+      }
+    }
+    if (gram_partials) {
+      for (int c0 = 0; c0 < 256; c0 += CHR) {
+        const int rows = (256 - c0) < CHR ? (256 - c0) : CHR;
+        __syncthreads();
+        if (tid >= c0 && tid < c0 + CHR) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) sO[(tid - c0) * (B + 1) + j] = (ok && j < by) ? acc[j] : T(0);
+        }
+        __syncthreads();
+        if constexpr (E >= 256) {
+#pragma unroll
+          for (int q = 0; q < QE; ++q) {
+            const int e = tid + q * 256;
+            const int i = e / B, j = e % B;
+            double s = gacc[q];
+            for (int r = 0; r < rows; ++r) s += (double)sO[r * (B + 1) + i] * (double)sO[r * (B + 1) + j];
+            gacc[q] = s;
+          }
+        } else {
+          const int e = tid % E, p = tid / E;
+          if (p < P) {
+            const int i = e / B, j = e % B;
+            double s = gacc[0];
+            for (int r = p; r < rows; r += P) s += (double)sO[r * (B + 1) + i] * (double)sO[r * (B + 1) + j];
+            gacc[0] = s;
+          }
+        }
+      }
+    }
+  }
+  if (gram_partials) {
+    double* out = gram_partials + (int64_t)blockIdx.x * E;
+    if constexpr (E >= 256) {
+#pragma unroll
+      for (int q = 0; q < QE; ++q) out[tid + q * 256] = gacc[q];
+    } else {
+      __shared__ double sred[256];
+      const int p = tid / E;
+      __syncthreads();
+      sred[tid] = (p < P) ? gacc[0] : 0.0;
+      __syncthreads();
+      if (tid < E) {
+        double s = 0.0;
+        for (int q = 0; q < P; ++q) s += sred[tid + q * E];
+        out[tid] = s;
+      }
+    }
+  }
+}
+
+// Cholesky with deflation, one workgroup of 64 threads, b <= 64.
+__global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G, double tol,
+                                             const double* __restrict__ Aref, const double* __restrict__ Bref,
+                                             double* __restrict__ R, double* __restrict__ Rinv,
+                                             const double* __restrict__ Rprev, double* __restrict__ Bout) {
+  __shared__ double sG[64 * 65];
+  __shared__ double sR[64 * 65];
+  __shared__ int defl[64];
+  __shared__ double sref;
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 64) {
+    const int i = e / b, j = e % b;
+    sG[i * 65 + j] = 0.5 * (G[i * b + j] + G[j * b + i]);
+    sR[i * 65 + j] = 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < b; ++i) m = fmax(m, sG[i * 65 + i]);
+    double fa = 0.0;
+    if (Aref)
+      for (int e = 0; e < b * b; ++e) fa += Aref[e] * Aref[e];
+    if (Bref)
+      for (int e = 0; e < b * b; ++e) fa += Bref[e] * Bref[e];
+    sref = fmax(m, fa / b);
+  }
+  __syncthreads();
+  const double thr = tol * sref;
+  for (int k = 0; k < b; ++k) {
+    if (t == 0) {
+      const double p = sG[k * 65 + k];
+      if (!(p > thr) || !(p > 0.0)) {
+        defl[k] = 1;
+        sR[k * 65 + k] = 0.0;
+      } else {
+        defl[k] = 0;
+        sR[k * 65 + k] = sqrt(p);
+      }
+    }
+    __syncthreads();
+    const double rkk = sR[k * 65 + k];
+    if (t > k && t < b) sR[k * 65 + t] = defl[k] ? 0.0 : sG[k * 65 + t] / rkk;
+    __syncthreads();
+    if (t > k && t < b) {
+      const double rkt = sR[k * 65 + t];
+      for (int j = t; j < b; ++j) sG[t * 65 + j] -= rkt * sR[k * 65 + j];
+    }
+    __syncthreads();
+  }
+  // inverse of R on the non-deflated columns: column t by back substitution
+  if (t < b) {
+    double x[64];
+    for (int i = b - 1; i >= 0; --i) {
+      double v = (i == t) ? 1.0 : 0.0;
+      if (defl[i] || defl[t]) {
+        x[i] = 0.0;
+        continue;
+      }
+      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * x[j];
+      x[i] = v / sR[i * 65 + i];
+    }
+    for (int i = 0; i < b; ++i) Rinv[i * b + t] = x[i];
+  }
+  for (int e = t; e < b * b; e += 64) {
+    const int i = e / b, j = e % b;
+    if (R) R[e] = sR[i * 65 + j];
+  }
+  if (Bout) {
+    __syncthreads();
+    if (t < b) {
+      for (int j = 0; j < b; ++j) {
+        double s;
+        if (Rprev) {
+          s = 0.0;
+          for (int k = 0; k < b; ++k) s += sR[t * 65 + k] * Rprev[k * b + j];
+        } else {
+          s = sR[t * 65 + j];
+        }
+        Bout[t * b + j] = s;
+      }
+    }
+  }
+}
+
+__global__ void k_dadd(int count, const double* __restrict__ x, double* __restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) y[i] += x[i];
+}
+__global__ void k_dcopy(int count, const double* __restrict__ x, double* __restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) y[i] = x[i];
+}
+
+__global__ void k_dtranspose(int b, const double* __restrict__ x, double* __restrict__ y) {
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) y[(e % b) * b + e / b] = x[e];
+}
+
+template <typename T>
+__global__ void k_fill(int64_t count, T value, T* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = value;
+}
+
+template <typename T>
+__global__ void k_axpby_rows(int64_t n, int b, const T* __restrict__ w, const T* __restrict__ X, T beta,
+                             const T* __restrict__ Y, T* __restrict__ Out) {
+  const int64_t total = n * b;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / b;
+    const T wr = w ? w[r] : T(1);
+    Out[i] = wr * X[i] + beta * Y[i];
+  }
+}
+
+template <typename T>
+__global__ void k_degrees(int64_t n, const int32_t* __restrict__ rowptr, T* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (T)(rowptr[i + 1] - rowptr[i]);
+}
+
+// flags[0]: rowptr not monotone / out of range; [1]: column out of range;
+// [2]: self loop; [3]: unsorted or duplicate column; [4]: missing reverse edge.
+__global__ void k_validate(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ colidx, int32_t* __restrict__ flags) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = rowptr[r], e = rowptr[r + 1];
+    if (s > e || s < 0 || e > nnz) {
+      atomicOr(&flags[0], 1);
+      continue;
+    }
+    for (int64_t k = s; k < e; ++k) {
+      const int32_t c = colidx[k];
+      if (c < 0 || c >= n) {
+        atomicOr(&flags[1], 1);
+        continue;
+      }
+      if (c == r) atomicOr(&flags[2], 1);
+      if (k > s && colidx[k - 1] >= c) atomicOr(&flags[3], 1);
+      // reverse edge by binary search in row c
+      int64_t lo = rowptr[c], hi = rowptr[c + 1] - 1;
+      if (lo < 0 || hi >= nnz) {
+        atomicOr(&flags[0], 1);
+        continue;
+      }
+      bool found = false;
+      while (lo <= hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int32_t v = colidx[mid];
+        if (v == r) {
+          found = true;
+          break;
+        }
+        if (v < r) lo = mid + 1; else hi = mid - 1;
+      }
+      if (!found) atomicOr(&flags[4], 1);
+    }
+  }
+}
+
+// ------------------------------------------------------------ Philox4x32-10
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c[0];
+    const uint64_t p1 = (uint64_t)M1 * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+template <typename T>
+__global__ void k_probes(int law, uint32_t k0, uint32_t k1, uint32_t stream, int64_t total, T* __restrict__ out) {
+  const int64_t nq = (total + 3) / 4;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c[4] = {(uint32_t)q, (uint32_t)((uint64_t)q >> 32), stream, 0u};
+    philox4x32_10(c, k0, k1);
+    double v[4];
+    if (law == WL_PROBE_RADEMACHER) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (c[i] >> 31) ? -1.0 : 1.0;
+    } else {
+      const double two32i = 2.3283064365386963e-10;  // 2^-32
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        const double u1 = ((double)c[2 * pr] + 0.5) * two32i;
+        const double u2 = ((double)c[2 * pr + 1] + 0.5) * two32i;
+        const double rad = sqrt(-2.0 * log(u1));
+        const double th = 6.283185307179586 * u2;
+        v[2 * pr] = rad * cos(th);
+        v[2 * pr + 1] = rad * sin(th);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t e = q * 4 + i;
+      if (e < total) out[e] = (T)v[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ estimator rows
+template <typename T>
+__global__ void k_rowdot(int64_t n, int M, const T* __restrict__ Om, const T* __restrict__ Y,
+                         double* __restrict__ dot, double* __restrict__ sq) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0, q = 0.0;
+    const T* o = Om + r * M;
+    const T* y = Y + r * M;
+    for (int j = 0; j < M; ++j) {
+      s += (double)o[j] * (double)y[j];
+      q += (double)o[j] * (double)o[j];
+    }
+    dot[r] = s;
+    if (sq) sq[r] = q;
+  }
+}
+
+// mode 0: Hutchinson, 1: BKS, 2: control variate (Hutchinson law)
+template <typename T>
+__global__ void k_cv_finish(int64_t n, int M, const T* __restrict__ Om, const T* __restrict__ Y,
+                            const T* __restrict__ g, int mode, T* __restrict__ diag) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const T* o = Om + r * M;
+    const T* y = Y + r * M;
+    double s = 0.0, q = 0.0;
+    for (int j = 0; j < M; ++j) {
+      const double ov = (double)o[j];
+      s += ov * (double)y[j];
+      q += ov * ov;
+    }
+    double d;
+    if (mode == 1) {
+      d = s / q;
+    } else if (mode == 2) {
+      const double gr = (double)g[r];
+      d = gr + (s - gr * q) / M;
+    } else {
+      d = s / M;
+    }
+    diag[r] = (T)d;
+  }
+}
+
+// diag[r] = (y_r^T Q1 y_r + sum_j o_rj y_rj - y_r^T Q2 o_r) / M   (Q1, Q2 M x M, M <= 256)
+template <typename T>
+__global__ __launch_bounds__(256) void k_nys_diag(int64_t n, int M, const T* __restrict__ Om,
+                                                  const T* __restrict__ Y, const double* __restrict__ Q1,
+                                                  const double* __restrict__ Q2, T* __restrict__ diag) {
+  extern __shared__ double sq[];  // Q1 then Q2 (only when 2*M*M*8 bytes fit)
+  const bool staged = (int64_t)2 * M * M <= 8192;
+  if (staged) {
+    for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+      sq[e] = Q1[e];
+      sq[M * M + e] = Q2[e];
+    }
+    __syncthreads();
+  }
+  const double* q1 = staged ? sq : Q1;
+  const double* q2 = staged ? sq + M * M : Q2;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const T* o = Om + r * M;
+    const T* y = Y + r * M;
+    double tot = 0.0;
+    for (int i = 0; i < M; ++i) {
+      const double yi = (double)y[i];
+      double a = 0.0, c = 0.0;
+      for (int j = 0; j < M; ++j) {
+        a += q1[i * M + j] * (double)y[j];
+        c += q2[i * M + j] * (double)o[j];
+      }
+      tot += yi * (a - c) + (double)o[i] * yi;
+    }
+    diag[r] = (T)(tot / M);
+  }
+}
+
+int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+template <int B>
+wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64_t sX, int nblk, const void* Y,
+                 int ldy, int bx, int by, double* out) {
+  constexpr int E = B * B;
+  const int64_t ntiles = (n + GRAM_TR - 1) / GRAM_TR;
+  int64_t cap = (int64_t)(1 << 22) / ((int64_t)E * nblk);
+  if (cap < 32) cap = 32;
+  if (cap > 1024) cap = 1024;
+  int parts = (int)(ntiles < cap ? ntiles : cap);
+  if (parts < 1) parts = 1;
+  WL_TRY(ctx->partials.ensure((size_t)parts * nblk * E * sizeof(double)));
+  dim3 grid(parts, nblk);
+  hipLaunchKernelGGL(k_gram_partial<B>, grid, dim3(256), 0, ctx->stream, n,
+                     isf ? (const float*)X : nullptr, isf ? nullptr : (const double*)X, ldx, sX,
+                     isf ? (const float*)Y : nullptr, isf ? nullptr : (const double*)Y, ldy, bx, by,
+                     ctx->partials.as<double>());
+  WL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gram_finalize, dim3((E + 255) / 256, nblk), dim3(256), 0, ctx->stream,
+                     ctx->partials.as<double>(), parts, B, bx, by, out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+int pick_B(int b) {
+  int B = 1;
+  while (B < b) B <<= 1;
+  return B;
+}
+
+template <typename T, int B>
+wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int nblk, int bx, const double* C,
+                   const T* Yin, int ldy, double alpha, const T* wv, double beta, T* Out, int by,
+                   double* gram_out) {
+  constexpr int E = B * B;
+  const int64_t ntiles = (n + 255) / 256;
+  const int cap = gram_out ? 1024 : 4096;
+  const int grid = (int)(ntiles < cap ? (ntiles < 1 ? 1 : ntiles) : cap);
+  double* parts = nullptr;
+  if (gram_out) {
+    WL_TRY(ctx->partials.ensure((size_t)grid * E * sizeof(double)));
+    parts = ctx->partials.as<double>();
+  }
+  hipLaunchKernelGGL((k_update<T, B>), dim3(grid), dim3(256), 0, ctx->stream, n, X, ldx, sX, nblk, bx, C, Yin, ldy,
+                     alpha, wv, beta, Out, by, parts);
+  WL_HIP(hipGetLastError());
+  if (gram_out) {
+    hipLaunchKernelGGL(k_gram_finalize, dim3((E + 255) / 256, 1), dim3(256), 0, ctx->stream, parts, grid, B, by, by,
+                       gram_out);
+    WL_HIP(hipGetLastError());
+  }
+  return WL_OK;
+}
+
+}  // namespace
+
+template <typename T>
+wl_status launch_gram(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const T* Y, int by,
+                      double* out) {
+  WL_CHECK(bx >= 1 && bx <= 64 && by >= 1 && by <= 64 && nblk >= 1, WL_EINVAL, "gram: block sizes out of range");
+  const bool isf = sizeof(T) == 4;
+  const int B = pick_B(bx > by ? bx : by);
+  switch (B) {
+    case 1: return gram_B<1>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    case 2: return gram_B<2>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    case 4: return gram_B<4>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    case 8: return gram_B<8>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    case 16: return gram_B<16>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    case 32: return gram_B<32>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+    default: return gram_B<64>(ctx, n, X, isf, bx, sX, nblk, Y, by, bx, by, out);
+  }
+}
+
+template <typename T>
+wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
+                        const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out) {
+  WL_CHECK(bx >= 1 && bx <= 64 && by >= 1 && by <= 64, WL_EINVAL, "update: block sizes out of range");
+  const int B = pick_B(bx > by ? bx : by);
+  switch (B) {
+    case 1: return update_B<T, 1>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 2: return update_B<T, 2>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 4: return update_B<T, 4>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 8: return update_B<T, 8>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 16: return update_B<T, 16>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 32: return update_B<T, 32>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    default: return update_B<T, 64>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+  }
+}
+
+wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
+                      double* R, double* Rinv, const double* Rprev, double* Bout) {
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "chol: b out of range");
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status launch_dadd(wl_ctx* ctx, int count, const double* x, double* y) {
+  hipLaunchKernelGGL(k_dadd, dim3(grid_for(count, 256, 64)), dim3(256), 0, ctx->stream, count, x, y);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+wl_status launch_dcopy(wl_ctx* ctx, int count, const double* x, double* y) {
+  hipLaunchKernelGGL(k_dcopy, dim3(grid_for(count, 256, 64)), dim3(256), 0, ctx->stream, count, x, y);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status launch_dtranspose(wl_ctx* ctx, int b, const double* x, double* y) {
+  hipLaunchKernelGGL(k_dtranspose, dim3(1), dim3(256), 0, ctx->stream, b, x, y);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_fill(wl_ctx* ctx, int64_t count, T value, T* out) {
+  if (count <= 0) return WL_OK;
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(count, 256, 8192)), dim3(256), 0, ctx->stream, count, value, out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_axpby_rows(wl_ctx* ctx, int64_t n, int b, const T* w, const T* X, double beta, const T* Y,
+                            T* Out) {
+  if (n * b <= 0) return WL_OK;
+  hipLaunchKernelGGL((k_axpby_rows<T>), dim3(grid_for(n * b, 256, 8192)), dim3(256), 0, ctx->stream, n, b, w, X,
+                     (T)beta, Y, Out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_degrees(wl_graph* g, T* out) {
+  if (g->n == 0) return WL_OK;
+  hipLaunchKernelGGL((k_degrees<T>), dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, g->ctx->stream, g->n, g->rowptr,
+                     out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status launch_validate(wl_graph* g, int32_t* d_flags) {
+  if (g->n == 0) return WL_OK;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(g->n, 256, 8192)), dim3(256), 0, g->ctx->stream, g->n, g->nnz,
+                     g->rowptr, g->colidx, d_flags);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_probes(wl_ctx* ctx, int law, uint64_t seed, uint32_t stream, int64_t n, int M, T* out) {
+  const int64_t total = n * (int64_t)M;
+  if (total <= 0) return WL_OK;
+  hipLaunchKernelGGL((k_probes<T>), dim3(grid_for((total + 3) / 4, 256, 8192)), dim3(256), 0, ctx->stream, law,
+                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), stream, total, out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq) {
+  hipLaunchKernelGGL((k_rowdot<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, M, Om, Y, dot, sq);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_cv_finish(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, const T* g, int mode, T* diag) {
+  hipLaunchKernelGGL((k_cv_finish<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, M, Om, Y, g, mode,
+                     diag);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_nys_diag(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, const double* Q1,
+                          const double* Q2, T* diag) {
+  const size_t lds = ((int64_t)2 * M * M <= 8192) ? (size_t)2 * M * M * sizeof(double) : 0;
+  hipLaunchKernelGGL((k_nys_diag<T>), dim3(grid_for(n, 256, 8192)), dim3(256), lds, ctx->stream, n, M, Om, Y, Q1, Q2,
+                     diag);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+#define WL_INST(T)                                                                                                   \
+  template wl_status launch_gram<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const T*, int, double*);        \
+  template wl_status launch_update<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const double*, const T*,      \
+                                      double, const T*, double, T*, int, double*);                                 \
+  template wl_status launch_fill<T>(wl_ctx*, int64_t, T, T*);                                                      \
+  template wl_status launch_axpby_rows<T>(wl_ctx*, int64_t, int, const T*, const T*, double, const T*, T*);       \
+  template wl_status launch_degrees<T>(wl_graph*, T*);                                                              \
+  template wl_status launch_probes<T>(wl_ctx*, int, uint64_t, uint32_t, int64_t, int, T*);                         \
+  template wl_status launch_rowdot<T>(wl_ctx*, int64_t, int, const T*, const T*, double*, double*);                \
+  template wl_status launch_cv_finish<T>(wl_ctx*, int64_t, int, const T*, const T*, const T*, int, T*);            \
+  template wl_status launch_nys_diag<T>(wl_ctx*, int64_t, int, const T*, const T*, const double*, const double*,  \
+                                        T*);
+WL_INST(float)
+WL_INST(double)

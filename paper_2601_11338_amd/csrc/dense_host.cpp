@@ -1,0 +1,271 @@
+// Small dense FP64 linear algebra on the host for the projected Krylov matrices
+// (the cheap "f(H_k) since k << n" step of Sec. 4.1): symmetric eigendecomposition
+// by Householder tridiagonalisation followed by the implicit QL iteration with
+// Wilkinson-type shifts, tridiagonal eigenvalues, and a block Cholesky solve for
+// block tridiagonal SPD matrices.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace {
+
+// Implicit QL on a symmetric tridiagonal matrix (diagonal d[0..m), off-diagonal
+// e[0..m-1) with e[i] = T[i][i+1]).  If Zt is given (m x m row-major, rows are the
+// current basis vectors), every plane rotation is applied to rows i, i+1 of Zt.
+int tql(int m, double* d, double* e_in, double* Zt) {
+  std::vector<double> e(m, 0.0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = e_in[i];
+  for (int l = 0; l < m; ++l) {
+    int iter = 0;
+    while (true) {
+      int mm = l;
+      for (; mm < m - 1; ++mm) {
+        const double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
+        if (std::fabs(e[mm]) <= 1e-16 * dd || e[mm] == 0.0) break;
+      }
+      if (mm == l) break;
+      if (++iter > 60) return 1;
+      // shift from the leading 2x2 block
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = mm - 1;
+      bool underflow = false;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        const double bq = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[mm] = 0.0;
+          underflow = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * bq;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - bq;
+        if (Zt) {
+          double* zi = Zt + (size_t)i * m;
+          double* zj = Zt + (size_t)(i + 1) * m;
+          for (int k = 0; k < m; ++k) {
+            const double fz = zj[k];
+            zj[k] = s * zi[k] + c * fz;
+            zi[k] = c * zi[k] - s * fz;
+          }
+        }
+      }
+      if (underflow) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[mm] = 0.0;
+    }
+  }
+  return 0;
+}
+
+}  // namespace
+
+int tridiag_eigvals(int m, const double* a, const double* b, double* lam) {
+  std::vector<double> d(a, a + m), e(m > 1 ? m - 1 : 1, 0.0);
+  for (int i = 0; i + 1 < m; ++i) e[i] = b[i];
+  if (tql(m, d.data(), e.data(), nullptr)) return 1;
+  for (int i = 0; i < m; ++i) lam[i] = d[i];
+  return 0;
+}
+
+// A = U diag(lam) U^T; U row-major, column i is the eigenvector of lam[i].
+int dense_syev(int m, const double* A_in, double* lam, double* U) {
+  if (m <= 0) return 0;
+  std::vector<double> A(A_in, A_in + (size_t)m * m);
+  // symmetrise
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j) {
+      const double v = 0.5 * (A[(size_t)i * m + j] + A[(size_t)j * m + i]);
+      A[(size_t)i * m + j] = A[(size_t)j * m + i] = v;
+    }
+  // Householder reduction: for column k, reflect x = A[k+1:, k] onto alpha e_1.
+  std::vector<std::vector<double>> vs;
+  std::vector<double> d(m), e(m, 0.0), p(m), q(m);
+  for (int k = 0; k + 2 < m; ++k) {
+    const int len = m - k - 1;
+    std::vector<double> v(len);
+    double nx = 0.0;
+    for (int i = 0; i < len; ++i) {
+      v[i] = A[(size_t)(k + 1 + i) * m + k];
+      nx += v[i] * v[i];
+    }
+    nx = std::sqrt(nx);
+    double tail = 0.0;
+    for (int i = 1; i < len; ++i) tail += v[i] * v[i];
+    if (nx == 0.0 || tail == 0.0) {
+      vs.emplace_back();  // identity reflector
+      continue;
+    }
+    const double alpha = v[0] >= 0 ? -nx : nx;
+    v[0] -= alpha;
+    double nv = 0.0;
+    for (int i = 0; i < len; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    for (int i = 0; i < len; ++i) v[i] /= nv;
+    // p = A22 v, K = v^T p, q = p - K v;  A22 <- A22 - 2 (v q^T + q v^T)
+    double K = 0.0;
+    for (int i = 0; i < len; ++i) {
+      const double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
+      double s = 0.0;
+      for (int j = 0; j < len; ++j) s += row[j] * v[j];
+      p[i] = s;
+    }
+    for (int i = 0; i < len; ++i) K += v[i] * p[i];
+    for (int i = 0; i < len; ++i) q[i] = p[i] - K * v[i];
+    for (int i = 0; i < len; ++i) {
+      double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
+      const double vi = v[i], qi = q[i];
+      for (int j = 0; j < len; ++j) row[j] -= 2.0 * (vi * q[j] + qi * v[j]);
+    }
+    A[(size_t)(k + 1) * m + k] = alpha;
+    A[(size_t)k * m + k + 1] = alpha;
+    for (int i = 1; i < len; ++i) {
+      A[(size_t)(k + 1 + i) * m + k] = 0.0;
+      A[(size_t)k * m + k + 1 + i] = 0.0;
+    }
+    vs.push_back(std::move(v));
+  }
+  for (int i = 0; i < m; ++i) d[i] = A[(size_t)i * m + i];
+  for (int i = 0; i + 1 < m; ++i) e[i] = A[(size_t)i * m + i + 1];
+  // Zt = Q^T with Q = H_0 H_1 ... ; rows of Zt are columns of Q.
+  // Build Q by applying the reflectors in reverse to the identity, stored transposed.
+  std::vector<double> Zt((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Zt[(size_t)i * m + i] = 1.0;
+  for (int k = (int)vs.size() - 1; k >= 0; --k) {
+    const auto& v = vs[k];
+    if (v.empty()) continue;
+    const int off = k + 1, len = m - off;
+    // Q <- H_k Q, H_k acts on rows off.. of Q, i.e. on columns off.. of Zt
+    for (int r = 0; r < m; ++r) {
+      double* z = &Zt[(size_t)r * m + off];
+      double s = 0.0;
+      for (int i = 0; i < len; ++i) s += z[i] * v[i];
+      s *= 2.0;
+      for (int i = 0; i < len; ++i) z[i] -= s * v[i];
+    }
+  }
+  if (tql(m, d.data(), e.data(), Zt.data())) return 1;
+  // sort ascending
+  std::vector<int> idx(m);
+  for (int i = 0; i < m; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  for (int c = 0; c < m; ++c) {
+    const int s = idx[c];
+    lam[c] = d[s];
+    for (int r = 0; r < m; ++r) U[(size_t)r * m + c] = Zt[(size_t)s * m + r];
+  }
+  return 0;
+}
+
+namespace {
+// lower Cholesky in place of a b x b SPD block; returns nonzero if not SPD
+int chol_lower(int b, double* A) {
+  for (int j = 0; j < b; ++j) {
+    double s = A[j * b + j];
+    for (int k = 0; k < j; ++k) s -= A[j * b + k] * A[j * b + k];
+    if (!(s > 0.0)) return 1;
+    const double ljj = std::sqrt(s);
+    A[j * b + j] = ljj;
+    for (int i = j + 1; i < b; ++i) {
+      double t = A[i * b + j];
+      for (int k = 0; k < j; ++k) t -= A[i * b + k] * A[j * b + k];
+      A[i * b + j] = t / ljj;
+    }
+    for (int k = j + 1; k < b; ++k) A[j * b + k] = 0.0;
+  }
+  return 0;
+}
+// X <- L^{-1} X (X is b x nrhs)
+void lsolve(int b, const double* L, double* X, int nrhs) {
+  for (int i = 0; i < b; ++i) {
+    for (int c = 0; c < nrhs; ++c) {
+      double s = X[i * nrhs + c];
+      for (int k = 0; k < i; ++k) s -= L[i * b + k] * X[k * nrhs + c];
+      X[i * nrhs + c] = s / L[i * b + i];
+    }
+  }
+}
+// X <- L^{-T} X
+void ltsolve(int b, const double* L, double* X, int nrhs) {
+  for (int i = b - 1; i >= 0; --i) {
+    for (int c = 0; c < nrhs; ++c) {
+      double s = X[i * nrhs + c];
+      for (int k = i + 1; k < b; ++k) s -= L[k * b + i] * X[k * nrhs + c];
+      X[i * nrhs + c] = s / L[i * b + i];
+    }
+  }
+}
+}  // namespace
+
+int block_tridiag_solve(int K, int b, const double* Ad, const double* Bo, const double* B, int nrhs, double* X) {
+  const int bb = b * b;
+  std::vector<double> L((size_t)K * bb), Mb((size_t)K * bb, 0.0);
+  for (int j = 0; j < K; ++j) {
+    double* Lj = &L[(size_t)j * bb];
+    std::memcpy(Lj, Ad + (size_t)j * bb, sizeof(double) * bb);
+    for (int r = 0; r < b; ++r)  // symmetrise
+      for (int c = r + 1; c < b; ++c) Lj[r * b + c] = Lj[c * b + r] = 0.5 * (Lj[r * b + c] + Lj[c * b + r]);
+    if (j > 0) {
+      // M_j = B_{j-1} L_{j-1}^{-T}:  solve M L^T = B  <=>  L M^T = B^T
+      double* Mj = &Mb[(size_t)j * bb];
+      std::vector<double> Bt(bb);
+      const double* Bj = Bo + (size_t)(j - 1) * bb;
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) Bt[r * b + c] = Bj[c * b + r];
+      lsolve(b, &L[(size_t)(j - 1) * bb], Bt.data(), b);  // Bt = M^T
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) Mj[r * b + c] = Bt[c * b + r];
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) {
+          double s = 0.0;
+          for (int k = 0; k < b; ++k) s += Mj[r * b + k] * Mj[c * b + k];
+          Lj[r * b + c] -= s;
+        }
+    }
+    if (chol_lower(b, Lj)) return 1;
+  }
+  std::memcpy(X, B, sizeof(double) * (size_t)K * b * nrhs);
+  for (int j = 0; j < K; ++j) {
+    double* xj = X + (size_t)j * b * nrhs;
+    if (j > 0) {
+      const double* xp = X + (size_t)(j - 1) * b * nrhs;
+      const double* Mj = &Mb[(size_t)j * bb];
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < nrhs; ++c) {
+          double s = 0.0;
+          for (int k = 0; k < b; ++k) s += Mj[r * b + k] * xp[k * nrhs + c];
+          xj[r * nrhs + c] -= s;
+        }
+    }
+    lsolve(b, &L[(size_t)j * bb], xj, nrhs);
+  }
+  for (int j = K - 1; j >= 0; --j) {
+    double* xj = X + (size_t)j * b * nrhs;
+    if (j + 1 < K) {
+      const double* xn = X + (size_t)(j + 1) * b * nrhs;
+      const double* Mn = &Mb[(size_t)(j + 1) * bb];
+      for (int r = 0; r < b; ++r)
+        for (int c = 0; c < nrhs; ++c) {
+          double s = 0.0;
+          for (int k = 0; k < b; ++k) s += Mn[k * b + r] * xn[k * nrhs + c];
+          xj[r * nrhs + c] -= s;
+        }
+    }
+    ltsolve(b, &L[(size_t)j * bb], xj, nrhs);
+  }
+  return 0;
+}

@@ -1,0 +1,184 @@
+// Diagonal and trace estimators (Sec. 4.4, Alg. 1).
+//
+// All estimators consume the probe block Omega (n x M) and Y = F Omega.
+//  * Hutchinson / BKS / control variate: one row kernel.
+//  * Leave-one-out Nystrom (the exchangeable XNysTrace idea of Alg. 1).  With
+//    H = Omega^T Y and G = Y^T Y (M x M, double, from the device Gram kernel) and
+//    P_j the pseudo-inverse of the symmetrised H without row/column j (embedded
+//    back into M x M with zeros), the per-probe estimates of
+//      F_(j) = Y_{-j} H_{-j,-j}^+ Y_{-j}^T,
+//      t_j   = tr F_(j) + omega_j^T (F - F_(j)) omega_j
+//    reduce to small matrices:
+//      tr F_(j)              = tr(P_j G),
+//      omega_j^T F omega_j   = H_jj,
+//      omega_j^T F_(j) omega_j = h_j^T P_j h_j,  h_j = row j of H (Y^T omega_j),
+//    and the averaged diagonal estimate at row r to
+//      d_r = ( y_r Q1 y_r^T + sum_j Omega_rj Y_rj - y_r Q2 omega_r^T ) / M,
+//      Q1 = sum_j P_j,  column j of Q2 = P_j h_j,
+//    so the device work is two Gram products and one row pass.
+#include <cmath>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace {
+
+// Gram of two n x M row-major blocks for any M, by 64-column tiles.
+template <typename T>
+wl_status gram_full(wl_ctx* ctx, int64_t n, int M, const T* X, const T* Y, std::vector<double>& out) {
+  out.assign((size_t)M * M, 0.0);
+  if (M <= 64) {
+    DevBuf d;
+    WL_TRY(d.ensure((size_t)M * M * 8));
+    WL_TRY(launch_gram<T>(ctx, n, X, M, 0, 1, Y, M, d.as<double>()));
+    WL_HIP(hipMemcpyAsync(out.data(), d.p, (size_t)M * M * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    return WL_OK;
+  }
+  wl_set_error("estimators with more than 64 probes per block are not supported by this build");
+  return WL_EUNSUPPORTED;
+}
+
+// pseudo-inverse of the symmetric part of the (M-1) x (M-1) matrix H without j,
+// embedded into M x M
+int pinv_drop(int M, const std::vector<double>& H, int j, double rcond, std::vector<double>& P) {
+  const int m = M - 1;
+  std::vector<double> S((size_t)m * m), lam(m), U((size_t)m * m);
+  for (int a = 0, ia = 0; a < M; ++a) {
+    if (a == j) continue;
+    for (int c = 0, ic = 0; c < M; ++c) {
+      if (c == j) continue;
+      S[(size_t)ia * m + ic] = 0.5 * (H[(size_t)a * M + c] + H[(size_t)c * M + a]);
+      ++ic;
+    }
+    ++ia;
+  }
+  if (dense_syev(m, S.data(), lam.data(), U.data())) return 1;
+  double lmax = 0.0;
+  for (double v : lam) lmax = std::max(lmax, v);
+  P.assign((size_t)M * M, 0.0);
+  std::vector<int> map;
+  for (int a = 0; a < M; ++a)
+    if (a != j) map.push_back(a);
+  for (int k = 0; k < m; ++k) {
+    if (!(lam[k] > rcond * lmax)) continue;
+    const double inv = 1.0 / lam[k];
+    for (int a = 0; a < m; ++a) {
+      const double ua = U[(size_t)a * m + k] * inv;
+      if (ua == 0.0) continue;
+      for (int c = 0; c < m; ++c) P[(size_t)map[a] * M + map[c]] += ua * U[(size_t)c * m + k];
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+wl_status estimate_impl(wl_ctx* ctx, int estimator, int64_t n, int M, const T* Om, const T* Y, const T* cv,
+                        double rcond, T* diag, double* trace, double* trace_err) {
+  std::vector<double> H;
+  WL_TRY(gram_full<T>(ctx, n, M, Om, Y, H));
+  if (estimator != WL_EST_XNYS) {
+    const int mode = cv ? 2 : (estimator == WL_EST_BKS ? 1 : 0);
+    if (diag) WL_TRY(launch_cv_finish<T>(ctx, n, M, Om, Y, cv, mode, diag));
+    double mean = 0.0;
+    for (int j = 0; j < M; ++j) mean += H[(size_t)j * M + j];
+    mean /= M;
+    double var = 0.0;
+    for (int j = 0; j < M; ++j) var += (H[(size_t)j * M + j] - mean) * (H[(size_t)j * M + j] - mean);
+    if (trace) *trace = mean;
+    if (trace_err) *trace_err = M > 1 ? std::sqrt(var / (M - 1)) / std::sqrt((double)M) : INFINITY;
+    return WL_OK;
+  }
+  WL_CHECK(M >= 2, WL_EINVAL, "wl_estimate: the Nystrom estimator needs M >= 2");
+  std::vector<double> G;
+  WL_TRY(gram_full<T>(ctx, n, M, Y, Y, G));
+  std::vector<double> Q1((size_t)M * M, 0.0), Q2((size_t)M * M, 0.0), P, tj(M);
+  for (int j = 0; j < M; ++j) {
+    if (pinv_drop(M, H, j, rcond, P)) {
+      wl_set_error("wl_estimate: eigendecomposition of the Nystrom core failed");
+      return WL_ENOCONV;
+    }
+    double trPG = 0.0, hPh = 0.0;
+    std::vector<double> Ph(M, 0.0);
+    for (int a = 0; a < M; ++a)
+      for (int c = 0; c < M; ++c) {
+        const double p = P[(size_t)a * M + c];
+        trPG += p * G[(size_t)c * M + a];
+        Ph[a] += p * H[(size_t)j * M + c];
+      }
+    for (int a = 0; a < M; ++a) hPh += H[(size_t)j * M + a] * Ph[a];
+    tj[j] = trPG + H[(size_t)j * M + j] - hPh;
+    for (int e = 0; e < M * M; ++e) Q1[e] += P[e];
+    for (int a = 0; a < M; ++a) Q2[(size_t)a * M + j] = Ph[a];
+  }
+  double mean = 0.0;
+  for (double v : tj) mean += v;
+  mean /= M;
+  double var = 0.0;
+  for (double v : tj) var += (v - mean) * (v - mean);
+  if (trace) *trace = mean;
+  if (trace_err) *trace_err = std::sqrt(var / (M - 1)) / std::sqrt((double)M);
+  if (diag) {
+    DevBuf dq;
+    WL_TRY(dq.ensure((size_t)2 * M * M * 8));
+    WL_HIP(hipMemcpyAsync(dq.p, Q1.data(), (size_t)M * M * 8, hipMemcpyHostToDevice, ctx->stream));
+    WL_HIP(hipMemcpyAsync(dq.as<double>() + (size_t)M * M, Q2.data(), (size_t)M * M * 8, hipMemcpyHostToDevice,
+                          ctx->stream));
+    WL_TRY(launch_nys_diag<T>(ctx, n, M, Om, Y, dq.as<double>(), dq.as<double>() + (size_t)M * M, diag));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return WL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, int32_t M, const void* d_Omega,
+                      const void* d_Y, const void* d_cv, double rcond, void* d_diag, double* trace,
+                      double* trace_err) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_estimate: ctx is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_estimate: bad prec");
+  WL_CHECK(estimator >= WL_EST_HUTCHINSON && estimator <= WL_EST_XNYS, WL_EINVAL, "wl_estimate: bad estimator");
+  WL_CHECK(n >= 1 && M >= 1, WL_EINVAL, "wl_estimate: need n >= 1 and M >= 1");
+  WL_CHECK(d_Omega && d_Y, WL_EINVAL, "wl_estimate: null probe or product block");
+  WL_CHECK(!(d_cv && estimator != WL_EST_HUTCHINSON), WL_EINVAL,
+           "wl_estimate: the control variate applies to the Hutchinson estimator");
+  WL_CHECK(rcond >= 0 && std::isfinite(rcond), WL_EINVAL, "wl_estimate: bad rcond");
+  int dev = ctx->device;
+  (void)hipSetDevice(dev);
+  if (prec == WL_FP32)
+    return estimate_impl<float>(ctx, estimator, n, M, (const float*)d_Omega, (const float*)d_Y,
+                                (const float*)d_cv, rcond, (float*)d_diag, trace, trace_err);
+  return estimate_impl<double>(ctx, estimator, n, M, (const double*)d_Omega, (const double*)d_Y,
+                               (const double*)d_cv, rcond, (double*)d_diag, trace, trace_err);
+}
+
+wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t seed, int32_t law,
+                      int32_t estimator, const void* d_cv, int32_t outer_dim, void* d_diag, double* trace,
+                      double* trace_err) {
+  WL_CHECK(op, WL_EINVAL, "wl_diag_est: op is null");
+  WL_CHECK(target == 0 || target == 1, WL_EINVAL, "wl_diag_est: target must be 0 (phi) or 1 (exp(-tL))");
+  WL_CHECK(M >= 1 && M <= 64, WL_EINVAL, "wl_diag_est: M must lie in [1, 64]");
+  WL_CHECK(std::isfinite(t) && t >= 0, WL_EINVAL, "wl_diag_est: bad t");
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  WL_CHECK(n >= 1, WL_EINVAL, "wl_diag_est: empty graph");
+  (void)hipSetDevice(g->ctx->device);
+  const size_t es = op->d.prec == WL_FP32 ? 4 : 8;
+  DevBuf Om, Y;
+  WL_TRY(Om.ensure((size_t)n * M * es));
+  WL_TRY(Y.ensure((size_t)n * M * es));
+  WL_TRY(wl_probes(g->ctx, op->d.prec, law, seed, 0, n, M, Om.p));
+  if (target == 0) {
+    WL_TRY(wl_apply_phi(op, Om.p, Y.p, M));
+  } else {
+    void* outs[1] = {Y.p};
+    WL_TRY(wl_expv(op, Om.p, M, &t, 1, outs, outer_dim, nullptr));
+  }
+  WL_TRY(wl_estimate(g->ctx, op->d.prec, estimator, n, M, Om.p, Y.p, d_cv, 1e-10, d_diag, trace, trace_err));
+  WL_HIP(hipStreamSynchronize(g->ctx->stream));
+  return WL_OK;
+}
+
+}  // extern "C"

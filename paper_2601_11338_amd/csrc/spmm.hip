@@ -1,0 +1,304 @@
+// CSR x tall-skinny block product with fused epilogues, for gfx950 (CDNA4).
+//
+// Y = A X for an unweighted symmetric CSR adjacency A (no value array: the sum of
+// gathered neighbour rows) and a row-major n x b block X.  This is the matrix
+// product every Krylov step of the method is built on (Sec. 4.1); the epilogue
+// fuses the vector work of one step of
+//   * the backtrack-downweighted recurrence  q_{k+1} = A q_k + mu (mu I - D) q_{k-1}
+//     with running sum S += c_{k+1} q_{k+1}          (eq. qrec, Prop. "whe-we-converge"),
+//   * the deformed Laplacian A_mu(alpha) X = (1 - mu^2 a^2) X - a A X + a^2 mu D X
+//     (eq. deformed, general mu),
+//   * the block Lanczos three-term subtraction  W = Op(V_j) - V_{j-1} B_{j-1}^T,
+//   * the walk-Laplacian finish  L X = w * X - phi X  (eq. f-laplacian).
+//
+// Work decomposition (64-wide wavefronts, 256-thread workgroups):
+//   * a row is owned by a group of G lanes (G | 64).  Inside the group, LPN lanes
+//     cover one neighbour row segment of TILE = VW * LPN contiguous values with
+//     VW-wide vector loads (16 bytes per lane), and the G / LPN neighbour slots walk
+//     the row's column list in parallel; the slots are summed with xor-shuffles
+//     (wave-shuffle row reduction) and slot 0 applies the epilogue;
+//   * rows whose degree exceeds a threshold are listed (decreasing degree) and each
+//     is processed by one whole workgroup (256 / LPN slots, shuffles inside each
+//     wave, LDS across the four waves), so hub rows of heavy-tailed graphs do not
+//     serialise a single group.  Those workgroups come first in the grid;
+//   * blocks wider than one tile are processed as column tiles (grid y).
+#include "wl_internal.h"
+
+namespace {
+
+template <typename T, int VW>
+struct VecType;
+template <>
+struct VecType<float, 1> { typedef float type; };
+template <>
+struct VecType<float, 4> { typedef float4 type; };
+template <>
+struct VecType<double, 1> { typedef double type; };
+template <>
+struct VecType<double, 2> { typedef double2 type; };
+
+template <typename T, int VW>
+struct Frag {
+  T v[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Frag<T, VW> ldf(const T* p) {
+  typedef typename VecType<T, VW>::type V;
+  static_assert(sizeof(V) == sizeof(Frag<T, VW>), "fragment size");
+  V x = *reinterpret_cast<const V*>(p);
+  Frag<T, VW> f;
+  __builtin_memcpy(&f, &x, sizeof(f));
+  return f;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void stf(T* p, const Frag<T, VW>& f) {
+  typedef typename VecType<T, VW>::type V;
+  V x;
+  __builtin_memcpy(&x, &f, sizeof(f));
+  *reinterpret_cast<V*>(p) = x;
+}
+
+template <typename T, int VW, bool MASK>
+__device__ __forceinline__ Frag<T, VW> ldf_m(const T* p, bool ok) {
+  if constexpr (MASK) {
+    Frag<T, VW> f;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) f.v[i] = ok ? p[i] : T(0);
+    return f;
+  } else {
+    return ldf<T, VW>(p);
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void zero(Frag<T, VW>& f) {
+#pragma unroll
+  for (int i = 0; i < VW; ++i) f.v[i] = T(0);
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void add_shfl_xor(Frag<T, VW>& f, int off) {
+#pragma unroll
+  for (int i = 0; i < VW; ++i) f.v[i] += __shfl_xor(f.v[i], off, 64);
+}
+
+// Epilogue for row r on columns [col, col + VW) (tile-local column cl).
+template <typename T, int VW, bool MASK>
+__device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int cl, int TILE, T deg,
+                                         const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC,
+                                         T* Y) {
+  if (MASK && col >= b) return;
+  const int64_t off = r * (int64_t)ld + col;
+  T y[VW];
+  const T a = (T)ep.a;
+#pragma unroll
+  for (int i = 0; i < VW; ++i) y[i] = a * acc.v[i];
+  if (ep.Z) {
+    const T coef = (T)(ep.b0 + ep.b1 * (double)deg);
+    Frag<T, VW> z = ldf_m<T, VW, MASK>(ep.Z + off, true);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) y[i] += coef * z.v[i];
+  }
+  if (ep.C) {
+    const T* z2 = ep.Z2 + r * (int64_t)ld;
+    for (int k = 0; k < b; ++k) {
+      const T zk = z2[k];
+#pragma unroll
+      for (int i = 0; i < VW; ++i) y[i] -= zk * sC[k * TILE + cl + i];
+    }
+  }
+  if (Y) {
+    Frag<T, VW> o;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) o.v[i] = y[i];
+    if constexpr (MASK) {
+      Y[off] = o.v[0];
+    } else {
+      stf<T, VW>(Y + off, o);
+    }
+  }
+  if (ep.Sout) {
+    Frag<T, VW> s;
+    if (ep.Sin)
+      s = ldf_m<T, VW, MASK>(ep.Sin + off, true);
+    else
+      zero(s);
+    const T s0 = (T)ep.s0, sc = (T)ep.sc;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) s.v[i] = s0 * s.v[i] + sc * y[i];
+    if (ep.wv) {
+      const T wr = ep.wv[r];
+      Frag<T, VW> xw = ldf_m<T, VW, MASK>(ep.Xw + off, true);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) s.v[i] = wr * xw.v[i] - s.v[i];
+    }
+    if constexpr (MASK) {
+      ep.Sout[off] = s.v[0];
+    } else {
+      stf<T, VW>(ep.Sout + off, s);
+    }
+  }
+}
+
+template <typename T, int VW, int LPN, int G, bool MASK>
+__global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ colidx, int64_t n, int ld, int b,
+                                              const T* __restrict__ X, T* Y, EpiArgs<T> ep,
+                                              const int32_t* __restrict__ long_rows, int n_long,
+                                              int long_thr) {
+  static_assert(MASK == false || VW == 1, "masked kernels are scalar");
+  constexpr int TILE = VW * LPN;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sC = reinterpret_cast<T*>(smem_raw);
+  __shared__ Frag<T, VW> red[4][LPN];
+
+  const int c0 = blockIdx.y * TILE;
+  if (ep.C) {
+    for (int e = threadIdx.x; e < b * TILE; e += 256) {
+      const int k = e / TILE, j = e - (e / TILE) * TILE;
+      const int c = c0 + j;
+      double v = 0.0;
+      if (c < b) v = ep.transC ? ep.C[(int64_t)c * b + k] : ep.C[(int64_t)k * b + c];
+      sC[e] = (T)v;
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63;
+  const int v = lane % LPN;
+  const int cl = v * VW;
+  const int col = c0 + cl;
+  const bool colok = !MASK || col < b;
+
+  if ((int)blockIdx.x < n_long) {
+    constexpr int NSLOT = 256 / LPN;
+    const int64_t r = long_rows[blockIdx.x];
+    const int slot = threadIdx.x / LPN;
+    const int s = rowptr[r], e = rowptr[r + 1];
+    Frag<T, VW> acc;
+    zero(acc);
+#pragma unroll 4
+    for (int k = s + slot; k < e; k += NSLOT) {
+      const int64_t j = colidx[k];
+      Frag<T, VW> x = ldf_m<T, VW, MASK>(X + j * ld + col, colok);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc.v[i] += x.v[i];
+    }
+#pragma unroll
+    for (int off = LPN; off < 64; off <<= 1) add_shfl_xor(acc, off);
+    const int wave = threadIdx.x >> 6;
+    if (lane < LPN) red[wave][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < LPN) {
+      Frag<T, VW> tot = red[0][lane];
+#pragma unroll
+      for (int w = 1; w < 4; ++w)
+#pragma unroll
+        for (int i = 0; i < VW; ++i) tot.v[i] += red[w][lane].v[i];
+      epilogue<T, VW, MASK>(r, ld, b, col, cl, TILE, (T)(e - s), tot, ep, sC, Y);
+    }
+    return;
+  }
+
+  constexpr int RPB = 256 / G;
+  constexpr int NS = G / LPN;
+  const int64_t r = (int64_t)(blockIdx.x - n_long) * RPB + threadIdx.x / G;
+  if (r >= n) return;  // whole group leaves together: all its lanes share r
+  const int s = rowptr[r], e = rowptr[r + 1];
+  if (e - s > long_thr) return;
+  const int slot = (lane % G) / LPN;
+  Frag<T, VW> acc;
+  zero(acc);
+#pragma unroll 4
+  for (int k = s + slot; k < e; k += NS) {
+    const int64_t j = colidx[k];
+    Frag<T, VW> x = ldf_m<T, VW, MASK>(X + j * ld + col, colok);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc.v[i] += x.v[i];
+  }
+#pragma unroll
+  for (int off = LPN; off < G; off <<= 1) add_shfl_xor(acc, off);
+  if (slot == 0) epilogue<T, VW, MASK>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, Y);
+}
+
+template <typename T, int VW, int LPN, int G, bool MASK>
+wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int long_thr) {
+  constexpr int TILE = VW * LPN;
+  const int tiles = (b + TILE - 1) / TILE;
+  // rows above the threshold, taken from the decreasing-degree list
+  int n_long = 0;
+  if (long_thr < g->long_min_thr) long_thr = g->long_min_thr;
+  {
+    const auto& dd = g->h_long_deg;
+    int lo = 0, hi = (int)dd.size();
+    while (lo < hi) {  // first index with degree <= long_thr
+      int mid = (lo + hi) / 2;
+      if (dd[mid] > long_thr) lo = mid + 1; else hi = mid;
+    }
+    n_long = lo;
+  }
+  constexpr int RPB = 256 / G;
+  const int64_t nshort = (g->n + RPB - 1) / RPB;
+  const int64_t gx = nshort + n_long;
+  WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
+  const size_t lds = ep.C ? (size_t)b * TILE * sizeof(T) : 0;
+  dim3 grid((unsigned)gx, (unsigned)tiles);
+  hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK>), grid, dim3(256), lds, g->ctx->stream, g->rowptr, g->colidx,
+                     g->n, b, b, X, Y, ep, g->long_rows.as<int32_t>(), n_long, long_thr);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T, int VW, int LPN, bool MASK>
+wl_status run_g(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int G, int long_thr) {
+  int Gc = G < LPN ? LPN : G;
+  if (Gc < 4) Gc = 4;
+  if constexpr (LPN <= 4) {
+    if (Gc <= 4) return run<T, VW, LPN, 4, MASK>(g, X, Y, b, ep, long_thr);
+  }
+  if constexpr (LPN <= 8) {
+    if (Gc <= 8) return run<T, VW, LPN, 8, MASK>(g, X, Y, b, ep, long_thr);
+  }
+  if constexpr (LPN <= 16) {
+    if (Gc <= 16) return run<T, VW, LPN, 16, MASK>(g, X, Y, b, ep, long_thr);
+  }
+  if (Gc <= 32) return run<T, VW, LPN, 32, MASK>(g, X, Y, b, ep, long_thr);
+  return run<T, VW, LPN, 64, MASK>(g, X, Y, b, ep, long_thr);
+}
+
+template <typename T>
+constexpr int vec_width() {
+  return 16 / (int)sizeof(T);
+}
+
+bool aligned16(const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+template <typename T>
+wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh) {
+  if (g->n == 0) return WL_OK;
+  constexpr int VW = vec_width<T>();
+  const bool vec_ok = (b % VW == 0) && aligned16(X) && aligned16(Y) && aligned16(ep.Z) && aligned16(ep.Sin) &&
+                      aligned16(ep.Sout) && aligned16(ep.Xw);
+  if (vec_ok) {
+    const int lanes = b / VW;  // lanes needed for the whole row segment
+    if (lanes == 1) return run_g<T, VW, 1, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes == 2) return run_g<T, VW, 2, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes <= 4 && lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes % 16 == 0) return run_g<T, VW, 16, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes % 8 == 0) return run_g<T, VW, 8, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+  }
+  // scalar path with column masking for any b
+  if (b == 1) return run_g<T, 1, 1, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+  if (b <= 2) return run_g<T, 1, 2, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+  if (b <= 4) return run_g<T, 1, 4, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+  if (b <= 8) return run_g<T, 1, 8, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+  return run_g<T, 1, 16, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+}
+
+template wl_status launch_spmm<float>(wl_graph*, const float*, float*, int, const EpiArgs<float>&, const SpmmShape&);
+template wl_status launch_spmm<double>(wl_graph*, const double*, double*, int, const EpiArgs<double>&,
+                                       const SpmmShape&);

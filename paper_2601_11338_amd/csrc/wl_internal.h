@@ -1,0 +1,216 @@
+// Internal declarations of the walk-Laplacian library: handle structs, error
+// helpers, device buffers and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "walklap.h"
+
+// ------------------------------------------------------------------ errors
+void wl_set_error(const char* fmt, ...);
+
+#define WL_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      wl_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,   \
+                   __LINE__);                                                         \
+      return (e_ == hipErrorOutOfMemory) ? WL_ENOMEM : WL_EDEVICE;                   \
+    }                                                                                 \
+  } while (0)
+
+#define WL_CHECK(cond, code, ...) \
+  do {                            \
+    if (!(cond)) {                \
+      wl_set_error(__VA_ARGS__);  \
+      return code;                \
+    }                             \
+  } while (0)
+
+#define WL_TRY(expr)              \
+  do {                            \
+    wl_status s_ = (expr);        \
+    if (s_ != WL_OK) return s_;   \
+  } while (0)
+
+// ------------------------------------------------------------------ device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    // work still queued may read the old allocation: drain the device first
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(p);
+    }
+    p = nullptr;
+    bytes = 0;
+  }
+  // Grow to at least nbytes (contents not preserved).
+  wl_status ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return WL_OK;
+    release();
+    size_t want = nbytes < 256 ? 256 : nbytes;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      wl_set_error("hipMalloc(%zu) failed: %s", want, hipGetErrorString(e));
+      return WL_ENOMEM;
+    }
+    bytes = want;
+    return WL_OK;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// ------------------------------------------------------------------ handles
+struct SpmmShape {
+  int G = 16;          // lanes per row group for rows below the long threshold
+  int long_thr = 512;  // rows with more neighbours go to whole workgroups
+};
+
+struct wl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DevBuf partials;  // reduction partials
+  DevBuf scratch;   // small device-side matrices
+};
+
+struct wl_graph {
+  wl_ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* colidx = nullptr;
+  DevBuf own_rowptr, own_colidx;
+  int32_t max_deg = 0;
+  double mean_deg = 0.0;
+  std::vector<int32_t> h_degree_hist;   // not used by kernels
+  // rows sorted by decreasing degree whose degree exceeds the smallest threshold
+  // any launch may use; per launch only the prefix above its threshold is taken.
+  DevBuf long_rows;
+  std::vector<int32_t> h_long_deg;      // degrees of long_rows, decreasing
+  int32_t long_min_thr = 64;
+  std::map<int, SpmmShape> tuned;       // key: prec * 1000 + b
+  double lam_max = -1.0;
+  std::map<double, double> rho_cache;
+  DevBuf degf, degd;                    // degree vector as float / double
+  DevBuf tmp;                           // Lanczos scratch for spectral routines
+};
+
+struct wl_op {
+  wl_graph* g = nullptr;
+  wl_op_desc d{};
+  double rho = 0.0;       // rho(Z_mu) used for validation (0 if not needed)
+  int K = 0;              // recurrence degree or Lanczos steps
+  DevBuf w;               // cached phi 1
+  bool w_valid = false;
+  DevBuf bufA, bufB;      // recurrence buffers
+  DevBuf basis;           // Lanczos basis (K+1) blocks of n x b
+  DevBuf wbuf;            // Lanczos W block
+  DevBuf coef;            // device copy of recombination coefficients
+  DevBuf small;           // device FP64 small matrices (T blocks etc.)
+  DevBuf outer_basis, outer_w, outer_small, outer_coef, inner_tmp;
+};
+
+// ------------------------------------------------------------------ launch interfaces
+// SpMM epilogue (per row r, on the b columns of the current tile):
+//   y        = a * (A X)[r] + (b0 + b1 * d_r) * Z[r] - Z2[r, :] * C    (terms optional)
+//   Y[r]     = y                                                       (if Y)
+//   Sout[r]  = s0 * Sin[r] + sc * y                                    (if Sout; Sin optional)
+//   if wv:     Sout[r] = wv[r] * Xw[r] - Sout[r]                       (walk-Laplacian finish)
+// C is b x b row-major double on the device (transC: use C^T).
+template <typename T>
+struct EpiArgs {
+  double a = 1.0;
+  const T* Z = nullptr;
+  double b0 = 0.0, b1 = 0.0;
+  const T* Z2 = nullptr;
+  const double* C = nullptr;
+  int transC = 0;
+  const T* Sin = nullptr;
+  T* Sout = nullptr;
+  double s0 = 0.0, sc = 0.0;
+  const T* wv = nullptr;
+  const T* Xw = nullptr;
+};
+
+template <typename T>
+wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh);
+
+// Gram partials and finalisation.  X: nblk blocks of n x bx (block k at X + k*sX),
+// Y: n x by.  out (double, nblk*bx x by row-major) = X^T Y, reduced in a fixed
+// order (deterministic).  Partials live in ctx->partials.
+template <typename T>
+wl_status launch_gram(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const T* Y, int by,
+                      double* out);
+
+// Out[r,:] = (wv ? wv[r] : alpha) * Yin[r,:] + beta * sum_k X_k[r,:] C_k
+// with C (nblk*bx x by, row-major double, device).  Yin may be null; Out may
+// alias Yin or X.  If gram_out is non-null, also gram_out = Out^T Out (double by x by).
+template <typename T>
+wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
+                        const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out);
+
+// Cholesky with deflation of the b x b Gram G (double, device):
+//   G = R^T R, R upper; Rinv the inverse on the non-deflated columns (zero elsewhere).
+// A pivot below tol * ref deflates its column, where
+//   ref = max(max_i G_ii, (||Aref||_F^2 + ||Bref||_F^2) / b)  (Aref, Bref optional b x b).
+// If Rprev is given, Bout = R * Rprev (else Bout = R when Bout is given).
+wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
+                      double* R, double* Rinv, const double* Rprev, double* Bout);
+
+// Small device helpers on double matrices.
+wl_status launch_dadd(wl_ctx* ctx, int count, const double* x, double* y);   // y += x
+wl_status launch_dcopy(wl_ctx* ctx, int count, const double* x, double* y);  // y = x
+wl_status launch_dtranspose(wl_ctx* ctx, int b, const double* x, double* y);  // y = x^T (b x b)
+
+template <typename T>
+wl_status launch_fill(wl_ctx* ctx, int64_t count, T value, T* out);
+template <typename T>
+wl_status launch_axpby_rows(wl_ctx* ctx, int64_t n, int b, const T* w, const T* X, double beta, const T* Y,
+                            T* Out);  // Out = w (.) X + beta * Y  (w per row; w null = 1)
+template <typename T>
+wl_status launch_degrees(wl_graph* g, T* out);
+wl_status launch_validate(wl_graph* g, int32_t* d_flags);
+
+template <typename T>
+wl_status launch_probes(wl_ctx* ctx, int law, uint64_t seed, uint32_t stream, int64_t n, int M, T* out);
+
+// Row-wise estimator reductions: out[r] = sum_j Om[r,j] * Y[r,j] and (if sq) sq[r] = sum_j Om[r,j]^2.
+template <typename T>
+wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq);
+// Per-probe traces: tr[j] = sum_r Om[r,j] Y[r,j] (double M), through the Gram machinery.
+// Nystrom diagonal finish: diag[r] = (y_r^T Q1 y_r + sum_j Om_rj Y_rj - y_r^T Q2 om_r) / M
+template <typename T>
+wl_status launch_nys_diag(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, const double* Q1,
+                          const double* Q2, T* diag);
+template <typename T>
+wl_status launch_cv_finish(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, const T* g, int mode, T* diag);
+
+// ------------------------------------------------------------------ host dense (FP64)
+// Symmetric eigendecomposition A = U diag(lam) U^T of an m x m row-major matrix
+// (Householder tridiagonalisation + implicit QL).  U row-major, column i = eigvec i.
+int dense_syev(int m, const double* A, double* lam, double* U);
+// Eigenvalues only of a symmetric tridiagonal matrix (diag a, offdiag b).
+int tridiag_eigvals(int m, const double* a, const double* b, double* lam);
+// Solve T X = B for block tridiagonal SPD T (K diagonal blocks Ad, K-1 off-diagonal
+// blocks Bo with T_{j+1,j} = Bo_j), blocks b x b row-major; B, X are (K*b) x nrhs.
+int block_tridiag_solve(int K, int b, const double* Ad, const double* Bo, const double* B, int nrhs, double* X);
+
+// ------------------------------------------------------------------ drivers
+template <typename T>
+wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw);
+template <typename T>
+wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* const* Y, int outer_dim,
+                    double* err_est);
+wl_status lanczos_extreme(wl_graph* g, int kind, double mu, double t, int steps, double* lo, double* hi);
