@@ -119,6 +119,15 @@ wl_status wl_ctx_set_stream(wl_ctx* ctx, void* stream);
 wl_status wl_ctx_synchronize(wl_ctx* ctx);
 wl_status wl_ctx_destroy(wl_ctx* ctx);
 
+/* Opt-in live timing of kernel classes on the context stream (HIP events around every
+ * launch of the class) with the algorithmic bytes each launch must move (CSR once,
+ * the gathered block once, every row-aligned input / output block once).  Turning
+ * profiling on or off clears the statistics.  Classes: 0 fused recurrence step
+ * (degree >= 2), 1 block Lanczos operator product, 2 other sparse products.        */
+wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on);
+wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launches, double* total_ms,
+                              double* alg_bytes);
+
 /* ---------------------------------------------------------------- graph (Sec. 2)
  * A simple undirected unweighted graph as symmetric CSR: d_rowptr (n+1 int32),
  * d_colidx (nnz int32), columns strictly increasing within a row, no self loops,

@@ -103,7 +103,7 @@ def deformed(A, mu, alpha):
     return sp.diags((1.0 - mu * mu * alpha * alpha) + alpha * alpha * mu * d) - alpha * A
 
 
-def phi_res_apply(A, mu, alpha, X, rtol=1e-14, direct_max_n=200000):
+def phi_res_apply(A, mu, alpha, X, rtol=1e-14, direct_max_n=3000):
     """(1 - mu^2 alpha^2) A_mu(alpha)^{-1} X (eq. deformed, general mu)."""
     M = deformed(A, mu, alpha).tocsc()
     X = np.asarray(X, dtype=np.float64)

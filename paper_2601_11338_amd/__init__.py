@@ -71,6 +71,15 @@ class Context:
     def synchronize(self):
         check(load().wl_ctx_synchronize(self.handle))
 
+    def set_profiling(self, on):
+        check(load().wl_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def kernel_stats(self, kernel_class):
+        """(launches, total_ms, algorithmic_bytes) of a timed kernel class."""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        check(load().wl_ctx_kernel_stats(self.handle, int(kernel_class), C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             load().wl_ctx_destroy(self.handle)

@@ -151,11 +151,47 @@ wl_status wl_ctx_synchronize(wl_ctx* ctx) {
   return WL_OK;
 }
 
+wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_ctx_set_profiling: ctx is null");
+  DeviceGuard dg(ctx->device);
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& k : ctx->kstats) {
+    k.launches = 0;
+    k.bytes = 0.0;
+    k.used = 0;
+  }
+  ctx->profiling = on != 0;
+  return WL_OK;
+}
+
+wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kclass, int64_t* launches, double* total_ms, double* alg_bytes) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_ctx_kernel_stats: ctx is null");
+  WL_CHECK(kclass >= 0 && kclass < WL_KC_COUNT, WL_EINVAL, "wl_ctx_kernel_stats: unknown kernel class");
+  DeviceGuard dg(ctx->device);
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  KernelStats& k = ctx->kstats[kclass];
+  double ms = 0.0;
+  for (size_t i = 0; i < k.used; ++i) {
+    float e = 0.f;
+    WL_HIP(hipEventElapsedTime(&e, k.events[i].first, k.events[i].second));
+    ms += e;
+  }
+  if (launches) *launches = k.launches;
+  if (total_ms) *total_ms = ms;
+  if (alg_bytes) *alg_bytes = k.bytes;
+  return WL_OK;
+}
+
 wl_status wl_ctx_destroy(wl_ctx* ctx) {
   if (!ctx) return WL_OK;
   {
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto& k : ctx->kstats)
+      for (auto& e : k.events) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
     ctx->partials.release();
     ctx->scratch.release();
   }
@@ -403,6 +439,7 @@ wl_status apply_lanczos_op(wl_graph* g, const LanczosOp<T>& L, const T* V, T* W,
       ep.C = Bprev;
       ep.transC = 1;
     }
+    ep.kclass = WL_KC_LANCZOS_OP;
     return launch_spmm<T>(g, V, W, b, ep, shape_for(g, prec_of<T>(), b));
   }
   // walk Laplacian: W = w (.) V - phi V, then the three-term subtraction
@@ -626,6 +663,7 @@ wl_status phi_recurrence(wl_op* op, const T* X, T* Y, int b, const T* wv, const 
       ep.wv = wv;
       ep.Xw = Xw;
     }
+    ep.kclass = b >= 4 ? WL_KC_RECURRENCE : WL_KC_OTHER_SPMM;
     // P_k overwrites the buffer of P_{k-2} (row r of P_{k-2} is read and row r of
     // P_k written by the same lanes); P_0 = X is never overwritten.
     T* out = (k == 2) ? spare : const_cast<T*>(Pm2);

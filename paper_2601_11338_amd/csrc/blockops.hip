@@ -89,18 +89,136 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, const float* __
   }
 }
 
-// out[(k*bx + i)*by + j] = sum over partial blocks (fixed order)
-__global__ void k_gram_finalize(const double* __restrict__ partials, int nparts, int B, int bx, int by,
-                                double* __restrict__ out) {
+// out[(k*bx + i)*by + j] = sum_q partials[k][q][i*B + j].  Fixed-order reduction:
+// a block owns EB = min(E, 16) entries; thread (entry, phase p) sums q = p, p + P, ...
+// (P = 256 / EB), then the P phase sums are combined by a tree in LDS.
+__global__ __launch_bounds__(256) void k_gram_finalize(const double* __restrict__ partials, int nparts, int B,
+                                                       int bx, int by, double* __restrict__ out) {
+  __shared__ double s[256];
   const int E = B * B;
+  const int EB = E < 16 ? E : 16;
+  const int P = 256 / EB;
   const int k = blockIdx.y;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+  const int t = threadIdx.x;
+  const int el = t % EB, p = t / EB;
+  const int e = blockIdx.x * EB + el;
+  double v = 0.0;
+  if (e < E) {
+    const double* src = partials + (int64_t)k * nparts * E + e;
+    for (int q = p; q < nparts; q += P) v += src[(int64_t)q * E];
+  }
+  s[t] = v;
+  __syncthreads();
+  for (int h = P / 2; h > 0; h >>= 1) {
+    if (p < h) s[t] += s[t + h * EB];
+    __syncthreads();
+  }
+  if (p == 0 && e < E) {
     const int i = e / B, j = e % B;
-    if (i >= bx || j >= by) continue;
-    const double* p = partials + (int64_t)k * nparts * E + e;
-    double s = 0.0;
-    for (int q = 0; q < nparts; ++q) s += p[(int64_t)q * E];
-    out[((int64_t)k * bx + i) * by + j] = s;
+    if (i < bx && j < by) out[((int64_t)k * bx + i) * by + j] = s[t];
+  }
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// X^T Y for FP32 blocks with B = 16 NT columns on the matrix cores, accumulated in
+// FP64 (v_mfma_f64_16x16x4f64: D += A B with A 16x4, B 4x16).  For four consecutive
+// rows r..r+3 lane l supplies A[i][kk] = X[r + kk][i] and B[kk][j] = Y[r + kk][j] with
+// kk = l / 16 and i = j = l % 16: one coalesced 256-byte load per operand tile.
+// Each wave writes its own partial (16 NT x 16 NT); D[i][j] sits in lane l, element v
+// with i = 4 (l / 16) + v, j = l % 16.
+template <int NT>
+__global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
+                                                   const float* __restrict__ Y, int ldy, int bx, int by,
+                                                   double* __restrict__ partials) {
+  constexpr int B = 16 * NT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* Xk = X + (int64_t)blockIdx.y * sX;
+  v4d acc[NT][NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = 0; J < NT; ++J) acc[I][J] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int rsub = lane >> 4, c = lane & 15;
+  const int64_t ngroups = (n + 3) / 4;
+  const int64_t gstride = (int64_t)gridDim.x * 4;
+#pragma unroll 2
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + wave; gi < ngroups; gi += gstride) {
+    const int64_t row = gi * 4 + rsub;
+    const bool rok = row < n;
+    double xa[NT], yb[NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      const int col = 16 * I + c;
+      xa[I] = (rok && col < bx) ? (double)Xk[row * ldx + col] : 0.0;
+      yb[I] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
+    }
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < NT; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I], yb[J], acc[I][J], 0, 0, 0);
+  }
+  double* out = partials + ((int64_t)blockIdx.y * gridDim.x * 4 + (int64_t)blockIdx.x * 4 + wave) * (B * B);
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(16 * I + 4 * rsub + v) * B + 16 * J + c] = acc[I][J][v];
+}
+
+// Out = (wv ? wv[r] : alpha) Yin + beta sum_k X_k C_k for FP32 blocks whose rows are
+// exactly B floats (B = 4 LPR): LPR lanes hold one row as float4 fragments (coalesced
+// 16-byte accesses across the wave); the row is shared inside its lane group with
+// shuffles and C_k is broadcast from LDS.
+template <int B>
+__global__ __launch_bounds__(256) void k_update_f4(int64_t n, const float* X, int64_t sX, int nblk,
+                                                   const double* __restrict__ C, const float* Yin, double alpha,
+                                                   const float* __restrict__ wv, double beta, float* Out) {
+  constexpr int LPR = B / 4;
+  constexpr int RPT = 256 / LPR;  // rows per tile
+  __shared__ float sC[B * B];
+  const int sub = threadIdx.x % LPR;
+  const int rloc = threadIdx.x / LPR;
+  const float tb = (float)beta;
+  const int64_t ntiles = (n + RPT - 1) / RPT;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t row = t * RPT + rloc;
+    const bool ok = row < n;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nblk; ++k) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < B * B; e += 256) sC[e] = (float)C[(int64_t)k * B * B + e];
+      __syncthreads();
+      float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) xv = *reinterpret_cast<const float4*>(X + (int64_t)k * sX + row * B + 4 * sub);
+#pragma unroll
+      for (int src = 0; src < LPR; ++src) {
+        float v[4];
+        v[0] = __shfl(xv.x, src, LPR);
+        v[1] = __shfl(xv.y, src, LPR);
+        v[2] = __shfl(xv.z, src, LPR);
+        v[3] = __shfl(xv.w, src, LPR);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float* crow = sC + (4 * src + q) * B + 4 * sub;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) acc[cc] += v[q] * crow[cc];
+        }
+      }
+    }
+    if (ok) {
+      float4 o = make_float4(tb * acc[0], tb * acc[1], tb * acc[2], tb * acc[3]);
+      if (Yin) {
+        const float sc = wv ? wv[row] : (float)alpha;
+        const float4 y = *reinterpret_cast<const float4*>(Yin + row * B + 4 * sub);
+        o.x += sc * y.x;
+        o.y += sc * y.y;
+        o.z += sc * y.z;
+        o.w += sc * y.w;
+      }
+      *reinterpret_cast<float4*>(Out + row * B + 4 * sub) = o;
+    }
   }
 }
 
@@ -506,14 +624,38 @@ int grid_for(int64_t work, int per_block, int cap) {
   return (int)g;
 }
 
+int fin_grid(int E) {
+  const int EB = E < 16 ? E : 16;
+  return (E + EB - 1) / EB;
+}
+
 template <int B>
 wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64_t sX, int nblk, const void* Y,
                  int ldy, int bx, int by, double* out) {
   constexpr int E = B * B;
+  if constexpr (B >= 16) {
+    if (isf) {
+      // matrix-core path, FP64 accumulation
+      constexpr int NT = B / 16;
+      const int64_t ngroups = (n + 3) / 4;
+      int64_t blocks = (ngroups + 31) / 32;
+      if (blocks > 256) blocks = 256;
+      if (blocks < 1) blocks = 1;
+      const int nparts = (int)blocks * 4;
+      WL_TRY(ctx->partials.ensure((size_t)nparts * nblk * E * sizeof(double)));
+      hipLaunchKernelGGL(k_gram_mfma<NT>, dim3((unsigned)blocks, nblk), dim3(256), 0, ctx->stream, n,
+                         (const float*)X, ldx, sX, (const float*)Y, ldy, bx, by, ctx->partials.as<double>());
+      WL_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
+                         ctx->partials.as<double>(), nparts, B, bx, by, out);
+      WL_HIP(hipGetLastError());
+      return WL_OK;
+    }
+  }
   const int64_t ntiles = (n + GRAM_TR - 1) / GRAM_TR;
   int64_t cap = (int64_t)(1 << 22) / ((int64_t)E * nblk);
   if (cap < 32) cap = 32;
-  if (cap > 1024) cap = 1024;
+  if (cap > 512) cap = 512;
   int parts = (int)(ntiles < cap ? ntiles : cap);
   if (parts < 1) parts = 1;
   WL_TRY(ctx->partials.ensure((size_t)parts * nblk * E * sizeof(double)));
@@ -523,7 +665,7 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
                      isf ? (const float*)Y : nullptr, isf ? nullptr : (const double*)Y, ldy, bx, by,
                      ctx->partials.as<double>());
   WL_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_gram_finalize, dim3((E + 255) / 256, nblk), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
                      ctx->partials.as<double>(), parts, B, bx, by, out);
   WL_HIP(hipGetLastError());
   return WL_OK;
@@ -540,8 +682,22 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
                    const T* Yin, int ldy, double alpha, const T* wv, double beta, T* Out, int by,
                    double* gram_out) {
   constexpr int E = B * B;
+  if constexpr (sizeof(T) == 4 && B >= 4) {
+    const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
+                      reinterpret_cast<uintptr_t>(Yin)) & 15u) == 0 && (sX % 4) == 0;
+    if (bx == B && by == B && ldx == B && ldy == B && al) {
+      constexpr int RPT = 256 / (B / 4);
+      int64_t ntiles = (n + RPT - 1) / RPT;
+      const int grid = (int)(ntiles < 1 ? 1 : (ntiles > 8192 ? 8192 : ntiles));
+      hipLaunchKernelGGL((k_update_f4<B>), dim3(grid), dim3(256), 0, ctx->stream, n, (const float*)X, sX, nblk, C,
+                         (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out);
+      WL_HIP(hipGetLastError());
+      if (gram_out) return gram_B<B>(ctx, n, Out, true, B, 0, 1, Out, B, B, B, gram_out);
+      return WL_OK;
+    }
+  }
   const int64_t ntiles = (n + 255) / 256;
-  const int cap = gram_out ? 1024 : 4096;
+  const int cap = gram_out ? 512 : 4096;
   const int grid = (int)(ntiles < cap ? (ntiles < 1 ? 1 : ntiles) : cap);
   double* parts = nullptr;
   if (gram_out) {
@@ -552,7 +708,7 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
                      alpha, wv, beta, Out, by, parts);
   WL_HIP(hipGetLastError());
   if (gram_out) {
-    hipLaunchKernelGGL(k_gram_finalize, dim3((E + 255) / 256, 1), dim3(256), 0, ctx->stream, parts, grid, B, by, by,
+    hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), 1), dim3(256), 0, ctx->stream, parts, grid, B, by, by,
                        gram_out);
     WL_HIP(hipGetLastError());
   }

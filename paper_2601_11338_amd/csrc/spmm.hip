@@ -244,9 +244,31 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
   WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
   const size_t lds = ep.C ? (size_t)b * TILE * sizeof(T) : 0;
   dim3 grid((unsigned)gx, (unsigned)tiles);
-  hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK>), grid, dim3(256), lds, g->ctx->stream, g->rowptr, g->colidx,
+  wl_ctx* ctx = g->ctx;
+  KernelStats* ks = nullptr;
+  if (ctx->profiling && ep.kclass >= 0 && ep.kclass < WL_KC_COUNT) {
+    ks = &ctx->kstats[ep.kclass];
+    if (ks->used == ks->events.size()) {
+      hipEvent_t a, c;
+      WL_HIP(hipEventCreate(&a));
+      WL_HIP(hipEventCreate(&c));
+      ks->events.emplace_back(a, c);
+    }
+    WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
+  }
+  hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK>), grid, dim3(256), lds, ctx->stream, g->rowptr, g->colidx,
                      g->n, b, b, X, Y, ep, g->long_rows.as<int32_t>(), n_long, long_thr);
   WL_HIP(hipGetLastError());
+  if (ks) {
+    WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));
+    ++ks->used;
+    ++ks->launches;
+    // algorithmic bytes: CSR once, the gathered block once (compulsory), every row stream once
+    const double s = sizeof(T), nb = (double)g->n * b;
+    int streams = 1 + (Y ? 1 : 0) + (ep.Z ? 1 : 0) + (ep.C ? 1 : 0) + (ep.Sin ? 1 : 0) + (ep.Sout ? 1 : 0) +
+                  (ep.Xw ? 1 : 0);
+    ks->bytes += 4.0 * g->nnz + 4.0 * (g->n + 1) + s * nb * streams + (ep.wv ? s * g->n : 0.0);
+  }
   return WL_OK;
 }
 

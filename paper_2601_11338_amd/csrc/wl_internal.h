@@ -79,11 +79,23 @@ struct SpmmShape {
   int long_thr = 512;  // rows with more neighbours go to whole workgroups
 };
 
+// Live timing of kernel classes (opt-in): HIP events recorded around each launch
+// on the context stream, algorithmic bytes counted per launch.
+enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_COUNT = 3 };
+struct KernelStats {
+  int64_t launches = 0;
+  double bytes = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t used = 0;
+};
+
 struct wl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   DevBuf partials;  // reduction partials
   DevBuf scratch;   // small device-side matrices
+  bool profiling = false;
+  KernelStats kstats[WL_KC_COUNT];
 };
 
 struct wl_graph {
@@ -142,6 +154,7 @@ struct EpiArgs {
   double s0 = 0.0, sc = 0.0;
   const T* wv = nullptr;
   const T* Xw = nullptr;
+  int kclass = WL_KC_OTHER_SPMM;  // timing class when profiling is on
 };
 
 template <typename T>

@@ -237,6 +237,25 @@ def test_estimators_match_oracle(ctx, wl, M):
     np.testing.assert_allclose(host(d), d_o, rtol=1e-8, atol=1e-10 * np.abs(d_o).max())
 
 
+@pytest.mark.parametrize("M", [16, 20, 32, 64])
+def test_estimators_fp32_matrix_core_gram(ctx, wl, M):
+    """FP32 blocks take the matrix-core Gram (FP64 accumulation); widths that are not
+    a multiple of 16 are padded.  Inputs are FP32-representable, so the oracle sees
+    exactly the GPU's inputs."""
+    n = 5000
+    rng = np.random.default_rng(M)
+    G = rng.standard_normal((n, 12)).astype(np.float32).astype(np.float64)
+    Om = philox.gaussian(n, M, 3).astype(np.float32).astype(np.float64)
+    Y = ((G @ (G.T @ Om)) / n + 0.5 * Om).astype(np.float32).astype(np.float64)
+    Omd, Yd = dev(Om, torch.float32), dev(Y, torch.float32)
+    _, tr, te = wl.estimate(ctx, Omd, Yd, "hutchinson", want_diag=False)
+    assert abs(tr - estimators.hutchinson_trace(Om, Y)) < 1e-9 * abs(tr)
+    d, tr, te = wl.estimate(ctx, Omd, Yd, "xnys", rcond=1e-9)
+    t_o, e_o, d_o, _ = estimators.xnys(Om, Y, rcond=1e-9)
+    assert abs(tr - t_o) < 1e-7 * abs(t_o)
+    np.testing.assert_allclose(host(d), d_o, rtol=2e-5, atol=2e-5 * np.abs(d_o).max())
+
+
 def test_xnys_low_rank_exact_on_gpu(ctx, wl):
     n, r, M = 200, 3, 8
     G = synth.gaussian_block(n, r, 2)
