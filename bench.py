@@ -39,7 +39,27 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--krylov", type=int, default=30)
     p.add_argument("--block", type=int, default=16)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 5 x (read 1 GiB + write 1 GiB).  Run under the same
+    hardware counters as the bench, it gives the factor between counter readings and
+    bytes actually moved."""
+    import torch
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_bytes_each": 2 * src.numel() * 4, "copies": 5, "seconds": dt,
+                      "GBps": 5 * 2 * src.numel() * 4 / dt / 1e9}), flush=True)
 
 
 def cpu_baseline(rp, ci, n, lam, X, K):
@@ -72,6 +92,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU is design-only)",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
 

@@ -185,6 +185,24 @@ wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b);
 wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt,
                   void* const* d_Y, int32_t outer_dim, double* err_est);
 
+/* ---------------------------------------------------------------- block Krylov primitives
+ * The tall-skinny kernels every block Lanczos step is made of (Sec. 4.1: the basis
+ * Q_k and its projection H_k), exposed for callers building their own drivers.
+ *
+ * wl_block_gram: G = [X_0 .. X_{nblk-1}]^T Y with X_k the k-th of nblk consecutive
+ * row-major n x bx blocks starting at d_X (block k at d_X + k n bx elements) and Y
+ * one n x by block.  G (host, double, (nblk bx) x by row-major) is accumulated in
+ * double in a fixed order (bitwise reproducible).  Synchronises the stream.
+ *
+ * wl_block_update: Out = alpha Yin + beta sum_k X_k C_k with X_k as above (width b),
+ * C (host, double, (nblk b) x b row-major), Yin / Out n x b (Yin may be NULL; Out may
+ * alias Yin or X_0 when nblk = 1).  If G (host, b x b) is not NULL it receives
+ * Out^T Out.  Synchronises the stream.                                             */
+wl_status wl_block_gram(wl_ctx* ctx, int32_t prec, int64_t n, int32_t nblk, int32_t bx, const void* d_X,
+                        int32_t by, const void* d_Y, double* G);
+wl_status wl_block_update(wl_ctx* ctx, int32_t prec, int64_t n, int32_t nblk, int32_t b, const void* d_X,
+                          const double* C, const void* d_Yin, double alpha, double beta, void* d_Out, double* G);
+
 /* ---------------------------------------------------------------- probes
  * Fill an n x M row-major block with Philox4x32-10 probes (Salmon et al., SC'11):
  * element (i, j) is word e mod 4 of Philox(counter (q lo, q hi, stream, 0),

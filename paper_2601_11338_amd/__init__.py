@@ -234,6 +234,35 @@ class Operator:
             pass
 
 
+def block_gram(ctx, X, Y, nblk=1):
+    """[X_0 .. X_{nblk-1}]^T Y (double) for X of shape (nblk*n, bx) viewed as nblk blocks."""
+    import numpy as np
+    X = X.contiguous()
+    Y = Y.contiguous()
+    n, by = Y.shape
+    bx = X.shape[1]
+    G = np.empty((nblk * bx, by), dtype=np.float64)
+    check(load().wl_block_gram(ctx.handle, _prec_of(X.dtype), n, nblk, bx, _ptr(X), by, _ptr(Y),
+                               G.ctypes.data_as(C.POINTER(C.c_double))))
+    return G
+
+
+def block_update(ctx, X, Cm, Yin=None, alpha=0.0, beta=1.0, out=None, nblk=1, want_gram=False):
+    """alpha Yin + beta sum_k X_k C_k (and optionally its Gram)."""
+    import numpy as np
+    torch = _torch()
+    X = X.contiguous()
+    b = X.shape[1]
+    n = X.shape[0] // nblk
+    Cm = np.ascontiguousarray(Cm, dtype=np.float64)
+    out = torch.empty((n, b), dtype=X.dtype, device=X.device) if out is None else out
+    G = np.empty((b, b), dtype=np.float64) if want_gram else None
+    check(load().wl_block_update(ctx.handle, _prec_of(X.dtype), n, nblk, b, _ptr(X),
+                                 Cm.ctypes.data_as(C.POINTER(C.c_double)), _ptr(Yin), float(alpha), float(beta),
+                                 _ptr(out), G.ctypes.data_as(C.POINTER(C.c_double)) if want_gram else None))
+    return (out, G) if want_gram else out
+
+
 def probes(ctx, n, M, seed, law="gauss", dtype=None, stream=0):
     torch = _torch()
     dtype = dtype or torch.float32

@@ -62,6 +62,8 @@ SIGNATURES = {
     "wl_apply_L": (C.c_int, [vp, vp, vp, i32]),
     "wl_expv": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd]),
     "wl_probes": (C.c_int, [vp, i32, i32, u64, u32, i64, i32, vp]),
+    "wl_block_gram": (C.c_int, [vp, i32, i64, i32, i32, vp, i32, vp, pd]),
+    "wl_block_update": (C.c_int, [vp, i32, i64, i32, i32, vp, pd, vp, f64, f64, vp, pd]),
     "wl_estimate": (C.c_int, [vp, i32, i32, i64, i32, vp, vp, vp, f64, vp, pd, pd]),
     "wl_diag_est": (C.c_int, [vp, i32, f64, i32, u64, i32, i32, vp, i32, vp, pd, pd]),
     "wl_features": (C.c_int, [vp, vp]),

@@ -1100,6 +1100,52 @@ wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32
   return expv_impl<double>(op, (const double*)d_U0, b, t, nt, (double* const*)d_Y, outer_dim, err_est);
 }
 
+wl_status wl_block_gram(wl_ctx* ctx, int32_t prec, int64_t n, int32_t nblk, int32_t bx, const void* d_X,
+                        int32_t by, const void* d_Y, double* G) {
+  WL_CHECK(ctx && G, WL_EINVAL, "wl_block_gram: null argument");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_block_gram: bad prec");
+  WL_CHECK(n >= 1 && nblk >= 1 && nblk <= 4096, WL_EINVAL, "wl_block_gram: bad size");
+  WL_CHECK(bx >= 1 && bx <= 64 && by >= 1 && by <= 64, WL_EINVAL, "wl_block_gram: widths must lie in [1, 64]");
+  WL_CHECK(d_X && d_Y, WL_EINVAL, "wl_block_gram: null block");
+  DeviceGuard dg(ctx->device);
+  DevBuf d;
+  const size_t cnt = (size_t)nblk * bx * by;
+  WL_TRY(d.ensure(cnt * 8));
+  if (prec == WL_FP32)
+    WL_TRY(launch_gram<float>(ctx, n, (const float*)d_X, bx, n * bx, nblk, (const float*)d_Y, by, d.as<double>()));
+  else
+    WL_TRY(launch_gram<double>(ctx, n, (const double*)d_X, bx, n * bx, nblk, (const double*)d_Y, by,
+                               d.as<double>()));
+  WL_HIP(hipMemcpyAsync(G, d.p, cnt * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
+wl_status wl_block_update(wl_ctx* ctx, int32_t prec, int64_t n, int32_t nblk, int32_t b, const void* d_X,
+                          const double* C, const void* d_Yin, double alpha, double beta, void* d_Out, double* G) {
+  WL_CHECK(ctx && C, WL_EINVAL, "wl_block_update: null argument");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_block_update: bad prec");
+  WL_CHECK(n >= 1 && nblk >= 1 && nblk <= 4096, WL_EINVAL, "wl_block_update: bad size");
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_block_update: b must lie in [1, 64]");
+  WL_CHECK(d_X && d_Out, WL_EINVAL, "wl_block_update: null block");
+  DeviceGuard dg(ctx->device);
+  DevBuf dc, dg2;
+  const size_t cnt = (size_t)nblk * b * b;
+  WL_TRY(dc.ensure(cnt * 8));
+  WL_TRY(dg2.ensure((size_t)b * b * 8));
+  WL_HIP(hipMemcpyAsync(dc.p, C, cnt * 8, hipMemcpyHostToDevice, ctx->stream));
+  if (prec == WL_FP32)
+    WL_TRY(launch_update<float>(ctx, n, (const float*)d_X, b, n * b, nblk, dc.as<double>(), (const float*)d_Yin,
+                                alpha, nullptr, beta, (float*)d_Out, b, G ? dg2.as<double>() : nullptr));
+  else
+    WL_TRY(launch_update<double>(ctx, n, (const double*)d_X, b, n * b, nblk, dc.as<double>(),
+                                 (const double*)d_Yin, alpha, nullptr, beta, (double*)d_Out, b,
+                                 G ? dg2.as<double>() : nullptr));
+  if (G) WL_HIP(hipMemcpyAsync(G, dg2.p, (size_t)b * b * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
 wl_status wl_probes(wl_ctx* ctx, int32_t prec, int32_t law, uint64_t seed, uint32_t stream, int64_t n, int32_t M,
                     void* d_out) {
   WL_CHECK(ctx, WL_EINVAL, "wl_probes: ctx is null");

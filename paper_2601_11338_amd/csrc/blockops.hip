@@ -126,7 +126,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // rows r..r+3 lane l supplies A[i][kk] = X[r + kk][i] and B[kk][j] = Y[r + kk][j] with
 // kk = l / 16 and i = j = l % 16: one coalesced 256-byte load per operand tile.
 // Each wave writes its own partial (16 NT x 16 NT); D[i][j] sits in lane l, element v
-// with i = 4 (l / 16) + v, j = l % 16.
+// with i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose
+// inputs make every output entry identify its (i, j)).
 template <int NT>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
                                                    const float* __restrict__ Y, int ldy, int bx, int by,
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
 #pragma unroll
     for (int J = 0; J < NT; ++J)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(16 * I + 4 * rsub + v) * B + 16 * J + c] = acc[I][J][v];
+      for (int v = 0; v < 4; ++v) out[(16 * I + 4 * v + rsub) * B + 16 * J + c] = acc[I][J][v];
 }
 
 // Out = (wv ? wv[r] : alpha) Yin + beta sum_k X_k C_k for FP32 blocks whose rows are
