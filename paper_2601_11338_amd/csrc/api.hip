@@ -464,8 +464,9 @@ struct SmallLayout {
   size_t Ri1() const { return (size_t)(2 * K + 3) * bb; }
   size_t R2() const { return (size_t)(2 * K + 4) * bb; }
   size_t Ri2() const { return (size_t)(2 * K + 5) * bb; }
-  size_t P() const { return (size_t)(2 * K + 6) * bb; }         // up to (K+1) blocks
-  size_t total() const { return (size_t)(3 * K + 8) * bb; }
+  size_t Cc() const { return (size_t)(2 * K + 6) * bb; }        // 3 blocks
+  size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+1) blocks
+  size_t total() const { return (size_t)(3 * K + 11) * bb; }
 };
 
 // Runs K block Lanczos steps from X (n x b).  basis must hold (K+1) blocks, Wb one
@@ -492,7 +493,32 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
   WL_TRY(launch_update<T>(ctx, n, basis, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, basis, b, nullptr));
   if (ring) reorth = 0;
   auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
-  for (int j = 0; j < K; ++j) {
+  if (!ring && reorth <= 1) {
+    // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] against W';
+    // projection and Cholesky of the projected Gram on the device; one in-place update
+    // V_{j+1} = [V_{j-1} V_j W'] Cc; a second CholQR pass for orthonormality.
+    for (int j = 0; j < K; ++j) {
+      T* Vj = slot(j);
+      T* Vn = slot(j + 1);
+      const T* Vp = j > 0 ? slot(j - 1) : nullptr;
+      WL_TRY(apply_lanczos_op<T>(g, L, Vj, Vn, b, Vp, j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.P()));
+      const int nbv = j > 0 ? 2 : 1;
+      const T* Vlo = j > 0 ? Vp : Vj;
+      WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nbv + 1, Vn, b, S + Ly.P()));
+      WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(),
+                                   S + Ly.Cc()));
+      if (j + 1 == K) {
+        WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
+        break;
+      }
+      WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,
+                              S + Ly.G()));
+      WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                         S + Ly.B(j)));
+      WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
+    }
+  }
+  for (int j = 0; j < K && (ring || reorth > 1); ++j) {
     T* Vj = slot(j);
     const T* Vp = j > 0 ? slot(j - 1) : nullptr;
     WL_TRY(apply_lanczos_op<T>(g, L, Vj, Wb, b, Vp, j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.P()));

@@ -335,6 +335,110 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T* X, int ldx, 
   }
 }
 
+// Right-looking Cholesky with deflation of the b x b matrix in sG (LDS, row stride 65),
+// 64 threads: a pivot <= thr zeroes its row of R and marks the column deflated.  Then
+// Rinv (global, b x b) = inverse of R on the non-deflated columns, zero elsewhere.
+__device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double thr, double* __restrict__ Rinv) {
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 64) sR[(e / b) * 65 + e % b] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    if (t == 0) {
+      const double p = sG[k * 65 + k];
+      if (!(p > thr) || !(p > 0.0)) {
+        defl[k] = 1;
+        sR[k * 65 + k] = 0.0;
+      } else {
+        defl[k] = 0;
+        sR[k * 65 + k] = sqrt(p);
+      }
+    }
+    __syncthreads();
+    const double rkk = sR[k * 65 + k];
+    if (t > k && t < b) sR[k * 65 + t] = defl[k] ? 0.0 : sG[k * 65 + t] / rkk;
+    __syncthreads();
+    if (t > k && t < b) {
+      const double rkt = sR[k * 65 + t];
+      for (int j = t; j < b; ++j) sG[t * 65 + j] -= rkt * sR[k * 65 + j];
+    }
+    __syncthreads();
+  }
+  if (t < b) {
+    double x[64];
+    for (int i = b - 1; i >= 0; --i) {
+      double v = (i == t) ? 1.0 : 0.0;
+      if (defl[i] || defl[t]) {
+        x[i] = 0.0;
+        continue;
+      }
+      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * x[j];
+      x[i] = v / sR[i * 65 + i];
+    }
+    for (int i = 0; i < b; ++i) Rinv[i * b + t] = x[i];
+  }
+  __syncthreads();
+}
+
+// One projection step of block Lanczos (classical Gram-Schmidt against V_{j-1} and V_j
+// with the Gram of the projected block obtained by Pythagoras).  P stacks nbv + 1 b x b
+// blocks: [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or [V_j^T W'; W'^T W'] (nbv = 1).
+// Outputs: Aout = sym(V_j^T W') (the diagonal block of T); R, Rinv from the deflated
+// Cholesky of G_W = W'^T W' - P1^T P1 - A^T A, the Gram of W = W' - V_{j-1} P1 - V_j A;
+// Cc = [-P1 Rinv; -A Rinv; Rinv] so that V_{j+1} = [V_{j-1} V_j W'] Cc.
+__global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const double* __restrict__ P, double tol,
+                                                       double* __restrict__ Aout, double* __restrict__ R,
+                                                       double* __restrict__ Rinv, double* __restrict__ Cc) {
+  __shared__ double sG[64 * 65];
+  __shared__ double sR[64 * 65];
+  __shared__ double sA[64 * 65];
+  __shared__ int defl[64];
+  __shared__ double sref;
+  const int t = threadIdx.x;
+  const int bb = b * b;
+  const double* P1 = nbv == 2 ? P : nullptr;
+  const double* Aj = P + (size_t)(nbv - 1) * bb;
+  const double* Gp = P + (size_t)nbv * bb;
+  for (int e = t; e < bb; e += 64) {
+    const int i = e / b, j = e % b;
+    const double a = 0.5 * (Aj[i * b + j] + Aj[j * b + i]);
+    sA[i * 65 + j] = a;
+    Aout[e] = a;
+  }
+  __syncthreads();
+  if (t < b) {
+    for (int k = 0; k < b; ++k) {
+      double s = 0.5 * (Gp[t * b + k] + Gp[k * b + t]);
+      for (int m = 0; m < b; ++m) s -= sA[m * 65 + t] * sA[m * 65 + k];
+      if (P1)
+        for (int m = 0; m < b; ++m) s -= P1[m * b + t] * P1[m * b + k];
+      sG[t * 65 + k] = s;
+    }
+  }
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < b; ++i) m = fmax(m, Gp[i * b + i]);
+    sref = m;
+  }
+  __syncthreads();
+  chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
+  for (int e = t; e < bb; e += 64) R[e] = sR[(e / b) * 65 + e % b];
+  __syncthreads();
+  // Cc blocks (Rinv was written by this workgroup to global memory above)
+  if (t < b) {
+    for (int c = 0; c < b; ++c) {
+      double sa = 0.0, sp = 0.0;
+      for (int m = 0; m < b; ++m) {
+        const double rv = Rinv[m * b + c];
+        sa += sA[t * 65 + m] * rv;
+        if (P1) sp += P1[t * b + m] * rv;
+      }
+      if (P1) Cc[t * b + c] = -sp;
+      Cc[(size_t)(nbv - 1) * bb + t * b + c] = -sa;
+      Cc[(size_t)nbv * bb + t * b + c] = Rinv[t * b + c];
+    }
+  }
+}
+
 // Cholesky with deflation, one workgroup of 64 threads, b <= 64.
 __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G, double tol,
                                              const double* __restrict__ Aref, const double* __restrict__ Bref,
@@ -749,6 +853,14 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
     case 32: return update_B<T, 32>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
     default: return update_B<T, 64>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
   }
+}
+
+wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
+                                double* Rinv, double* Cc) {
+  WL_CHECK(b >= 1 && b <= 64 && (nbv == 1 || nbv == 2), WL_EINVAL, "lanczos coefficients: bad sizes");
+  hipLaunchKernelGGL(k_lanczos_coeffs, dim3(1), dim3(64), 0, ctx->stream, b, nbv, P, tol, Aout, R, Rinv, Cc);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
 }
 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,

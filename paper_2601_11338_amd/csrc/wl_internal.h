@@ -182,6 +182,12 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout);
 
+// One block Lanczos projection: from P = [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or
+// [V_j^T W'; W'^T W'] (nbv = 1) form A_j (Aout), the deflated Cholesky factor R (and
+// Rinv) of the projected block's Gram, and Cc with V_{j+1} = [V_{j-1} V_j W'] Cc.
+wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
+                                double* Rinv, double* Cc);
+
 // Small device helpers on double matrices.
 wl_status launch_dadd(wl_ctx* ctx, int count, const double* x, double* y);   // y += x
 wl_status launch_dcopy(wl_ctx* ctx, int count, const double* x, double* y);  // y = x
