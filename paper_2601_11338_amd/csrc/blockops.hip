@@ -128,44 +128,65 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // Each wave writes its own partial (16 NT x 16 NT); D[i][j] sits in lane l, element v
 // with i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose
 // inputs make every output entry identify its (i, j)).
-template <int NT>
+// NB X blocks (block k at X + k sX) share one pass over Y: grid y walks chunks of NB
+// blocks, and each wave unrolls U four-row groups so 2 U + U NB loads are in flight
+// before their matrix-core products.
+template <int NT, int NB>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
-                                                   const float* __restrict__ Y, int ldy, int bx, int by,
+                                                   int nblk, const float* __restrict__ Y, int ldy, int bx, int by,
                                                    double* __restrict__ partials) {
   constexpr int B = 16 * NT;
+  constexpr int U = NT * NB <= 2 ? 4 : (NT * NB <= 4 ? 2 : 1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float* Xk = X + (int64_t)blockIdx.y * sX;
-  v4d acc[NT][NT];
+  const int kb0 = blockIdx.y * NB;
+  const int nb = (nblk - kb0) < NB ? (nblk - kb0) : NB;
+  v4d acc[NB][NT][NT];
 #pragma unroll
-  for (int I = 0; I < NT; ++I)
-#pragma unroll
-    for (int J = 0; J < NT; ++J) acc[I][J] = v4d{0.0, 0.0, 0.0, 0.0};
-  const int rsub = lane >> 4, c = lane & 15;
-  const int64_t ngroups = (n + 3) / 4;
-  const int64_t gstride = (int64_t)gridDim.x * 4;
-#pragma unroll 2
-  for (int64_t gi = (int64_t)blockIdx.x * 4 + wave; gi < ngroups; gi += gstride) {
-    const int64_t row = gi * 4 + rsub;
-    const bool rok = row < n;
-    double xa[NT], yb[NT];
-#pragma unroll
-    for (int I = 0; I < NT; ++I) {
-      const int col = 16 * I + c;
-      xa[I] = (rok && col < bx) ? (double)Xk[row * ldx + col] : 0.0;
-      yb[I] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
-    }
+  for (int q = 0; q < NB; ++q)
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
-      for (int J = 0; J < NT; ++J) acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I], yb[J], acc[I][J], 0, 0, 0);
+      for (int J = 0; J < NT; ++J) acc[q][I][J] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int rsub = lane >> 4, c = lane & 15;
+  const int64_t ngroups = (n + 3) / 4;
+  const int64_t gstride = (int64_t)gridDim.x * 4;
+  for (int64_t g0 = (int64_t)blockIdx.x * 4 + wave; g0 < ngroups; g0 += gstride * U) {
+    double xa[U][NB][NT], yb[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = (g0 + u * gstride) * 4 + rsub;
+      const bool rok = row < n;
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        const int col = 16 * I + c;
+        yb[u][I] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          xa[u][q][I] = (rok && q < nb && col < bx) ? (double)X[(int64_t)(kb0 + q) * sX + row * ldx + col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+          for (int J = 0; J < NT; ++J)
+            acc[q][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][q][I], yb[u][J], acc[q][I][J], 0, 0, 0);
   }
-  double* out = partials + ((int64_t)blockIdx.y * gridDim.x * 4 + (int64_t)blockIdx.x * 4 + wave) * (B * B);
+  const int nparts = gridDim.x * 4;
 #pragma unroll
-  for (int I = 0; I < NT; ++I)
+  for (int q = 0; q < NB; ++q) {
+    if (q >= nb) break;
+    double* out = partials + ((int64_t)(kb0 + q) * nparts + (int64_t)blockIdx.x * 4 + wave) * (B * B);
 #pragma unroll
-    for (int J = 0; J < NT; ++J)
+    for (int I = 0; I < NT; ++I)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) out[(16 * I + 4 * v + rsub) * B + 16 * J + c] = acc[I][J][v];
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[(16 * I + 4 * v + rsub) * B + 16 * J + c] = acc[q][I][J][v];
+  }
 }
 
 // Out = (wv ? wv[r] : alpha) Yin + beta sum_k X_k C_k for FP32 blocks whose rows are
@@ -337,7 +358,8 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T* X, int ldx, 
 
 // Right-looking Cholesky with deflation of the b x b matrix in sG (LDS, row stride 65),
 // 64 threads: a pivot <= thr zeroes its row of R and marks the column deflated.  Then
-// Rinv (global, b x b) = inverse of R on the non-deflated columns, zero elsewhere.
+// the inverse of R on the non-deflated columns (zero elsewhere) overwrites sG and, if
+// Rinv is given, is copied to global memory.
 __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double thr, double* __restrict__ Rinv) {
   const int t = threadIdx.x;
   for (int e = t; e < b * b; e += 64) sR[(e / b) * 65 + e % b] = 0.0;
@@ -363,20 +385,21 @@ __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double th
     }
     __syncthreads();
   }
+  // the factorisation has consumed sG: column t of the inverse is built in place there
   if (t < b) {
-    double x[64];
     for (int i = b - 1; i >= 0; --i) {
       double v = (i == t) ? 1.0 : 0.0;
       if (defl[i] || defl[t]) {
-        x[i] = 0.0;
+        sG[i * 65 + t] = 0.0;
         continue;
       }
-      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * x[j];
-      x[i] = v / sR[i * 65 + i];
+      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * sG[j * 65 + t];
+      sG[i * 65 + t] = v / sR[i * 65 + i];
     }
-    for (int i = 0; i < b; ++i) Rinv[i * b + t] = x[i];
   }
   __syncthreads();
+  if (Rinv)
+    for (int e = t; e < b * b; e += 64) Rinv[e] = sG[(e / b) * 65 + e % b];
 }
 
 // One projection step of block Lanczos (classical Gram-Schmidt against V_{j-1} and V_j
@@ -391,11 +414,12 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
   __shared__ double sG[64 * 65];
   __shared__ double sR[64 * 65];
   __shared__ double sA[64 * 65];
+  __shared__ double sP[64 * 65];
   __shared__ int defl[64];
   __shared__ double sref;
   const int t = threadIdx.x;
   const int bb = b * b;
-  const double* P1 = nbv == 2 ? P : nullptr;
+  const bool hasP1 = nbv == 2;
   const double* Aj = P + (size_t)(nbv - 1) * bb;
   const double* Gp = P + (size_t)nbv * bb;
   for (int e = t; e < bb; e += 64) {
@@ -403,16 +427,8 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
     const double a = 0.5 * (Aj[i * b + j] + Aj[j * b + i]);
     sA[i * 65 + j] = a;
     Aout[e] = a;
-  }
-  __syncthreads();
-  if (t < b) {
-    for (int k = 0; k < b; ++k) {
-      double s = 0.5 * (Gp[t * b + k] + Gp[k * b + t]);
-      for (int m = 0; m < b; ++m) s -= sA[m * 65 + t] * sA[m * 65 + k];
-      if (P1)
-        for (int m = 0; m < b; ++m) s -= P1[m * b + t] * P1[m * b + k];
-      sG[t * 65 + k] = s;
-    }
+    sP[i * 65 + j] = hasP1 ? P[e] : 0.0;
+    sG[i * 65 + j] = 0.5 * (Gp[i * b + j] + Gp[j * b + i]);
   }
   if (t == 0) {
     double m = 0.0;
@@ -420,21 +436,30 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
     sref = m;
   }
   __syncthreads();
+  if (t < b) {
+    for (int k = 0; k < b; ++k) {
+      double s = sG[t * 65 + k];
+      for (int m = 0; m < b; ++m) s -= sA[m * 65 + t] * sA[m * 65 + k] + sP[m * 65 + t] * sP[m * 65 + k];
+      sR[t * 65 + k] = s;  // staged here, moved back below
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < bb; e += 64) sG[(e / b) * 65 + e % b] = sR[(e / b) * 65 + e % b];
+  __syncthreads();
   chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
   for (int e = t; e < bb; e += 64) R[e] = sR[(e / b) * 65 + e % b];
-  __syncthreads();
-  // Cc blocks (Rinv was written by this workgroup to global memory above)
+  // Cc blocks from the inverse left in sG by the factorisation
   if (t < b) {
     for (int c = 0; c < b; ++c) {
       double sa = 0.0, sp = 0.0;
       for (int m = 0; m < b; ++m) {
-        const double rv = Rinv[m * b + c];
+        const double rv = sG[m * 65 + c];
         sa += sA[t * 65 + m] * rv;
-        if (P1) sp += P1[t * b + m] * rv;
+        sp += sP[t * 65 + m] * rv;
       }
-      if (P1) Cc[t * b + c] = -sp;
+      if (hasP1) Cc[t * b + c] = -sp;
       Cc[(size_t)(nbv - 1) * bb + t * b + c] = -sa;
-      Cc[(size_t)nbv * bb + t * b + c] = Rinv[t * b + c];
+      Cc[(size_t)nbv * bb + t * b + c] = sG[t * 65 + c];
     }
   }
 }
@@ -466,42 +491,7 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     sref = fmax(m, fa / b);
   }
   __syncthreads();
-  const double thr = tol * sref;
-  for (int k = 0; k < b; ++k) {
-    if (t == 0) {
-      const double p = sG[k * 65 + k];
-      if (!(p > thr) || !(p > 0.0)) {
-        defl[k] = 1;
-        sR[k * 65 + k] = 0.0;
-      } else {
-        defl[k] = 0;
-        sR[k * 65 + k] = sqrt(p);
-      }
-    }
-    __syncthreads();
-    const double rkk = sR[k * 65 + k];
-    if (t > k && t < b) sR[k * 65 + t] = defl[k] ? 0.0 : sG[k * 65 + t] / rkk;
-    __syncthreads();
-    if (t > k && t < b) {
-      const double rkt = sR[k * 65 + t];
-      for (int j = t; j < b; ++j) sG[t * 65 + j] -= rkt * sR[k * 65 + j];
-    }
-    __syncthreads();
-  }
-  // inverse of R on the non-deflated columns: column t by back substitution
-  if (t < b) {
-    double x[64];
-    for (int i = b - 1; i >= 0; --i) {
-      double v = (i == t) ? 1.0 : 0.0;
-      if (defl[i] || defl[t]) {
-        x[i] = 0.0;
-        continue;
-      }
-      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * x[j];
-      x[i] = v / sR[i * 65 + i];
-    }
-    for (int i = 0; i < b; ++i) Rinv[i * b + t] = x[i];
-  }
+  chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
   for (int e = t; e < b * b; e += 64) {
     const int i = e / b, j = e % b;
     if (R) R[e] = sR[i * 65 + j];
@@ -748,8 +738,19 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
       if (blocks < 1) blocks = 1;
       const int nparts = (int)blocks * 4;
       WL_TRY(ctx->partials.ensure((size_t)nparts * nblk * E * sizeof(double)));
-      hipLaunchKernelGGL(k_gram_mfma<NT>, dim3((unsigned)blocks, nblk), dim3(256), 0, ctx->stream, n,
-                         (const float*)X, ldx, sX, (const float*)Y, ldy, bx, by, ctx->partials.as<double>());
+      double* pp = ctx->partials.as<double>();
+      const float* Xf = (const float*)X;
+      const float* Yf = (const float*)Y;
+      if (NT >= 4 || nblk == 1) {
+        hipLaunchKernelGGL((k_gram_mfma<NT, 1>), dim3((unsigned)blocks, nblk), dim3(256), 0, ctx->stream, n, Xf,
+                           ldx, sX, nblk, Yf, ldy, bx, by, pp);
+      } else if (nblk == 2 || NT == 2) {
+        hipLaunchKernelGGL((k_gram_mfma<NT, 2>), dim3((unsigned)blocks, (nblk + 1) / 2), dim3(256), 0, ctx->stream,
+                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp);
+      } else {
+        hipLaunchKernelGGL((k_gram_mfma<NT, 3>), dim3((unsigned)blocks, (nblk + 2) / 3), dim3(256), 0, ctx->stream,
+                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp);
+      }
       WL_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
                          ctx->partials.as<double>(), nparts, B, bx, by, out);

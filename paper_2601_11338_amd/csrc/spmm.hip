@@ -72,6 +72,36 @@ __device__ __forceinline__ Frag<T, VW> ldf_m(const T* p, bool ok) {
   }
 }
 
+// Streaming (non-temporal) accesses for row-aligned blocks that no later gather reads
+// (the running sum, P_{k-2}, the Laplacian finish input): they should not displace
+// the gathered block from the caches.
+template <typename T, int VW>
+__device__ __forceinline__ Frag<T, VW> ldf_nt(const T* p) {
+  Frag<T, VW> f;
+  if constexpr (VW == 1) {
+    f.v[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T V __attribute__((ext_vector_type(VW)));
+    V x = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+#pragma unroll
+    for (int i = 0; i < VW; ++i) f.v[i] = x[i];
+  }
+  return f;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void stf_nt(T* p, const Frag<T, VW>& f) {
+  if constexpr (VW == 1) {
+    __builtin_nontemporal_store(f.v[0], p);
+  } else {
+    typedef T V __attribute__((ext_vector_type(VW)));
+    V x;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) x[i] = f.v[i];
+    __builtin_nontemporal_store(x, reinterpret_cast<V*>(p));
+  }
+}
+
 template <typename T, int VW>
 __device__ __forceinline__ void zero(Frag<T, VW>& f) {
 #pragma unroll
@@ -122,7 +152,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
   if (ep.Sout) {
     Frag<T, VW> s;
     if (ep.Sin)
-      s = ldf_m<T, VW, MASK>(ep.Sin + off, true);
+      s = MASK ? ldf_m<T, VW, MASK>(ep.Sin + off, true) : ldf_nt<T, VW>(ep.Sin + off);
     else
       zero(s);
     const T s0 = (T)ep.s0, sc = (T)ep.sc;
@@ -130,14 +160,14 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
     for (int i = 0; i < VW; ++i) s.v[i] = s0 * s.v[i] + sc * y[i];
     if (ep.wv) {
       const T wr = ep.wv[r];
-      Frag<T, VW> xw = ldf_m<T, VW, MASK>(ep.Xw + off, true);
+      Frag<T, VW> xw = MASK ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
 #pragma unroll
       for (int i = 0; i < VW; ++i) s.v[i] = wr * xw.v[i] - s.v[i];
     }
     if constexpr (MASK) {
       ep.Sout[off] = s.v[0];
     } else {
-      stf<T, VW>(ep.Sout + off, s);
+      stf_nt<T, VW>(ep.Sout + off, s);
     }
   }
 }
