@@ -128,15 +128,18 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // Each wave writes its own partial (16 NT x 16 NT); D[i][j] sits in lane l, element v
 // with i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose
 // inputs make every output entry identify its (i, j)).
-// NB X blocks (block k at X + k sX) share one pass over Y: grid y walks chunks of NB
-// blocks, and each wave unrolls U four-row groups so 2 U + U NB loads are in flight
-// before their matrix-core products.
+// NB X blocks (block k at X + k sX) share one pass over Y (grid y walks chunks of NB
+// blocks).  When every operand row is exactly B = 16 NT floats (aligned), a wave
+// loads 16-row tiles with 16-byte coalesced loads, stages them in its own LDS slice
+// and reads the operands back in the layout above; otherwise it falls back to one
+// element per lane straight from memory.
 template <int NT, int NB>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
                                                    int nblk, const float* __restrict__ Y, int ldy, int bx, int by,
                                                    double* __restrict__ partials) {
   constexpr int B = 16 * NT;
-  constexpr int U = NT * NB <= 2 ? 4 : (NT * NB <= 4 ? 2 : 1);
+  constexpr int TILE = 16 * B;  // floats per 16-row tile of one operand
+  __shared__ float sm[4][NB + 1][TILE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kb0 = blockIdx.y * NB;
   const int nb = (nblk - kb0) < NB ? (nblk - kb0) : NB;
@@ -148,32 +151,71 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
 #pragma unroll
       for (int J = 0; J < NT; ++J) acc[q][I][J] = v4d{0.0, 0.0, 0.0, 0.0};
   const int rsub = lane >> 4, c = lane & 15;
-  const int64_t ngroups = (n + 3) / 4;
-  const int64_t gstride = (int64_t)gridDim.x * 4;
-  for (int64_t g0 = (int64_t)blockIdx.x * 4 + wave; g0 < ngroups; g0 += gstride * U) {
-    double xa[U][NB][NT], yb[U][NT];
+  const bool packed = ldx == B && ldy == B && bx == B && by == B && (sX % 4) == 0 &&
+                      ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
+  const int64_t nchunks = (n + 15) / 16;
+  const int64_t cstride = (int64_t)gridDim.x * 4;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
+    const int64_t r0 = ch * 16;
+    if (packed) {
+      // 16 rows x B floats = 4 B float4 per operand, NT per lane
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t row = (g0 + u * gstride) * 4 + rsub;
-      const bool rok = row < n;
+      for (int s = 0; s < NT; ++s) {
+        const int f = s * 64 + lane;       // float4 index inside the tile
+        const int64_t row = r0 + (f * 4) / B;
+        const bool rok = row < n;
+        const int64_t off = r0 * B + (int64_t)f * 4;
+        float4 y4 = rok ? *reinterpret_cast<const float4*>(Y + off) : make_float4(0.f, 0.f, 0.f, 0.f);
+        *reinterpret_cast<float4*>(&sm[wave][NB][f * 4]) = y4;
 #pragma unroll
-      for (int I = 0; I < NT; ++I) {
-        const int col = 16 * I + c;
-        yb[u][I] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
+        for (int q = 0; q < NB; ++q) {
+          float4 x4 = (rok && q < nb) ? *reinterpret_cast<const float4*>(X + (int64_t)(kb0 + q) * sX + off)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+          *reinterpret_cast<float4*>(&sm[wave][q][f * 4]) = x4;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int rl = 4 * m + rsub;
+        double yb[NT];
+#pragma unroll
+        for (int J = 0; J < NT; ++J) yb[J] = (double)sm[wave][NB][rl * B + 16 * J + c];
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-          xa[u][q][I] = (rok && q < nb && col < bx) ? (double)X[(int64_t)(kb0 + q) * sX + row * ldx + col] : 0.0;
+#pragma unroll
+          for (int I = 0; I < NT; ++I) {
+            const double xa = (double)sm[wave][q][rl * B + 16 * I + c];
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+              acc[q][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb[J], acc[q][I][J], 0, 0, 0);
+          }
+      }
+      __builtin_amdgcn_wave_barrier();
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int64_t row = r0 + 4 * m + rsub;
+        const bool rok = row < n;
+        double yb[NT];
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+          const int col = 16 * J + c;
+          yb[J] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int I = 0; I < NT; ++I) {
+            const int col = 16 * I + c;
+            const double xa =
+                (rok && q < nb && col < bx) ? (double)X[(int64_t)(kb0 + q) * sX + row * ldx + col] : 0.0;
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+              acc[q][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb[J], acc[q][I][J], 0, 0, 0);
+          }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < NB; ++q)
-#pragma unroll
-        for (int I = 0; I < NT; ++I)
-#pragma unroll
-          for (int J = 0; J < NT; ++J)
-            acc[q][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[u][q][I], yb[u][J], acc[q][I][J], 0, 0, 0);
   }
   const int nparts = gridDim.x * 4;
 #pragma unroll
@@ -732,9 +774,9 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
     if (isf) {
       // matrix-core path, FP64 accumulation
       constexpr int NT = B / 16;
-      const int64_t ngroups = (n + 3) / 4;
-      int64_t blocks = (ngroups + 31) / 32;
-      if (blocks > 256) blocks = 256;
+      const int64_t nchunks = (n + 15) / 16;
+      int64_t blocks = (nchunks + 15) / 16;
+      if (blocks > 512) blocks = 512;
       if (blocks < 1) blocks = 1;
       const int nparts = (int)blocks * 4;
       WL_TRY(ctx->partials.ensure((size_t)nparts * nblk * E * sizeof(double)));
