@@ -235,6 +235,42 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
                       int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
                       void* d_diag, double* trace, double* trace_err);
 
+/* ---------------------------------------------------------------- learned control variate
+ * No counterpart in the paper: a small network predicts diag(phi) from cheap local
+ * features and serves as a control variate for the diagonal estimator.
+ *
+ * wl_features: d_feat (n x 8 float, row-major) = local features of every node, with
+ * structural counts scaled by s (alpha or beta of the target operator):
+ * log1p(s d), log1p(s^2 d), log1p(s^3 2t), log1p(s^2 S2), log1p(s mean_j d_j),
+ * log1p(s rms_j d_j), log1p(s max_j d_j), clustering 2t / (d (d - 1)); d = degree,
+ * t = triangles through the node, S2 = sum of neighbour degrees (2-walk count),
+ * j over neighbours.  Synchronises the stream.
+ *
+ * wl_diag_exact: d_out[j] = phi[nodes[j], nodes[j]] for count device node indices,
+ * from unit-vector blocks of the given width pushed through the operator (the
+ * method's own exact diagonal, used as training targets).  Element type by op.
+ *
+ * wl_mlp_*: 8 -> 64 -> 64 -> 1 multilayer perceptron with tanh hidden units, FP32
+ * parameters (4801 values: W1 64x8, b1, W2 64x64, b2, W3 1x64, b3), mean-squared-
+ * error loss, Adam (beta1 0.9, beta2 0.999, eps 1e-8).  Gradients are reduced in
+ * double in a fixed order.  h_params may be NULL (zeros).  wl_mlp_loss_grad returns
+ * the loss and (if h_grad is not NULL) the gradient (4801 doubles) without updating.
+ * wl_mlp_save / wl_mlp_load: flat binary file, 8-byte magic "WLMLP001", int32 count,
+ * float parameters.                                                               */
+wl_status wl_features(wl_graph* g, double scale, void* d_feat);
+wl_status wl_diag_exact(wl_op* op, const int32_t* d_nodes, int64_t count, int32_t width, void* d_out);
+int32_t wl_mlp_num_params(void);
+wl_status wl_mlp_create(wl_ctx* ctx, const float* h_params, wl_mlp** out);
+wl_status wl_mlp_destroy(wl_mlp* net);
+wl_status wl_mlp_get_params(const wl_mlp* net, float* h_params);
+wl_status wl_mlp_forward(wl_mlp* net, const void* d_feat, int64_t n, void* d_out);
+wl_status wl_mlp_loss_grad(wl_mlp* net, const void* d_feat, const void* d_target, int64_t n, double* loss,
+                           double* h_grad);
+wl_status wl_mlp_train_step(wl_mlp* net, const void* d_feat, const void* d_target, int64_t n, double lr,
+                            double* loss);
+wl_status wl_mlp_save(const wl_mlp* net, const char* path);
+wl_status wl_mlp_load(wl_ctx* ctx, const char* path, wl_mlp** out);
+
 #ifdef __cplusplus
 }
 #endif

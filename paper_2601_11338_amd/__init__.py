@@ -141,11 +141,12 @@ class Graph:
         check(load().wl_spectral_radius(self.handle, float(mu), tol, C.byref(out)))
         return out.value
 
-    def features(self, out=None):
+    def features(self, scale, out=None):
+        """n x 8 float32 local features scaled by the operator parameter."""
         torch = _torch()
         if out is None:
             out = torch.empty((self.n, 8), dtype=torch.float32, device=self.ctx.torch_device)
-        check(load().wl_features(self.handle, _ptr(out)))
+        check(load().wl_features(self.handle, float(scale), _ptr(out)))
         return out
 
     def close(self):
@@ -222,6 +223,14 @@ class Operator:
                                  C.byref(te)))
         return out, tr.value, te.value
 
+    def diag_exact(self, nodes, width=32):
+        """phi[i, i] for the given node indices (unit-vector blocks through the operator)."""
+        torch = _torch()
+        nodes = torch.as_tensor(nodes).to(device=self.graph.ctx.torch_device, dtype=torch.int32).contiguous()
+        out = self._empty(nodes.numel())
+        check(load().wl_diag_exact(self.handle, _ptr(nodes), nodes.numel(), int(width), _ptr(out)))
+        return out
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             load().wl_op_destroy(self.handle)
@@ -281,3 +290,67 @@ def estimate(ctx, Omega, Y, estimator="hutchinson", cv=None, rcond=1e-10, want_d
     check(load().wl_estimate(ctx.handle, _prec_of(Omega.dtype), ESTIMATORS[estimator], n, M, _ptr(Omega), _ptr(Y),
                              _ptr(cv), float(rcond), _ptr(diag), C.byref(tr), C.byref(te)))
     return diag, tr.value, te.value
+
+
+class MLP:
+    """The control-variate network (8 -> 64 -> 64 -> 1, tanh), trained on the device."""
+
+    def __init__(self, ctx, params=None, handle=None):
+        import numpy as np
+        self.ctx = ctx
+        lib = load()
+        self.nparams = lib.wl_mlp_num_params()
+        self.handle = C.c_void_p()
+        if handle is not None:
+            self.handle = handle
+            return
+        arr = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        check(lib.wl_mlp_create(ctx.handle, arr.ctypes.data_as(C.c_void_p) if arr is not None else None,
+                                C.byref(self.handle)))
+
+    @classmethod
+    def load_file(cls, ctx, path):
+        h = C.c_void_p()
+        check(load().wl_mlp_load(ctx.handle, str(path).encode(), C.byref(h)))
+        return cls(ctx, handle=h)
+
+    def save(self, path):
+        check(load().wl_mlp_save(self.handle, str(path).encode()))
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.nparams, dtype=np.float32)
+        check(load().wl_mlp_get_params(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def forward(self, feat, out=None):
+        torch = _torch()
+        feat = feat.contiguous()
+        out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device) if out is None else out
+        check(load().wl_mlp_forward(self.handle, _ptr(feat), feat.shape[0], _ptr(out)))
+        return out
+
+    def loss_grad(self, feat, target):
+        import numpy as np
+        g = np.empty(self.nparams, dtype=np.float64)
+        loss = C.c_double()
+        check(load().wl_mlp_loss_grad(self.handle, _ptr(feat.contiguous()), _ptr(target.contiguous()),
+                                      feat.shape[0], C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def train_step(self, feat, target, lr):
+        loss = C.c_double()
+        check(load().wl_mlp_train_step(self.handle, _ptr(feat), _ptr(target), feat.shape[0], float(lr),
+                                       C.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_mlp_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -66,13 +66,17 @@ SIGNATURES = {
     "wl_block_update": (C.c_int, [vp, i32, i64, i32, i32, vp, pd, vp, f64, f64, vp, pd]),
     "wl_estimate": (C.c_int, [vp, i32, i32, i64, i32, vp, vp, vp, f64, vp, pd, pd]),
     "wl_diag_est": (C.c_int, [vp, i32, f64, i32, u64, i32, i32, vp, i32, vp, pd, pd]),
-    "wl_features": (C.c_int, [vp, vp]),
+    "wl_features": (C.c_int, [vp, f64, vp]),
+    "wl_diag_exact": (C.c_int, [vp, vp, i64, i32, vp]),
+    "wl_mlp_num_params": (i32, []),
     "wl_mlp_create": (C.c_int, [vp, vp, C.POINTER(vp)]),
     "wl_mlp_destroy": (C.c_int, [vp]),
     "wl_mlp_get_params": (C.c_int, [vp, vp]),
     "wl_mlp_forward": (C.c_int, [vp, vp, i64, vp]),
     "wl_mlp_loss_grad": (C.c_int, [vp, vp, vp, i64, pd, vp]),
     "wl_mlp_train_step": (C.c_int, [vp, vp, vp, i64, f64, pd]),
+    "wl_mlp_save": (C.c_int, [vp, C.c_char_p]),
+    "wl_mlp_load": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
 }
 
 _lib = None
