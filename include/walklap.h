@@ -28,8 +28,9 @@
  *  - Dense blocks are ROW-MAJOR n x b (the b values of one node contiguous),
  *    element type given by the precision of the object (float for WL_FP32,
  *    double for WL_FP64), base address 16-byte aligned.
- *  - Handles are created and destroyed by the library; destroying a context
- *    does not destroy graphs or operators made from it (destroy those first).
+ *  - Handles are created and destroyed by the library and reference counted: a
+ *    graph or network keeps its context alive and an operator keeps its graph
+ *    alive, so handles may be destroyed in any order (each exactly once).
  *  - Workspace (Krylov bases, recurrence buffers, reduction partials) is
  *    allocated by the library on the device and kept in the operator or graph
  *    for reuse; WL_ENOMEM if it cannot be allocated.

@@ -183,7 +183,16 @@ wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kclass, int64_t* launches, do
 }
 
 wl_status wl_ctx_destroy(wl_ctx* ctx) {
-  if (!ctx) return WL_OK;
+  ctx_release(ctx);
+  return WL_OK;
+}
+
+}  // extern "C"
+
+// Handles are reference counted: a graph or network keeps its context alive and an
+// operator keeps its graph alive, so the caller may destroy them in any order.
+void ctx_release(wl_ctx* ctx) {
+  if (!ctx || --ctx->refs > 0) return;
   {
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
@@ -196,8 +205,20 @@ wl_status wl_ctx_destroy(wl_ctx* ctx) {
     ctx->scratch.release();
   }
   delete ctx;
-  return WL_OK;
 }
+
+void graph_release(wl_graph* g) {
+  if (!g || --g->refs > 0) return;
+  wl_ctx* ctx = g->ctx;
+  {
+    DeviceGuard dg(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    delete g;
+  }
+  ctx_release(ctx);
+}
+
+extern "C" {
 
 // ------------------------------------------------------------------ graph
 wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_colidx,
@@ -316,6 +337,7 @@ wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_
   if (s == WL_OK) s = launch_degrees<float>(g, g->degf.as<float>());
   if (s == WL_OK) s = launch_degrees<double>(g, g->degd.as<double>());
   if (s != WL_OK) return fail(s);
+  ++ctx->refs;
   *out = g;
   return WL_OK;
 }
@@ -329,10 +351,7 @@ wl_status wl_graph_info(const wl_graph* g, int64_t* n, int64_t* nnz, int32_t* ma
 }
 
 wl_status wl_graph_destroy(wl_graph* g) {
-  if (!g) return WL_OK;
-  DeviceGuard dg(g->ctx->device);
-  (void)hipStreamSynchronize(g->ctx->stream);
-  delete g;
+  graph_release(g);
   return WL_OK;
 }
 
@@ -705,7 +724,8 @@ template <typename T>
 wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
   wl_graph* g = op->g;
   const int64_t n = g->n;
-  const int K = op->K;
+  // the block Krylov space has dimension <= n: more steps only add deflated blocks
+  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(op->K, (n + b - 1) / b + 1));
   const double mu = op->d.mu, p = op->d.param;
   LanczosOp<T> L;
   double scale = 1.0;
@@ -730,7 +750,20 @@ wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* 
     std::vector<double> rhs((size_t)Ke * b * b, 0.0), sol((size_t)Ke * b * b);
     for (int r = 0; r < b; ++r)
       for (int c = 0; c < b; ++c) rhs[(size_t)r * b + c] = hR0[(size_t)r * b + c];
-    bool ok = block_tridiag_solve(Ke, b, hA.data(), hB.data(), rhs.data(), b, sol.data()) == 0;
+    // Deflated basis columns leave rows of T that are exactly zero (and zero right-hand
+    // sides): give them a unit diagonal so they decouple from the solve.
+    std::vector<double> Ad(hA.begin(), hA.begin() + (size_t)Ke * b * b);
+    for (int j = 0; j < Ke; ++j)
+      for (int c = 0; c < b; ++c) {
+        bool zero = true;
+        for (int k = 0; k < b && zero; ++k) {
+          zero = Ad[(size_t)j * b * b + c * b + k] == 0.0;
+          if (zero && j > 0) zero = hB[(size_t)(j - 1) * b * b + c * b + k] == 0.0;   // T_{j, j-1} row c
+          if (zero && j + 1 < Ke) zero = hB[(size_t)j * b * b + k * b + c] == 0.0;    // T_{j+1, j} column c
+        }
+        if (zero) Ad[(size_t)j * b * b + c * b + c] = 1.0;
+      }
+    bool ok = block_tridiag_solve(Ke, b, Ad.data(), hB.data(), rhs.data(), b, sol.data()) == 0;
     if (ok) {
       F.resize(sol.size());
       for (size_t i = 0; i < sol.size(); ++i) F[i] = scale * sol[i];
@@ -1025,6 +1058,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   }
   auto* op = new wl_op;
   op->g = g;
+  ++g->refs;
   op->d = *d;
   op->d.method = method;
   op->rho = rho;
@@ -1035,9 +1069,13 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
 
 wl_status wl_op_destroy(wl_op* op) {
   if (!op) return WL_OK;
-  DeviceGuard dg(op->g->ctx->device);
-  (void)hipStreamSynchronize(op->g->ctx->stream);
-  delete op;
+  wl_graph* g = op->g;
+  {
+    DeviceGuard dg(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    delete op;
+  }
+  graph_release(g);
   return WL_OK;
 }
 

@@ -18,13 +18,18 @@ namespace {
 int tql(int m, double* d, double* e_in, double* Zt) {
   std::vector<double> e(m, 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = e_in[i];
+  // absolute floor for negligible couplings (exactly decoupled blocks with zero
+  // diagonal, as left by an exhausted Krylov space, must not stall the iteration)
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(d[i]) + (i + 1 < m ? std::fabs(e[i]) : 0.0));
+  const double floor_abs = 1e-16 * scale;
   for (int l = 0; l < m; ++l) {
     int iter = 0;
     while (true) {
       int mm = l;
       for (; mm < m - 1; ++mm) {
         const double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
-        if (std::fabs(e[mm]) <= 1e-16 * dd || e[mm] == 0.0) break;
+        if (std::fabs(e[mm]) <= 1e-16 * dd || std::fabs(e[mm]) <= floor_abs) break;
       }
       if (mm == l) break;
       if (++iter > 60) return 1;

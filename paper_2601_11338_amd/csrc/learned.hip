@@ -427,15 +427,18 @@ wl_status wl_mlp_create(wl_ctx* ctx, const float* h_params, wl_mlp** out) {
     wl_set_error("wl_mlp_create: upload failed");
     return WL_EDEVICE;
   }
+  ++ctx->refs;
   *out = net;
   return WL_OK;
 }
 
 wl_status wl_mlp_destroy(wl_mlp* net) {
   if (!net) return WL_OK;
-  (void)hipSetDevice(net->ctx->device);
-  (void)hipStreamSynchronize(net->ctx->stream);
+  wl_ctx* ctx = net->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   delete net;
+  ctx_release(ctx);
   return WL_OK;
 }
 

@@ -96,7 +96,9 @@ struct wl_ctx {
   DevBuf scratch;   // small device-side matrices
   bool profiling = false;
   KernelStats kstats[WL_KC_COUNT];
+  int refs = 1;  // the caller's handle + every graph / network made from it
 };
+void ctx_release(wl_ctx* ctx);
 
 struct wl_graph {
   wl_ctx* ctx = nullptr;
@@ -117,7 +119,9 @@ struct wl_graph {
   std::map<double, double> rho_cache;
   DevBuf degf, degd;                    // degree vector as float / double
   DevBuf tmp;                           // Lanczos scratch for spectral routines
+  int refs = 1;                         // the caller's handle + every operator on it
 };
+void graph_release(wl_graph* g);
 
 struct wl_op {
   wl_graph* g = nullptr;
