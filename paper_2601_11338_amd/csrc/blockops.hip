@@ -452,7 +452,15 @@ __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double th
 // Cc = [-P1 Rinv; -A Rinv; Rinv] so that V_{j+1} = [V_{j-1} V_j W'] Cc.
 __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const double* __restrict__ P, double tol,
                                                        double* __restrict__ Aout, double* __restrict__ R,
-                                                       double* __restrict__ Rinv, double* __restrict__ Cc) {
+                                                       double* __restrict__ Rinv, double* __restrict__ Cc,
+                                                       int64_t gs) {
+  // one workgroup per graph of a batch: every matrix of graph g sits gs doubles further
+  const int64_t go = (int64_t)blockIdx.x * gs;
+  P += go;
+  Aout += go;
+  R += go;
+  Rinv += go;
+  Cc += go;
   __shared__ double sG[64 * 65];
   __shared__ double sR[64 * 65];
   __shared__ double sA[64 * 65];
@@ -510,7 +518,16 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
 __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G, double tol,
                                              const double* __restrict__ Aref, const double* __restrict__ Bref,
                                              double* __restrict__ R, double* __restrict__ Rinv,
-                                             const double* __restrict__ Rprev, double* __restrict__ Bout) {
+                                             const double* __restrict__ Rprev, double* __restrict__ Bout,
+                                             int64_t gs) {
+  const int64_t go = (int64_t)blockIdx.x * gs;  // batch: graph g's matrices at +g gs
+  G += go;
+  if (Aref) Aref += go;
+  if (Bref) Bref += go;
+  if (R) R += go;
+  Rinv += go;
+  if (Rprev) Rprev += go;
+  if (Bout) Bout += go;
   __shared__ double sG[64 * 65];
   __shared__ double sR[64 * 65];
   __shared__ int defl[64];
@@ -899,17 +916,20 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 }
 
 wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
-                                double* Rinv, double* Cc) {
-  WL_CHECK(b >= 1 && b <= 64 && (nbv == 1 || nbv == 2), WL_EINVAL, "lanczos coefficients: bad sizes");
-  hipLaunchKernelGGL(k_lanczos_coeffs, dim3(1), dim3(64), 0, ctx->stream, b, nbv, P, tol, Aout, R, Rinv, Cc);
+                                double* Rinv, double* Cc, int ngraphs, int64_t gs) {
+  WL_CHECK(b >= 1 && b <= 64 && (nbv == 1 || nbv == 2) && ngraphs >= 1, WL_EINVAL,
+           "lanczos coefficients: bad sizes");
+  hipLaunchKernelGGL(k_lanczos_coeffs, dim3(ngraphs), dim3(64), 0, ctx->stream, b, nbv, P, tol, Aout, R, Rinv, Cc,
+                     gs);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
-                      double* R, double* Rinv, const double* Rprev, double* Bout) {
-  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "chol: b out of range");
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout);
+                      double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs) {
+  WL_CHECK(b >= 1 && b <= 64 && ngraphs >= 1, WL_EINVAL, "chol: b out of range");
+  hipLaunchKernelGGL(k_chol, dim3(ngraphs), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout,
+                     gs);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }

@@ -121,12 +121,22 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
                                          T* Y) {
   if (MASK && col >= b) return;
   const int64_t off = r * (int64_t)ld + col;
+  double ca = ep.a, cb0 = ep.b0, cb1 = ep.b1, csc = ep.sc;
+  bool fin = ep.wv != nullptr;
+  if (ep.gid) {
+    const double* c = ep.gtab + 5 * (int64_t)ep.gid[r];
+    ca = c[0];
+    cb0 = c[1];
+    cb1 = c[2];
+    csc = c[3];
+    fin = fin && c[4] != 0.0;
+  }
   T y[VW];
-  const T a = (T)ep.a;
+  const T a = (T)ca;
 #pragma unroll
   for (int i = 0; i < VW; ++i) y[i] = a * acc.v[i];
   if (ep.Z) {
-    const T coef = (T)(ep.b0 + ep.b1 * (double)deg);
+    const T coef = (T)(cb0 + cb1 * (double)deg);
     Frag<T, VW> z = ldf_m<T, VW, MASK>(ep.Z + off, true);
 #pragma unroll
     for (int i = 0; i < VW; ++i) y[i] += coef * z.v[i];
@@ -155,10 +165,10 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
       s = MASK ? ldf_m<T, VW, MASK>(ep.Sin + off, true) : ldf_nt<T, VW>(ep.Sin + off);
     else
       zero(s);
-    const T s0 = (T)ep.s0, sc = (T)ep.sc;
+    const T s0 = (T)ep.s0, sc = (T)csc;
 #pragma unroll
     for (int i = 0; i < VW; ++i) s.v[i] = s0 * s.v[i] + sc * y[i];
-    if (ep.wv) {
+    if (fin) {
       const T wr = ep.wv[r];
       Frag<T, VW> xw = MASK ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
 #pragma unroll
@@ -204,6 +214,10 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   if ((int)blockIdx.x < n_long) {
     constexpr int NSLOT = 256 / LPN;
     const int64_t r = long_rows[blockIdx.x];
+    if (ep.gid) {  // whole workgroup decides together
+      const double* c = ep.gtab + 5 * (int64_t)ep.gid[r];
+      if (c[0] == 0.0 && c[3] == 0.0) return;
+    }
     const int slot = threadIdx.x / LPN;
     const int s = rowptr[r], e = rowptr[r + 1];
     Frag<T, VW> acc;
@@ -237,6 +251,10 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   if (r >= n) return;  // whole group leaves together: all its lanes share r
   const int s = rowptr[r], e = rowptr[r + 1];
   if (e - s > long_thr) return;
+  if (ep.gid) {  // graph finished its recurrence: nothing to gather or write
+    const double* c = ep.gtab + 5 * (int64_t)ep.gid[r];
+    if (c[0] == 0.0 && c[3] == 0.0) return;
+  }
   const int slot = (lane % G) / LPN;
   Frag<T, VW> acc;
   zero(acc);

@@ -159,6 +159,11 @@ struct EpiArgs {
   const T* wv = nullptr;
   const T* Xw = nullptr;
   int kclass = WL_KC_OTHER_SPMM;  // timing class when profiling is on
+  // Batched graphs: row r belongs to graph gid[r]; gtab holds, per graph, the five
+  // coefficients {a, b0, b1, sc, fin} of this launch (replacing a, b0, b1, sc; fin != 0
+  // applies the walk-Laplacian finish).  Rows of graphs with a = sc = 0 are skipped.
+  const int32_t* gid = nullptr;
+  const double* gtab = nullptr;
 };
 
 template <typename T>
@@ -183,14 +188,17 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 // A pivot below tol * ref deflates its column, where
 //   ref = max(max_i G_ii, (||Aref||_F^2 + ||Bref||_F^2) / b)  (Aref, Bref optional b x b).
 // If Rprev is given, Bout = R * Rprev (else Bout = R when Bout is given).
+// ngraphs workgroups run independent instances, instance g on matrices offset by g * gs.
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
-                      double* R, double* Rinv, const double* Rprev, double* Bout);
+                      double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs = 1,
+                      int64_t gs = 0);
 
 // One block Lanczos projection: from P = [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or
 // [V_j^T W'; W'^T W'] (nbv = 1) form A_j (Aout), the deflated Cholesky factor R (and
 // Rinv) of the projected block's Gram, and Cc with V_{j+1} = [V_{j-1} V_j W'] Cc.
+// Batched like launch_chol.
 wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
-                                double* Rinv, double* Cc);
+                                double* Rinv, double* Cc, int ngraphs = 1, int64_t gs = 0);
 
 // Small device helpers on double matrices.
 wl_status launch_dadd(wl_ctx* ctx, int count, const double* x, double* y);   // y += x
