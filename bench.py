@@ -62,6 +62,23 @@ def copy_calibration():
                       "GBps": 5 * 2 * src.numel() * 4 / dt / 1e9}), flush=True)
 
 
+def measured_traffic(n, m, b):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs, scaled by the copy-kernel calibration; None when the
+    kernel source changed since the counters were taken or the workload differs."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_spmm_recurrence_ba1m_traffic.json")
+    src = os.path.join(ROOT, "paper_2601_11338_amd", "csrc", "spmm.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if sha != rec.get("source_sha1") or (n, m, b) != (1000000, 5, 16):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(rp, ci, n, lam, X, K):
     """The oracle (sparse FP64 series, eq. qrec) on a bounded sample of the step:
     one of the ten operators (mu = 0.5, exponential), degree K, on 1 + b columns."""
@@ -185,7 +202,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(n, m, b),
             "kernel": "k_spmm<float,4,4,G> fused recurrence step (b=16)",
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": kbytes / max(launches, 1),

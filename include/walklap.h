@@ -236,6 +236,36 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
                       int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
                       void* d_diag, double* trace, double* trace_err);
 
+/* ---------------------------------------------------------------- batches of graphs
+ * Many graphs with their own walk variant and weights, evaluated together: the
+ * graphs are concatenated into one block-diagonal CSR whose per-graph row ranges start
+ * at 16-row boundaries (offsets from wl_batch_info; padding rows have no edges and
+ * must hold zeros in inputs), so every sparse product, Gram and block update of a
+ * Krylov step is one launch for the whole batch.  Inner phi products use each graph's
+ * truncated series (eq. qrec) with degree from tol (exponential: tail bound with
+ * lambda_max; resolvent: geometric bound alpha lambda_max, or the asymptotic ratio
+ * alpha rho(Z_mu) plus 20 terms when alpha lambda_max >= 1).  FP32 vectors.
+ *
+ * wl_batch_create: descs[g] describes graph g (mu, func, param; krylov_dim > 0 fixes
+ * its series degree; rho_hint as for operators).  Computes every walk degree.
+ * wl_batch_apply_L: Y = L_g X_g for every graph (d_X, d_Y: total_rows x b).
+ * wl_batch_expv: Y_g = exp(-t_g L_g) U0_g for every graph (t: host array of ngraphs
+ * times) by outer_dim block Lanczos steps per graph, the projected exponential
+ * computed on the device; b in [2, 16] and 5 outer_dim b^2 doubles <= 150 KiB.
+ * If p_hat / p_err (host, ngraphs) are given and U0 holds iid Gaussian probes, they
+ * receive the leave-one-out Nystrom estimate of tr exp(-t_g L_g) / n_g (the average
+ * return probability, eq. average_return_probabilities, Alg. 1) and its error
+ * estimate, computed from the projected quantities only.                          */
+typedef struct wl_batch wl_batch;
+wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs, const wl_op_desc* descs,
+                          double tol, wl_batch** out);
+wl_status wl_batch_info(const wl_batch* batch, int64_t* total_rows, int32_t* max_series_degree,
+                        int64_t* row_offsets);
+wl_status wl_batch_apply_L(wl_batch* batch, const void* d_X, void* d_Y, int32_t b);
+wl_status wl_batch_expv(wl_batch* batch, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
+                        double* p_hat, double* p_err);
+wl_status wl_batch_destroy(wl_batch* batch);
+
 /* ---------------------------------------------------------------- learned control variate
  * No counterpart in the paper: a small network predicts diag(phi) from cheap local
  * features and serves as a control variate for the diagonal estimator.

@@ -354,3 +354,67 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many graphs evaluated together (one launch per Krylov step for the whole batch)."""
+
+    def __init__(self, ctx, graphs, descs, tol=1e-10):
+        """descs: list of dicts with mu, func ('exp' / 'res'), param [, krylov_dim, rho_hint]."""
+        self.ctx = ctx
+        self.graphs = list(graphs)
+        arr = (_lib.OpDesc * len(graphs))()
+        for i, d in enumerate(descs):
+            arr[i] = _lib.OpDesc(mu=float(d["mu"]), func=FUNCS[d["func"]], param=float(d["param"]), prec=WL_FP32,
+                                 krylov_dim=int(d.get("krylov_dim", 0)), tol=0.0, method=WL_M_RECURRENCE, reorth=1,
+                                 rho_hint=float(d.get("rho_hint", 0.0)))
+        handles = (C.c_void_p * len(graphs))(*[g.handle.value for g in graphs])
+        self.handle = C.c_void_p()
+        check(load().wl_batch_create(ctx.handle, len(graphs), handles, arr, float(tol), C.byref(self.handle)))
+        import numpy as np
+        total, kmax = C.c_int64(), C.c_int32()
+        offs = np.zeros(len(graphs), dtype=np.int64)
+        check(load().wl_batch_info(self.handle, C.byref(total), C.byref(kmax), offs.ctypes.data_as(C.c_void_p)))
+        self.total_rows, self.max_series_degree, self.offsets = total.value, kmax.value, offs
+        self.sizes = [g.n for g in graphs]
+
+    def pack(self, blocks):
+        """Place per-graph (n_g x b) tensors at their row offsets in one zero-padded block."""
+        torch = _torch()
+        b = blocks[0].shape[1]
+        out = torch.zeros((self.total_rows, b), dtype=torch.float32, device=self.ctx.torch_device)
+        for o, blk in zip(self.offsets, blocks):
+            out[int(o):int(o) + blk.shape[0]] = blk.to(torch.float32)
+        return out
+
+    def unpack(self, packed):
+        return [packed[int(o):int(o) + n] for o, n in zip(self.offsets, self.sizes)]
+
+    def apply_L(self, X, out=None):
+        out = _torch().empty_like(X) if out is None else out
+        check(load().wl_batch_apply_L(self.handle, _ptr(X), _ptr(out), X.shape[1]))
+        return out
+
+    def expv(self, U0, ts, outer_dim=30, out=None, want_trace=True):
+        import numpy as np
+        torch = _torch()
+        out = torch.empty_like(U0) if out is None else out
+        t = np.ascontiguousarray(ts, dtype=np.float64)
+        ph = np.zeros(len(self.graphs))
+        pe = np.zeros(len(self.graphs))
+        pd_ = C.POINTER(C.c_double)
+        check(load().wl_batch_expv(self.handle, _ptr(U0), U0.shape[1], t.ctypes.data_as(pd_), int(outer_dim),
+                                   _ptr(out), ph.ctypes.data_as(pd_) if want_trace else None,
+                                   pe.ctypes.data_as(pd_) if want_trace else None))
+        return out, ph, pe
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,701 @@
+// Many graphs in one launch per Krylov step.
+//
+// The graphs of a batch are concatenated into one block-diagonal CSR whose per-graph
+// row ranges are padded to multiples of 16 rows (padding rows have no edges), so
+//  * every sparse product of the recurrence is one launch over all graphs, with the
+//    per-graph coefficients of eq. qrec / the weights c_k read from a table indexed
+//    by the row's graph id (graphs whose series is already converged skip their rows);
+//  * every 16-row chunk belongs to one graph, so Gram products reduce per graph over
+//    fixed "units" of rows (deterministic) and block updates read the coefficient
+//    matrices of the row's graph;
+//  * the small dense work (projection coefficients, Cholesky, exp(-t T) E_1 R_0) runs
+//    one workgroup per graph.
+// Diffusion per graph is exp(-t_g L_g) U0_g by block Lanczos on the walk Laplacian
+// (inner phi products by the truncated series, eq. diffusion_on_G_with_downweighted_walk),
+// and the average return probability p_hat(t_g) (eq. average_return_probabilities) is
+// the leave-one-out Nystrom trace of Alg. 1 computed from the projected quantities alone:
+// with Omega = V_0 R_0 and Y = V F, Omega^T Y = R_0^T F_0 and Y^T Y = F^T F.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace {
+
+constexpr int UNIT_ROWS = 2048;  // rows per reduction unit (multiple of 16)
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Segmented Gram: for every unit u (rows [us[u], us[u+1]) of one graph, a multiple of
+// 16), partial[k][u] = X_k[rows]^T Y[rows] for b <= 16 columns, on the matrix cores
+// (FP64 accumulation, the operand layout of the single-graph Gram).
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_seg(const int64_t* __restrict__ us, int nunits,
+                                                  const float* __restrict__ X, int64_t sX, int nblk,
+                                                  const float* __restrict__ Y, int b,
+                                                  double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rsub = lane >> 4, c = lane & 15;
+  const int kb0 = blockIdx.y * NB;
+  const int nb = (nblk - kb0) < NB ? (nblk - kb0) : NB;
+  const bool cok = c < b;
+  for (int u = blockIdx.x * 4 + wave; u < nunits; u += gridDim.x * 4) {
+    v4d acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t r0 = us[u], r1 = us[u + 1];
+    for (int64_t r = r0; r < r1; r += 16) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int64_t row = r + 4 * m + rsub;
+        const double yb = cok ? (double)Y[row * b + c] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const double xa = (cok && q < nb) ? (double)X[(int64_t)(kb0 + q) * sX + row * b + c] : 0.0;
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc[q], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      if (q >= nb) break;
+      double* out = partials + ((int64_t)(kb0 + q) * nunits + u) * 256;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(4 * v + rsub) * 16 + c] = acc[q][v];
+    }
+  }
+}
+
+// out_g[(k b + i) b + j] = sum_{u in graph g} partial[k][u][i 16 + j]  (fixed order);
+// out_g = out + g * gs.
+__global__ __launch_bounds__(256) void k_gram_seg_finalize(const double* __restrict__ partials, int nunits,
+                                                           const int* __restrict__ gu0, int b,
+                                                           double* __restrict__ out, int64_t gs) {
+  const int g = blockIdx.z, k = blockIdx.y;
+  const int t = threadIdx.x;
+  const int el = t % 16, p = t / 16;  // 16 entries per block, 16 phases
+  const int e = blockIdx.x * 16 + el;
+  const int u0 = gu0[g], u1 = gu0[g + 1];
+  __shared__ double s[256];
+  double v = 0.0;
+  if (e < 256) {
+    const double* src = partials + (int64_t)k * nunits * 256 + e;
+    for (int u = u0 + p; u < u1; u += 16) v += src[(int64_t)u * 256];
+  }
+  s[t] = v;
+  __syncthreads();
+  for (int h = 8; h > 0; h >>= 1) {
+    if (p < h) s[t] += s[t + h * 16];
+    __syncthreads();
+  }
+  if (p == 0 && e < 256) {
+    const int i = e / 16, j = e % 16;
+    if (i < b && j < b) out[(int64_t)g * gs + ((int64_t)k * b + i) * b + j] = s[t];
+  }
+}
+
+// Out[r] = (wv ? wv[r] : alpha) Yin[r] + beta sum_k X_k[r] C_{g(r)}[k]   (b <= 16),
+// C_g = C + g * cgs, (nblk b) x b row-major double.
+template <int B>
+__global__ __launch_bounds__(256) void k_update_seg(int64_t N, const float* X, int64_t sX, int nblk, int b,
+                                                    const double* __restrict__ C, int64_t cgs,
+                                                    const int32_t* __restrict__ gid, const float* Yin, double alpha,
+                                                    const float* __restrict__ wv, double beta, float* Out) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+    const double* Cg = C + (int64_t)gid[r] * cgs;
+    float acc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = 0.f;
+    for (int k = 0; k < nblk; ++k) {
+      const float* xr = X + (int64_t)k * sX + r * b;
+      float xv[B];
+#pragma unroll
+      for (int i = 0; i < B; ++i) xv[i] = i < b ? xr[i] : 0.f;
+      const double* Ck = Cg + (int64_t)k * b * b;
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        if (i >= b) break;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          if (j < b) acc[j] += xv[i] * (float)Ck[i * b + j];
+      }
+    }
+    const float sc = wv ? wv[r] : (float)alpha;
+    float* o = Out + r * b;
+    const float* y = Yin ? Yin + r * b : nullptr;
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (j < b) o[j] = (float)beta * acc[j] + (y ? sc * y[j] : 0.f);
+  }
+}
+
+__global__ void k_dcopy_batched(int count, const double* __restrict__ x, double* __restrict__ y, int64_t gs) {
+  const int64_t go = (int64_t)blockIdx.x * gs;
+  for (int e = threadIdx.x; e < count; e += blockDim.x) y[go + e] = x[go + e];
+}
+
+__global__ void k_dtranspose_batched(int b, const double* __restrict__ x, double* __restrict__ y, int64_t gs) {
+  const int64_t go = (int64_t)blockIdx.x * gs;
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) y[go + (e % b) * b + e / b] = x[go + e];
+}
+
+// F_g = exp(-t_g T_g) E_1 R0_g for the block tridiagonal T_g (K blocks of b x b: A_j at
+// S_g + offA + j bb, T_{j+1,j} = B_j at S_g + offB + j bb), one workgroup per graph, FP64.
+// Sub-stepped Taylor series: s = ceil(t ||T||_inf) steps of length h = t / s, each
+// sum_i (-h T)^i V / i! until the term is negligible (h ||T|| <= 1, so <= 30 terms).
+constexpr int EXP_MAXM = 512;  // K b
+__global__ __launch_bounds__(256) void k_expT_batched(int K, int b, const double* __restrict__ S, int64_t gs,
+                                                      int64_t offA, int64_t offB, int64_t offR0,
+                                                      const double* __restrict__ tvals, double* __restrict__ F,
+                                                      int64_t fgs) {
+  extern __shared__ double sh[];
+  const int g = blockIdx.x;
+  const int bb = b * b, m = K * b, mb = m * b;
+  double* sA = sh;                 // K bb
+  double* sB = sA + (size_t)K * bb;  // K bb
+  double* sV = sB + (size_t)K * bb;  // m b   current vector
+  double* sT = sV + mb;            // m b   current Taylor term
+  double* sU = sT + mb;            // m b   scratch
+  __shared__ double red[256];
+  __shared__ double snorm;
+  const double* Sg = S + (int64_t)g * gs;
+  const int t = threadIdx.x;
+  for (int e = t; e < K * bb; e += 256) {
+    sA[e] = Sg[offA + e];
+    sB[e] = Sg[offB + e];
+  }
+  for (int e = t; e < mb; e += 256) {
+    const int r = e / b, c = e % b;
+    sV[e] = r < b ? Sg[offR0 + r * b + c] : 0.0;
+  }
+  __syncthreads();
+  // ||T||_inf
+  double mx = 0.0;
+  for (int r = t; r < m; r += 256) {
+    const int j = r / b, i = r % b;
+    double s = 0.0;
+    for (int c = 0; c < b; ++c) {
+      s += fabs(sA[j * bb + i * b + c]);
+      if (j > 0) s += fabs(sB[(j - 1) * bb + i * b + c]);      // T_{j, j-1} = B_{j-1}
+      if (j + 1 < K) s += fabs(sB[j * bb + c * b + i]);         // T_{j, j+1} = B_j^T
+    }
+    mx = fmax(mx, s);
+  }
+  red[t] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmax(red[t], red[t + h]);
+    __syncthreads();
+  }
+  if (t == 0) snorm = red[0];
+  __syncthreads();
+  const double tv = tvals[g];
+  const int steps = (int)fmin(1e6, fmax(1.0, ceil(tv * snorm)));
+  const double hstep = tv / steps;
+  for (int st = 0; st < steps; ++st) {
+    // term = V; sum into V itself: V_new = sum_i term_i
+    for (int e = t; e < mb; e += 256) sT[e] = sV[e];
+    __syncthreads();
+    for (int i = 1; i <= 40; ++i) {
+      // U = T * term
+      for (int e = t; e < mb; e += 256) {
+        const int r = e / b, c = e % b;
+        const int j = r / b, ii = r % b;
+        double s = 0.0;
+        for (int k = 0; k < b; ++k) {
+          s += sA[j * bb + ii * b + k] * sT[(j * b + k) * b + c];
+          if (j > 0) s += sB[(j - 1) * bb + ii * b + k] * sT[((j - 1) * b + k) * b + c];
+          if (j + 1 < K) s += sB[j * bb + k * b + ii] * sT[((j + 1) * b + k) * b + c];
+        }
+        sU[e] = s;
+      }
+      __syncthreads();
+      double tn = 0.0, vn = 0.0;
+      const double f = -hstep / i;
+      for (int e = t; e < mb; e += 256) {
+        const double v = f * sU[e];
+        sT[e] = v;
+        sV[e] += v;
+        tn = fmax(tn, fabs(v));
+        vn = fmax(vn, fabs(sV[e]));
+      }
+      red[t] = tn;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] = fmax(red[t], red[t + h]);
+        __syncthreads();
+      }
+      const double tmax = red[0];
+      __syncthreads();
+      red[t] = vn;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) red[t] = fmax(red[t], red[t + h]);
+        __syncthreads();
+      }
+      const double vmax = red[0];
+      __syncthreads();
+      if (tmax <= 1e-17 * vmax) break;
+    }
+  }
+  double* Fg = F + (int64_t)g * fgs;
+  for (int e = t; e < mb; e += 256) Fg[e] = sV[e];
+}
+
+struct Layout {  // small matrices of one graph (doubles), as in the single-graph driver
+  int b, K;
+  int64_t bb;
+  int64_t A(int j) const { return (int64_t)j * bb; }
+  int64_t B(int j) const { return (int64_t)(K + j) * bb; }
+  int64_t R0() const { return (int64_t)(2 * K) * bb; }
+  int64_t G() const { return (int64_t)(2 * K + 1) * bb; }
+  int64_t R1() const { return (int64_t)(2 * K + 2) * bb; }
+  int64_t Ri1() const { return (int64_t)(2 * K + 3) * bb; }
+  int64_t R2() const { return (int64_t)(2 * K + 4) * bb; }
+  int64_t Ri2() const { return (int64_t)(2 * K + 5) * bb; }
+  int64_t Cc() const { return (int64_t)(2 * K + 6) * bb; }
+  int64_t P() const { return (int64_t)(2 * K + 9) * bb; }   // 3 blocks
+  int64_t Bt() const { return (int64_t)(2 * K + 12) * bb; }
+  int64_t total() const { return (int64_t)(2 * K + 13) * bb; }
+};
+
+}  // namespace
+
+struct wl_batch {
+  wl_ctx* ctx = nullptr;
+  int ng = 0;
+  std::vector<int64_t> n, roff, npad;
+  int64_t N = 0;
+  DevBuf rowptr, colidx, gid;
+  wl_graph* G = nullptr;
+  std::vector<wl_op_desc> d;
+  std::vector<int> K;
+  int Kmax = 0;
+  DevBuf gtab;       // [Kmax][ng][5]
+  DevBuf gtab_none;  // all-zero-finish copy used for phi 1 (no Laplacian finish)
+  DevBuf w;          // walk degrees, N floats
+  std::vector<int64_t> us;
+  std::vector<int> gu0;
+  DevBuf d_us, d_gu0;
+  DevBuf bufA, bufB, ones, basis, S, F, partials, tvals;
+  int basis_b = 0, basis_K = 0;
+};
+
+namespace {
+
+wl_status batch_gram(wl_batch* bt, const float* X, int64_t sX, int nblk, const float* Y, int b, double* out,
+                     int64_t gs) {
+  wl_ctx* ctx = bt->ctx;
+  const int nunits = (int)bt->us.size() - 1;
+  WL_TRY(bt->partials.ensure((size_t)nblk * nunits * 256 * sizeof(double)));
+  const int blocks = std::max(1, std::min(1024, (nunits + 3) / 4));
+  const int NB = nblk >= 3 ? 3 : nblk;
+  dim3 grid(blocks, (nblk + NB - 1) / NB);
+  if (NB == 1)
+    hipLaunchKernelGGL(k_gram_seg<1>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
+                       b, bt->partials.as<double>());
+  else if (NB == 2)
+    hipLaunchKernelGGL(k_gram_seg<2>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
+                       b, bt->partials.as<double>());
+  else
+    hipLaunchKernelGGL(k_gram_seg<3>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
+                       b, bt->partials.as<double>());
+  WL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_gram_seg_finalize, dim3(16, nblk, bt->ng), dim3(256), 0, ctx->stream,
+                     bt->partials.as<double>(), nunits, bt->d_gu0.as<int>(), b, out, gs);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status batch_update(wl_batch* bt, const float* X, int64_t sX, int nblk, int b, const double* C, int64_t cgs,
+                       const float* Yin, double alpha, const float* wv, double beta, float* Out) {
+  const int grid = (int)std::min<int64_t>(8192, (bt->N + 255) / 256);
+  if (b <= 8)
+    hipLaunchKernelGGL((k_update_seg<8>), dim3(grid), dim3(256), 0, bt->ctx->stream, bt->N, X, sX, nblk, b, C, cgs,
+                       bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+  else
+    hipLaunchKernelGGL((k_update_seg<16>), dim3(grid), dim3(256), 0, bt->ctx->stream, bt->N, X, sX, nblk, b, C, cgs,
+                       bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+// phi X for every graph by its truncated series (eq. qrec), optionally finished into
+// the walk Laplacian (Y = w * X - phi X at each graph's last degree).
+wl_status batch_phi(wl_batch* bt, const float* X, float* Y, int b, bool laplacian) {
+  wl_graph* g = bt->G;
+  const int64_t N = bt->N;
+  WL_TRY(bt->bufA.ensure((size_t)N * b * 4));
+  WL_TRY(bt->bufB.ensure((size_t)N * b * 4));
+  float* A = bt->bufA.as<float>();
+  float* B = bt->bufB.as<float>();
+  const SpmmShape sh = [&] {
+    auto it = g->tuned.find(WL_FP32 * 1000 + b);
+    if (it != g->tuned.end()) return it->second;
+    SpmmShape s;
+    s.G = 16;
+    s.long_thr = 512;
+    return s;
+  }();
+  const double* tab = laplacian ? bt->gtab.as<double>() : bt->gtab_none.as<double>();
+  const int64_t tstride = (int64_t)bt->ng * 5;
+  {
+    EpiArgs<float> ep;
+    ep.gid = bt->gid.as<int32_t>();
+    ep.gtab = tab;
+    ep.Sin = X;
+    ep.Sout = Y;
+    ep.s0 = 1.0;
+    if (laplacian) {
+      ep.wv = bt->w.as<float>();
+      ep.Xw = X;
+    }
+    ep.kclass = WL_KC_RECURRENCE;
+    WL_TRY(launch_spmm<float>(g, X, A, b, ep, sh));
+  }
+  const float* Pm2 = X;
+  float* Pm1 = A;
+  for (int k = 2; k <= bt->Kmax; ++k) {
+    EpiArgs<float> ep;
+    ep.gid = bt->gid.as<int32_t>();
+    ep.gtab = tab + (int64_t)(k - 1) * tstride;
+    ep.Z = Pm2;
+    ep.Sin = Y;
+    ep.Sout = Y;
+    ep.s0 = 1.0;
+    if (laplacian) {
+      ep.wv = bt->w.as<float>();
+      ep.Xw = X;
+    }
+    ep.kclass = WL_KC_RECURRENCE;
+    float* out = (k == 2) ? B : const_cast<float*>(Pm2);
+    WL_TRY(launch_spmm<float>(g, Pm1, out, b, ep, sh));
+    Pm2 = Pm1;
+    Pm1 = out;
+  }
+  return WL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs, const wl_op_desc* descs,
+                          double tol, wl_batch** out) {
+  WL_CHECK(ctx && graphs && descs && out, WL_EINVAL, "wl_batch_create: null argument");
+  *out = nullptr;
+  WL_CHECK(ngraphs >= 1, WL_EINVAL, "wl_batch_create: need at least one graph");
+  WL_CHECK(std::isfinite(tol) && tol >= 0, WL_EINVAL, "wl_batch_create: bad tol");
+  if (tol == 0) tol = 1e-10;
+  (void)hipSetDevice(ctx->device);
+  auto* bt = new wl_batch;
+  bt->ctx = ctx;
+  bt->ng = ngraphs;
+  auto fail = [&](wl_status s) {
+    if (bt->G) graph_release(bt->G);
+    delete bt;
+    return s;
+  };
+  // sizes, padded offsets, per-graph series degree
+  int64_t nnz_tot = 0;
+  bt->n.resize(ngraphs);
+  bt->roff.resize(ngraphs);
+  bt->npad.resize(ngraphs);
+  bt->K.resize(ngraphs);
+  bt->d.assign(descs, descs + ngraphs);
+  for (int gi = 0; gi < ngraphs; ++gi) {
+    wl_graph* g = graphs[gi];
+    if (!g || g->ctx != ctx) {
+      wl_set_error("wl_batch_create: graph %d is null or from another context", gi);
+      return fail(WL_EINVAL);
+    }
+    const wl_op_desc& d = descs[gi];
+    if (!(d.mu >= 0 && d.mu <= 1) || !(d.param > 0) || (d.func != WL_F_EXP && d.func != WL_F_RESOLVENT)) {
+      wl_set_error("wl_batch_create: bad descriptor for graph %d", gi);
+      return fail(WL_EINVAL);
+    }
+    bt->n[gi] = g->n;
+    bt->npad[gi] = std::max<int64_t>(16, (g->n + 15) / 16 * 16);
+    bt->roff[gi] = bt->N;
+    bt->N += bt->npad[gi];
+    nnz_tot += g->nnz;
+    double lam;
+    wl_status s = wl_lambda_max(g, 1e-10, &lam);
+    if (s != WL_OK) return fail(s);
+    int K = d.krylov_dim;
+    if (K == 0) {
+      if (d.func == WL_F_EXP) {
+        const double x = d.param * lam;
+        double term = 1.0, tail = std::exp(x) - 1.0;
+        K = 0;
+        while (tail > tol * std::exp(x) && K < 400) {
+          ++K;
+          term *= x / K;
+          tail -= term;
+        }
+      } else {
+        // ||q_k|| <= lambda_max^k: geometric tail of ratio r = alpha lambda_max
+        double rho = d.rho_hint;
+        if (!(rho > 0)) {
+          s = wl_spectral_radius(g, d.mu, 1e-8, &rho);
+          if (s != WL_OK) return fail(s);
+        }
+        if (d.param * rho >= 1.0) {
+          wl_set_error("wl_batch_create: alpha * rho(Z_mu) >= 1 for graph %d", gi);
+          return fail(WL_ERANGE);
+        }
+        // rigorous when alpha lambda_max < 1 (||q_k|| <= lambda_max^k); otherwise the
+        // asymptotic ratio alpha rho(Z_mu) with a margin of 20 terms
+        const double r = d.param * lam;
+        if (r < 1.0)
+          K = (int)std::ceil(std::log(tol * (1.0 - r)) / std::log(r));
+        else
+          K = (int)std::ceil(std::log(tol * (1.0 - d.param * rho)) / std::log(d.param * rho)) + 20;
+        K = std::max(1, std::min(K, 400));
+      }
+    }
+    bt->K[gi] = std::max(1, K);
+    bt->Kmax = std::max(bt->Kmax, bt->K[gi]);
+  }
+  WL_CHECK(nnz_tot < (1ll << 31) && bt->N < (1ll << 31) - 1, WL_ERANGE, "wl_batch_create: batch too large");
+  // concatenated CSR on the host
+  std::vector<int32_t> hrp(bt->N + 1), hgid(bt->N);
+  std::vector<int32_t> hci((size_t)std::max<int64_t>(nnz_tot, 1));
+  int64_t pos = 0;
+  for (int gi = 0; gi < ngraphs; ++gi) {
+    wl_graph* g = graphs[gi];
+    std::vector<int32_t> rp(g->n + 1);
+    if (hipMemcpy(rp.data(), g->rowptr, (g->n + 1) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        (g->nnz > 0 && hipMemcpy(hci.data() + pos, g->colidx, g->nnz * 4, hipMemcpyDeviceToHost) != hipSuccess)) {
+      wl_set_error("wl_batch_create: reading graph %d failed", gi);
+      return fail(WL_EDEVICE);
+    }
+    const int64_t ro = bt->roff[gi];
+    for (int64_t r = 0; r < bt->npad[gi]; ++r) {
+      hrp[ro + r] = (int32_t)(pos + (r < g->n ? rp[r] : g->nnz));
+      hgid[ro + r] = gi;
+    }
+    for (int64_t e = 0; e < g->nnz; ++e) hci[pos + e] += (int32_t)ro;
+    pos += g->nnz;
+  }
+  hrp[bt->N] = (int32_t)pos;
+  wl_status s = bt->rowptr.ensure((bt->N + 1) * 4);
+  if (s == WL_OK) s = bt->colidx.ensure(hci.size() * 4);
+  if (s == WL_OK) s = bt->gid.ensure(bt->N * 4);
+  if (s != WL_OK) return fail(s);
+  if (hipMemcpy(bt->rowptr.p, hrp.data(), (bt->N + 1) * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bt->colidx.p, hci.data(), hci.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bt->gid.p, hgid.data(), bt->N * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    wl_set_error("wl_batch_create: upload failed");
+    return fail(WL_EDEVICE);
+  }
+  s = wl_graph_create(ctx, bt->N, pos, bt->rowptr.as<int32_t>(), bt->colidx.as<int32_t>(), 0, &bt->G);
+  if (s != WL_OK) return fail(s);
+  // reduction units
+  bt->gu0.resize(ngraphs + 1);
+  for (int gi = 0; gi < ngraphs; ++gi) {
+    bt->gu0[gi] = (int)bt->us.size();
+    for (int64_t r = 0; r < bt->npad[gi]; r += UNIT_ROWS) bt->us.push_back(bt->roff[gi] + r);
+  }
+  bt->gu0[ngraphs] = (int)bt->us.size();
+  bt->us.push_back(bt->N);
+  s = bt->d_us.ensure(bt->us.size() * 8);
+  if (s == WL_OK) s = bt->d_gu0.ensure(bt->gu0.size() * 4);
+  if (s != WL_OK) return fail(s);
+  if (hipMemcpy(bt->d_us.p, bt->us.data(), bt->us.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bt->d_gu0.p, bt->gu0.data(), bt->gu0.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(WL_EDEVICE);
+  // coefficient tables: step k (1-based) of graph g: {a, b0, b1, sc, fin}
+  std::vector<double> tab((size_t)bt->Kmax * ngraphs * 5, 0.0), tab0;
+  for (int gi = 0; gi < ngraphs; ++gi) {
+    const double sp = bt->d[gi].param, mu = bt->d[gi].mu;
+    double omega = 1.0;
+    for (int k = 1; k <= bt->K[gi]; ++k) {
+      if (bt->d[gi].func == WL_F_EXP) omega /= k;  // c_k / s^k = 1 / k!
+      double* c = &tab[((size_t)(k - 1) * ngraphs + gi) * 5];
+      c[0] = sp;
+      c[1] = k >= 3 ? sp * sp * mu * mu : 0.0;
+      c[2] = k >= 2 ? -sp * sp * mu : 0.0;
+      c[3] = omega;
+      c[4] = k == bt->K[gi] ? 1.0 : 0.0;
+    }
+  }
+  tab0 = tab;
+  for (size_t i = 4; i < tab0.size(); i += 5) tab0[i] = 0.0;
+  s = bt->gtab.ensure(tab.size() * 8);
+  if (s == WL_OK) s = bt->gtab_none.ensure(tab.size() * 8);
+  if (s != WL_OK) return fail(s);
+  if (hipMemcpy(bt->gtab.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(bt->gtab_none.p, tab0.data(), tab0.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(WL_EDEVICE);
+  // walk degrees w = phi 1 for every graph
+  s = bt->w.ensure(bt->N * 4);
+  if (s == WL_OK) s = bt->ones.ensure(bt->N * 4);
+  if (s == WL_OK) s = launch_fill<float>(ctx, bt->N, 1.0f, bt->ones.as<float>());
+  if (s == WL_OK) s = batch_phi(bt, bt->ones.as<float>(), bt->w.as<float>(), 1, false);
+  if (s == WL_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) s = WL_EDEVICE;
+  if (s != WL_OK) return fail(s);
+  ++ctx->refs;
+  *out = bt;
+  return WL_OK;
+}
+
+wl_status wl_batch_destroy(wl_batch* bt) {
+  if (!bt) return WL_OK;
+  wl_ctx* ctx = bt->ctx;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  graph_release(bt->G);
+  delete bt;
+  ctx_release(ctx);
+  return WL_OK;
+}
+
+wl_status wl_batch_info(const wl_batch* bt, int64_t* total_rows, int32_t* max_degree_series, int64_t* row_offsets) {
+  WL_CHECK(bt, WL_EINVAL, "wl_batch_info: batch is null");
+  if (total_rows) *total_rows = bt->N;
+  if (max_degree_series) *max_degree_series = bt->Kmax;
+  if (row_offsets)
+    for (int g = 0; g < bt->ng; ++g) row_offsets[g] = bt->roff[g];
+  return WL_OK;
+}
+
+wl_status wl_batch_apply_L(wl_batch* bt, const void* d_X, void* d_Y, int32_t b) {
+  WL_CHECK(bt && d_X && d_Y && d_X != d_Y, WL_EINVAL, "wl_batch_apply_L: bad arguments");
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_batch_apply_L: b must lie in [1, 64]");
+  (void)hipSetDevice(bt->ctx->device);
+  return batch_phi(bt, (const float*)d_X, (float*)d_Y, b, true);
+}
+
+wl_status wl_batch_expv(wl_batch* bt, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
+                        double* p_hat, double* p_err) {
+  WL_CHECK(bt && d_U0 && d_Y && t && d_U0 != d_Y, WL_EINVAL, "wl_batch_expv: bad arguments");
+  WL_CHECK(b >= 2 && b <= 16, WL_EINVAL, "wl_batch_expv: b must lie in [2, 16]");
+  WL_CHECK(outer_dim >= 1 && outer_dim * b <= EXP_MAXM, WL_EINVAL, "wl_batch_expv: outer_dim * b must be <= %d",
+           EXP_MAXM);
+  // the projected matrix, its exponential's work vectors live in one workgroup's LDS
+  WL_CHECK((size_t)5 * outer_dim * b * b * 8 <= 150 * 1024, WL_EINVAL,
+           "wl_batch_expv: outer_dim * b^2 too large for the on-chip exponential (5 outer_dim b^2 doubles <= 150 KiB)");
+  for (int g = 0; g < bt->ng; ++g) WL_CHECK(std::isfinite(t[g]) && t[g] >= 0, WL_EINVAL, "wl_batch_expv: bad t");
+  wl_ctx* ctx = bt->ctx;
+  (void)hipSetDevice(ctx->device);
+  const int K = outer_dim, ng = bt->ng;
+  const int64_t N = bt->N, blk = N * b;
+  Layout Ly{b, K, (int64_t)b * b};
+  const int64_t gs = Ly.total();
+  WL_TRY(bt->basis.ensure((size_t)(K + 1) * blk * 4));
+  WL_TRY(bt->S.ensure((size_t)ng * gs * 8));
+  WL_TRY(bt->F.ensure((size_t)ng * K * b * b * 8));
+  WL_TRY(bt->tvals.ensure((size_t)ng * 8));
+  float* V = bt->basis.as<float>();
+  double* S = bt->S.as<double>();
+  const double tol = 1e-10;
+  const float* U0 = (const float*)d_U0;
+  // V_0 R_0 = U0 by CholQR2, per graph
+  WL_TRY(batch_gram(bt, U0, 0, 1, U0, b, S + Ly.G(), gs));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, ng, gs));
+  WL_TRY(batch_update(bt, U0, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, V));
+  WL_TRY(batch_gram(bt, V, 0, 1, V, b, S + Ly.G(), gs));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
+                     ng, gs));
+  WL_TRY(batch_update(bt, V, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, V));
+  for (int j = 0; j < K; ++j) {
+    float* Vj = V + (int64_t)j * blk;
+    float* Vn = V + (int64_t)(j + 1) * blk;
+    WL_TRY(batch_phi(bt, Vj, Vn, b, true));  // W' = L V_j
+    if (j > 0) {
+      hipLaunchKernelGGL(k_dtranspose_batched, dim3(ng), dim3(64), 0, ctx->stream, b, S + Ly.B(j - 1), S + Ly.Bt(),
+                         gs);
+      WL_HIP(hipGetLastError());
+      WL_TRY(batch_update(bt, Vj - blk, 0, 1, b, S + Ly.Bt(), gs, Vn, 1.0, nullptr, -1.0, Vn));
+    }
+    const int nbv = j > 0 ? 2 : 1;
+    float* Vlo = j > 0 ? Vj - blk : Vj;
+    WL_TRY(batch_gram(bt, Vlo, blk, nbv + 1, Vn, b, S + Ly.P(), gs));
+    WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(), S + Ly.Cc(),
+                                 ng, gs));
+    if (j + 1 == K) {  // residual coupling B_{K-1} = R1 of every graph
+      hipLaunchKernelGGL(k_dcopy_batched, dim3(ng), dim3(64), 0, ctx->stream, b * b, S + Ly.R1(), S + Ly.B(j), gs);
+      WL_HIP(hipGetLastError());
+      break;
+    }
+    WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+    WL_TRY(batch_gram(bt, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
+    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                       S + Ly.B(j), ng, gs));
+    WL_TRY(batch_update(bt, Vn, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+  }
+  // F_g = exp(-t_g T_g) E_1 R0_g on the device, then Y = V F per graph
+  WL_HIP(hipMemcpyAsync(bt->tvals.p, t, (size_t)ng * 8, hipMemcpyHostToDevice, ctx->stream));
+  const size_t lds = ((size_t)2 * K * b * b + 3 * (size_t)K * b * b) * sizeof(double);
+  WL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expT_batched),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_expT_batched, dim3(ng), dim3(256), lds, ctx->stream, K, b, S, gs, Ly.A(0), Ly.B(0), Ly.R0(),
+                     bt->tvals.as<double>(), bt->F.as<double>(), (int64_t)K * b * b);
+  WL_HIP(hipGetLastError());
+  WL_TRY(batch_update(bt, V, blk, K, b, bt->F.as<double>(), (int64_t)K * b * b, nullptr, 0.0, nullptr, 1.0,
+                      (float*)d_Y));
+  if (p_hat || p_err) {
+    // Nystrom trace per graph from F_g and R0_g alone (Omega = V_0 R0, Y = V F).
+    std::vector<double> hF((size_t)ng * K * b * b), hS((size_t)ng * gs);
+    WL_HIP(hipMemcpyAsync(hF.data(), bt->F.p, hF.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    for (int g = 0; g < ng; ++g) {
+      const double* Fg = &hF[(size_t)g * K * b * b];
+      const double* R0 = &hS[(size_t)g * gs + Ly.R0()];
+      const int M = b, m = K * b;
+      std::vector<double> H((size_t)M * M, 0.0), Gm((size_t)M * M, 0.0);
+      for (int i = 0; i < M; ++i)
+        for (int jj = 0; jj < M; ++jj) {
+          double s1 = 0.0, s2 = 0.0;
+          for (int k = 0; k < M; ++k) s1 += R0[k * M + i] * Fg[k * M + jj];  // (R0^T F_0)
+          for (int r = 0; r < m; ++r) s2 += Fg[(size_t)r * M + i] * Fg[(size_t)r * M + jj];
+          H[(size_t)i * M + jj] = s1;
+          Gm[(size_t)i * M + jj] = s2;
+        }
+      // leave-one-out Nystrom (same formulas as wl_estimate)
+      std::vector<double> tj(M);
+      for (int j = 0; j < M; ++j) {
+        const int mm = M - 1;
+        std::vector<double> Sm((size_t)mm * mm), lam(mm), U((size_t)mm * mm);
+        std::vector<int> map;
+        for (int a = 0; a < M; ++a)
+          if (a != j) map.push_back(a);
+        for (int a = 0; a < mm; ++a)
+          for (int c = 0; c < mm; ++c)
+            Sm[(size_t)a * mm + c] =
+                0.5 * (H[(size_t)map[a] * M + map[c]] + H[(size_t)map[c] * M + map[a]]);
+        double trPG = 0.0, hPh = 0.0;
+        if (mm > 0 && dense_syev(mm, Sm.data(), lam.data(), U.data()) == 0) {
+          double lmax = 0.0;
+          for (double v : lam) lmax = std::max(lmax, v);
+          std::vector<double> P((size_t)mm * mm, 0.0);
+          for (int k = 0; k < mm; ++k) {
+            if (!(lam[k] > 1e-10 * lmax)) continue;
+            for (int a = 0; a < mm; ++a)
+              for (int c = 0; c < mm; ++c) P[(size_t)a * mm + c] += U[(size_t)a * mm + k] * U[(size_t)c * mm + k] / lam[k];
+          }
+          for (int a = 0; a < mm; ++a)
+            for (int c = 0; c < mm; ++c) {
+              trPG += P[(size_t)a * mm + c] * Gm[(size_t)map[c] * M + map[a]];
+              hPh += H[(size_t)j * M + map[a]] * P[(size_t)a * mm + c] * H[(size_t)j * M + map[c]];
+            }
+        }
+        tj[j] = trPG + H[(size_t)j * M + j] - hPh;
+      }
+      double mean = 0.0;
+      for (double v : tj) mean += v;
+      mean /= M;
+      double var = 0.0;
+      for (double v : tj) var += (v - mean) * (v - mean);
+      if (p_hat) p_hat[g] = mean / (double)bt->n[g];
+      if (p_err) p_err[g] = std::sqrt(var / (M - 1)) / std::sqrt((double)M) / (double)bt->n[g];
+    }
+  }
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
+}  // extern "C"

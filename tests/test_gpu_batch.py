@@ -1,0 +1,86 @@
+"""Batched evaluation of many graphs (one launch per Krylov step) against the
+per-graph dense oracle: walk Laplacian products, diffusion exp(-t L) U0, and the
+Nystrom average return probability."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimators, genfun, laplacian, philox, walks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def mixed_graphs():
+    gs = [
+        (300,) + synth.erdos_renyi_gnm(300, 1200, 1),
+        (250,) + synth.barabasi_albert(250, 3, 2),
+        (400,) + synth.stochastic_block_model(400, 4, 10, 20, 3),
+        (350,) + synth.configuration_model_powerlaw(350, 2.5, 2, 18, 4),
+        (13,) + synth.toy_g58(),
+        (200,) + synth.erdos_renyi_gnm(200, 900, 5),
+    ]
+    variants = [(0.0, "res"), (0.5, "exp"), (1.0, "res"), (0.25, "exp"), (0.75, "res"), (1.0, "exp")]
+    ts = [1.0, 0.1, 10.0, 1.0, 0.5, 10.0]
+    return gs, variants, ts
+
+
+def dense_phi(n, rp, ci, mu, kind):
+    A = walks.adjacency(n, rp, ci)
+    if kind == "exp":
+        param = 1.0 / max(np.linalg.eigvalsh(A)[-1], 1e-12)
+    else:
+        param = 0.5 / walks.spectral_radius(walks.linearisation(A, mu))
+    return param, genfun.phi(A, mu, kind, param)
+
+
+@pytest.fixture(scope="module")
+def setup(ctx, lib):
+    gs, variants, ts = mixed_graphs()
+    graphs, descs, phis = [], [], []
+    for (n, rp, ci), (mu, kind) in zip(gs, variants):
+        param, ph = dense_phi(n, rp, ci, mu, kind)
+        graphs.append(lib.Graph(ctx, rp, ci, validate=True))
+        descs.append({"mu": mu, "func": kind, "param": param})
+        phis.append(ph)
+    batch = lib.Batch(ctx, graphs, descs, tol=1e-12)
+    return batch, phis, ts
+
+
+def test_batch_apply_L(setup):
+    batch, phis, _ = setup
+    b = 8
+    Xs = [synth.gaussian_block(ph.shape[0], b, 10 + i) for i, ph in enumerate(phis)]
+    X = batch.pack([torch.tensor(x, dtype=torch.float32, device="cuda") for x in Xs])
+    Y = batch.apply_L(X)
+    for i, (ph, x, y) in enumerate(zip(phis, Xs, batch.unpack(Y))):
+        ref = laplacian.apply_laplacian(ph, x.astype(np.float32).astype(np.float64))
+        w = ph.sum(1)
+        scale = np.linalg.norm(w[:, None] * x) + np.linalg.norm(ph @ x)
+        err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / scale
+        assert err < 2e-5, (i, err)
+
+
+def test_batch_expv_and_return_probability(setup):
+    batch, phis, ts = setup
+    b = 8
+    Oms = [philox.gaussian(ph.shape[0], b, 100 + i).astype(np.float32).astype(np.float64) for i, ph in enumerate(phis)]
+    U0 = batch.pack([torch.tensor(o, dtype=torch.float32, device="cuda") for o in Oms])
+    Y, p_hat, p_err = batch.expv(U0, ts, outer_dim=30)
+    for i, (ph, om, y, t) in enumerate(zip(phis, Oms, batch.unpack(Y), ts)):
+        L = laplacian.walk_laplacian(ph)
+        (ref,) = laplacian.expv(L, om, [t])
+        err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref)
+        assert err < 1e-4, (i, err)
+        n = ph.shape[0]
+        tr_o, e_o, _, _ = estimators.xnys(om, ref, rcond=1e-10)
+        assert abs(p_hat[i] - tr_o / n) < 1e-4 * max(tr_o / n, 1e-3) + 1e-6, (i, p_hat[i], tr_o / n)
+        # the estimate is close to the true average return probability
+        exact = laplacian.average_return_probability(L, t)
+        assert abs(p_hat[i] - exact) < 6 * max(p_err[i], 1e-3), (i, p_hat[i], exact, p_err[i])
