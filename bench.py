@@ -35,7 +35,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="ba1m", choices=["ba1m"])
+    p.add_argument("--workload", default="ba1m", choices=["ba1m", "batch512", "cv-rmat22"],
+                   help="ba1m: one Barabasi-Albert graph, n=10^6 (default); batch512: 512 SBM / "
+                        "configuration-model graphs, diffusion and return probabilities in one batch; "
+                        "cv-rmat22: learned control variate trained on 200 small graphs, diagonal "
+                        "error versus probes on an R-MAT scale-22 graph")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--krylov", type=int, default=30)
     p.add_argument("--block", type=int, default=16)
@@ -103,6 +107,289 @@ def cpu_baseline(rp, ci, n, lam, X, K):
     }
 
 
+def _gen_spec(spec):
+    import synth
+    return synth.graph_from_spec(spec)
+
+
+def run_batch512(args):
+    """512 graphs (SBM with 4..32 blocks and p_in/p_out = 20, power-law configuration
+    model with exponent 2.5; sizes log-uniform on [1e3, 2e5]) with mixed variants:
+    graph i has mu = (0, .25, .5, .75, 1)[i % 5], the exponential (beta = 1/lambda_max)
+    or the resolvent (alpha = 0.5/lambda_max, which is below 1/rho(Z_mu) for every mu)
+    alternating every five graphs, and t = (0.1, 1, 10)[i % 3].  One step = one batched
+    diffusion exp(-t_g L_g) U0_g with 8 Gaussian probes per graph and 30 outer block
+    Lanczos steps, plus every graph's Nystrom return probability p_hat(t_g)."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+
+    import paper_2601_11338_amd as wl
+    import synth
+
+    count, b, K_out = 512, 8, args.krylov
+    specs = synth.batch_specs(count, seed=2026)
+    log(f"generating {count} graphs")
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        csrs = list(ex.map(_gen_spec, specs, chunksize=8))
+    ctx = wl.Context(0)
+    graphs = [wl.Graph(ctx, rp, ci) for rp, ci in csrs]
+    nnz = np.array([g.nnz for g in graphs], dtype=np.int64)
+    log(f"graphs uploaded: sum n={sum(g.n for g in graphs)} sum nnz={int(nnz.sum())}")
+    mus = [0.0, 0.25, 0.5, 0.75, 1.0]
+    descs, ts = [], []
+    for i, g in enumerate(graphs):
+        lam = g.lambda_max()
+        mu = mus[i % 5]
+        if (i // 5) % 2 == 0:
+            descs.append({"mu": mu, "func": "exp", "param": 1.0 / lam})
+        else:
+            descs.append({"mu": mu, "func": "res", "param": 0.5 / lam, "rho_hint": lam})
+        ts.append((0.1, 1.0, 10.0)[i % 3])
+    log("spectral scales done; building the batch")
+    batch = wl.Batch(ctx, graphs, descs, tol=1e-8)
+    batch.autotune(b)
+    Kg = batch.series_degrees.astype(np.int64)
+    offs = np.append(batch.offsets, batch.total_rows)
+    npad = np.diff(offs)
+    log(f"batch rows {batch.total_rows}, series degrees {Kg.min()}..{Kg.max()} (mean {Kg.mean():.1f})")
+    # 8 Gaussian probes per graph (Philox), zero on the padding rows
+    U0 = wl.probes(ctx, batch.total_rows, b, seed=11)
+    keep = torch.zeros(batch.total_rows, dtype=torch.bool, device="cuda")
+    for o, g in zip(batch.offsets, graphs):
+        keep[int(o):int(o) + g.n] = True
+    U0 = (U0 * keep[:, None]).contiguous()
+    Y = torch.empty_like(U0)
+
+    def step():
+        return batch.expv(U0, ts, outer_dim=K_out, out=Y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, p_hat, p_err = step()
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done")
+    t1 = time.perf_counter()
+    rec = ctx.kernel_stats(0)
+    ctx.set_profiling(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    edge_vec = K_out * float((Kg * nnz).sum()) * b
+    value = edge_vec / (ms * 1e-3) / 1e9
+    # algorithmic bytes of the recurrence launches of one inner product, counting only
+    # the rows of graphs still inside their series (the others are skipped)
+    alg = 0.0
+    for k in range(1, int(Kg.max()) + 1):
+        act = Kg >= k
+        streams = 4 if k == 1 else 5
+        alg += float((4 * nnz[act] + 4 * npad[act] + 4 * b * npad[act] * streams).sum())
+        fin = Kg == k
+        alg += float((4 * b * npad[fin] + 4 * npad[fin]).sum())
+    alg *= K_out * args.steps
+    launches, kms, _ = rec
+    achieved = alg / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    log(f"recurrence kernel: {launches} launches, avg {kms / max(launches, 1) * 1e3:.1f} us, "
+        f"{achieved:.0f} GB/s algorithmic; mean p_hat {np.mean(p_hat):.4f}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GEdge·vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch of {count} graphs (SBM 4..32 blocks p_in/p_out=20, power-law CM exponent 2.5; "
+                        f"n log-uniform 1e3..2e5); mixed mu/f, t in {{0.1,1,10}}; b={b} Gaussian probes; "
+                        f"outer Krylov dim {K_out}; inner series to 1e-8; p_hat per graph",
+            "graphs": count,
+            "sum_n": int(sum(g.n for g in graphs)),
+            "sum_nnz": int(nnz.sum()),
+            "block": b,
+            "krylov_dim": K_out,
+            "series_degree_max": int(Kg.max()),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_spmm batched recurrence step (b=8, per-graph coefficient table)",
+            "avg_launch_us": kms / max(launches, 1) * 1e3,
+            "alg_bytes_per_launch": alg / max(launches, 1),
+        },
+        "p_hat_mean": float(np.mean(p_hat)),
+        "p_err_mean": float(np.mean(p_err)),
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline_batch(csrs, descs, b)
+    return out
+
+
+def cpu_baseline_batch(csrs, descs, b, budget_s=15.0):
+    """The oracle's sparse FP64 series (eq. qrec) applied to a b-column block, graph
+    after graph, until the time budget is spent: the inner product of one outer step."""
+    import numpy as np
+    from oracle import sparse
+
+    done_ev, t_used, graphs = 0.0, 0.0, 0
+    for (rp, ci), d in zip(csrs, descs):
+        n = len(rp) - 1
+        A = sparse.adjacency(n, rp, ci)
+        K = 30
+        if d["func"] == "exp":
+            coeffs = np.array([d["param"] ** k / math.factorial(k) for k in range(K + 1)])
+        else:
+            coeffs = np.array([d["param"] ** k for k in range(K + 1)])
+        X = np.ones((n, b))
+        t0 = time.perf_counter()
+        sparse.series_apply(A, d["mu"], coeffs, X)
+        t_used += time.perf_counter() - t0
+        done_ev += K * A.nnz * b
+        graphs += 1
+        if t_used > budget_s:
+            break
+    return {
+        "value": done_ev / t_used / 1e9,
+        "unit": "GEdge·vec/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"degree-30 series on 8 columns for the first {graphs} graphs of the batch, "
+                  f"scipy.sparse single-threaded FP64, {t_used:.1f} s",
+    }
+
+
+MLP_SHAPES = [(64, 8), (64,), (64, 64), (64,), (1, 64), (1,)]
+
+
+def run_cv_rmat22(args):
+    """Learned control variate.  Operator: mu = 0.5 (theta = 0.5), exponential with
+    beta = 1/lambda_max, truncated series (FP32 vectors).  Training: 200 graphs
+    (Barabasi-Albert, SBM, power-law configuration model; 2k..20k nodes), up to 1024
+    nodes each with exact diag phi from unit blocks through the operator; the network
+    learns diag phi - 1 from the 8 local features, trained by the library's kernels
+    (full batch Adam).  Evaluation: R-MAT scale 22 (edge factor 16, a = 0.57,
+    b = c = 0.19), exact diagonal on 4096 sampled nodes, ten probe seeds for each
+    M in {16, 64, 256}: plain Gaussian Hutchinson, the same probes with the control
+    variate, Gaussian BKS and Rademacher Hutchinson.  err = ||d_hat - d|| / ||d - 1||
+    over the sampled nodes."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+
+    import paper_2601_11338_amd as wl
+    import synth
+
+    mu = 0.5
+    ctx = wl.Context(0)
+    specs = synth.training_specs(200, seed=7)
+    log("generating 200 training graphs")
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        csrs = list(ex.map(_gen_spec, specs, chunksize=4))
+    rng = np.random.default_rng(5)
+    feats, targs = [], []
+    t_data = time.perf_counter()
+    for rp, ci in csrs:
+        g = wl.Graph(ctx, rp, ci)
+        beta = 1.0 / g.lambda_max()
+        op = wl.Operator(g, mu, "exp", beta, dtype=torch.float32)
+        nodes = np.sort(rng.choice(g.n, size=min(1024, g.n), replace=False)).astype(np.int32)
+        f = g.features(beta)
+        feats.append(f[torch.as_tensor(nodes, device="cuda").long()])
+        targs.append(op.diag_exact(nodes, width=64) - 1.0)
+        del op, g
+    F = torch.cat(feats).contiguous()
+    T = torch.cat(targs).contiguous()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t_data
+    log(f"training set: {F.shape[0]} nodes ({t_data:.1f} s for exact diagonals and features)")
+    net = wl.MLP(ctx, synth.glorot_params(MLP_SHAPES, 1))
+    t_train = time.perf_counter()
+    steps = 2000
+    for it in range(steps):
+        lr = 3e-3 if it < 1500 else 1e-3
+        loss = net.train_step(F, T, lr)
+        if it % 500 == 0 or it == steps - 1:
+            log(f"train step {it}: mse {loss:.3e} (target variance {float(T.var()):.3e})")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+    log("generating R-MAT scale 22 on the device")
+    rp, ci = synth.rmat_device(22, 16, 0.57, 0.19, 0.19, seed=2022)
+    g = wl.Graph(ctx, rp, ci, validate=True)
+    n, nnz = g.n, g.nnz
+    g.autotune(torch.float32, 64)
+    beta = 1.0 / g.lambda_max()
+    op = wl.Operator(g, mu, "exp", beta, dtype=torch.float32)
+    ghat = (net.forward(g.features(beta)) + 1.0).contiguous()
+    S = np.sort(np.random.default_rng(9).choice(n, size=4096, replace=False)).astype(np.int32)
+    St = torch.as_tensor(S, device="cuda").long()
+    d_true = op.diag_exact(S, width=64).double()
+    den = float(torch.linalg.norm(d_true - 1.0))
+    log(f"R-MAT n={n} nnz={nnz}; ||d - 1|| on the sample {den:.4e}")
+    ests = {
+        "plain_gauss": dict(law="gauss", estimator="hutchinson", cv=None),
+        "cv_gauss": dict(law="gauss", estimator="hutchinson", cv=ghat),
+        "bks_gauss": dict(law="gauss", estimator="bks", cv=None),
+        "rademacher": dict(law="rademacher", estimator="hutchinson", cv=None),
+    }
+    Ms = [16, 64, 256]
+    seeds = range(10)
+    errs = {k: {} for k in ests}
+    t_eval = time.perf_counter()
+    for M in Ms:
+        for name, kw in ests.items():
+            e = []
+            for sd in seeds:
+                d, _, _ = op.diag_est(M, 1000 + sd, target="phi", **kw)
+                e.append(float(torch.linalg.norm(d[St].double() - d_true)) / den)
+            errs[name][M] = float(np.mean(e))
+        log("M=%d: " % M + ", ".join(f"{k} {errs[k][M]:.4e}" for k in ests))
+    torch.cuda.synchronize()
+    t_eval = time.perf_counter() - t_eval
+    gain = {M: (errs["plain_gauss"][M] / errs["cv_gauss"][M]) ** 2 for M in Ms}
+    value = float(np.mean(list(gain.values())))
+    passed = errs["cv_gauss"][16] <= errs["plain_gauss"][64] and errs["cv_gauss"][64] <= errs["plain_gauss"][256]
+    return {
+        "metric": "diag-estimate error vs probes (learned vs plain)",
+        "value": value,
+        "unit": "x fewer probes at equal error (mean over M of (err_plain/err_cv)^2)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": t_eval * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"learned control variate: mu=0.5 exp beta=1/lambda_max; trained on 200 graphs "
+                        f"(BA/SBM/CM, 2k..20k nodes, {F.shape[0]} exact diagonals); evaluated on R-MAT "
+                        f"scale 22 ef 16 (n={n}, nnz={nnz}) at 4096 sampled nodes, 10 seeds",
+            "n": n,
+            "nnz": nnz,
+            "probes": Ms,
+        },
+        "errors": errs,
+        "probe_gain": gain,
+        "pass_cv16_le_plain64_and_cv64_le_plain256": bool(passed),
+        "train_seconds": t_train,
+        "target_seconds": t_data,
+        "eval_seconds": t_eval,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -111,6 +398,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batch512":
+        print(json.dumps(run_batch512(args)), flush=True)
+        return
+    if args.workload == "cv-rmat22":
+        print(json.dumps(run_cv_rmat22(args)), flush=True)
         return
     import numpy as np
     import torch

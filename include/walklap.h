@@ -231,7 +231,13 @@ wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, i
                       void* d_diag, double* trace, double* trace_err);
 
 /* Convenience: diag phi (target 0) or diag exp(-t L) (target 1) estimated from M
- * probes drawn by wl_probes(seed, law).  d_diag n values.                         */
+ * probes drawn by wl_probes(seed, law), then wl_estimate.  d_diag: n values of the
+ * operator's precision (device).  M in [1, 4096]; for M <= 64 the probes are one
+ * n x M block of Philox stream 0.  For M > 64 (Hutchinson, BKS and the control
+ * variate only; the Nystrom estimator takes M <= 64) the probes are ceil(M / 64)
+ * blocks of 64 columns (the last one narrower), block c drawn from Philox stream c,
+ * each pushed through the operator in turn with the per-row sums accumulated on the
+ * device: the result is the M-probe estimator over those columns.                  */
 wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t seed,
                       int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
                       void* d_diag, double* trace, double* trace_err);
@@ -246,8 +252,12 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
  * lambda_max; resolvent: geometric bound alpha lambda_max, or the asymptotic ratio
  * alpha rho(Z_mu) plus 20 terms when alpha lambda_max >= 1).  FP32 vectors.
  *
- * wl_batch_create: descs[g] describes graph g (mu, func, param; krylov_dim > 0 fixes
+ * wl_batch_create: 1 <= ngraphs <= 65535; descs[g] describes graph g (mu, func, param; krylov_dim > 0 fixes
  * its series degree; rho_hint as for operators).  Computes every walk degree.
+ * wl_batch_info: any output may be NULL; row_offsets (int64) and series_degrees
+ * (int32, the truncation degree K_g of graph g's series) are host arrays of ngraphs.
+ * wl_batch_autotune: times SpMM launch shapes on the concatenated graph for b columns
+ * (as wl_autotune) and keeps the fastest for the batch's sparse products.
  * wl_batch_apply_L: Y = L_g X_g for every graph (d_X, d_Y: total_rows x b).
  * wl_batch_expv: Y_g = exp(-t_g L_g) U0_g for every graph (t: host array of ngraphs
  * times) by outer_dim block Lanczos steps per graph, the projected exponential
@@ -260,7 +270,8 @@ typedef struct wl_batch wl_batch;
 wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs, const wl_op_desc* descs,
                           double tol, wl_batch** out);
 wl_status wl_batch_info(const wl_batch* batch, int64_t* total_rows, int32_t* max_series_degree,
-                        int64_t* row_offsets);
+                        int64_t* row_offsets, int32_t* series_degrees);
+wl_status wl_batch_autotune(wl_batch* batch, int32_t b);
 wl_status wl_batch_apply_L(wl_batch* batch, const void* d_X, void* d_Y, int32_t b);
 wl_status wl_batch_expv(wl_batch* batch, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
                         double* p_hat, double* p_err);

@@ -56,6 +56,23 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
 
 
+def _need(t, name, dtype, shape):
+    """Check that a tensor handed to the library is a contiguous device tensor of the
+    given dtype and shape (None in shape: any extent); the library cannot check the
+    sizes of the buffers behind its pointers."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    ok = t.dim() == len(shape) and all(s is None or t.shape[i] == s for i, s in enumerate(shape))
+    if not ok:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
 class Context:
     """A device and the stream the library enqueues on."""
 
@@ -122,9 +139,12 @@ class Graph:
     def spmm(self, X, Y=None):
         torch = _torch()
         X = X.contiguous()
-        b = X.shape[1] if X.dim() == 2 else 1
+        _prec_of(X.dtype)
+        X2 = _need(X.view(-1, 1) if X.dim() == 1 else X, "X", X.dtype, (self.n, None))
+        b = X2.shape[1]
         if Y is None:
             Y = torch.empty_like(X)
+        _need(Y.view(self.n, -1) if Y.is_contiguous() and Y.numel() == X.numel() else Y, "Y", X.dtype, (self.n, b))
         check(load().wl_spmm(self.handle, _prec_of(X.dtype), _ptr(X), _ptr(Y), b))
         return Y
 
@@ -146,6 +166,7 @@ class Graph:
         torch = _torch()
         if out is None:
             out = torch.empty((self.n, 8), dtype=torch.float32, device=self.ctx.torch_device)
+        _need(out, "out", torch.float32, (self.n, 8))
         check(load().wl_features(self.handle, float(scale), _ptr(out)))
         return out
 
@@ -183,6 +204,7 @@ class Operator:
 
     def fdeg(self, out=None):
         out = self._empty(self.graph.n) if out is None else out
+        _need(out, "out", self.dtype, (self.graph.n,))
         check(load().wl_fdeg(self.handle, _ptr(out)))
         return out
 
@@ -190,17 +212,22 @@ class Operator:
         X = X.to(self.dtype).contiguous()
         if X.dim() == 1:
             X = X.view(-1, 1)
-        return X
+        return _need(X, "X", self.dtype, (self.graph.n, None))
+
+    def _out(self, out, X):
+        out = _torch().empty_like(X) if out is None else out
+        return _need(out.view(X.shape) if out.is_contiguous() and out.numel() == X.numel() else out, "out",
+                     self.dtype, tuple(X.shape))
 
     def apply_phi(self, X, out=None):
         X = self._block(X)
-        out = _torch().empty_like(X) if out is None else out
+        out = self._out(out, X)
         check(load().wl_apply_phi(self.handle, _ptr(X), _ptr(out), X.shape[1]))
         return out
 
     def apply_L(self, X, out=None):
         X = self._block(X)
-        out = _torch().empty_like(X) if out is None else out
+        out = self._out(out, X)
         check(load().wl_apply_L(self.handle, _ptr(X), _ptr(out), X.shape[1]))
         return out
 
@@ -209,6 +236,9 @@ class Operator:
         ts = [float(t) for t in ts]
         torch = _torch()
         outs = [torch.empty_like(U0) for _ in ts] if outs is None else outs
+        if len(outs) != len(ts):
+            raise ValueError("one output block per time is needed")
+        outs = [self._out(o, U0) for o in outs]
         tarr = (C.c_double * len(ts))(*ts)
         parr = (C.c_void_p * len(ts))(*[o.data_ptr() for o in outs])
         err = (C.c_double * len(ts))()
@@ -217,6 +247,8 @@ class Operator:
 
     def diag_est(self, M, seed, target="phi", t=0.0, law="gauss", estimator="hutchinson", cv=None, outer_dim=30):
         out = self._empty(self.graph.n)
+        if cv is not None:
+            _need(cv, "cv", self.dtype, (self.graph.n,))
         tr, te = C.c_double(), C.c_double()
         check(load().wl_diag_est(self.handle, 0 if target == "phi" else 1, float(t), int(M), int(seed), LAWS[law],
                                  ESTIMATORS[estimator], _ptr(cv), int(outer_dim), _ptr(out), C.byref(tr),
@@ -250,6 +282,8 @@ def block_gram(ctx, X, Y, nblk=1):
     Y = Y.contiguous()
     n, by = Y.shape
     bx = X.shape[1]
+    _need(Y, "Y", X.dtype, (n, by))
+    _need(X, "X", X.dtype, (nblk * n, bx))
     G = np.empty((nblk * bx, by), dtype=np.float64)
     check(load().wl_block_gram(ctx.handle, _prec_of(X.dtype), n, nblk, bx, _ptr(X), by, _ptr(Y),
                                G.ctypes.data_as(C.POINTER(C.c_double))))
@@ -265,6 +299,12 @@ def block_update(ctx, X, Cm, Yin=None, alpha=0.0, beta=1.0, out=None, nblk=1, wa
     n = X.shape[0] // nblk
     Cm = np.ascontiguousarray(Cm, dtype=np.float64)
     out = torch.empty((n, b), dtype=X.dtype, device=X.device) if out is None else out
+    _need(X, "X", X.dtype, (nblk * n, b))
+    if Cm.size != nblk * b * b:
+        raise ValueError(f"C must hold {nblk} blocks of {b} x {b}")
+    if Yin is not None:
+        _need(Yin, "Yin", X.dtype, (n, b))
+    _need(out, "out", X.dtype, (n, b))
     G = np.empty((b, b), dtype=np.float64) if want_gram else None
     check(load().wl_block_update(ctx.handle, _prec_of(X.dtype), n, nblk, b, _ptr(X),
                                  Cm.ctypes.data_as(C.POINTER(C.c_double)), _ptr(Yin), float(alpha), float(beta),
@@ -285,6 +325,9 @@ def estimate(ctx, Omega, Y, estimator="hutchinson", cv=None, rcond=1e-10, want_d
     Omega = Omega.contiguous()
     Y = Y.contiguous()
     n, M = Omega.shape
+    _need(Y, "Y", Omega.dtype, (n, M))
+    if cv is not None:
+        _need(cv, "cv", Omega.dtype, (n,))
     diag = torch.empty(n, dtype=Omega.dtype, device=Omega.device) if want_diag else None
     tr, te = C.c_double(), C.c_double()
     check(load().wl_estimate(ctx.handle, _prec_of(Omega.dtype), ESTIMATORS[estimator], n, M, _ptr(Omega), _ptr(Y),
@@ -325,20 +368,27 @@ class MLP:
 
     def forward(self, feat, out=None):
         torch = _torch()
-        feat = feat.contiguous()
+        feat = _need(feat.contiguous(), "feat", torch.float32, (None, 8))
         out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device) if out is None else out
+        _need(out, "out", torch.float32, (feat.shape[0],))
         check(load().wl_mlp_forward(self.handle, _ptr(feat), feat.shape[0], _ptr(out)))
         return out
 
     def loss_grad(self, feat, target):
         import numpy as np
+        torch = _torch()
         g = np.empty(self.nparams, dtype=np.float64)
         loss = C.c_double()
-        check(load().wl_mlp_loss_grad(self.handle, _ptr(feat.contiguous()), _ptr(target.contiguous()),
+        feat = _need(feat.contiguous(), "feat", torch.float32, (None, 8))
+        target = _need(target.contiguous(), "target", torch.float32, (feat.shape[0],))
+        check(load().wl_mlp_loss_grad(self.handle, _ptr(feat), _ptr(target),
                                       feat.shape[0], C.byref(loss), g.ctypes.data_as(C.c_void_p)))
         return loss.value, g
 
     def train_step(self, feat, target, lr):
+        torch = _torch()
+        _need(feat, "feat", torch.float32, (None, 8))
+        _need(target, "target", torch.float32, (feat.shape[0],))
         loss = C.c_double()
         check(load().wl_mlp_train_step(self.handle, _ptr(feat), _ptr(target), feat.shape[0], float(lr),
                                        C.byref(loss)))
@@ -374,8 +424,11 @@ class Batch:
         import numpy as np
         total, kmax = C.c_int64(), C.c_int32()
         offs = np.zeros(len(graphs), dtype=np.int64)
-        check(load().wl_batch_info(self.handle, C.byref(total), C.byref(kmax), offs.ctypes.data_as(C.c_void_p)))
+        degs = np.zeros(len(graphs), dtype=np.int32)
+        check(load().wl_batch_info(self.handle, C.byref(total), C.byref(kmax), offs.ctypes.data_as(C.c_void_p),
+                                   degs.ctypes.data_as(C.c_void_p)))
         self.total_rows, self.max_series_degree, self.offsets = total.value, kmax.value, offs
+        self.series_degrees = degs
         self.sizes = [g.n for g in graphs]
 
     def pack(self, blocks):
@@ -390,16 +443,27 @@ class Batch:
     def unpack(self, packed):
         return [packed[int(o):int(o) + n] for o, n in zip(self.offsets, self.sizes)]
 
+    def autotune(self, b):
+        check(load().wl_batch_autotune(self.handle, int(b)))
+
+    def _blocks(self, X, out):
+        torch = _torch()
+        _need(X, "X", torch.float32, (self.total_rows, None))
+        out = torch.empty_like(X) if out is None else out
+        return _need(out, "out", torch.float32, tuple(X.shape))
+
     def apply_L(self, X, out=None):
-        out = _torch().empty_like(X) if out is None else out
+        out = self._blocks(X, out)
         check(load().wl_batch_apply_L(self.handle, _ptr(X), _ptr(out), X.shape[1]))
         return out
 
     def expv(self, U0, ts, outer_dim=30, out=None, want_trace=True):
         import numpy as np
         torch = _torch()
-        out = torch.empty_like(U0) if out is None else out
+        out = self._blocks(U0, out)
         t = np.ascontiguousarray(ts, dtype=np.float64)
+        if t.shape != (len(self.graphs),):
+            raise ValueError("one time per graph is needed")
         ph = np.zeros(len(self.graphs))
         pe = np.zeros(len(self.graphs))
         pd_ = C.POINTER(C.c_double)

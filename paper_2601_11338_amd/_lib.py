@@ -76,7 +76,8 @@ SIGNATURES = {
     "wl_mlp_loss_grad": (C.c_int, [vp, vp, vp, i64, pd, vp]),
     "wl_mlp_train_step": (C.c_int, [vp, vp, vp, i64, f64, pd]),
     "wl_batch_create": (C.c_int, [vp, i32, vp, vp, f64, C.POINTER(vp)]),
-    "wl_batch_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32), vp]),
+    "wl_batch_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32), vp, vp]),
+    "wl_batch_autotune": (C.c_int, [vp, i32]),
     "wl_batch_apply_L": (C.c_int, [vp, vp, vp, i32]),
     "wl_batch_expv": (C.c_int, [vp, vp, i32, pd, i32, vp, pd, pd]),
     "wl_batch_destroy": (C.c_int, [vp]),

@@ -80,6 +80,15 @@ int lanes_for(int prec, int b) {
   return b == 1 ? 1 : std::min(16, next_pow2(b));
 }
 
+template <typename T>
+T* tptr(const DevBuf& b, size_t off_elems = 0) {
+  return b.as<T>() + off_elems;
+}
+
+}  // namespace
+
+// The autotuned shape of (prec, b) if there is one, else a heuristic from the mean
+// degree: enough neighbour slots per row to cover about half the mean degree.
 SpmmShape shape_for(wl_graph* g, int prec, int b) {
   auto it = g->tuned.find(prec * 1000 + std::min(b, 999));
   if (it != g->tuned.end()) return it->second;
@@ -92,13 +101,6 @@ SpmmShape shape_for(wl_graph* g, int prec, int b) {
   s.long_thr = std::max(g->long_min_thr, 32 * (G / lpn));
   return s;
 }
-
-template <typename T>
-T* tptr(const DevBuf& b, size_t off_elems = 0) {
-  return b.as<T>() + off_elems;
-}
-
-}  // namespace
 
 extern "C" {
 

@@ -330,14 +330,7 @@ wl_status batch_phi(wl_batch* bt, const float* X, float* Y, int b, bool laplacia
   WL_TRY(bt->bufB.ensure((size_t)N * b * 4));
   float* A = bt->bufA.as<float>();
   float* B = bt->bufB.as<float>();
-  const SpmmShape sh = [&] {
-    auto it = g->tuned.find(WL_FP32 * 1000 + b);
-    if (it != g->tuned.end()) return it->second;
-    SpmmShape s;
-    s.G = 16;
-    s.long_thr = 512;
-    return s;
-  }();
+  const SpmmShape sh = shape_for(g, WL_FP32, b);
   const double* tab = laplacian ? bt->gtab.as<double>() : bt->gtab_none.as<double>();
   const int64_t tstride = (int64_t)bt->ng * 5;
   {
@@ -385,7 +378,7 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
                           double tol, wl_batch** out) {
   WL_CHECK(ctx && graphs && descs && out, WL_EINVAL, "wl_batch_create: null argument");
   *out = nullptr;
-  WL_CHECK(ngraphs >= 1, WL_EINVAL, "wl_batch_create: need at least one graph");
+  WL_CHECK(ngraphs >= 1 && ngraphs <= 65535, WL_EINVAL, "wl_batch_create: ngraphs must lie in [1, 65535]");
   WL_CHECK(std::isfinite(tol) && tol >= 0, WL_EINVAL, "wl_batch_create: bad tol");
   if (tol == 0) tol = 1e-10;
   (void)hipSetDevice(ctx->device);
@@ -552,13 +545,21 @@ wl_status wl_batch_destroy(wl_batch* bt) {
   return WL_OK;
 }
 
-wl_status wl_batch_info(const wl_batch* bt, int64_t* total_rows, int32_t* max_degree_series, int64_t* row_offsets) {
+wl_status wl_batch_info(const wl_batch* bt, int64_t* total_rows, int32_t* max_degree_series, int64_t* row_offsets,
+                        int32_t* series_degrees) {
   WL_CHECK(bt, WL_EINVAL, "wl_batch_info: batch is null");
   if (total_rows) *total_rows = bt->N;
   if (max_degree_series) *max_degree_series = bt->Kmax;
   if (row_offsets)
     for (int g = 0; g < bt->ng; ++g) row_offsets[g] = bt->roff[g];
+  if (series_degrees)
+    for (int g = 0; g < bt->ng; ++g) series_degrees[g] = bt->K[g];
   return WL_OK;
+}
+
+wl_status wl_batch_autotune(wl_batch* bt, int32_t b) {
+  WL_CHECK(bt, WL_EINVAL, "wl_batch_autotune: batch is null");
+  return wl_autotune(bt->G, WL_FP32, b);
 }
 
 wl_status wl_batch_apply_L(wl_batch* bt, const void* d_X, void* d_Y, int32_t b) {

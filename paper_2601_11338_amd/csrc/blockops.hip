@@ -698,9 +698,9 @@ __global__ void k_probes(int law, uint32_t k0, uint32_t k1, uint32_t stream, int
 // ------------------------------------------------------------ estimator rows
 template <typename T>
 __global__ void k_rowdot(int64_t n, int M, const T* __restrict__ Om, const T* __restrict__ Y,
-                         double* __restrict__ dot, double* __restrict__ sq) {
+                         double* __restrict__ dot, double* __restrict__ sq, int accumulate) {
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0, q = 0.0;
+    double s = accumulate ? dot[r] : 0.0, q = accumulate ? sq[r] : 0.0;
     const T* o = Om + r * M;
     const T* y = Y + r * M;
     for (int j = 0; j < M; ++j) {
@@ -708,7 +708,27 @@ __global__ void k_rowdot(int64_t n, int M, const T* __restrict__ Om, const T* __
       q += (double)o[j] * (double)o[j];
     }
     dot[r] = s;
-    if (sq) sq[r] = q;
+    sq[r] = q;
+  }
+}
+
+// Diagonal estimate from the accumulated row sums s_r = sum_j Omega_rj Y_rj and
+// q_r = sum_j Omega_rj^2 over M probes (modes as in k_cv_finish).
+template <typename T>
+__global__ void k_sums_finish(int64_t n, int M, const double* __restrict__ dot, const double* __restrict__ sq,
+                              const T* __restrict__ g, int mode, T* __restrict__ diag) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const double s = dot[r], q = sq[r];
+    double d;
+    if (mode == 1) {
+      d = s / q;
+    } else if (mode == 2) {
+      const double gr = (double)g[r];
+      d = gr + (s - gr * q) / M;
+    } else {
+      d = s / M;
+    }
+    diag[r] = (T)d;
   }
 }
 
@@ -997,8 +1017,19 @@ wl_status launch_probes(wl_ctx* ctx, int law, uint64_t seed, uint32_t stream, in
 }
 
 template <typename T>
-wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq) {
-  hipLaunchKernelGGL((k_rowdot<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, M, Om, Y, dot, sq);
+wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq,
+                        int accumulate) {
+  hipLaunchKernelGGL((k_rowdot<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, M, Om, Y, dot, sq,
+                     accumulate);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+template <typename T>
+wl_status launch_sums_finish(wl_ctx* ctx, int64_t n, int M, const double* dot, const double* sq, const T* g,
+                             int mode, T* diag) {
+  hipLaunchKernelGGL((k_sums_finish<T>), dim3(grid_for(n, 256, 8192)), dim3(256), 0, ctx->stream, n, M, dot, sq, g,
+                     mode, diag);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -1029,7 +1060,8 @@ wl_status launch_nys_diag(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y
   template wl_status launch_axpby_rows<T>(wl_ctx*, int64_t, int, const T*, const T*, double, const T*, T*);       \
   template wl_status launch_degrees<T>(wl_graph*, T*);                                                              \
   template wl_status launch_probes<T>(wl_ctx*, int, uint64_t, uint32_t, int64_t, int, T*);                         \
-  template wl_status launch_rowdot<T>(wl_ctx*, int64_t, int, const T*, const T*, double*, double*);                \
+  template wl_status launch_rowdot<T>(wl_ctx*, int64_t, int, const T*, const T*, double*, double*, int);           \
+  template wl_status launch_sums_finish<T>(wl_ctx*, int64_t, int, const double*, const double*, const T*, int, T*); \
   template wl_status launch_cv_finish<T>(wl_ctx*, int64_t, int, const T*, const T*, const T*, int, T*);            \
   template wl_status launch_nys_diag<T>(wl_ctx*, int64_t, int, const T*, const T*, const double*, const double*,  \
                                         T*);

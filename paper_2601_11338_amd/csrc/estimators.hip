@@ -16,6 +16,7 @@
 //      d_r = ( y_r Q1 y_r^T + sum_j Omega_rj Y_rj - y_r Q2 omega_r^T ) / M,
 //      Q1 = sum_j P_j,  column j of Q2 = P_j h_j,
 //    so the device work is two Gram products and one row pass.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -23,7 +24,9 @@
 
 namespace {
 
-// Gram of two n x M row-major blocks for any M, by 64-column tiles.
+constexpr int DIAG_CHUNK = 64;  // probes per block in wl_diag_est
+
+// Gram of two n x M row-major blocks (M <= 64: one launch of the Gram kernel).
 template <typename T>
 wl_status gram_full(wl_ctx* ctx, int64_t n, int M, const T* X, const T* Y, std::vector<double>& out) {
   out.assign((size_t)M * M, 0.0);
@@ -159,25 +162,76 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
                       double* trace_err) {
   WL_CHECK(op, WL_EINVAL, "wl_diag_est: op is null");
   WL_CHECK(target == 0 || target == 1, WL_EINVAL, "wl_diag_est: target must be 0 (phi) or 1 (exp(-tL))");
-  WL_CHECK(M >= 1 && M <= 64, WL_EINVAL, "wl_diag_est: M must lie in [1, 64]");
+  WL_CHECK(M >= 1 && M <= 4096, WL_EINVAL, "wl_diag_est: M must lie in [1, 4096]");
+  WL_CHECK(M <= DIAG_CHUNK || estimator != WL_EST_XNYS, WL_EINVAL,
+           "wl_diag_est: the Nystrom estimator takes at most %d probes", DIAG_CHUNK);
+  WL_CHECK(!(d_cv && estimator != WL_EST_HUTCHINSON), WL_EINVAL,
+           "wl_diag_est: the control variate applies to the Hutchinson estimator");
+  WL_CHECK(law == WL_PROBE_GAUSS || law == WL_PROBE_RADEMACHER, WL_EINVAL, "wl_diag_est: bad probe law");
   WL_CHECK(std::isfinite(t) && t >= 0, WL_EINVAL, "wl_diag_est: bad t");
   wl_graph* g = op->g;
   const int64_t n = g->n;
   WL_CHECK(n >= 1, WL_EINVAL, "wl_diag_est: empty graph");
+  WL_CHECK(d_diag, WL_EINVAL, "wl_diag_est: d_diag is null");
   (void)hipSetDevice(g->ctx->device);
+  wl_ctx* ctx = g->ctx;
   const size_t es = op->d.prec == WL_FP32 ? 4 : 8;
+  const int mc = M < DIAG_CHUNK ? M : DIAG_CHUNK;
   DevBuf Om, Y;
-  WL_TRY(Om.ensure((size_t)n * M * es));
-  WL_TRY(Y.ensure((size_t)n * M * es));
-  WL_TRY(wl_probes(g->ctx, op->d.prec, law, seed, 0, n, M, Om.p));
-  if (target == 0) {
-    WL_TRY(wl_apply_phi(op, Om.p, Y.p, M));
-  } else {
+  WL_TRY(Om.ensure((size_t)n * mc * es));
+  WL_TRY(Y.ensure((size_t)n * mc * es));
+  auto product = [&](int m) -> wl_status {
+    if (target == 0) return wl_apply_phi(op, Om.p, Y.p, m);
     void* outs[1] = {Y.p};
-    WL_TRY(wl_expv(op, Om.p, M, &t, 1, outs, outer_dim, nullptr));
+    return wl_expv(op, Om.p, m, &t, 1, outs, outer_dim, nullptr);
+  };
+  if (M <= DIAG_CHUNK) {
+    WL_TRY(wl_probes(ctx, op->d.prec, law, seed, 0, n, M, Om.p));
+    WL_TRY(product(M));
+    WL_TRY(wl_estimate(ctx, op->d.prec, estimator, n, M, Om.p, Y.p, d_cv, 1e-10, d_diag, trace, trace_err));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    return WL_OK;
   }
-  WL_TRY(wl_estimate(g->ctx, op->d.prec, estimator, n, M, Om.p, Y.p, d_cv, 1e-10, d_diag, trace, trace_err));
-  WL_HIP(hipStreamSynchronize(g->ctx->stream));
+  // more probes than one block: blocks of DIAG_CHUNK columns (block c from Philox
+  // stream c), row sums accumulated on the device, per-probe traces from the Gram
+  // diagonal of each block
+  DevBuf sums, H;
+  WL_TRY(sums.ensure((size_t)2 * n * 8));
+  WL_TRY(H.ensure((size_t)DIAG_CHUNK * DIAG_CHUNK * 8));
+  std::vector<double> tj;
+  std::vector<double> hH((size_t)DIAG_CHUNK * DIAG_CHUNK);
+  const int nchunks = (M + DIAG_CHUNK - 1) / DIAG_CHUNK;
+  for (int c = 0; c < nchunks; ++c) {
+    const int m = std::min(DIAG_CHUNK, M - c * DIAG_CHUNK);
+    WL_TRY(wl_probes(ctx, op->d.prec, law, seed, (uint32_t)c, n, m, Om.p));
+    WL_TRY(product(m));
+    if (op->d.prec == WL_FP32) {
+      WL_TRY(launch_rowdot<float>(ctx, n, m, Om.as<float>(), Y.as<float>(), sums.as<double>(),
+                                  sums.as<double>() + n, c > 0));
+      WL_TRY(launch_gram<float>(ctx, n, Om.as<float>(), m, 0, 1, Y.as<float>(), m, H.as<double>()));
+    } else {
+      WL_TRY(launch_rowdot<double>(ctx, n, m, Om.as<double>(), Y.as<double>(), sums.as<double>(),
+                                   sums.as<double>() + n, c > 0));
+      WL_TRY(launch_gram<double>(ctx, n, Om.as<double>(), m, 0, 1, Y.as<double>(), m, H.as<double>()));
+    }
+    WL_HIP(hipMemcpyAsync(hH.data(), H.p, (size_t)m * m * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    for (int j = 0; j < m; ++j) tj.push_back(hH[(size_t)j * m + j]);
+  }
+  const int mode = d_cv ? 2 : (estimator == WL_EST_BKS ? 1 : 0);
+  if (op->d.prec == WL_FP32)
+    WL_TRY(launch_sums_finish<float>(ctx, n, M, sums.as<double>(), sums.as<double>() + n, (const float*)d_cv, mode,
+                                     (float*)d_diag));
+  else
+    WL_TRY(launch_sums_finish<double>(ctx, n, M, sums.as<double>(), sums.as<double>() + n, (const double*)d_cv,
+                                      mode, (double*)d_diag));
+  double mean = 0.0, var = 0.0;
+  for (double v : tj) mean += v;
+  mean /= M;
+  for (double v : tj) var += (v - mean) * (v - mean);
+  if (trace) *trace = mean;
+  if (trace_err) *trace_err = std::sqrt(var / (M - 1)) / std::sqrt((double)M);
+  WL_HIP(hipStreamSynchronize(ctx->stream));
   return WL_OK;
 }
 

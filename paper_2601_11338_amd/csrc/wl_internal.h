@@ -169,6 +169,9 @@ struct EpiArgs {
 template <typename T>
 wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh);
 
+// SpMM launch shape for (prec, b) on g: the autotuned one if present, else a heuristic.
+SpmmShape shape_for(wl_graph* g, int prec, int b);
+
 // Gram partials and finalisation.  X: nblk blocks of n x bx (block k at X + k*sX),
 // Y: n x by.  out (double, nblk*bx x by row-major) = X^T Y, reduced in a fixed
 // order (deterministic).  Partials live in ctx->partials.
@@ -217,9 +220,16 @@ wl_status launch_validate(wl_graph* g, int32_t* d_flags);
 template <typename T>
 wl_status launch_probes(wl_ctx* ctx, int law, uint64_t seed, uint32_t stream, int64_t n, int M, T* out);
 
-// Row-wise estimator reductions: out[r] = sum_j Om[r,j] * Y[r,j] and (if sq) sq[r] = sum_j Om[r,j]^2.
+// Row-wise estimator reductions: dot[r] (+)= sum_j Om[r,j] Y[r,j], sq[r] (+)= sum_j Om[r,j]^2
+// (accumulate != 0 adds to the values already there); launch_sums_finish turns the
+// sums over M probes into the Hutchinson (mode 0), BKS (1) or control-variate (2)
+// diagonal.
 template <typename T>
-wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq);
+wl_status launch_rowdot(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y, double* dot, double* sq,
+                        int accumulate);
+template <typename T>
+wl_status launch_sums_finish(wl_ctx* ctx, int64_t n, int M, const double* dot, const double* sq, const T* g,
+                             int mode, T* diag);
 // Per-probe traces: tr[j] = sum_r Om[r,j] Y[r,j] (double M), through the Gram machinery.
 // Nystrom diagonal finish: diag[r] = (y_r^T Q1 y_r + sum_j Om_rj Y_rj - y_r^T Q2 om_r) / M
 template <typename T>

@@ -21,5 +21,9 @@ from .graphs import (  # noqa: F401
     star_graph,
     toy_g58,
     csr_from_dense,
+    batch_specs,
+    training_specs,
+    graph_from_spec,
+    rmat_device,
 )
 from .blocks import gaussian_block, rademacher_block, spike_block, sparse_initial_block, glorot_params  # noqa: F401

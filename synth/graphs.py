@@ -223,3 +223,99 @@ def rmat(scale, edge_factor, a, b, c, seed, chunk=1 << 24):
     lo = key // n
     hi = key - lo * n
     return csr_from_edges(n, perm[lo], perm[hi])
+
+
+def batch_specs(count, seed, n_min=1000, n_max=200000):
+    """Recipes of a many-graph workload: sizes log-uniform on [n_min, n_max];
+    even entries a stochastic block model (4..32 equal blocks, p_in/p_out = 20,
+    mean degree 10), odd entries an erased power-law configuration model
+    (exponent 2.5, degrees 2..sqrt(n)).  Each recipe carries its own seed."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_min), np.log(n_max), count)).astype(np.int64)
+    specs = []
+    for i, n in enumerate(sizes):
+        s = int(seed) * 100003 + i
+        if i % 2 == 0:
+            specs.append(("sbm", int(n), int(rng.integers(4, 33)), s))
+        else:
+            specs.append(("cm", int(n), max(3, int(np.sqrt(n))), s))
+    return specs
+
+
+def training_specs(count, seed, n_min=2000, n_max=20000):
+    """Recipes of small training graphs shaped like the large workloads: sizes
+    log-uniform on [n_min, n_max], cycling Barabasi-Albert (m in 3..6), stochastic
+    block model and power-law configuration model recipes."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_min), np.log(n_max), count)).astype(np.int64)
+    specs = []
+    for i, n in enumerate(sizes):
+        s = int(seed) * 100003 + i
+        kind = ("ba", "sbm", "cm")[i % 3]
+        if kind == "ba":
+            specs.append(("ba", int(n), int(rng.integers(3, 7)), s))
+        elif kind == "sbm":
+            specs.append(("sbm", int(n), int(rng.integers(4, 33)), s))
+        else:
+            specs.append(("cm", int(n), max(3, int(np.sqrt(n))), s))
+    return specs
+
+
+def graph_from_spec(spec):
+    """CSR of one recipe from batch_specs / training_specs."""
+    kind, n, p, s = spec
+    if kind == "sbm":
+        return stochastic_block_model(n, p, 10, 20, s)
+    if kind == "cm":
+        return configuration_model_powerlaw(n, 2.5, 2, p, s)
+    if kind == "ba":
+        return barabasi_albert(n, p, s)
+    raise ValueError(f"unknown graph recipe {kind}")
+
+
+def rmat_device(scale, edge_factor, a, b, c, seed, device="cuda"):
+    """R-MAT drawn on a torch device (for graphs too large for host generation in a
+    few seconds): same recipe as ``rmat`` (one quadrant per level with probabilities
+    a, b, c, 1-a-b-c; symmetrised, deduped, loops dropped, seeded relabelling) from
+    torch's generator, so the edges differ from ``rmat`` for the same seed.  Returns
+    device int32 (rowptr, colidx)."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    n = 1 << scale
+    m = edge_factor * n
+    chunk = 1 << 26
+    ab, abc = a + b, a + b + c
+    keys = []
+    for start in range(0, m, chunk):
+        cnt = min(chunk, m - start)
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for lev in range(scale):
+            r = torch.rand(cnt, generator=gen, device=device)
+            bit = 1 << (scale - 1 - lev)
+            u += (r >= ab).to(torch.int64) * bit
+            v += (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64) * bit
+        ok = u != v
+        lo = torch.minimum(u[ok], v[ok])
+        hi = torch.maximum(u[ok], v[ok])
+        keys.append(torch.unique(lo * n + hi))
+        del u, v, ok, lo, hi
+    key = torch.unique(torch.cat(keys))
+    del keys
+    perm = torch.randperm(n, generator=gen, device=device)
+    lo = perm[key // n]
+    hi = perm[key % n]
+    del key
+    src = torch.cat([lo, hi])
+    dst = torch.cat([hi, lo])
+    del lo, hi
+    order = torch.argsort(src * n + dst)
+    src = src[order]
+    colidx = dst[order].to(torch.int32)
+    del dst, order
+    counts = torch.bincount(src, minlength=n)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    rowptr[1:] = torch.cumsum(counts, 0)
+    return rowptr.to(torch.int32), colidx

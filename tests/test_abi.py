@@ -69,3 +69,17 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_binding_rejects_mis_shaped_tensors():
+    """Tensors are checked for device, dtype, contiguity and shape before any pointer
+    reaches the library (which cannot check buffer sizes itself)."""
+    import pytest
+    import torch
+    import paper_2601_11338_amd as wl
+    with pytest.raises(ValueError, match="device tensor"):
+        wl._need(torch.zeros(3), "x", torch.float32, (3,))
+    with pytest.raises(ValueError, match="device tensor"):
+        wl._need(None, "x", torch.float32, (3,))
+    with pytest.raises(ValueError, match="device tensor"):
+        wl._need(torch.zeros(4, 2).t(), "x", torch.float32, (2, 4))
