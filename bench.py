@@ -282,8 +282,9 @@ def run_cv_rmat22(args):
     (full batch Adam).  Evaluation: R-MAT scale 22 (edge factor 16, a = 0.57,
     b = c = 0.19), exact diagonal on 4096 sampled nodes, ten probe seeds for each
     M in {16, 64, 256}: plain Gaussian Hutchinson, the same probes with the control
-    variate, Gaussian BKS and Rademacher Hutchinson.  err = ||d_hat - d|| / ||d - 1||
-    over the sampled nodes."""
+    variate, Gaussian BKS, Rademacher Hutchinson, and the low-order surrogate (exact
+    diagonal of the degree-3 series, Hutchinson on the remainder) without and with the
+    learned control variate.  err = ||d_hat - d|| / ||d - 1|| over the sampled nodes."""
     import numpy as np
     import torch
     from concurrent.futures import ProcessPoolExecutor
@@ -342,6 +343,9 @@ def run_cv_rmat22(args):
         "cv_gauss": dict(law="gauss", estimator="hutchinson", cv=ghat),
         "bks_gauss": dict(law="gauss", estimator="bks", cv=None),
         "rademacher": dict(law="rademacher", estimator="hutchinson", cv=None),
+        "surrogate_gauss": dict(law="gauss", estimator="surrogate", cv=None),
+        "surrogate_cv_gauss": dict(law="gauss", estimator="surrogate", cv=ghat),
+        "surrogate_cv_rademacher": dict(law="rademacher", estimator="surrogate", cv=ghat),
     }
     Ms = [16, 64, 256]
     seeds = range(10)
@@ -358,6 +362,7 @@ def run_cv_rmat22(args):
     torch.cuda.synchronize()
     t_eval = time.perf_counter() - t_eval
     gain = {M: (errs["plain_gauss"][M] / errs["cv_gauss"][M]) ** 2 for M in Ms}
+    gain_sur = {M: (errs["plain_gauss"][M] / errs["surrogate_cv_gauss"][M]) ** 2 for M in Ms}
     value = float(np.mean(list(gain.values())))
     passed = errs["cv_gauss"][16] <= errs["plain_gauss"][64] and errs["cv_gauss"][64] <= errs["plain_gauss"][256]
     return {
@@ -383,6 +388,7 @@ def run_cv_rmat22(args):
         },
         "errors": errs,
         "probe_gain": gain,
+        "probe_gain_surrogate_cv": gain_sur,
         "pass_cv16_le_plain64_and_cv64_le_plain256": bool(passed),
         "train_seconds": t_train,
         "target_seconds": t_data,

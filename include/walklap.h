@@ -67,7 +67,12 @@ typedef enum {
   WL_M_LANCZOS = 2      /* block Lanczos (mu = 0: on A; resolvent: on A_mu(alpha)) */
 } wl_method;
 typedef enum { WL_PROBE_GAUSS = 0, WL_PROBE_RADEMACHER = 1 } wl_probe_law;
-typedef enum { WL_EST_HUTCHINSON = 0, WL_EST_BKS = 1, WL_EST_XNYS = 2 } wl_estimator;
+typedef enum {
+  WL_EST_HUTCHINSON = 0,
+  WL_EST_BKS = 1,
+  WL_EST_XNYS = 2,
+  WL_EST_SURROGATE = 3  /* wl_diag_est only: Hutchinson on phi - G, G the degree-3 series */
+} wl_estimator;
 
 /* Graph flags */
 #define WL_GRAPH_COPY 1u      /* library copies the CSR arrays (else it borrows them) */
@@ -237,7 +242,14 @@ wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, i
  * variate only; the Nystrom estimator takes M <= 64) the probes are ceil(M / 64)
  * blocks of 64 columns (the last one narrower), block c drawn from Philox stream c,
  * each pushed through the operator in turn with the per-row sums accumulated on the
- * device: the result is the M-probe estimator over those columns.                  */
+ * device: the result is the M-probe estimator over those columns.
+ * WL_EST_SURROGATE (target 0 only): with G = sum_{k<=3} c_k q_k(A) (eq. qrec, the
+ * operator's own weights), whose diagonal is exact from the degrees and triangle
+ * counts (diag q_1 = 0, diag q_2 = (1 - mu) d, diag q_3 = diag A^3 = 2 t):
+ *   d_i = g_i + (1/M) sum_j Omega_ij ((phi - G) Omega)_ij + (diag G_i - g_i) s_i / M,
+ *   s_i = sum_j Omega_ij^2, g = d_cv if given, else diag G.
+ * Unbiased for any g: G's off-diagonal part no longer enters the probe noise.  The
+ * trace estimate is tr G + the mean of the per-probe omega^T (phi - G) omega.     */
 wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t seed,
                       int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
                       void* d_diag, double* trace, double* trace_err);

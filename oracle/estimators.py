@@ -17,6 +17,11 @@ symmetric target F (phi, or exp(-t L) for the return probabilities of Sec. 4.4).
   The Nystrom approximation needs F positive semidefinite.
 * Control-variate diagonal: with a prediction g of diag F,
       d_i = g_i + (1/M) sum_j Omega_ij (Y_ij - g_i Omega_ij).
+* Low-order surrogate: with a matrix G whose diagonal is known exactly and
+  Z = G Omega, Hutchinson on F - G plus diag G, optionally with a control variate g:
+      d_i = g_i + (1/M) sum_j Omega_ij ((Y - Z)_ij + (diag G_i - g_i) Omega_ij),
+  g = diag G when no control variate is given.  Only G's off-diagonal part is
+  removed from the probe noise, so the estimator stays unbiased for any g.
 Test infrastructure: see the package docstring.
 """
 
@@ -38,6 +43,17 @@ def bks_diag(Omega, Y):
 def cv_diag(Omega, Y, g):
     g = np.asarray(g, dtype=np.float64)
     return g + (Omega * (Y - g[:, None] * Omega)).mean(axis=1)
+
+
+def surrogate_diag(Omega, Y, Z, gdiag, g=None):
+    gdiag = np.asarray(gdiag, dtype=np.float64)
+    g = gdiag if g is None else np.asarray(g, dtype=np.float64)
+    return g + (Omega * ((Y - Z) + (gdiag - g)[:, None] * Omega)).mean(axis=1)
+
+
+def surrogate_trace(Omega, Y, Z, gdiag):
+    """tr G + the mean over probes of omega_j^T (F - G) omega_j."""
+    return float(np.sum(gdiag)) + float((Omega * (Y - Z)).sum() / Omega.shape[1])
 
 
 def _pinv_sym(H, rcond):

@@ -12,6 +12,7 @@ from . import _lib
 from ._lib import (  # noqa: F401
     WL_EST_BKS,
     WL_EST_HUTCHINSON,
+    WL_EST_SURROGATE,
     WL_EST_XNYS,
     WL_F_EXP,
     WL_F_RESOLVENT,
@@ -29,7 +30,8 @@ from ._lib import (  # noqa: F401
 
 FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP}
 METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS}
-ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS}
+ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS,
+              "surrogate": WL_EST_SURROGATE}
 LAWS = {"gauss": WL_PROBE_GAUSS, "gaussian": WL_PROBE_GAUSS, "rademacher": WL_PROBE_RADEMACHER}
 
 

@@ -26,6 +26,20 @@ namespace {
 
 constexpr int DIAG_CHUNK = 64;  // probes per block in wl_diag_est
 
+// Surrogate estimator finish: diag G_i = 1 + c2m d_i + c3 tri2_i (c2m = c_2 (1 - mu),
+// tri2_i = (A^3)_ii); dot_i = sum_j Omega_ij ((phi - G) Omega)_ij, sq_i = sum_j Omega_ij^2;
+// d_i = g_i + (dot_i + (diag G_i - g_i) sq_i) / M with g = cv, or diag G without one.
+template <typename T>
+__global__ void k_surrogate_finish(int64_t n, int M, const double* __restrict__ dot, const double* __restrict__ sq,
+                                   const int32_t* __restrict__ rowptr, const unsigned long long* __restrict__ tri2,
+                                   double c2m, double c3, const T* __restrict__ cv, T* __restrict__ diag) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const double gd = 1.0 + c2m * (double)(rowptr[r + 1] - rowptr[r]) + c3 * (double)tri2[r];
+    const double gh = cv ? (double)cv[r] : gd;
+    diag[r] = (T)(gh + (dot[r] + (gd - gh) * sq[r]) / M);
+  }
+}
+
 // Gram of two n x M row-major blocks (M <= 64: one launch of the Gram kernel).
 template <typename T>
 wl_status gram_full(wl_ctx* ctx, int64_t n, int M, const T* X, const T* Y, std::vector<double>& out) {
@@ -163,10 +177,14 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
   WL_CHECK(op, WL_EINVAL, "wl_diag_est: op is null");
   WL_CHECK(target == 0 || target == 1, WL_EINVAL, "wl_diag_est: target must be 0 (phi) or 1 (exp(-tL))");
   WL_CHECK(M >= 1 && M <= 4096, WL_EINVAL, "wl_diag_est: M must lie in [1, 4096]");
+  WL_CHECK(estimator >= WL_EST_HUTCHINSON && estimator <= WL_EST_SURROGATE, WL_EINVAL,
+           "wl_diag_est: bad estimator");
   WL_CHECK(M <= DIAG_CHUNK || estimator != WL_EST_XNYS, WL_EINVAL,
            "wl_diag_est: the Nystrom estimator takes at most %d probes", DIAG_CHUNK);
-  WL_CHECK(!(d_cv && estimator != WL_EST_HUTCHINSON), WL_EINVAL,
-           "wl_diag_est: the control variate applies to the Hutchinson estimator");
+  WL_CHECK(!(d_cv && estimator != WL_EST_HUTCHINSON && estimator != WL_EST_SURROGATE), WL_EINVAL,
+           "wl_diag_est: the control variate applies to the Hutchinson and surrogate estimators");
+  WL_CHECK(!(estimator == WL_EST_SURROGATE && target != 0), WL_EINVAL,
+           "wl_diag_est: the surrogate estimator applies to phi (target 0)");
   WL_CHECK(law == WL_PROBE_GAUSS || law == WL_PROBE_RADEMACHER, WL_EINVAL, "wl_diag_est: bad probe law");
   WL_CHECK(std::isfinite(t) && t >= 0, WL_EINVAL, "wl_diag_est: bad t");
   wl_graph* g = op->g;
@@ -185,7 +203,8 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
     void* outs[1] = {Y.p};
     return wl_expv(op, Om.p, m, &t, 1, outs, outer_dim, nullptr);
   };
-  if (M <= DIAG_CHUNK) {
+  const bool sur = estimator == WL_EST_SURROGATE;
+  if (M <= DIAG_CHUNK && !sur) {
     WL_TRY(wl_probes(ctx, op->d.prec, law, seed, 0, n, M, Om.p));
     WL_TRY(product(M));
     WL_TRY(wl_estimate(ctx, op->d.prec, estimator, n, M, Om.p, Y.p, d_cv, 1e-10, d_diag, trace, trace_err));
@@ -195,9 +214,30 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
   // more probes than one block: blocks of DIAG_CHUNK columns (block c from Philox
   // stream c), row sums accumulated on the device, per-probe traces from the Gram
   // diagonal of each block
-  DevBuf sums, H;
+  // (the surrogate estimator takes this path for any M: Y becomes (phi - G) Omega)
+  DevBuf sums, H, Z, tri;
   WL_TRY(sums.ensure((size_t)2 * n * 8));
   WL_TRY(H.ensure((size_t)DIAG_CHUNK * DIAG_CHUNK * 8));
+  wl_op gop;  // the degree-3 truncation of the same series (borrows the graph)
+  double c2m = 0.0, c3 = 0.0, trG = 0.0;
+  if (sur) {
+    gop.g = g;
+    gop.d = op->d;
+    gop.d.method = WL_M_RECURRENCE;
+    gop.K = 3;
+    const double p = op->d.param;
+    const bool ex = op->d.func == WL_F_EXP;
+    c2m = (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
+    c3 = ex ? p * p * p / 6.0 : p * p * p;
+    WL_TRY(Z.ensure((size_t)n * mc * es));
+    WL_TRY(graph_tri2(g, tri));
+    std::vector<unsigned long long> ht(n);
+    WL_HIP(hipMemcpyAsync(ht.data(), tri.p, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    double st = 0.0;
+    for (unsigned long long v : ht) st += (double)v;
+    trG = (double)n + c2m * (double)g->nnz + c3 * st;
+  }
   std::vector<double> tj;
   std::vector<double> hH((size_t)DIAG_CHUNK * DIAG_CHUNK);
   const int nchunks = (M + DIAG_CHUNK - 1) / DIAG_CHUNK;
@@ -205,6 +245,16 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
     const int m = std::min(DIAG_CHUNK, M - c * DIAG_CHUNK);
     WL_TRY(wl_probes(ctx, op->d.prec, law, seed, (uint32_t)c, n, m, Om.p));
     WL_TRY(product(m));
+    if (sur) {  // Y <- Y - G Omega
+      if (op->d.prec == WL_FP32) {
+        WL_TRY(phi_apply_impl<float>(&gop, Om.as<float>(), Z.as<float>(), m, nullptr, nullptr));
+        WL_TRY(launch_axpby_rows<float>(ctx, n, m, nullptr, Y.as<float>(), -1.0, Z.as<float>(), Y.as<float>()));
+      } else {
+        WL_TRY(phi_apply_impl<double>(&gop, Om.as<double>(), Z.as<double>(), m, nullptr, nullptr));
+        WL_TRY(launch_axpby_rows<double>(ctx, n, m, nullptr, Y.as<double>(), -1.0, Z.as<double>(),
+                                         Y.as<double>()));
+      }
+    }
     if (op->d.prec == WL_FP32) {
       WL_TRY(launch_rowdot<float>(ctx, n, m, Om.as<float>(), Y.as<float>(), sums.as<double>(),
                                   sums.as<double>() + n, c > 0));
@@ -219,17 +269,29 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
     for (int j = 0; j < m; ++j) tj.push_back(hH[(size_t)j * m + j]);
   }
   const int mode = d_cv ? 2 : (estimator == WL_EST_BKS ? 1 : 0);
-  if (op->d.prec == WL_FP32)
+  const int gb = (int)std::min<int64_t>(8192, (n + 255) / 256);
+  if (sur && op->d.prec == WL_FP32) {
+    hipLaunchKernelGGL(k_surrogate_finish<float>, dim3(gb), dim3(256), 0, ctx->stream, n, M, sums.as<double>(),
+                       sums.as<double>() + n, g->rowptr, tri.as<unsigned long long>(), c2m, c3,
+                       (const float*)d_cv, (float*)d_diag);
+    WL_HIP(hipGetLastError());
+  } else if (sur) {
+    hipLaunchKernelGGL(k_surrogate_finish<double>, dim3(gb), dim3(256), 0, ctx->stream, n, M, sums.as<double>(),
+                       sums.as<double>() + n, g->rowptr, tri.as<unsigned long long>(), c2m, c3,
+                       (const double*)d_cv, (double*)d_diag);
+    WL_HIP(hipGetLastError());
+  } else if (op->d.prec == WL_FP32) {
     WL_TRY(launch_sums_finish<float>(ctx, n, M, sums.as<double>(), sums.as<double>() + n, (const float*)d_cv, mode,
                                      (float*)d_diag));
-  else
+  } else {
     WL_TRY(launch_sums_finish<double>(ctx, n, M, sums.as<double>(), sums.as<double>() + n, (const double*)d_cv,
                                       mode, (double*)d_diag));
+  }
   double mean = 0.0, var = 0.0;
   for (double v : tj) mean += v;
   mean /= M;
   for (double v : tj) var += (v - mean) * (v - mean);
-  if (trace) *trace = mean;
+  if (trace) *trace = mean + trG;
   if (trace_err) *trace_err = std::sqrt(var / (M - 1)) / std::sqrt((double)M);
   WL_HIP(hipStreamSynchronize(ctx->stream));
   return WL_OK;

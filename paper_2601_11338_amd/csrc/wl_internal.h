@@ -169,6 +169,10 @@ struct EpiArgs {
 template <typename T>
 wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh);
 
+// tri2[i] = (A^3)_ii = twice the triangles through node i (n unsigned 64-bit counts in
+// tri, resized as needed); colidx must be sorted within rows.
+wl_status graph_tri2(wl_graph* g, DevBuf& tri);
+
 // SpMM launch shape for (prec, b) on g: the autotuned one if present, else a heuristic.
 SpmmShape shape_for(wl_graph* g, int prec, int b);
 

@@ -23,7 +23,7 @@ def setup(lib):
     alpha = 0.5 / np.linalg.eigvalsh(A)[-1]
     op = lib.Operator(g, 0.5, "res", alpha, dtype=torch.float64, tol=1e-13)
     F = genfun.phi(A, 0.5, "res", alpha)
-    return ctx, g, op, F, n
+    return ctx, g, op, F, n, A, alpha
 
 
 def probes(n, M, seed, law):
@@ -41,9 +41,12 @@ def probes(n, M, seed, law):
     (100, "hutchinson", "gauss", False),
     (100, "bks", "gauss", False),
     (200, "hutchinson", "rademacher", True),
+    (16, "surrogate", "gauss", False),
+    (16, "surrogate", "gauss", True),
+    (100, "surrogate", "rademacher", True),
 ])
 def test_diag_est_phi(setup, M, est, law, use_cv):
-    ctx, g, op, F, n = setup
+    ctx, g, op, F, n, A, alpha = setup
     print(f"[gpu] diag_est phi M={M} {est} {law} cv={use_cv}", flush=True)
     seed = 77
     Om = probes(n, M, seed, law)
@@ -55,13 +58,19 @@ def test_diag_est_phi(setup, M, est, law, use_cv):
     if est == "xnys":
         t_o, e_o, ref, _ = estimators.xnys(Om, Y, rcond=1e-10)
         assert abs(tr - t_o) < 1e-8 * abs(t_o)
+    elif est == "surrogate":
+        G = genfun.phi_series(A, 0.5, genfun.coefficients("res", alpha, 3))
+        Z = G @ Om
+        ref = estimators.surrogate_diag(Om, Y, Z, np.diag(G), gcv)
+        t_o = estimators.surrogate_trace(Om, Y, Z, np.diag(G))
+        assert abs(tr - t_o) < 1e-8 * abs(t_o)
     elif use_cv:
         ref = estimators.cv_diag(Om, Y, gcv)
     elif est == "bks":
         ref = estimators.bks_diag(Om, Y)
     else:
         ref = estimators.hutchinson_diag(Om, Y)
-    if est != "xnys":
+    if est not in ("xnys", "surrogate"):
         per_probe = np.einsum("ij,ij->j", Om, Y)
         assert abs(tr - per_probe.mean()) < 1e-8 * abs(per_probe.mean())
         assert abs(te - per_probe.std(ddof=1) / np.sqrt(M)) < 1e-6 * te
@@ -69,7 +78,7 @@ def test_diag_est_phi(setup, M, est, law, use_cv):
 
 
 def test_diag_est_return_probabilities(setup):
-    ctx, g, op, F, n = setup
+    ctx, g, op, F, n, A, alpha = setup
     print("[gpu] diag_est exp(-tL) xnys", flush=True)
     M, seed, t = 24, 5, 1.0
     Om = probes(n, M, seed, "gauss")
@@ -82,10 +91,12 @@ def test_diag_est_return_probabilities(setup):
 
 
 def test_diag_est_rejects_bad_arguments(setup, lib):
-    ctx, g, op, F, n = setup
+    ctx, g, op, F, n, A, alpha = setup
     with pytest.raises(lib.WLError):
         op.diag_est(100, 1, estimator="xnys")
     with pytest.raises(lib.WLError):
         op.diag_est(5000, 1)
     with pytest.raises(lib.WLError):
         op.diag_est(0, 1)
+    with pytest.raises(lib.WLError):
+        op.diag_est(16, 1, target="L", estimator="surrogate")

@@ -134,6 +134,69 @@ def test_xnys_trace_unbiased_on_full_rank():
     assert abs(ts.mean() - np.trace(F)) < 4.5 * ts.std(ddof=1) / np.sqrt(reps)
 
 
+def brute_triangles(A):
+    n = A.shape[0]
+    t = np.zeros(n)
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                if A[i, j] and A[j, k] and A[i, k]:
+                    t[[i, j, k]] += 1
+    return t
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3, 1.0])
+@pytest.mark.parametrize("kind", ["exp", "res"])
+def test_low_order_series_diagonal_closed_form(mu, kind):
+    """diag of sum_{k<=3} c_k q_k = 1 + c_2 (1 - mu) d + 2 c_3 t (t: triangles, counted
+    by brute force over node triples; q_k from walk enumeration)."""
+    n, rp, ci = er(25, 70, 8)
+    A = walks.adjacency(n, rp, ci)
+    c = genfun.coefficients(kind, 0.2, 3)
+    G = genfun.phi_series(A, mu, c)
+    d = A.sum(1)
+    t = brute_triangles(A)
+    assert t.sum() > 0
+    np.testing.assert_allclose(np.diag(G), 1 + c[2] * (1 - mu) * d + 2 * c[3] * t, rtol=1e-14)
+
+
+def test_surrogate_exact_when_target_is_the_surrogate():
+    """F = G with Rademacher probes: omega_i^2 = 1 and the off-diagonal noise is gone,
+    so the estimate is diag G for any control variate."""
+    n, rp, ci = er(30, 80, 4)
+    A = walks.adjacency(n, rp, ci)
+    G = genfun.phi_series(A, 0.5, genfun.coefficients("exp", 0.3, 3))
+    Om = philox.rademacher(n, 5, 9)
+    Z = G @ Om
+    np.testing.assert_allclose(estimators.surrogate_diag(Om, Z, Z, np.diag(G)), np.diag(G), rtol=1e-14)
+    g = np.linspace(0.5, 2.0, n)
+    np.testing.assert_allclose(estimators.surrogate_diag(Om, Z, Z, np.diag(G), g), np.diag(G), rtol=1e-14)
+    assert abs(estimators.surrogate_trace(Om, Z, Z, np.diag(G)) - np.trace(G)) < 1e-12 * np.trace(G)
+
+
+def test_surrogate_unbiased_and_removes_offdiagonal_noise():
+    """E[d_hat] = diag F for any g; the per-node variance is that of Hutchinson on F - G
+    (Gaussian: 2 (F_ii - g_i)^2 + sum_{k != i} (F - G)_ik^2), below plain Hutchinson."""
+    n = 8
+    rp, ci = synth.erdos_renyi_gnm(n, 14, 2)
+    A = walks.adjacency(n, rp, ci)
+    F = genfun.phi(A, 0.5, "exp", 0.4)
+    G = genfun.phi_series(A, 0.5, genfun.coefficients("exp", 0.4, 3))
+    g = np.diag(F) * 1.1
+    M, reps = 4, 4000
+    Om = philox.gaussian(n, M * reps, 31)
+    Y, Z = F @ Om, G @ Om
+    est = np.stack([estimators.surrogate_diag(Om[:, r * M:(r + 1) * M], Y[:, r * M:(r + 1) * M],
+                                              Z[:, r * M:(r + 1) * M], np.diag(G), g) for r in range(reps)], 1)
+    R = F - G
+    var_pred = (2 * (np.diag(F) - g) ** 2 + (R ** 2).sum(1) - np.diag(R) ** 2) / M
+    z = np.abs(est.mean(1) - np.diag(F)) / np.sqrt(var_pred / reps)
+    assert z.max() < 4.5
+    np.testing.assert_allclose(est.var(1, ddof=1), var_pred, rtol=0.15)
+    var_plain = (2 * np.diag(F) ** 2 + (F ** 2).sum(1) - np.diag(F) ** 2) / M
+    assert np.all(var_pred < var_plain)
+
+
 # ------------------------------------------------------------------ philox
 def test_philox_known_answer_vectors():
     """Published Philox4x32-10 known-answer vectors (Random123 distribution)."""
