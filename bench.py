@@ -35,11 +35,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="ba1m", choices=["ba1m", "batch512", "cv-rmat22"],
+    p.add_argument("--workload", default="ba1m", choices=["ba1m", "batch512", "cv-rmat22", "expv-rmat25"],
                    help="ba1m: one Barabasi-Albert graph, n=10^6 (default); batch512: 512 SBM / "
                         "configuration-model graphs, diffusion and return probabilities in one batch; "
                         "cv-rmat22: learned control variate trained on 200 small graphs, diagonal "
-                        "error versus probes on an R-MAT scale-22 graph")
+                        "error versus probes on an R-MAT scale-22 graph; expv-rmat25: diffusion of 32 "
+                        "sparse initial conditions on an R-MAT scale-25 graph (33.5M nodes)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--krylov", type=int, default=30)
     p.add_argument("--block", type=int, default=16)
@@ -270,6 +271,110 @@ def cpu_baseline_batch(csrs, descs, b, budget_s=15.0):
     }
 
 
+def run_expv_rmat25(args):
+    """Diffusion on R-MAT scale 25 (edge factor 16, a = 0.57, b = c = 0.19; 33.5M
+    nodes, about 1e9 symmetric nonzeros): exp(-t L) U0 for t in {0.1, 1, 10} with
+    L the walk Laplacian of mu = 0.5 (theta = 0.5) and the exponential (beta =
+    1/lambda_max, inner series degree from the tail bound at 1e-9), U0 = 32 sparse
+    probability vectors (16 random non-isolated nodes each), 40 outer block Lanczos
+    steps, FP32 vectors with FP64 coefficients.  One step = one wl_expv call for the
+    three times (one Krylov basis serves all t)."""
+    import torch
+
+    import paper_2601_11338_amd as wl
+    import synth
+
+    b, K_out, ts = 32, args.krylov if args.krylov != 30 else 40, [0.1, 1.0, 10.0]
+    log("generating R-MAT scale 25 on the device")
+    rp, ci = synth.rmat_device(25, 16, 0.57, 0.19, 0.19, seed=2025)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the Krylov basis (about 176 GB) is allocated by the library
+    ctx = wl.Context(0)
+    g = wl.Graph(ctx, rp, ci, validate=True)
+    n, nnz = g.n, g.nnz
+    log(f"graph n={n} nnz={nnz} max_degree={g.info()[2]}")
+    g.autotune(torch.float32, b)
+    lam = g.lambda_max()
+    op = wl.Operator(g, 0.5, "exp", 1.0 / lam, dtype=torch.float32, tol=1e-9)
+    K_in, _ = op.info()
+    log(f"lambda_max={lam:.4f}; inner series degree {K_in}")
+    deg = rp[1:] - rp[:-1]
+    pool = torch.nonzero(deg > 0).flatten()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(25)
+    U0 = torch.zeros((n, b), dtype=torch.float32, device="cuda")
+    for j in range(b):
+        sel = pool[torch.randperm(pool.numel(), generator=gen, device="cuda")[:16]]
+        U0[sel, j] = 1.0 / 16
+    del pool, deg
+    outs = [torch.empty_like(U0) for _ in ts]
+    op.fdeg()
+
+    def step():
+        return op.expv(U0, ts, outer_dim=K_out, outs=outs)
+
+    for _ in range(args.warmup):
+        step()
+        log("warm-up step done")
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, err = step()
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done; a-posteriori errors {['%.2e' % e for e in err]}")
+    t1 = time.perf_counter()
+    rec = ctx.kernel_stats(0)
+    oth = ctx.kernel_stats(2)
+    ctx.set_profiling(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    # inner products: K_in sparse products on b columns per outer step
+    edge_vec = K_out * K_in * float(nnz) * b
+    value = edge_vec / (ms * 1e-3) / 1e9
+    launches, kms, kbytes = rec
+    avg_ms = kms / max(launches, 1)
+    achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    mass = [float(o.sum()) / float(U0.sum()) for o in outs]
+    log(f"recurrence kernel: {launches} launches, avg {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic; "
+        f"first-step kernel: {oth[0]} launches; mass ratio {mass}")
+    return {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GEdge·vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"R-MAT scale 25 ef 16 (a=.57 b=c=.19) n={n} nnz={nnz}; mu=0.5 exp beta=1/lambda_max "
+                        f"(inner degree {K_in}); exp(-tL)U0 for t in {ts}, U0 32 sparse probability vectors; "
+                        f"outer Krylov dim {K_out}; FP32 vectors, FP64 coefficients",
+            "n": n,
+            "nnz": nnz,
+            "block": b,
+            "krylov_dim": K_out,
+            "inner_degree": K_in,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_spmm fused recurrence step (b=32)",
+            "avg_launch_us": avg_ms * 1e3,
+            "alg_bytes_per_launch": kbytes / max(launches, 1),
+        },
+        "mass_ratio": mass,
+    }
+
+
 MLP_SHAPES = [(64, 8), (64,), (64, 64), (64,), (1, 64), (1,)]
 
 
@@ -410,6 +515,9 @@ def main():
         return
     if args.workload == "cv-rmat22":
         print(json.dumps(run_cv_rmat22(args)), flush=True)
+        return
+    if args.workload == "expv-rmat25":
+        print(json.dumps(run_expv_rmat25(args)), flush=True)
         return
     import numpy as np
     import torch

@@ -170,6 +170,10 @@ wl_status wl_spectral_radius(wl_graph* g, double mu, double tol, double* rho);
 /* ---------------------------------------------------------------- operator */
 wl_status wl_op_create(wl_graph* g, const wl_op_desc* desc, wl_op** out);
 wl_status wl_op_destroy(wl_op* op);
+/* The truncation degree (recurrence) or number of block Lanczos steps the operator
+ * settled on, and its method (WL_M_RECURRENCE or WL_M_LANCZOS).  Either output may
+ * be NULL.                                                                        */
+wl_status wl_op_info(const wl_op* op, int32_t* degree_or_steps, int32_t* method);
 
 /* w = phi 1 (n values): total communicability t(f) (Sec. 3.1) and the diagonal of
  * the walk Laplacian's degree part (eq. weighted_laplacian).  Includes c_0 = 1.
@@ -288,6 +292,22 @@ wl_status wl_batch_apply_L(wl_batch* batch, const void* d_X, void* d_Y, int32_t 
 wl_status wl_batch_expv(wl_batch* batch, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
                         double* p_hat, double* p_err);
 wl_status wl_batch_destroy(wl_batch* batch);
+
+/* Replayable batched diffusion for fixed buffers (serving loops): the whole device
+ * part of wl_batch_expv for (d_U0, b, outer_dim, d_Y) captured once into a HIP
+ * graph with scratch of its own.  wl_batch_graph_launch copies the ngraphs times t
+ * (host) to the device, launches the graph on the context's stream and returns
+ * without waiting unless p_hat / p_err are requested (as in wl_batch_expv; then it
+ * synchronises).  d_U0 is read and d_Y written at every launch; their contents may
+ * change between launches, their addresses may not.  Launches of one graph are
+ * ordered on the stream; a graph must be destroyed before its batch
+ * (wl_batch_destroy returns WL_EINVAL while graphs are alive).  Same limits on b
+ * and outer_dim as wl_batch_expv.                                                  */
+typedef struct wl_batch_graph wl_batch_graph;
+wl_status wl_batch_graph_create(wl_batch* batch, const void* d_U0, int32_t b, int32_t outer_dim, void* d_Y,
+                                wl_batch_graph** out);
+wl_status wl_batch_graph_launch(wl_batch_graph* graph, const double* t, double* p_hat, double* p_err);
+wl_status wl_batch_graph_destroy(wl_batch_graph* graph);
 
 /* ---------------------------------------------------------------- learned control variate
  * No counterpart in the paper: a small network predicts diag(phi) from cheap local

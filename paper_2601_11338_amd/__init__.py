@@ -204,6 +204,12 @@ class Operator:
     def _empty(self, *shape):
         return _torch().empty(shape, dtype=self.dtype, device=self.graph.ctx.torch_device)
 
+    def info(self):
+        """(truncation degree or Lanczos steps, method code)."""
+        k, m = C.c_int32(), C.c_int32()
+        check(load().wl_op_info(self.handle, C.byref(k), C.byref(m)))
+        return k.value, m.value
+
     def fdeg(self, out=None):
         out = self._empty(self.graph.n) if out is None else out
         _need(out, "out", self.dtype, (self.graph.n,))
@@ -474,9 +480,50 @@ class Batch:
                                    pe.ctypes.data_as(pd_) if want_trace else None))
         return out, ph, pe
 
+    def graph(self, U0, Y, outer_dim=30):
+        """Capture the batched diffusion for these fixed buffers (see BatchGraph)."""
+        return BatchGraph(self, U0, Y, outer_dim)
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             load().wl_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchGraph:
+    """A captured batched diffusion bound to fixed U0 / Y buffers; launch() replays it."""
+
+    def __init__(self, batch, U0, Y, outer_dim=30):
+        torch = _torch()
+        _need(U0, "U0", torch.float32, (batch.total_rows, None))
+        _need(Y, "Y", torch.float32, tuple(U0.shape))
+        self.batch, self.U0, self.Y = batch, U0, Y  # keep the buffers (and the batch) alive
+        self.handle = C.c_void_p()
+        check(load().wl_batch_graph_create(batch.handle, _ptr(U0), U0.shape[1], int(outer_dim), _ptr(Y),
+                                           C.byref(self.handle)))
+
+    def launch(self, ts, want_trace=False):
+        import numpy as np
+        t = np.ascontiguousarray(ts, dtype=np.float64)
+        if t.shape != (len(self.batch.graphs),):
+            raise ValueError("one time per graph is needed")
+        ng = len(self.batch.graphs)
+        ph, pe = np.zeros(ng), np.zeros(ng)
+        pd_ = C.POINTER(C.c_double)
+        check(load().wl_batch_graph_launch(self.handle, t.ctypes.data_as(pd_),
+                                           ph.ctypes.data_as(pd_) if want_trace else None,
+                                           pe.ctypes.data_as(pd_) if want_trace else None))
+        return (ph, pe) if want_trace else None
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_batch_graph_destroy(self.handle)
             self.handle = C.c_void_p()
 
     def __del__(self):

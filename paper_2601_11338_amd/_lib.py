@@ -57,6 +57,7 @@ SIGNATURES = {
     "wl_spectral_radius": (C.c_int, [vp, f64, f64, pd]),
     "wl_op_create": (C.c_int, [vp, C.POINTER(OpDesc), C.POINTER(vp)]),
     "wl_op_destroy": (C.c_int, [vp]),
+    "wl_op_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32)]),
     "wl_fdeg": (C.c_int, [vp, vp]),
     "wl_apply_phi": (C.c_int, [vp, vp, vp, i32]),
     "wl_apply_L": (C.c_int, [vp, vp, vp, i32]),
@@ -81,6 +82,9 @@ SIGNATURES = {
     "wl_batch_apply_L": (C.c_int, [vp, vp, vp, i32]),
     "wl_batch_expv": (C.c_int, [vp, vp, i32, pd, i32, vp, pd, pd]),
     "wl_batch_destroy": (C.c_int, [vp]),
+    "wl_batch_graph_create": (C.c_int, [vp, vp, i32, i32, vp, C.POINTER(vp)]),
+    "wl_batch_graph_launch": (C.c_int, [vp, pd, pd, pd]),
+    "wl_batch_graph_destroy": (C.c_int, [vp]),
     "wl_mlp_save": (C.c_int, [vp, C.c_char_p]),
     "wl_mlp_load": (C.c_int, [vp, C.c_char_p, C.POINTER(vp)]),
 }

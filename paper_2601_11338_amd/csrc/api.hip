@@ -58,10 +58,15 @@ constexpr int prec_of() {
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-// deflation thresholds on squared norms (Gram pivots)
+// Deflation thresholds on squared norms (Gram pivots), relative to the block's norm
+// before projection.  The projected Gram is formed by Pythagoras from inner products
+// of stored vectors; with FP32 storage the basis is orthonormal only to ~1e-7, so
+// pivots below ~1e-7 of the reference are rounding noise (a direction whose residual
+// is below ~1e-3 of the block cannot be resolved): such columns are dropped rather
+// than normalised into spurious basis vectors.
 template <typename T>
 double defl_tol() {
-  return sizeof(T) == 4 ? 1e-10 : 1e-24;
+  return sizeof(T) == 4 ? 1e-6 : 1e-24;
 }
 
 int next_pow2(int x) {
@@ -1066,6 +1071,13 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   op->rho = rho;
   op->K = K;
   *out = op;
+  return WL_OK;
+}
+
+wl_status wl_op_info(const wl_op* op, int32_t* degree_or_steps, int32_t* method) {
+  WL_CHECK(op, WL_EINVAL, "wl_op_info: op is null");
+  if (degree_or_steps) *degree_or_steps = op->K;
+  if (method) *method = op->d.method;
   return WL_OK;
 }
 

@@ -135,6 +135,21 @@ __global__ void k_dcopy_batched(int count, const double* __restrict__ x, double*
   for (int e = threadIdx.x; e < count; e += blockDim.x) y[go + e] = x[go + e];
 }
 
+// Graphs whose Krylov space is exhausted at step j (kcap[g] == j + 1 blocks span their
+// whole space): zero the coupling B_j and the inverse Cholesky factor of the second
+// pass, so V_{j+1} = 0 and every later block of that graph stays zero (its projected
+// matrix decouples exactly instead of continuing on rounding noise).
+__global__ void k_cap_blocks(int ng, const int32_t* __restrict__ kcap, int j, double* __restrict__ S, int64_t gs,
+                             int64_t offRi, int64_t offB, int bb) {
+  const int g = blockIdx.x;
+  if (g >= ng || kcap[g] != j + 1) return;
+  double* Sg = S + (int64_t)g * gs;
+  for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+    Sg[offRi + e] = 0.0;
+    Sg[offB + e] = 0.0;
+  }
+}
+
 __global__ void k_dtranspose_batched(int b, const double* __restrict__ x, double* __restrict__ y, int64_t gs) {
   const int64_t go = (int64_t)blockIdx.x * gs;
   for (int e = threadIdx.x; e < b * b; e += blockDim.x) y[go + (e % b) * b + e / b] = x[go + e];
@@ -262,6 +277,13 @@ struct Layout {  // small matrices of one graph (doubles), as in the single-grap
 
 }  // namespace
 
+// Scratch of one batched evaluation: recurrence buffers, Krylov basis, small matrices,
+// Gram partials, times and per-graph step caps.  A captured graph owns its own.
+struct BatchWork {
+  DevBuf bufA, bufB, basis, S, F, partials, tvals, kcap;
+  std::vector<char> cap_at;  // cap_at[j]: some graph's Krylov space ends at block j + 1
+};
+
 struct wl_batch {
   wl_ctx* ctx = nullptr;
   int ng = 0;
@@ -278,32 +300,33 @@ struct wl_batch {
   std::vector<int64_t> us;
   std::vector<int> gu0;
   DevBuf d_us, d_gu0;
-  DevBuf bufA, bufB, ones, basis, S, F, partials, tvals;
-  int basis_b = 0, basis_K = 0;
+  DevBuf ones;
+  BatchWork work;  // scratch of the eager entry points
+  int graphs = 0;  // live captured graphs (they hold pointers into the batch)
 };
 
 namespace {
 
-wl_status batch_gram(wl_batch* bt, const float* X, int64_t sX, int nblk, const float* Y, int b, double* out,
-                     int64_t gs) {
+wl_status batch_gram(wl_batch* bt, BatchWork& wk, const float* X, int64_t sX, int nblk, const float* Y, int b,
+                     double* out, int64_t gs) {
   wl_ctx* ctx = bt->ctx;
   const int nunits = (int)bt->us.size() - 1;
-  WL_TRY(bt->partials.ensure((size_t)nblk * nunits * 256 * sizeof(double)));
+  WL_TRY(wk.partials.ensure((size_t)nblk * nunits * 256 * sizeof(double)));
   const int blocks = std::max(1, std::min(1024, (nunits + 3) / 4));
   const int NB = nblk >= 3 ? 3 : nblk;
   dim3 grid(blocks, (nblk + NB - 1) / NB);
   if (NB == 1)
     hipLaunchKernelGGL(k_gram_seg<1>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
-                       b, bt->partials.as<double>());
+                       b, wk.partials.as<double>());
   else if (NB == 2)
     hipLaunchKernelGGL(k_gram_seg<2>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
-                       b, bt->partials.as<double>());
+                       b, wk.partials.as<double>());
   else
     hipLaunchKernelGGL(k_gram_seg<3>, grid, dim3(256), 0, ctx->stream, bt->d_us.as<int64_t>(), nunits, X, sX, nblk, Y,
-                       b, bt->partials.as<double>());
+                       b, wk.partials.as<double>());
   WL_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_gram_seg_finalize, dim3(16, nblk, bt->ng), dim3(256), 0, ctx->stream,
-                     bt->partials.as<double>(), nunits, bt->d_gu0.as<int>(), b, out, gs);
+                     wk.partials.as<double>(), nunits, bt->d_gu0.as<int>(), b, out, gs);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -323,13 +346,13 @@ wl_status batch_update(wl_batch* bt, const float* X, int64_t sX, int nblk, int b
 
 // phi X for every graph by its truncated series (eq. qrec), optionally finished into
 // the walk Laplacian (Y = w * X - phi X at each graph's last degree).
-wl_status batch_phi(wl_batch* bt, const float* X, float* Y, int b, bool laplacian) {
+wl_status batch_phi(wl_batch* bt, BatchWork& wk, const float* X, float* Y, int b, bool laplacian) {
   wl_graph* g = bt->G;
   const int64_t N = bt->N;
-  WL_TRY(bt->bufA.ensure((size_t)N * b * 4));
-  WL_TRY(bt->bufB.ensure((size_t)N * b * 4));
-  float* A = bt->bufA.as<float>();
-  float* B = bt->bufB.as<float>();
+  WL_TRY(wk.bufA.ensure((size_t)N * b * 4));
+  WL_TRY(wk.bufB.ensure((size_t)N * b * 4));
+  float* A = wk.bufA.as<float>();
+  float* B = wk.bufB.as<float>();
   const SpmmShape sh = shape_for(g, WL_FP32, b);
   const double* tab = laplacian ? bt->gtab.as<double>() : bt->gtab_none.as<double>();
   const int64_t tstride = (int64_t)bt->ng * 5;
@@ -366,6 +389,186 @@ wl_status batch_phi(wl_batch* bt, const float* X, float* Y, int b, bool laplacia
     WL_TRY(launch_spmm<float>(g, Pm1, out, b, ep, sh));
     Pm2 = Pm1;
     Pm1 = out;
+  }
+  return WL_OK;
+}
+
+}  // namespace
+
+struct wl_batch_graph {
+  wl_batch* bt = nullptr;
+  int b = 0, K = 0;
+  BatchWork work;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+wl_status expv_check(wl_batch* bt, int b, int outer_dim) {
+  WL_CHECK(b >= 2 && b <= 16, WL_EINVAL, "batched diffusion: b must lie in [2, 16]");
+  WL_CHECK(outer_dim >= 1 && outer_dim * b <= EXP_MAXM, WL_EINVAL, "batched diffusion: outer_dim * b must be <= %d",
+           EXP_MAXM);
+  // the projected matrix and its exponential's work vectors live in one workgroup's LDS
+  WL_CHECK((size_t)5 * outer_dim * b * b * 8 <= 150 * 1024, WL_EINVAL,
+           "batched diffusion: outer_dim * b^2 too large for the on-chip exponential (5 outer_dim b^2 doubles <= "
+           "150 KiB)");
+  return WL_OK;
+}
+
+// Every buffer the enqueued work touches, sized for (b, K), plus the per-graph caps.
+wl_status expv_prepare(wl_batch* bt, BatchWork& wk, int b, int K) {
+  wl_ctx* ctx = bt->ctx;
+  const int ng = bt->ng;
+  const int64_t blk = bt->N * b;
+  Layout Ly{b, K, (int64_t)b * b};
+  const int64_t gs = Ly.total();
+  const int nunits = (int)bt->us.size() - 1;
+  WL_TRY(wk.basis.ensure((size_t)(K + 1) * blk * 4));
+  WL_TRY(wk.S.ensure((size_t)ng * gs * 8));
+  WL_TRY(wk.F.ensure((size_t)ng * K * b * b * 8));
+  WL_TRY(wk.tvals.ensure((size_t)ng * 8));
+  WL_TRY(wk.kcap.ensure((size_t)ng * 4));
+  WL_TRY(wk.partials.ensure((size_t)3 * nunits * 256 * sizeof(double)));
+  WL_TRY(wk.bufA.ensure((size_t)blk * 4));
+  WL_TRY(wk.bufB.ensure((size_t)blk * 4));
+  // blocks after which each graph's Krylov space is exhausted (ceil(n_g / b))
+  std::vector<int32_t> kcap(ng);
+  wk.cap_at.assign(K, 0);
+  for (int g = 0; g < ng; ++g) {
+    kcap[g] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(K, (bt->n[g] + b - 1) / b));
+    wk.cap_at[kcap[g] - 1] = 1;
+  }
+  WL_HIP(hipMemcpyAsync(wk.kcap.p, kcap.data(), (size_t)ng * 4, hipMemcpyHostToDevice, ctx->stream));
+  const size_t lds = (size_t)5 * K * b * b * sizeof(double);
+  WL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expT_batched),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
+// The device part of the batched diffusion: kernels only (no allocation, no host
+// synchronisation), so that it can be captured.  Times are read from wk.tvals.
+wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int K, float* Y) {
+  wl_ctx* ctx = bt->ctx;
+  const int ng = bt->ng;
+  const int64_t blk = bt->N * b;
+  Layout Ly{b, K, (int64_t)b * b};
+  const int64_t gs = Ly.total();
+  float* V = wk.basis.as<float>();
+  double* S = wk.S.as<double>();
+  const double tol = 1e-6;  // FP32 deflation threshold on relative squared norms (as the single-graph path)
+  // V_0 R_0 = U0 by CholQR2, per graph
+  WL_TRY(batch_gram(bt, wk, U0, 0, 1, U0, b, S + Ly.G(), gs));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, ng, gs));
+  WL_TRY(batch_update(bt, U0, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, V));
+  WL_TRY(batch_gram(bt, wk, V, 0, 1, V, b, S + Ly.G(), gs));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
+                     ng, gs));
+  WL_TRY(batch_update(bt, V, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, V));
+  for (int j = 0; j < K; ++j) {
+    float* Vj = V + (int64_t)j * blk;
+    float* Vn = V + (int64_t)(j + 1) * blk;
+    WL_TRY(batch_phi(bt, wk, Vj, Vn, b, true));  // W' = L V_j
+    if (j > 0) {
+      hipLaunchKernelGGL(k_dtranspose_batched, dim3(ng), dim3(64), 0, ctx->stream, b, S + Ly.B(j - 1), S + Ly.Bt(),
+                         gs);
+      WL_HIP(hipGetLastError());
+      WL_TRY(batch_update(bt, Vj - blk, 0, 1, b, S + Ly.Bt(), gs, Vn, 1.0, nullptr, -1.0, Vn));
+    }
+    const int nbv = j > 0 ? 2 : 1;
+    float* Vlo = j > 0 ? Vj - blk : Vj;
+    WL_TRY(batch_gram(bt, wk, Vlo, blk, nbv + 1, Vn, b, S + Ly.P(), gs));
+    WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(), S + Ly.Cc(),
+                                 ng, gs));
+    if (j + 1 == K) {  // residual coupling B_{K-1} = R1 of every graph
+      hipLaunchKernelGGL(k_dcopy_batched, dim3(ng), dim3(64), 0, ctx->stream, b * b, S + Ly.R1(), S + Ly.B(j), gs);
+      WL_HIP(hipGetLastError());
+      break;
+    }
+    WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+    WL_TRY(batch_gram(bt, wk, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
+    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                       S + Ly.B(j), ng, gs));
+    if (wk.cap_at[j]) {
+      hipLaunchKernelGGL(k_cap_blocks, dim3(ng), dim3(64), 0, ctx->stream, ng, wk.kcap.as<int32_t>(), j, S, gs,
+                         Ly.Ri2(), Ly.B(j), b * b);
+      WL_HIP(hipGetLastError());
+    }
+    WL_TRY(batch_update(bt, Vn, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+  }
+  // F_g = exp(-t_g T_g) E_1 R0_g on the device, then Y = V F per graph
+  const size_t lds = (size_t)5 * K * b * b * sizeof(double);
+  hipLaunchKernelGGL(k_expT_batched, dim3(ng), dim3(256), lds, ctx->stream, K, b, S, gs, Ly.A(0), Ly.B(0), Ly.R0(),
+                     wk.tvals.as<double>(), wk.F.as<double>(), (int64_t)K * b * b);
+  WL_HIP(hipGetLastError());
+  WL_TRY(batch_update(bt, V, blk, K, b, wk.F.as<double>(), (int64_t)K * b * b, nullptr, 0.0, nullptr, 1.0, Y));
+  return WL_OK;
+}
+
+// p_hat / p_err per graph (leave-one-out Nystrom, Alg. 1) from F and R0 alone
+// (Omega = V_0 R0, Y = V F: Omega^T Y = R0^T F_0, Y^T Y = F^T F).  Synchronises.
+wl_status return_probabilities(wl_batch* bt, BatchWork& wk, int b, int K, double* p_hat, double* p_err) {
+  wl_ctx* ctx = bt->ctx;
+  const int ng = bt->ng;
+  Layout Ly{b, K, (int64_t)b * b};
+  const int64_t gs = Ly.total();
+  if (p_hat || p_err) {
+    // Nystrom trace per graph from F_g and R0_g alone (Omega = V_0 R0, Y = V F).
+    std::vector<double> hF((size_t)ng * K * b * b), hS((size_t)ng * gs);
+    WL_HIP(hipMemcpyAsync(hF.data(), wk.F.p, hF.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipMemcpyAsync(hS.data(), wk.S.p, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    for (int g = 0; g < ng; ++g) {
+      const double* Fg = &hF[(size_t)g * K * b * b];
+      const double* R0 = &hS[(size_t)g * gs + Ly.R0()];
+      const int M = b, m = K * b;
+      std::vector<double> H((size_t)M * M, 0.0), Gm((size_t)M * M, 0.0);
+      for (int i = 0; i < M; ++i)
+        for (int jj = 0; jj < M; ++jj) {
+          double s1 = 0.0, s2 = 0.0;
+          for (int k = 0; k < M; ++k) s1 += R0[k * M + i] * Fg[k * M + jj];  // (R0^T F_0)
+          for (int r = 0; r < m; ++r) s2 += Fg[(size_t)r * M + i] * Fg[(size_t)r * M + jj];
+          H[(size_t)i * M + jj] = s1;
+          Gm[(size_t)i * M + jj] = s2;
+        }
+      // leave-one-out Nystrom (same formulas as wl_estimate)
+      std::vector<double> tj(M);
+      for (int j = 0; j < M; ++j) {
+        const int mm = M - 1;
+        std::vector<double> Sm((size_t)mm * mm), lam(mm), U((size_t)mm * mm);
+        std::vector<int> map;
+        for (int a = 0; a < M; ++a)
+          if (a != j) map.push_back(a);
+        for (int a = 0; a < mm; ++a)
+          for (int c = 0; c < mm; ++c)
+            Sm[(size_t)a * mm + c] =
+                0.5 * (H[(size_t)map[a] * M + map[c]] + H[(size_t)map[c] * M + map[a]]);
+        double trPG = 0.0, hPh = 0.0;
+        if (mm > 0 && dense_syev(mm, Sm.data(), lam.data(), U.data()) == 0) {
+          double lmax = 0.0;
+          for (double v : lam) lmax = std::max(lmax, v);
+          std::vector<double> P((size_t)mm * mm, 0.0);
+          for (int k = 0; k < mm; ++k) {
+            if (!(lam[k] > 1e-10 * lmax)) continue;
+            for (int a = 0; a < mm; ++a)
+              for (int c = 0; c < mm; ++c) P[(size_t)a * mm + c] += U[(size_t)a * mm + k] * U[(size_t)c * mm + k] / lam[k];
+          }
+          for (int a = 0; a < mm; ++a)
+            for (int c = 0; c < mm; ++c) {
+              trPG += P[(size_t)a * mm + c] * Gm[(size_t)map[c] * M + map[a]];
+              hPh += H[(size_t)j * M + map[a]] * P[(size_t)a * mm + c] * H[(size_t)j * M + map[c]];
+            }
+        }
+        tj[j] = trPG + H[(size_t)j * M + j] - hPh;
+      }
+      double mean = 0.0;
+      for (double v : tj) mean += v;
+      mean /= M;
+      double var = 0.0;
+      for (double v : tj) var += (v - mean) * (v - mean);
+      if (p_hat) p_hat[g] = mean / (double)bt->n[g];
+      if (p_err) p_err[g] = std::sqrt(var / (M - 1)) / std::sqrt((double)M) / (double)bt->n[g];
+    }
   }
   return WL_OK;
 }
@@ -526,7 +729,7 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
   s = bt->w.ensure(bt->N * 4);
   if (s == WL_OK) s = bt->ones.ensure(bt->N * 4);
   if (s == WL_OK) s = launch_fill<float>(ctx, bt->N, 1.0f, bt->ones.as<float>());
-  if (s == WL_OK) s = batch_phi(bt, bt->ones.as<float>(), bt->w.as<float>(), 1, false);
+  if (s == WL_OK) s = batch_phi(bt, bt->work, bt->ones.as<float>(), bt->w.as<float>(), 1, false);
   if (s == WL_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) s = WL_EDEVICE;
   if (s != WL_OK) return fail(s);
   ++ctx->refs;
@@ -536,6 +739,8 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
 
 wl_status wl_batch_destroy(wl_batch* bt) {
   if (!bt) return WL_OK;
+  WL_CHECK(bt->graphs == 0, WL_EINVAL, "wl_batch_destroy: %d captured graphs of this batch are still alive",
+           bt->graphs);
   wl_ctx* ctx = bt->ctx;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
@@ -566,136 +771,108 @@ wl_status wl_batch_apply_L(wl_batch* bt, const void* d_X, void* d_Y, int32_t b) 
   WL_CHECK(bt && d_X && d_Y && d_X != d_Y, WL_EINVAL, "wl_batch_apply_L: bad arguments");
   WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_batch_apply_L: b must lie in [1, 64]");
   (void)hipSetDevice(bt->ctx->device);
-  return batch_phi(bt, (const float*)d_X, (float*)d_Y, b, true);
+  return batch_phi(bt, bt->work, (const float*)d_X, (float*)d_Y, b, true);
 }
 
 wl_status wl_batch_expv(wl_batch* bt, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
                         double* p_hat, double* p_err) {
   WL_CHECK(bt && d_U0 && d_Y && t && d_U0 != d_Y, WL_EINVAL, "wl_batch_expv: bad arguments");
-  WL_CHECK(b >= 2 && b <= 16, WL_EINVAL, "wl_batch_expv: b must lie in [2, 16]");
-  WL_CHECK(outer_dim >= 1 && outer_dim * b <= EXP_MAXM, WL_EINVAL, "wl_batch_expv: outer_dim * b must be <= %d",
-           EXP_MAXM);
-  // the projected matrix, its exponential's work vectors live in one workgroup's LDS
-  WL_CHECK((size_t)5 * outer_dim * b * b * 8 <= 150 * 1024, WL_EINVAL,
-           "wl_batch_expv: outer_dim * b^2 too large for the on-chip exponential (5 outer_dim b^2 doubles <= 150 KiB)");
+  WL_TRY(expv_check(bt, b, outer_dim));
   for (int g = 0; g < bt->ng; ++g) WL_CHECK(std::isfinite(t[g]) && t[g] >= 0, WL_EINVAL, "wl_batch_expv: bad t");
   wl_ctx* ctx = bt->ctx;
   (void)hipSetDevice(ctx->device);
-  const int K = outer_dim, ng = bt->ng;
-  const int64_t N = bt->N, blk = N * b;
-  Layout Ly{b, K, (int64_t)b * b};
-  const int64_t gs = Ly.total();
-  WL_TRY(bt->basis.ensure((size_t)(K + 1) * blk * 4));
-  WL_TRY(bt->S.ensure((size_t)ng * gs * 8));
-  WL_TRY(bt->F.ensure((size_t)ng * K * b * b * 8));
-  WL_TRY(bt->tvals.ensure((size_t)ng * 8));
-  float* V = bt->basis.as<float>();
-  double* S = bt->S.as<double>();
-  const double tol = 1e-10;
-  const float* U0 = (const float*)d_U0;
-  // V_0 R_0 = U0 by CholQR2, per graph
-  WL_TRY(batch_gram(bt, U0, 0, 1, U0, b, S + Ly.G(), gs));
-  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, ng, gs));
-  WL_TRY(batch_update(bt, U0, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, V));
-  WL_TRY(batch_gram(bt, V, 0, 1, V, b, S + Ly.G(), gs));
-  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
-                     ng, gs));
-  WL_TRY(batch_update(bt, V, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, V));
-  for (int j = 0; j < K; ++j) {
-    float* Vj = V + (int64_t)j * blk;
-    float* Vn = V + (int64_t)(j + 1) * blk;
-    WL_TRY(batch_phi(bt, Vj, Vn, b, true));  // W' = L V_j
-    if (j > 0) {
-      hipLaunchKernelGGL(k_dtranspose_batched, dim3(ng), dim3(64), 0, ctx->stream, b, S + Ly.B(j - 1), S + Ly.Bt(),
-                         gs);
-      WL_HIP(hipGetLastError());
-      WL_TRY(batch_update(bt, Vj - blk, 0, 1, b, S + Ly.Bt(), gs, Vn, 1.0, nullptr, -1.0, Vn));
-    }
-    const int nbv = j > 0 ? 2 : 1;
-    float* Vlo = j > 0 ? Vj - blk : Vj;
-    WL_TRY(batch_gram(bt, Vlo, blk, nbv + 1, Vn, b, S + Ly.P(), gs));
-    WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(), S + Ly.Cc(),
-                                 ng, gs));
-    if (j + 1 == K) {  // residual coupling B_{K-1} = R1 of every graph
-      hipLaunchKernelGGL(k_dcopy_batched, dim3(ng), dim3(64), 0, ctx->stream, b * b, S + Ly.R1(), S + Ly.B(j), gs);
-      WL_HIP(hipGetLastError());
-      break;
-    }
-    WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
-    WL_TRY(batch_gram(bt, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
-    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j), ng, gs));
-    WL_TRY(batch_update(bt, Vn, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
-  }
-  // F_g = exp(-t_g T_g) E_1 R0_g on the device, then Y = V F per graph
-  WL_HIP(hipMemcpyAsync(bt->tvals.p, t, (size_t)ng * 8, hipMemcpyHostToDevice, ctx->stream));
-  const size_t lds = ((size_t)2 * K * b * b + 3 * (size_t)K * b * b) * sizeof(double);
-  WL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expT_batched),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_expT_batched, dim3(ng), dim3(256), lds, ctx->stream, K, b, S, gs, Ly.A(0), Ly.B(0), Ly.R0(),
-                     bt->tvals.as<double>(), bt->F.as<double>(), (int64_t)K * b * b);
-  WL_HIP(hipGetLastError());
-  WL_TRY(batch_update(bt, V, blk, K, b, bt->F.as<double>(), (int64_t)K * b * b, nullptr, 0.0, nullptr, 1.0,
-                      (float*)d_Y));
-  if (p_hat || p_err) {
-    // Nystrom trace per graph from F_g and R0_g alone (Omega = V_0 R0, Y = V F).
-    std::vector<double> hF((size_t)ng * K * b * b), hS((size_t)ng * gs);
-    WL_HIP(hipMemcpyAsync(hF.data(), bt->F.p, hF.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
-    WL_HIP(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
-    WL_HIP(hipStreamSynchronize(ctx->stream));
-    for (int g = 0; g < ng; ++g) {
-      const double* Fg = &hF[(size_t)g * K * b * b];
-      const double* R0 = &hS[(size_t)g * gs + Ly.R0()];
-      const int M = b, m = K * b;
-      std::vector<double> H((size_t)M * M, 0.0), Gm((size_t)M * M, 0.0);
-      for (int i = 0; i < M; ++i)
-        for (int jj = 0; jj < M; ++jj) {
-          double s1 = 0.0, s2 = 0.0;
-          for (int k = 0; k < M; ++k) s1 += R0[k * M + i] * Fg[k * M + jj];  // (R0^T F_0)
-          for (int r = 0; r < m; ++r) s2 += Fg[(size_t)r * M + i] * Fg[(size_t)r * M + jj];
-          H[(size_t)i * M + jj] = s1;
-          Gm[(size_t)i * M + jj] = s2;
-        }
-      // leave-one-out Nystrom (same formulas as wl_estimate)
-      std::vector<double> tj(M);
-      for (int j = 0; j < M; ++j) {
-        const int mm = M - 1;
-        std::vector<double> Sm((size_t)mm * mm), lam(mm), U((size_t)mm * mm);
-        std::vector<int> map;
-        for (int a = 0; a < M; ++a)
-          if (a != j) map.push_back(a);
-        for (int a = 0; a < mm; ++a)
-          for (int c = 0; c < mm; ++c)
-            Sm[(size_t)a * mm + c] =
-                0.5 * (H[(size_t)map[a] * M + map[c]] + H[(size_t)map[c] * M + map[a]]);
-        double trPG = 0.0, hPh = 0.0;
-        if (mm > 0 && dense_syev(mm, Sm.data(), lam.data(), U.data()) == 0) {
-          double lmax = 0.0;
-          for (double v : lam) lmax = std::max(lmax, v);
-          std::vector<double> P((size_t)mm * mm, 0.0);
-          for (int k = 0; k < mm; ++k) {
-            if (!(lam[k] > 1e-10 * lmax)) continue;
-            for (int a = 0; a < mm; ++a)
-              for (int c = 0; c < mm; ++c) P[(size_t)a * mm + c] += U[(size_t)a * mm + k] * U[(size_t)c * mm + k] / lam[k];
-          }
-          for (int a = 0; a < mm; ++a)
-            for (int c = 0; c < mm; ++c) {
-              trPG += P[(size_t)a * mm + c] * Gm[(size_t)map[c] * M + map[a]];
-              hPh += H[(size_t)j * M + map[a]] * P[(size_t)a * mm + c] * H[(size_t)j * M + map[c]];
-            }
-        }
-        tj[j] = trPG + H[(size_t)j * M + j] - hPh;
-      }
-      double mean = 0.0;
-      for (double v : tj) mean += v;
-      mean /= M;
-      double var = 0.0;
-      for (double v : tj) var += (v - mean) * (v - mean);
-      if (p_hat) p_hat[g] = mean / (double)bt->n[g];
-      if (p_err) p_err[g] = std::sqrt(var / (M - 1)) / std::sqrt((double)M) / (double)bt->n[g];
-    }
-  }
+  BatchWork& wk = bt->work;
+  WL_TRY(expv_prepare(bt, wk, b, outer_dim));
+  WL_HIP(hipMemcpyAsync(wk.tvals.p, t, (size_t)bt->ng * 8, hipMemcpyHostToDevice, ctx->stream));
+  WL_TRY(expv_enqueue(bt, wk, (const float*)d_U0, b, outer_dim, (float*)d_Y));
+  if (p_hat || p_err) WL_TRY(return_probabilities(bt, wk, b, outer_dim, p_hat, p_err));
   WL_HIP(hipStreamSynchronize(ctx->stream));
+  return WL_OK;
+}
+
+wl_status wl_batch_graph_create(wl_batch* bt, const void* d_U0, int32_t b, int32_t outer_dim, void* d_Y,
+                                wl_batch_graph** out) {
+  WL_CHECK(bt && d_U0 && d_Y && out && d_U0 != d_Y, WL_EINVAL, "wl_batch_graph_create: bad arguments");
+  *out = nullptr;
+  WL_TRY(expv_check(bt, b, outer_dim));
+  wl_ctx* ctx = bt->ctx;
+  (void)hipSetDevice(ctx->device);
+  auto* gr = new wl_batch_graph;
+  gr->bt = bt;
+  gr->b = b;
+  gr->K = outer_dim;
+  wl_status s = expv_prepare(bt, gr->work, b, outer_dim);
+  if (s != WL_OK) {
+    delete gr;
+    return s;
+  }
+  // capture on a private stream (the context's may be the legacy default stream, which
+  // cannot be captured); no allocation, synchronisation or profiling event inside
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    delete gr;
+    wl_set_error("wl_batch_graph_create: stream creation failed");
+    return WL_EDEVICE;
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  hipStream_t saved = ctx->stream;
+  const int saved_prof = ctx->profiling;
+  ctx->stream = cs;
+  ctx->profiling = 0;
+  hipGraph_t graph = nullptr;
+  s = WL_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    wl_set_error("wl_batch_graph_create: stream capture could not start");
+    s = WL_EDEVICE;
+  } else {
+    s = expv_enqueue(bt, gr->work, (const float*)d_U0, b, outer_dim, (float*)d_Y);
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (s == WL_OK && e != hipSuccess) {
+      wl_set_error("wl_batch_graph_create: capture failed: %s", hipGetErrorString(e));
+      s = WL_EDEVICE;
+    }
+  }
+  ctx->stream = saved;
+  ctx->profiling = saved_prof;
+  if (s == WL_OK && hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    wl_set_error("wl_batch_graph_create: graph instantiation failed");
+    s = WL_EDEVICE;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  if (s != WL_OK) {
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    delete gr;
+    return s;
+  }
+  ++bt->graphs;
+  *out = gr;
+  return WL_OK;
+}
+
+wl_status wl_batch_graph_launch(wl_batch_graph* gr, const double* t, double* p_hat, double* p_err) {
+  WL_CHECK(gr && t, WL_EINVAL, "wl_batch_graph_launch: bad arguments");
+  wl_batch* bt = gr->bt;
+  for (int g = 0; g < bt->ng; ++g)
+    WL_CHECK(std::isfinite(t[g]) && t[g] >= 0, WL_EINVAL, "wl_batch_graph_launch: bad t");
+  wl_ctx* ctx = bt->ctx;
+  (void)hipSetDevice(ctx->device);
+  WL_HIP(hipMemcpyAsync(gr->work.tvals.p, t, (size_t)bt->ng * 8, hipMemcpyHostToDevice, ctx->stream));
+  WL_HIP(hipGraphLaunch(gr->exec, ctx->stream));
+  if (p_hat || p_err) {
+    WL_TRY(return_probabilities(bt, gr->work, gr->b, gr->K, p_hat, p_err));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  return WL_OK;
+}
+
+wl_status wl_batch_graph_destroy(wl_batch_graph* gr) {
+  if (!gr) return WL_OK;
+  (void)hipSetDevice(gr->bt->ctx->device);
+  (void)hipStreamSynchronize(gr->bt->ctx->stream);
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  --gr->bt->graphs;
+  delete gr;
   return WL_OK;
 }
 

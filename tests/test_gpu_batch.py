@@ -84,3 +84,31 @@ def test_batch_expv_and_return_probability(setup):
         # the estimate is close to the true average return probability
         exact = laplacian.average_return_probability(L, t)
         assert abs(p_hat[i] - exact) < 6 * max(p_err[i], 1e-3), (i, p_hat[i], exact, p_err[i])
+
+
+def test_batch_graph_replays_match_eager(setup, lib):
+    """The captured diffusion replays with new U0 contents and times; every replay, with
+    eager batched work between replays, equals the eager call bit for bit (same kernels
+    in the same order on their own scratch)."""
+    batch, phis, ts = setup
+    b = 8
+    U0 = batch.pack([torch.tensor(philox.gaussian(ph.shape[0], b, 200 + i), dtype=torch.float32, device="cuda")
+                     for i, ph in enumerate(phis)])
+    Y = torch.empty_like(U0)
+    gr = batch.graph(U0, Y, outer_dim=30)
+    assert lib.load().wl_batch_destroy(batch.handle) == lib._lib.WL_EINVAL  # graph still alive
+    Ye = torch.empty_like(U0)
+    for r in range(3):
+        print(f"[gpu] batch graph replay {r}", flush=True)
+        fresh = batch.pack([torch.tensor(philox.gaussian(ph.shape[0], b, 300 + 10 * r + i), dtype=torch.float32,
+                                         device="cuda") for i, ph in enumerate(phis)])
+        U0.copy_(fresh)
+        tr = [t * (1.0 + 0.5 * r) for t in ts]
+        _, ph_e, pe_e = batch.expv(U0, tr, outer_dim=30, out=Ye)
+        torch.cuda.synchronize()
+        ph_g, pe_g = gr.launch(tr, want_trace=True)
+        torch.cuda.synchronize()
+        assert torch.equal(Y, Ye), r
+        np.testing.assert_array_equal(ph_g, ph_e)
+        np.testing.assert_array_equal(pe_g, pe_e)
+    gr.close()

@@ -315,6 +315,34 @@ def test_edgeless_and_tiny_graphs(ctx, wl):
         np.testing.assert_allclose(w, genfun.phi(A, mu, kind, param).sum(1), rtol=1e-10)
 
 
+@pytest.mark.parametrize("n,m,b", [(13, None, 8), (200, 900, 8), (60, 200, 16)])
+def test_fp32_krylov_space_exhausted(ctx, wl, n, m, b):
+    """FP32 graphs smaller than the Krylov dimension (n < K b, n not a multiple of b):
+    the last block is partly rounding noise and must be deflated, not normalised.
+    apply_L (resolvent, Lanczos) 2e-5 and diffusion 1e-4 against the dense oracle."""
+    print(f"[gpu] exhausted Krylov space n={n} b={b}", flush=True)
+    if m is None:
+        rp, ci = synth.toy_g58()
+    else:
+        rp, ci = synth.erdos_renyi_gnm(n, m, 12)
+    A = walks.adjacency(n, rp, ci)
+    g = wl.Graph(ctx, rp, ci, validate=True)
+    lam = np.linalg.eigvalsh(A)[-1]
+    X = synth.gaussian_block(n, b, 3).astype(np.float32).astype(np.float64)
+    for mu, kind, param in [(0.5, "res", 0.5 / lam), (0.25, "exp", 1.0 / lam)]:
+        ph = genfun.phi(A, mu, kind, param)
+        op = wl.Operator(g, mu, kind, param, dtype=torch.float32, krylov_dim=30)
+        Y = host(op.apply_L(dev(X, torch.float32)))
+        ref = laplacian.apply_laplacian(ph, X)
+        scale = np.linalg.norm(ph.sum(1)[:, None] * X) + np.linalg.norm(ph @ X)
+        assert np.linalg.norm(Y - ref) < 2e-5 * scale, (mu, kind)
+        L = laplacian.walk_laplacian(ph)
+        outs, _ = op.expv(dev(X, torch.float32), [0.1, 1.0, 10.0], outer_dim=30)
+        for t, o in zip([0.1, 1.0, 10.0], outs):
+            (r,) = laplacian.expv(L, X, [t])
+            assert np.linalg.norm(host(o) - r) < 1e-4 * np.linalg.norm(r), (mu, kind, t)
+
+
 def test_fig1_stationary_from_gpu_fdeg(ctx, wl):
     """The printed Fig. 1 bars follow from the GPU walk degree: pi = w / sum(w)."""
     from test_oracle_genfun import load_fig1
