@@ -128,8 +128,10 @@ wl_status wl_ctx_destroy(wl_ctx* ctx);
 /* Opt-in live timing of kernel classes on the context stream (HIP events around every
  * launch of the class) with the algorithmic bytes each launch must move (CSR once,
  * the gathered block once, every row-aligned input / output block once).  Turning
- * profiling on or off clears the statistics.  Classes: 0 fused recurrence step
- * (degree >= 2), 1 block Lanczos operator product, 2 other sparse products.        */
+ * profiling on or off clears the statistics.  Classes: 0 fused recurrence step of one
+ * operator (degree >= 2, b >= 4), 1 block Lanczos operator product (b >= 4), 2 other
+ * sparse products, 3 side-by-side operator step (wl_multi_*, width >= 32).  Batched
+ * steps count as class 0.                                                          */
 wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on);
 wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launches, double* total_ms,
                               double* alg_bytes);
@@ -257,6 +259,27 @@ wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, i
 wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t seed,
                       int32_t law, int32_t estimator, const void* d_cv, int32_t outer_dim,
                       void* d_diag, double* trace, double* trace_err);
+
+/* ---------------------------------------------------------------- several operators
+ * Operators of one graph evaluated together: their truncated series (eq. qrec; every
+ * operator must use WL_M_RECURRENCE, i.e. the exponential or a resolvent with an
+ * explicit degree, and all share graph and precision) run side by side on one wide
+ * block, operator g on columns [g b, (g + 1) b), with one sparse product per step for
+ * all of them and each group's weights of that step from a table (operators with a
+ * lower degree stop contributing after their last step).  Results equal those of the
+ * single operators up to the summation order of the sparse products.
+ * wl_multi_create: 1 <= nops <= 64 operators; the handle keeps the graph alive (not
+ * the operators, whose descriptors it copies).
+ * wl_multi_apply: d_X n x b (the same block for every operator), d_Y n x (nops b)
+ * row-major, laplacian != 0: L_g X in group g, else phi_g X.  nops b <= 4096.  Wide
+ * rows gather whole cache lines: nops b = 32 or 64 FP32 values per row is where the
+ * sharing pays most.
+ * wl_multi_fdeg: d_W n x nops, column g = phi_g 1.                                   */
+typedef struct wl_multi wl_multi;
+wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out);
+wl_status wl_multi_apply(wl_multi* multi, const void* d_X, int32_t b, void* d_Y, int32_t laplacian);
+wl_status wl_multi_fdeg(wl_multi* multi, void* d_W);
+wl_status wl_multi_destroy(wl_multi* multi);
 
 /* ---------------------------------------------------------------- batches of graphs
  * Many graphs with their own walk variant and weights, evaluated together: the

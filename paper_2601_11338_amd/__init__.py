@@ -414,6 +414,58 @@ class MLP:
             pass
 
 
+class Multi:
+    """Several truncated-series operators of one graph evaluated side by side."""
+
+    def __init__(self, ops):
+        self.ops = list(ops)
+        self.graph = self.ops[0].graph
+        self.dtype = self.ops[0].dtype
+        handles = (C.c_void_p * len(self.ops))(*[o.handle.value for o in self.ops])
+        self.handle = C.c_void_p()
+        check(load().wl_multi_create(handles, len(self.ops), C.byref(self.handle)))
+
+    def _run(self, X, out, laplacian):
+        torch = _torch()
+        X = X.to(self.dtype).contiguous()
+        if X.dim() == 1:
+            X = X.view(-1, 1)
+        _need(X, "X", self.dtype, (self.graph.n, None))
+        shape = (self.graph.n, X.shape[1] * len(self.ops))
+        out = torch.empty(shape, dtype=self.dtype, device=X.device) if out is None else out
+        _need(out, "out", self.dtype, shape)
+        check(load().wl_multi_apply(self.handle, _ptr(X), X.shape[1], _ptr(out), 1 if laplacian else 0))
+        return out
+
+    def apply_phi(self, X, out=None):
+        """n x (nops b): group g = phi_g X."""
+        return self._run(X, out, False)
+
+    def apply_L(self, X, out=None):
+        """n x (nops b): group g = L_g X."""
+        return self._run(X, out, True)
+
+    def fdeg(self, out=None):
+        """n x nops: column g = phi_g 1."""
+        torch = _torch()
+        shape = (self.graph.n, len(self.ops))
+        out = torch.empty(shape, dtype=self.dtype, device=self.graph.ctx.torch_device) if out is None else out
+        _need(out, "out", self.dtype, shape)
+        check(load().wl_multi_fdeg(self.handle, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            load().wl_multi_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Many graphs evaluated together (one launch per Krylov step for the whole batch)."""
 

@@ -39,17 +39,6 @@ void wl_set_error(const char* fmt, ...) {
 
 namespace {
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
 
 template <typename T>
 constexpr int prec_of() {
@@ -465,7 +454,7 @@ wl_status apply_lanczos_op(wl_graph* g, const LanczosOp<T>& L, const T* V, T* W,
       ep.C = Bprev;
       ep.transC = 1;
     }
-    ep.kclass = WL_KC_LANCZOS_OP;
+    ep.kclass = b >= 4 ? WL_KC_LANCZOS_OP : WL_KC_OTHER_SPMM;
     return launch_spmm<T>(g, V, W, b, ep, shape_for(g, prec_of<T>(), b));
   }
   // walk Laplacian: W = w (.) V - phi V, then the three-term subtraction

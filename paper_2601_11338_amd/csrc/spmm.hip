@@ -131,6 +131,14 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
     csc = c[3];
     fin = fin && c[4] != 0.0;
   }
+  if (ep.ctab) {  // the VW columns of this lane lie in one operator's group
+    const double* c = ep.ctab + 5 * (col / ep.cgw);
+    ca = c[0];
+    cb0 = c[1];
+    cb1 = c[2];
+    csc = c[3];
+    fin = fin && c[4] != 0.0;
+  }
   T y[VW];
   const T a = (T)ca;
 #pragma unroll
@@ -169,7 +177,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
 #pragma unroll
     for (int i = 0; i < VW; ++i) s.v[i] = s0 * s.v[i] + sc * y[i];
     if (fin) {
-      const T wr = ep.wv[r];
+      const T wr = ep.wld ? ep.wv[r * (int64_t)ep.wld + col / ep.cgw] : ep.wv[r];
       Frag<T, VW> xw = MASK ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
 #pragma unroll
       for (int i = 0; i < VW; ++i) s.v[i] = wr * xw.v[i] - s.v[i];
@@ -350,8 +358,8 @@ template <typename T>
 wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh) {
   if (g->n == 0) return WL_OK;
   constexpr int VW = vec_width<T>();
-  const bool vec_ok = (b % VW == 0) && aligned16(X) && aligned16(Y) && aligned16(ep.Z) && aligned16(ep.Sin) &&
-                      aligned16(ep.Sout) && aligned16(ep.Xw);
+  const bool vec_ok = (b % VW == 0) && (!ep.ctab || ep.cgw % VW == 0) && aligned16(X) && aligned16(Y) &&
+                      aligned16(ep.Z) && aligned16(ep.Sin) && aligned16(ep.Sout) && aligned16(ep.Xw);
   if (vec_ok) {
     const int lanes = b / VW;  // lanes needed for the whole row segment
     if (lanes == 1) return run_g<T, VW, 1, false>(g, X, Y, b, ep, sh.G, sh.long_thr);

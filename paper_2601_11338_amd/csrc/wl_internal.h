@@ -38,6 +38,19 @@ void wl_set_error(const char* fmt, ...);
     if (s_ != WL_OK) return s_;   \
   } while (0)
 
+// Makes dev current for a scope and restores the previous device.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
 // ------------------------------------------------------------------ device buffer
 struct DevBuf {
   void* p = nullptr;
@@ -81,7 +94,9 @@ struct SpmmShape {
 
 // Live timing of kernel classes (opt-in): HIP events recorded around each launch
 // on the context stream, algorithmic bytes counted per launch.
-enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_COUNT = 3 };
+// Timing classes of sparse products: single-operator series steps (b >= 4), Lanczos
+// operator products (b >= 4), side-by-side operator steps (width >= 32), the rest.
+enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_MULTI = 3, WL_KC_COUNT = 4 };
 struct KernelStats {
   int64_t launches = 0;
   double bytes = 0.0;
@@ -164,6 +179,12 @@ struct EpiArgs {
   // applies the walk-Laplacian finish).  Rows of graphs with a = sc = 0 are skipped.
   const int32_t* gid = nullptr;
   const double* gtab = nullptr;
+  // Several operators side by side: column c belongs to operator c / cgw, whose five
+  // coefficients of this launch are ctab[5 (c / cgw) ...]; the finish weight is then
+  // wv[r * wld + c / cgw] (wv holds one walk-degree column per operator).
+  const double* ctab = nullptr;
+  int cgw = 0;
+  int wld = 0;
 };
 
 template <typename T>

@@ -1,0 +1,96 @@
+"""Several truncated-series operators of one graph evaluated side by side (one sparse
+product per step for all of them) against the single operators and the dense oracle.
+FP64: 1e-8 against the oracle, 1e-12 against the single operators (only the summation
+order of the sparse products differs); FP32: 2e-5 / 1e-6."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import genfun, laplacian, sparse, walks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def test_multi_fp64_matches_single_and_dense(ctx, lib):
+    print("[gpu] multi fp64", flush=True)
+    n = 400
+    rp, ci = synth.erdos_renyi_gnm(n, 1600, 21)
+    A = walks.adjacency(n, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    g = lib.Graph(ctx, rp, ci)
+    specs = [(0.0, "exp", 1.0 / lam, 0), (0.5, "res", 0.5 / lam, 45), (1.0, "exp", 1.0 / lam, 0),
+             (0.25, "exp", 0.5 / lam, 0)]
+    ops = [lib.Operator(g, mu, f, p, dtype=torch.float64, krylov_dim=K, method="recurrence")
+           for mu, f, p, K in specs]
+    assert len({op.info()[0] for op in ops}) > 1  # different degrees in one pass
+    multi = lib.Multi(ops)
+    b = 3
+    X = synth.gaussian_block(n, b, 5)
+    Xd = dev(X, torch.float64)
+    W = host(multi.fdeg())
+    PX = host(multi.apply_phi(Xd))
+    LX = host(multi.apply_L(Xd))
+    for i, (op, (mu, f, p, K)) in enumerate(zip(ops, specs)):
+        ph = genfun.phi(A, mu, f, p)
+        w = ph.sum(1)
+        cols = slice(i * b, (i + 1) * b)
+        np.testing.assert_allclose(W[:, i], host(op.fdeg()), rtol=1e-12)
+        assert np.linalg.norm(W[:, i] - w) < 1e-8 * np.linalg.norm(w)
+        assert np.linalg.norm(PX[:, cols] - host(op.apply_phi(Xd))) < 1e-12 * np.linalg.norm(PX[:, cols])
+        assert np.linalg.norm(PX[:, cols] - ph @ X) < 1e-8 * np.linalg.norm(ph @ X)
+        scale = np.linalg.norm(w[:, None] * X) + np.linalg.norm(ph @ X)
+        assert np.linalg.norm(LX[:, cols] - host(op.apply_L(Xd))) < 1e-12 * scale
+        assert np.linalg.norm(LX[:, cols] - laplacian.apply_laplacian(ph, X)) < 1e-8 * scale
+
+
+def test_multi_fp32_four_operators_block16(ctx, lib):
+    """Four operators x 16 columns: rows of 64 FP32 values, two whole cache lines."""
+    print("[gpu] multi fp32 BA20k", flush=True)
+    n = 20000
+    rp, ci = synth.barabasi_albert(n, 5, 11)
+    As = sparse.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = g.lambda_max()
+    mus = [0.0, 0.25, 0.5, 1.0]
+    ops = [lib.Operator(g, mu, "exp", 1.0 / lam, dtype=torch.float32, krylov_dim=30) for mu in mus]
+    multi = lib.Multi(ops)
+    X = synth.rademacher_block(n, 16, 3)
+    Xd = dev(X, torch.float32)
+    LX = host(multi.apply_L(Xd))
+    for i, (mu, op) in enumerate(zip(mus, ops)):
+        cols = slice(16 * i, 16 * (i + 1))
+        single = host(op.apply_L(Xd))
+        wr = sparse.fdeg(As, mu, "exp", 1.0 / lam)
+        pr = sparse.phi_apply(As, mu, "exp", 1.0 / lam, X)
+        scale = np.linalg.norm(wr[:, None] * X) + np.linalg.norm(pr)
+        assert np.linalg.norm(LX[:, cols] - single) < 1e-6 * scale
+        assert np.linalg.norm(LX[:, cols] - (wr[:, None] * X - pr)) < 2e-5 * scale
+
+
+def test_multi_rejects_lanczos_and_mixed_graphs(ctx, lib):
+    n = 300
+    rp, ci = synth.erdos_renyi_gnm(n, 900, 2)
+    g1, g2 = lib.Graph(ctx, rp, ci), lib.Graph(ctx, rp, ci)
+    lam = g1.lambda_max()
+    lan = lib.Operator(g1, 0.0, "res", 0.5 / lam, dtype=torch.float64, krylov_dim=20)  # Lanczos
+    rec1 = lib.Operator(g1, 0.5, "exp", 1.0 / lam, dtype=torch.float64)
+    rec2 = lib.Operator(g2, 0.5, "exp", 1.0 / lam, dtype=torch.float64)
+    with pytest.raises(lib.WLError, match="UNSUPPORTED"):
+        lib.Multi([rec1, lan])
+    with pytest.raises(lib.WLError, match="EINVAL"):
+        lib.Multi([rec1, rec2])
