@@ -124,22 +124,26 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // X^T Y for FP32 blocks with B = 16 NT columns on the matrix cores, accumulated in
 // FP64 (v_mfma_f64_16x16x4f64: D += A B with A 16x4, B 4x16).  For four consecutive
 // rows r..r+3 lane l supplies A[i][kk] = X[r + kk][i] and B[kk][j] = Y[r + kk][j] with
-// kk = l / 16 and i = j = l % 16: one coalesced 256-byte load per operand tile.
-// Each wave writes its own partial (16 NT x 16 NT); D[i][j] sits in lane l, element v
-// with i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose
-// inputs make every output entry identify its (i, j)).
+// kk = l / 16 and i = j = l % 16.  D[i][j] sits in lane l, element v with
+// i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose inputs
+// make every output entry identify its (i, j)).
 // NB X blocks (block k at X + k sX) share one pass over Y (grid y walks chunks of NB
-// blocks).  When every operand row is exactly B = 16 NT floats (aligned), a wave
-// loads 16-row tiles with 16-byte coalesced loads, stages them in its own LDS slice
-// and reads the operands back in the layout above; otherwise it falls back to one
-// element per lane straight from memory.
+// blocks).  Every wave walks 16-row chunks.  When every operand row is exactly
+// B = 16 NT floats (aligned), a chunk is loaded with 16-byte coalesced loads into
+// registers one chunk ahead (the loads of chunk i + 1 are in flight while chunk i,
+// staged in the wave's own LDS slice, feeds the matrix cores); otherwise one element
+// per lane comes straight from memory.  The four waves' accumulators are summed in
+// LDS in a fixed order and each workgroup writes one partial (deterministic).
 template <int NT, int NB>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
                                                    int nblk, const float* __restrict__ Y, int ldy, int bx, int by,
                                                    double* __restrict__ partials) {
   constexpr int B = 16 * NT;
   constexpr int TILE = 16 * B;  // floats per 16-row tile of one operand
-  __shared__ float sm[4][NB + 1][TILE];
+  constexpr size_t TILE_BYTES = (size_t)4 * (NB + 1) * TILE * sizeof(float);
+  constexpr size_t RED_BYTES = (size_t)NB * B * B * sizeof(double);
+  __shared__ __align__(16) unsigned char smem[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
+  float(*sm)[NB + 1][TILE] = reinterpret_cast<float(*)[NB + 1][TILE]>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kb0 = blockIdx.y * NB;
   const int nb = (nblk - kb0) < NB ? (nblk - kb0) : NB;
@@ -155,26 +159,36 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
                       ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
   const int64_t nchunks = (n + 15) / 16;
   const int64_t cstride = (int64_t)gridDim.x * 4;
-  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
-    const int64_t r0 = ch * 16;
-    if (packed) {
-      // 16 rows x B floats = 4 B float4 per operand, NT per lane
+  if (packed) {
+    // 16 rows x B floats = 4 B float4 per operand, NT per lane
+    float4 ry[NT], rx[NB][NT];
+    auto fetch = [&](int64_t ch) {
+      const int64_t r0 = ch * 16;
 #pragma unroll
       for (int s = 0; s < NT; ++s) {
-        const int f = s * 64 + lane;       // float4 index inside the tile
+        const int f = s * 64 + lane;  // float4 index inside the tile
         const int64_t row = r0 + (f * 4) / B;
         const bool rok = row < n;
         const int64_t off = r0 * B + (int64_t)f * 4;
-        float4 y4 = rok ? *reinterpret_cast<const float4*>(Y + off) : make_float4(0.f, 0.f, 0.f, 0.f);
-        *reinterpret_cast<float4*>(&sm[wave][NB][f * 4]) = y4;
+        ry[s] = rok ? *reinterpret_cast<const float4*>(Y + off) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          float4 x4 = (rok && q < nb) ? *reinterpret_cast<const float4*>(X + (int64_t)(kb0 + q) * sX + off)
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-          *reinterpret_cast<float4*>(&sm[wave][q][f * 4]) = x4;
-        }
+        for (int q = 0; q < NB; ++q)
+          rx[q][s] = (rok && q < nb) ? *reinterpret_cast<const float4*>(X + (int64_t)(kb0 + q) * sX + off)
+                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    int64_t ch = (int64_t)blockIdx.x * 4 + wave;
+    if (ch < nchunks) fetch(ch);
+    for (; ch < nchunks; ch += cstride) {
+#pragma unroll
+      for (int s = 0; s < NT; ++s) {
+        const int f = s * 64 + lane;
+        *reinterpret_cast<float4*>(&sm[wave][NB][f * 4]) = ry[s];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) *reinterpret_cast<float4*>(&sm[wave][q][f * 4]) = rx[q][s];
       }
       __builtin_amdgcn_wave_barrier();
+      if (ch + cstride < nchunks) fetch(ch + cstride);  // next chunk in flight during the products
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int rl = 4 * m + rsub;
@@ -192,7 +206,10 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
           }
       }
       __builtin_amdgcn_wave_barrier();
-    } else {
+    }
+  } else {
+    for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
+      const int64_t r0 = ch * 16;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int64_t row = r0 + 4 * m + rsub;
@@ -217,17 +234,29 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
       }
     }
   }
-  const int nparts = gridDim.x * 4;
+  // waves 0..3 add their accumulators into LDS in turn (the tiles are no longer needed)
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    if (q >= nb) break;
-    double* out = partials + ((int64_t)(kb0 + q) * nparts + (int64_t)blockIdx.x * 4 + wave) * (B * B);
+      for (int q = 0; q < NB; ++q)
 #pragma unroll
-    for (int I = 0; I < NT; ++I)
+        for (int I = 0; I < NT; ++I)
 #pragma unroll
-      for (int J = 0; J < NT; ++J)
+          for (int J = 0; J < NT; ++J)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[(16 * I + 4 * v + rsub) * B + 16 * J + c] = acc[q][I][J][v];
+            for (int v = 0; v < 4; ++v) {
+              const int idx = q * B * B + (16 * I + 4 * v + rsub) * B + 16 * J + c;
+              red[idx] = (w == 0 ? 0.0 : red[idx]) + acc[q][I][J][v];
+            }
+    }
+    __syncthreads();
+  }
+  const int nparts = gridDim.x;
+  for (int e = threadIdx.x; e < nb * B * B; e += 256) {
+    const int q = e / (B * B);
+    partials[((int64_t)(kb0 + q) * nparts + blockIdx.x) * (B * B) + (e - q * B * B)] = red[e];
   }
 }
 
@@ -813,9 +842,9 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
       constexpr int NT = B / 16;
       const int64_t nchunks = (n + 15) / 16;
       int64_t blocks = (nchunks + 15) / 16;
-      if (blocks > 512) blocks = 512;
+      if (blocks > 1024) blocks = 1024;
       if (blocks < 1) blocks = 1;
-      const int nparts = (int)blocks * 4;
+      const int nparts = (int)blocks;  // one partial per workgroup
       WL_TRY(ctx->partials.ensure((size_t)nparts * nblk * E * sizeof(double)));
       double* pp = ctx->partials.as<double>();
       const float* Xf = (const float*)X;
