@@ -263,40 +263,60 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
 // Out = (wv ? wv[r] : alpha) Yin + beta sum_k X_k C_k for FP32 blocks whose rows are
 // exactly B floats (B = 4 LPR): LPR lanes hold one row as float4 fragments (coalesced
 // 16-byte accesses across the wave); the row is shared inside its lane group with
-// shuffles and C_k is broadcast from LDS.
+// shuffles.  The C_k are staged in LDS (converted to float) once per workgroup when
+// they fit (kc blocks at a time otherwise), and the X_k fragments of up to four
+// blocks are loaded together so their latencies overlap.
 template <int B>
-__global__ __launch_bounds__(256) void k_update_f4(int64_t n, const float* X, int64_t sX, int nblk,
+__global__ __launch_bounds__(256) void k_update_f4(int64_t n, const float* X, int64_t sX, int nblk, int kc,
                                                    const double* __restrict__ C, const float* Yin, double alpha,
                                                    const float* __restrict__ wv, double beta, float* Out) {
   constexpr int LPR = B / 4;
   constexpr int RPT = 256 / LPR;  // rows per tile
-  __shared__ float sC[B * B];
+  extern __shared__ float sC[];   // kc blocks of B x B
   const int sub = threadIdx.x % LPR;
   const int rloc = threadIdx.x / LPR;
   const float tb = (float)beta;
+  const bool once = kc >= nblk;
+  if (once) {
+    for (int e = threadIdx.x; e < nblk * B * B; e += 256) sC[e] = (float)C[e];
+    __syncthreads();
+  }
   const int64_t ntiles = (n + RPT - 1) / RPT;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t row = t * RPT + rloc;
     const bool ok = row < n;
     float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < nblk; ++k) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < B * B; e += 256) sC[e] = (float)C[(int64_t)k * B * B + e];
-      __syncthreads();
-      float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok) xv = *reinterpret_cast<const float4*>(X + (int64_t)k * sX + row * B + 4 * sub);
+    for (int c0 = 0; c0 < nblk; c0 += kc) {
+      const int c1 = c0 + kc < nblk ? c0 + kc : nblk;
+      if (!once) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < (c1 - c0) * B * B; e += 256) sC[e] = (float)C[(int64_t)c0 * B * B + e];
+        __syncthreads();
+      }
+      for (int k0 = c0; k0 < c1; k0 += 4) {
+        float4 xv[4];
 #pragma unroll
-      for (int src = 0; src < LPR; ++src) {
-        float v[4];
-        v[0] = __shfl(xv.x, src, LPR);
-        v[1] = __shfl(xv.y, src, LPR);
-        v[2] = __shfl(xv.z, src, LPR);
-        v[3] = __shfl(xv.w, src, LPR);
+        for (int u = 0; u < 4; ++u)
+          xv[u] = (ok && k0 + u < c1) ? *reinterpret_cast<const float4*>(X + (int64_t)(k0 + u) * sX + row * B + 4 * sub)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float* crow = sC + (4 * src + q) * B + 4 * sub;
+        for (int u = 0; u < 4; ++u) {
+          if (k0 + u >= c1) break;
+          const float* Ck = sC + (int64_t)(k0 + u - c0) * B * B;
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) acc[cc] += v[q] * crow[cc];
+          for (int src = 0; src < LPR; ++src) {
+            float v[4];
+            v[0] = __shfl(xv[u].x, src, LPR);
+            v[1] = __shfl(xv[u].y, src, LPR);
+            v[2] = __shfl(xv[u].z, src, LPR);
+            v[3] = __shfl(xv[u].w, src, LPR);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float* crow = Ck + (4 * src + q) * B + 4 * sub;
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) acc[cc] += v[q] * crow[cc];
+            }
+          }
         }
       }
     }
@@ -903,8 +923,11 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
       constexpr int RPT = 256 / (B / 4);
       int64_t ntiles = (n + RPT - 1) / RPT;
       const int grid = (int)(ntiles < 1 ? 1 : (ntiles > 8192 ? 8192 : ntiles));
-      hipLaunchKernelGGL((k_update_f4<B>), dim3(grid), dim3(256), 0, ctx->stream, n, (const float*)X, sX, nblk, C,
-                         (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out);
+      // C blocks staged per workgroup: all of them if they fit in 48 KB
+      const int kc = std::max(1, std::min(nblk, 12288 / (B * B)));
+      const size_t lds = (size_t)kc * B * B * sizeof(float);
+      hipLaunchKernelGGL((k_update_f4<B>), dim3(grid), dim3(256), lds, ctx->stream, n, (const float*)X, sX, nblk,
+                         kc, C, (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out);
       WL_HIP(hipGetLastError());
       if (gram_out) return gram_B<B>(ctx, n, Out, true, B, 0, 1, Out, B, B, B, gram_out);
       return WL_OK;
