@@ -47,15 +47,22 @@ constexpr int prec_of() {
 
 bool is_finite(double x) { return std::isfinite(x); }
 
-// Deflation thresholds on squared norms (Gram pivots), relative to the block's norm
-// before projection.  The projected Gram is formed by Pythagoras from inner products
-// of stored vectors; with FP32 storage the basis is orthonormal only to ~1e-7, so
-// pivots below ~1e-7 of the reference are rounding noise (a direction whose residual
-// is below ~1e-3 of the block cannot be resolved): such columns are dropped rather
-// than normalised into spurious basis vectors.
+// Deflation thresholds on squared norms (Gram pivots) of the first CholQR pass,
+// relative to the block's norm before projection.  The projected Gram is formed by
+// Pythagoras from inner products of stored vectors, so small pivots are unreliable
+// (the basis is orthonormal only to the storage precision); they are kept here and
+// judged after the second pass (post_tol), which measures them directly.
 template <typename T>
 double defl_tol() {
-  return sizeof(T) == 4 ? 1e-6 : 1e-24;
+  return sizeof(T) == 4 ? 1e-10 : 1e-24;
+}
+
+// After the second CholQR pass the combined factor gives the true norm of every new
+// component; components below this fraction of the block's scale before projection
+// are rounding noise of the stored basis (~1e-7 FP32, ~1e-16 FP64) and are dropped.
+template <typename T>
+double post_tol() {
+  return sizeof(T) == 4 ? 1e-5 : 1e-10;
 }
 
 int next_pow2(int x) {
@@ -480,8 +487,9 @@ struct SmallLayout {
   size_t R2() const { return (size_t)(2 * K + 4) * bb; }
   size_t Ri2() const { return (size_t)(2 * K + 5) * bb; }
   size_t Cc() const { return (size_t)(2 * K + 6) * bb; }        // 3 blocks
-  size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+1) blocks
-  size_t total() const { return (size_t)(3 * K + 11) * bb; }
+  size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+2) blocks
+  size_t Ref() const { return (size_t)(3 * K + 11) * bb; }      // one double: reference scale
+  size_t total() const { return (size_t)(3 * K + 12) * bb; }
 };
 
 // Runs K block Lanczos steps from X (n x b).  basis must hold (K+1) blocks, Wb one
@@ -499,12 +507,14 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
   WL_TRY(small.ensure(Ly.total() * sizeof(double)));
   double* S = small.as<double>();
   const double tol = defl_tol<T>();
+  const double ptol = post_tol<T>();
   // V_0 R0 = X by CholQR2
   WL_TRY(launch_gram<T>(ctx, n, X, b, 0, 1, X, b, S + Ly.G()));
-  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, 1, 0,
+                     S + Ly.Ref()));
   WL_TRY(launch_update<T>(ctx, n, X, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, basis, b, S + Ly.G()));
   WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                     S + Ly.R0()));
+                     S + Ly.R0(), 1, 0, S + Ly.Ref(), ptol));
   WL_TRY(launch_update<T>(ctx, n, basis, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, basis, b, nullptr));
   if (ring) reorth = 0;
   auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
@@ -521,7 +531,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
       const T* Vlo = j > 0 ? Vp : Vj;
       WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nbv + 1, Vn, b, S + Ly.P()));
       WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(),
-                                   S + Ly.Cc()));
+                                   S + Ly.Cc(), 1, 0, S + Ly.Ref()));
       if (j + 1 == K) {
         WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
         break;
@@ -529,7 +539,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
       WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,
                               S + Ly.G()));
       WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                         S + Ly.B(j)));
+                         S + Ly.B(j), 1, 0, S + Ly.Ref(), ptol));
       WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
     }
   }
@@ -552,7 +562,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
     }
     // W = V_{j+1} B_j by CholQR2
     WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, S + Ly.A(j), j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.R1(),
-                       S + Ly.Ri1(), nullptr, nullptr));
+                       S + Ly.Ri1(), nullptr, nullptr, 1, 0, S + Ly.Ref()));
     if (j + 1 == K) {
       WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
       break;
@@ -560,7 +570,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
     T* Vn = slot(j + 1);
     WL_TRY(launch_update<T>(ctx, n, Wb, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G()));
     WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j)));
+                       S + Ly.B(j), 1, 0, S + Ly.Ref(), ptol));
     WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
   }
   hA.assign((size_t)K * b * b, 0.0);

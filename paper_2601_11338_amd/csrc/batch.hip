@@ -272,7 +272,8 @@ struct Layout {  // small matrices of one graph (doubles), as in the single-grap
   int64_t Cc() const { return (int64_t)(2 * K + 6) * bb; }
   int64_t P() const { return (int64_t)(2 * K + 9) * bb; }   // 3 blocks
   int64_t Bt() const { return (int64_t)(2 * K + 12) * bb; }
-  int64_t total() const { return (int64_t)(2 * K + 13) * bb; }
+  int64_t Ref() const { return (int64_t)(2 * K + 13) * bb; }  // one double: reference scale
+  int64_t total() const { return (int64_t)(2 * K + 14) * bb; }
 };
 
 }  // namespace
@@ -456,14 +457,15 @@ wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int 
   const int64_t gs = Ly.total();
   float* V = wk.basis.as<float>();
   double* S = wk.S.as<double>();
-  const double tol = 1e-6;  // FP32 deflation threshold on relative squared norms (as the single-graph path)
+  const double tol = 1e-10, ptol = 1e-5;  // FP32 deflation thresholds (as the single-graph path)
   // V_0 R_0 = U0 by CholQR2, per graph
   WL_TRY(batch_gram(bt, wk, U0, 0, 1, U0, b, S + Ly.G(), gs));
-  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, ng, gs));
+  WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, ng, gs,
+                     S + Ly.Ref()));
   WL_TRY(batch_update(bt, U0, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, V));
   WL_TRY(batch_gram(bt, wk, V, 0, 1, V, b, S + Ly.G(), gs));
   WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
-                     ng, gs));
+                     ng, gs, S + Ly.Ref(), ptol));
   WL_TRY(batch_update(bt, V, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, V));
   for (int j = 0; j < K; ++j) {
     float* Vj = V + (int64_t)j * blk;
@@ -479,7 +481,7 @@ wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int 
     float* Vlo = j > 0 ? Vj - blk : Vj;
     WL_TRY(batch_gram(bt, wk, Vlo, blk, nbv + 1, Vn, b, S + Ly.P(), gs));
     WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(), S + Ly.Cc(),
-                                 ng, gs));
+                                 ng, gs, S + Ly.Ref()));
     if (j + 1 == K) {  // residual coupling B_{K-1} = R1 of every graph
       hipLaunchKernelGGL(k_dcopy_batched, dim3(ng), dim3(64), 0, ctx->stream, b * b, S + Ly.R1(), S + Ly.B(j), gs);
       WL_HIP(hipGetLastError());
@@ -488,7 +490,7 @@ wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int 
     WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
     WL_TRY(batch_gram(bt, wk, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
     WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j), ng, gs));
+                       S + Ly.B(j), ng, gs, S + Ly.Ref(), ptol));
     if (wk.cap_at[j]) {
       hipLaunchKernelGGL(k_cap_blocks, dim3(ng), dim3(64), 0, ctx->stream, ng, wk.kcap.as<int32_t>(), j, S, gs,
                          Ly.Ri2(), Ly.B(j), b * b);

@@ -502,7 +502,7 @@ __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double th
 __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const double* __restrict__ P, double tol,
                                                        double* __restrict__ Aout, double* __restrict__ R,
                                                        double* __restrict__ Rinv, double* __restrict__ Cc,
-                                                       int64_t gs) {
+                                                       int64_t gs, double* __restrict__ ref_out) {
   // one workgroup per graph of a batch: every matrix of graph g sits gs doubles further
   const int64_t go = (int64_t)blockIdx.x * gs;
   P += go;
@@ -510,6 +510,7 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
   R += go;
   Rinv += go;
   Cc += go;
+  if (ref_out) ref_out += go;
   __shared__ double sG[64 * 65];
   __shared__ double sR[64 * 65];
   __shared__ double sA[64 * 65];
@@ -533,6 +534,7 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
     double m = 0.0;
     for (int i = 0; i < b; ++i) m = fmax(m, Gp[i * b + i]);
     sref = m;
+    if (ref_out) ref_out[0] = m;  // reference for the second pass's check
   }
   __syncthreads();
   if (t < b) {
@@ -568,8 +570,9 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
                                              const double* __restrict__ Aref, const double* __restrict__ Bref,
                                              double* __restrict__ R, double* __restrict__ Rinv,
                                              const double* __restrict__ Rprev, double* __restrict__ Bout,
-                                             int64_t gs) {
+                                             int64_t gs, double* __restrict__ ref_io, double post_tol) {
   const int64_t go = (int64_t)blockIdx.x * gs;  // batch: graph g's matrices at +g gs
+  if (ref_io) ref_io += go;
   G += go;
   if (Aref) Aref += go;
   if (Bref) Bref += go;
@@ -597,6 +600,7 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     if (Bref)
       for (int e = 0; e < b * b; ++e) fa += Bref[e] * Bref[e];
     sref = fmax(m, fa / b);
+    if (ref_io && !Rprev) ref_io[0] = sref;  // first pass: reference for the second
   }
   __syncthreads();
   chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
@@ -616,6 +620,21 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
           s = sR[t * 65 + j];
         }
         Bout[t * b + j] = s;
+      }
+    }
+    // Second pass: Bout = R2 R1 is the R factor of the block before both passes, so
+    // Bout_kk is the true norm of its k-th orthogonal component.  Components at the
+    // rounding level of the reference (the block's scale before projection) are
+    // dropped: column k of Rinv and row k of Bout become zero, so V_{j+1} loses that
+    // column instead of carrying normalised noise.
+    if (Rprev && ref_io && post_tol > 0.0) {
+      __shared__ int drop[64];
+      __syncthreads();
+      if (t < b) drop[t] = fabs(Bout[t * b + t]) <= post_tol * sqrt(fmax(ref_io[0], 0.0));
+      __syncthreads();
+      if (t < b && drop[t]) {
+        for (int j = 0; j < b; ++j) Bout[t * b + j] = 0.0;
+        for (int i = 0; i < b; ++i) Rinv[i * b + t] = 0.0;
       }
     }
   }
@@ -988,20 +1007,21 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 }
 
 wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
-                                double* Rinv, double* Cc, int ngraphs, int64_t gs) {
+                                double* Rinv, double* Cc, int ngraphs, int64_t gs, double* ref_out) {
   WL_CHECK(b >= 1 && b <= 64 && (nbv == 1 || nbv == 2) && ngraphs >= 1, WL_EINVAL,
            "lanczos coefficients: bad sizes");
   hipLaunchKernelGGL(k_lanczos_coeffs, dim3(ngraphs), dim3(64), 0, ctx->stream, b, nbv, P, tol, Aout, R, Rinv, Cc,
-                     gs);
+                     gs, ref_out);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
-                      double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs) {
+                      double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs,
+                      double* ref_io, double post_tol) {
   WL_CHECK(b >= 1 && b <= 64 && ngraphs >= 1, WL_EINVAL, "chol: b out of range");
   hipLaunchKernelGGL(k_chol, dim3(ngraphs), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout,
-                     gs);
+                     gs, ref_io, post_tol);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
