@@ -517,6 +517,11 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
                      S + Ly.R0(), 1, 0, S + Ly.Ref(), ptol));
   WL_TRY(launch_update<T>(ctx, n, basis, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, basis, b, nullptr));
   if (ring) reorth = 0;
+  // A basis that will span more than half of the space loses orthogonality under local
+  // reorthogonalisation as its Ritz values converge (at exhaustion the projected matrix
+  // gains spurious eigenvalues); there every block is orthogonalised against all
+  // earlier ones, which costs little at such sizes.
+  if (!ring && (int64_t)(K + 1) * b * 2 > n) reorth = std::max(reorth, 2);
   auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
   if (!ring && reorth <= 1) {
     // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] against W';
