@@ -215,7 +215,8 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
   // stream c), row sums accumulated on the device, per-probe traces from the Gram
   // diagonal of each block
   // (the surrogate estimator takes this path for any M: Y becomes (phi - G) Omega)
-  DevBuf sums, H, Z, tri;
+  DevBuf sums, H, Z;
+  const unsigned long long* tri = nullptr;
   WL_TRY(sums.ensure((size_t)2 * n * 8));
   WL_TRY(H.ensure((size_t)DIAG_CHUNK * DIAG_CHUNK * 8));
   wl_op gop;  // the degree-3 truncation of the same series (borrows the graph)
@@ -230,9 +231,9 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
     c2m = (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
     c3 = ex ? p * p * p / 6.0 : p * p * p;
     WL_TRY(Z.ensure((size_t)n * mc * es));
-    WL_TRY(graph_tri2(g, tri));
+    WL_TRY(graph_tri2(g, &tri));
     std::vector<unsigned long long> ht(n);
-    WL_HIP(hipMemcpyAsync(ht.data(), tri.p, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipMemcpyAsync(ht.data(), tri, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
     WL_HIP(hipStreamSynchronize(ctx->stream));
     double st = 0.0;
     for (unsigned long long v : ht) st += (double)v;
@@ -272,12 +273,12 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
   const int gb = (int)std::min<int64_t>(8192, (n + 255) / 256);
   if (sur && op->d.prec == WL_FP32) {
     hipLaunchKernelGGL(k_surrogate_finish<float>, dim3(gb), dim3(256), 0, ctx->stream, n, M, sums.as<double>(),
-                       sums.as<double>() + n, g->rowptr, tri.as<unsigned long long>(), c2m, c3,
+                       sums.as<double>() + n, g->rowptr, tri, c2m, c3,
                        (const float*)d_cv, (float*)d_diag);
     WL_HIP(hipGetLastError());
   } else if (sur) {
     hipLaunchKernelGGL(k_surrogate_finish<double>, dim3(gb), dim3(256), 0, ctx->stream, n, M, sums.as<double>(),
-                       sums.as<double>() + n, g->rowptr, tri.as<unsigned long long>(), c2m, c3,
+                       sums.as<double>() + n, g->rowptr, tri, c2m, c3,
                        (const double*)d_cv, (double*)d_diag);
     WL_HIP(hipGetLastError());
   } else if (op->d.prec == WL_FP32) {

@@ -340,22 +340,26 @@ wl_status mlp_grad(wl_mlp* net, const float* feat, const float* tgt, int64_t n, 
 }
 }  // namespace
 
-wl_status graph_tri2(wl_graph* g, DevBuf& tri) {
+wl_status graph_tri2(wl_graph* g, const unsigned long long** out) {
   hipStream_t st = g->ctx->stream;
-  WL_TRY(tri.ensure((size_t)std::max<int64_t>(g->n, 1) * 8));
-  if (g->n == 0) return WL_OK;
-  WL_HIP(hipMemsetAsync(tri.p, 0, (size_t)g->n * 8, st));
-  if (g->nnz == 0) return WL_OK;
-  DevBuf rowof;
-  WL_TRY(rowof.ensure((size_t)g->nnz * 4));
-  const int gb = (int)std::min<int64_t>(8192, (g->n + 255) / 256);
-  hipLaunchKernelGGL(k_rowof, dim3(gb), dim3(256), 0, st, g->n, g->rowptr, rowof.as<int32_t>());
-  WL_HIP(hipGetLastError());
-  const int ge = (int)std::min<int64_t>(65536, (g->nnz + 255) / 256);
-  hipLaunchKernelGGL(k_triangles, dim3(ge), dim3(256), 0, st, g->n, g->nnz, g->rowptr, g->colidx,
-                     rowof.as<int32_t>(), tri.as<unsigned long long>());
-  WL_HIP(hipGetLastError());
-  // rowof is released (after a device synchronisation) when it leaves scope
+  if (!g->tri2_valid) {
+    WL_TRY(g->tri2.ensure((size_t)std::max<int64_t>(g->n, 1) * 8));
+    if (g->n > 0) WL_HIP(hipMemsetAsync(g->tri2.p, 0, (size_t)g->n * 8, st));
+    if (g->nnz > 0) {
+      DevBuf rowof;
+      WL_TRY(rowof.ensure((size_t)g->nnz * 4));
+      const int gb = (int)std::min<int64_t>(8192, (g->n + 255) / 256);
+      hipLaunchKernelGGL(k_rowof, dim3(gb), dim3(256), 0, st, g->n, g->rowptr, rowof.as<int32_t>());
+      WL_HIP(hipGetLastError());
+      const int ge = (int)std::min<int64_t>(65536, (g->nnz + 255) / 256);
+      hipLaunchKernelGGL(k_triangles, dim3(ge), dim3(256), 0, st, g->n, g->nnz, g->rowptr, g->colidx,
+                         rowof.as<int32_t>(), g->tri2.as<unsigned long long>());
+      WL_HIP(hipGetLastError());
+      // rowof is released (after a device synchronisation) when it leaves scope
+    }
+    g->tri2_valid = true;
+  }
+  *out = g->tri2.as<unsigned long long>();
   return WL_OK;
 }
 
@@ -368,11 +372,11 @@ wl_status wl_features(wl_graph* g, double scale, void* d_feat) {
   if (g->n == 0) return WL_OK;
   (void)hipSetDevice(g->ctx->device);
   hipStream_t st = g->ctx->stream;
-  DevBuf tri;
-  WL_TRY(graph_tri2(g, tri));
+  const unsigned long long* tri = nullptr;
+  WL_TRY(graph_tri2(g, &tri));
   const int gb = (int)std::min<int64_t>(8192, (g->n + 255) / 256);
   hipLaunchKernelGGL(k_features, dim3(gb), dim3(256), 0, st, g->n, g->rowptr, g->colidx,
-                     tri.as<unsigned long long>(), scale, (float*)d_feat);
+                     tri, scale, (float*)d_feat);
   WL_HIP(hipGetLastError());
   WL_HIP(hipStreamSynchronize(st));
   return WL_OK;

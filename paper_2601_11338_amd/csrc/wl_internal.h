@@ -133,7 +133,9 @@ struct wl_graph {
   double lam_max = -1.0;
   std::map<double, double> rho_cache;
   DevBuf degf, degd;                    // degree vector as float / double
-  DevBuf tmp;                           // Lanczos scratch for spectral routines
+  DevBuf tmp;
+  DevBuf tri2;                          // (A^3)_ii, once computed
+  bool tri2_valid = false;                           // Lanczos scratch for spectral routines
   int refs = 1;                         // the caller's handle + every operator on it
 };
 void graph_release(wl_graph* g);
@@ -190,9 +192,10 @@ struct EpiArgs {
 template <typename T>
 wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, const SpmmShape& sh);
 
-// tri2[i] = (A^3)_ii = twice the triangles through node i (n unsigned 64-bit counts in
-// tri, resized as needed); colidx must be sorted within rows.
-wl_status graph_tri2(wl_graph* g, DevBuf& tri);
+// tri2[i] = (A^3)_ii = twice the triangles through node i (n unsigned 64-bit counts),
+// computed on first use and kept in the graph; colidx must be sorted within rows.
+// *out receives the device array (valid while the graph lives).
+wl_status graph_tri2(wl_graph* g, const unsigned long long** out);
 
 // SpMM launch shape for (prec, b) on g: the autotuned one if present, else a heuristic.
 SpmmShape shape_for(wl_graph* g, int prec, int b);

@@ -343,6 +343,26 @@ def test_fp32_krylov_space_exhausted(ctx, wl, n, m, b):
             assert np.linalg.norm(host(o) - r) < 1e-4 * np.linalg.norm(r), (mu, kind, t)
 
 
+def test_fp64_lanczos_spanning_the_space(ctx, wl):
+    """FP64 block Lanczos whose basis spans most of the space (K b > n): every block is
+    orthogonalised against all earlier ones, so the projection stays exact (1e-8)."""
+    print("[gpu] fp64 Lanczos spanning the space", flush=True)
+    n = 300
+    rp, ci = synth.erdos_renyi_gnm(n, 1200, 8)
+    A = walks.adjacency(n, rp, ci)
+    g = wl.Graph(ctx, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    X = synth.gaussian_block(n, 24, 2)
+    for mu, kind, param, method in [(0.5, "res", 0.5 / lam, "lanczos"), (0.0, "exp", 1.0 / lam, "lanczos")]:
+        op = wl.Operator(g, mu, kind, param, dtype=torch.float64, krylov_dim=30, method=method, tol=1e-13)
+        ph = genfun.phi(A, mu, kind, param)
+        assert rel(host(op.apply_phi(dev(X, torch.float64))), ph @ X) < 1e-8, (mu, kind)
+        L = laplacian.walk_laplacian(ph)
+        outs, _ = op.expv(dev(X, torch.float64), [1.0], outer_dim=30)
+        (r,) = laplacian.expv(L, X, [1.0])
+        assert rel(host(outs[0]), r) < 1e-8, (mu, kind)
+
+
 def test_fig1_stationary_from_gpu_fdeg(ctx, wl):
     """The printed Fig. 1 bars follow from the GPU walk degree: pi = w / sum(w)."""
     from test_oracle_genfun import load_fig1
