@@ -537,6 +537,9 @@ def main():
     log(f"graph n={n} nnz={nnz} max_degree={g.info()[2]}")
     g.autotune(torch.float32, b)
     g.autotune(torch.float32, 1)
+    if not args.separate:
+        g.autotune(torch.float32, 4 * b)  # four series operators side by side
+        g.autotune(torch.float32, 5)      # five walk-degree columns
     lam = g.lambda_max()
     mus = [0.0, 0.25, 0.5, 0.75, 1.0]
     ops = []
