@@ -284,7 +284,7 @@ wl_status wl_multi_destroy(wl_multi* multi);
 /* ---------------------------------------------------------------- batches of graphs
  * Many graphs with their own walk variant and weights, evaluated together: the
  * graphs are concatenated into one block-diagonal CSR whose per-graph row ranges start
- * at 16-row boundaries (offsets from wl_batch_info; padding rows have no edges and
+ * at 64-row boundaries (offsets from wl_batch_info; padding rows have no edges and
  * must hold zeros in inputs), so every sparse product, Gram and block update of a
  * Krylov step is one launch for the whole batch.  Inner phi products use each graph's
  * truncated series (eq. qrec) with degree from tol (exponential: tail bound with

@@ -1,7 +1,7 @@
 // Many graphs in one launch per Krylov step.
 //
 // The graphs of a batch are concatenated into one block-diagonal CSR whose per-graph
-// row ranges are padded to multiples of 16 rows (padding rows have no edges), so
+// row ranges are padded to multiples of 64 rows (padding rows have no edges), so
 //  * every sparse product of the recurrence is one launch over all graphs, with the
 //    per-graph coefficients of eq. qrec / the weights c_k read from a table indexed
 //    by the row's graph id (graphs whose series is already converged skip their rows);
@@ -303,6 +303,7 @@ struct wl_batch {
   DevBuf d_us, d_gu0;
   DevBuf ones;
   BatchWork work;  // scratch of the eager entry points
+  XcdTileMap xmap;  // every graph's row tiles on one XCD
   int graphs = 0;  // live captured graphs (they hold pointers into the batch)
 };
 
@@ -359,6 +360,7 @@ wl_status batch_phi(wl_batch* bt, BatchWork& wk, const float* X, float* Y, int b
   const int64_t tstride = (int64_t)bt->ng * 5;
   {
     EpiArgs<float> ep;
+    ep.xmap = &bt->xmap;
     ep.gid = bt->gid.as<int32_t>();
     ep.gtab = tab;
     ep.Sin = X;
@@ -375,6 +377,7 @@ wl_status batch_phi(wl_batch* bt, BatchWork& wk, const float* X, float* Y, int b
   float* Pm1 = A;
   for (int k = 2; k <= bt->Kmax; ++k) {
     EpiArgs<float> ep;
+    ep.xmap = &bt->xmap;
     ep.gid = bt->gid.as<int32_t>();
     ep.gtab = tab + (int64_t)(k - 1) * tstride;
     ep.Z = Pm2;
@@ -614,7 +617,7 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
       return fail(WL_EINVAL);
     }
     bt->n[gi] = g->n;
-    bt->npad[gi] = std::max<int64_t>(16, (g->n + 15) / 16 * 16);
+    bt->npad[gi] = std::max<int64_t>(64, (g->n + 63) / 64 * 64);
     bt->roff[gi] = bt->N;
     bt->N += bt->npad[gi];
     nnz_tot += g->nnz;
@@ -690,6 +693,24 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
   }
   s = wl_graph_create(ctx, bt->N, pos, bt->rowptr.as<int32_t>(), bt->colidx.as<int32_t>(), 0, &bt->G);
   if (s != WL_OK) return fail(s);
+  // XCD placement: graphs by decreasing nonzeros onto the least loaded XCD
+  {
+    std::vector<int> order(ngraphs);
+    for (int gi = 0; gi < ngraphs; ++gi) order[gi] = gi;
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return graphs[a]->nnz > graphs[c]->nnz; });
+    double load[XcdTileMap::NXCD] = {0};
+    bt->xmap.start.assign(bt->roff.begin(), bt->roff.end());
+    bt->xmap.end.resize(ngraphs);
+    bt->xmap.xcd.resize(ngraphs);
+    for (int gi = 0; gi < ngraphs; ++gi) bt->xmap.end[gi] = bt->roff[gi] + bt->npad[gi];
+    for (int gi : order) {
+      int best = 0;
+      for (int x = 1; x < XcdTileMap::NXCD; ++x)
+        if (load[x] < load[best]) best = x;
+      bt->xmap.xcd[gi] = best;
+      load[best] += (double)graphs[gi]->nnz + (double)bt->npad[gi];
+    }
+  }
   // reduction units
   bt->gu0.resize(ngraphs + 1);
   for (int gi = 0; gi < ngraphs; ++gi) {

@@ -255,7 +255,12 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
 
   constexpr int RPB = 256 / G;
   constexpr int NS = G / LPN;
-  const int64_t r = (int64_t)(blockIdx.x - n_long) * RPB + threadIdx.x / G;
+  int64_t tile = (int64_t)blockIdx.x - n_long;
+  if (ep.tile_map) {
+    tile = ep.tile_map[tile];
+    if (tile < 0) return;  // idle block of the XCD placement (whole workgroup)
+  }
+  const int64_t r = tile * RPB + threadIdx.x / G;
   if (r >= n) return;  // whole group leaves together: all its lanes share r
   const int s = rowptr[r], e = rowptr[r + 1];
   if (e - s > long_thr) return;
@@ -295,7 +300,13 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     n_long = lo;
   }
   constexpr int RPB = 256 / G;
-  const int64_t nshort = (g->n + RPB - 1) / RPB;
+  int64_t nshort = (g->n + RPB - 1) / RPB;
+  EpiArgs<T> epx = ep;
+  if (ep.xmap) {  // XCD-aware order of the short-row tiles
+    int64_t blocks = 0;
+    WL_TRY(const_cast<XcdTileMap*>(ep.xmap)->get(RPB, n_long, &epx.tile_map, &blocks));
+    nshort = blocks;
+  }
   const int64_t gx = nshort + n_long;
   WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
   const size_t lds = ep.C ? (size_t)b * TILE * sizeof(T) : 0;
@@ -313,7 +324,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
   }
   hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK>), grid, dim3(256), lds, ctx->stream, g->rowptr, g->colidx,
-                     g->n, b, b, X, Y, ep, g->long_rows.as<int32_t>(), n_long, long_thr);
+                     g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
   WL_HIP(hipGetLastError());
   if (ks) {
     WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));
@@ -380,3 +391,35 @@ wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep
 template wl_status launch_spmm<float>(wl_graph*, const float*, float*, int, const EpiArgs<float>&, const SpmmShape&);
 template wl_status launch_spmm<double>(wl_graph*, const double*, double*, int, const EpiArgs<double>&,
                                        const SpmmShape&);
+
+wl_status XcdTileMap::get(int rpb, int lead, const int32_t** map, int64_t* blocks) {
+  auto key = std::make_pair(rpb, lead % NXCD);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    std::vector<std::vector<int32_t>> tiles(NXCD);
+    for (size_t p = 0; p < start.size(); ++p)
+      for (int64_t t = start[p] / rpb; t < (end[p] + rpb - 1) / rpb; ++t) tiles[xcd[p]].push_back((int32_t)t);
+    size_t per = 0;
+    for (const auto& v : tiles) per = std::max(per, v.size());
+    // block s (after lead other blocks) runs on XCD (s + lead) mod 8 and is the
+    // (s / 8)-th block of that XCD
+    std::vector<int32_t> h((size_t)NXCD * per, -1);
+    for (size_t s = 0; s < h.size(); ++s) {
+      const int x = (int)((s + (size_t)lead) % NXCD);
+      const size_t k = s / NXCD;
+      if (k < tiles[x].size()) h[s] = tiles[x][k];
+    }
+    Entry& e = cache[key];
+    WL_TRY(e.map.ensure(std::max<size_t>(h.size(), 1) * 4));
+    if (!h.empty() && hipMemcpy(e.map.p, h.data(), h.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      cache.erase(key);
+      wl_set_error("XCD tile map upload failed");
+      return WL_EDEVICE;
+    }
+    e.blocks = (int64_t)h.size();
+    it = cache.find(key);
+  }
+  *map = it->second.map.as<int32_t>();
+  *blocks = it->second.blocks;
+  return WL_OK;
+}

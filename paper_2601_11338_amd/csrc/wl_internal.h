@@ -187,6 +187,29 @@ struct EpiArgs {
   const double* ctab = nullptr;
   int cgw = 0;
   int wld = 0;
+  // Row-tile order of the short-row blocks (host object, resolved by the launcher):
+  // block s of the launch processes row tile map[s] (-1: idle), so that tiles that
+  // gather from the same rows can be placed on one XCD.  Null: tile s = block s.
+  const struct XcdTileMap* xmap = nullptr;
+  const int32_t* tile_map = nullptr;  // device map, filled in by the launcher
+};
+
+// Tiles of a block-diagonal graph (consecutive row ranges that only touch their own
+// rows) assigned to XCDs: workgroups are dispatched to the 8 XCDs round-robin, so
+// launch block b runs on XCD b mod 8.  Each range goes to one XCD (balanced by
+// nonzeros), and the map puts its row tiles on blocks of that XCD; the rows it
+// gathers then stay in that XCD's L2.  Ranges must start at multiples of 64 rows.
+struct XcdTileMap {
+  static constexpr int NXCD = 8;
+  std::vector<int64_t> start, end;  // row range of every part
+  std::vector<int> xcd;             // its XCD
+  struct Entry {
+    DevBuf map;
+    int64_t blocks = 0;
+  };
+  std::map<std::pair<int, int>, Entry> cache;  // (rows per tile, blocks before the tiles)
+  // Device map for tiles of rpb rows placed after lead other blocks; builds on first use.
+  wl_status get(int rpb, int lead, const int32_t** map, int64_t* blocks);
 };
 
 template <typename T>
