@@ -514,7 +514,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
                      S + Ly.Ref()));
   WL_TRY(launch_update<T>(ctx, n, X, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, basis, b, S + Ly.G()));
   WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                     S + Ly.R0(), 1, 0, S + Ly.Ref(), ptol));
+                     S + Ly.R0(), 1, 0, nullptr, S + Ly.Ref(), ptol));
   WL_TRY(launch_update<T>(ctx, n, basis, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, basis, b, nullptr));
   if (ring) reorth = 0;
   // A basis that will span more than half of the space loses orthogonality under local
@@ -524,9 +524,10 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
   if (!ring && (int64_t)(K + 1) * b * 2 > n) reorth = std::max(reorth, 2);
   auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
   if (!ring && reorth <= 1) {
-    // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] against W';
-    // projection and Cholesky of the projected Gram on the device; one in-place update
-    // V_{j+1} = [V_{j-1} V_j W'] Cc; a second CholQR pass for orthonormality.
+    // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] against W'
+    // gives the projection; W = [V_{j-1} V_j W'] Cc is formed in place together with
+    // its own Gram; CholQR2 on that true Gram (with the deflation check of the first
+    // factor against W's scale before projection) orthonormalises it in place.
     for (int j = 0; j < K; ++j) {
       T* Vj = slot(j);
       T* Vn = slot(j + 1);
@@ -535,16 +536,18 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
       const int nbv = j > 0 ? 2 : 1;
       const T* Vlo = j > 0 ? Vp : Vj;
       WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nbv + 1, Vn, b, S + Ly.P()));
-      WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(),
-                                   S + Ly.Cc(), 1, 0, S + Ly.Ref()));
-      if (j + 1 == K) {
+      WL_TRY(launch_lanczos_proj(ctx, b, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref()));
+      WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,
+                              S + Ly.G()));
+      WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), 1, 0,
+                         nullptr, S + Ly.Ref(), ptol));
+      if (j + 1 == K) {  // residual coupling B_{K-1} (a-posteriori error estimates)
         WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
         break;
       }
-      WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,
-                              S + Ly.G()));
+      WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G()));
       WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                         S + Ly.B(j), 1, 0, S + Ly.Ref(), ptol));
+                         S + Ly.B(j)));
       WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
     }
   }
@@ -575,7 +578,7 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
     T* Vn = slot(j + 1);
     WL_TRY(launch_update<T>(ctx, n, Wb, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G()));
     WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j), 1, 0, S + Ly.Ref(), ptol));
+                       S + Ly.B(j), 1, 0, nullptr, S + Ly.Ref(), ptol));
     WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
   }
   hA.assign((size_t)K * b * b, 0.0);
@@ -836,7 +839,12 @@ wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* c
   L.inner = op;
   std::vector<double> hA, hB, hR0;
   int Ke = K;
-  WL_TRY(block_lanczos<T>(g, L, U0, b, K, op->d.reorth, op->outer_basis.as<T>(), op->outer_w.as<T>(),
+  // The walk Laplacian of a graph with hubs has a few large, quickly converging Ritz
+  // values; with local reorthogonalisation the basis then loses orthogonality and the
+  // projected matrix gains spurious (even negative) eigenvalues, which exp(-t T)
+  // amplifies.  The outer basis is therefore orthogonalised against every earlier
+  // block (its cost is small next to the inner products with phi).
+  WL_TRY(block_lanczos<T>(g, L, U0, b, K, std::max(op->d.reorth, 2), op->outer_basis.as<T>(), op->outer_w.as<T>(),
                           op->outer_small, hA, hB, hR0, &Ke));
   const int m = Ke * b;
   std::vector<double> Tm = assemble_T(Ke, b, hA, hB);

@@ -468,7 +468,7 @@ wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int 
   WL_TRY(batch_update(bt, U0, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, V));
   WL_TRY(batch_gram(bt, wk, V, 0, 1, V, b, S + Ly.G(), gs));
   WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
-                     ng, gs, S + Ly.Ref(), ptol));
+                     ng, gs, nullptr, S + Ly.Ref(), ptol));
   WL_TRY(batch_update(bt, V, 0, 1, b, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, V));
   for (int j = 0; j < K; ++j) {
     float* Vj = V + (int64_t)j * blk;
@@ -483,17 +483,21 @@ wl_status expv_enqueue(wl_batch* bt, BatchWork& wk, const float* U0, int b, int 
     const int nbv = j > 0 ? 2 : 1;
     float* Vlo = j > 0 ? Vj - blk : Vj;
     WL_TRY(batch_gram(bt, wk, Vlo, blk, nbv + 1, Vn, b, S + Ly.P(), gs));
-    WL_TRY(launch_lanczos_coeffs(ctx, b, nbv, S + Ly.P(), tol, S + Ly.A(j), S + Ly.R1(), S + Ly.Ri1(), S + Ly.Cc(),
-                                 ng, gs, S + Ly.Ref()));
+    WL_TRY(launch_lanczos_proj(ctx, b, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref(), ng, gs));
+    // W = [V_{j-1} V_j W'] Cc in place, then CholQR2 on its true Gram
+    WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+    WL_TRY(batch_gram(bt, wk, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
+    WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), ng, gs,
+                       nullptr, S + Ly.Ref(), ptol));
     if (j + 1 == K) {  // residual coupling B_{K-1} = R1 of every graph
       hipLaunchKernelGGL(k_dcopy_batched, dim3(ng), dim3(64), 0, ctx->stream, b * b, S + Ly.R1(), S + Ly.B(j), gs);
       WL_HIP(hipGetLastError());
       break;
     }
-    WL_TRY(batch_update(bt, Vlo, blk, nbv + 1, b, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
+    WL_TRY(batch_update(bt, Vn, 0, 1, b, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, Vn));
     WL_TRY(batch_gram(bt, wk, Vn, 0, 1, Vn, b, S + Ly.G(), gs));
     WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j), ng, gs, S + Ly.Ref(), ptol));
+                       S + Ly.B(j), ng, gs));
     if (wk.cap_at[j]) {
       hipLaunchKernelGGL(k_cap_blocks, dim3(ng), dim3(64), 0, ctx->stream, ng, wk.kcap.as<int32_t>(), j, S, gs,
                          Ly.Ri2(), Ly.B(j), b * b);

@@ -493,30 +493,21 @@ __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double th
     for (int e = t; e < b * b; e += 64) Rinv[e] = sG[(e / b) * 65 + e % b];
 }
 
-// One projection step of block Lanczos (classical Gram-Schmidt against V_{j-1} and V_j
-// with the Gram of the projected block obtained by Pythagoras).  P stacks nbv + 1 b x b
-// blocks: [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or [V_j^T W'; W'^T W'] (nbv = 1).
-// Outputs: Aout = sym(V_j^T W') (the diagonal block of T); R, Rinv from the deflated
-// Cholesky of G_W = W'^T W' - P1^T P1 - A^T A, the Gram of W = W' - V_{j-1} P1 - V_j A;
-// Cc = [-P1 Rinv; -A Rinv; Rinv] so that V_{j+1} = [V_{j-1} V_j W'] Cc.
-__global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const double* __restrict__ P, double tol,
-                                                       double* __restrict__ Aout, double* __restrict__ R,
-                                                       double* __restrict__ Rinv, double* __restrict__ Cc,
-                                                       int64_t gs, double* __restrict__ ref_out) {
+// One projection step of block Lanczos (classical Gram-Schmidt against V_{j-1} and
+// V_j).  P stacks nbv + 1 b x b blocks: [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or
+// [V_j^T W'; W'^T W'] (nbv = 1).  Outputs: Aout = sym(V_j^T W') (the diagonal block of
+// T); Cc = [-P1; -A; I] so that W = [V_{j-1} V_j W'] Cc is the projected block; ref =
+// max_i (W'^T W')_ii, the block's scale before projection.  The projected block's
+// Gram is then taken from W itself: forming it by Pythagoras from these inner
+// products fails as soon as the basis loses orthogonality (converged Ritz vectors).
+__global__ __launch_bounds__(64) void k_lanczos_proj(int b, int nbv, const double* __restrict__ P,
+                                                     double* __restrict__ Aout, double* __restrict__ Cc, int64_t gs,
+                                                     double* __restrict__ ref_out) {
   // one workgroup per graph of a batch: every matrix of graph g sits gs doubles further
   const int64_t go = (int64_t)blockIdx.x * gs;
   P += go;
   Aout += go;
-  R += go;
-  Rinv += go;
   Cc += go;
-  if (ref_out) ref_out += go;
-  __shared__ double sG[64 * 65];
-  __shared__ double sR[64 * 65];
-  __shared__ double sA[64 * 65];
-  __shared__ double sP[64 * 65];
-  __shared__ int defl[64];
-  __shared__ double sref;
   const int t = threadIdx.x;
   const int bb = b * b;
   const bool hasP1 = nbv == 2;
@@ -525,43 +516,15 @@ __global__ __launch_bounds__(64) void k_lanczos_coeffs(int b, int nbv, const dou
   for (int e = t; e < bb; e += 64) {
     const int i = e / b, j = e % b;
     const double a = 0.5 * (Aj[i * b + j] + Aj[j * b + i]);
-    sA[i * 65 + j] = a;
     Aout[e] = a;
-    sP[i * 65 + j] = hasP1 ? P[e] : 0.0;
-    sG[i * 65 + j] = 0.5 * (Gp[i * b + j] + Gp[j * b + i]);
+    if (hasP1) Cc[e] = -P[e];
+    Cc[(size_t)(nbv - 1) * bb + e] = -a;
+    Cc[(size_t)nbv * bb + e] = i == j ? 1.0 : 0.0;
   }
-  if (t == 0) {
+  if (t == 0 && ref_out) {
     double m = 0.0;
     for (int i = 0; i < b; ++i) m = fmax(m, Gp[i * b + i]);
-    sref = m;
-    if (ref_out) ref_out[0] = m;  // reference for the second pass's check
-  }
-  __syncthreads();
-  if (t < b) {
-    for (int k = 0; k < b; ++k) {
-      double s = sG[t * 65 + k];
-      for (int m = 0; m < b; ++m) s -= sA[m * 65 + t] * sA[m * 65 + k] + sP[m * 65 + t] * sP[m * 65 + k];
-      sR[t * 65 + k] = s;  // staged here, moved back below
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < bb; e += 64) sG[(e / b) * 65 + e % b] = sR[(e / b) * 65 + e % b];
-  __syncthreads();
-  chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
-  for (int e = t; e < bb; e += 64) R[e] = sR[(e / b) * 65 + e % b];
-  // Cc blocks from the inverse left in sG by the factorisation
-  if (t < b) {
-    for (int c = 0; c < b; ++c) {
-      double sa = 0.0, sp = 0.0;
-      for (int m = 0; m < b; ++m) {
-        const double rv = sG[m * 65 + c];
-        sa += sA[t * 65 + m] * rv;
-        sp += sP[t * 65 + m] * rv;
-      }
-      if (hasP1) Cc[t * b + c] = -sp;
-      Cc[(size_t)(nbv - 1) * bb + t * b + c] = -sa;
-      Cc[(size_t)nbv * bb + t * b + c] = sG[t * 65 + c];
-    }
+    ref_out[go] = m;
   }
 }
 
@@ -570,9 +533,11 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
                                              const double* __restrict__ Aref, const double* __restrict__ Bref,
                                              double* __restrict__ R, double* __restrict__ Rinv,
                                              const double* __restrict__ Rprev, double* __restrict__ Bout,
-                                             int64_t gs, double* __restrict__ ref_io, double post_tol) {
+                                             int64_t gs, double* __restrict__ ref_out, const double* ref_in,
+                                             double post_tol) {
   const int64_t go = (int64_t)blockIdx.x * gs;  // batch: graph g's matrices at +g gs
-  if (ref_io) ref_io += go;
+  if (ref_out) ref_out += go;
+  if (ref_in) ref_in += go;
   G += go;
   if (Aref) Aref += go;
   if (Bref) Bref += go;
@@ -600,7 +565,7 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     if (Bref)
       for (int e = 0; e < b * b; ++e) fa += Bref[e] * Bref[e];
     sref = fmax(m, fa / b);
-    if (ref_io && !Rprev) ref_io[0] = sref;  // first pass: reference for the second
+    if (ref_out) ref_out[0] = sref;  // reference scale for a later check
   }
   __syncthreads();
   chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
@@ -622,15 +587,15 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
         Bout[t * b + j] = s;
       }
     }
-    // Second pass: Bout = R2 R1 is the R factor of the block before both passes, so
-    // Bout_kk is the true norm of its k-th orthogonal component.  Components at the
-    // rounding level of the reference (the block's scale before projection) are
-    // dropped: column k of Rinv and row k of Bout become zero, so V_{j+1} loses that
-    // column instead of carrying normalised noise.
-    if (Rprev && ref_io && post_tol > 0.0) {
+    // Bout is the R factor of the block as stored (R of its true Gram, or R2 R1 after a
+    // second pass), so Bout_kk is the true norm of its k-th orthogonal component.
+    // Components at the rounding level of the reference scale are dropped: column k of
+    // Rinv and row k of Bout become zero, so the next basis block loses that column
+    // instead of carrying normalised noise.
+    if (ref_in && post_tol > 0.0) {
       __shared__ int drop[64];
       __syncthreads();
-      if (t < b) drop[t] = fabs(Bout[t * b + t]) <= post_tol * sqrt(fmax(ref_io[0], 0.0));
+      if (t < b) drop[t] = fabs(Bout[t * b + t]) <= post_tol * sqrt(fmax(ref_in[0], 0.0));
       __syncthreads();
       if (t < b && drop[t]) {
         for (int j = 0; j < b; ++j) Bout[t * b + j] = 0.0;
@@ -1006,22 +971,21 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
   }
 }
 
-wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
-                                double* Rinv, double* Cc, int ngraphs, int64_t gs, double* ref_out) {
+wl_status launch_lanczos_proj(wl_ctx* ctx, int b, int nbv, const double* P, double* Aout, double* Cc,
+                              double* ref_out, int ngraphs, int64_t gs) {
   WL_CHECK(b >= 1 && b <= 64 && (nbv == 1 || nbv == 2) && ngraphs >= 1, WL_EINVAL,
-           "lanczos coefficients: bad sizes");
-  hipLaunchKernelGGL(k_lanczos_coeffs, dim3(ngraphs), dim3(64), 0, ctx->stream, b, nbv, P, tol, Aout, R, Rinv, Cc,
-                     gs, ref_out);
+           "lanczos projection: bad sizes");
+  hipLaunchKernelGGL(k_lanczos_proj, dim3(ngraphs), dim3(64), 0, ctx->stream, b, nbv, P, Aout, Cc, gs, ref_out);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs,
-                      double* ref_io, double post_tol) {
+                      double* ref_out, const double* ref_in, double post_tol) {
   WL_CHECK(b >= 1 && b <= 64 && ngraphs >= 1, WL_EINVAL, "chol: b out of range");
   hipLaunchKernelGGL(k_chol, dim3(ngraphs), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout,
-                     gs, ref_io, post_tol);
+                     gs, ref_out, ref_in, post_tol);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }

@@ -243,21 +243,21 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 //   ref = max(max_i G_ii, (||Aref||_F^2 + ||Bref||_F^2) / b)  (Aref, Bref optional b x b).
 // If Rprev is given, Bout = R * Rprev (else Bout = R when Bout is given).
 // ngraphs workgroups run independent instances, instance g on matrices offset by g * gs.
-// ref_io (one double, optional): a first pass (no Rprev) stores its ref there; a second
-// pass (Rprev, Bout) with post_tol > 0 drops every k with |Bout_kk| <= post_tol sqrt(ref)
-// (zero row k of Bout, zero column k of Rinv): components at the rounding level.
+// ref_out (one double, optional) receives ref.  With ref_in and post_tol > 0 every k
+// with |Bout_kk| <= post_tol sqrt(*ref_in) is dropped (zero row k of Bout, zero column k
+// of Rinv): Bout_kk is the true norm of the k-th component when G is the true Gram of
+// the block (or Bout = R2 R1 after a second pass).
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs = 1,
-                      int64_t gs = 0, double* ref_io = nullptr, double post_tol = 0.0);
+                      int64_t gs = 0, double* ref_out = nullptr, const double* ref_in = nullptr,
+                      double post_tol = 0.0);
 
 // One block Lanczos projection: from P = [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or
-// [V_j^T W'; W'^T W'] (nbv = 1) form A_j (Aout), the deflated Cholesky factor R (and
-// Rinv) of the projected block's Gram, and Cc with V_{j+1} = [V_{j-1} V_j W'] Cc.
-// Batched like launch_chol; ref_out (optional) receives the reference scale
-// max_i (W'^T W')_ii for the second pass's check.
-wl_status launch_lanczos_coeffs(wl_ctx* ctx, int b, int nbv, const double* P, double tol, double* Aout, double* R,
-                                double* Rinv, double* Cc, int ngraphs = 1, int64_t gs = 0,
-                                double* ref_out = nullptr);
+// [V_j^T W'; W'^T W'] (nbv = 1) form A_j = sym(V_j^T W') (Aout), Cc = [-P1; -A_j; I] with
+// W = [V_{j-1} V_j W'] Cc the projected block, and ref = max_i (W'^T W')_ii (ref_out,
+// optional).  Batched like launch_chol.
+wl_status launch_lanczos_proj(wl_ctx* ctx, int b, int nbv, const double* P, double* Aout, double* Cc,
+                              double* ref_out = nullptr, int ngraphs = 1, int64_t gs = 0);
 
 // Small device helpers on double matrices.
 wl_status launch_dadd(wl_ctx* ctx, int count, const double* x, double* y);   // y += x
