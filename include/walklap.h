@@ -355,12 +355,24 @@ wl_status wl_batch_graph_destroy(wl_batch_graph* graph);
  * wl_mlp_save / wl_mlp_load: flat binary file, 8-byte magic "WLMLP001", int32 count,
  * float parameters.                                                               */
 wl_status wl_features(wl_graph* g, double scale, void* d_feat);
+/* Low-order part of diag phi and the scale of the rest, per node (element type by op):
+ *   base_i  = diag of sum_{k<=3} c_k q_k = 1 + c_2 (1 - mu) d_i + c_3 (A^3)_ii,
+ *   scale_i = c_4 max(1, d_i^2 + S2_i),  S2_i = sum_{j in N(i)} d_j.
+ * Either output may be NULL.  wl_surrogate_target: for count device node indices,
+ * d_out[j] = (phi[i, i] - base_i) / scale_i with phi[i, i] from wl_diag_exact: the
+ * training target of a network that predicts diag phi as base + scale * net(features).
+ * wl_mlp_predict: d_out = base + scale * net(feat) (FP32; base / scale may be NULL for
+ * 0 / 1): a control variate for the Hutchinson and surrogate estimators.           */
+wl_status wl_surrogate_diag(wl_op* op, void* d_base, void* d_scale);
+wl_status wl_surrogate_target(wl_op* op, const int32_t* d_nodes, int64_t count, int32_t width, void* d_out);
 wl_status wl_diag_exact(wl_op* op, const int32_t* d_nodes, int64_t count, int32_t width, void* d_out);
 int32_t wl_mlp_num_params(void);
 wl_status wl_mlp_create(wl_ctx* ctx, const float* h_params, wl_mlp** out);
 wl_status wl_mlp_destroy(wl_mlp* net);
 wl_status wl_mlp_get_params(const wl_mlp* net, float* h_params);
 wl_status wl_mlp_forward(wl_mlp* net, const void* d_feat, int64_t n, void* d_out);
+wl_status wl_mlp_predict(wl_mlp* net, const void* d_feat, int64_t n, const void* d_base, const void* d_scale,
+                         void* d_out);
 wl_status wl_mlp_loss_grad(wl_mlp* net, const void* d_feat, const void* d_target, int64_t n, double* loss,
                            double* h_grad);
 wl_status wl_mlp_train_step(wl_mlp* net, const void* d_feat, const void* d_target, int64_t n, double lr,

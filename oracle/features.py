@@ -30,3 +30,15 @@ def features(n, rowptr, colidx, s):
         cc = np.where(d >= 2, 2 * t / np.maximum(d * (d - 1), 1), 0.0)
     return np.stack([np.log1p(s * d), np.log1p(s * s * d), np.log1p(s ** 3 * 2 * t), np.log1p(s * s * S2),
                      np.log1p(s * mean), np.log1p(s * rms), np.log1p(s * mx), cc], axis=1)
+
+
+def surrogate_terms(A, mu, kind, param):
+    """Exact low-order part of diag phi and the scale of the remainder (dense A):
+    base = diag sum_{k<=3} c_k q_k (eq. qrec truncated), scale = c_4 max(1, d^2 + S2)
+    with S2 = A d (sum of neighbour degrees)."""
+    from .genfun import coefficients, phi_series
+    c = coefficients(kind, param, 4)
+    base = np.diag(phi_series(A, mu, c[:4])).copy()
+    d = A.sum(1)
+    scale = c[4] * np.maximum(1.0, d * d + A @ d)
+    return base, scale

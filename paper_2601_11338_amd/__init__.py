@@ -263,6 +263,20 @@ class Operator:
                                  C.byref(te)))
         return out, tr.value, te.value
 
+    def surrogate_diag(self):
+        """(base, scale): exact degree-3 part of diag phi and the scale of the rest (n each)."""
+        base, scale = self._empty(self.graph.n), self._empty(self.graph.n)
+        check(load().wl_surrogate_diag(self.handle, _ptr(base), _ptr(scale)))
+        return base, scale
+
+    def surrogate_target(self, nodes, width=32):
+        """(diag phi - base) / scale at the given nodes (training targets)."""
+        torch = _torch()
+        nodes = torch.as_tensor(nodes).to(device=self.graph.ctx.torch_device, dtype=torch.int32).contiguous()
+        out = self._empty(nodes.numel())
+        check(load().wl_surrogate_target(self.handle, _ptr(nodes), nodes.numel(), int(width), _ptr(out)))
+        return out
+
     def diag_exact(self, nodes, width=32):
         """phi[i, i] for the given node indices (unit-vector blocks through the operator)."""
         torch = _torch()
@@ -380,6 +394,19 @@ class MLP:
         out = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device) if out is None else out
         _need(out, "out", torch.float32, (feat.shape[0],))
         check(load().wl_mlp_forward(self.handle, _ptr(feat), feat.shape[0], _ptr(out)))
+        return out
+
+    def predict(self, feat, base=None, scale=None, out=None):
+        """base + scale * net(feat) (FP32)."""
+        torch = _torch()
+        feat = _need(feat.contiguous(), "feat", torch.float32, (None, 8))
+        n = feat.shape[0]
+        for t, name in ((base, "base"), (scale, "scale")):
+            if t is not None:
+                _need(t, name, torch.float32, (n,))
+        out = torch.empty(n, dtype=torch.float32, device=feat.device) if out is None else out
+        _need(out, "out", torch.float32, (n,))
+        check(load().wl_mlp_predict(self.handle, _ptr(feat), n, _ptr(base), _ptr(scale), _ptr(out)))
         return out
 
     def loss_grad(self, feat, target):

@@ -68,6 +68,9 @@ SIGNATURES = {
     "wl_estimate": (C.c_int, [vp, i32, i32, i64, i32, vp, vp, vp, f64, vp, pd, pd]),
     "wl_diag_est": (C.c_int, [vp, i32, f64, i32, u64, i32, i32, vp, i32, vp, pd, pd]),
     "wl_features": (C.c_int, [vp, f64, vp]),
+    "wl_surrogate_diag": (C.c_int, [vp, vp, vp]),
+    "wl_surrogate_target": (C.c_int, [vp, vp, i64, i32, vp]),
+    "wl_mlp_predict": (C.c_int, [vp, vp, i64, vp, vp, vp]),
     "wl_diag_exact": (C.c_int, [vp, vp, i64, i32, vp]),
     "wl_mlp_num_params": (i32, []),
     "wl_mlp_create": (C.c_int, [vp, vp, C.POINTER(vp)]),

@@ -338,6 +338,64 @@ wl_status mlp_grad(wl_mlp* net, const float* feat, const float* tgt, int64_t n, 
   }
   return WL_OK;
 }
+// Degree-3 series diagonal and the scale of the remainder at row r (the exact low-order
+// part of diag phi and the size of what is left, which the network learns):
+//   base  = 1 + c2m d + c3 tri2           (diag q_2 = (1 - mu) d, diag q_3 = (A^3)_rr)
+//   scale = c4 max(1, d^2 + S2),  S2 = sum_{j in N(r)} d_j   (bounds the 4-walk count)
+__device__ inline void surrogate_terms(int64_t r, const int32_t* __restrict__ rowptr,
+                                       const int32_t* __restrict__ colidx, const unsigned long long* __restrict__ tri2,
+                                       double c2m, double c3, double c4, double* base, double* scale) {
+  const int32_t a = rowptr[r], e = rowptr[r + 1];
+  const double d = e - a;
+  double s2 = 0.0;
+  for (int32_t k = a; k < e; ++k) {
+    const int32_t j = colidx[k];
+    s2 += (double)(rowptr[j + 1] - rowptr[j]);
+  }
+  *base = 1.0 + c2m * d + c3 * (double)tri2[r];
+  *scale = c4 * fmax(1.0, d * d + s2);
+}
+
+template <typename T>
+__global__ void k_surrogate_diag(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                 const unsigned long long* __restrict__ tri2, double c2m, double c3, double c4,
+                                 T* __restrict__ base, T* __restrict__ scale) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double bs, sc;
+    surrogate_terms(r, rowptr, colidx, tri2, c2m, c3, c4, &bs, &sc);
+    if (base) base[r] = (T)bs;
+    if (scale) scale[r] = (T)sc;
+  }
+}
+
+// out[j] = (d[j] - base(nodes[j])) / scale(nodes[j]) in place (d: diag phi at the nodes)
+template <typename T>
+__global__ void k_surrogate_target(int64_t count, const int32_t* __restrict__ nodes,
+                                   const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                   const unsigned long long* __restrict__ tri2, double c2m, double c3, double c4,
+                                   T* __restrict__ d) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < count; j += (int64_t)gridDim.x * blockDim.x) {
+    double bs, sc;
+    surrogate_terms(nodes[j], rowptr, colidx, tri2, c2m, c3, c4, &bs, &sc);
+    d[j] = (T)(((double)d[j] - bs) / sc);
+  }
+}
+
+__global__ void k_affine(int64_t n, const float* __restrict__ base, const float* __restrict__ scale,
+                         float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (base ? base[i] : 0.f) + (scale ? scale[i] : 1.f) * y[i];
+}
+
+// c_2 (1 - mu), c_3, c_4 of the operator's weights
+void surrogate_coeffs(const wl_op* op, double* c2m, double* c3, double* c4) {
+  const double p = op->d.param;
+  const bool ex = op->d.func == WL_F_EXP;
+  *c2m = (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
+  *c3 = ex ? p * p * p / 6.0 : p * p * p;
+  *c4 = ex ? p * p * p * p / 24.0 : p * p * p * p;
+}
+
 }  // namespace
 
 wl_status graph_tri2(wl_graph* g, const unsigned long long** out) {
@@ -415,6 +473,58 @@ wl_status wl_diag_exact(wl_op* op, const int32_t* d_nodes, int64_t count, int32_
     WL_HIP(hipGetLastError());
   }
   WL_HIP(hipStreamSynchronize(st));
+  return WL_OK;
+}
+
+wl_status wl_surrogate_diag(wl_op* op, void* d_base, void* d_scale) {
+  WL_CHECK(op, WL_EINVAL, "wl_surrogate_diag: op is null");
+  wl_graph* g = op->g;
+  WL_CHECK(g->n == 0 || d_base || d_scale, WL_EINVAL, "wl_surrogate_diag: no output");
+  if (g->n == 0) return WL_OK;
+  (void)hipSetDevice(g->ctx->device);
+  const unsigned long long* tri = nullptr;
+  WL_TRY(graph_tri2(g, &tri));
+  double c2m, c3, c4;
+  surrogate_coeffs(op, &c2m, &c3, &c4);
+  const int gb = (int)std::min<int64_t>(8192, (g->n + 255) / 256);
+  if (op->d.prec == WL_FP32)
+    hipLaunchKernelGGL(k_surrogate_diag<float>, dim3(gb), dim3(256), 0, g->ctx->stream, g->n, g->rowptr, g->colidx,
+                       tri, c2m, c3, c4, (float*)d_base, (float*)d_scale);
+  else
+    hipLaunchKernelGGL(k_surrogate_diag<double>, dim3(gb), dim3(256), 0, g->ctx->stream, g->n, g->rowptr,
+                       g->colidx, tri, c2m, c3, c4, (double*)d_base, (double*)d_scale);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status wl_surrogate_target(wl_op* op, const int32_t* d_nodes, int64_t count, int32_t width, void* d_out) {
+  WL_TRY(wl_diag_exact(op, d_nodes, count, width, d_out));
+  if (count == 0) return WL_OK;
+  wl_graph* g = op->g;
+  const unsigned long long* tri = nullptr;
+  WL_TRY(graph_tri2(g, &tri));
+  double c2m, c3, c4;
+  surrogate_coeffs(op, &c2m, &c3, &c4);
+  const int gb = (int)std::min<int64_t>(8192, (count + 255) / 256);
+  if (op->d.prec == WL_FP32)
+    hipLaunchKernelGGL(k_surrogate_target<float>, dim3(gb), dim3(256), 0, g->ctx->stream, count, d_nodes,
+                       g->rowptr, g->colidx, tri, c2m, c3, c4, (float*)d_out);
+  else
+    hipLaunchKernelGGL(k_surrogate_target<double>, dim3(gb), dim3(256), 0, g->ctx->stream, count, d_nodes,
+                       g->rowptr, g->colidx, tri, c2m, c3, c4, (double*)d_out);
+  WL_HIP(hipGetLastError());
+  WL_HIP(hipStreamSynchronize(g->ctx->stream));
+  return WL_OK;
+}
+
+wl_status wl_mlp_predict(wl_mlp* net, const void* d_feat, int64_t n, const void* d_base, const void* d_scale,
+                         void* d_out) {
+  WL_TRY(wl_mlp_forward(net, d_feat, n, d_out));
+  if (n == 0) return WL_OK;
+  const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(k_affine, dim3(grid), dim3(256), 0, net->ctx->stream, n, (const float*)d_base,
+                     (const float*)d_scale, (float*)d_out);
+  WL_HIP(hipGetLastError());
   return WL_OK;
 }
 

@@ -132,3 +132,40 @@ def test_training_reduces_loss_and_cv_helps(ctx, lib):
         errs_plain.append(np.linalg.norm(estimators.hutchinson_diag(Om, Y) - d) / np.linalg.norm(d - 1))
         errs_cv.append(np.linalg.norm(estimators.cv_diag(Om, Y, ghat) - d) / np.linalg.norm(d - 1))
     assert np.mean(errs_cv) < 0.5 * np.mean(errs_plain)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("mu,kind", [(0.5, "exp"), (1.0, "res"), (0.0, "exp")])
+def test_surrogate_terms_and_targets(ctx, lib, dtype, tol, mu, kind):
+    """Degree-3 diagonal and remainder scale per node, and the residual training targets
+    (diag phi - base) / scale, against the dense oracle."""
+    from oracle import features as ofeat
+    n = 500
+    rp, ci = synth.erdos_renyi_gnm(n, 2500, 6)
+    A = walks.adjacency(n, rp, ci)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    g = lib.Graph(ctx, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    param = 1.0 / lam if kind == "exp" else 0.5 / lam
+    op = lib.Operator(g, mu, kind, param, dtype=td, krylov_dim=40)
+    base, scale = op.surrogate_diag()
+    rb, rs = ofeat.surrogate_terms(A, mu, kind, param)
+    np.testing.assert_allclose(base.cpu().numpy(), rb, rtol=tol)
+    np.testing.assert_allclose(scale.cpu().numpy(), rs, rtol=tol)
+    nodes = np.arange(0, n, 7, dtype=np.int32)
+    tgt = op.surrogate_target(nodes, width=16).cpu().numpy().astype(np.float64)
+    ref = (np.diag(genfun.phi(A, mu, kind, param))[nodes] - rb[nodes]) / rs[nodes]
+    # the remainder is small next to diag phi: compare against the remainder's own size
+    assert np.abs(tgt - ref).max() <= (tol * 50 if dtype == "f32" else 1e-6) * max(1.0, np.abs(ref).max())
+
+
+def test_mlp_predict_is_affine_forward(ctx, lib):
+    net = lib.MLP(ctx, synth.glorot_params(mlp.SIZES, 4))
+    rng = np.random.default_rng(0)
+    F = torch.tensor(rng.standard_normal((1000, 8)), dtype=torch.float32, device="cuda")
+    base = torch.tensor(rng.standard_normal(1000), dtype=torch.float32, device="cuda")
+    scale = torch.tensor(rng.random(1000), dtype=torch.float32, device="cuda")
+    y = net.forward(F)
+    p = net.predict(F, base, scale)
+    np.testing.assert_allclose(p.cpu().numpy(), (base + scale * y).cpu().numpy(), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(net.predict(F).cpu().numpy(), y.cpu().numpy(), rtol=0, atol=0)
