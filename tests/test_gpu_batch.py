@@ -112,3 +112,29 @@ def test_batch_graph_replays_match_eager(setup, lib):
         np.testing.assert_array_equal(ph_g, ph_e)
         np.testing.assert_array_equal(pe_g, pe_e)
     gr.close()
+
+
+def test_batch_diffusion_on_hub_graphs(lib):
+    """Power-law graphs with hubs (a few large, fast-converging Ritz values of L) and a
+    block model in one batch: exp(-t L) U0 against the dense oracle at t = 1 and 10."""
+    print("[gpu] batch hub graphs", flush=True)
+    ctx = lib.Context(0)
+    gs = [(3000,) + synth.configuration_model_powerlaw(3000, 2.5, 2, 55, 41),
+          (2000,) + synth.stochastic_block_model(2000, 8, 10, 20, 42)]
+    graphs, descs, phis = [], [], []
+    for n, rp, ci in gs:
+        A = walks.adjacency(n, rp, ci)
+        lam = np.linalg.eigvalsh(A)[-1]
+        graphs.append(lib.Graph(ctx, rp, ci))
+        descs.append({"mu": 0.5, "func": "res", "param": 0.5 / lam, "rho_hint": lam})
+        phis.append(genfun.phi(A, 0.5, "res", 0.5 / lam))
+    batch = lib.Batch(ctx, graphs, descs, tol=1e-10)
+    b = 8
+    Oms = [philox.gaussian(ph.shape[0], b, 70 + i).astype(np.float32).astype(np.float64) for i, ph in enumerate(phis)]
+    U0 = batch.pack([torch.tensor(o, dtype=torch.float32, device="cuda") for o in Oms])
+    for t in (1.0, 10.0):
+        Y, _, _ = batch.expv(U0, [t, t], outer_dim=30)
+        for i, (ph, om, y) in enumerate(zip(phis, Oms, batch.unpack(Y))):
+            (ref,) = laplacian.expv(laplacian.walk_laplacian(ph), om, [t])
+            err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref)
+            assert err < 1e-4, (t, i, err)

@@ -155,8 +155,10 @@ def test_surrogate_terms_and_targets(ctx, lib, dtype, tol, mu, kind):
     nodes = np.arange(0, n, 7, dtype=np.int32)
     tgt = op.surrogate_target(nodes, width=16).cpu().numpy().astype(np.float64)
     ref = (np.diag(genfun.phi(A, mu, kind, param))[nodes] - rb[nodes]) / rs[nodes]
-    # the remainder is small next to diag phi: compare against the remainder's own size
-    assert np.abs(tgt - ref).max() <= (tol * 50 if dtype == "f32" else 1e-6) * max(1.0, np.abs(ref).max())
+    # in units of diag phi (~1) the error is that of diag phi itself (the FP32 / FP64
+    # contract); the target divides it by the small scale
+    err_phi = np.abs(tgt - ref) * rs[nodes]
+    assert err_phi.max() <= (2e-5 if dtype == "f32" else 1e-10), err_phi.max()
 
 
 def test_mlp_predict_is_affine_forward(ctx, lib):
