@@ -155,7 +155,8 @@ def run_batch512(args):
     Kg = batch.series_degrees.astype(np.int64)
     offs = np.append(batch.offsets, batch.total_rows)
     npad = np.diff(offs)
-    log(f"batch rows {batch.total_rows}, series degrees {Kg.min()}..{Kg.max()} (mean {Kg.mean():.1f})")
+    log(f"batch rows {batch.total_rows}, series degrees {Kg.min()}..{Kg.max()} (mean {Kg.mean():.1f}); "
+        f"XCD-grouped tile order chosen: {batch.xcd_grouped}")
     # 8 Gaussian probes per graph (Philox), zero on the padding rows
     U0 = wl.probes(ctx, batch.total_rows, b, seed=11)
     keep = torch.zeros(batch.total_rows, dtype=torch.bool, device="cuda")
@@ -219,6 +220,7 @@ def run_batch512(args):
             "block": b,
             "krylov_dim": K_out,
             "series_degree_max": int(Kg.max()),
+            "xcd_grouped_tiles": batch.xcd_grouped,
         },
         "roofline": {
             "bound": "hbm",

@@ -296,7 +296,11 @@ wl_status wl_multi_destroy(wl_multi* multi);
  * wl_batch_info: any output may be NULL; row_offsets (int64) and series_degrees
  * (int32, the truncation degree K_g of graph g's series) are host arrays of ngraphs.
  * wl_batch_autotune: times SpMM launch shapes on the concatenated graph for b columns
- * (as wl_autotune) and keeps the fastest for the batch's sparse products.
+ * (as wl_autotune) and keeps the fastest for the batch's sparse products; then times
+ * the XCD-grouped tile order (every graph's row tiles on one XCD, so its gathered rows
+ * stay in that XCD's L2) against the plain order and keeps the faster (plain until
+ * tuned).  wl_batch_tile_order reports the choice (1: XCD-grouped);
+ * wl_batch_set_tile_order sets it (results do not depend on it).
  * wl_batch_apply_L: Y = L_g X_g for every graph (d_X, d_Y: total_rows x b).
  * wl_batch_expv: Y_g = exp(-t_g L_g) U0_g for every graph (t: host array of ngraphs
  * times) by outer_dim block Lanczos steps per graph, the projected exponential
@@ -311,6 +315,8 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
 wl_status wl_batch_info(const wl_batch* batch, int64_t* total_rows, int32_t* max_series_degree,
                         int64_t* row_offsets, int32_t* series_degrees);
 wl_status wl_batch_autotune(wl_batch* batch, int32_t b);
+wl_status wl_batch_tile_order(const wl_batch* batch, int32_t* xcd_grouped);
+wl_status wl_batch_set_tile_order(wl_batch* batch, int32_t xcd_grouped);
 wl_status wl_batch_apply_L(wl_batch* batch, const void* d_X, void* d_Y, int32_t b);
 wl_status wl_batch_expv(wl_batch* batch, const void* d_U0, int32_t b, const double* t, int32_t outer_dim, void* d_Y,
                         double* p_hat, double* p_err);

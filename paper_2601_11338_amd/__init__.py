@@ -533,6 +533,16 @@ class Batch:
     def autotune(self, b):
         check(load().wl_batch_autotune(self.handle, int(b)))
 
+    @property
+    def xcd_grouped(self):
+        v = C.c_int32()
+        check(load().wl_batch_tile_order(self.handle, C.byref(v)))
+        return bool(v.value)
+
+    @xcd_grouped.setter
+    def xcd_grouped(self, on):
+        check(load().wl_batch_set_tile_order(self.handle, 1 if on else 0))
+
     def _blocks(self, X, out):
         torch = _torch()
         _need(X, "X", torch.float32, (self.total_rows, None))

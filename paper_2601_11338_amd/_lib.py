@@ -86,6 +86,8 @@ SIGNATURES = {
     "wl_batch_create": (C.c_int, [vp, i32, vp, vp, f64, C.POINTER(vp)]),
     "wl_batch_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32), vp, vp]),
     "wl_batch_autotune": (C.c_int, [vp, i32]),
+    "wl_batch_tile_order": (C.c_int, [vp, C.POINTER(i32)]),
+    "wl_batch_set_tile_order": (C.c_int, [vp, i32]),
     "wl_batch_apply_L": (C.c_int, [vp, vp, vp, i32]),
     "wl_batch_expv": (C.c_int, [vp, vp, i32, pd, i32, vp, pd, pd]),
     "wl_batch_destroy": (C.c_int, [vp]),

@@ -304,6 +304,7 @@ struct wl_batch {
   DevBuf ones;
   BatchWork work;  // scratch of the eager entry points
   XcdTileMap xmap;  // every graph's row tiles on one XCD
+  bool use_xmap = false;  // chosen by wl_batch_autotune (timed against the plain order)
   int graphs = 0;  // live captured graphs (they hold pointers into the batch)
 };
 
@@ -360,7 +361,7 @@ wl_status batch_phi(wl_batch* bt, BatchWork& wk, const float* X, float* Y, int b
   const int64_t tstride = (int64_t)bt->ng * 5;
   {
     EpiArgs<float> ep;
-    ep.xmap = &bt->xmap;
+    ep.xmap = bt->use_xmap ? &bt->xmap : nullptr;
     ep.gid = bt->gid.as<int32_t>();
     ep.gtab = tab;
     ep.Sin = X;
@@ -377,7 +378,7 @@ wl_status batch_phi(wl_batch* bt, BatchWork& wk, const float* X, float* Y, int b
   float* Pm1 = A;
   for (int k = 2; k <= bt->Kmax; ++k) {
     EpiArgs<float> ep;
-    ep.xmap = &bt->xmap;
+    ep.xmap = bt->use_xmap ? &bt->xmap : nullptr;
     ep.gid = bt->gid.as<int32_t>();
     ep.gtab = tab + (int64_t)(k - 1) * tstride;
     ep.Z = Pm2;
@@ -791,7 +792,54 @@ wl_status wl_batch_info(const wl_batch* bt, int64_t* total_rows, int32_t* max_de
 
 wl_status wl_batch_autotune(wl_batch* bt, int32_t b) {
   WL_CHECK(bt, WL_EINVAL, "wl_batch_autotune: batch is null");
-  return wl_autotune(bt->G, WL_FP32, b);
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_batch_autotune: b must lie in [1, 64]");
+  WL_TRY(wl_autotune(bt->G, WL_FP32, b));
+  // then the tile order: XCD-grouped graphs against the plain order, timed on the
+  // batch's own series products (walk degrees' coefficients, no finish)
+  wl_ctx* ctx = bt->ctx;
+  DeviceGuard dg(ctx->device);
+  DevBuf X, Y;
+  WL_TRY(X.ensure((size_t)bt->N * b * 4));
+  WL_TRY(Y.ensure((size_t)bt->N * b * 4));
+  WL_TRY(launch_fill<float>(ctx, bt->N * b, 1.0f, X.as<float>()));
+  hipEvent_t e0, e1;
+  WL_HIP(hipEventCreate(&e0));
+  WL_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  bool best_map = false;
+  wl_status s = WL_OK;
+  for (int rep = 0; rep < 2 && s == WL_OK; ++rep)
+    for (int m = 0; m < 2 && s == WL_OK; ++m) {
+      bt->use_xmap = m == 1;
+      s = batch_phi(bt, bt->work, X.as<float>(), Y.as<float>(), b, false);  // warm
+      if (s != WL_OK) break;
+      (void)hipEventRecord(e0, ctx->stream);
+      s = batch_phi(bt, bt->work, X.as<float>(), Y.as<float>(), b, false);
+      (void)hipEventRecord(e1, ctx->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep == 1 && ms < best) {
+        best = ms;
+        best_map = bt->use_xmap;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bt->use_xmap = best_map;
+  return s;
+}
+
+wl_status wl_batch_tile_order(const wl_batch* bt, int32_t* xcd_grouped) {
+  WL_CHECK(bt && xcd_grouped, WL_EINVAL, "wl_batch_tile_order: null argument");
+  *xcd_grouped = bt->use_xmap ? 1 : 0;
+  return WL_OK;
+}
+
+wl_status wl_batch_set_tile_order(wl_batch* bt, int32_t xcd_grouped) {
+  WL_CHECK(bt, WL_EINVAL, "wl_batch_set_tile_order: batch is null");
+  bt->use_xmap = xcd_grouped != 0;
+  return WL_OK;
 }
 
 wl_status wl_batch_apply_L(wl_batch* bt, const void* d_X, void* d_Y, int32_t b) {

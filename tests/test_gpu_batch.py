@@ -67,6 +67,19 @@ def test_batch_apply_L(setup):
         assert err < 2e-5, (i, err)
 
 
+def test_batch_tile_order_does_not_change_results(setup):
+    """The XCD-grouped tile order only permutes which workgroup handles which rows."""
+    batch, phis, _ = setup
+    X = batch.pack([torch.tensor(synth.gaussian_block(ph.shape[0], 8, 30 + i), dtype=torch.float32, device="cuda")
+                    for i, ph in enumerate(phis)])
+    batch.xcd_grouped = False
+    Y0 = batch.apply_L(X)
+    batch.xcd_grouped = True
+    Y1 = batch.apply_L(X)
+    batch.xcd_grouped = False
+    assert torch.equal(Y0, Y1)
+
+
 def test_batch_expv_and_return_probability(setup):
     batch, phis, ts = setup
     b = 8
