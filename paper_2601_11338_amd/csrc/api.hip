@@ -60,6 +60,14 @@ double defl_tol() {
 // After the second CholQR pass the combined factor gives the true norm of every new
 // component; components below this fraction of the block's scale before projection
 // are rounding noise of the stored basis (~1e-7 FP32, ~1e-16 FP64) and are dropped.
+// A second CholQR pass is skipped when the first factor's kept pivots span less than
+// this ratio (orthogonality after one pass ~ u_64 kappa^2: 1e-8 for FP32 storage,
+// 1e-10 for FP64).
+template <typename T>
+double skip_ratio() {
+  return sizeof(T) == 4 ? 1e-8 : 1e-6;
+}
+
 template <typename T>
 double post_tol() {
   return sizeof(T) == 4 ? 1e-5 : 1e-10;
@@ -489,7 +497,8 @@ struct SmallLayout {
   size_t Cc() const { return (size_t)(2 * K + 6) * bb; }        // 3 blocks
   size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+2) blocks
   size_t Ref() const { return (size_t)(3 * K + 11) * bb; }      // one double: reference scale
-  size_t total() const { return (size_t)(3 * K + 12) * bb; }
+  size_t Skip() const { return Ref() + 1; }                     // one double: second pass not needed
+  size_t total() const { return Ref() + 2; }
 };
 
 // Runs K block Lanczos steps from X (n x b).  basis must hold (K+1) blocks, Wb one
@@ -540,15 +549,19 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
       WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,
                               S + Ly.G()));
       WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), 1, 0,
-                         nullptr, S + Ly.Ref(), ptol));
+                         nullptr, S + Ly.Ref(), ptol, S + Ly.Skip(), skip_ratio<T>()));
       if (j + 1 == K) {  // residual coupling B_{K-1} (a-posteriori error estimates)
         WL_TRY(launch_dcopy(ctx, b * b, S + Ly.R1(), S + Ly.B(j)));
         break;
       }
-      WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G()));
+      // the second CholQR pass runs only when the first factor was ill conditioned
+      // (device flag): otherwise its Gram and update return at once and B_j = R1
+      WL_TRY(launch_update_skip<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri1(), nullptr, 0.0, nullptr, 1.0, Vn, b, S + Ly.G(),
+                                   nullptr, S + Ly.Skip()));
       WL_TRY(launch_chol(ctx, b, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                         S + Ly.B(j)));
-      WL_TRY(launch_update<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr));
+                         S + Ly.B(j), 1, 0, nullptr, nullptr, 0.0, nullptr, 0.0, S + Ly.Skip()));
+      WL_TRY(launch_update_skip<T>(ctx, n, Vn, b, 0, 1, S + Ly.Ri2(), nullptr, 0.0, nullptr, 1.0, Vn, b, nullptr,
+                                   S + Ly.Skip(), nullptr));
     }
   }
   for (int j = 0; j < K && (ring || reorth > 1); ++j) {

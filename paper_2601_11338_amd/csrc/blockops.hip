@@ -93,7 +93,9 @@ __global__ __launch_bounds__(256) void k_gram_partial(int64_t n, const float* __
 // a block owns EB = min(E, 16) entries; thread (entry, phase p) sums q = p, p + P, ...
 // (P = 256 / EB), then the P phase sums are combined by a tree in LDS.
 __global__ __launch_bounds__(256) void k_gram_finalize(const double* __restrict__ partials, int nparts, int B,
-                                                       int bx, int by, double* __restrict__ out) {
+                                                       int bx, int by, double* __restrict__ out,
+                                                       const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;  // the caller does not need this Gram
   __shared__ double s[256];
   const int E = B * B;
   const int EB = E < 16 ? E : 16;
@@ -137,7 +139,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <int NT, int NB>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
                                                    int nblk, const float* __restrict__ Y, int ldy, int bx, int by,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials, const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;  // the caller does not need this Gram
   constexpr int B = 16 * NT;
   constexpr int TILE = 16 * B;  // floats per 16-row tile of one operand
   constexpr size_t TILE_BYTES = (size_t)4 * (NB + 1) * TILE * sizeof(float);
@@ -269,7 +272,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
 template <int B>
 __global__ __launch_bounds__(256) void k_update_f4(int64_t n, const float* X, int64_t sX, int nblk, int kc,
                                                    const double* __restrict__ C, const float* Yin, double alpha,
-                                                   const float* __restrict__ wv, double beta, float* Out) {
+                                                   const float* __restrict__ wv, double beta, float* Out,
+                                                   const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;  // identity update the caller elides
   constexpr int LPR = B / 4;
   constexpr int RPT = 256 / LPR;  // rows per tile
   extern __shared__ float sC[];   // kc blocks of B x B
@@ -534,10 +539,29 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
                                              double* __restrict__ R, double* __restrict__ Rinv,
                                              const double* __restrict__ Rprev, double* __restrict__ Bout,
                                              int64_t gs, double* __restrict__ ref_out, const double* ref_in,
-                                             double post_tol) {
+                                             double post_tol, double* skip_out, double skip_ratio,
+                                             const double* skip_in) {
   const int64_t go = (int64_t)blockIdx.x * gs;  // batch: graph g's matrices at +g gs
   if (ref_out) ref_out += go;
   if (ref_in) ref_in += go;
+  if (skip_out) skip_out += go;
+  if (skip_in) skip_in += go;
+  const int t = threadIdx.x;
+  if (skip_in && *skip_in != 0.0) {
+    // second pass not needed: identity factors, Bout = Rprev (the first pass's factor)
+    G += go;
+    if (R) R += go;
+    Rinv += go;
+    if (Rprev) Rprev += go;
+    if (Bout) Bout += go;
+    for (int e = t; e < b * b; e += 64) {
+      const double id = (e / b == e % b) ? 1.0 : 0.0;
+      if (R) R[e] = id;
+      Rinv[e] = id;
+      if (Bout) Bout[e] = Rprev ? Rprev[e] : id;
+    }
+    return;
+  }
   G += go;
   if (Aref) Aref += go;
   if (Bref) Bref += go;
@@ -549,7 +573,7 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
   __shared__ double sR[64 * 65];
   __shared__ int defl[64];
   __shared__ double sref;
-  const int t = threadIdx.x;
+  // (t defined above)
   for (int e = t; e < b * b; e += 64) {
     const int i = e / b, j = e % b;
     sG[i * 65 + j] = 0.5 * (G[i * b + j] + G[j * b + i]);
@@ -601,6 +625,23 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
         for (int j = 0; j < b; ++j) Bout[t * b + j] = 0.0;
         for (int i = 0; i < b; ++i) Rinv[i * b + t] = 0.0;
       }
+    }
+  }
+  // Is a second CholQR pass needed?  One pass with the Gram accumulated in FP64 leaves
+  // the new block orthonormal to about u_64 kappa^2; kappa^2 is the ratio of the largest
+  // to the smallest kept pivot.  skip_out = 1 when min / max >= skip_ratio.
+  if (skip_out) {
+    __syncthreads();
+    if (t == 0) {
+      double pmax = 0.0, pmin = INFINITY;
+      for (int k = 0; k < b; ++k) {
+        const double r = sR[k * 65 + k];
+        const bool kept = r > 0.0 && !(Bout && Bout[k * b + k] == 0.0);
+        if (!kept) continue;
+        pmax = fmax(pmax, r * r);
+        pmin = fmin(pmin, r * r);
+      }
+      *skip_out = (pmax == 0.0 || pmin >= skip_ratio * pmax) ? 1.0 : 0.0;
     }
   }
 }
@@ -838,7 +879,7 @@ int fin_grid(int E) {
 
 template <int B>
 wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64_t sX, int nblk, const void* Y,
-                 int ldy, int bx, int by, double* out) {
+                 int ldy, int bx, int by, double* out, const double* skip = nullptr) {
   constexpr int E = B * B;
   if constexpr (B >= 16) {
     if (isf) {
@@ -855,17 +896,17 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
       const float* Yf = (const float*)Y;
       if (NT >= 4 || nblk == 1) {
         hipLaunchKernelGGL((k_gram_mfma<NT, 1>), dim3((unsigned)blocks, nblk), dim3(256), 0, ctx->stream, n, Xf,
-                           ldx, sX, nblk, Yf, ldy, bx, by, pp);
+                           ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
       } else if (nblk == 2 || NT == 2) {
         hipLaunchKernelGGL((k_gram_mfma<NT, 2>), dim3((unsigned)blocks, (nblk + 1) / 2), dim3(256), 0, ctx->stream,
-                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp);
+                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
       } else {
         hipLaunchKernelGGL((k_gram_mfma<NT, 3>), dim3((unsigned)blocks, (nblk + 2) / 3), dim3(256), 0, ctx->stream,
-                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp);
+                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
       }
       WL_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
-                         ctx->partials.as<double>(), nparts, B, bx, by, out);
+                         ctx->partials.as<double>(), nparts, B, bx, by, out, skip);
       WL_HIP(hipGetLastError());
       return WL_OK;
     }
@@ -884,7 +925,7 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
                      ctx->partials.as<double>());
   WL_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
-                     ctx->partials.as<double>(), parts, B, bx, by, out);
+                     ctx->partials.as<double>(), parts, B, bx, by, out, nullptr);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -898,7 +939,7 @@ int pick_B(int b) {
 template <typename T, int B>
 wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int nblk, int bx, const double* C,
                    const T* Yin, int ldy, double alpha, const T* wv, double beta, T* Out, int by,
-                   double* gram_out) {
+                   double* gram_out, const double* skip, const double* skip_gram) {
   constexpr int E = B * B;
   if constexpr (sizeof(T) == 4 && B >= 4) {
     const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
@@ -911,9 +952,9 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
       const int kc = std::max(1, std::min(nblk, 12288 / (B * B)));
       const size_t lds = (size_t)kc * B * B * sizeof(float);
       hipLaunchKernelGGL((k_update_f4<B>), dim3(grid), dim3(256), lds, ctx->stream, n, (const float*)X, sX, nblk,
-                         kc, C, (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out);
+                         kc, C, (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out, skip);
       WL_HIP(hipGetLastError());
-      if (gram_out) return gram_B<B>(ctx, n, Out, true, B, 0, 1, Out, B, B, B, gram_out);
+      if (gram_out) return gram_B<B>(ctx, n, Out, true, B, 0, 1, Out, B, B, B, gram_out, skip_gram);
       return WL_OK;
     }
   }
@@ -930,7 +971,7 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
   WL_HIP(hipGetLastError());
   if (gram_out) {
     hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), 1), dim3(256), 0, ctx->stream, parts, grid, B, by, by,
-                       gram_out);
+                       gram_out, nullptr);
     WL_HIP(hipGetLastError());
   }
   return WL_OK;
@@ -956,19 +997,34 @@ wl_status launch_gram(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, in
 }
 
 template <typename T>
-wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
-                        const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out) {
+wl_status launch_update_skip(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
+                             const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out,
+                             const double* skip, const double* skip_gram) {
   WL_CHECK(bx >= 1 && bx <= 64 && by >= 1 && by <= 64, WL_EINVAL, "update: block sizes out of range");
   const int B = pick_B(bx > by ? bx : by);
   switch (B) {
-    case 1: return update_B<T, 1>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    case 2: return update_B<T, 2>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    case 4: return update_B<T, 4>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    case 8: return update_B<T, 8>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    case 16: return update_B<T, 16>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    case 32: return update_B<T, 32>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
-    default: return update_B<T, 64>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out);
+    case 1: return update_B<T, 1>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    case 2: return update_B<T, 2>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    case 4: return update_B<T, 4>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    case 8: return update_B<T, 8>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    case 16: return update_B<T, 16>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    case 32: return update_B<T, 32>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
+    default: return update_B<T, 64>(ctx, n, X, bx, sX, nblk, bx, C, Yin, by, alpha, wv, beta, Out, by, gram_out,
+                                                   skip, skip_gram);
   }
+}
+
+template <typename T>
+wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
+                        const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out) {
+  return launch_update_skip<T>(ctx, n, X, bx, sX, nblk, C, Yin, alpha, wv, beta, Out, by, gram_out, nullptr,
+                               nullptr);
 }
 
 wl_status launch_lanczos_proj(wl_ctx* ctx, int b, int nbv, const double* P, double* Aout, double* Cc,
@@ -982,10 +1038,11 @@ wl_status launch_lanczos_proj(wl_ctx* ctx, int b, int nbv, const double* P, doub
 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs,
-                      double* ref_out, const double* ref_in, double post_tol) {
+                      double* ref_out, const double* ref_in, double post_tol, double* skip_out, double skip_ratio,
+                      const double* skip_in) {
   WL_CHECK(b >= 1 && b <= 64 && ngraphs >= 1, WL_EINVAL, "chol: b out of range");
   hipLaunchKernelGGL(k_chol, dim3(ngraphs), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout,
-                     gs, ref_out, ref_in, post_tol);
+                     gs, ref_out, ref_in, post_tol, skip_out, skip_ratio, skip_in);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -1092,6 +1149,9 @@ wl_status launch_nys_diag(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y
   template wl_status launch_gram<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const T*, int, double*);        \
   template wl_status launch_update<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const double*, const T*,      \
                                       double, const T*, double, T*, int, double*);                                 \
+  template wl_status launch_update_skip<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const double*, const T*, \
+                                           double, const T*, double, T*, int, double*, const double*,             \
+                                           const double*);                                                         \
   template wl_status launch_fill<T>(wl_ctx*, int64_t, T, T*);                                                      \
   template wl_status launch_axpby_rows<T>(wl_ctx*, int64_t, int, const T*, const T*, double, const T*, T*);       \
   template wl_status launch_degrees<T>(wl_graph*, T*);                                                              \

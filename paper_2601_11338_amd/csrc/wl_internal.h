@@ -236,6 +236,13 @@ wl_status launch_gram(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, in
 template <typename T>
 wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
                         const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out);
+// The same with device flags (may be NULL): when *skip != 0 the update is an identity
+// the caller elides (the kernel returns at once); when *skip_gram != 0 the Gram of the
+// output is not needed.  Only the FP32 block paths honour them (others compute).
+template <typename T>
+wl_status launch_update_skip(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, int nblk, const double* C,
+                             const T* Yin, double alpha, const T* wv, double beta, T* Out, int by, double* gram_out,
+                             const double* skip, const double* skip_gram);
 
 // Cholesky with deflation of the b x b Gram G (double, device):
 //   G = R^T R, R upper; Rinv the inverse on the non-deflated columns (zero elsewhere).
@@ -250,7 +257,12 @@ wl_status launch_update(wl_ctx* ctx, int64_t n, const T* X, int bx, int64_t sX, 
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs = 1,
                       int64_t gs = 0, double* ref_out = nullptr, const double* ref_in = nullptr,
-                      double post_tol = 0.0);
+                      double post_tol = 0.0, double* skip_out = nullptr, double skip_ratio = 0.0,
+                      const double* skip_in = nullptr);
+// skip_out (one double): 1 when the kept pivots satisfy min / max >= skip_ratio (a
+// second CholQR pass would change nothing at working precision), else 0.  skip_in:
+// when *skip_in != 0 the kernel only writes identity factors (R, Rinv) and
+// Bout = Rprev, standing in for a second pass that was not needed.
 
 // One block Lanczos projection: from P = [V_{j-1}^T W'; V_j^T W'; W'^T W'] (nbv = 2) or
 // [V_j^T W'; W'^T W'] (nbv = 1) form A_j = sym(V_j^T W') (Aout), Cc = [-P1; -A_j; I] with
