@@ -69,19 +69,20 @@ def copy_calibration():
                       "GBps": 5 * 2 * src.numel() * 4 / dt / 1e9}), flush=True)
 
 
-def measured_traffic(n, m, b):
+def measured_traffic(n, m, b, lanes):
     """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
     WRITE_SIZE counter runs, scaled by the copy-kernel calibration; None when the
-    kernel source changed since the counters were taken or the workload differs."""
+    kernel source changed since the counters were taken, the workload differs or the
+    autotuner picked another launch shape."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_spmm_recurrence_ba1m_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_spmm_b16_ba1m_traffic.json")
     src = os.path.join(ROOT, "paper_2601_11338_amd", "csrc", "spmm.hip")
     try:
         rec = json.load(open(path))
         sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if sha != rec.get("source_sha1") or (n, m, b) != (1000000, 5, 16):
+    if sha != rec.get("source_sha1") or (n, m, b) != (1000000, 5, 16) or rec.get("lanes_per_row") != lanes:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -644,8 +645,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(n, m, b),
-            "kernel": "k_spmm<float,4,4,G> (b=16: series steps and Lanczos operator products)",
+            "traffic": measured_traffic(n, m, b, g.shape(torch.float32, b)[0]),
+            "kernel": f"k_spmm<float,4,4,{g.shape(torch.float32, b)[0]}> (b=16: series steps and Lanczos operator "
+                      f"products)",
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
             "side_by_side_kernel": {"launches": mul[0], "avg_launch_us": mul_avg * 1e3, "achieved": mul_gbs},

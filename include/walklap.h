@@ -157,6 +157,10 @@ wl_status wl_spmm(wl_graph* g, int32_t prec, const void* d_X, void* d_Y, int32_t
  * by timing candidates on this graph; the choice is kept in the graph.  Without
  * it a heuristic from the mean degree is used.  Enqueues and synchronises.     */
 wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b);
+/* The launch shape used for (prec, b): lanes per row (the kernel's row group size,
+ * rounded up to a power of two >= the lanes one row segment needs) and the degree
+ * above which a row gets a whole workgroup.  Either output may be NULL.           */
+wl_status wl_graph_shape(wl_graph* g, int32_t prec, int32_t b, int32_t* lanes_per_row, int32_t* long_row_threshold);
 
 /* Largest adjacency eigenvalue lambda_max(A) = rho(A) by Lanczos (double).  Used
  * for beta ~ 1/rho(A) (Sec. 4.1.2).  tol: relative.                              */

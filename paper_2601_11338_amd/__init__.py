@@ -153,6 +153,12 @@ class Graph:
     def autotune(self, dtype, b):
         check(load().wl_autotune(self.handle, _prec_of(dtype), b))
 
+    def shape(self, dtype, b):
+        """(lanes per row, long-row threshold) used for (dtype, b)."""
+        g, t = C.c_int32(), C.c_int32()
+        check(load().wl_graph_shape(self.handle, _prec_of(dtype), b, C.byref(g), C.byref(t)))
+        return g.value, t.value
+
     def lambda_max(self, tol=1e-12):
         out = C.c_double()
         check(load().wl_lambda_max(self.handle, tol, C.byref(out)))

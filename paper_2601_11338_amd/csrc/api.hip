@@ -428,7 +428,9 @@ wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b) {
     WL_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     WL_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
+    // a later candidate must win by 3% (timing noise would otherwise flip between
+    // near-equal shapes from run to run)
+    if (ms < 0.97f * best) {
       best = ms;
       bests = s;
     }
@@ -436,6 +438,16 @@ wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   g->tuned[prec * 1000 + std::min(b, 999)] = bests;
+  return WL_OK;
+}
+
+wl_status wl_graph_shape(wl_graph* g, int32_t prec, int32_t b, int32_t* lanes_per_row, int32_t* long_row_threshold) {
+  WL_CHECK(g, WL_EINVAL, "wl_graph_shape: graph is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_graph_shape: bad prec");
+  WL_CHECK(b >= 1 && b <= 4096, WL_EINVAL, "wl_graph_shape: b out of range");
+  const SpmmShape s = shape_for(g, prec, b);
+  if (lanes_per_row) *lanes_per_row = s.G;
+  if (long_row_threshold) *long_row_threshold = s.long_thr;
   return WL_OK;
 }
 
