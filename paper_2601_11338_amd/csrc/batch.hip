@@ -95,38 +95,88 @@ __global__ __launch_bounds__(256) void k_gram_seg_finalize(const double* __restr
   }
 }
 
-// Out[r] = (wv ? wv[r] : alpha) Yin[r] + beta sum_k X_k[r] C_{g(r)}[k]   (b <= 16),
-// C_g = C + g * cgs, (nblk b) x b row-major double.
+// Out[r] = (wv ? wv[r] : alpha) Yin[r] + beta sum_k X_k[r] C_{g(r)}[k]   (b <= B <= 16),
+// C_g = C + g * cgs, (nblk b) x b row-major double.  One row per thread; a workgroup's
+// 256 consecutive rows nearly always belong to one graph (graphs span >= 64 aligned
+// rows), whose coefficients are staged in LDS as float once per graph change (rows of
+// another graph read theirs from memory).  Rows of exactly B floats load as float4.
 template <int B>
 __global__ __launch_bounds__(256) void k_update_seg(int64_t N, const float* X, int64_t sX, int nblk, int b,
                                                     const double* __restrict__ C, int64_t cgs,
                                                     const int32_t* __restrict__ gid, const float* Yin, double alpha,
                                                     const float* __restrict__ wv, double beta, float* Out) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
-    const double* Cg = C + (int64_t)gid[r] * cgs;
+  extern __shared__ float sCg[];  // nblk * b * b
+  const int cb = nblk * b * b;
+  const bool vec = b == B;
+  int staged = -1;
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < N; r0 += (int64_t)gridDim.x * blockDim.x) {
+    const int g0 = gid[r0];  // the same for the whole workgroup
+    if (g0 != staged) {
+      __syncthreads();
+      const double* Cg = C + (int64_t)g0 * cgs;
+      for (int e = threadIdx.x; e < cb; e += blockDim.x) sCg[e] = (float)Cg[e];
+      __syncthreads();
+      staged = g0;
+    }
+    const int64_t r = r0 + threadIdx.x;
+    if (r >= N) continue;
+    const int gr = gid[r];
+    const double* Cglob = C + (int64_t)gr * cgs;
     float acc[B];
 #pragma unroll
     for (int j = 0; j < B; ++j) acc[j] = 0.f;
     for (int k = 0; k < nblk; ++k) {
       const float* xr = X + (int64_t)k * sX + r * b;
       float xv[B];
+      if (vec) {
 #pragma unroll
-      for (int i = 0; i < B; ++i) xv[i] = i < b ? xr[i] : 0.f;
-      const double* Ck = Cg + (int64_t)k * b * b;
+        for (int q = 0; q < B / 4; ++q) {
+          const float4 v = reinterpret_cast<const float4*>(xr)[q];
+          xv[4 * q] = v.x;
+          xv[4 * q + 1] = v.y;
+          xv[4 * q + 2] = v.z;
+          xv[4 * q + 3] = v.w;
+        }
+      } else {
 #pragma unroll
-      for (int i = 0; i < B; ++i) {
-        if (i >= b) break;
+        for (int i = 0; i < B; ++i) xv[i] = i < b ? xr[i] : 0.f;
+      }
+      if (gr == g0) {
+        const float* Ck = sCg + k * b * b;
 #pragma unroll
-        for (int j = 0; j < B; ++j)
-          if (j < b) acc[j] += xv[i] * (float)Ck[i * b + j];
+        for (int i = 0; i < B; ++i) {
+          if (i >= b) break;
+#pragma unroll
+          for (int j = 0; j < B; ++j)
+            if (j < b) acc[j] += xv[i] * Ck[i * b + j];
+        }
+      } else {
+        const double* Ck = Cglob + (int64_t)k * b * b;
+        for (int i = 0; i < b; ++i)
+#pragma unroll
+          for (int j = 0; j < B; ++j)
+            if (j < b) acc[j] += xv[i] * (float)Ck[i * b + j];
       }
     }
     const float sc = wv ? wv[r] : (float)alpha;
     float* o = Out + r * b;
     const float* y = Yin ? Yin + r * b : nullptr;
+    if (vec) {
 #pragma unroll
-    for (int j = 0; j < B; ++j)
-      if (j < b) o[j] = (float)beta * acc[j] + (y ? sc * y[j] : 0.f);
+      for (int q = 0; q < B / 4; ++q) {
+        float4 v;
+        const float4 yy = y ? reinterpret_cast<const float4*>(y)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        v.x = (float)beta * acc[4 * q] + sc * yy.x;
+        v.y = (float)beta * acc[4 * q + 1] + sc * yy.y;
+        v.z = (float)beta * acc[4 * q + 2] + sc * yy.z;
+        v.w = (float)beta * acc[4 * q + 3] + sc * yy.w;
+        reinterpret_cast<float4*>(o)[q] = v;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < B; ++j)
+        if (j < b) o[j] = (float)beta * acc[j] + (y ? sc * y[j] : 0.f);
+    }
   }
 }
 
@@ -337,12 +387,23 @@ wl_status batch_gram(wl_batch* bt, BatchWork& wk, const float* X, int64_t sX, in
 wl_status batch_update(wl_batch* bt, const float* X, int64_t sX, int nblk, int b, const double* C, int64_t cgs,
                        const float* Yin, double alpha, const float* wv, double beta, float* Out) {
   const int grid = (int)std::min<int64_t>(8192, (bt->N + 255) / 256);
-  if (b <= 8)
-    hipLaunchKernelGGL((k_update_seg<8>), dim3(grid), dim3(256), 0, bt->ctx->stream, bt->N, X, sX, nblk, b, C, cgs,
-                       bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+  const size_t lds = (size_t)nblk * b * b * sizeof(float);
+  WL_CHECK(lds <= 64 * 1024, WL_EINVAL, "batched update: %d coefficient blocks of %d x %d exceed 64 KiB", nblk, b, b);
+  // float4 row loads need 16-byte aligned rows: b a multiple of 4 and aligned bases
+  const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
+                    reinterpret_cast<uintptr_t>(Yin)) & 15u) == 0 && (sX % 4) == 0;
+  if (b <= 8 && (b == 8 ? al : true))
+    hipLaunchKernelGGL((k_update_seg<8>), dim3(grid), dim3(256), lds, bt->ctx->stream, bt->N, X, sX, nblk, b, C,
+                       cgs, bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+  else if (b <= 8)
+    hipLaunchKernelGGL((k_update_seg<9>), dim3(grid), dim3(256), lds, bt->ctx->stream, bt->N, X, sX, nblk, b, C,
+                       cgs, bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+  else if (b == 16 && al)
+    hipLaunchKernelGGL((k_update_seg<16>), dim3(grid), dim3(256), lds, bt->ctx->stream, bt->N, X, sX, nblk, b, C,
+                       cgs, bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
   else
-    hipLaunchKernelGGL((k_update_seg<16>), dim3(grid), dim3(256), 0, bt->ctx->stream, bt->N, X, sX, nblk, b, C, cgs,
-                       bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
+    hipLaunchKernelGGL((k_update_seg<17>), dim3(grid), dim3(256), lds, bt->ctx->stream, bt->N, X, sX, nblk, b, C,
+                       cgs, bt->gid.as<int32_t>(), Yin, alpha, wv, beta, Out);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
