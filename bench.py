@@ -582,8 +582,8 @@ def main():
         for si, ts in enumerate(tstreams):
             c = wl.Context(0, stream=ts.cuda_stream)
             gi = wl.Graph(c, g.rowptr, g.colidx)
-            gi.autotune(torch.float32, b)
-            gi.autotune(torch.float32, 1)
+            for bb in (b, 1):  # the main handle's tuned shapes: one kernel instantiation per width
+                gi.set_shape(torch.float32, bb, *g.shape(torch.float32, bb))
             ctxs.append(c)
             workers.append({"ctx": c, "graph": gi, "ops": [], "W": torch.empty((n, 1), dtype=torch.float32,
                                                                                 device="cuda"),

@@ -161,6 +161,11 @@ wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b);
  * rounded up to a power of two >= the lanes one row segment needs) and the degree
  * above which a row gets a whole workgroup.  Either output may be NULL.           */
 wl_status wl_graph_shape(wl_graph* g, int32_t prec, int32_t b, int32_t* lanes_per_row, int32_t* long_row_threshold);
+/* Set the launch shape for (prec, b) explicitly (e.g. to give several graph handles
+ * of one CSR the shape one of them was tuned to): lanes per row a power of two in
+ * [1, 64] (raised to what one row segment needs), threshold >= 1 (raised to the
+ * graph's minimum long-row degree).                                                */
+wl_status wl_graph_set_shape(wl_graph* g, int32_t prec, int32_t b, int32_t lanes_per_row, int32_t long_row_threshold);
 
 /* Largest adjacency eigenvalue lambda_max(A) = rho(A) by Lanczos (double).  Used
  * for beta ~ 1/rho(A) (Sec. 4.1.2).  tol: relative.                              */

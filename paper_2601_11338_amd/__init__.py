@@ -159,6 +159,10 @@ class Graph:
         check(load().wl_graph_shape(self.handle, _prec_of(dtype), b, C.byref(g), C.byref(t)))
         return g.value, t.value
 
+    def set_shape(self, dtype, b, lanes_per_row, long_row_threshold):
+        check(load().wl_graph_set_shape(self.handle, _prec_of(dtype), b, int(lanes_per_row),
+                                        int(long_row_threshold)))
+
     def lambda_max(self, tol=1e-12):
         out = C.c_double()
         check(load().wl_lambda_max(self.handle, tol, C.byref(out)))

@@ -54,6 +54,7 @@ SIGNATURES = {
     "wl_spmm": (C.c_int, [vp, i32, vp, vp, i32]),
     "wl_autotune": (C.c_int, [vp, i32, i32]),
     "wl_graph_shape": (C.c_int, [vp, i32, i32, C.POINTER(i32), C.POINTER(i32)]),
+    "wl_graph_set_shape": (C.c_int, [vp, i32, i32, i32, i32]),
     "wl_lambda_max": (C.c_int, [vp, f64, pd]),
     "wl_spectral_radius": (C.c_int, [vp, f64, f64, pd]),
     "wl_op_create": (C.c_int, [vp, C.POINTER(OpDesc), C.POINTER(vp)]),

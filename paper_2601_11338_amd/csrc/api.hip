@@ -446,6 +446,20 @@ wl_status wl_autotune(wl_graph* g, int32_t prec, int32_t b) {
   return WL_OK;
 }
 
+wl_status wl_graph_set_shape(wl_graph* g, int32_t prec, int32_t b, int32_t lanes_per_row, int32_t long_row_threshold) {
+  WL_CHECK(g, WL_EINVAL, "wl_graph_set_shape: graph is null");
+  WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_graph_set_shape: bad prec");
+  WL_CHECK(b >= 1 && b <= 4096, WL_EINVAL, "wl_graph_set_shape: b out of range");
+  WL_CHECK(lanes_per_row >= 1 && lanes_per_row <= 64 && (lanes_per_row & (lanes_per_row - 1)) == 0, WL_EINVAL,
+           "wl_graph_set_shape: lanes per row must be a power of two in [1, 64]");
+  WL_CHECK(long_row_threshold >= 1, WL_EINVAL, "wl_graph_set_shape: bad long-row threshold");
+  SpmmShape s;
+  s.G = lanes_per_row;
+  s.long_thr = long_row_threshold;
+  g->tuned[prec * 1000 + std::min(b, 999)] = s;
+  return WL_OK;
+}
+
 wl_status wl_graph_shape(wl_graph* g, int32_t prec, int32_t b, int32_t* lanes_per_row, int32_t* long_row_threshold) {
   WL_CHECK(g, WL_EINVAL, "wl_graph_shape: graph is null");
   WL_CHECK(prec == WL_FP32 || prec == WL_FP64, WL_EINVAL, "wl_graph_shape: bad prec");
