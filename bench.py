@@ -54,7 +54,45 @@ def parse():
     p.add_argument("--block", type=int, default=16)
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM counters)")
+    p.add_argument("--summarize", metavar="DIR",
+                   help="only summarise a rocprofv3 output folder (kernel trace or counter CSVs): per kernel, the "
+                        "number of dispatches, the mean over all and over the last --last dispatches")
+    p.add_argument("--last", type=int, default=358, help="dispatches per kernel averaged by --summarize")
     return p.parse_args()
+
+
+def summarize(folder, last):
+    """Per-kernel figures from rocprofv3 CSV output: durations in us for a kernel trace,
+    the counter value for a counter collection.  The last dispatches of a kernel are the
+    last step(s) of the command, after autotuning and warm-up."""
+    import collections
+    import csv
+    import glob
+
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*.csv"), recursive=True)):
+        trace = f.endswith("kernel_trace.csv")
+        if not (trace or f.endswith("counter_collection.csv")):
+            continue
+        per = collections.defaultdict(list)
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if trace:
+                    per[r["Kernel_Name"]].append((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) -
+                                                                              int(r["Start_Timestamp"])) / 1e3))
+                else:
+                    key = f"{r['Counter_Name']} {r['Kernel_Name']}"
+                    per[key].append((int(r.get("Dispatch_Id") or 0), float(r["Counter_Value"])))
+        print(f"# {os.path.relpath(f, folder)}: " + ("duration us" if trace else "counter value per dispatch"))
+        rows = []
+        for k, v in per.items():
+            v.sort()
+            vals = [x for _, x in v]
+            tail = vals[-last:]
+            rows.append((sum(vals) if trace else len(vals), k, len(vals), sum(vals) / len(vals), len(tail),
+                         sum(tail) / len(tail)))
+        rows.sort(reverse=True)
+        for _, k, nv, avg, nt, avgt in rows[:30]:
+            print(f"{nv:7d} x {avg:12.1f} | last {nt:5d}: {avgt:12.1f}  {k[:120]}")
 
 
 def copy_calibration():
@@ -523,6 +561,9 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (multi-GPU is design-only)",
               file=sys.stderr)
         sys.exit(2)
+    if args.summarize:
+        summarize(args.summarize, args.last)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

@@ -454,8 +454,8 @@ wl_status wl_graph_set_shape(wl_graph* g, int32_t prec, int32_t b, int32_t lanes
            "wl_graph_set_shape: lanes per row must be a power of two in [1, 64]");
   WL_CHECK(long_row_threshold >= 1, WL_EINVAL, "wl_graph_set_shape: bad long-row threshold");
   SpmmShape s;
-  s.G = lanes_per_row;
-  s.long_thr = long_row_threshold;
+  s.G = std::max({4, lanes_for(prec, b), (int)lanes_per_row});
+  s.long_thr = std::max(g->long_min_thr, (int)long_row_threshold);
   g->tuned[prec * 1000 + std::min(b, 999)] = s;
   return WL_OK;
 }

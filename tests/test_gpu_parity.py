@@ -80,6 +80,18 @@ def test_spmm_autotuned_shape_same_result(ctx, wl):
     assert rel(after, ref) < 2e-6 and rel(before, ref) < 2e-6
 
 
+@pytest.mark.parametrize("G", [1, 4, 16, 64])
+def test_spmm_explicit_shape_same_result(ctx, wl, G):
+    n, rp, ci = spmm_graphs()["ba"]
+    g = wl.Graph(ctx, rp, ci)
+    g.set_shape(torch.float32, 16, G, 8)
+    got_g, got_thr = g.shape(torch.float32, 16)
+    assert got_g == max(G, 4) and got_thr >= 8
+    X = dev(synth.gaussian_block(n, 16, 2), torch.float32)
+    ref = sparse.adjacency(n, rp, ci) @ host(X)
+    assert rel(host(g.spmm(X)), ref) < 2e-6
+
+
 # ------------------------------------------------------------------ FP64, dense oracle
 def er_small():
     n = 400
