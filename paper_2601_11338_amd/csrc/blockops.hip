@@ -106,8 +106,16 @@ __global__ __launch_bounds__(256) void k_gram_finalize(const double* __restrict_
   const int e = blockIdx.x * EB + el;
   double v = 0.0;
   if (e < E) {
+    // eight independent sums so that eight loads are in flight per thread
     const double* src = partials + (int64_t)k * nparts * E + e;
-    for (int q = p; q < nparts; q += P) v += src[(int64_t)q * E];
+    double u[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int q = p;
+    for (; q + 7 * P < nparts; q += 8 * P) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) u[i] += src[(int64_t)(q + i * P) * E];
+    }
+    for (; q < nparts; q += P) u[0] += src[(int64_t)q * E];
+    v = ((u[0] + u[1]) + (u[2] + u[3])) + ((u[4] + u[5]) + (u[6] + u[7]));
   }
   s[t] = v;
   __syncthreads();
@@ -340,10 +348,249 @@ __global__ __launch_bounds__(256) void k_update_f4(int64_t n, const float* X, in
   }
 }
 
+// Out = beta sum_k X_k C_k + (wv ? wv : alpha) .* Yin for n x 16 FP32 blocks, as a
+// tall-skinny product on the matrix cores (v_mfma_f32_16x16x4f32), optionally with the
+// Gram Out^T Out accumulated in FP64 on the same registers (v_mfma_f64_16x16x4f64).
+// A wave takes 16-row chunks.  Lane l loads 16 bytes of the chunk, row l % 16, columns
+// 4 (l / 16) .. + 3; product step s uses the s-th of them as the A operand, i.e. the
+// step runs over the columns {4 g + s : g = 0..3} of every X_k, and lane l supplies the
+// matching B operand C_k[4 (l / 16) + s][l % 16] from a lane-ordered copy of C in LDS.
+// Lane l then holds result rows 4 (l / 16) + v, column l % 16 (v = 0..3), which are
+// also exactly its operands for the Gram: step v sums over rows {4 g + v}.  Rows past
+// n load zeros and are not stored.  Out may alias X_k or Yin (a chunk is read whole
+// before it is written).  The four waves' Grams are summed in LDS in a fixed order;
+// each workgroup writes one 16 x 16 partial.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int UPD_MFMA_MAXK = 48;
+
+template <bool GRAM>
+__global__ __launch_bounds__(256) void k_update_mfma16(int64_t n, const float* X, int64_t sX, int nblk,
+                                                       const double* __restrict__ C, const float* Yin, double alpha,
+                                                       const float* __restrict__ wv, double beta, float* Out,
+                                                       double* __restrict__ partials,
+                                                       const double* __restrict__ skip,
+                                                       const double* __restrict__ skip_gram) {
+  if (skip && *skip != 0.0) return;  // identity update the caller elides
+  extern __shared__ float4 sCl[];  // nblk x 64 lane-ordered operands (nblk KiB)
+  __shared__ double red[256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  for (int e = threadIdx.x; e < nblk * 64; e += 256) {
+    const int k = e >> 6, l = e & 63, gg = l >> 4, cc = l & 15;
+    const double* Ck = C + (int64_t)k * 256 + (4 * gg) * 16 + cc;
+    sCl[e] = make_float4((float)Ck[0], (float)Ck[16], (float)Ck[32], (float)Ck[48]);
+  }
+  __syncthreads();
+  const bool gram = GRAM && !(skip_gram && *skip_gram != 0.0);
+  const float tb = (float)beta, ta = (float)alpha;
+  v4d gacc = {0.0, 0.0, 0.0, 0.0};
+  const int64_t nchunks = (n + 15) / 16;
+  const int64_t cstride = (int64_t)gridDim.x * 4;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
+    const int64_t r0 = ch * 16;
+    const bool okA = r0 + c < n;
+    const float* xa = X + (r0 + c) * 16 + 4 * g;
+    v4f d = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < nblk; k0 += 4) {
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        x[u] = (okA && k0 + u < nblk) ? *reinterpret_cast<const float4*>(xa + (int64_t)(k0 + u) * sX)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (k0 + u >= nblk) break;
+        const float4 bq = sCl[(k0 + u) * 64 + lane];
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].x, bq.x, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].y, bq.y, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].z, bq.z, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].w, bq.w, d, 0, 0, 0);
+      }
+    }
+    float o[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * g + v;
+      o[v] = tb * d[v];
+      if (Yin && row < n) o[v] += (wv ? wv[row] : ta) * Yin[row * 16 + c];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * g + v;
+      if (row < n) Out[row * 16 + c] = o[v];
+    }
+    if (gram) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double ov = (double)o[v];
+        gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(ov, ov, gacc, 0, 0, 0);
+      }
+    }
+  }
+  if (!gram) return;  // uniform over the workgroup
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int idx = (4 * v + g) * 16 + c;  // FP64 16x16x4 output layout
+        red[idx] = (w == 0 ? 0.0 : red[idx]) + gacc[v];
+      }
+    }
+    __syncthreads();
+  }
+  partials[(int64_t)blockIdx.x * 256 + threadIdx.x] = red[threadIdx.x];
+}
+
 template <typename T, int B>
 struct RowVec {
   T v[B];
 };
+
+// Single-column blocks are plain vectors: rows are consecutive, so each lane moves 16
+// contiguous bytes per load.  Dot products accumulate in FP64.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float4 type;
+  static constexpr int W = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int W = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ double vdot(const typename Vec16<T>::type& x, const typename Vec16<T>::type& y) {
+  if constexpr (Vec16<T>::W == 4)
+    return (double)x.x * (double)y.x + (double)x.y * (double)y.y + (double)x.z * (double)y.z +
+           (double)x.w * (double)y.w;
+  else
+    return (double)x.x * (double)y.x + (double)x.y * (double)y.y;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+constexpr int VDOT_KB = 4;  // vectors X_k dotted with Y per workgroup
+
+// partials[k * gridDim.x + blockIdx.x] = X_k . Y over this workgroup's rows, for
+// k in [blockIdx.y * VDOT_KB, +VDOT_KB) and k < nblk.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vdot(int64_t n, const T* __restrict__ X, int64_t sX, int nblk,
+                                              const T* __restrict__ Y, double* __restrict__ partials,
+                                              const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  const int k0 = blockIdx.y * VDOT_KB;
+  const int kn = min(VDOT_KB, nblk - k0);
+  double acc[VDOT_KB] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t nv = n / W;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += (int64_t)gridDim.x * 256) {
+    const V y = reinterpret_cast<const V*>(Y)[i];
+#pragma unroll
+    for (int kk = 0; kk < VDOT_KB; ++kk)
+      if (kk < kn) acc[kk] += vdot<T>(reinterpret_cast<const V*>(X + (int64_t)(k0 + kk) * sX)[i], y);
+  }
+  if (blockIdx.x == 0) {  // rows past the last whole vector
+    const int64_t r = nv * W + threadIdx.x;
+    if (r < n) {
+#pragma unroll
+      for (int kk = 0; kk < VDOT_KB; ++kk)
+        if (kk < kn) acc[kk] += (double)X[(int64_t)(k0 + kk) * sX + r] * (double)Y[r];
+    }
+  }
+  __shared__ double red[4][VDOT_KB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int kk = 0; kk < VDOT_KB; ++kk) {
+    const double v = wave_sum(acc[kk]);
+    if (lane == 0) red[wave][kk] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kn)
+    partials[(int64_t)(k0 + threadIdx.x) * gridDim.x + blockIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+constexpr int VUPD_MAXK = 64;  // vectors combined by one update
+
+// Out = (wv ? wv : alpha) .* Yin + beta * sum_k C[k] X_k on vectors (Out may alias X_k
+// or Yin: every element is read and written by the same lane); with partials, the
+// workgroup's part of Out . Out goes to partials[blockIdx.x].
+template <typename T>
+__global__ __launch_bounds__(256) void k_vupdate(int64_t n, const T* X, int64_t sX, int nblk,
+                                                 const double* __restrict__ C, const T* Yin, double alpha,
+                                                 const T* __restrict__ wv, double beta, T* Out,
+                                                 double* __restrict__ partials, const double* __restrict__ skip) {
+  if (skip && *skip != 0.0) return;
+  typedef typename Vec16<T>::type V;
+  constexpr int W = Vec16<T>::W;
+  __shared__ T sC[VUPD_MAXK];
+  if ((int)threadIdx.x < nblk) sC[threadIdx.x] = (T)C[threadIdx.x];
+  __syncthreads();
+  const T tb = (T)beta, ta = (T)alpha;
+  double dot = 0.0;
+  const int64_t nv = n / W;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += (int64_t)gridDim.x * 256) {
+    T acc[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) acc[l] = T(0);
+    for (int k = 0; k < nblk; ++k) {
+      const V x = reinterpret_cast<const V*>(X + (int64_t)k * sX)[i];
+      const T c = sC[k];
+      const T* xs = reinterpret_cast<const T*>(&x);
+#pragma unroll
+      for (int l = 0; l < W; ++l) acc[l] += xs[l] * c;
+    }
+    T o[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) o[l] = tb * acc[l];
+    if (Yin) {
+      const V y = reinterpret_cast<const V*>(Yin)[i];
+      const T* ys = reinterpret_cast<const T*>(&y);
+      if (wv) {
+        const V w = reinterpret_cast<const V*>(wv)[i];
+        const T* ws = reinterpret_cast<const T*>(&w);
+#pragma unroll
+        for (int l = 0; l < W; ++l) o[l] += ws[l] * ys[l];
+      } else {
+#pragma unroll
+        for (int l = 0; l < W; ++l) o[l] += ta * ys[l];
+      }
+    }
+    V ov;
+    __builtin_memcpy(&ov, o, sizeof(V));
+    reinterpret_cast<V*>(Out)[i] = ov;
+    if (partials) {
+#pragma unroll
+      for (int l = 0; l < W; ++l) dot += (double)o[l] * (double)o[l];
+    }
+  }
+  if (blockIdx.x == 0) {  // rows past the last whole vector
+    const int64_t r = nv * W + threadIdx.x;
+    if (r < n) {
+      T acc = T(0);
+      for (int k = 0; k < nblk; ++k) acc += X[(int64_t)k * sX + r] * sC[k];
+      T o = tb * acc;
+      if (Yin) o += (wv ? wv[r] : ta) * Yin[r];
+      Out[r] = o;
+      if (partials) dot += (double)o * (double)o;
+    }
+  }
+  if (partials) {
+    __shared__ double red[4];
+    const double v = wave_sum(dot);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
 
 // Out[r,:] = (wv ? wv[r] : alpha) * Yin[r,:] + beta * sum_k X_k[r,0:bx] C_k,  C_k = C[k*bx:(k+1)*bx, 0:by]
 template <typename T, int B>
@@ -580,16 +827,24 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     sR[i * 65 + j] = 0.0;
   }
   __syncthreads();
-  if (t == 0) {
-    double m = 0.0;
-    for (int i = 0; i < b; ++i) m = fmax(m, sG[i * 65 + i]);
-    double fa = 0.0;
+  {
+    // reference scale: max diagonal of G and ||Aref||_F^2 + ||Bref||_F^2 over b, the
+    // sums spread over the 64 lanes of the (single-wave) workgroup
+    double m = 0.0, fa = 0.0;
+    for (int i = t; i < b; i += 64) m = fmax(m, sG[i * 65 + i]);
     if (Aref)
-      for (int e = 0; e < b * b; ++e) fa += Aref[e] * Aref[e];
+      for (int e = t; e < b * b; e += 64) fa += Aref[e] * Aref[e];
     if (Bref)
-      for (int e = 0; e < b * b; ++e) fa += Bref[e] * Bref[e];
-    sref = fmax(m, fa / b);
-    if (ref_out) ref_out[0] = sref;  // reference scale for a later check
+      for (int e = t; e < b * b; e += 64) fa += Bref[e] * Bref[e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      m = fmax(m, __shfl_xor(m, off, 64));
+      fa += __shfl_xor(fa, off, 64);
+    }
+    if (t == 0) {
+      sref = fmax(m, fa / b);
+      if (ref_out) ref_out[0] = sref;  // reference scale for a later check
+    }
   }
   __syncthreads();
   chol_deflate(b, sG, sR, defl, tol * sref, Rinv);
@@ -597,18 +852,25 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     const int i = e / b, j = e % b;
     if (R) R[e] = sR[i * 65 + j];
   }
+  // diagonal of Bout, kept on chip for the checks below (0 for a dropped component)
+  __shared__ double sBd[64];
   if (Bout) {
     __syncthreads();
+    if (Rprev) {  // the first pass's factor, staged (sG is free once Rinv is written)
+      for (int e = t; e < b * b; e += 64) sG[(e / b) * 65 + e % b] = Rprev[e];
+      __syncthreads();
+    }
     if (t < b) {
       for (int j = 0; j < b; ++j) {
         double s;
         if (Rprev) {
           s = 0.0;
-          for (int k = 0; k < b; ++k) s += sR[t * 65 + k] * Rprev[k * b + j];
+          for (int k = t; k <= j; ++k) s += sR[t * 65 + k] * sG[k * 65 + j];  // both upper triangular
         } else {
           s = sR[t * 65 + j];
         }
         Bout[t * b + j] = s;
+        if (j == t) sBd[t] = s;
       }
     }
     // Bout is the R factor of the block as stored (R of its true Gram, or R2 R1 after a
@@ -617,13 +879,11 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
     // Rinv and row k of Bout become zero, so the next basis block loses that column
     // instead of carrying normalised noise.
     if (ref_in && post_tol > 0.0) {
-      __shared__ int drop[64];
-      __syncthreads();
-      if (t < b) drop[t] = fabs(Bout[t * b + t]) <= post_tol * sqrt(fmax(ref_in[0], 0.0));
-      __syncthreads();
-      if (t < b && drop[t]) {
+      const double lim = post_tol * sqrt(fmax(ref_in[0], 0.0));
+      if (t < b && fabs(sBd[t]) <= lim) {
         for (int j = 0; j < b; ++j) Bout[t * b + j] = 0.0;
         for (int i = 0; i < b; ++i) Rinv[i * b + t] = 0.0;
+        sBd[t] = 0.0;
       }
     }
   }
@@ -632,17 +892,21 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
   // to the smallest kept pivot.  skip_out = 1 when min / max >= skip_ratio.
   if (skip_out) {
     __syncthreads();
-    if (t == 0) {
-      double pmax = 0.0, pmin = INFINITY;
-      for (int k = 0; k < b; ++k) {
-        const double r = sR[k * 65 + k];
-        const bool kept = r > 0.0 && !(Bout && Bout[k * b + k] == 0.0);
-        if (!kept) continue;
+    double pmax = 0.0, pmin = INFINITY;
+    for (int k = t; k < b; k += 64) {
+      const double r = sR[k * 65 + k];
+      const bool kept = r > 0.0 && !(Bout && sBd[k] == 0.0);
+      if (kept) {
         pmax = fmax(pmax, r * r);
         pmin = fmin(pmin, r * r);
       }
-      *skip_out = (pmax == 0.0 || pmin >= skip_ratio * pmax) ? 1.0 : 0.0;
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
+      pmin = fmin(pmin, __shfl_xor(pmin, off, 64));
+    }
+    if (t == 0) *skip_out = (pmax == 0.0 || pmin >= skip_ratio * pmax) ? 1.0 : 0.0;
   }
 }
 
@@ -911,6 +1175,28 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
       return WL_OK;
     }
   }
+  if constexpr (B == 1) {
+    const int W = isf ? 4 : 2;
+    if (bx == 1 && by == 1 && ldx == 1 && ldy == 1 && sX % W == 0 &&
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0) {
+      int64_t parts = (n / W + 511) / 512;  // two vectors of 16 bytes per lane
+      if (parts > 1024) parts = 1024;
+      if (parts < 1) parts = 1;
+      WL_TRY(ctx->partials.ensure((size_t)parts * nblk * sizeof(double)));
+      const dim3 grid((unsigned)parts, (unsigned)((nblk + VDOT_KB - 1) / VDOT_KB));
+      if (isf)
+        hipLaunchKernelGGL(k_vdot<float>, grid, dim3(256), 0, ctx->stream, n, (const float*)X, sX, nblk,
+                           (const float*)Y, ctx->partials.as<double>(), skip);
+      else
+        hipLaunchKernelGGL(k_vdot<double>, grid, dim3(256), 0, ctx->stream, n, (const double*)X, sX, nblk,
+                           (const double*)Y, ctx->partials.as<double>(), skip);
+      WL_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_gram_finalize, dim3(1, nblk), dim3(256), 0, ctx->stream, ctx->partials.as<double>(),
+                         (int)parts, 1, 1, 1, out, skip);
+      WL_HIP(hipGetLastError());
+      return WL_OK;
+    }
+  }
   const int64_t ntiles = (n + GRAM_TR - 1) / GRAM_TR;
   int64_t cap = (int64_t)(1 << 22) / ((int64_t)E * nblk);
   if (cap < 32) cap = 32;
@@ -941,6 +1227,33 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
                    const T* Yin, int ldy, double alpha, const T* wv, double beta, T* Out, int by,
                    double* gram_out, const double* skip, const double* skip_gram) {
   constexpr int E = B * B;
+  if constexpr (sizeof(T) == 4 && B == 16) {
+    const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
+                      reinterpret_cast<uintptr_t>(Yin)) & 15u) == 0 && (sX % 4) == 0;
+    if (bx == 16 && by == 16 && ldx == 16 && ldy == 16 && al && nblk <= UPD_MFMA_MAXK && !(skip && gram_out)) {
+      const int64_t nchunks = (n + 15) / 16;
+      int64_t grid = (nchunks + 15) / 16;  // about four chunks per wave
+      if (grid > 1024) grid = 1024;
+      if (grid < 1) grid = 1;
+      const size_t lds = (size_t)nblk * 64 * sizeof(float4);
+      if (gram_out) {
+        WL_TRY(ctx->partials.ensure((size_t)grid * 256 * sizeof(double)));
+        hipLaunchKernelGGL(k_update_mfma16<true>, dim3((unsigned)grid), dim3(256), lds, ctx->stream, n,
+                           (const float*)X, sX, nblk, C, (const float*)Yin, alpha, (const float*)wv, beta,
+                           (float*)Out, ctx->partials.as<double>(), skip, skip_gram);
+        WL_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(256), 1), dim3(256), 0, ctx->stream,
+                           ctx->partials.as<double>(), (int)grid, 16, 16, 16, gram_out, skip_gram);
+        WL_HIP(hipGetLastError());
+      } else {
+        hipLaunchKernelGGL(k_update_mfma16<false>, dim3((unsigned)grid), dim3(256), lds, ctx->stream, n,
+                           (const float*)X, sX, nblk, C, (const float*)Yin, alpha, (const float*)wv, beta,
+                           (float*)Out, nullptr, skip, nullptr);
+        WL_HIP(hipGetLastError());
+      }
+      return WL_OK;
+    }
+  }
   if constexpr (sizeof(T) == 4 && B >= 4) {
     const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
                       reinterpret_cast<uintptr_t>(Yin)) & 15u) == 0 && (sX % 4) == 0;
@@ -955,6 +1268,31 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
                          kc, C, (const float*)Yin, alpha, (const float*)wv, beta, (float*)Out, skip);
       WL_HIP(hipGetLastError());
       if (gram_out) return gram_B<B>(ctx, n, Out, true, B, 0, 1, Out, B, B, B, gram_out, skip_gram);
+      return WL_OK;
+    }
+  }
+  if constexpr (B == 1) {
+    constexpr int W = sizeof(T) == 4 ? 4 : 2;
+    // (an update that may be skipped and also yields a Gram takes the general path)
+    if (bx == 1 && by == 1 && ldx == 1 && ldy == 1 && nblk <= VUPD_MAXK && sX % W == 0 && !(skip && gram_out) &&
+        ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) | reinterpret_cast<uintptr_t>(Yin) |
+          reinterpret_cast<uintptr_t>(wv)) & 15u) == 0) {
+      int64_t grid = (n / W + 1023) / 1024;
+      if (grid > (gram_out ? 512 : 2048)) grid = gram_out ? 512 : 2048;
+      if (grid < 1) grid = 1;
+      double* parts = nullptr;
+      if (gram_out) {
+        WL_TRY(ctx->partials.ensure((size_t)grid * sizeof(double)));
+        parts = ctx->partials.as<double>();
+      }
+      hipLaunchKernelGGL(k_vupdate<T>, dim3((unsigned)grid), dim3(256), 0, ctx->stream, n, X, sX, nblk, C, Yin,
+                         alpha, wv, beta, Out, parts, skip);
+      WL_HIP(hipGetLastError());
+      if (gram_out) {
+        hipLaunchKernelGGL(k_gram_finalize, dim3(1, 1), dim3(256), 0, ctx->stream, parts, (int)grid, 1, 1, 1,
+                           gram_out, skip_gram);
+        WL_HIP(hipGetLastError());
+      }
       return WL_OK;
     }
   }

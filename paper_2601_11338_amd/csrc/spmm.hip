@@ -190,6 +190,39 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
   }
 }
 
+// Sum of the neighbour row segments X[colidx[k], col : col + VW] over k = k0, k0 + stride,
+// ... < e.  The column indices of U neighbours are loaded first (one round trip), then
+// the U gathers are issued together (one more): a short row costs two memory
+// latencies instead of two per neighbour.  Lanes past the end of their row are masked
+// off, so they issue no traffic.  The summation order is k order.
+template <typename T, int VW, bool MASK, int U>
+__device__ __forceinline__ void gather_sum(const int32_t* __restrict__ colidx, int k0, int e, int stride,
+                                           const T* __restrict__ X, int ld, int col, bool colok,
+                                           Frag<T, VW>& acc) {
+  for (int k = k0; k < e; k += U * stride) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = k + u * stride < e ? colidx[k + u * stride] : 0;
+    Frag<T, VW> x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k + u * stride < e)
+        x[u] = ldf_m<T, VW, MASK>(X + (int64_t)j[u] * ld + col, colok);
+      else
+        zero(x[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc.v[i] += x[u].v[i];
+  }
+}
+
+template <typename T, int VW>
+constexpr int gather_unroll() {
+  return VW == 1 && sizeof(T) == 4 ? 16 : 8;
+}
+
 template <typename T, int VW, int LPN, int G, bool MASK>
 __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ colidx, int64_t n, int ld, int b,
@@ -230,13 +263,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
     const int s = rowptr[r], e = rowptr[r + 1];
     Frag<T, VW> acc;
     zero(acc);
-#pragma unroll 4
-    for (int k = s + slot; k < e; k += NSLOT) {
-      const int64_t j = colidx[k];
-      Frag<T, VW> x = ldf_m<T, VW, MASK>(X + j * ld + col, colok);
-#pragma unroll
-      for (int i = 0; i < VW; ++i) acc.v[i] += x.v[i];
-    }
+    gather_sum<T, VW, MASK, gather_unroll<T, VW>()>(colidx, s + slot, e, NSLOT, X, ld, col, colok, acc);
 #pragma unroll
     for (int off = LPN; off < 64; off <<= 1) add_shfl_xor(acc, off);
     const int wave = threadIdx.x >> 6;
@@ -271,13 +298,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   const int slot = (lane % G) / LPN;
   Frag<T, VW> acc;
   zero(acc);
-#pragma unroll 4
-  for (int k = s + slot; k < e; k += NS) {
-    const int64_t j = colidx[k];
-    Frag<T, VW> x = ldf_m<T, VW, MASK>(X + j * ld + col, colok);
-#pragma unroll
-    for (int i = 0; i < VW; ++i) acc.v[i] += x.v[i];
-  }
+  gather_sum<T, VW, MASK, gather_unroll<T, VW>()>(colidx, s + slot, e, NS, X, ld, col, colok, acc);
 #pragma unroll
   for (int off = LPN; off < G; off <<= 1) add_shfl_xor(acc, off);
   if (slot == 0) epilogue<T, VW, MASK>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, Y);
