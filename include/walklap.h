@@ -270,19 +270,27 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
                       void* d_diag, double* trace, double* trace_err);
 
 /* ---------------------------------------------------------------- several operators
- * Operators of one graph evaluated together: their truncated series (eq. qrec; every
- * operator must use WL_M_RECURRENCE, i.e. the exponential or a resolvent with an
- * explicit degree, and all share graph and precision) run side by side on one wide
- * block, operator g on columns [g b, (g + 1) b), with one sparse product per step for
- * all of them and each group's weights of that step from a table (operators with a
- * lower degree stop contributing after their last step).  Results equal those of the
- * single operators up to the summation order of the sparse products.
- * wl_multi_create: 1 <= nops <= 64 operators; the handle keeps the graph alive (not
- * the operators, whose descriptors it copies).
+ * Operators of one graph evaluated together on one wide block, operator g on columns
+ * [g b, (g + 1) b), with one sparse product per step for all of them (wide rows gather
+ * whole cache lines).  All operators share graph, precision and evaluation method:
+ *   * WL_M_RECURRENCE: their truncated series (eq. qrec) step side by side with each
+ *     group's weights of that step from a table (operators with a lower degree stop
+ *     contributing after their last step).  Results equal those of the single
+ *     operators up to the summation order of the sparse products.
+ *   * WL_M_LANCZOS (Sec. 4.1): one block Lanczos process per operator, in lock step:
+ *     the sparse product applies every group's own symmetric matrix and three-term
+ *     subtraction, and the projections, CholQR factorisations and basis updates of all
+ *     groups run as single passes over the wide block.  Each group's result uses its
+ *     own number of steps; it agrees with the single operator's to the rounding level
+ *     of the Krylov recurrence (the grouped kernels sum in another order).  Grouped
+ *     kernels cover FP32 with b = 16 and b = 1 (nops <= 8, any precision); other
+ *     shapes, and Krylov spaces so small that full reorthogonalisation is needed
+ *     ((steps + 1) 2 b > n), are evaluated operator by operator into the same layout.
+ * wl_multi_create: 1 <= nops <= 64 operators (WL_EUNSUPPORTED for mixed methods); the
+ * handle keeps the graph alive (not the operators, whose descriptors it copies).
  * wl_multi_apply: d_X n x b (the same block for every operator), d_Y n x (nops b)
- * row-major, laplacian != 0: L_g X in group g, else phi_g X.  nops b <= 4096.  Wide
- * rows gather whole cache lines: nops b = 32 or 64 FP32 values per row is where the
- * sharing pays most.
+ * row-major, laplacian != 0: L_g X in group g, else phi_g X.  nops b <= 4096.  Rows of
+ * nops b = 32 or 64 FP32 values are where the sharing pays most.
  * wl_multi_fdeg: d_W n x nops, column g = phi_g 1.                                   */
 typedef struct wl_multi wl_multi;
 wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out);

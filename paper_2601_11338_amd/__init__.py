@@ -452,7 +452,8 @@ class MLP:
 
 
 class Multi:
-    """Several truncated-series operators of one graph evaluated side by side."""
+    """Several operators of one graph (all truncated series or all Lanczos) evaluated
+    side by side on one wide block."""
 
     def __init__(self, ops):
         self.ops = list(ops)

@@ -40,38 +40,7 @@ void wl_set_error(const char* fmt, ...) {
 namespace {
 
 
-template <typename T>
-constexpr int prec_of() {
-  return sizeof(T) == 4 ? WL_FP32 : WL_FP64;
-}
-
 bool is_finite(double x) { return std::isfinite(x); }
-
-// Deflation thresholds on squared norms (Gram pivots) of the first CholQR pass,
-// relative to the block's norm before projection.  The projected Gram is formed by
-// Pythagoras from inner products of stored vectors, so small pivots are unreliable
-// (the basis is orthonormal only to the storage precision); they are kept here and
-// judged after the second pass (post_tol), which measures them directly.
-template <typename T>
-double defl_tol() {
-  return sizeof(T) == 4 ? 1e-10 : 1e-24;
-}
-
-// After the second CholQR pass the combined factor gives the true norm of every new
-// component; components below this fraction of the block's scale before projection
-// are rounding noise of the stored basis (~1e-7 FP32, ~1e-16 FP64) and are dropped.
-// A second CholQR pass is skipped when the first factor's kept pivots span less than
-// this ratio (orthogonality after one pass ~ u_64 kappa^2: 1e-8 for FP32 storage,
-// 1e-10 for FP64).
-template <typename T>
-double skip_ratio() {
-  return sizeof(T) == 4 ? 1e-8 : 1e-6;
-}
-
-template <typename T>
-double post_tol() {
-  return sizeof(T) == 4 ? 1e-5 : 1e-10;
-}
 
 int next_pow2(int x) {
   int p = 1;
@@ -513,25 +482,6 @@ wl_status apply_lanczos_op(wl_graph* g, const LanczosOp<T>& L, const T* V, T* W,
   return WL_OK;
 }
 
-// Device-resident layout of the small matrices of one Lanczos run.
-struct SmallLayout {
-  int b, K;
-  size_t bb;
-  size_t A(int j) const { return (size_t)j * bb; }              // K blocks
-  size_t B(int j) const { return (size_t)(K + j) * bb; }        // K blocks
-  size_t R0() const { return (size_t)(2 * K) * bb; }
-  size_t G() const { return (size_t)(2 * K + 1) * bb; }
-  size_t R1() const { return (size_t)(2 * K + 2) * bb; }
-  size_t Ri1() const { return (size_t)(2 * K + 3) * bb; }
-  size_t R2() const { return (size_t)(2 * K + 4) * bb; }
-  size_t Ri2() const { return (size_t)(2 * K + 5) * bb; }
-  size_t Cc() const { return (size_t)(2 * K + 6) * bb; }        // 3 blocks
-  size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+2) blocks
-  size_t Ref() const { return (size_t)(3 * K + 11) * bb; }      // one double: reference scale
-  size_t Skip() const { return Ref() + 1; }                     // one double: second pass not needed
-  size_t total() const { return Ref() + 2; }
-};
-
 // Runs K block Lanczos steps from X (n x b).  basis must hold (K+1) blocks, Wb one
 // block.  On return the host arrays hold A_j (K blocks), B_j (K blocks; B_{K-1}
 // is the residual coupling), R0 (X = V_0 R0).
@@ -778,31 +728,31 @@ wl_status phi_recurrence(wl_op* op, const T* X, T* Y, int b, const T* wv, const 
   return WL_OK;
 }
 
-template <typename T>
-wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
-  wl_graph* g = op->g;
-  const int64_t n = g->n;
+}  // namespace
+
+int lanczos_steps(const wl_op* op, int64_t n, int b) {
   // the block Krylov space has dimension <= n: more steps only add deflated blocks
-  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(op->K, (n + b - 1) / b + 1));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(op->K, (n + b - 1) / b + 1));
+}
+
+void lanczos_params(const wl_op* op, double* a, double* b0, double* b1) {
   const double mu = op->d.mu, p = op->d.param;
-  LanczosOp<T> L;
-  double scale = 1.0;
   if (op->d.func == WL_F_RESOLVENT) {
     // A_mu(alpha) = (1 - mu^2 a^2) I - a A + a^2 mu D
-    L.a = -p;
-    L.b0 = 1.0 - mu * mu * p * p;
-    L.b1 = p * p * mu;
-    scale = 1.0 - mu * mu * p * p;
+    *a = -p;
+    *b0 = 1.0 - mu * mu * p * p;
+    *b1 = p * p * mu;
   } else {
-    L.a = 1.0;  // mu = 0: phi = exp(beta A)
+    *a = 1.0;  // mu = 0: phi = exp(beta A)
+    *b0 = *b1 = 0.0;
   }
-  WL_TRY(op->basis.ensure((size_t)(K + 1) * n * b * sizeof(T)));
-  WL_TRY(op->wbuf.ensure((size_t)n * b * sizeof(T)));
-  std::vector<double> hA, hB, hR0;
-  int Ke = K;
-  WL_TRY(block_lanczos<T>(g, L, X, b, K, op->d.reorth, op->basis.as<T>(), op->wbuf.as<T>(), op->small, hA, hB, hR0,
-                          &Ke));
-  std::vector<double> F;
+}
+
+wl_status lanczos_coefficients(const wl_op* op, int Ke, int b, const std::vector<double>& hA,
+                               const std::vector<double>& hB, const std::vector<double>& hR0,
+                               std::vector<double>& F) {
+  const double mu = op->d.mu, p = op->d.param;
+  const double scale = op->d.func == WL_F_RESOLVENT ? 1.0 - mu * mu * p * p : 1.0;
   if (op->d.func == WL_F_RESOLVENT) {
     // F = scale * T^{-1} E_1 R0
     std::vector<double> rhs((size_t)Ke * b * b, 0.0), sol((size_t)Ke * b * b);
@@ -855,6 +805,26 @@ wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* 
       return WL_ENOCONV;
     }
   }
+  return WL_OK;
+}
+
+namespace {
+
+template <typename T>
+wl_status phi_lanczos(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
+  wl_graph* g = op->g;
+  const int64_t n = g->n;
+  const int K = lanczos_steps(op, n, b);
+  LanczosOp<T> L;
+  lanczos_params(op, &L.a, &L.b0, &L.b1);
+  WL_TRY(op->basis.ensure((size_t)(K + 1) * n * b * sizeof(T)));
+  WL_TRY(op->wbuf.ensure((size_t)n * b * sizeof(T)));
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<T>(g, L, X, b, K, op->d.reorth, op->basis.as<T>(), op->wbuf.as<T>(), op->small, hA, hB, hR0,
+                          &Ke));
+  std::vector<double> F;
+  WL_TRY(lanczos_coefficients(op, Ke, b, hA, hB, hR0, F));
   return recombine<T>(g, op->basis.as<T>(), b, Ke, F, op->coef, wv, Xw, Y);
 }
 
@@ -1151,7 +1121,6 @@ wl_status wl_op_destroy(wl_op* op) {
 
 }  // extern "C"
 
-namespace {
 template <typename T>
 wl_status ensure_w(wl_op* op) {
   if (op->w_valid) return WL_OK;
@@ -1166,7 +1135,8 @@ wl_status ensure_w(wl_op* op) {
   op->w_valid = true;
   return WL_OK;
 }
-}  // namespace
+template wl_status ensure_w<float>(wl_op*);
+template wl_status ensure_w<double>(wl_op*);
 
 extern "C" {
 

@@ -704,45 +704,70 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, const T* X, int ldx, 
 // the inverse of R on the non-deflated columns (zero elsewhere) overwrites sG and, if
 // Rinv is given, is copied to global memory.
 __device__ void chol_deflate(int b, double* sG, double* sR, int* defl, double thr, double* __restrict__ Rinv) {
+  // Right-looking Cholesky of the upper triangle of sG (stride 65) with deflation: a
+  // pivot at or below thr gives a zero row of R.  Every lane derives the pivot's root
+  // and reciprocals itself, and the trailing update is spread over all 64 lanes with
+  // the operands of four entries loaded before any is written (the workgroup is one
+  // wave, so LDS accesses stay in program order).
+  __shared__ double sdi[64];  // 1 / R_kk (0 for a deflated k)
   const int t = threadIdx.x;
-  for (int e = t; e < b * b; e += 64) sR[(e / b) * 65 + e % b] = 0.0;
+  const int bb = b * b;
+  for (int e = t; e < bb; e += 64) sR[(e / b) * 65 + e % b] = 0.0;
   __syncthreads();
   for (int k = 0; k < b; ++k) {
+    const double p = sG[k * 65 + k];
+    const bool dk = !(p > thr) || !(p > 0.0);
+    const double rkk = dk ? 0.0 : sqrt(p);
+    const double irkk = dk ? 0.0 : 1.0 / rkk;
+    const double ip = irkk * irkk;
     if (t == 0) {
-      const double p = sG[k * 65 + k];
-      if (!(p > thr) || !(p > 0.0)) {
-        defl[k] = 1;
-        sR[k * 65 + k] = 0.0;
-      } else {
-        defl[k] = 0;
-        sR[k * 65 + k] = sqrt(p);
-      }
+      defl[k] = dk ? 1 : 0;
+      sdi[k] = irkk;
     }
-    __syncthreads();
-    const double rkk = sR[k * 65 + k];
-    if (t > k && t < b) sR[k * 65 + t] = defl[k] ? 0.0 : sG[k * 65 + t] / rkk;
-    __syncthreads();
-    if (t > k && t < b) {
-      const double rkt = sR[k * 65 + t];
-      for (int j = t; j < b; ++j) sG[t * 65 + j] -= rkt * sR[k * 65 + j];
+    if (t >= k && t < b) sR[k * 65 + t] = (t == k) ? rkk : sG[k * 65 + t] * irkk;
+    for (int e0 = 0; e0 < bb; e0 += 256) {
+      double gi[4], gj[4], gij[4];
+      int at[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * 64 + t;
+        const int i = e / b, j = e - (e / b) * b;
+        at[q] = (e < bb && i > k && j >= i) ? i * 65 + j : -1;
+        if (at[q] >= 0) {
+          gi[q] = sG[k * 65 + i];
+          gj[q] = sG[k * 65 + j];
+          gij[q] = sG[at[q]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (at[q] >= 0) sG[at[q]] = gij[q] - gi[q] * gj[q] * ip;
     }
     __syncthreads();
   }
   // the factorisation has consumed sG: column t of the inverse is built in place there
+  // by back substitution (R_ii^{-1} from sdi; deflated rows and columns stay zero)
   if (t < b) {
     for (int i = b - 1; i >= 0; --i) {
-      double v = (i == t) ? 1.0 : 0.0;
       if (defl[i] || defl[t]) {
         sG[i * 65 + t] = 0.0;
         continue;
       }
-      for (int j = i + 1; j < b; ++j) v -= sR[i * 65 + j] * sG[j * 65 + t];
-      sG[i * 65 + t] = v / sR[i * 65 + i];
+      double v0 = (i == t) ? 1.0 : 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+      int j = i + 1;
+      for (; j + 3 < b; j += 4) {
+        v0 -= sR[i * 65 + j] * sG[j * 65 + t];
+        v1 -= sR[i * 65 + j + 1] * sG[(j + 1) * 65 + t];
+        v2 -= sR[i * 65 + j + 2] * sG[(j + 2) * 65 + t];
+        v3 -= sR[i * 65 + j + 3] * sG[(j + 3) * 65 + t];
+      }
+      for (; j < b; ++j) v0 -= sR[i * 65 + j] * sG[j * 65 + t];
+      sG[i * 65 + t] = ((v0 + v1) + (v2 + v3)) * sdi[i];
     }
   }
   __syncthreads();
   if (Rinv)
-    for (int e = t; e < b * b; e += 64) Rinv[e] = sG[(e / b) * 65 + e % b];
+    for (int e = t; e < bb; e += 64) Rinv[e] = sG[(e / b) * 65 + e % b];
 }
 
 // One projection step of block Lanczos (classical Gram-Schmidt against V_{j-1} and

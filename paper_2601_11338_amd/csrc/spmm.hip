@@ -151,7 +151,9 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
   }
   if (ep.C) {
     const T* z2 = ep.Z2 + r * (int64_t)ld;
-    for (int k = 0; k < b; ++k) {
+    const int kw = ep.ctab ? ep.cgw : b;                    // rows of C that meet this column
+    if (ep.ctab) z2 += (col / ep.cgw) * ep.cgw;             // the operator's own segment
+    for (int k = 0; k < kw; ++k) {
       const T zk = z2[k];
 #pragma unroll
       for (int i = 0; i < VW; ++i) y[i] -= zk * sC[k * TILE + cl + i];
@@ -237,11 +239,20 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
 
   const int c0 = blockIdx.y * TILE;
   if (ep.C) {
-    for (int e = threadIdx.x; e < b * TILE; e += 256) {
+    const int kw = ep.ctab ? ep.cgw : b;
+    for (int e = threadIdx.x; e < kw * TILE; e += 256) {
       const int k = e / TILE, j = e - (e / TILE) * TILE;
       const int c = c0 + j;
       double v = 0.0;
-      if (c < b) v = ep.transC ? ep.C[(int64_t)c * b + k] : ep.C[(int64_t)k * b + c];
+      if (c < b) {
+        if (ep.ctab) {  // block-diagonal C: operator q = c / cgw, local column jc
+          const int q = c / ep.cgw, jc = c - q * ep.cgw;
+          const double* Cq = ep.C + q * ep.cgs;
+          v = ep.transC ? Cq[(int64_t)jc * ep.cgw + k] : Cq[(int64_t)k * ep.cgw + jc];
+        } else {
+          v = ep.transC ? ep.C[(int64_t)c * b + k] : ep.C[(int64_t)k * b + c];
+        }
+      }
       sC[e] = (T)v;
     }
     __syncthreads();

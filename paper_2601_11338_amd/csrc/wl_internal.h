@@ -184,9 +184,12 @@ struct EpiArgs {
   // Several operators side by side: column c belongs to operator c / cgw, whose five
   // coefficients of this launch are ctab[5 (c / cgw) ...]; the finish weight is then
   // wv[r * wld + c / cgw] (wv holds one walk-degree column per operator).
+  // With C as well, C is block diagonal: operator q's cgw x cgw block sits at
+  // C + q * cgs, and Z2's row segment of that operator is what multiplies it.
   const double* ctab = nullptr;
   int cgw = 0;
   int wld = 0;
+  int64_t cgs = 0;
   // Row-tile order of the short-row blocks (host object, resolved by the launcher):
   // block s of the launch processes row tile map[s] (-1: idle), so that tiles that
   // gather from the same rows can be placed on one XCD.  Null: tile s = block s.
@@ -316,7 +319,95 @@ int tridiag_eigvals(int m, const double* a, const double* b, double* lam);
 // blocks Bo with T_{j+1,j} = Bo_j), blocks b x b row-major; B, X are (K*b) x nrhs.
 int block_tridiag_solve(int K, int b, const double* Ad, const double* Bo, const double* B, int nrhs, double* X);
 
+// ------------------------------------------------------------------ Lanczos settings
+template <typename T>
+constexpr int prec_of() {
+  return sizeof(T) == 4 ? WL_FP32 : WL_FP64;
+}
+
+// Deflation thresholds on squared norms (Gram pivots) of the first CholQR pass,
+// relative to the block's norm before projection.  Small pivots of the first pass are
+// unreliable (the basis is orthonormal only to the storage precision); they are kept
+// there and judged after the second pass (post_tol), which measures them directly.
+template <typename T>
+inline double defl_tol() {
+  return sizeof(T) == 4 ? 1e-10 : 1e-24;
+}
+
+// A second CholQR pass is skipped when the first factor's kept pivots span less than
+// this ratio (orthogonality after one pass ~ u_64 kappa^2: 1e-8 for FP32 storage,
+// 1e-10 for FP64).
+template <typename T>
+inline double skip_ratio() {
+  return sizeof(T) == 4 ? 1e-8 : 1e-6;
+}
+
+// After the second CholQR pass the combined factor gives the true norm of every new
+// component; components below this fraction of the block's scale before projection
+// are rounding noise of the stored basis (~1e-7 FP32, ~1e-16 FP64) and are dropped.
+template <typename T>
+inline double post_tol() {
+  return sizeof(T) == 4 ? 1e-5 : 1e-10;
+}
+
+// Device-resident layout of the small matrices of one Lanczos run (doubles).
+struct SmallLayout {
+  int b, K;
+  size_t bb;
+  size_t A(int j) const { return (size_t)j * bb; }              // K blocks
+  size_t B(int j) const { return (size_t)(K + j) * bb; }        // K blocks
+  size_t R0() const { return (size_t)(2 * K) * bb; }
+  size_t G() const { return (size_t)(2 * K + 1) * bb; }
+  size_t R1() const { return (size_t)(2 * K + 2) * bb; }
+  size_t Ri1() const { return (size_t)(2 * K + 3) * bb; }
+  size_t R2() const { return (size_t)(2 * K + 4) * bb; }
+  size_t Ri2() const { return (size_t)(2 * K + 5) * bb; }
+  size_t Cc() const { return (size_t)(2 * K + 6) * bb; }        // 3 blocks
+  size_t P() const { return (size_t)(2 * K + 9) * bb; }         // up to (K+2) blocks
+  size_t Ref() const { return (size_t)(3 * K + 11) * bb; }      // one double: reference scale
+  size_t Skip() const { return Ref() + 1; }                     // one double: second pass not needed
+  size_t total() const { return Ref() + 2; }
+};
+
+// Block Lanczos steps used for an operator's evaluation at block width b.
+int lanczos_steps(const wl_op* op, int64_t n, int b);
+// The symmetric matrix Lanczos runs on, as a A + (b0 + b1 D): A_mu(alpha) for the
+// resolvent, A for the exponential (mu = 0).
+void lanczos_params(const wl_op* op, double* a, double* b0, double* b1);
+// Recombination coefficients F ((Ke b) x b) of phi X = V F from the projected blocks
+// A_j, B_j and X = V_0 R0 (resolvent: scale T^{-1} E_1 R0; exponential: exp(beta T) E_1 R0).
+wl_status lanczos_coefficients(const wl_op* op, int Ke, int b, const std::vector<double>& hA,
+                               const std::vector<double>& hB, const std::vector<double>& hR0,
+                               std::vector<double>& F);
+
+// ------------------------------------------------------------------ grouped blocks
+// ng blocks of width gb side by side in one n x (ng gb) row-major block (group q owns
+// columns [q gb, (q + 1) gb)); the small matrices of group q sit gs doubles apart.
+// Supported: FP32 with gb = 16 (matrix cores) and gb = 1 (any precision, ng <= 8).
+bool grouped_supported(int prec, int gb, int ng);
+// out_q + k gb^2 = (X_k)_q^T Y_q for k < nblk (X_k at X + k sX); groups whose skip flag
+// (at skip + q gs) is set are left alone.
+template <typename T>
+wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk, const T* Y,
+                       double* out, int64_t gs, const double* skip = nullptr);
+// Out_q = (wv ? wv[:, q] : alpha) .* Yin_q + beta sum_k (X_k)_q C_{q,k}, C_{q,k} at
+// C + q cs + k gb^2 (gb x gb row-major); wv is n x ng.  gram_out (optional): Out_q^T Out_q
+// at gram_out + q gs.  Per-group flags: skip (the group's update is elided: in-place
+// updates only) and skip_gram (its Gram is not formed).  Out may alias X_k or Yin.
+template <typename T>
+wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk,
+                         const double* C, int64_t cs, const T* Yin, double alpha, const T* wv, double beta, T* Out,
+                         double* gram_out, int64_t gs, const double* skip = nullptr,
+                         const double* skip_gram = nullptr);
+// y_q = x_q (count doubles) for q < ng at stride gs
+wl_status launch_dcopy_groups(wl_ctx* ctx, int ng, int count, const double* x, double* y, int64_t gs);
+// Y (n x ng b) column group q = X (n x b), or X's column group q into Y (n x b)
+template <typename T>
+wl_status launch_group_copy(wl_ctx* ctx, int64_t n, int b, int ng, int q, const T* X, T* Y, bool into_group);
+
 // ------------------------------------------------------------------ drivers
+template <typename T>
+wl_status ensure_w(wl_op* op);
 template <typename T>
 wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw);
 template <typename T>

@@ -1,7 +1,11 @@
-"""Several truncated-series operators of one graph evaluated side by side (one sparse
-product per step for all of them) against the single operators and the dense oracle.
-FP64: 1e-8 against the oracle, 1e-12 against the single operators (only the summation
-order of the sparse products differs); FP32: 2e-5 / 1e-6."""
+"""Several operators of one graph evaluated side by side (one sparse product per step
+for all of them) against the single operators and the oracle.
+Truncated series: FP64 1e-8 against the oracle, 1e-12 against the single operators
+(only the summation order of the sparse products differs); FP32 2e-5 / 1e-6.
+Lanczos groups (Sec. 4.1 run per group in lock step): FP64 1e-8 against the oracle and
+1e-10 against the single operators (grouped kernels sum in another order, amplified by
+the Krylov recurrence); FP32 2e-5 against the oracle (scaled as the single-operator
+tests) and 2e-5 against the single operators."""
 
 import numpy as np
 import pytest
@@ -82,7 +86,7 @@ def test_multi_fp32_four_operators_block16(ctx, lib):
         assert np.linalg.norm(LX[:, cols] - (wr[:, None] * X - pr)) < 2e-5 * scale
 
 
-def test_multi_rejects_lanczos_and_mixed_graphs(ctx, lib):
+def test_multi_rejects_mixed_methods_and_graphs(ctx, lib):
     n = 300
     rp, ci = synth.erdos_renyi_gnm(n, 900, 2)
     g1, g2 = lib.Graph(ctx, rp, ci), lib.Graph(ctx, rp, ci)
@@ -94,3 +98,88 @@ def test_multi_rejects_lanczos_and_mixed_graphs(ctx, lib):
         lib.Multi([rec1, lan])
     with pytest.raises(lib.WLError, match="EINVAL"):
         lib.Multi([rec1, rec2])
+
+
+def _res_alpha(g, mu, lam):
+    return 0.5 / (g.spectral_radius(mu) if mu > 0 else lam)
+
+
+def test_multi_lanczos_fp64_single_columns_and_fallback(ctx, lib):
+    """FP64 Lanczos groups: walk degrees through the grouped single-column kernels; a
+    3-wide block is evaluated operator by operator (no grouped kernels for it)."""
+    print("[gpu] multi lanczos fp64", flush=True)
+    n = 400
+    rp, ci = synth.erdos_renyi_gnm(n, 1600, 21)
+    A = walks.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    specs = [(0.0, "res", 0.5 / lam), (0.5, "res", _res_alpha(g, 0.5, lam)), (1.0, "res", _res_alpha(g, 1.0, lam)),
+             (0.0, "exp", 1.0 / lam)]
+    ops = [lib.Operator(g, mu, f, p, dtype=torch.float64, krylov_dim=40, method="lanczos") for mu, f, p in specs]
+    multi = lib.Multi(ops)
+    W = host(multi.fdeg())
+    b = 3
+    X = synth.gaussian_block(n, b, 5)
+    Xd = dev(X, torch.float64)
+    LX = host(multi.apply_L(Xd))
+    PX = host(multi.apply_phi(Xd))
+    for i, (op, (mu, f, p)) in enumerate(zip(ops, specs)):
+        ph = genfun.phi(A, mu, f, p)
+        w = ph.sum(1)
+        assert np.linalg.norm(W[:, i] - w) < 1e-8 * np.linalg.norm(w), (mu, f)
+        assert np.linalg.norm(W[:, i] - host(op.fdeg())) < 1e-10 * np.linalg.norm(w), (mu, f)
+        cols = slice(i * b, (i + 1) * b)
+        assert np.linalg.norm(PX[:, cols] - ph @ X) < 1e-8 * np.linalg.norm(ph @ X), (mu, f)
+        scale = np.linalg.norm(w[:, None] * X) + np.linalg.norm(ph @ X)
+        assert np.linalg.norm(LX[:, cols] - laplacian.apply_laplacian(ph, X)) < 1e-8 * scale, (mu, f)
+        np.testing.assert_allclose(PX[:, cols], host(op.apply_phi(Xd)), rtol=0, atol=1e-12 * np.abs(PX).max())
+
+
+@pytest.mark.parametrize("nops", [2, 3])
+def test_multi_lanczos_fp32_block16(ctx, lib, nops):
+    """FP32 Lanczos groups of 16 columns (32 or 48 values per row; three groups take two
+    workgroup column chunks in the grouped kernels), Barabasi-Albert n = 3000."""
+    print(f"[gpu] multi lanczos fp32 b16 nops={nops}", flush=True)
+    n = 3000
+    rp, ci = synth.barabasi_albert(n, 5, 13)
+    As = sparse.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = g.lambda_max()
+    specs = [(0.5, "res", _res_alpha(g, 0.5, lam)), (1.0, "res", _res_alpha(g, 1.0, lam)),
+             (0.0, "exp", 1.0 / lam)][:nops]
+    ops = [lib.Operator(g, mu, f, p, dtype=torch.float32, krylov_dim=30, method="lanczos") for mu, f, p in specs]
+    multi = lib.Multi(ops)
+    X = synth.rademacher_block(n, 16, 3)
+    Xd = dev(X, torch.float32)
+    LX = host(multi.apply_L(Xd))
+    W = host(multi.fdeg())
+    for i, (op, (mu, f, p)) in enumerate(zip(ops, specs)):
+        cols = slice(16 * i, 16 * (i + 1))
+        wr = sparse.fdeg(As, mu, f, p)
+        pr = sparse.phi_apply(As, mu, f, p, X)
+        assert np.linalg.norm(W[:, i] - wr) < 2e-5 * np.linalg.norm(wr), (mu, f)
+        scale = np.linalg.norm(wr[:, None] * X) + np.linalg.norm(pr)
+        assert np.linalg.norm(LX[:, cols] - (wr[:, None] * X - pr)) < 2e-5 * scale, (mu, f)
+        assert np.linalg.norm(LX[:, cols] - host(op.apply_L(Xd))) < 2e-5 * scale, (mu, f)
+
+
+def test_multi_lanczos_small_graph_full_reorth_fallback(ctx, lib):
+    """(steps + 1) 2 b > n: every operator runs alone (full reorthogonalisation), and the
+    grouped result equals the single operators'."""
+    print("[gpu] multi lanczos small graph", flush=True)
+    n = 90
+    rp, ci = synth.erdos_renyi_gnm(n, 400, 4)
+    A = walks.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    ops = [lib.Operator(g, mu, "res", 0.5 / lam, dtype=torch.float64, krylov_dim=20, method="lanczos")
+           for mu in (0.0, 0.25)]
+    multi = lib.Multi(ops)
+    X = synth.gaussian_block(n, 16, 9)
+    Xd = dev(X, torch.float64)
+    PX = host(multi.apply_phi(Xd))
+    for i, (op, mu) in enumerate(zip(ops, (0.0, 0.25))):
+        ph = genfun.phi(A, mu, "res", 0.5 / lam)
+        cols = slice(16 * i, 16 * (i + 1))
+        assert np.linalg.norm(PX[:, cols] - ph @ X) < 1e-8 * np.linalg.norm(ph @ X)
+        np.testing.assert_allclose(PX[:, cols], host(op.apply_phi(Xd)), rtol=0, atol=1e-12 * np.abs(PX).max())
