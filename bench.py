@@ -113,20 +113,21 @@ def copy_calibration():
                       "GBps": 5 * 2 * src.numel() * 4 / dt / 1e9}), flush=True)
 
 
-def measured_traffic(n, m, b, lanes):
-    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs, scaled by the copy-kernel calibration; None when the
-    kernel source changed since the counters were taken, the workload differs or the
-    autotuner picked another launch shape."""
+def measured_traffic(n, m, width, lanes):
+    """HBM bytes per launch of the dominant kernel (the sparse product at this block
+    width) from the committed FETCH_SIZE / WRITE_SIZE counter runs, scaled by the
+    copy-kernel calibration; None when no such record exists, the kernel source changed
+    since the counters were taken, the workload differs or the autotuner picked another
+    launch shape."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_spmm_b16_ba1m_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_spmm_w{width}_ba1m_traffic.json")
     src = os.path.join(ROOT, "paper_2601_11338_amd", "csrc", "spmm.hip")
     try:
         rec = json.load(open(path))
         sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if sha != rec.get("source_sha1") or (n, m, b) != (1000000, 5, 16) or rec.get("lanes_per_row") != lanes:
+    if sha != rec.get("source_sha1") or (n, m) != (1000000, 5) or rec.get("lanes_per_row") != lanes:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -612,69 +613,105 @@ def main():
         op.fdeg()  # cached w for the Laplacian finish
     exp_ops = [op for _, f, op in ops if f == "exp"]
     res_ops = [op for _, f, op in ops if f == "res"]
-    # extra streams: the resolvent operators (block Lanczos: latency-bound small kernels
-    # between the sparse products) run on their own contexts and streams, each with a
-    # graph handle borrowing the same device CSR, so their work overlaps
-    nstreams = max(1, min(args.streams, 1 + len(res_ops))) if not args.separate else 1
-    ctxs, workers = [ctx], []
-    if nstreams > 1:
-        import threading
-        tstreams = [torch.cuda.Stream() for _ in range(nstreams - 1)]
-        for si, ts in enumerate(tstreams):
-            c = wl.Context(0, stream=ts.cuda_stream)
-            gi = wl.Graph(c, g.rowptr, g.colidx)
-            for bb in (b, 1):  # the main handle's tuned shapes: one kernel instantiation per width
-                gi.set_shape(torch.float32, bb, *g.shape(torch.float32, bb))
-            ctxs.append(c)
-            workers.append({"ctx": c, "graph": gi, "ops": [], "W": torch.empty((n, 1), dtype=torch.float32,
-                                                                                device="cuda"),
-                            "Y": torch.empty((n, b), dtype=torch.float32, device="cuda")})
-        for k, (mu, f, op) in enumerate([o for o in ops if o[1] == "res"]):
-            wk = workers[k % len(workers)]
-            rho = op.desc.rho_hint
-            wk["ops"].append(wl.Operator(wk["graph"], mu, "res", 0.5 / rho, dtype=torch.float32, krylov_dim=K,
-                                         rho_hint=rho))
-        for wk in workers:
-            for op in wk["ops"]:
-                op.fdeg()
-        torch.cuda.synchronize()
+    res_specs = [(mu, op.desc.rho_hint) for mu, f, op in ops if f == "res"]
     if not args.separate:
-        # the five series operators side by side: walk degrees in one pass (n x 5), and
-        # L V for four of them in one pass on 64-wide rows (two whole cache lines per
-        # gathered row), the fifth alone
+        g.autotune(torch.float32, 2 * b)  # two Lanczos processes side by side
+    # Work items of one step.  Series operators: walk degrees of all five in one pass
+    # (n x 5), L V for four of them on 64-wide rows (two whole cache lines per gathered
+    # row), the fifth alone.  Resolvent operators (block Lanczos): walk degrees of all
+    # five as five single-column Lanczos processes side by side, L V of two pairs on
+    # 32-wide rows (one whole line per gathered row), the fifth alone.  Without
+    # side-by-side evaluation (--separate) every operator runs alone.
+    W5 = torch.empty((n, len(exp_ops)), dtype=torch.float32, device="cuda")
+    Y4 = torch.empty((n, 4 * b), dtype=torch.float32, device="cuda")
+
+    def res_items(graph, ops_r, sel):
+        """Callables (those with index in sel) evaluating the resolvent part of a step
+        on graph's context."""
+        if ops_r is None:
+            ops_r = [wl.Operator(graph, mu, "res", 0.5 / rho, dtype=torch.float32, krylov_dim=K, rho_hint=rho)
+                     for mu, rho in res_specs]
+        W1 = torch.empty((n, 1), dtype=torch.float32, device="cuda")
+        Y1 = torch.empty((n, b), dtype=torch.float32, device="cuda")
+        keep.extend([ops_r, W1, Y1])
+        if args.separate:
+            return [(lambda op=op: (op.apply_phi(ones, out=W1), op.apply_L(X, out=Y1)))
+                    for i, op in enumerate(ops_r) if i in sel]
+        items = []
+        if 0 in sel:
+            fdeg_all = wl.Multi(ops_r)
+            Wr = torch.empty((n, len(ops_r)), dtype=torch.float32, device="cuda")
+            ops_r[4].fdeg()  # cached w for the Laplacian finish
+            keep.extend([fdeg_all, Wr])
+            items.append(lambda: (fdeg_all.fdeg(out=Wr), ops_r[4].apply_L(X, out=Y1)))
+        for i, (lo, hi) in ((1, (0, 2)), (2, (2, 4))):
+            if i in sel:
+                pm = wl.Multi(ops_r[lo:hi])
+                Yp = torch.empty((n, 2 * b), dtype=torch.float32, device="cuda")
+                pm.apply_L(X, out=Yp)  # walk degrees of the pair, cached for the finish
+                keep.extend([pm, Yp])
+                items.append(lambda pm=pm, Yp=Yp: pm.apply_L(X, out=Yp))
+        return items
+
+    keep = []
+    if not args.separate:
         multi_all = wl.Multi(exp_ops)
         multi4 = wl.Multi(exp_ops[:4])
-        W5 = torch.empty((n, len(exp_ops)), dtype=torch.float32, device="cuda")
-        Y4 = torch.empty((n, 4 * b), dtype=torch.float32, device="cuda")
         multi4.apply_L(X, out=Y4)  # walk degrees of the group, cached
 
-    def run_worker(wk):
-        # the library enqueues on the worker context's stream; the host thread only waits
-        # for that stream when a Lanczos run reads its projected matrix
-        for op in wk["ops"]:
-            op.apply_phi(ones, out=wk["W"])
-            op.apply_L(X, out=wk["Y"])
-
-    def step():
+    def series_item():
         if args.separate:
-            for _, _, op in ops:
+            for op in exp_ops:
                 op.apply_phi(ones, out=W)
                 op.apply_L(X, out=Y)
             return
+        multi_all.fdeg(out=W5)
+        multi4.apply_L(X, out=Y4)
+        exp_ops[4].apply_L(X, out=Y)
+
+    # extra streams: the resolvent items (block Lanczos: latency-bound small kernels
+    # between the sparse products) run on their own contexts and streams, each with a
+    # graph handle borrowing the same device CSR and the main handle's tuned launch
+    # shapes, so their work overlaps
+    nstreams = max(1, args.streams) if not args.separate else 1
+    ctxs, workers = [ctx], []
+    if nstreams > 1:
+        import threading
+        nitems = 3 if not args.separate else len(res_ops)
+        tstreams = [torch.cuda.Stream() for _ in range(min(nstreams - 1, nitems))]
+        wgraphs = []
+        for ts in tstreams:
+            c = wl.Context(0, stream=ts.cuda_stream)
+            gi = wl.Graph(c, g.rowptr, g.colidx)
+            for bb in (b, 1, 2 * b, 5):  # one kernel instantiation per width
+                gi.set_shape(torch.float32, bb, *g.shape(torch.float32, bb))
+            ctxs.append(c)
+            wgraphs.append(gi)
+        # item i runs on worker i mod count, built on that worker's graph
+        for wi, gi in enumerate(wgraphs):
+            workers.append(res_items(gi, None, {i for i in range(nitems) if i % len(wgraphs) == wi}))
+        torch.cuda.synchronize()
+        res_serial = None
+    else:
+        res_serial = res_items(g, res_ops, set(range(len(res_ops))))
+
+    def run_worker(items):
+        # the library enqueues on the worker context's stream; the host thread only waits
+        # for that stream when a Lanczos run reads its projected matrices
+        for it in items:
+            it()
+
+    def step():
         if workers:
             threads = [threading.Thread(target=run_worker, args=(wk,)) for wk in workers]
             for t in threads:
                 t.start()
-        multi_all.fdeg(out=W5)
-        multi4.apply_L(X, out=Y4)
-        exp_ops[4].apply_L(X, out=Y)
+        series_item()
         if workers:
             for t in threads:
                 t.join()
             return
-        for op in res_ops:
-            op.apply_phi(ones, out=W)
-            op.apply_L(X, out=Y)
+        run_worker(res_serial)
 
     for _ in range(args.warmup):
         step()
@@ -706,9 +743,7 @@ def main():
             c.set_profiling(False)
             c.set_profiling(True)
         for _ in range(2):
-            multi_all.fdeg(out=W5)
-            multi4.apply_L(X, out=Y4)
-            exp_ops[4].apply_L(X, out=Y)
+            series_item()
             torch.cuda.synchronize()
             for wk in workers:
                 run_worker(wk)
@@ -716,21 +751,31 @@ def main():
         roofline_phase = "serialized replay of the step after the concurrent timed region"
     else:
         roofline_phase = "timed region"
-    rec, lan, mul = stats(0), stats(1), stats(3)
+    # sparse-product kernels by width: the 16-wide product (one instantiation serves the
+    # series steps of a single operator, class 0, and the Lanczos operator products,
+    # class 1), 64-wide side-by-side series steps (class 3), 32-wide side-by-side
+    # Lanczos operator products (class 4)
+    kern = []
+    for width, classes, what in ((b, (0, 1), "series steps and Lanczos operator products of single operators"),
+                                 (4 * b, (3,), "four series operators side by side"),
+                                 (2 * b, (4,), "two Lanczos operator products side by side")):
+        st = [stats(k) for k in classes]
+        nl, kms, kby = sum(x[0] for x in st), sum(x[1] for x in st), sum(x[2] for x in st)
+        if nl == 0:
+            continue
+        lanes = g.shape(torch.float32, width)[0]
+        lpn = min(16, width // 4)
+        kern.append({"kernel": f"k_spmm<float,4,{lpn},{lanes}>", "width": width, "what": what, "launches": nl,
+                     "total_ms": kms, "avg_launch_us": kms / nl * 1e3, "alg_bytes_per_launch": kby / nl,
+                     "achieved": kby / (kms * 1e-3) / 1e9, "lanes": lanes})
     for c in ctxs:
         c.set_profiling(False)
     edge_vec = len(ops) * K * nnz * (1 + b)
     value = edge_vec / (ms * 1e-3) / 1e9
-    # dominant kernel: the 16-wide sparse product (one instantiation serves the series
-    # steps of a single operator, class 0, and the Lanczos operator products, class 1)
-    launches, kms, kbytes = rec[0] + lan[0], rec[1] + lan[1], rec[2] + lan[2]
-    avg_ms = kms / max(launches, 1)
-    achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-    mul_avg = mul[1] / max(mul[0], 1)
-    mul_gbs = mul[2] / (mul[1] * 1e-3) / 1e9 if mul[1] > 0 else 0.0
-    log(f"b=16 sparse product: {launches} launches (series {rec[0]}, Lanczos {lan[0]}), avg {avg_ms * 1e3:.1f} us, "
-        f"{achieved:.0f} GB/s algorithmic; side-by-side (64 wide): {mul[0]} launches, avg {mul_avg * 1e3:.1f} us, "
-        f"{mul_gbs:.0f} GB/s algorithmic")
+    dom = max(kern, key=lambda k: k["total_ms"])
+    for k in kern:
+        log(f"width {k['width']} ({k['what']}): {k['launches']} launches, avg {k['avg_launch_us']:.1f} us, "
+            f"{k['achieved']:.0f} GB/s algorithmic, {k['total_ms']:.1f} ms in the measured steps")
     out = {
         "metric": METRIC,
         "value": value,
@@ -757,16 +802,15 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
+            "achieved": dom["achieved"],
+            "peak": 8000.0,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(n, m, b, g.shape(torch.float32, b)[0]),
-            "kernel": f"k_spmm<float,4,4,{g.shape(torch.float32, b)[0]}> (b=16: series steps and Lanczos operator "
-                      f"products)",
-            "avg_launch_us": avg_ms * 1e3,
-            "alg_bytes_per_launch": kbytes / max(launches, 1),
-            "side_by_side_kernel": {"launches": mul[0], "avg_launch_us": mul_avg * 1e3, "achieved": mul_gbs},
+            "frac": dom["achieved"] / 8000.0,
+            "traffic": measured_traffic(n, m, dom["width"], dom["lanes"]),
+            "kernel": f"{dom['kernel']} ({dom['width']} wide: {dom['what']})",
+            "avg_launch_us": dom["avg_launch_us"],
+            "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+            "other_kernels": [{k2: v for k2, v in k.items() if k2 != "lanes"} for k in kern if k is not dom],
             "measured_in": roofline_phase,
         },
     }

@@ -130,8 +130,8 @@ wl_status wl_ctx_destroy(wl_ctx* ctx);
  * the gathered block once, every row-aligned input / output block once).  Turning
  * profiling on or off clears the statistics.  Classes: 0 fused recurrence step of one
  * operator (degree >= 2, b >= 4), 1 block Lanczos operator product (b >= 4), 2 other
- * sparse products, 3 side-by-side operator step (wl_multi_*, width >= 32).  Batched
- * steps count as class 0.                                                          */
+ * sparse products, 3 side-by-side series step (wl_multi_*, width >= 32), 4 side-by-side
+ * Lanczos operator product (wl_multi_*, width >= 32).  Batched steps count as class 0. */
 wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on);
 wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launches, double* total_ms,
                               double* alg_bytes);

@@ -409,10 +409,18 @@ __global__ __launch_bounds__(256) void k_update_mfma16(int64_t n, const float* X
     }
     float o[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t row = r0 + 4 * g + v;
-      o[v] = tb * d[v];
-      if (Yin && row < n) o[v] += (wv ? wv[row] : ta) * Yin[row * 16 + c];
+    for (int v = 0; v < 4; ++v) o[v] = tb * d[v];
+    if (Yin) {  // clamped loads, zero weight past n
+      float yv[4], wq[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = min(r0 + 4 * g + v, n - 1);
+        yv[v] = Yin[row * 16 + c];
+        wq[v] = wv ? wv[row] : ta;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (r0 + 4 * g + v < n) o[v] += wq[v] * yv[v];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

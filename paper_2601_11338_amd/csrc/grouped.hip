@@ -31,7 +31,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int G1_MAXG = 8;   // groups of single columns
 constexpr int G1_MAXK = 64;  // blocks combined by one single-column update
 constexpr int G16_MAXG = 4;  // 16-wide groups per workgroup (accumulator registers)
-constexpr int G16_LDS_KB = 48;
+constexpr int G16_LDS_KB = 120;  // gfx950: up to 160 KiB of LDS per workgroup
 
 // ------------------------------------------------------------------ gb = 16 (FP32)
 
@@ -54,25 +54,30 @@ __global__ __launch_bounds__(256) void k_ggram16(int64_t n, const float* __restr
   const int64_t nchunks = (n + 15) / 16;
   for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
     const int64_t r0 = ch * 16;
+    // every operand of the chunk is requested before the first product: addresses are
+    // clamped into the block (rows past n, groups past the last) instead of branching
+    // around the loads, and rows past n get a zero Y operand
+    float y[NG][4], x[NG][NB][4];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int64_t col = (int64_t)min(qb + q, ngt - 1) * 16 + c;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = min(r0 + 4 * g + v, n - 1);
+        y[q][v] = Y[row * ld + col];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) x[q][k][v] = X[(int64_t)k * sX + row * ld + col];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
       if (!act[q]) continue;
-      const int64_t col = (int64_t)(qb + q) * 16 + c;
-      float y[4], x[NB][4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + 4 * g + v;
-        const bool ok = row < n;
-        y[v] = ok ? Y[row * ld + col] : 0.f;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) x[k][v] = ok ? X[(int64_t)k * sX + row * ld + col] : 0.f;
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double yd = (double)y[v];
+        const double yd = r0 + 4 * g + v < n ? (double)y[q][v] : 0.0;
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-          acc[q][k] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)x[k][v], yd, acc[q][k], 0, 0, 0);
+          acc[q][k] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)x[q][k][v], yd, acc[q][k], 0, 0, 0);
       }
     }
   }
@@ -162,10 +167,18 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
       }
       float o[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + 4 * g + v;
-        o[v] = tb * d[v];
-        if (Yin && row < n) o[v] += (wv ? wv[row * ngt + qb + q] : ta) * Yin[row * ld + colq + c];
+      for (int v = 0; v < 4; ++v) o[v] = tb * d[v];
+      if (Yin) {  // clamped loads, zero weight past n
+        float yv[4], wq[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = min(r0 + 4 * g + v, n - 1);
+          yv[v] = Yin[row * ld + colq + c];
+          wq[v] = wv ? wv[row * ngt + qb + q] : ta;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (r0 + 4 * g + v < n) o[v] += wq[v] * yv[v];
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -377,11 +390,24 @@ void launch_ggram16_nb(wl_ctx* ctx, dim3 grid, int ngchunk, int64_t n, const flo
     hipLaunchKernelGGL((k_ggram16<NB, 4>), grid, dim3(256), 0, ctx->stream, n, X, sX, Y, ld, ng, pp, skip, gs);
 }
 
+template <bool GRAM, int NG>
+void allow_lds() {
+  static bool done = false;  // once per instantiation and process (the attribute is per function)
+  if (!done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gupdate16<GRAM, NG>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, G16_LDS_KB * 1024);
+    done = true;
+  }
+}
+
 template <bool GRAM>
 void launch_gupdate16_ng(wl_ctx* ctx, dim3 grid, size_t lds, int ngchunk, int64_t n, const float* X, int64_t sX,
                          int nblk, int ld, int ng, const double* C, int64_t cs, const float* Yin, double alpha,
                          const float* wv, double beta, float* Out, double* pp, const double* skip,
                          const double* skip_gram, int64_t gs) {
+  allow_lds<GRAM, 1>();
+  allow_lds<GRAM, 2>();
+  allow_lds<GRAM, 4>();
   if (ngchunk == 1)
     hipLaunchKernelGGL((k_gupdate16<GRAM, 1>), grid, dim3(256), lds, ctx->stream, n, X, sX, nblk, ld, ng, C, cs,
                        Yin, alpha, wv, beta, Out, pp, skip, skip_gram, gs);

@@ -188,7 +188,7 @@ wl_status multi_lanczos(wl_multi* m, const T* X, const T* Xr, int b, T* Y, const
       ep.cgs = gs;
       ep.transC = 1;
     }
-    ep.kclass = wd >= 32 ? WL_KC_MULTI : WL_KC_OTHER_SPMM;
+    ep.kclass = wd >= 32 ? WL_KC_MULTI_LANCZOS : WL_KC_OTHER_SPMM;
     WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
     const int nbv = j > 0 ? 2 : 1;
     const T* Vlo = j > 0 ? Vp : Vj;

@@ -96,7 +96,8 @@ struct SpmmShape {
 // on the context stream, algorithmic bytes counted per launch.
 // Timing classes of sparse products: single-operator series steps (b >= 4), Lanczos
 // operator products (b >= 4), side-by-side operator steps (width >= 32), the rest.
-enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_MULTI = 3, WL_KC_COUNT = 4 };
+enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_MULTI = 3, WL_KC_MULTI_LANCZOS = 4,
+       WL_KC_COUNT = 5 };
 struct KernelStats {
   int64_t launches = 0;
   double bytes = 0.0;
