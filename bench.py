@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--separate", action="store_true",
                    help="ba1m: evaluate every operator on its own (no side-by-side series operators)")
+    p.add_argument("--shapes", default="",
+                   help="ba1m: fixed sparse-product launch shapes width:lanes:threshold,... instead of autotuning "
+                        "(e.g. to take hardware counters on the shapes a timed run chose)")
     p.add_argument("--streams", type=int, default=4,
                    help="ba1m: independent operator groups run concurrently on this many streams (one library "
                         "context per stream, all borrowing one device CSR)")
@@ -591,11 +594,16 @@ def main():
     ctx = wl.Context(0)
     g = wl.Graph(ctx, rp, ci, validate=True)
     log(f"graph n={n} nnz={nnz} max_degree={g.info()[2]}")
-    g.autotune(torch.float32, b)
-    g.autotune(torch.float32, 1)
-    if not args.separate:
-        g.autotune(torch.float32, 4 * b)  # four series operators side by side
-        g.autotune(torch.float32, 5)      # five walk-degree columns
+    widths = [b, 1] if args.separate else [b, 1, 4 * b, 5, 2 * b]  # 4 b: four series operators side by
+    if args.shapes:                                                    # side; 5: five walk-degree columns;
+        for item in args.shapes.split(","):                            # 2 b: two Lanczos processes
+            w_, l_, t_ = (int(x) for x in item.split(":"))
+            g.set_shape(torch.float32, w_, l_, t_)
+    else:
+        for w_ in widths:
+            g.autotune(torch.float32, w_)
+    log("launch shapes width:lanes:threshold " +
+        ",".join(f"{w_}:{g.shape(torch.float32, w_)[0]}:{g.shape(torch.float32, w_)[1]}" for w_ in widths))
     lam = g.lambda_max()
     mus = [0.0, 0.25, 0.5, 0.75, 1.0]
     ops = []
@@ -614,8 +622,6 @@ def main():
     exp_ops = [op for _, f, op in ops if f == "exp"]
     res_ops = [op for _, f, op in ops if f == "res"]
     res_specs = [(mu, op.desc.rho_hint) for mu, f, op in ops if f == "res"]
-    if not args.separate:
-        g.autotune(torch.float32, 2 * b)  # two Lanczos processes side by side
     # Work items of one step.  Series operators: walk degrees of all five in one pass
     # (n x 5), L V for four of them on 64-wide rows (two whole cache lines per gathered
     # row), the fifth alone.  Resolvent operators (block Lanczos): walk degrees of all
