@@ -139,9 +139,25 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
 #pragma unroll
   for (int q = 0; q < NG; ++q) gacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nchunks = (n + 15) / 16;
+  const bool few = nblk <= 4;  // every operand of a chunk fits in registers
   for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
     const int64_t r0 = ch * 16;
     const bool okA = r0 + c < n;
+    // with few blocks, all groups' operands of the chunk are requested before the first
+    // product (addresses clamped into the block, rows past n zeroed)
+    float4 xs[NG][4];
+    if (few) {
+      const int64_t rA = min(r0 + c, n - 1);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const float* xa = X + rA * ld + (int64_t)min(qb + q, ngt - 1) * 16 + 4 * g;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float4 t = *reinterpret_cast<const float4*>(xa + (int64_t)min(u, nblk - 1) * sX);
+          xs[q][u] = okA ? t : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
       if (!act[q]) continue;
@@ -149,7 +165,18 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
       const float* xa = X + (r0 + c) * ld + colq + 4 * g;
       const float4* cl = sCl + (int64_t)q * nblk * 64 + lane;
       v4f d = {0.f, 0.f, 0.f, 0.f};
-      for (int k0 = 0; k0 < nblk; k0 += 4) {
+      if (few) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u >= nblk) break;
+          const float4 bq = cl[u * 64];
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].x, bq.x, d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].y, bq.y, d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].z, bq.z, d, 0, 0, 0);
+          d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].w, bq.w, d, 0, 0, 0);
+        }
+      }
+      for (int k0 = 0; !few && k0 < nblk; k0 += 4) {
         float4 x[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -446,7 +473,7 @@ wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64
   if constexpr (sizeof(T) == 4) {
     if (gb == 16) {
       const int ngc = group_chunk(ng, 1);
-      nparts = gparts(((n + 15) / 16 + 15) / 16, 512);
+      nparts = gparts(((n + 15) / 16 + 15) / 16, 1024);
       WL_TRY(ctx->partials.ensure((size_t)nparts * ng * nblk * E * sizeof(double)));
       const dim3 grid((unsigned)nparts, (unsigned)((ng + ngc - 1) / ngc));
       double* pp = ctx->partials.as<double>();
@@ -492,7 +519,7 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
   if constexpr (sizeof(T) == 4) {
     if (gb == 16) {
       const int ngc = group_chunk(ng, std::max(nblk, 1));
-      nparts = gparts(((n + 15) / 16 + 15) / 16, gram_out ? 512 : 1024);
+      nparts = gparts(((n + 15) / 16 + 15) / 16, 1024);
       const dim3 grid((unsigned)nparts, (unsigned)((ng + ngc - 1) / ngc));
       const size_t lds = (size_t)ngc * nblk * 64 * sizeof(float4);
       const int ld = ng * 16;

@@ -183,3 +183,29 @@ def test_multi_lanczos_small_graph_full_reorth_fallback(ctx, lib):
         cols = slice(16 * i, 16 * (i + 1))
         assert np.linalg.norm(PX[:, cols] - ph @ X) < 1e-8 * np.linalg.norm(ph @ X)
         np.testing.assert_allclose(PX[:, cols], host(op.apply_phi(Xd)), rtol=0, atol=1e-12 * np.abs(PX).max())
+
+
+def test_multi_fp32_narrow_rows_per_column_weights(ctx, lib):
+    """Five series operators with one column each (rows of 5 FP32 values held by one
+    lane, every column with its own operator's weights and finish): walk degrees and
+    L x against the single operators."""
+    print("[gpu] multi fp32 narrow rows", flush=True)
+    n = 5000
+    rp, ci = synth.barabasi_albert(n, 4, 17)
+    As = sparse.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = g.lambda_max()
+    mus = [0.0, 0.25, 0.5, 0.75, 1.0]
+    ops = [lib.Operator(g, mu, "exp", 1.0 / lam, dtype=torch.float32, krylov_dim=20 + 2 * i)
+           for i, mu in enumerate(mus)]
+    multi = lib.Multi(ops)
+    W = host(multi.fdeg())
+    x = synth.gaussian_block(n, 1, 8)
+    LX = host(multi.apply_L(dev(x, torch.float32)))
+    for i, (op, mu) in enumerate(zip(ops, mus)):
+        wr = sparse.fdeg(As, mu, "exp", 1.0 / lam)
+        assert np.linalg.norm(W[:, i] - wr) < 1e-5 * np.linalg.norm(wr), mu
+        assert np.linalg.norm(W[:, i] - host(op.fdeg())) < 1e-6 * np.linalg.norm(wr), mu
+        pr = sparse.phi_apply(As, mu, "exp", 1.0 / lam, x)
+        scale = np.linalg.norm(wr[:, None] * x) + np.linalg.norm(pr)
+        assert np.linalg.norm(LX[:, i] - (wr * x[:, 0] - pr[:, 0])) < 2e-5 * scale, mu
