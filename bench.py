@@ -739,12 +739,21 @@ def main():
             st = c.kernel_stats(k)
             tot = [tot[0] + st[0], tot[1] + st[1], tot[2] + st[2]]
         return tot
+    # per-width kernel statistics of the timed region itself (events on each launch's
+    # stream; with several streams an interval also spans other streams' work)
+    timed_kern = {}
+    for width, classes in ((b, (0, 1)), (4 * b, (3,)), (2 * b, (4,))):
+        st = [stats(k) for k in classes]
+        nl, kms, kby = sum(x[0] for x in st), sum(x[1] for x in st), sum(x[2] for x in st)
+        if nl:
+            timed_kern[width] = {"launches": nl, "avg_launch_us": kms / nl * 1e3,
+                                 "achieved": kby / (kms * 1e-3) / 1e9}
     if len(ctxs) > 1:
         # With several streams the kernels of different operators share the memory
         # system, and the HIP events around one launch also span others' work.  The
         # kernel roofline therefore comes from a serialized replay of the same step
         # (same kernels, shapes and data; one stream at a time) right after the timed
-        # region.
+        # region; the timed region's own figures are reported beside it.
         for c in ctxs:
             c.set_profiling(False)
             c.set_profiling(True)
@@ -818,6 +827,7 @@ def main():
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
             "other_kernels": [{k2: v for k2, v in k.items() if k2 != "lanes"} for k in kern if k is not dom],
             "measured_in": roofline_phase,
+            "timed_region": timed_kern.get(dom["width"]),
         },
     }
     if not args.no_cpu_baseline:
