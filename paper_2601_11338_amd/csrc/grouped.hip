@@ -103,7 +103,9 @@ __global__ __launch_bounds__(256) void k_ggram16(int64_t n, const float* __restr
   }
 }
 
-template <bool GRAM, int NG>
+// NBF: the number of blocks when it is 1..4 (operands held in registers, no loads past
+// the last block), 0 for any other count
+template <bool GRAM, int NG, int NBF>
 __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, int64_t sX, int nblk, int ld, int ngt,
                                                    const double* __restrict__ C, int64_t cs, const float* Yin,
                                                    double alpha, const float* __restrict__ wv, double beta,
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
                                                    const double* __restrict__ skip_gram, int64_t gs) {
   extern __shared__ float4 sCl[];  // [NG][nblk][64] lane-ordered B operands
   __shared__ double red[NG * 256];
+  __shared__ __align__(16) float sT[4][16 * 20];  // per wave: a 16 x 16 result tile (row stride 20)
   const int qb = blockIdx.y * NG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c = lane & 15;
@@ -139,21 +142,21 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
 #pragma unroll
   for (int q = 0; q < NG; ++q) gacc[q] = v4d{0.0, 0.0, 0.0, 0.0};
   const int64_t nchunks = (n + 15) / 16;
-  const bool few = nblk <= 4;  // every operand of a chunk fits in registers
+  constexpr bool few = NBF > 0;  // every operand of a chunk fits in registers
   for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += (int64_t)gridDim.x * 4) {
     const int64_t r0 = ch * 16;
     const bool okA = r0 + c < n;
     // with few blocks, all groups' operands of the chunk are requested before the first
     // product (addresses clamped into the block, rows past n zeroed)
-    float4 xs[NG][4];
-    if (few) {
+    float4 xs[NG][NBF > 0 ? NBF : 1];
+    if constexpr (few) {
       const int64_t rA = min(r0 + c, n - 1);
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
         const float* xa = X + rA * ld + (int64_t)min(qb + q, ngt - 1) * 16 + 4 * g;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const float4 t = *reinterpret_cast<const float4*>(xa + (int64_t)min(u, nblk - 1) * sX);
+        for (int u = 0; u < NBF; ++u) {
+          const float4 t = *reinterpret_cast<const float4*>(xa + (int64_t)u * sX);
           xs[q][u] = okA ? t : make_float4(0.f, 0.f, 0.f, 0.f);
         }
       }
@@ -165,10 +168,9 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
       const float* xa = X + (r0 + c) * ld + colq + 4 * g;
       const float4* cl = sCl + (int64_t)q * nblk * 64 + lane;
       v4f d = {0.f, 0.f, 0.f, 0.f};
-      if (few) {
+      if constexpr (few) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (u >= nblk) break;
+        for (int u = 0; u < NBF; ++u) {
           const float4 bq = cl[u * 64];
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].x, bq.x, d, 0, 0, 0);
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].y, bq.y, d, 0, 0, 0);
@@ -176,14 +178,14 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q][u].w, bq.w, d, 0, 0, 0);
         }
       }
-      for (int k0 = 0; !few && k0 < nblk; k0 += 4) {
-        float4 x[4];
+      for (int k0 = 0; !few && k0 < nblk; k0 += 8) {  // eight blocks' loads in flight
+        float4 x[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 8; ++u)
           x[u] = (okA && k0 + u < nblk) ? *reinterpret_cast<const float4*>(xa + (int64_t)(k0 + u) * sX)
                                         : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           if (k0 + u >= nblk) break;
           const float4 bq = cl[(k0 + u) * 64];
           d = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u].x, bq.x, d, 0, 0, 0);
@@ -207,11 +209,6 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
         for (int v = 0; v < 4; ++v)
           if (r0 + 4 * g + v < n) o[v] += wq[v] * yv[v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + 4 * g + v;
-        if (row < n) Out[row * ld + colq + c] = o[v];
-      }
       if (gact[q]) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -219,6 +216,17 @@ __global__ __launch_bounds__(256) void k_gupdate16(int64_t n, const float* X, in
           gacc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ov, ov, gacc[q], 0, 0, 0);
         }
       }
+      // through the wave's LDS tile to row order: lane l stores row l / 4, columns
+      // 4 (l % 4) .. + 3 as one 16-byte write
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sT[wave][(4 * g + v) * 20 + c] = o[v];
+      __builtin_amdgcn_wave_barrier();
+      {
+        const int rr = lane >> 2, cc = (lane & 3) * 4;
+        const float4 t = *reinterpret_cast<const float4*>(&sT[wave][rr * 20 + cc]);
+        if (r0 + rr < n) *reinterpret_cast<float4*>(Out + (r0 + rr) * ld + colq + cc) = t;
+      }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   if (!GRAM) return;
@@ -417,13 +425,37 @@ void launch_ggram16_nb(wl_ctx* ctx, dim3 grid, int ngchunk, int64_t n, const flo
     hipLaunchKernelGGL((k_ggram16<NB, 4>), grid, dim3(256), 0, ctx->stream, n, X, sX, Y, ld, ng, pp, skip, gs);
 }
 
-template <bool GRAM, int NG>
-void allow_lds() {
-  static bool done = false;  // once per instantiation and process (the attribute is per function)
-  if (!done) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gupdate16<GRAM, NG>),
+template <bool GRAM, int NG, int NBF>
+void launch_gupdate16_k(wl_ctx* ctx, dim3 grid, size_t lds, int64_t n, const float* X, int64_t sX, int nblk, int ld,
+                        int ng, const double* C, int64_t cs, const float* Yin, double alpha, const float* wv,
+                        double beta, float* Out, double* pp, const double* skip, const double* skip_gram,
+                        int64_t gs) {
+  static bool lds_set = false;  // once per instantiation and process (the attribute is per function)
+  if (!lds_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gupdate16<GRAM, NG, NBF>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, G16_LDS_KB * 1024);
-    done = true;
+    lds_set = true;
+  }
+  hipLaunchKernelGGL((k_gupdate16<GRAM, NG, NBF>), grid, dim3(256), lds, ctx->stream, n, X, sX, nblk, ld, ng, C,
+                     cs, Yin, alpha, wv, beta, Out, pp, skip, skip_gram, gs);
+}
+
+template <bool GRAM, int NG>
+void launch_gupdate16_nb(wl_ctx* ctx, dim3 grid, size_t lds, int64_t n, const float* X, int64_t sX, int nblk, int ld,
+                         int ng, const double* C, int64_t cs, const float* Yin, double alpha, const float* wv,
+                         double beta, float* Out, double* pp, const double* skip, const double* skip_gram,
+                         int64_t gs) {
+  switch (nblk) {
+    case 1: return launch_gupdate16_k<GRAM, NG, 1>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv,
+                                                   beta, Out, pp, skip, skip_gram, gs);
+    case 2: return launch_gupdate16_k<GRAM, NG, 2>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv,
+                                                   beta, Out, pp, skip, skip_gram, gs);
+    case 3: return launch_gupdate16_k<GRAM, NG, 3>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv,
+                                                   beta, Out, pp, skip, skip_gram, gs);
+    case 4: return launch_gupdate16_k<GRAM, NG, 4>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv,
+                                                   beta, Out, pp, skip, skip_gram, gs);
+    default: return launch_gupdate16_k<GRAM, NG, 0>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv,
+                                                    beta, Out, pp, skip, skip_gram, gs);
   }
 }
 
@@ -432,18 +464,15 @@ void launch_gupdate16_ng(wl_ctx* ctx, dim3 grid, size_t lds, int ngchunk, int64_
                          int nblk, int ld, int ng, const double* C, int64_t cs, const float* Yin, double alpha,
                          const float* wv, double beta, float* Out, double* pp, const double* skip,
                          const double* skip_gram, int64_t gs) {
-  allow_lds<GRAM, 1>();
-  allow_lds<GRAM, 2>();
-  allow_lds<GRAM, 4>();
   if (ngchunk == 1)
-    hipLaunchKernelGGL((k_gupdate16<GRAM, 1>), grid, dim3(256), lds, ctx->stream, n, X, sX, nblk, ld, ng, C, cs,
-                       Yin, alpha, wv, beta, Out, pp, skip, skip_gram, gs);
+    launch_gupdate16_nb<GRAM, 1>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv, beta, Out, pp, skip,
+                                 skip_gram, gs);
   else if (ngchunk == 2)
-    hipLaunchKernelGGL((k_gupdate16<GRAM, 2>), grid, dim3(256), lds, ctx->stream, n, X, sX, nblk, ld, ng, C, cs,
-                       Yin, alpha, wv, beta, Out, pp, skip, skip_gram, gs);
+    launch_gupdate16_nb<GRAM, 2>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv, beta, Out, pp, skip,
+                                 skip_gram, gs);
   else
-    hipLaunchKernelGGL((k_gupdate16<GRAM, 4>), grid, dim3(256), lds, ctx->stream, n, X, sX, nblk, ld, ng, C, cs,
-                       Yin, alpha, wv, beta, Out, pp, skip, skip_gram, gs);
+    launch_gupdate16_nb<GRAM, 4>(ctx, grid, lds, n, X, sX, nblk, ld, ng, C, cs, Yin, alpha, wv, beta, Out, pp, skip,
+                                 skip_gram, gs);
 }
 
 // groups per workgroup for the 16-wide kernels: a power of two <= 4 whose operands fit
