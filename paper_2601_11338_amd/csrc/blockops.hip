@@ -1,17 +1,19 @@
 // Tall-skinny block kernels for the Krylov drivers and estimators (gfx950).
 //
-//  * gram:    X^T Y for n x B blocks (B <= 64), double accumulation.  Each
-//             workgroup stages 32-row tiles of both operands in LDS (coalesced
-//             loads of contiguous rows) and every thread owns entries (i, j) of
-//             the B x B result; per-workgroup partials are reduced by a second
-//             kernel in a fixed order, so results are bitwise reproducible.
-//  * update:  Out = w (.) Yin + beta * sum_k X_k C_k, one thread per row: the row
-//             segment of X_k is loaded with vector loads into registers and C_k
-//             (B x B) is broadcast from LDS; optionally the Gram of the result is
-//             accumulated in the same pass (block CholQR needs W^T W right after
-//             W is formed).
+//  * gram:    X^T Y for n x B blocks (B <= 64), double accumulation.  FP32 blocks of
+//             16, 32 or 64 columns use the FP64 matrix cores on 16-row chunks;
+//             other shapes stage 32-row tiles in LDS with every thread owning
+//             entries (i, j); single columns are plain 16-byte dot products.
+//             Per-workgroup partials are reduced by a second kernel in a fixed
+//             order, so results are bitwise reproducible.
+//  * update:  Out = w (.) Yin + beta * sum_k X_k C_k.  16-wide FP32 blocks run as a
+//             tall-skinny product on the FP32 matrix cores with the FP64 Gram of the
+//             result fused (block CholQR needs W^T W right after W is formed); other
+//             widths hold rows in registers with C_k (B x B) broadcast from LDS;
+//             single columns are 16-byte vector updates.
 //  * chol:    Cholesky with deflation of a B x B Gram and the inverse of its
-//             factor, one workgroup (column-parallel).
+//             factor, one single-wave workgroup per matrix (batched over graphs or
+//             operator groups).
 //  * probes:  Philox4x32-10 (Salmon et al., SC'11) Rademacher / Gaussian blocks.
 //  * small helpers: fills, scaled row sums, degree vector, CSR validation.
 #include "wl_internal.h"
