@@ -45,14 +45,24 @@ __global__ __launch_bounds__(256) void k_gram_seg(const int64_t* __restrict__ us
 #pragma unroll
     for (int q = 0; q < NB; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
     const int64_t r0 = us[u], r1 = us[u + 1];
+    const int cc = cok ? c : 0;  // lanes past the block width read column 0 and use zero
     for (int64_t r = r0; r < r1; r += 16) {
+      // every operand of the 16 rows is requested before the first product (a branch
+      // around each load would wait for it)
+      float yv[4], xv[NB][4];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int64_t row = r + 4 * m + rsub;
-        const double yb = cok ? (double)Y[row * b + c] : 0.0;
+        yv[m] = Y[row * b + cc];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) xv[q][m] = X[(int64_t)(kb0 + min(q, nb - 1)) * sX + row * b + cc];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double yb = cok ? (double)yv[m] : 0.0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-          const double xa = (cok && q < nb) ? (double)X[(int64_t)(kb0 + q) * sX + row * b + c] : 0.0;
+          const double xa = (cok && q < nb) ? (double)xv[q][m] : 0.0;
           acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb, acc[q], 0, 0, 0);
         }
       }
