@@ -223,23 +223,32 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
   } else {
     for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
       const int64_t r0 = ch * 16;
+      // every operand element of the chunk is requested before the first product, at
+      // addresses clamped into the blocks (a branch around each load would wait for it);
+      // out-of-range entries are zeroed afterwards
+      float ys[4][NT], xs[4][NB][NT];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const int64_t row = r0 + 4 * m + rsub;
-        const bool rok = row < n;
+        const int64_t row = min(r0 + 4 * m + rsub, n - 1);
+#pragma unroll
+        for (int J = 0; J < NT; ++J) ys[m][J] = Y[row * ldy + min(16 * J + c, by - 1)];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+          for (int I = 0; I < NT; ++I)
+            xs[m][q][I] = X[(int64_t)(kb0 + min(q, nb - 1)) * sX + row * ldx + min(16 * I + c, bx - 1)];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const bool rok = r0 + 4 * m + rsub < n;
         double yb[NT];
 #pragma unroll
-        for (int J = 0; J < NT; ++J) {
-          const int col = 16 * J + c;
-          yb[J] = (rok && col < by) ? (double)Y[row * ldy + col] : 0.0;
-        }
+        for (int J = 0; J < NT; ++J) yb[J] = (rok && 16 * J + c < by) ? (double)ys[m][J] : 0.0;
 #pragma unroll
         for (int q = 0; q < NB; ++q)
 #pragma unroll
           for (int I = 0; I < NT; ++I) {
-            const int col = 16 * I + c;
-            const double xa =
-                (rok && q < nb && col < bx) ? (double)X[(int64_t)(kb0 + q) * sX + row * ldx + col] : 0.0;
+            const double xa = (rok && q < nb && 16 * I + c < bx) ? (double)xs[m][q][I] : 0.0;
 #pragma unroll
             for (int J = 0; J < NT; ++J)
               acc[q][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, yb[J], acc[q][I][J], 0, 0, 0);
