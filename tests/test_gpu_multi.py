@@ -233,3 +233,22 @@ def test_multi_lanczos_fp32_rank_deficient_block(ctx, lib):
         cols = slice(16 * i, 16 * (i + 1))
         assert np.linalg.norm(PX[:, cols] - pr) < 2e-5 * np.linalg.norm(pr), (mu, f)
         assert np.linalg.norm(PX[:, cols][:, 10:] - PX[:, cols][:, :6]) < 2e-5 * np.linalg.norm(pr), (mu, f)
+
+
+def test_multi_lanczos_nine_single_columns_fall_back(ctx, lib):
+    """Nine single-column Lanczos groups exceed the grouped kernels' eight: the walk
+    degrees are evaluated operator by operator and equal the single operators'."""
+    print("[gpu] multi lanczos nine groups", flush=True)
+    n = 500
+    rp, ci = synth.erdos_renyi_gnm(n, 2500, 31)
+    A = walks.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = np.linalg.eigvalsh(A)[-1]
+    mus = np.linspace(0.0, 1.0, 9)
+    ops = [lib.Operator(g, mu, "res", _res_alpha(g, mu, lam), dtype=torch.float64, krylov_dim=40, method="lanczos")
+           for mu in mus]
+    W = host(lib.Multi(ops).fdeg())
+    for i, (op, mu) in enumerate(zip(ops, mus)):
+        w = genfun.phi(A, mu, "res", _res_alpha(g, mu, lam)).sum(1)
+        assert np.linalg.norm(W[:, i] - w) < 1e-8 * np.linalg.norm(w), mu
+        np.testing.assert_allclose(W[:, i], host(op.fdeg()), rtol=0, atol=1e-13 * np.abs(w).max())
