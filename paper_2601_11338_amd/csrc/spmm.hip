@@ -60,12 +60,22 @@ __device__ __forceinline__ void stf(T* p, const Frag<T, VW>& f) {
   *reinterpret_cast<V*>(p) = x;
 }
 
+// Masked fragment load: lanes whose columns lie past the block read nothing.  With
+// VW > 1 the block width is a multiple of VW, so a fragment is wholly in or out.
 template <typename T, int VW, bool MASK>
 __device__ __forceinline__ Frag<T, VW> ldf_m(const T* p, bool ok) {
-  if constexpr (MASK) {
+  if constexpr (MASK && VW == 1) {
     Frag<T, VW> f;
+    f.v[0] = ok ? p[0] : T(0);
+    return f;
+  } else if constexpr (MASK) {
+    Frag<T, VW> f;
+    if (ok) {
+      f = ldf<T, VW>(p);
+    } else {
 #pragma unroll
-    for (int i = 0; i < VW; ++i) f.v[i] = ok ? p[i] : T(0);
+      for (int i = 0; i < VW; ++i) f.v[i] = T(0);
+    }
     return f;
   } else {
     return ldf<T, VW>(p);
@@ -163,7 +173,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
     Frag<T, VW> o;
 #pragma unroll
     for (int i = 0; i < VW; ++i) o.v[i] = y[i];
-    if constexpr (MASK) {
+    if constexpr (MASK && VW == 1) {
       Y[off] = o.v[0];
     } else {
       stf<T, VW>(Y + off, o);
@@ -172,7 +182,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
   if (ep.Sout) {
     Frag<T, VW> s;
     if (ep.Sin)
-      s = MASK ? ldf_m<T, VW, MASK>(ep.Sin + off, true) : ldf_nt<T, VW>(ep.Sin + off);
+      s = (MASK && VW == 1) ? ldf_m<T, VW, MASK>(ep.Sin + off, true) : ldf_nt<T, VW>(ep.Sin + off);
     else
       zero(s);
     const T s0 = (T)ep.s0, sc = (T)csc;
@@ -180,11 +190,11 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
     for (int i = 0; i < VW; ++i) s.v[i] = s0 * s.v[i] + sc * y[i];
     if (fin) {
       const T wr = ep.wld ? ep.wv[r * (int64_t)ep.wld + col / ep.cgw] : ep.wv[r];
-      Frag<T, VW> xw = MASK ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
+      Frag<T, VW> xw = (MASK && VW == 1) ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
 #pragma unroll
       for (int i = 0; i < VW; ++i) s.v[i] = wr * xw.v[i] - s.v[i];
     }
-    if constexpr (MASK) {
+    if constexpr (MASK && VW == 1) {
       ep.Sout[off] = s.v[0];
     } else {
       stf_nt<T, VW>(ep.Sout + off, s);
@@ -231,7 +241,6 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
                                               const T* __restrict__ X, T* Y, EpiArgs<T> ep,
                                               const int32_t* __restrict__ long_rows, int n_long,
                                               int long_thr) {
-  static_assert(MASK == false || VW == 1, "masked kernels are scalar");
   constexpr int TILE = VW * LPN;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sC = reinterpret_cast<T*>(smem_raw);
@@ -409,6 +418,9 @@ wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep
     if (lanes == 2) return run_g<T, VW, 2, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes <= 4 && lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 16 == 0) return run_g<T, VW, 16, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    // 12 vectors (48 FP32 values): one 16-lane segment with the last four lanes idle
+    // gathers each neighbour row once, where three 4-lane tiles would gather it thrice
+    if (lanes == 12) return run_g<T, VW, 16, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 8 == 0) return run_g<T, VW, 8, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
   }
