@@ -57,3 +57,33 @@ def stationary_distribution(phi):
     """pi = w / sum(w): pi P = 1^T phi / sum(w) = pi since phi is symmetric."""
     w = walk_degree(phi)
     return w / w.sum()
+
+
+def markov_steps(phi, P0, steps):
+    """Discrete-time diffusion p_{k+1} = p_k P (Sec. "Simulating discrete-time
+    diffusion"), for the distributions stored as the columns of P0 (column j = p_0^T):
+    each step multiplies by P^T.  Returns the columns after `steps` steps."""
+    P = markov_transition(phi)
+    X = np.array(P0, dtype=np.float64)
+    for _ in range(steps):
+        X = P.T @ X
+    return X
+
+
+def markov_spectrum(phi):
+    """Eigenvalues of P = diag(w)^{-1} phi in increasing order, from the symmetric
+    matrix diag(w)^{-1/2} phi diag(w)^{-1/2} that is similar to P (w > 0)."""
+    w = walk_degree(phi)
+    r = 1.0 / np.sqrt(w)
+    S = r[:, None] * phi * r[None, :]
+    return np.linalg.eigvalsh(0.5 * (S + S.T))
+
+
+def spectral_gap(phi):
+    """(lambda_2, lambda_min, gap) of the chain: lambda_2 is the largest eigenvalue of P
+    below the top one (1, eigenvector 1), lambda_min the smallest, and the gap separates
+    1 from the next eigenvalue in modulus: gap = 1 - max(|lambda_2|, |lambda_min|)
+    (the quantity compared across Laplacians in the tree experiment of Sec. 5)."""
+    lam = markov_spectrum(phi)
+    lam2, lmin = lam[-2], lam[0]
+    return float(lam2), float(lmin), float(1.0 - max(abs(lam2), abs(lmin)))
