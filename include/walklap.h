@@ -206,6 +206,27 @@ wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b);
 wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt,
                   void* const* d_Y, int32_t outer_dim, double* err_est);
 
+/* ---------------------------------------------------------------- discrete-time diffusion
+ * The Markov chain of a walk Laplacian (Sec. "Simulating discrete-time diffusion",
+ * eq. let_there_be_markov): P = I - D^{-1} L with D = diag(w), w = phi 1 (the reading
+ * that reproduces the stationary distributions printed in Fig. 1), so
+ * P = diag(w)^{-1} phi is row-stochastic with stationary distribution pi = w / sum(w).
+ * The chain needs w > 0 (every resolvent, the exponential at mu = 0).
+ *
+ * wl_markov_step: d_X (n x b, row-major) holds b distributions as columns (p_0^T);
+ * d_Y receives them after `steps` >= 1 steps p_{k+1} = p_k P, each computed as
+ * p_{k+1}^T = phi (p_k^T ./ w) (one phi product).  1 <= b <= 64, d_X != d_Y.
+ * wl_markov_stationary: d_pi (n) = w / sum(w).
+ * wl_markov_gap: lambda_2 (largest eigenvalue of P below 1), lambda_min and
+ * gap = 1 - max(|lambda_2|, |lambda_min|), estimated by outer_dim (2..1000) fully
+ * reorthogonalised single-vector Lanczos steps on diag(w)^{-1/2} phi diag(w)^{-1/2}
+ * with the eigenvector sqrt(w) deflated, from a Gaussian start vector (Philox stream
+ * `seed`); each step is one phi product.  Any output pointer may be NULL.  n >= 3.  */
+wl_status wl_markov_step(wl_op* op, const void* d_X, int32_t b, int32_t steps, void* d_Y);
+wl_status wl_markov_stationary(wl_op* op, void* d_pi);
+wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
+                        double* gap);
+
 /* ---------------------------------------------------------------- block Krylov primitives
  * The tall-skinny kernels every block Lanczos step is made of (Sec. 4.1: the basis
  * Q_k and its projection H_k), exposed for callers building their own drivers.

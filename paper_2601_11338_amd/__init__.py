@@ -263,6 +263,27 @@ class Operator:
         check(load().wl_expv(self.handle, _ptr(U0), U0.shape[1], tarr, len(ts), parr, int(outer_dim), err))
         return outs, list(err)
 
+    def markov_step(self, X, steps=1, out=None):
+        """Distributions held as the columns of X (n x b) after `steps` steps of the
+        chain P = diag(w)^{-1} phi (p_{k+1} = p_k P)."""
+        X = self._block(X)
+        out = self._out(out, X)
+        check(load().wl_markov_step(self.handle, _ptr(X), X.shape[1], int(steps), _ptr(out)))
+        return out
+
+    def markov_stationary(self, out=None):
+        """pi = w / sum(w), the chain's stationary distribution."""
+        out = self._empty(self.graph.n) if out is None else out
+        _need(out, "out", self.dtype, (self.graph.n,))
+        check(load().wl_markov_stationary(self.handle, _ptr(out)))
+        return out
+
+    def markov_gap(self, outer_dim=60, seed=7):
+        """(lambda_2, lambda_min, gap) of the chain, by Lanczos on its symmetrised form."""
+        l2, lm, gp = C.c_double(), C.c_double(), C.c_double()
+        check(load().wl_markov_gap(self.handle, int(outer_dim), int(seed), C.byref(l2), C.byref(lm), C.byref(gp)))
+        return l2.value, lm.value, gp.value
+
     def diag_est(self, M, seed, target="phi", t=0.0, law="gauss", estimator="hutchinson", cv=None, outer_dim=30):
         out = self._empty(self.graph.n)
         if cv is not None:

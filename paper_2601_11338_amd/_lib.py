@@ -64,6 +64,9 @@ SIGNATURES = {
     "wl_apply_phi": (C.c_int, [vp, vp, vp, i32]),
     "wl_apply_L": (C.c_int, [vp, vp, vp, i32]),
     "wl_expv": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd]),
+    "wl_markov_step": (C.c_int, [vp, vp, i32, i32, vp]),
+    "wl_markov_stationary": (C.c_int, [vp, vp]),
+    "wl_markov_gap": (C.c_int, [vp, i32, C.c_uint64, pd, pd, pd]),
     "wl_probes": (C.c_int, [vp, i32, i32, u64, u32, i64, i32, vp]),
     "wl_block_gram": (C.c_int, [vp, i32, i64, i32, i32, vp, i32, vp, pd]),
     "wl_block_update": (C.c_int, [vp, i32, i64, i32, i32, vp, pd, vp, f64, f64, vp, pd]),

@@ -448,9 +448,14 @@ namespace {
 // three-term subtraction W -= Vprev Bprev^T fused when possible.
 template <typename T>
 struct LanczosOp {
-  int kind = 0;  // 0: a*A + (b0 + b1 d) I (one SpMM); 1: walk Laplacian of an operator
+  // 0: a*A + (b0 + b1 d) I (one SpMM); 1: walk Laplacian of an operator;
+  // 2: the symmetrised Markov matrix of an operator, diag(w)^{-1/2} phi diag(w)^{-1/2}
+  int kind = 0;
   double a = 1.0, b0 = 0.0, b1 = 0.0;
-  wl_op* inner = nullptr;  // kind 1
+  wl_op* inner = nullptr;  // kinds 1, 2
+  const T* rw = nullptr;   // kind 2: w^{-1/2}
+  T* tmp1 = nullptr;       // kind 2: n x b scratch
+  T* tmp2 = nullptr;       // kind 2: n x b scratch
 };
 
 template <typename T>
@@ -472,9 +477,18 @@ wl_status apply_lanczos_op(wl_graph* g, const LanczosOp<T>& L, const T* V, T* W,
     ep.kclass = b >= 4 ? WL_KC_LANCZOS_OP : WL_KC_OTHER_SPMM;
     return launch_spmm<T>(g, V, W, b, ep, shape_for(g, prec_of<T>(), b));
   }
-  // walk Laplacian: W = w (.) V - phi V, then the three-term subtraction
   wl_op* op = L.inner;
-  WL_TRY(phi_apply_impl<T>(op, V, W, b, op->w.as<T>(), V));
+  if (L.kind == 2) {
+    // W = D^{-1/2} phi D^{-1/2} V (the driver keeps the basis orthogonal to v)
+    const int64_t n = g->n;
+    WL_TRY(launch_axpby_rows<T>(g->ctx, n, b, L.rw, V, 0.0, V, L.tmp1));
+    WL_TRY(phi_apply_impl<T>(op, L.tmp1, L.tmp2, b, nullptr, nullptr));
+    WL_TRY(launch_axpby_rows<T>(g->ctx, n, b, L.rw, L.tmp2, 0.0, L.tmp2, W));
+  } else {
+    // walk Laplacian: W = w (.) V - phi V
+    WL_TRY(phi_apply_impl<T>(op, V, W, b, op->w.as<T>(), V));
+  }
+  // then the three-term subtraction
   if (Vprev) {
     WL_TRY(launch_dtranspose(g->ctx, b, Bprev, scratch));
     WL_TRY(launch_update<T>(g->ctx, g->n, Vprev, b, 0, 1, scratch, W, 1.0, nullptr, -1.0, W, b, nullptr));
@@ -555,7 +569,8 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
     WL_TRY(launch_update<T>(ctx, n, Vj, b, 0, 1, S + Ly.A(j), Wb, 1.0, nullptr, -1.0, Wb, b,
                             second ? nullptr : S + Ly.G()));
     if (second) {
-      const int lo = reorth >= 2 ? 0 : std::max(0, j - 1);
+      // reorth 3: also against the block stored just before slot 0 (a locked vector)
+      const int lo = reorth >= 3 ? -1 : (reorth >= 2 ? 0 : std::max(0, j - 1));
       const int nb = j - lo + 1;
       const T* Vlo = basis + (size_t)lo * blk;
       WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nb, Wb, b, S + Ly.P()));
@@ -906,6 +921,78 @@ wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* c
 template wl_status expv_impl<float>(wl_op*, const float*, int, const double*, int, float* const*, int, double*);
 template wl_status expv_impl<double>(wl_op*, const double*, int, const double*, int, double* const*, int, double*);
 
+// The chain P = diag(w)^{-1} phi (Sec. "Simulating discrete-time diffusion") is similar
+// to the symmetric S = D^{-1/2} phi D^{-1/2}, whose top eigenvalue 1 has eigenvector
+// sqrt(w).  Single-vector Lanczos, fully reorthogonalised, on S with that eigenvector
+// deflated, from a seeded Gaussian start vector orthogonal to it: the extreme Ritz
+// values of the projected tridiagonal matrix estimate lambda_2 and lambda_min of P, and
+// the gap separates 1 from the next eigenvalue in modulus (the quantity compared
+// across Laplacians in the tree experiment, Sec. 5).
+template <typename T>
+wl_status markov_gap_impl(wl_op* op, int outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
+                          double* gap) {
+  wl_graph* g = op->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  WL_CHECK(n >= 3, WL_EINVAL, "wl_markov_gap: needs n >= 3");
+  WL_TRY(ensure_w<T>(op));
+  const int K = (int)std::max<int64_t>(2, std::min<int64_t>(outer_dim, n - 1));
+  // outer basis: v = sqrt(w) / ||sqrt(w)|| in the block before slot 0, so that every
+  // new Lanczos vector is orthogonalised against it with the earlier ones (a rounding-
+  // level component along v would otherwise grow from step to step, by about
+  // alpha / beta, until the eigenvalue 1 reappears among the Ritz values)
+  WL_TRY(op->outer_basis.ensure((size_t)(K + 2) * n * sizeof(T)));
+  WL_TRY(op->outer_w.ensure((size_t)n * sizeof(T)));
+  T* vptr = op->outer_basis.as<T>();
+  DevBuf rw, x0, t1, t2, dd;
+  WL_TRY(rw.ensure((size_t)n * sizeof(T)));
+  WL_TRY(x0.ensure((size_t)n * sizeof(T)));
+  WL_TRY(t1.ensure((size_t)n * sizeof(T)));
+  WL_TRY(t2.ensure((size_t)n * sizeof(T)));
+  WL_TRY(dd.ensure(2 * sizeof(double)));
+  WL_TRY(launch_wpow<T>(ctx, n, op->w.as<T>(), 1, rw.as<T>()));  // w^{-1/2}
+  WL_TRY(launch_wpow<T>(ctx, n, op->w.as<T>(), 2, t1.as<T>()));  // sqrt(w)
+  WL_TRY(launch_gram<T>(ctx, n, t1.as<T>(), 1, 0, 1, t1.as<T>(), 1, dd.as<double>()));
+  double sw = 0.0;  // sum(w) = ||sqrt(w)||^2
+  WL_HIP(hipMemcpyAsync(&sw, dd.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  WL_CHECK(sw > 0.0 && is_finite(sw), WL_ENUMERIC, "wl_markov_gap: walk degrees do not sum to a positive number");
+  WL_TRY(launch_update<T>(ctx, n, t1.as<T>(), 1, 0, 0, nullptr, t1.as<T>(), 1.0 / std::sqrt(sw), nullptr, 0.0, vptr,
+                          1, nullptr));
+  // start vector: Gaussian, with its component along v removed
+  WL_TRY(launch_probes<T>(ctx, WL_PROBE_GAUSS, seed, 0, n, 1, x0.as<T>()));
+  WL_TRY(launch_gram<T>(ctx, n, vptr, 1, 0, 1, x0.as<T>(), 1, dd.as<double>()));
+  WL_TRY(launch_update<T>(ctx, n, vptr, 1, 0, 1, dd.as<double>(), x0.as<T>(), 1.0, nullptr, -1.0, x0.as<T>(), 1,
+                          nullptr));
+  LanczosOp<T> L;
+  L.kind = 2;
+  L.inner = op;
+  L.rw = rw.as<T>();
+  L.tmp1 = t1.as<T>();
+  L.tmp2 = t2.as<T>();
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<T>(g, L, x0.as<T>(), 1, K, 3, vptr + n, op->outer_w.as<T>(), op->outer_small, hA, hB, hR0,
+                          &Ke));
+  std::vector<double> lam(Ke);
+  if (tridiag_eigvals(Ke, hA.data(), hB.data(), lam.data())) {
+    wl_set_error("wl_markov_gap: eigenvalues of the projected matrix failed");
+    return WL_ENOCONV;
+  }
+  double lmax = lam[0], lmin = lam[0];
+  for (double x : lam) {
+    lmax = std::max(lmax, x);
+    lmin = std::min(lmin, x);
+  }
+  if (lambda2) *lambda2 = lmax;
+  if (lambda_min) *lambda_min = lmin;
+  if (gap) *gap = 1.0 - std::max(std::fabs(lmax), std::fabs(lmin));
+  return WL_OK;
+}
+
+template wl_status markov_gap_impl<float>(wl_op*, int, uint64_t, double*, double*, double*);
+template wl_status markov_gap_impl<double>(wl_op*, int, uint64_t, double*, double*, double*);
+
 // ------------------------------------------------------------------ spectral scale
 // kind 0: A; kind 1: A_mu(t).  Runs `steps` single-vector Lanczos steps from 1 and
 // returns the extreme Ritz values.
@@ -1181,6 +1268,15 @@ wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
   }
   WL_TRY(ensure_w<double>(op));
   return phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, op->w.as<double>(), (const double*)d_X);
+}
+
+wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
+                        double* gap) {
+  WL_CHECK(op, WL_EINVAL, "wl_markov_gap: op is null");
+  WL_CHECK(outer_dim >= 2 && outer_dim <= 1000, WL_EINVAL, "wl_markov_gap: outer_dim must lie in [2, 1000]");
+  DeviceGuard dg(op->g->ctx->device);
+  if (op->d.prec == WL_FP32) return markov_gap_impl<float>(op, outer_dim, seed, lambda2, lambda_min, gap);
+  return markov_gap_impl<double>(op, outer_dim, seed, lambda2, lambda_min, gap);
 }
 
 wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,

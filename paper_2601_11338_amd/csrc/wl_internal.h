@@ -406,6 +406,14 @@ wl_status launch_dcopy_groups(wl_ctx* ctx, int ng, int count, const double* x, d
 template <typename T>
 wl_status launch_group_copy(wl_ctx* ctx, int64_t n, int b, int ng, int q, const T* X, T* Y, bool into_group);
 
+// ------------------------------------------------------------------ discrete-time diffusion
+// out = x^(-1) (mode 0), x^(-1/2) (mode 1) or x^(1/2) (mode 2), elementwise over n
+template <typename T>
+wl_status launch_wpow(wl_ctx* ctx, int64_t n, const T* x, int mode, T* out);
+// out = x / *den with den one device double
+template <typename T>
+wl_status launch_div_by(wl_ctx* ctx, int64_t n, const T* x, const double* den, T* out);
+
 // ------------------------------------------------------------------ drivers
 template <typename T>
 wl_status ensure_w(wl_op* op);
@@ -414,4 +422,7 @@ wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const 
 template <typename T>
 wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* const* Y, int outer_dim,
                     double* err_est);
+template <typename T>
+wl_status markov_gap_impl(wl_op* op, int outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
+                          double* gap);
 wl_status lanczos_extreme(wl_graph* g, int kind, double mu, double t, int steps, double* lo, double* hi);
