@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="ba1m", choices=["ba1m", "batch512", "cv-rmat22", "expv-rmat25"],
+    p.add_argument("--workload", default="ba1m", choices=["ba1m", "batch512", "cv-rmat22", "expv-rmat25", "markov-ba1m"],
                    help="ba1m: one Barabasi-Albert graph, n=10^6 (default); batch512: 512 SBM / "
                         "configuration-model graphs, diffusion and return probabilities in one batch; "
                         "cv-rmat22: learned control variate trained on 200 small graphs, diagonal "
@@ -431,6 +431,145 @@ def run_expv_rmat25(args):
 MLP_SHAPES = [(64, 8), (64,), (64, 64), (64,), (1, 64), (1,)]
 
 
+def run_markov_ba1m(args):
+    """Discrete-time diffusion on the BA graph of the default workload (n = 1e6, m = 5):
+    the chain P = diag(w)^{-1} phi of the nonbacktracking exponential (mu = 1, beta =
+    1/lambda_max, series degree from the tail bound at 1e-9), the operator whose chain
+    explores a tree most widely in the paper's tree experiment.  One step = 20 steps of
+    the chain from 16 starting nodes (point masses, FP32) + its stationary distribution
+    + its spectral gap (Lanczos, 60 steps, on the symmetrised chain)."""
+    import numpy as np
+    import torch
+
+    import paper_2601_11338_amd as wl
+    import synth
+
+    n, m, b, chain, gap_dim = 1_000_000, 5, 16, 20, 60
+    log("generating Barabasi-Albert graph")
+    rp, ci = synth.barabasi_albert(n, m, seed=2026)
+    nnz = int(ci.size)
+    starts = np.random.default_rng(590).choice(n, size=b, replace=False)
+    P0_h = synth.spike_block(n, starts, dtype=np.float32)
+    ctx = wl.Context(0)
+    g = wl.Graph(ctx, rp, ci, validate=True)
+    for w_ in (b, 1):
+        g.autotune(torch.float32, w_)
+    lam = g.lambda_max()
+    op = wl.Operator(g, 1.0, "exp", 1.0 / lam, dtype=torch.float32, tol=1e-9)
+    K_in, _ = op.info()
+    log(f"graph n={n} nnz={nnz}; lambda_max={lam:.4f}; series degree {K_in}")
+    P0 = torch.tensor(P0_h, device="cuda")
+    Pk = torch.empty_like(P0)
+    pi = torch.empty(n, dtype=torch.float32, device="cuda")
+    op.fdeg()  # w, cached by the operator
+
+    def step():
+        op.markov_step(P0, steps=chain, out=Pk)
+        op.markov_stationary(out=pi)
+        return op.markov_gap(outer_dim=gap_dim, seed=7)
+
+    for _ in range(args.warmup):
+        step()
+        log("warm-up step done")
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        l2, lmin, gap = step()
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done; lambda_2={l2:.6f} lambda_min={lmin:.6f} gap={gap:.6f}")
+    t1 = time.perf_counter()
+    rec = ctx.kernel_stats(0)   # series steps on the 16 distributions
+    oth = ctx.kernel_stats(2)   # first steps and the single-vector products of the gap
+    ctx.set_profiling(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    # every application of phi is K_in sparse products: chain * b columns for the
+    # steps and gap_dim single columns for the gap
+    edge_vec = K_in * float(nnz) * (chain * b + gap_dim)
+    value = edge_vec / (ms * 1e-3) / 1e9
+    launches, kms, kbytes = rec
+    avg_ms = kms / max(launches, 1)
+    achieved = (kbytes / max(launches, 1)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    mass = [float(x) for x in Pk.sum(dim=0).cpu()]
+    tv = float((Pk - pi[:, None]).abs().sum(dim=0).max()) / 2
+    log(f"series kernel: {launches} launches, avg {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic; "
+        f"other: {oth[0]} launches, {oth[1]:.1f} ms; mass {min(mass):.6f}..{max(mass):.6f}; "
+        f"max TV distance to pi after {chain} steps {tv:.4f}")
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GEdge·vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"discrete-time diffusion on barabasi-albert n={n} m={m} nnz={nnz}: chain of the "
+                        f"mu=1 exp (beta=1/lambda_max, series degree {K_in}); {chain} chain steps from {b} "
+                        f"starting nodes + stationary distribution + spectral gap (Lanczos dim {gap_dim}); "
+                        f"FP32 vectors, FP64 coefficients",
+            "n": n,
+            "nnz": nnz,
+            "block": b,
+            "chain_steps": chain,
+            "gap_krylov_dim": gap_dim,
+            "inner_degree": K_in,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": f"k_spmm fused recurrence step (b={b})",
+            "avg_launch_us": avg_ms * 1e3,
+            "alg_bytes_per_launch": kbytes / max(launches, 1),
+            "other_kernels": [{"what": "first steps and single-vector products of the gap", "launches": oth[0],
+                               "total_ms": oth[1],
+                               "achieved": oth[2] / (oth[1] * 1e-3) / 1e9 if oth[1] else 0.0}],
+        },
+        "gap": {"lambda_2": l2, "lambda_min": lmin, "gap": gap},
+        "mass": [min(mass), max(mass)],
+        "tv_to_stationary": tv,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline_markov(rp, ci, n, lam, K_in, P0_h)
+    return out
+
+
+def cpu_baseline_markov(rp, ci, n, lam, K, P0):
+    """The oracle (sparse FP64 series, eq. qrec) on a bounded sample of the step: the
+    walk degrees w and two chain steps p <- phi (p ./ w) on the 16 distributions."""
+    import numpy as np
+    from oracle import sparse
+
+    A = sparse.adjacency(n, rp, ci)
+    beta = 1.0 / lam
+    coeffs = np.array([beta ** k / math.factorial(k) for k in range(K + 1)])
+    t0 = time.perf_counter()
+    w = sparse.series_apply(A, 1.0, coeffs, np.ones((n, 1)))
+    X = P0.astype(np.float64)
+    for _ in range(2):
+        X = sparse.series_apply(A, 1.0, coeffs, X / w)
+    dt = time.perf_counter() - t0
+    ev = K * A.nnz * (1 + 2 * P0.shape[1])
+    return {
+        "value": ev / dt / 1e9,
+        "unit": "GEdge·vec/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"walk degrees + 2 chain steps on {P0.shape[1]} distributions (mu=1, exp, degree {K}), "
+                  f"scipy.sparse single-threaded FP64, {dt:.1f} s",
+    }
+
+
 def run_cv_rmat22(args):
     """Learned control variate.  Operator: mu = 0.5 (theta = 0.5), exponential with
     beta = 1/lambda_max, truncated series (FP32 vectors).  Training: 200 graphs
@@ -579,6 +718,9 @@ def main():
         return
     if args.workload == "expv-rmat25":
         print(json.dumps(run_expv_rmat25(args)), flush=True)
+        return
+    if args.workload == "markov-ba1m":
+        print(json.dumps(run_markov_ba1m(args)), flush=True)
         return
     import numpy as np
     import torch
