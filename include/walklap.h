@@ -227,6 +227,55 @@ wl_status wl_markov_stationary(wl_op* op, void* d_pi);
 wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
                         double* gap);
 
+/* ---------------------------------------------------------------- rational Krylov (Alg. 1)
+ * Average return probability p(t) = tr exp(-t L) / n (eq. average_return_probabilities)
+ * by the randomized estimate of Alg. 1: AAA poles of exp(-x) on [0, t_max rho(L)], the
+ * block rational Krylov space of L and Omega with those poles
+ * (eq. block-rational-Krylov), exp(-t T) of the projected matrix for every t, and the
+ * leave-one-out Nystrom trace estimate on Y(t) = V exp(-t T) V^T Omega / n with Omega.
+ *
+ * wl_aaa: AAA (Nakatsukasa, Sete, Trefethen 2018) on N real samples F = f(Z) (host
+ * arrays), tolerance tol relative to max |F|, at most mmax support points.  poles:
+ * host array of 2 cap doubles receiving (re, im) of up to cap poles of the approximant;
+ * npoles their number; max_err the largest error on Z (each may be NULL).  Host only.
+ * wl_exp_poles: the poles wl_return_prob uses for exp(-x) on [0, xmax]: AAA on 1000
+ * equispaced points plus 1000 points xmax 10^(-6 + 6 i / 999), real poles lying on
+ * [0, xmax] (spurious pole-zero pairs) dropped.  Host only.
+ *
+ * wl_return_prob: d_Omega n x M (row-major, operator precision, device; e.g. Gaussian
+ * probes from wl_probes), 2 <= M <= 32, n > M.  t (host, nt values >= 0); t_max > 0 the
+ * end of the time window; rho > 0 the spectral radius of L to use (<= 0: estimated by
+ * 40 Lanczos steps: the largest Ritz value plus its residual norm).  Poles: the wl_exp_poles
+ * poles for xmax = t_max rho, divided by pole_time (1: as the algorithm states; t_max:
+ * the poles of r(t_max lambda) ~ exp(-t_max lambda), accurate for t near t_max).  Each
+ * real pole adds one basis block, each conjugate pair two (the real and imaginary parts
+ * of (L - xi)^{-1} U, U the last block); the shifted systems are solved by COCG to the
+ * relative residual solve_tol within max_iters iterations (WL_ENOCONV otherwise).  The
+ * projected matrix is V^T L V.  p_hat, e_hat (host, nt, may be NULL): the estimates and
+ * their error estimates (standard error over the left-out probes).  poles (host,
+ * 2 poles_cap doubles, may be NULL): the poles used.  info (may be NULL): counts and
+ * residuals.  rcond: the Nystrom cores drop eigenvalues below rcond times the largest.
+ * Memory: (1 + poles) blocks of n x M plus four n x 2M blocks.                      */
+typedef struct {
+  int32_t npoles;      /* finite poles used (a conjugate pair counts two) */
+  int32_t nblocks;     /* basis blocks: Omega's, one per real pole, two per pair */
+  int32_t solves;      /* shifted solves: one per real pole or conjugate pair */
+  int32_t iters_total; /* COCG iterations over all solves */
+  int32_t iters_max;   /* COCG iterations of the longest solve */
+  double rho;          /* spectral radius used for the AAA interval */
+  double aaa_err;      /* AAA's largest error on its sample points */
+  double solve_res;    /* largest relative residual at the end of a solve */
+} wl_rk_info;
+
+wl_status wl_aaa(int64_t N, const double* Z, const double* F, double tol, int32_t mmax, double* poles, int32_t cap,
+                 int32_t* npoles, double* max_err);
+wl_status wl_exp_poles(double xmax, double tol, int32_t mmax, double* poles, int32_t cap, int32_t* npoles,
+                       double* max_err);
+wl_status wl_return_prob(wl_op* op, const void* d_Omega, int32_t M, const double* t, int32_t nt, double t_max,
+                         double rho, double pole_time, double aaa_tol, double solve_tol, int32_t max_iters,
+                         double rcond, double* p_hat, double* e_hat, double* poles, int32_t poles_cap,
+                         wl_rk_info* info);
+
 /* ---------------------------------------------------------------- block Krylov primitives
  * The tall-skinny kernels every block Lanczos step is made of (Sec. 4.1: the basis
  * Q_k and its projection H_k), exposed for callers building their own drivers.

@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
     WL_M_RECURRENCE,
     WL_PROBE_GAUSS,
     WL_PROBE_RADEMACHER,
+    RkInfo,
     WLError,
     check,
     load,
@@ -56,6 +57,11 @@ def _dtype_of(prec):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dptr(a):
+    """Host pointer to a contiguous float64 numpy array."""
+    return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
 def _need(t, name, dtype, shape):
@@ -284,6 +290,27 @@ class Operator:
         check(load().wl_markov_gap(self.handle, int(outer_dim), int(seed), C.byref(l2), C.byref(lm), C.byref(gp)))
         return l2.value, lm.value, gp.value
 
+    def return_prob(self, Omega, ts, t_max, rho=0.0, pole_time=1.0, aaa_tol=1e-13, solve_tol=1e-6,
+                    max_iters=500, rcond=1e-10):
+        """Alg. 1: (p_hat, e_hat, poles, info) for the times ts, from the probe block
+        Omega (n x M): AAA poles of exp(-x) on [0, t_max rho] / pole_time, the block
+        rational Krylov basis, and the leave-one-out Nystrom estimate for every t."""
+        import numpy as np
+        Omega = self._block(Omega)
+        ts = np.ascontiguousarray(ts, dtype=np.float64)
+        nt = ts.size
+        p = np.empty(nt)
+        e = np.empty(nt)
+        cap = 256
+        pol = np.zeros(2 * cap)
+        info = RkInfo()
+        check(load().wl_return_prob(self.handle, _ptr(Omega), Omega.shape[1], _dptr(ts), nt, float(t_max), float(rho),
+                                    float(pole_time), float(aaa_tol), float(solve_tol), int(max_iters), float(rcond),
+                                    _dptr(p), _dptr(e), _dptr(pol), cap, C.byref(info)))
+        k = min(info.npoles, cap)
+        poles = pol[0:2 * k:2] + 1j * pol[1:2 * k:2]
+        return p, e, poles, {f: getattr(info, f) for f, _ in RkInfo._fields_}
+
     def diag_est(self, M, seed, target="phi", t=0.0, law="gauss", estimator="hutchinson", cv=None, outer_dim=30):
         out = self._empty(self.graph.n)
         if cv is not None:
@@ -363,6 +390,35 @@ def block_update(ctx, X, Cm, Yin=None, alpha=0.0, beta=1.0, out=None, nblk=1, wa
                                  Cm.ctypes.data_as(C.POINTER(C.c_double)), _ptr(Yin), float(alpha), float(beta),
                                  _ptr(out), G.ctypes.data_as(C.POINTER(C.c_double)) if want_gram else None))
     return (out, G) if want_gram else out
+
+
+def _poles_out(status, pol, npoles, cap):
+    check(status)
+    k = min(npoles.value, cap)
+    return pol[0:2 * k:2] + 1j * pol[1:2 * k:2]
+
+
+def aaa(Z, F, tol=1e-13, mmax=100):
+    """AAA on real samples F = f(Z) (host computation): (poles, max error on Z)."""
+    import numpy as np
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    cap = max(1, min(mmax, Z.size))
+    pol = np.zeros(2 * cap)
+    npoles, err = C.c_int32(), C.c_double()
+    st = load().wl_aaa(Z.size, _dptr(Z), _dptr(F), float(tol), int(mmax), _dptr(pol), cap, C.byref(npoles),
+                       C.byref(err))
+    return _poles_out(st, pol, npoles, cap), err.value
+
+
+def exp_poles(xmax, tol=1e-13, mmax=100):
+    """The AAA poles of exp(-x) on [0, xmax] that the rational Krylov estimate uses."""
+    import numpy as np
+    cap = mmax
+    pol = np.zeros(2 * cap)
+    npoles, err = C.c_int32(), C.c_double()
+    st = load().wl_exp_poles(float(xmax), float(tol), int(mmax), _dptr(pol), cap, C.byref(npoles), C.byref(err))
+    return _poles_out(st, pol, npoles, cap), err.value
 
 
 def probes(ctx, n, M, seed, law="gauss", dtype=None, stream=0):

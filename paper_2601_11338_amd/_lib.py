@@ -20,6 +20,19 @@ STATUS_NAMES = {
 }
 
 
+class RkInfo(C.Structure):
+    _fields_ = [
+        ("npoles", C.c_int32),
+        ("nblocks", C.c_int32),
+        ("solves", C.c_int32),
+        ("iters_total", C.c_int32),
+        ("iters_max", C.c_int32),
+        ("rho", C.c_double),
+        ("aaa_err", C.c_double),
+        ("solve_res", C.c_double),
+    ]
+
+
 class OpDesc(C.Structure):
     _fields_ = [
         ("mu", C.c_double),
@@ -67,6 +80,10 @@ SIGNATURES = {
     "wl_markov_step": (C.c_int, [vp, vp, i32, i32, vp]),
     "wl_markov_stationary": (C.c_int, [vp, vp]),
     "wl_markov_gap": (C.c_int, [vp, i32, C.c_uint64, pd, pd, pd]),
+    "wl_aaa": (C.c_int, [i64, pd, pd, f64, i32, pd, i32, C.POINTER(i32), pd]),
+    "wl_exp_poles": (C.c_int, [f64, f64, i32, pd, i32, C.POINTER(i32), pd]),
+    "wl_return_prob": (C.c_int, [vp, vp, i32, pd, i32, f64, f64, f64, f64, f64, i32, f64, pd, pd, pd, i32,
+                                 C.POINTER(RkInfo)]),
     "wl_probes": (C.c_int, [vp, i32, i32, u64, u32, i64, i32, vp]),
     "wl_block_gram": (C.c_int, [vp, i32, i64, i32, i32, vp, i32, vp, pd]),
     "wl_block_update": (C.c_int, [vp, i32, i64, i32, i32, vp, pd, vp, f64, f64, vp, pd]),

@@ -993,6 +993,49 @@ wl_status markov_gap_impl(wl_op* op, int outer_dim, uint64_t seed, double* lambd
 template wl_status markov_gap_impl<float>(wl_op*, int, uint64_t, double*, double*, double*);
 template wl_status markov_gap_impl<double>(wl_op*, int, uint64_t, double*, double*, double*);
 
+// Spectral radius of the walk Laplacian: `steps` fully reorthogonalised single-vector
+// Lanczos steps on L from a Gaussian vector (Philox stream `seed`); the largest Ritz
+// value plus its residual norm (the Ritz value converges from below).
+template <typename T>
+wl_status laplacian_rho_impl(wl_op* op, int steps, uint64_t seed, double* rho) {
+  wl_graph* g = op->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  WL_TRY(ensure_w<T>(op));
+  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(steps, n));
+  DevBuf basis, wb, x0, small;
+  WL_TRY(basis.ensure((size_t)(K + 1) * n * sizeof(T)));
+  WL_TRY(wb.ensure((size_t)n * sizeof(T)));
+  WL_TRY(x0.ensure((size_t)n * sizeof(T)));
+  WL_TRY(launch_probes<T>(ctx, WL_PROBE_GAUSS, seed, 0, n, 1, x0.as<T>()));
+  LanczosOp<T> L;
+  L.kind = 1;
+  L.inner = op;
+  std::vector<double> hA, hB, hR0;
+  int Ke = K;
+  WL_TRY(block_lanczos<T>(g, L, x0.as<T>(), 1, K, 2, basis.as<T>(), wb.as<T>(), small, hA, hB, hR0, &Ke));
+  // Ritz pair (theta, y) of the largest Ritz value; ||L V y - theta V y|| = |beta s_K|
+  // with s_K the last component of y, which bounds the distance from theta to the
+  // spectrum
+  std::vector<double> Tm((size_t)Ke * Ke, 0.0), lam(Ke), S((size_t)Ke * Ke);
+  for (int j = 0; j < Ke; ++j) {
+    Tm[(size_t)j * Ke + j] = hA[j];
+    if (j + 1 < Ke) Tm[(size_t)j * Ke + j + 1] = Tm[(size_t)(j + 1) * Ke + j] = hB[j];
+  }
+  if (dense_syev(Ke, Tm.data(), lam.data(), S.data())) {
+    wl_set_error("spectral radius of the walk Laplacian: eigendecomposition of the projected matrix failed");
+    return WL_ENOCONV;
+  }
+  int top = 0;
+  for (int i = 1; i < Ke; ++i)
+    if (lam[i] > lam[top]) top = i;
+  *rho = lam[top] + std::fabs(hB[(size_t)(Ke - 1)] * S[(size_t)(Ke - 1) * Ke + top]);
+  return WL_OK;
+}
+
+template wl_status laplacian_rho_impl<float>(wl_op*, int, uint64_t, double*);
+template wl_status laplacian_rho_impl<double>(wl_op*, int, uint64_t, double*);
+
 // ------------------------------------------------------------------ spectral scale
 // kind 0: A; kind 1: A_mu(t).  Runs `steps` single-vector Lanczos steps from 1 and
 // returns the extreme Ritz values.

@@ -149,6 +149,36 @@ wl_status estimate_impl(wl_ctx* ctx, int estimator, int64_t n, int M, const T* O
 
 }  // namespace
 
+int xnys_trace_host(int M, const std::vector<double>& H, const std::vector<double>& G, double rcond, double* trace,
+                    double* trace_err) {
+  // t_j = tr(Hp_j G) + H_jj - h_j^T Hp_j h_j, Hp_j the pseudo-inverse of the core
+  // without probe j, h_j = row j of H: the leave-one-out estimate written with the
+  // M x M Grams alone (F_(j) = Y_{-j} Hp_j Y_{-j}^T, never formed)
+  if (M < 2) return -1;
+  std::vector<double> P, tj(M);
+  for (int j = 0; j < M; ++j) {
+    if (pinv_drop(M, H, j, rcond, P)) return -1;
+    double trPG = 0.0, hPh = 0.0;
+    for (int a = 0; a < M; ++a) {
+      double ph = 0.0;
+      for (int c = 0; c < M; ++c) {
+        trPG += P[(size_t)a * M + c] * G[(size_t)c * M + a];
+        ph += P[(size_t)a * M + c] * H[(size_t)j * M + c];
+      }
+      hPh += H[(size_t)j * M + a] * ph;
+    }
+    tj[j] = trPG + H[(size_t)j * M + j] - hPh;
+  }
+  double mean = 0.0;
+  for (double v : tj) mean += v;
+  mean /= M;
+  double var = 0.0;
+  for (double v : tj) var += (v - mean) * (v - mean);
+  *trace = mean;
+  *trace_err = std::sqrt(var / (M - 1)) / std::sqrt((double)M);
+  return 0;
+}
+
 extern "C" {
 
 wl_status wl_estimate(wl_ctx* ctx, int32_t prec, int32_t estimator, int64_t n, int32_t M, const void* d_Omega,

@@ -287,6 +287,70 @@ wl_status multi_dispatch(wl_multi* m, const T* X, int b, T* Y, bool laplacian) {
 
 }  // namespace
 
+wl_status multi_groups_create(wl_op* op, int G, wl_multi** out) {
+  *out = nullptr;
+  WL_CHECK(op->d.method == WL_M_LANCZOS && G >= 1 && G <= 64, WL_EINVAL, "column groups: Lanczos operators only");
+  wl_graph* g = op->g;
+  auto* m = new wl_multi;
+  m->g = g;
+  m->nops = G;
+  m->prec = op->d.prec;
+  m->method = WL_M_LANCZOS;
+  m->K.assign(G, op->K);
+  m->desc.assign(G, op->d);
+  m->Kmax = std::max(op->K, 1);
+  std::vector<double> lt((size_t)G * 5, 0.0);
+  for (int i = 0; i < G; ++i) lanczos_params(op, &lt[i * 5], &lt[i * 5 + 1], &lt[i * 5 + 2]);
+  wl_status s = m->ltab.ensure(lt.size() * 8);
+  if (s == WL_OK && hipMemcpy(m->ltab.p, lt.data(), lt.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    wl_set_error("column groups: coefficient upload failed");
+    s = WL_EDEVICE;
+  }
+  // the operator's walk degrees in every group's column (for the Laplacian finish)
+  if (s == WL_OK && op->w_valid) {
+    const size_t es = m->prec == WL_FP32 ? 4 : 8;
+    s = m->W.ensure((size_t)std::max<int64_t>(g->n, 1) * G * es);
+    for (int q = 0; q < G && s == WL_OK; ++q)
+      s = m->prec == WL_FP32
+              ? launch_group_copy<float>(g->ctx, g->n, 1, G, q, op->w.as<float>(), m->W.as<float>(), true)
+              : launch_group_copy<double>(g->ctx, g->n, 1, G, q, op->w.as<double>(), m->W.as<double>(), true);
+    m->w_valid = s == WL_OK;
+  }
+  if (s != WL_OK) {
+    delete m;
+    return s;
+  }
+  ++g->refs;
+  *out = m;
+  return WL_OK;
+}
+
+void multi_groups_destroy(wl_multi* m) {
+  if (!m) return;
+  wl_graph* g = m->g;
+  (void)hipStreamSynchronize(g->ctx->stream);
+  delete m;
+  graph_release(g);
+}
+
+template <typename T>
+wl_status multi_groups_apply(wl_multi* m, const T* X, int b, T* Y, bool laplacian, bool* done) {
+  *done = false;
+  const int64_t n = m->g->n;
+  wl_op op;
+  group_op(m, 0, &op);
+  const int K = lanczos_steps(&op, n, b);
+  if (!grouped_supported(m->prec, b, m->nops) || (int64_t)(K + 1) * b * 2 > n || m->desc[0].reorth > 1 ||
+      (laplacian && !m->w_valid))
+    return WL_OK;
+  WL_TRY(multi_lanczos<T>(m, X, X, b, Y, laplacian ? m->W.as<T>() : nullptr));
+  *done = true;
+  return WL_OK;
+}
+
+template wl_status multi_groups_apply<float>(wl_multi*, const float*, int, float*, bool, bool*);
+template wl_status multi_groups_apply<double>(wl_multi*, const double*, int, double*, bool, bool*);
+
 extern "C" {
 
 wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out) {

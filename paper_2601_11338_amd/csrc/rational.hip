@@ -1,0 +1,633 @@
+// Rational Krylov estimate of the average return probability (Alg. 1, Sec. 4.4).
+//
+//   1. rho(L): Lanczos on the walk Laplacian (or the caller's value);
+//   2. poles: AAA on exp(-x) over [0, t* rho] (host), divided by pole_time;
+//   3. basis: block rational Krylov space of L and Omega (eq. block-rational-Krylov),
+//      built in real arithmetic: a real pole xi adds (L - xi)^{-1} U, a conjugate pair
+//      (xi, conj xi) adds Re and Im of (L - xi)^{-1} U (together they span what the two
+//      complex poles add), U the last basis block.  Every new block is orthogonalised
+//      twice against the basis and orthonormalised by CholQR2 with deflation;
+//   4. shifted solves: COCG (conjugate orthogonal CG for complex symmetric systems)
+//      column by column, the M complex columns held as one n x 2M real block
+//      [Re | Im] so that every iteration is one walk-Laplacian product on 2M columns;
+//   5. projection: T = V^T L V (the Rayleigh quotient; with exact solves it equals the
+//      reduced pencil Hhat Khat^{-1} of a pole sequence closed by infinity);
+//   6. per time t, on the host from T's eigendecomposition T = S diag(lam) S^T and
+//      Z = S^T E_1 R0 (Omega = V_0 R0): Omega^T Y(t) = Z^T e^{-t lam} Z / n and
+//      Y(t)^T Y(t) = Z^T e^{-2 t lam} Z / n^2 with Y(t) = V e^{-tT} V^T Omega / n; the
+//      leave-one-out Nystrom trace estimate needs only these two M x M matrices, so
+//      Y(t) itself is never formed.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "wl_internal.h"
+
+namespace {
+
+constexpr int RK_MAXM = 32;       // columns of Omega (2M <= 64, the block-width limit)
+constexpr int RK_THREADS = 256;   // 8 rows x 32 columns per pass
+constexpr int RK_BLOCKS = 1024;   // grid of the row reductions (partials per block)
+
+struct ColCoef {
+  double re[RK_MAXM];
+  double im[RK_MAXM];
+};
+
+// Sum of per-block partials (nblk x K, row-major) into out[K], one workgroup per value,
+// fixed summation order.
+__global__ void k_rk_finish(int nblk, int K, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double s[RK_THREADS];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += part[(size_t)b * K + k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = s[0];
+}
+
+// Reduce nv values per column over the 8 row slots of a workgroup into part[block].
+template <int NV>
+__device__ void block_colsum(double (&v)[NV], int M, double* __restrict__ part) {
+  __shared__ double s[NV][8][RK_MAXM];
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) s[q][ry][c] = v[q];
+  __syncthreads();
+  if (ry == 0 && c < M) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double a = 0.0;
+      for (int y = 0; y < 8; ++y) a += s[q][y][c];
+      part[(size_t)blockIdx.x * NV * M + q * M + c] = a;
+    }
+  }
+}
+
+// x = 0, r = p = [U | 0]; partial sums of ||u_c||^2
+template <typename T>
+__global__ void k_rk_init(int64_t n, int M, const T* __restrict__ U, T* __restrict__ X, T* __restrict__ R,
+                          T* __restrict__ P, double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[1] = {0.0};
+  if (c < M)
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const T u = U[r * M + c];
+      const int64_t o = r * 2 * M + c;
+      X[o] = T(0);
+      X[o + M] = T(0);
+      R[o] = u;
+      R[o + M] = T(0);
+      P[o] = u;
+      P[o + M] = T(0);
+      v[0] += (double)u * (double)u;
+    }
+  block_colsum<1>(v, M, part);
+}
+
+// Q <- Q - xi P (Q holds L P on entry); partials of p^T q (complex, unconjugated)
+template <typename T>
+__global__ void k_rk_shift_dot(int64_t n, int M, double a, double b, const T* __restrict__ P, T* __restrict__ Q,
+                               double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[2] = {0.0, 0.0};
+  if (c < M)
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const int64_t o = r * 2 * M + c;
+      const double pr = P[o], pi = P[o + M];
+      const double qr = (double)Q[o] - (a * pr - b * pi);
+      const double qi = (double)Q[o + M] - (a * pi + b * pr);
+      Q[o] = (T)qr;
+      Q[o + M] = (T)qi;
+      v[0] += pr * qr - pi * qi;
+      v[1] += pr * qi + pi * qr;
+    }
+  block_colsum<2>(v, M, part);
+}
+
+// x += alpha p, r -= alpha q (complex alpha per column); partials of r^T r (complex)
+// and ||r||^2
+template <typename T>
+__global__ void k_rk_xr(int64_t n, int M, ColCoef al, const T* __restrict__ P, const T* __restrict__ Q,
+                        T* __restrict__ X, T* __restrict__ R, double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (c < M) {
+    const double ar = al.re[c], ai = al.im[c];
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const int64_t o = r * 2 * M + c;
+      const double pr = P[o], pi = P[o + M], qr = Q[o], qi = Q[o + M];
+      X[o] = (T)((double)X[o] + ar * pr - ai * pi);
+      X[o + M] = (T)((double)X[o + M] + ar * pi + ai * pr);
+      const double rr = (double)R[o] - (ar * qr - ai * qi);
+      const double ri = (double)R[o + M] - (ar * qi + ai * qr);
+      R[o] = (T)rr;
+      R[o + M] = (T)ri;
+      v[0] += rr * rr - ri * ri;
+      v[1] += 2.0 * rr * ri;
+      v[2] += rr * rr + ri * ri;
+    }
+  }
+  block_colsum<3>(v, M, part);
+}
+
+// p = r + beta p (complex beta per column)
+template <typename T>
+__global__ void k_rk_dir(int64_t n, int M, ColCoef be, const T* __restrict__ R, T* __restrict__ P) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  if (c >= M) return;
+  const double br = be.re[c], bi = be.im[c];
+  for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+    const int64_t o = r * 2 * M + c;
+    const double pr = P[o], pi = P[o + M];
+    P[o] = (T)((double)R[o] + br * pr - bi * pi);
+    P[o + M] = (T)((double)R[o + M] + br * pi + bi * pr);
+  }
+}
+
+// out (n x M) = real (part 0) or imaginary (part 1) half of X (n x 2M)
+template <typename T>
+__global__ void k_rk_part(int64_t n, int M, const T* __restrict__ X, int part, T* __restrict__ out) {
+  const int64_t total = n * M;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / M;
+    const int c = (int)(e - r * M);
+    out[e] = X[r * 2 * M + part * M + c];
+  }
+}
+
+// dst (n x Mp) = src (n x M) followed by Mp - M zero columns
+template <typename T>
+__global__ void k_rk_pad(int64_t n, int M, int Mp, const T* __restrict__ src, T* __restrict__ dst) {
+  const int64_t total = n * Mp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / Mp;
+    const int c = (int)(e - r * Mp);
+    dst[e] = c < M ? src[r * M + c] : T(0);
+  }
+}
+
+int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RK_BLOCKS, (n + 7) / 8)); }
+
+// Cholesky of the M x M Gram G (row-major) with deflation: a pivot at or below
+// tol * ref drops its column (row of R and column of Rinv zero).  Rinv is the inverse
+// of R on the kept columns.
+void host_chol_deflate(int M, const std::vector<double>& G, double tol, double ref, std::vector<double>& R,
+                       std::vector<double>& Rinv, std::vector<char>& keep) {
+  R.assign((size_t)M * M, 0.0);
+  Rinv.assign((size_t)M * M, 0.0);
+  keep.assign(M, 0);
+  for (int k = 0; k < M; ++k) {
+    double d = G[(size_t)k * M + k];
+    for (int i = 0; i < k; ++i) d -= R[(size_t)i * M + k] * R[(size_t)i * M + k];
+    if (!(d > tol * ref)) continue;
+    keep[k] = 1;
+    const double rkk = std::sqrt(d);
+    R[(size_t)k * M + k] = rkk;
+    for (int j = k + 1; j < M; ++j) {
+      double s = G[(size_t)k * M + j];
+      for (int i = 0; i < k; ++i) s -= R[(size_t)i * M + k] * R[(size_t)i * M + j];
+      R[(size_t)k * M + j] = s / rkk;
+    }
+  }
+  // Rinv: solve R Rinv = I on the kept indices (upper triangular, back substitution)
+  for (int c = 0; c < M; ++c) {
+    if (!keep[c]) continue;
+    for (int i = c; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int j = i + 1; j <= c; ++j)
+        if (keep[j]) s -= R[(size_t)i * M + j] * Rinv[(size_t)j * M + c];
+      Rinv[(size_t)i * M + c] = s / R[(size_t)i * M + i];
+    }
+  }
+}
+
+template <typename T>
+struct RkWork {
+  wl_op* op;
+  wl_ctx* ctx;
+  int64_t n;
+  int M;
+  T* basis;          // nb_max blocks of n x M
+  int nb = 0;        // blocks in the basis
+  DevBuf dsmall;     // device doubles: Grams, coefficients
+  DevBuf part, sums;  // row-reduction partials and their sums
+  wl_multi* groups_wide = nullptr;  // the operator on 2M columns as 16-column groups
+  wl_multi* groups_narrow = nullptr;  // ... on M columns
+  ~RkWork() {
+    multi_groups_destroy(groups_wide);
+    multi_groups_destroy(groups_narrow);
+  }
+};
+
+// Y = L X on cols columns: the column-group runner when it covers the shape (16-column
+// groups of a Lanczos operator), else the operator's own product on the whole block.
+template <typename T>
+wl_status rk_apply(RkWork<T>& W, const T* X, int cols, T* Y) {
+  wl_multi* m = cols == 2 * W.M ? W.groups_wide : (cols == W.M ? W.groups_narrow : nullptr);
+  if (m) {
+    bool done = false;
+    WL_TRY(multi_groups_apply<T>(m, X, 16, Y, true, &done));
+    if (done) return WL_OK;
+  }
+  return phi_apply_impl<T>(W.op, X, Y, cols, W.op->w.template as<T>(), X);
+}
+
+template <typename T>
+wl_status rk_sums(RkWork<T>& W, int K, std::vector<double>& out) {
+  k_rk_finish<<<K, RK_THREADS, 0, W.ctx->stream>>>(grid_rows(W.n), K, W.part.template as<double>(),
+                                                   W.sums.template as<double>());
+  WL_HIP(hipGetLastError());
+  out.resize(K);
+  WL_HIP(hipMemcpyAsync(out.data(), W.sums.p, (size_t)K * 8, hipMemcpyDeviceToHost, W.ctx->stream));
+  WL_HIP(hipStreamSynchronize(W.ctx->stream));
+  return WL_OK;
+}
+
+// Host copy of the nb*bx x by Gram of the basis blocks [0, nblk) against Y.
+template <typename T>
+wl_status rk_gram(RkWork<T>& W, const T* X, int nblk, const T* Y, std::vector<double>& G) {
+  const int M = W.M;
+  WL_TRY(launch_gram<T>(W.ctx, W.n, X, M, W.n * M, nblk, Y, M, W.dsmall.template as<double>()));
+  G.resize((size_t)nblk * M * M);
+  WL_HIP(hipMemcpyAsync(G.data(), W.dsmall.p, G.size() * 8, hipMemcpyDeviceToHost, W.ctx->stream));
+  WL_HIP(hipStreamSynchronize(W.ctx->stream));
+  return WL_OK;
+}
+
+// Out = Yin - X C (X: nblk basis blocks, C host nblk*M x M), or Out = X_0 C when Yin null.
+template <typename T>
+wl_status rk_update(RkWork<T>& W, const T* X, int nblk, const std::vector<double>& C, const T* Yin, T* Out) {
+  const int M = W.M;
+  WL_HIP(hipMemcpyAsync(W.dsmall.p, C.data(), C.size() * 8, hipMemcpyHostToDevice, W.ctx->stream));
+  if (Yin)
+    WL_TRY(launch_update<T>(W.ctx, W.n, X, M, W.n * M, nblk, W.dsmall.template as<double>(), Yin, 1.0, nullptr,
+                            -1.0, Out, M, nullptr));
+  else
+    WL_TRY(launch_update<T>(W.ctx, W.n, X, M, W.n * M, nblk, W.dsmall.template as<double>(), nullptr, 0.0, nullptr,
+                            1.0, Out, M, nullptr));
+  WL_HIP(hipStreamSynchronize(W.ctx->stream));  // C (host) may go out of scope on return
+  return WL_OK;
+}
+
+// Orthonormalise block Wb (n x M) against the basis (two classical Gram-Schmidt passes)
+// and append it by CholQR2 with deflation; R (host, M x M) receives the factor of the
+// projected block (Wb_projected = V_new R).  Components whose true norm is below the
+// deflation level relative to Wb's scale before projection are dropped (zero columns).
+template <typename T>
+wl_status rk_append(RkWork<T>& W, T* Wb, std::vector<double>* Rout) {
+  const int M = W.M;
+  const int64_t blk = W.n * M;
+  std::vector<double> G, R1, R1i, R2, R2i;
+  std::vector<char> k1, k2;
+  WL_TRY(rk_gram<T>(W, Wb, 1, Wb, G));
+  double ref = 0.0;
+  for (int c = 0; c < M; ++c) ref = std::max(ref, G[(size_t)c * M + c]);
+  if (W.nb > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> C;
+      WL_TRY(rk_gram<T>(W, W.basis, W.nb, Wb, C));
+      WL_TRY(rk_update<T>(W, W.basis, W.nb, C, Wb, Wb));
+    }
+    WL_TRY(rk_gram<T>(W, Wb, 1, Wb, G));
+  }
+  T* slot = W.basis + (size_t)W.nb * blk;
+  const double tol = defl_tol<T>();
+  host_chol_deflate(M, G, tol, ref, R1, R1i, k1);
+  WL_TRY(rk_update<T>(W, Wb, 1, R1i, nullptr, slot));
+  WL_TRY(rk_gram<T>(W, slot, 1, slot, G));
+  host_chol_deflate(M, G, tol, 1.0, R2, R2i, k2);
+  // true norms of the new components: diag(R2 R1); drop the negligible ones
+  const double ptol = post_tol<T>();
+  for (int c = 0; c < M; ++c) {
+    const double d = std::fabs(R2[(size_t)c * M + c] * R1[(size_t)c * M + c]);
+    if (!(d > ptol * std::sqrt(ref)))
+      for (int i = 0; i < M; ++i) R2i[(size_t)i * M + c] = 0.0;
+  }
+  WL_TRY(rk_update<T>(W, slot, 1, R2i, nullptr, slot));
+  if (Rout) {
+    Rout->assign((size_t)M * M, 0.0);
+    for (int i = 0; i < M; ++i)
+      for (int j = 0; j < M; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < M; ++k) s += R2[(size_t)i * M + k] * R1[(size_t)k * M + j];
+        (*Rout)[(size_t)i * M + j] = s;
+      }
+  }
+  ++W.nb;
+  return WL_OK;
+}
+
+// COCG on (L - xi I) X = U, U real n x M, X complex as an n x 2M block [Re | Im].
+template <typename T>
+wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R, T* P, T* Q, double tol,
+                   int max_iters, int* iters, double* res_out) {
+  const int M = W.M;
+  const int64_t n = W.n;
+  wl_ctx* ctx = W.ctx;
+  const int grid = grid_rows(n);
+  using cd = std::complex<double>;
+  std::vector<double> s;
+  k_rk_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, X, R, P, W.part.template as<double>());
+  WL_HIP(hipGetLastError());
+  WL_TRY(rk_sums<T>(W, M, s));
+  std::vector<cd> rho(M);
+  std::vector<double> nrm0(M);
+  std::vector<char> active(M);
+  int nact = 0;
+  for (int c = 0; c < M; ++c) {
+    rho[c] = cd(s[c], 0.0);
+    nrm0[c] = std::sqrt(s[c]);
+    active[c] = nrm0[c] > 0.0;
+    nact += active[c];
+  }
+  double worst = 0.0, final_res = 0.0;  // largest residual of an open / a converged column
+  int it = 0;
+  for (; it < max_iters && nact > 0; ++it) {
+    WL_TRY(rk_apply<T>(W, P, 2 * M, Q));  // Q = L P
+    k_rk_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, xi.real(), xi.imag(), P, Q,
+                                                            W.part.template as<double>());
+    WL_HIP(hipGetLastError());
+    WL_TRY(rk_sums<T>(W, 2 * M, s));
+    ColCoef al{}, be{};
+    for (int c = 0; c < M; ++c) {
+      if (!active[c]) continue;
+      const cd pq(s[c], s[M + c]);
+      if (pq == cd(0.0)) {
+        wl_set_error("rational Krylov: COCG broke down (p^T (L - xi) p = 0)");
+        return WL_ENUMERIC;
+      }
+      const cd a = rho[c] / pq;
+      al.re[c] = a.real();
+      al.im[c] = a.imag();
+    }
+    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, W.part.template as<double>());
+    WL_HIP(hipGetLastError());
+    WL_TRY(rk_sums<T>(W, 3 * M, s));
+    worst = 0.0;
+    for (int c = 0; c < M; ++c) {
+      if (!active[c]) continue;
+      const double res = std::sqrt(s[2 * M + c]) / nrm0[c];
+      if (!std::isfinite(res)) {
+        wl_set_error("rational Krylov: non-finite residual in the shifted solve");
+        return WL_ENUMERIC;
+      }
+      const cd rn(s[c], s[M + c]);
+      if (res <= tol) {
+        active[c] = 0;
+        --nact;
+        final_res = std::max(final_res, res);
+        continue;
+      }
+      worst = std::max(worst, res);
+      const cd b = rn / rho[c];
+      be.re[c] = b.real();
+      be.im[c] = b.imag();
+      rho[c] = rn;
+    }
+    if (nact == 0) {
+      ++it;
+      break;
+    }
+    k_rk_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, R, P);
+    WL_HIP(hipGetLastError());
+  }
+  *iters = it;
+  *res_out = nact > 0 ? worst : final_res;
+  if (nact > 0) {
+    wl_set_error("rational Krylov: shifted solve did not reach %g in %d iterations (residual %g)", tol, max_iters,
+                 worst);
+    return WL_ENOCONV;
+  }
+  return WL_OK;
+}
+
+template <typename T>
+wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int nt, double t_max, double rho,
+                           double pole_time, double aaa_tol, double solve_tol, int max_iters, double rcond,
+                           double* p_hat, double* e_hat, double* poles_out, int poles_cap, wl_rk_info* info) {
+  wl_graph* g = op->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  using cd = std::complex<double>;
+  WL_TRY(ensure_w<T>(op));
+  if (!(rho > 0.0)) WL_TRY(laplacian_rho_impl<T>(op, 40, 0x5eed, &rho));
+  std::vector<cd> poles;
+  double aaa_err = 0.0;
+  if (exp_poles(t_max * rho, aaa_tol, 100, poles, &aaa_err)) {
+    wl_set_error("wl_return_prob: AAA failed");
+    return WL_ENOCONV;
+  }
+  for (auto& p : poles) p /= pole_time;
+  // real poles and one representative (Im > 0) per conjugate pair
+  const double itol = 1e-10;
+  std::vector<cd> reps;
+  int npos = 0, nneg = 0;
+  for (const cd& p : poles) {
+    if (std::fabs(p.imag()) <= itol * std::abs(p)) {
+      reps.push_back(cd(p.real(), 0.0));
+    } else if (p.imag() > 0) {
+      reps.push_back(p);
+      ++npos;
+    } else {
+      ++nneg;
+    }
+  }
+  if (npos != nneg) {
+    wl_set_error("wl_return_prob: AAA poles are not closed under conjugation");
+    return WL_ENUMERIC;
+  }
+  int nb_max = 1;
+  for (const cd& p : reps) nb_max += p.imag() == 0.0 ? 1 : 2;
+  // Lanczos operators in FP32: the blocks are padded to a multiple of 16 columns (zero
+  // columns, which deflate) so that every product runs as 16-column groups in lock
+  // step instead of one wide block Lanczos process (whose small-matrix work grows
+  // with the square of the width)
+  const bool grouped = op->d.prec == WL_FP32 && op->d.method == WL_M_LANCZOS;
+  const int Mp = grouped ? (M + 15) / 16 * 16 : M;
+  RkWork<T> W;
+  W.op = op;
+  W.ctx = ctx;
+  W.n = n;
+  W.M = Mp;
+  if (grouped) {
+    WL_TRY(multi_groups_create(op, 2 * Mp / 16, &W.groups_wide));
+    WL_TRY(multi_groups_create(op, Mp / 16, &W.groups_narrow));
+  }
+  DevBuf basis, wb, X, R, P, Q;
+  const size_t blk = (size_t)n * Mp;
+  WL_TRY(basis.ensure((size_t)nb_max * blk * sizeof(T)));
+  WL_TRY(wb.ensure(blk * sizeof(T)));
+  WL_TRY(X.ensure(2 * blk * sizeof(T)));
+  WL_TRY(R.ensure(2 * blk * sizeof(T)));
+  WL_TRY(P.ensure(2 * blk * sizeof(T)));
+  WL_TRY(Q.ensure(2 * blk * sizeof(T)));
+  WL_TRY(W.dsmall.ensure((size_t)nb_max * Mp * Mp * 8));
+  WL_TRY(W.part.ensure((size_t)RK_BLOCKS * 3 * Mp * 8));
+  WL_TRY(W.sums.ensure((size_t)3 * Mp * 8));
+  W.basis = basis.as<T>();
+  const int eg = (int)std::min<int64_t>(4096, (2 * (int64_t)blk + 255) / 256);
+  // V_0 R0 = Omega (padded)
+  std::vector<double> R0;
+  k_rk_pad<T><<<eg, 256, 0, ctx->stream>>>(n, M, Mp, Om, wb.as<T>());
+  WL_HIP(hipGetLastError());
+  WL_TRY(rk_append<T>(W, wb.as<T>(), &R0));
+  int iters_total = 0, iters_max = 0, solves = 0;
+  double worst = 0.0;
+  for (const cd& xi : reps) {
+    const T* U = W.basis + (size_t)(W.nb - 1) * blk;  // continuation: the last block
+    int its = 0;
+    double res = 0.0;
+    WL_TRY(rk_solve<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), solve_tol, max_iters, &its, &res));
+    ++solves;
+    iters_total += its;
+    iters_max = std::max(iters_max, its);
+    worst = std::max(worst, res);
+    k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, X.as<T>(), 0, wb.as<T>());
+    WL_HIP(hipGetLastError());
+    WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
+    if (xi.imag() != 0.0) {
+      k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, X.as<T>(), 1, wb.as<T>());
+      WL_HIP(hipGetLastError());
+      WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
+    }
+  }
+  // T = V^T L V, one column block per basis block
+  const int nb = W.nb, m = nb * Mp;
+  std::vector<double> Tm((size_t)m * m), col;
+  for (int j = 0; j < nb; ++j) {
+    const T* Vj = W.basis + (size_t)j * blk;
+    WL_TRY(rk_apply<T>(W, Vj, Mp, wb.as<T>()));
+    WL_TRY(rk_gram<T>(W, W.basis, nb, wb.as<T>(), col));
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < Mp; ++c) Tm[(size_t)r * m + j * Mp + c] = col[(size_t)r * Mp + c];
+  }
+  std::vector<double> lam(m), S((size_t)m * m);
+  if (dense_syev(m, Tm.data(), lam.data(), S.data())) {
+    wl_set_error("wl_return_prob: eigendecomposition of the projected matrix failed");
+    return WL_ENOCONV;
+  }
+  // Z = S^T E_1 R0 (m x M: the probe columns, not the padding)
+  std::vector<double> Z((size_t)m * M, 0.0);
+  for (int e = 0; e < m; ++e)
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+      for (int r = 0; r < Mp; ++r) s += S[(size_t)r * m + e] * R0[(size_t)r * Mp + c];
+      Z[(size_t)e * M + c] = s;
+    }
+  std::vector<double> H((size_t)M * M), G((size_t)M * M), e1(m), e2(m);
+  const double inv_n = 1.0 / (double)n;
+  for (int k = 0; k < nt; ++k) {
+    for (int e = 0; e < m; ++e) {
+      e1[e] = std::exp(-ts[k] * lam[e]) * inv_n;
+      e2[e] = e1[e] * e1[e];
+    }
+    for (int i = 0; i < M; ++i)
+      for (int c = i; c < M; ++c) {
+        double h = 0.0, gg = 0.0;
+        for (int e = 0; e < m; ++e) {
+          const double zz = Z[(size_t)e * M + i] * Z[(size_t)e * M + c];
+          h += zz * e1[e];
+          gg += zz * e2[e];
+        }
+        H[(size_t)i * M + c] = H[(size_t)c * M + i] = h;
+        G[(size_t)i * M + c] = G[(size_t)c * M + i] = gg;
+      }
+    double tr = 0.0, te = 0.0;
+    if (xnys_trace_host(M, H, G, rcond, &tr, &te)) {
+      wl_set_error("wl_return_prob: eigendecomposition of a Nystrom core failed");
+      return WL_ENOCONV;
+    }
+    if (p_hat) p_hat[k] = tr;
+    if (e_hat) e_hat[k] = te;
+  }
+  if (poles_out)
+    for (int i = 0; i < (int)poles.size() && i < poles_cap; ++i) {
+      poles_out[2 * i] = poles[i].real();
+      poles_out[2 * i + 1] = poles[i].imag();
+    }
+  if (info) {
+    info->npoles = (int32_t)poles.size();
+    info->nblocks = nb;
+    info->solves = solves;
+    info->iters_total = iters_total;
+    info->iters_max = iters_max;
+    info->rho = rho;
+    info->aaa_err = aaa_err;
+    info->solve_res = worst;
+  }
+  return WL_OK;
+}
+
+wl_status copy_poles(const std::vector<std::complex<double>>& poles, double* out, int32_t cap, int32_t* npoles) {
+  if (npoles) *npoles = (int32_t)poles.size();
+  if (out)
+    for (int i = 0; i < (int)poles.size() && i < cap; ++i) {
+      out[2 * i] = poles[i].real();
+      out[2 * i + 1] = poles[i].imag();
+    }
+  return WL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wl_status wl_aaa(int64_t N, const double* Z, const double* F, double tol, int32_t mmax, double* poles, int32_t cap,
+                 int32_t* npoles, double* max_err) {
+  WL_CHECK(N >= 2 && Z && F, WL_EINVAL, "wl_aaa: need N >= 2 points and values");
+  WL_CHECK(mmax >= 1 && mmax <= 500, WL_EINVAL, "wl_aaa: mmax must lie in [1, 500]");
+  WL_CHECK(tol >= 0.0, WL_EINVAL, "wl_aaa: tol must be >= 0");
+  WL_CHECK(cap >= 0 && (cap == 0 || poles), WL_EINVAL, "wl_aaa: bad pole buffer");
+  for (int64_t i = 0; i < N; ++i)
+    WL_CHECK(std::isfinite(Z[i]) && std::isfinite(F[i]), WL_EINVAL, "wl_aaa: non-finite sample");
+  std::vector<double> z, f, w;
+  WL_CHECK(aaa_real(N, Z, F, tol, mmax, z, f, w, max_err) == 0, WL_ENOCONV, "wl_aaa: failed");
+  std::vector<std::complex<double>> p;
+  aaa_poles(z, w, p);
+  return copy_poles(p, poles, cap, npoles);
+}
+
+wl_status wl_exp_poles(double xmax, double tol, int32_t mmax, double* poles, int32_t cap, int32_t* npoles,
+                       double* max_err) {
+  WL_CHECK(xmax > 0.0 && std::isfinite(xmax), WL_EINVAL, "wl_exp_poles: xmax must be positive");
+  WL_CHECK(mmax >= 1 && mmax <= 500, WL_EINVAL, "wl_exp_poles: mmax must lie in [1, 500]");
+  WL_CHECK(cap >= 0 && (cap == 0 || poles), WL_EINVAL, "wl_exp_poles: bad pole buffer");
+  std::vector<std::complex<double>> p;
+  WL_CHECK(exp_poles(xmax, tol, mmax, p, max_err) == 0, WL_ENOCONV, "wl_exp_poles: AAA failed");
+  return copy_poles(p, poles, cap, npoles);
+}
+
+wl_status wl_return_prob(wl_op* op, const void* d_Omega, int32_t M, const double* t, int32_t nt, double t_max,
+                         double rho, double pole_time, double aaa_tol, double solve_tol, int32_t max_iters,
+                         double rcond, double* p_hat, double* e_hat, double* poles, int32_t poles_cap,
+                         wl_rk_info* info) {
+  WL_CHECK(op, WL_EINVAL, "wl_return_prob: op is null");
+  WL_CHECK(M >= 2 && M <= RK_MAXM, WL_EINVAL, "wl_return_prob: M must lie in [2, %d]", RK_MAXM);
+  WL_CHECK(d_Omega, WL_EINVAL, "wl_return_prob: Omega is null");
+  WL_CHECK(nt >= 0 && (nt == 0 || t), WL_EINVAL, "wl_return_prob: bad time list");
+  for (int k = 0; k < nt; ++k)
+    WL_CHECK(std::isfinite(t[k]) && t[k] >= 0.0, WL_EINVAL, "wl_return_prob: times must be finite and >= 0");
+  WL_CHECK(t_max > 0.0 && std::isfinite(t_max), WL_EINVAL, "wl_return_prob: t_max must be positive");
+  WL_CHECK(pole_time > 0.0 && std::isfinite(pole_time), WL_EINVAL, "wl_return_prob: pole_time must be positive");
+  WL_CHECK(std::isfinite(rho), WL_EINVAL, "wl_return_prob: rho must be finite (<= 0: estimate it)");
+  WL_CHECK(aaa_tol > 0.0 && solve_tol > 0.0 && solve_tol < 1.0, WL_EINVAL, "wl_return_prob: bad tolerances");
+  WL_CHECK(max_iters >= 1, WL_EINVAL, "wl_return_prob: max_iters must be >= 1");
+  WL_CHECK(rcond >= 0.0 && rcond < 1.0, WL_EINVAL, "wl_return_prob: rcond must lie in [0, 1)");
+  WL_CHECK(poles_cap >= 0 && (poles_cap == 0 || poles), WL_EINVAL, "wl_return_prob: bad pole buffer");
+  WL_CHECK(op->g->n > M, WL_EINVAL, "wl_return_prob: needs n > M");
+  DeviceGuard dg(op->g->ctx->device);
+  if (op->d.prec == WL_FP32)
+    return return_prob_impl<float>(op, (const float*)d_Omega, M, t, nt, t_max, rho, pole_time, aaa_tol, solve_tol,
+                                   max_iters, rcond, p_hat, e_hat, poles, poles_cap, info);
+  return return_prob_impl<double>(op, (const double*)d_Omega, M, t, nt, t_max, rho, pole_time, aaa_tol, solve_tol,
+                                  max_iters, rcond, p_hat, e_hat, poles, poles_cap, info);
+}
+
+}  // extern "C"

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <complex>
 #include <vector>
 
 #include "walklap.h"
@@ -426,3 +427,33 @@ template <typename T>
 wl_status markov_gap_impl(wl_op* op, int outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
                           double* gap);
 wl_status lanczos_extreme(wl_graph* g, int kind, double mu, double t, int steps, double* lo, double* hi);
+template <typename T>
+wl_status laplacian_rho_impl(wl_op* op, int steps, uint64_t seed, double* rho);
+
+// One Lanczos operator on a wide block split into G column groups of b columns, each
+// group its own block Lanczos process, all in lock step through the grouped kernels
+// (one sparse product per step for all groups).  The handle keeps its basis between
+// calls.  Create after the operator's walk degrees are cached (the Laplacian finish
+// needs them).  multi_groups_apply sets *done = false and launches nothing when the
+// grouped kernels do not cover the shape (the caller then applies the operator itself).
+wl_status multi_groups_create(wl_op* op, int G, wl_multi** out);
+void multi_groups_destroy(wl_multi* m);
+template <typename T>
+wl_status multi_groups_apply(wl_multi* m, const T* X, int b, T* Y, bool laplacian, bool* done);
+
+// ------------------------------------------------------------------ rational approximation (host)
+// AAA on real samples F = f(Z) (N points): support points z, values f, weights w of the
+// barycentric approximant; max_err its largest error on Z.  0 on success.
+int aaa_real(int64_t N, const double* Z, const double* F, double tol, int mmax, std::vector<double>& z,
+             std::vector<double>& f, std::vector<double>& w, double* max_err);
+// Zeros of sum_j w_j / (x - z_j) (the poles of the approximant).
+int aaa_poles(const std::vector<double>& z, const std::vector<double>& w, std::vector<std::complex<double>>& poles);
+// The points exp(-x) is sampled on over [0, xmax], and the AAA poles of exp(-x) there
+// (real poles on the interval itself dropped).
+void exp_sample_points(double xmax, std::vector<double>& Z);
+int exp_poles(double xmax, double tol, int mmax, std::vector<std::complex<double>>& poles, double* max_err);
+// Leave-one-out Nystrom trace estimate from H = Omega^T Y and G = Y^T Y (M x M,
+// row-major): the mean over j of tr F_(j) + omega_j^T (F - F_(j)) omega_j and its
+// standard error.  0 on success.
+int xnys_trace_host(int M, const std::vector<double>& H, const std::vector<double>& G, double rcond, double* trace,
+                    double* trace_err);

@@ -11,6 +11,7 @@ from .graphs import (  # noqa: F401
     csr_from_edges,
     erdos_renyi_gnm,
     barabasi_albert,
+    road_grid,
     stochastic_block_model,
     configuration_model_powerlaw,
     rmat,

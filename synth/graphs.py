@@ -148,6 +148,19 @@ def barabasi_albert(n, m, seed):
     return csr_from_edges(n, ends[0::2], ends[1::2])
 
 
+def road_grid(nx, ny, p_keep, seed):
+    """Road-network stand-in: the nx x ny square lattice (node i * ny + j at row i,
+    column j) with every lattice edge kept independently with probability p_keep
+    (p_keep = 0.7 gives mean degree 2.8 and maximum degree 4, the planar, nearly
+    regular, locally numbered structure of a road map)."""
+    rng = np.random.default_rng(seed)
+    idx = np.arange(nx * ny, dtype=np.int64).reshape(nx, ny)
+    u = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+    v = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    keep = rng.random(u.size) < p_keep
+    return csr_from_edges(nx * ny, u[keep], v[keep])
+
+
 def stochastic_block_model(n, k, mean_degree, ratio, seed):
     """k equal blocks; p_in / p_out = ratio; expected mean degree ``mean_degree``."""
     rng = np.random.default_rng(seed)

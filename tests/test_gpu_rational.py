@@ -1,0 +1,165 @@
+"""Rational Krylov average return probability (Alg. 1) through the C ABI against the
+oracle.
+
+The library returns the poles it used; the oracle builds its (complex, exactly solved)
+block rational Arnoldi basis from the same poles, so both estimate from the same space
+and the same probes.  Differences come from the shifted solves (COCG to solve_tol), the
+projection (Rayleigh quotient V^T L V against the reduced pencil, equal with exact
+solves) and the vector precision.  Tolerances on p_hat, relative: FP64 1e-7 (solves to
+1e-12), FP32 2e-4 (basis orthogonal to ~1e-6, solves to 1e-6); on e_hat, absolute in
+units of p_hat: FP64 1e-6, FP32 2e-3.  At t = 0, Y(0) = Omega / n exactly, so p_hat(0)
+is the Nystrom estimate of the identity from Omega alone, to rounding at any size."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import estimators, genfun, laplacian, rational, walks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def ba(n, m, seed):
+    rp, ci = synth.barabasi_albert(n, m, seed)
+    return rp, ci, walks.adjacency(n, rp, ci)
+
+
+def compare(lib, op, Lap, Om, ts, t_max, dtype, rtol_p, atol_e, pole_time=1.0, solve_tol=1e-12):
+    n = Lap.shape[0]
+    rho = np.linalg.eigvalsh(Lap).max()
+    p, e, poles, info = op.return_prob(dev(Om, dtype), ts, t_max, rho=rho, pole_time=pole_time,
+                                       solve_tol=solve_tol, max_iters=2000)
+    assert info["npoles"] == poles.size and info["rho"] == rho
+    assert info["solve_res"] <= solve_tol
+    po, eo, _ = rational.return_probability_estimate(Lap, Om, ts, t_max, rho, poles=poles)
+    np.testing.assert_allclose(p, po, rtol=rtol_p, atol=0)
+    np.testing.assert_allclose(e, eo, rtol=0, atol=atol_e * np.abs(po).max())
+    tr0, te0, _, _ = estimators.xnys(Om, Om / n)
+    if ts[0] == 0.0:
+        assert abs(p[0] - tr0) < 1e-5 * abs(tr0) and abs(e[0] - te0) < 1e-5 * abs(tr0)
+    return p, e, poles, info
+
+
+@pytest.mark.parametrize("mu,pole_time", [(0.0, 1.0), (0.5, 1.0), (0.5, 10.0), (1.0, 1.0)])
+def test_fp64_exponential(ctx, lib, mu, pole_time):
+    print(f"[gpu] return_prob fp64 exp mu={mu} pole_time={pole_time}", flush=True)
+    n = 300
+    rp, ci, A = ba(n, 2, 17)
+    beta = 1.0 / np.linalg.eigvalsh(A)[-1]
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, mu, "exp", beta, dtype=torch.float64, tol=1e-15)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, mu, "exp", beta))
+    Om = synth.gaussian_block(n, 4, seed=3)
+    ts = [0.0, 0.1, 1.0, 5.0, 10.0]
+    p, e, poles, info = compare(lib, op, Lap, Om, ts, 10.0, torch.float64, 1e-7, 1e-6, pole_time=pole_time)
+    assert info["nblocks"] == 1 + poles.size
+
+
+def test_fp64_resolvent_lanczos(ctx, lib):
+    print("[gpu] return_prob fp64 res mu=1 lanczos", flush=True)
+    n = 300
+    rp, ci, A = ba(n, 3, 5)
+    alpha = 0.5 / walks.spectral_radius(walks.linearisation(A, 1.0))
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float64, krylov_dim=60, method="lanczos", tol=1e-14)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
+    Om = synth.gaussian_block(n, 5, seed=8)
+    compare(lib, op, Lap, Om, [0.0, 0.5, 2.0, 20.0], 20.0, torch.float64, 1e-7, 1e-6)
+
+
+def test_fp32_exponential_ba(ctx, lib):
+    print("[gpu] return_prob fp32 BA n=1500", flush=True)
+    n = 1500
+    rp, ci, A = ba(n, 3, 11)
+    beta = 1.0 / np.linalg.eigvalsh(A)[-1]
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.5, "exp", beta, dtype=torch.float32, tol=1e-9)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 0.5, "exp", beta))
+    Om = synth.gaussian_block(n, 8, seed=21)
+    compare(lib, op, Lap, Om, [0.0, 0.3, 3.0, 30.0], 30.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
+
+
+@pytest.mark.parametrize("M", [5, 20])
+def test_fp32_resolvent_column_groups(ctx, lib, M):
+    """FP32 Lanczos operators run every product as 16-column groups (the blocks padded
+    with zero columns): M = 5 pads to 16 (groups of 2 and 1), M = 20 to 32 (4 and 2)."""
+    print(f"[gpu] return_prob fp32 res mu=1 column groups M={M}", flush=True)
+    n = 2500
+    rp, ci, A = ba(n, 3, 23)
+    alpha = 0.5 / walks.spectral_radius(walks.linearisation(A, 1.0))
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float32, krylov_dim=30, method="lanczos", tol=1e-7)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
+    Om = synth.gaussian_block(n, M, seed=31)
+    compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
+
+
+def test_estimated_rho_and_components_limit(ctx, lib):
+    print("[gpu] return_prob components limit, estimated rho", flush=True)
+    blocks = []
+    for seed in (1, 2, 3):
+        rp, ci, A = ba(60, 2, seed)
+        blocks.append(A)
+    import scipy.linalg as sla
+    A = sla.block_diag(*blocks)
+    n = A.shape[0]
+    rp, ci = synth.csr_from_dense(A)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.0, "exp", 0.2, dtype=torch.float64, tol=1e-15)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 0.0, "exp", 0.2))
+    lam = np.sort(np.linalg.eigvalsh(Lap))
+    t_end = 200.0 / lam[3]
+    Om = synth.gaussian_block(n, 6, seed=4)
+    p, e, poles, info = op.return_prob(dev(Om, torch.float64), [0.0, t_end], t_end, rho=0.0, pole_time=t_end,
+                                       solve_tol=1e-12, max_iters=4000)
+    assert lam[-1] * (1 - 1e-9) <= info["rho"] <= 1.05 * lam[-1], (info["rho"], lam[-1])
+    assert abs(p[1] - 3.0 / n) < 1e-8 and e[1] < 1e-8
+
+
+def test_rank_deficient_probes(ctx, lib):
+    print("[gpu] return_prob rank-deficient probe block", flush=True)
+    n = 200
+    rp, ci, A = ba(n, 2, 9)
+    beta = 1.0 / np.linalg.eigvalsh(A)[-1]
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.0, "exp", beta, dtype=torch.float64, tol=1e-15)
+    Om = synth.gaussian_block(n, 4, seed=2)
+    Om[:, 3] = Om[:, 1]
+    p, e, poles, info = op.return_prob(dev(Om, torch.float64), [0.0, 1.0, 4.0], 4.0, solve_tol=1e-10)
+    assert np.all(np.isfinite(p)) and np.all(np.isfinite(e))
+    tr0, te0, _, _ = estimators.xnys(Om, Om / n)
+    assert abs(p[0] - tr0) < 1e-8 * abs(tr0)
+
+
+def test_bad_arguments(ctx, lib):
+    print("[gpu] return_prob bad arguments", flush=True)
+    n = 100
+    rp, ci, A = ba(n, 2, 1)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.0, "exp", 0.1, dtype=torch.float64, tol=1e-12)
+    Om = dev(synth.gaussian_block(n, 4, seed=1), torch.float64)
+    with pytest.raises(lib.WLError):
+        op.return_prob(dev(synth.gaussian_block(n, 1, seed=1), torch.float64), [1.0], 1.0)
+    with pytest.raises(lib.WLError):
+        op.return_prob(dev(synth.gaussian_block(n, 33, seed=1), torch.float64), [1.0], 1.0)
+    with pytest.raises(lib.WLError):
+        op.return_prob(Om, [-1.0], 1.0)
+    with pytest.raises(lib.WLError):
+        op.return_prob(Om, [1.0], 0.0)
+    with pytest.raises(lib.WLError):
+        op.return_prob(Om, [1.0], 1.0, pole_time=0.0)
+    with pytest.raises(lib.WLError):
+        op.return_prob(Om, [1.0], 1.0, solve_tol=0.0)
+    # an unreachable iteration budget is reported, not hidden
+    with pytest.raises(lib.WLError):
+        op.return_prob(Om, [1.0], 1.0, solve_tol=1e-14, max_iters=1)
