@@ -265,6 +265,7 @@ typedef struct {
   double rho;          /* spectral radius used for the AAA interval */
   double aaa_err;      /* AAA's largest error on its sample points */
   double solve_res;    /* largest relative residual at the end of a solve */
+  double products;     /* sparse products times the probe columns they acted on (work) */
 } wl_rk_info;
 
 wl_status wl_aaa(int64_t N, const double* Z, const double* F, double tol, int32_t mmax, double* poles, int32_t cap,

@@ -30,6 +30,7 @@ class RkInfo(C.Structure):
         ("rho", C.c_double),
         ("aaa_err", C.c_double),
         ("solve_res", C.c_double),
+        ("products", C.c_double),
     ]
 
 

@@ -9,7 +9,9 @@
 //      twice against the basis and orthonormalised by CholQR2 with deflation;
 //   4. shifted solves: COCG (conjugate orthogonal CG for complex symmetric systems)
 //      column by column, the M complex columns held as one n x 2M real block
-//      [Re | Im] so that every iteration is one walk-Laplacian product on 2M columns;
+//      [Re | Im]; for a resolvent operator on its symmetrised form, one sparse product
+//      with A_mu(alpha) per iteration (see k_fl_sqrt), otherwise one walk-Laplacian
+//      product on 2M columns per iteration;
 //   5. projection: T = V^T L V (the Rayleigh quotient; with exact solves it equals the
 //      reduced pencil Hhat Khat^{-1} of a pole sequence closed by infinity);
 //   6. per time t, on the host from T's eigendecomposition T = S diag(lam) S^T and
@@ -112,9 +114,12 @@ __global__ void k_rk_shift_dot(int64_t n, int M, double a, double b, const T* __
 
 // x += alpha p, r -= alpha q (complex alpha per column); partials of r^T r (complex)
 // and ||r||^2
+// With dre/dim given the third sum is ||d (.) r||^2 (the residual of the original system
+// when r is that of the symmetrised one).
 template <typename T>
 __global__ void k_rk_xr(int64_t n, int M, ColCoef al, const T* __restrict__ P, const T* __restrict__ Q,
-                        T* __restrict__ X, T* __restrict__ R, double* __restrict__ part) {
+                        T* __restrict__ X, T* __restrict__ R, const T* __restrict__ dre, const T* __restrict__ dim,
+                        double* __restrict__ part) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   double v[3] = {0.0, 0.0, 0.0};
   if (c < M) {
@@ -130,10 +135,91 @@ __global__ void k_rk_xr(int64_t n, int M, ColCoef al, const T* __restrict__ P, c
       R[o + M] = (T)ri;
       v[0] += rr * rr - ri * ri;
       v[1] += 2.0 * rr * ri;
-      v[2] += rr * rr + ri * ri;
+      const double w2 = dre ? (double)dre[r] * dre[r] + (double)dim[r] * dim[r] : 1.0;
+      v[2] += w2 * (rr * rr + ri * ri);
     }
   }
   block_colsum<3>(v, M, part);
+}
+
+// ---- the resolvent's shifted systems without inner solves.  With phi = s A^{-1}
+// (A = A_mu(alpha), s = 1 - mu^2 alpha^2) and D = diag(w) - xi I,
+//   (L - xi I) x = u  <=>  (D A - s I) y = u, x = A y  <=>  (d A d - s I) z = u / d, y = d z
+// for d = D^{1/2} elementwise: a complex symmetric system whose product is one sparse
+// product with A.  Its residual r_z relates to the original one by r_x = d (.) r_z.
+
+// d = sqrt(w - xi) (principal branch), as two real arrays
+template <typename T>
+__global__ void k_fl_sqrt(int64_t n, const T* __restrict__ w, double a, double b, T* __restrict__ dre,
+                          T* __restrict__ dim) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = (double)w[i] - a, y = -b;
+    const double r = sqrt(x * x + y * y);
+    const double re = sqrt(0.5 * (r + x));
+    const double im = (y >= 0 ? 1.0 : -1.0) * sqrt(fmax(0.0, 0.5 * (r - x)));
+    dre[i] = (T)re;
+    dim[i] = (T)im;
+  }
+}
+
+// z = 0, r = p = u / d; partials of r^T r (complex) and ||u||^2
+template <typename T>
+__global__ void k_fl_init(int64_t n, int M, const T* __restrict__ U, const T* __restrict__ dre,
+                          const T* __restrict__ dim, T* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
+                          double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (c < M)
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const double u = U[r * M + c];
+      const double dr = dre[r], di = dim[r], m2 = dr * dr + di * di;
+      const double rr = u * dr / m2, ri = -u * di / m2;
+      const int64_t o = r * 2 * M + c;
+      X[o] = T(0);
+      X[o + M] = T(0);
+      R[o] = (T)rr;
+      R[o + M] = (T)ri;
+      P[o] = (T)rr;
+      P[o + M] = (T)ri;
+      v[0] += rr * rr - ri * ri;
+      v[1] += 2.0 * rr * ri;
+      v[2] += u * u;
+    }
+  block_colsum<3>(v, M, part);
+}
+
+// V = d (.) P (every complex column of a row scaled by that row's d)
+template <typename T>
+__global__ void k_fl_scale(int64_t n, int M, const T* __restrict__ dre, const T* __restrict__ dim,
+                           const T* __restrict__ P, T* __restrict__ V) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  if (c >= M) return;
+  for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+    const int64_t o = r * 2 * M + c;
+    const double dr = dre[r], di = dim[r], pr = P[o], pi = P[o + M];
+    V[o] = (T)(dr * pr - di * pi);
+    V[o + M] = (T)(dr * pi + di * pr);
+  }
+}
+
+// Q <- d (.) Q - s P (Q holds A (d (.) P) on entry); partials of p^T q
+template <typename T>
+__global__ void k_fl_shift_dot(int64_t n, int M, const T* __restrict__ dre, const T* __restrict__ dim, double s,
+                               const T* __restrict__ P, T* __restrict__ Q, double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[2] = {0.0, 0.0};
+  if (c < M)
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const int64_t o = r * 2 * M + c;
+      const double dr = dre[r], di = dim[r], pr = P[o], pi = P[o + M], ar = Q[o], ai = Q[o + M];
+      const double qr = dr * ar - di * ai - s * pr;
+      const double qi = dr * ai + di * ar - s * pi;
+      Q[o] = (T)qr;
+      Q[o + M] = (T)qi;
+      v[0] += pr * qr - pi * qi;
+      v[1] += pr * qi + pi * qr;
+    }
+  block_colsum<2>(v, M, part);
 }
 
 // p = r + beta p (complex beta per column)
@@ -367,7 +453,8 @@ wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R
       al.re[c] = a.real();
       al.im[c] = a.imag();
     }
-    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, W.part.template as<double>());
+    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, nullptr, nullptr,
+                                                     W.part.template as<double>());
     WL_HIP(hipGetLastError());
     WL_TRY(rk_sums<T>(W, 3 * M, s));
     worst = 0.0;
@@ -408,6 +495,113 @@ wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R
   return WL_OK;
 }
 
+// COCG on the symmetrised system of a resolvent operator (see k_fl_sqrt): the same
+// solution x of (L - xi I) x = u as rk_solve, with one sparse product per iteration
+// instead of a Lanczos run.  Convergence is judged on the original residual d (.) r_z.
+// The solution lands in Q; V is scratch.
+template <typename T>
+wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R, T* P, T* Q, T* V, T* dre,
+                        T* dim, double tol, int max_iters, int* iters, double* res_out) {
+  const int M = W.M;
+  const int64_t n = W.n;
+  wl_ctx* ctx = W.ctx;
+  wl_graph* g = W.op->g;
+  const int grid = grid_rows(n);
+  using cd = std::complex<double>;
+  double a, b0, b1;
+  lanczos_params(W.op, &a, &b0, &b1);  // A_mu(alpha) = a A + b0 I + b1 D, and phi = b0 A_mu^{-1}
+  const double s = b0;
+  EpiArgs<T> ep;
+  ep.a = a;
+  ep.b0 = b0;
+  ep.b1 = b1;
+  ep.kclass = WL_KC_LANCZOS_OP;
+  const SpmmShape sh = shape_for(g, prec_of<T>(), 2 * M);
+  const int eg = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  k_fl_sqrt<T><<<eg, 256, 0, ctx->stream>>>(n, W.op->w.template as<T>(), xi.real(), xi.imag(), dre, dim);
+  WL_HIP(hipGetLastError());
+  std::vector<double> sm;
+  k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, P, W.part.template as<double>());
+  WL_HIP(hipGetLastError());
+  WL_TRY(rk_sums<T>(W, 3 * M, sm));
+  std::vector<cd> rho(M);
+  std::vector<double> nrm0(M);
+  std::vector<char> active(M);
+  int nact = 0;
+  for (int c = 0; c < M; ++c) {
+    rho[c] = cd(sm[c], sm[M + c]);
+    nrm0[c] = std::sqrt(sm[2 * M + c]);
+    active[c] = nrm0[c] > 0.0;
+    nact += active[c];
+  }
+  double worst = 0.0, final_res = 0.0;
+  int it = 0;
+  for (; it < max_iters && nact > 0; ++it) {
+    k_fl_scale<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, P, V);
+    WL_HIP(hipGetLastError());
+    ep.Z = V;
+    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu (d (.) P)
+    k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, P, Q, W.part.template as<double>());
+    WL_HIP(hipGetLastError());
+    WL_TRY(rk_sums<T>(W, 2 * M, sm));
+    ColCoef al{}, be{};
+    for (int c = 0; c < M; ++c) {
+      if (!active[c]) continue;
+      const cd pq(sm[c], sm[M + c]);
+      if (pq == cd(0.0)) {
+        wl_set_error("rational Krylov: COCG broke down (p^T K p = 0)");
+        return WL_ENUMERIC;
+      }
+      const cd al_c = rho[c] / pq;
+      al.re[c] = al_c.real();
+      al.im[c] = al_c.imag();
+    }
+    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, dre, dim, W.part.template as<double>());
+    WL_HIP(hipGetLastError());
+    WL_TRY(rk_sums<T>(W, 3 * M, sm));
+    worst = 0.0;
+    for (int c = 0; c < M; ++c) {
+      if (!active[c]) continue;
+      const double res = std::sqrt(sm[2 * M + c]) / nrm0[c];
+      if (!std::isfinite(res)) {
+        wl_set_error("rational Krylov: non-finite residual in the shifted solve");
+        return WL_ENUMERIC;
+      }
+      const cd rn(sm[c], sm[M + c]);
+      if (res <= tol) {
+        active[c] = 0;
+        --nact;
+        final_res = std::max(final_res, res);
+        continue;
+      }
+      worst = std::max(worst, res);
+      const cd bc = rn / rho[c];
+      be.re[c] = bc.real();
+      be.im[c] = bc.imag();
+      rho[c] = rn;
+    }
+    if (nact == 0) {
+      ++it;
+      break;
+    }
+    k_rk_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, R, P);
+    WL_HIP(hipGetLastError());
+  }
+  *iters = it;
+  *res_out = nact > 0 ? worst : final_res;
+  if (nact > 0) {
+    wl_set_error("rational Krylov: shifted solve did not reach %g in %d iterations (residual %g)", tol, max_iters,
+                 worst);
+    return WL_ENOCONV;
+  }
+  // x = A_mu (d (.) z)
+  k_fl_scale<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, X, V);
+  WL_HIP(hipGetLastError());
+  ep.Z = V;
+  WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));
+  return WL_OK;
+}
+
 template <typename T>
 wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int nt, double t_max, double rho,
                            double pole_time, double aaa_tol, double solve_tol, int max_iters, double rcond,
@@ -417,7 +611,13 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   const int64_t n = g->n;
   using cd = std::complex<double>;
   WL_TRY(ensure_w<T>(op));
-  if (!(rho > 0.0)) WL_TRY(laplacian_rho_impl<T>(op, 40, 0x5eed, &rho));
+  // work: sparse products times the probe columns they act on (a walk-Laplacian
+  // product on b columns is op->K products: Lanczos steps or series degree)
+  double products = 0.0;
+  if (!(rho > 0.0)) {
+    WL_TRY(laplacian_rho_impl<T>(op, 40, 0x5eed, &rho));
+    products += 40.0 * op->K;
+  }
   std::vector<cd> poles;
   double aaa_err = 0.0;
   if (exp_poles(t_max * rho, aaa_tol, 100, poles, &aaa_err)) {
@@ -460,7 +660,10 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     WL_TRY(multi_groups_create(op, 2 * Mp / 16, &W.groups_wide));
     WL_TRY(multi_groups_create(op, Mp / 16, &W.groups_narrow));
   }
-  DevBuf basis, wb, X, R, P, Q;
+  // resolvents: shifted solves on the symmetrised system (one sparse product per
+  // iteration); other operators: COCG with the walk-Laplacian product itself
+  const bool flat = op->d.func == WL_F_RESOLVENT;
+  DevBuf basis, wb, X, R, P, Q, V, dd;
   const size_t blk = (size_t)n * Mp;
   WL_TRY(basis.ensure((size_t)nb_max * blk * sizeof(T)));
   WL_TRY(wb.ensure(blk * sizeof(T)));
@@ -468,6 +671,10 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   WL_TRY(R.ensure(2 * blk * sizeof(T)));
   WL_TRY(P.ensure(2 * blk * sizeof(T)));
   WL_TRY(Q.ensure(2 * blk * sizeof(T)));
+  if (flat) {
+    WL_TRY(V.ensure(2 * blk * sizeof(T)));
+    WL_TRY(dd.ensure(2 * (size_t)n * sizeof(T)));
+  }
   WL_TRY(W.dsmall.ensure((size_t)nb_max * Mp * Mp * 8));
   WL_TRY(W.part.ensure((size_t)RK_BLOCKS * 3 * Mp * 8));
   WL_TRY(W.sums.ensure((size_t)3 * Mp * 8));
@@ -484,16 +691,22 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     const T* U = W.basis + (size_t)(W.nb - 1) * blk;  // continuation: the last block
     int its = 0;
     double res = 0.0;
-    WL_TRY(rk_solve<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), solve_tol, max_iters, &its, &res));
+    if (flat)
+      WL_TRY(rk_solve_flat<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), V.as<T>(), dd.as<T>(),
+                              dd.as<T>() + n, solve_tol, max_iters, &its, &res));
+    else
+      WL_TRY(rk_solve<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), solve_tol, max_iters, &its, &res));
+    const T* sol = flat ? Q.as<T>() : X.as<T>();
+    products += flat ? 2.0 * M * (its + 1) : 2.0 * M * its * op->K;
     ++solves;
     iters_total += its;
     iters_max = std::max(iters_max, its);
     worst = std::max(worst, res);
-    k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, X.as<T>(), 0, wb.as<T>());
+    k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, sol, 0, wb.as<T>());
     WL_HIP(hipGetLastError());
     WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
     if (xi.imag() != 0.0) {
-      k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, X.as<T>(), 1, wb.as<T>());
+      k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, sol, 1, wb.as<T>());
       WL_HIP(hipGetLastError());
       WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
     }
@@ -508,6 +721,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     for (int r = 0; r < m; ++r)
       for (int c = 0; c < Mp; ++c) Tm[(size_t)r * m + j * Mp + c] = col[(size_t)r * Mp + c];
   }
+  products += (double)nb * M * op->K;
   std::vector<double> lam(m), S((size_t)m * m);
   if (dense_syev(m, Tm.data(), lam.data(), S.data())) {
     wl_set_error("wl_return_prob: eigendecomposition of the projected matrix failed");
@@ -561,6 +775,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     info->rho = rho;
     info->aaa_err = aaa_err;
     info->solve_res = worst;
+    info->products = products;
   }
   return WL_OK;
 }

@@ -63,6 +63,10 @@ def test_fp64_exponential(ctx, lib, mu, pole_time):
     ts = [0.0, 0.1, 1.0, 5.0, 10.0]
     p, e, poles, info = compare(lib, op, Lap, Om, ts, 10.0, torch.float64, 1e-7, 1e-6, pole_time=pole_time)
     assert info["nblocks"] == 1 + poles.size
+    # work: every COCG iteration a walk-Laplacian product (K series steps) on 2M columns,
+    # plus the projection's products on the basis blocks
+    K, M = op.info()[0], Om.shape[1]
+    assert info["products"] == 2 * M * info["iters_total"] * K + info["nblocks"] * M * K
 
 
 def test_fp64_resolvent_lanczos(ctx, lib):
@@ -74,7 +78,11 @@ def test_fp64_resolvent_lanczos(ctx, lib):
     op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float64, krylov_dim=60, method="lanczos", tol=1e-14)
     Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
     Om = synth.gaussian_block(n, 5, seed=8)
-    compare(lib, op, Lap, Om, [0.0, 0.5, 2.0, 20.0], 20.0, torch.float64, 1e-7, 1e-6)
+    p, e, poles, info = compare(lib, op, Lap, Om, [0.0, 0.5, 2.0, 20.0], 20.0, torch.float64, 1e-7, 1e-6)
+    # the resolvent's shifted solves take one sparse product per COCG iteration (plus
+    # one for the solution); the projection K Lanczos steps per basis block
+    K, M = op.info()[0], Om.shape[1]
+    assert info["products"] == 2 * M * (info["iters_total"] + info["solves"]) + info["nblocks"] * M * K
 
 
 def test_fp32_exponential_ba(ctx, lib):
