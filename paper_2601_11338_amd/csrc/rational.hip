@@ -162,11 +162,11 @@ __global__ void k_fl_sqrt(int64_t n, const T* __restrict__ w, double a, double b
   }
 }
 
-// z = 0, r = p = u / d; partials of r^T r (complex) and ||u||^2
+// z = 0, r = p = u / d, V = d (.) p; partials of r^T r (complex) and ||u||^2
 template <typename T>
 __global__ void k_fl_init(int64_t n, int M, const T* __restrict__ U, const T* __restrict__ dre,
                           const T* __restrict__ dim, T* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
-                          double* __restrict__ part) {
+                          T* __restrict__ V, double* __restrict__ part) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   double v[3] = {0.0, 0.0, 0.0};
   if (c < M)
@@ -181,6 +181,8 @@ __global__ void k_fl_init(int64_t n, int M, const T* __restrict__ U, const T* __
       R[o + M] = (T)ri;
       P[o] = (T)rr;
       P[o + M] = (T)ri;
+      V[o] = (T)u;  // d (.) (u / d)
+      V[o + M] = T(0);
       v[0] += rr * rr - ri * ri;
       v[1] += 2.0 * rr * ri;
       v[2] += u * u;
@@ -199,6 +201,26 @@ __global__ void k_fl_scale(int64_t n, int M, const T* __restrict__ dre, const T*
     const double dr = dre[r], di = dim[r], pr = P[o], pi = P[o + M];
     V[o] = (T)(dr * pr - di * pi);
     V[o + M] = (T)(dr * pi + di * pr);
+  }
+}
+
+// p = r + beta p and V = d (.) p in one pass
+template <typename T>
+__global__ void k_fl_dir(int64_t n, int M, ColCoef be, const T* __restrict__ dre, const T* __restrict__ dim,
+                         const T* __restrict__ R, T* __restrict__ P, T* __restrict__ V) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  if (c >= M) return;
+  const double br = be.re[c], bi = be.im[c];
+  for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+    const int64_t o = r * 2 * M + c;
+    const double pr0 = P[o], pi0 = P[o + M];
+    const T pr = (T)((double)R[o] + br * pr0 - bi * pi0);
+    const T pi = (T)((double)R[o + M] + br * pi0 + bi * pr0);
+    P[o] = pr;
+    P[o + M] = pi;
+    const double dr = dre[r], di = dim[r];
+    V[o] = (T)(dr * (double)pr - di * (double)pi);
+    V[o + M] = (T)(dr * (double)pi + di * (double)pr);
   }
 }
 
@@ -521,7 +543,7 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   k_fl_sqrt<T><<<eg, 256, 0, ctx->stream>>>(n, W.op->w.template as<T>(), xi.real(), xi.imag(), dre, dim);
   WL_HIP(hipGetLastError());
   std::vector<double> sm;
-  k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, P, W.part.template as<double>());
+  k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, P, V, W.part.template as<double>());
   WL_HIP(hipGetLastError());
   WL_TRY(rk_sums<T>(W, 3 * M, sm));
   std::vector<cd> rho(M);
@@ -537,10 +559,8 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   double worst = 0.0, final_res = 0.0;
   int it = 0;
   for (; it < max_iters && nact > 0; ++it) {
-    k_fl_scale<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, P, V);
-    WL_HIP(hipGetLastError());
     ep.Z = V;
-    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu (d (.) P)
+    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) P
     k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, P, Q, W.part.template as<double>());
     WL_HIP(hipGetLastError());
     WL_TRY(rk_sums<T>(W, 2 * M, sm));
@@ -584,7 +604,7 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
       ++it;
       break;
     }
-    k_rk_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, R, P);
+    k_fl_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, dre, dim, R, P, V);
     WL_HIP(hipGetLastError());
   }
   *iters = it;
