@@ -13,9 +13,11 @@
 namespace {
 
 // Implicit QL on a symmetric tridiagonal matrix (diagonal d[0..m), off-diagonal
-// e[0..m-1) with e[i] = T[i][i+1]).  If Zt is given (m x m row-major, rows are the
-// current basis vectors), every plane rotation is applied to rows i, i+1 of Zt.
-int tql(int m, double* d, double* e_in, double* Zt) {
+// e[0..m-1) with e[i] = T[i][i+1]).  If Zt is given (m x cols row-major, rows are the
+// current basis vectors, or their first cols components), every plane rotation is
+// applied to rows i, i+1 of Zt.
+int tql(int m, double* d, double* e_in, double* Zt, int cols = -1) {
+  if (cols < 0) cols = m;
   std::vector<double> e(m, 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = e_in[i];
   // absolute floor for negligible couplings (exactly decoupled blocks with zero
@@ -59,9 +61,9 @@ int tql(int m, double* d, double* e_in, double* Zt) {
         d[i + 1] = g + p;
         g = c * r - bq;
         if (Zt) {
-          double* zi = Zt + (size_t)i * m;
-          double* zj = Zt + (size_t)(i + 1) * m;
-          for (int k = 0; k < m; ++k) {
+          double* zi = Zt + (size_t)i * cols;
+          double* zj = Zt + (size_t)(i + 1) * cols;
+          for (int k = 0; k < cols; ++k) {
             const double fz = zj[k];
             zj[k] = s * zi[k] + c * fz;
             zi[k] = c * zi[k] - s * fz;
@@ -87,9 +89,13 @@ int tridiag_eigvals(int m, const double* a, const double* b, double* lam) {
   return 0;
 }
 
-// A = U diag(lam) U^T; U row-major, column i is the eigenvector of lam[i].
-int dense_syev(int m, const double* A_in, double* lam, double* U) {
-  if (m <= 0) return 0;
+namespace {
+
+// Householder tridiagonalisation of the symmetric part of A (m x m row-major):
+// A = Q T Q^T with Q = H_0 H_1 ..., T = tridiag(e, d, e); vs[k] the unit reflector
+// of H_k acting on indices k+1.. (empty: identity).
+void householder_tridiag(int m, const double* A_in, std::vector<double>& d, std::vector<double>& e,
+                         std::vector<std::vector<double>>& vs) {
   std::vector<double> A(A_in, A_in + (size_t)m * m);
   // symmetrise
   for (int i = 0; i < m; ++i)
@@ -98,8 +104,10 @@ int dense_syev(int m, const double* A_in, double* lam, double* U) {
       A[(size_t)i * m + j] = A[(size_t)j * m + i] = v;
     }
   // Householder reduction: for column k, reflect x = A[k+1:, k] onto alpha e_1.
-  std::vector<std::vector<double>> vs;
-  std::vector<double> d(m), e(m, 0.0), p(m), q(m);
+  vs.clear();
+  d.assign(m, 0.0);
+  e.assign(m, 0.0);
+  std::vector<double> p(m), q(m);
   for (int k = 0; k + 2 < m; ++k) {
     const int len = m - k - 1;
     std::vector<double> v(len);
@@ -146,6 +154,16 @@ int dense_syev(int m, const double* A_in, double* lam, double* U) {
   }
   for (int i = 0; i < m; ++i) d[i] = A[(size_t)i * m + i];
   for (int i = 0; i + 1 < m; ++i) e[i] = A[(size_t)i * m + i + 1];
+}
+
+}  // namespace
+
+// A = U diag(lam) U^T; U row-major, column i is the eigenvector of lam[i].
+int dense_syev(int m, const double* A_in, double* lam, double* U) {
+  if (m <= 0) return 0;
+  std::vector<double> d, e;
+  std::vector<std::vector<double>> vs;
+  householder_tridiag(m, A_in, d, e, vs);
   // Zt = Q^T with Q = H_0 H_1 ... ; rows of Zt are columns of Q.
   // Build Q by applying the reflectors in reverse to the identity, stored transposed.
   std::vector<double> Zt((size_t)m * m, 0.0);
@@ -172,6 +190,44 @@ int dense_syev(int m, const double* A_in, double* lam, double* U) {
     const int s = idx[c];
     lam[c] = d[s];
     for (int r = 0; r < m; ++r) U[(size_t)r * m + c] = Zt[(size_t)s * m + r];
+  }
+  return 0;
+}
+
+// Eigenvalues (ascending) and the first kr rows of the eigenvector matrix:
+// Ur (kr x m row-major), Ur[r][c] = component r of the eigenvector of lam[c].  The
+// rows of Q needed are e_r^T H_0 H_1 ..., and the QL rotations act on kr components
+// only: O(m^3) for the reduction, O(kr m^2) for the vectors.
+int dense_syev_rows(int m, const double* A_in, int kr, double* lam, double* Ur) {
+  if (m <= 0) return 0;
+  kr = std::min(kr, m);
+  std::vector<double> d, e;
+  std::vector<std::vector<double>> vs;
+  householder_tridiag(m, A_in, d, e, vs);
+  // Zt (m x kr): Zt[j][r] = Q[r][j]
+  std::vector<double> Zt((size_t)m * kr, 0.0), x(m);
+  for (int r = 0; r < kr; ++r) {
+    std::fill(x.begin(), x.end(), 0.0);
+    x[r] = 1.0;
+    for (size_t k = 0; k < vs.size(); ++k) {
+      const auto& v = vs[k];
+      if (v.empty()) continue;
+      const int off = (int)k + 1, len = m - off;
+      double s = 0.0;
+      for (int i = 0; i < len; ++i) s += x[off + i] * v[i];
+      s *= 2.0;
+      for (int i = 0; i < len; ++i) x[off + i] -= s * v[i];
+    }
+    for (int j = 0; j < m; ++j) Zt[(size_t)j * kr + r] = x[j];
+  }
+  if (tql(m, d.data(), e.data(), Zt.data(), kr)) return 1;
+  std::vector<int> idx(m);
+  for (int i = 0; i < m; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  for (int c = 0; c < m; ++c) {
+    const int s = idx[c];
+    lam[c] = d[s];
+    for (int r = 0; r < kr; ++r) Ur[(size_t)r * m + c] = Zt[(size_t)s * kr + r];
   }
   return 0;
 }

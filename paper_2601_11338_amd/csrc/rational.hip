@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <thread>
 #include <vector>
 
 #include "wl_internal.h"
@@ -742,45 +743,60 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
       for (int c = 0; c < Mp; ++c) Tm[(size_t)r * m + j * Mp + c] = col[(size_t)r * Mp + c];
   }
   products += (double)nb * M * op->K;
-  std::vector<double> lam(m), S((size_t)m * m);
-  if (dense_syev(m, Tm.data(), lam.data(), S.data())) {
+  // only the first Mp components of the eigenvectors enter: Z = S^T E_1 R0
+  std::vector<double> lam(m), S1((size_t)Mp * m);
+  if (dense_syev_rows(m, Tm.data(), Mp, lam.data(), S1.data())) {
     wl_set_error("wl_return_prob: eigendecomposition of the projected matrix failed");
     return WL_ENOCONV;
   }
-  // Z = S^T E_1 R0 (m x M: the probe columns, not the padding)
+  // Z (m x M: the probe columns, not the padding)
   std::vector<double> Z((size_t)m * M, 0.0);
   for (int e = 0; e < m; ++e)
     for (int c = 0; c < M; ++c) {
       double s = 0.0;
-      for (int r = 0; r < Mp; ++r) s += S[(size_t)r * m + e] * R0[(size_t)r * Mp + c];
+      for (int r = 0; r < Mp; ++r) s += S1[(size_t)r * m + e] * R0[(size_t)r * Mp + c];
       Z[(size_t)e * M + c] = s;
     }
-  std::vector<double> H((size_t)M * M), G((size_t)M * M), e1(m), e2(m);
+  // the times are independent (Alg. 1 runs them as a parallel loop): host threads
   const double inv_n = 1.0 / (double)n;
-  for (int k = 0; k < nt; ++k) {
-    for (int e = 0; e < m; ++e) {
-      e1[e] = std::exp(-ts[k] * lam[e]) * inv_n;
-      e2[e] = e1[e] * e1[e];
-    }
-    for (int i = 0; i < M; ++i)
-      for (int c = i; c < M; ++c) {
-        double h = 0.0, gg = 0.0;
-        for (int e = 0; e < m; ++e) {
-          const double zz = Z[(size_t)e * M + i] * Z[(size_t)e * M + c];
-          h += zz * e1[e];
-          gg += zz * e2[e];
-        }
-        H[(size_t)i * M + c] = H[(size_t)c * M + i] = h;
-        G[(size_t)i * M + c] = G[(size_t)c * M + i] = gg;
+  const int nth = std::max(1, std::min({nt, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));
+  std::vector<char> failed(nth, 0);
+  auto estimate_times = [&](int tid) {
+    std::vector<double> H((size_t)M * M), G((size_t)M * M), e1(m), e2(m);
+    for (int k = tid; k < nt; k += nth) {
+      for (int e = 0; e < m; ++e) {
+        e1[e] = std::exp(-ts[k] * lam[e]) * inv_n;
+        e2[e] = e1[e] * e1[e];
       }
-    double tr = 0.0, te = 0.0;
-    if (xnys_trace_host(M, H, G, rcond, &tr, &te)) {
+      for (int i = 0; i < M; ++i)
+        for (int c = i; c < M; ++c) {
+          double h = 0.0, gg = 0.0;
+          for (int e = 0; e < m; ++e) {
+            const double zz = Z[(size_t)e * M + i] * Z[(size_t)e * M + c];
+            h += zz * e1[e];
+            gg += zz * e2[e];
+          }
+          H[(size_t)i * M + c] = H[(size_t)c * M + i] = h;
+          G[(size_t)i * M + c] = G[(size_t)c * M + i] = gg;
+        }
+      double tr = 0.0, te = 0.0;
+      if (xnys_trace_host(M, H, G, rcond, &tr, &te)) {
+        failed[tid] = 1;
+        return;
+      }
+      if (p_hat) p_hat[k] = tr;
+      if (e_hat) e_hat[k] = te;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int tid = 1; tid < nth; ++tid) pool.emplace_back(estimate_times, tid);
+  estimate_times(0);
+  for (auto& th : pool) th.join();
+  for (char f : failed)
+    if (f) {
       wl_set_error("wl_return_prob: eigendecomposition of a Nystrom core failed");
       return WL_ENOCONV;
     }
-    if (p_hat) p_hat[k] = tr;
-    if (e_hat) e_hat[k] = te;
-  }
   if (poles_out)
     for (int i = 0; i < (int)poles.size() && i < poles_cap; ++i) {
       poles_out[2 * i] = poles[i].real();

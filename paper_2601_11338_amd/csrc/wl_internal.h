@@ -315,6 +315,8 @@ wl_status launch_cv_finish(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* 
 // Symmetric eigendecomposition A = U diag(lam) U^T of an m x m row-major matrix
 // (Householder tridiagonalisation + implicit QL).  U row-major, column i = eigvec i.
 int dense_syev(int m, const double* A, double* lam, double* U);
+// The same with only the first kr rows of U (kr x m row-major).
+int dense_syev_rows(int m, const double* A, int kr, double* lam, double* Ur);
 // Eigenvalues only of a symmetric tridiagonal matrix (diag a, offdiag b).
 int tridiag_eigvals(int m, const double* a, const double* b, double* lam);
 // Solve T X = B for block tridiagonal SPD T (K diagonal blocks Ad, K-1 off-diagonal
