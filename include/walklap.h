@@ -64,7 +64,11 @@ typedef enum { WL_FP32 = 4, WL_FP64 = 8 } wl_prec;
 typedef enum {
   WL_M_AUTO = 0,        /* exponential: recurrence; resolvent: block Lanczos on A_mu */
   WL_M_RECURRENCE = 1,  /* truncated series by the fused three-term recurrence (exponential) */
-  WL_M_LANCZOS = 2      /* block Lanczos (mu = 0: on A; resolvent: on A_mu(alpha)) */
+  WL_M_LANCZOS = 2,     /* block Lanczos (mu = 0: on A; resolvent: on A_mu(alpha)) */
+  WL_M_ARNOLDI = 3      /* exponential, any mu: block Arnoldi on the 2n x 2n linearisation Z
+                           (eq. Zdef), phi X = X + [I O] beta phi_1(beta Z) [q_1 X; q_2 X]
+                           (Prop. "whe-we-converge"); krylov_dim Arnoldi steps (required).
+                           For beta rho(Z) large, where the series degree grows with it. */
 } wl_method;
 typedef enum { WL_PROBE_GAUSS = 0, WL_PROBE_RADEMACHER = 1 } wl_probe_law;
 typedef enum {
@@ -182,7 +186,7 @@ wl_status wl_spectral_radius(wl_graph* g, double mu, double tol, double* rho);
 wl_status wl_op_create(wl_graph* g, const wl_op_desc* desc, wl_op** out);
 wl_status wl_op_destroy(wl_op* op);
 /* The truncation degree (recurrence) or number of block Lanczos steps the operator
- * settled on, and its method (WL_M_RECURRENCE or WL_M_LANCZOS).  Either output may
+ * settled on, and its method (WL_M_RECURRENCE, WL_M_LANCZOS or WL_M_ARNOLDI).  Either output may
  * be NULL.                                                                        */
 wl_status wl_op_info(const wl_op* op, int32_t* degree_or_steps, int32_t* method);
 

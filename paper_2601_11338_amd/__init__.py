@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     WL_F_RESOLVENT,
     WL_FP32,
     WL_FP64,
+    WL_M_ARNOLDI,
     WL_M_AUTO,
     WL_M_LANCZOS,
     WL_M_RECURRENCE,
@@ -30,7 +31,7 @@ from ._lib import (  # noqa: F401
 )
 
 FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP}
-METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS}
+METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS, "arnoldi": WL_M_ARNOLDI}
 ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS,
               "surrogate": WL_EST_SURROGATE}
 LAWS = {"gauss": WL_PROBE_GAUSS, "gaussian": WL_PROBE_GAUSS, "rademacher": WL_PROBE_RADEMACHER}

@@ -680,18 +680,24 @@ template <typename T>
 wl_status phi_recurrence(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
   wl_graph* g = op->g;
   const int64_t n = g->n;
-  const double mu = op->d.mu, s = op->d.param;
+  const double mu = op->d.mu;
+  // P_k = s^k q_k X and weights omega_k = c_k / s^k.  Resolvent: s = alpha (alpha
+  // rho(Z) < 1 keeps both bounded).  Exponential: s = min(beta, 1 / lambda_max) keeps
+  // P_k bounded (q_k <= A^k entrywise) and omega_k = (beta / s)^k / k! <= e^{beta / s};
+  // with s = beta the P_k would grow like (beta lambda_max)^k and leave the FP32 range.
+  const bool ex = op->d.func == WL_F_EXP;
+  const double s = ex && op->lam > 0.0 ? std::min(op->d.param, 1.0 / op->lam) : op->d.param;
+  const double ratio = ex ? op->d.param / s : 1.0;
   const int K = op->K;
   WL_TRY(op->bufA.ensure((size_t)n * b * sizeof(T)));
   WL_TRY(op->bufB.ensure((size_t)n * b * sizeof(T)));
   T* A = op->bufA.as<T>();
   T* B = op->bufB.as<T>();
   const SpmmShape sh = shape_for(g, prec_of<T>(), b);
-  // weights omega_k = c_k / s^k
   auto omega = [&](int k) {
-    if (op->d.func == WL_F_RESOLVENT) return 1.0;
+    if (!ex) return 1.0;
     double f = 1.0;
-    for (int i = 2; i <= k; ++i) f /= i;
+    for (int i = 1; i <= k; ++i) f *= ratio / i;
     return f;
   };
   if (K == 0) {
@@ -849,6 +855,7 @@ template <typename T>
 wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw) {
   if (op->g->n == 0) return WL_OK;
   if (op->d.method == WL_M_LANCZOS) return phi_lanczos<T>(op, X, Y, b, wv, Xw);
+  if (op->d.method == WL_M_ARNOLDI) return phi_arnoldi<T>(op, X, Y, b, wv, Xw);
   return phi_recurrence<T>(op, X, Y, b, wv, Xw);
 }
 
@@ -1173,7 +1180,11 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   WL_CHECK(d->prec == WL_FP32 || d->prec == WL_FP64, WL_EINVAL, "wl_op_create: prec must be WL_FP32 or WL_FP64");
   WL_CHECK(d->krylov_dim >= 0 && d->krylov_dim <= 2000, WL_EINVAL, "wl_op_create: krylov_dim out of range");
   WL_CHECK(is_finite(d->tol) && d->tol >= 0.0, WL_EINVAL, "wl_op_create: bad tol");
-  WL_CHECK(d->method >= WL_M_AUTO && d->method <= WL_M_LANCZOS, WL_EINVAL, "wl_op_create: unknown method");
+  WL_CHECK(d->method >= WL_M_AUTO && d->method <= WL_M_ARNOLDI, WL_EINVAL, "wl_op_create: unknown method");
+  WL_CHECK(d->method != WL_M_ARNOLDI || d->func == WL_F_EXP, WL_EUNSUPPORTED,
+           "wl_op_create: the Arnoldi method evaluates exponential weights only");
+  WL_CHECK(d->method != WL_M_ARNOLDI || d->krylov_dim > 0, WL_EINVAL,
+           "wl_op_create: the Arnoldi method needs an explicit krylov_dim");
   WL_CHECK(d->reorth >= 0 && d->reorth <= 2, WL_EINVAL, "wl_op_create: reorth must be 0, 1 or 2");
   int method = d->method;
   if (method == WL_M_AUTO) method = d->func == WL_F_EXP ? WL_M_RECURRENCE : WL_M_LANCZOS;
@@ -1192,12 +1203,13 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
     WL_CHECK(d->param * rho < 1.0, WL_ERANGE,
              "wl_op_create: alpha * rho(Z_mu) = %.6g >= 1: the series does not converge", d->param * rho);
   }
+  double lam_exp = 0.0;  // lambda_max(A) for exponential weights (series scaling, degree)
+  if (d->func == WL_F_EXP) WL_TRY(wl_lambda_max(g, 1e-10, &lam_exp));
   int K = d->krylov_dim;
   if (K == 0) {
     const double tol = d->tol > 0 ? d->tol : 1e-12;
     if (d->func == WL_F_EXP) {
-      double lam;
-      WL_TRY(wl_lambda_max(g, 1e-10, &lam));
+      const double lam = lam_exp;
       // smallest K with sum_{k>K} (beta lam)^k / k! <= tol * e^{beta lam}
       const double x = d->param * lam;
       double term = 1.0, tail = std::exp(x) - 1.0;
@@ -1225,6 +1237,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   op->d = *d;
   op->d.method = method;
   op->rho = rho;
+  op->lam = lam_exp;
   op->K = K;
   *out = op;
   return WL_OK;

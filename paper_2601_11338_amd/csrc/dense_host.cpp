@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "wl_internal.h"
@@ -328,5 +329,160 @@ int block_tridiag_solve(int K, int b, const double* Ad, const double* Bo, const 
     }
     ltsolve(b, &L[(size_t)j * bb], xj, nrhs);
   }
+  return 0;
+}
+
+// ------------------------------------------------------------------ deflating Cholesky
+void host_chol_deflate(int M, const std::vector<double>& G, double tol, double ref, std::vector<double>& R,
+                       std::vector<double>& Rinv, std::vector<char>& keep) {
+  R.assign((size_t)M * M, 0.0);
+  Rinv.assign((size_t)M * M, 0.0);
+  keep.assign(M, 0);
+  for (int k = 0; k < M; ++k) {
+    double d = G[(size_t)k * M + k];
+    for (int i = 0; i < k; ++i) d -= R[(size_t)i * M + k] * R[(size_t)i * M + k];
+    if (!(d > tol * ref)) continue;
+    keep[k] = 1;
+    const double rkk = std::sqrt(d);
+    R[(size_t)k * M + k] = rkk;
+    for (int j = k + 1; j < M; ++j) {
+      double s = G[(size_t)k * M + j];
+      for (int i = 0; i < k; ++i) s -= R[(size_t)i * M + k] * R[(size_t)i * M + j];
+      R[(size_t)k * M + j] = s / rkk;
+    }
+  }
+  // Rinv: R Rinv = I on the kept indices (upper triangular, back substitution)
+  for (int c = 0; c < M; ++c) {
+    if (!keep[c]) continue;
+    for (int i = c; i >= 0; --i) {
+      if (!keep[i]) continue;
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int j = i + 1; j <= c; ++j)
+        if (keep[j]) s -= R[(size_t)i * M + j] * Rinv[(size_t)j * M + c];
+      Rinv[(size_t)i * M + c] = s / R[(size_t)i * M + i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ phi_1 of a general matrix
+namespace {
+
+// C = A B for m x m row-major matrices, rows split over host threads
+void matmul(int m, const double* A, const double* B, double* C) {
+  const int nth = std::max(1, std::min({16, (m + 31) / 32, (int)std::max(1u, std::thread::hardware_concurrency())}));
+  auto rows = [&](int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+      double* c = C + (size_t)i * m;
+      std::fill(c, c + m, 0.0);
+      for (int k = 0; k < m; ++k) {
+        const double a = A[(size_t)i * m + k];
+        if (a == 0.0) continue;
+        const double* b = B + (size_t)k * m;
+        for (int j = 0; j < m; ++j) c[j] += a * b[j];
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  const int per = (m + nth - 1) / nth;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(rows, std::min(m, t * per), std::min(m, (t + 1) * per));
+  rows(0, std::min(m, per));
+  for (auto& th : pool) th.join();
+}
+
+// X = V^{-1} B (m x m) by LU with partial pivoting; nonzero if singular
+int lu_solve(int m, std::vector<double> V, std::vector<double>& B) {
+  std::vector<int> piv(m);
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::fabs(V[(size_t)i * m + k]) > std::fabs(V[(size_t)p * m + k])) p = i;
+    if (V[(size_t)p * m + k] == 0.0) return 1;
+    if (p != k) {
+      for (int j = 0; j < m; ++j) std::swap(V[(size_t)p * m + j], V[(size_t)k * m + j]);
+      for (int j = 0; j < m; ++j) std::swap(B[(size_t)p * m + j], B[(size_t)k * m + j]);
+    }
+    const double inv = 1.0 / V[(size_t)k * m + k];
+    for (int i = k + 1; i < m; ++i) {
+      const double f = V[(size_t)i * m + k] * inv;
+      if (f == 0.0) continue;
+      V[(size_t)i * m + k] = f;
+      for (int j = k + 1; j < m; ++j) V[(size_t)i * m + j] -= f * V[(size_t)k * m + j];
+      for (int j = 0; j < m; ++j) B[(size_t)i * m + j] -= f * B[(size_t)k * m + j];
+    }
+  }
+  for (int k = m - 1; k >= 0; --k) {
+    const double inv = 1.0 / V[(size_t)k * m + k];
+    for (int j = 0; j < m; ++j) B[(size_t)k * m + j] *= inv;
+    for (int i = 0; i < k; ++i) {
+      const double f = V[(size_t)i * m + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < m; ++j) B[(size_t)i * m + j] -= f * B[(size_t)k * m + j];
+    }
+  }
+  return 0;
+}
+
+// exp(A) by scaling and squaring with the [13/13] Pade approximant (Higham, SIAM J.
+// Matrix Anal. Appl. 26, 2005): s with ||A / 2^s||_1 <= theta_13, r_13 = (V - U)^{-1}
+// (V + U) from the even and odd parts, then s squarings.
+int dense_expm(int m, std::vector<double>& A) {
+  static const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0, 1187353796428800.0,
+                               129060195264000.0,   10559470521600.0,    670442572800.0,     33522128640.0,
+                               1323241920.0,        40840800.0,          960960.0,           16380.0,
+                               182.0,               1.0};
+  const double theta13 = 5.371920351148152;
+  double nrm = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double c = 0.0;
+    for (int i = 0; i < m; ++i) c += std::fabs(A[(size_t)i * m + j]);
+    nrm = std::max(nrm, c);
+  }
+  if (!std::isfinite(nrm)) return 1;
+  int sq = 0;
+  if (nrm > theta13) sq = (int)std::ceil(std::log2(nrm / theta13));
+  const double sc = std::ldexp(1.0, -sq);
+  for (double& x : A) x *= sc;
+  const size_t mm = (size_t)m * m;
+  std::vector<double> A2(mm), A4(mm), A6(mm), T1(mm), U(mm), V(mm);
+  matmul(m, A.data(), A.data(), A2.data());
+  matmul(m, A2.data(), A2.data(), A4.data());
+  matmul(m, A4.data(), A2.data(), A6.data());
+  for (size_t e = 0; e < mm; ++e) T1[e] = b[13] * A6[e] + b[11] * A4[e] + b[9] * A2[e];
+  matmul(m, A6.data(), T1.data(), U.data());
+  for (size_t e = 0; e < mm; ++e) U[e] += b[7] * A6[e] + b[5] * A4[e] + b[3] * A2[e];
+  for (int i = 0; i < m; ++i) U[(size_t)i * m + i] += b[1];
+  matmul(m, A.data(), U.data(), T1.data());  // U = A (...)
+  std::swap(U, T1);
+  for (size_t e = 0; e < mm; ++e) T1[e] = b[12] * A6[e] + b[10] * A4[e] + b[8] * A2[e];
+  matmul(m, A6.data(), T1.data(), V.data());
+  for (size_t e = 0; e < mm; ++e) V[e] += b[6] * A6[e] + b[4] * A4[e] + b[2] * A2[e];
+  for (int i = 0; i < m; ++i) V[(size_t)i * m + i] += b[0];
+  std::vector<double> P(mm), Q(mm);
+  for (size_t e = 0; e < mm; ++e) {
+    P[e] = V[e] + U[e];
+    Q[e] = V[e] - U[e];
+  }
+  if (lu_solve(m, Q, P)) return 1;
+  for (int k = 0; k < sq; ++k) {
+    matmul(m, P.data(), P.data(), T1.data());
+    std::swap(P, T1);
+  }
+  A.swap(P);
+  return 0;
+}
+
+}  // namespace
+
+int dense_phi1_times(int m, const double* M, int k, const double* B, double* out) {
+  // phi_1(M) B is the top-right block of exp([[M, B], [0, 0]])
+  const int a = m + k;
+  std::vector<double> E((size_t)a * a, 0.0);
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) E[(size_t)i * a + j] = M[(size_t)i * m + j];
+    for (int j = 0; j < k; ++j) E[(size_t)i * a + m + j] = B[(size_t)i * k + j];
+  }
+  if (dense_expm(a, E)) return 1;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < k; ++j) out[(size_t)i * k + j] = E[(size_t)i * a + m + j];
   return 0;
 }

@@ -361,6 +361,7 @@ wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out) {
   wl_graph* g = ops[0]->g;
   const int prec = ops[0]->d.prec;
   const int method = ops[0]->d.method;
+  WL_CHECK(method != WL_M_ARNOLDI, WL_EUNSUPPORTED, "wl_multi_create: Arnoldi operators are evaluated alone");
   for (int i = 0; i < nops; ++i) {
     WL_CHECK(ops[i]->g == g, WL_EINVAL, "wl_multi_create: operators must share one graph");
     WL_CHECK(ops[i]->d.prec == prec, WL_EINVAL, "wl_multi_create: operators must share one precision");
@@ -399,11 +400,14 @@ wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out) {
     // omega_k = c_k / s^k, finish at k = K_i; all zero past K_i (the group is done)
     std::vector<double> tab((size_t)m->Kmax * nops * 5, 0.0);
     for (int i = 0; i < nops; ++i) {
-      const double sp = ops[i]->d.param, mu = ops[i]->d.mu;
+      // scaling s as for one operator: exponential s = min(beta, 1 / lambda_max), weights
+      // (beta / s)^k / k!; resolvent s = alpha, weights 1
       const bool ex = ops[i]->d.func == WL_F_EXP;
+      const double sp = ex && ops[i]->lam > 0.0 ? std::min(ops[i]->d.param, 1.0 / ops[i]->lam) : ops[i]->d.param;
+      const double mu = ops[i]->d.mu, ratio = ex ? ops[i]->d.param / sp : 1.0;
       double omega = 1.0;
       for (int k = 1; k <= m->K[i]; ++k) {
-        if (ex) omega /= k;
+        if (ex) omega *= ratio / k;
         double* c = &tab[((size_t)(k - 1) * nops + i) * 5];
         c[0] = sp;
         c[1] = k >= 3 ? sp * sp * mu * mu : 0.0;

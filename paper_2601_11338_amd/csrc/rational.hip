@@ -283,40 +283,6 @@ __global__ void k_rk_pad(int64_t n, int M, int Mp, const T* __restrict__ src, T*
 
 int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RK_BLOCKS, (n + 7) / 8)); }
 
-// Cholesky of the M x M Gram G (row-major) with deflation: a pivot at or below
-// tol * ref drops its column (row of R and column of Rinv zero).  Rinv is the inverse
-// of R on the kept columns.
-void host_chol_deflate(int M, const std::vector<double>& G, double tol, double ref, std::vector<double>& R,
-                       std::vector<double>& Rinv, std::vector<char>& keep) {
-  R.assign((size_t)M * M, 0.0);
-  Rinv.assign((size_t)M * M, 0.0);
-  keep.assign(M, 0);
-  for (int k = 0; k < M; ++k) {
-    double d = G[(size_t)k * M + k];
-    for (int i = 0; i < k; ++i) d -= R[(size_t)i * M + k] * R[(size_t)i * M + k];
-    if (!(d > tol * ref)) continue;
-    keep[k] = 1;
-    const double rkk = std::sqrt(d);
-    R[(size_t)k * M + k] = rkk;
-    for (int j = k + 1; j < M; ++j) {
-      double s = G[(size_t)k * M + j];
-      for (int i = 0; i < k; ++i) s -= R[(size_t)i * M + k] * R[(size_t)i * M + j];
-      R[(size_t)k * M + j] = s / rkk;
-    }
-  }
-  // Rinv: solve R Rinv = I on the kept indices (upper triangular, back substitution)
-  for (int c = 0; c < M; ++c) {
-    if (!keep[c]) continue;
-    for (int i = c; i >= 0; --i) {
-      if (!keep[i]) continue;
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int j = i + 1; j <= c; ++j)
-        if (keep[j]) s -= R[(size_t)i * M + j] * Rinv[(size_t)j * M + c];
-      Rinv[(size_t)i * M + c] = s / R[(size_t)i * M + i];
-    }
-  }
-}
-
 template <typename T>
 struct RkWork {
   wl_op* op;
@@ -416,8 +382,10 @@ wl_status rk_append(RkWork<T>& W, T* Wb, std::vector<double>* Rout) {
   const double ptol = post_tol<T>();
   for (int c = 0; c < M; ++c) {
     const double d = std::fabs(R2[(size_t)c * M + c] * R1[(size_t)c * M + c]);
-    if (!(d > ptol * std::sqrt(ref)))
+    if (!(d > ptol * std::sqrt(ref))) {
       for (int i = 0; i < M; ++i) R2i[(size_t)i * M + c] = 0.0;
+      for (int j = 0; j < M; ++j) R2[(size_t)c * M + j] = 0.0;  // the dropped component has no coupling
+    }
   }
   WL_TRY(rk_update<T>(W, slot, 1, R2i, nullptr, slot));
   if (Rout) {

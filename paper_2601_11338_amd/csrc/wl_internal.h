@@ -146,6 +146,7 @@ struct wl_op {
   wl_graph* g = nullptr;
   wl_op_desc d{};
   double rho = 0.0;       // rho(Z_mu) used for validation (0 if not needed)
+  double lam = 0.0;       // lambda_max(A) (exponential weights: scaling of the series)
   int K = 0;              // recurrence degree or Lanczos steps
   DevBuf w;               // cached phi 1
   bool w_valid = false;
@@ -317,6 +318,13 @@ wl_status launch_cv_finish(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* 
 int dense_syev(int m, const double* A, double* lam, double* U);
 // The same with only the first kr rows of U (kr x m row-major).
 int dense_syev_rows(int m, const double* A, int kr, double* lam, double* Ur);
+// out (m x k) = phi_1(M) B, phi_1(x) = (e^x - 1) / x, for a general m x m M (row-major),
+// from exp([[M, B], [0, 0]]) by Pade scaling and squaring.  Nonzero on failure.
+int dense_phi1_times(int m, const double* M, int k, const double* B, double* out);
+// Cholesky of an M x M Gram with deflation: pivots at or below tol * ref drop their
+// column (zero row of R, zero column of Rinv); Rinv inverts R on the kept columns.
+void host_chol_deflate(int M, const std::vector<double>& G, double tol, double ref, std::vector<double>& R,
+                       std::vector<double>& Rinv, std::vector<char>& keep);
 // Eigenvalues only of a symmetric tridiagonal matrix (diag a, offdiag b).
 int tridiag_eigvals(int m, const double* a, const double* b, double* lam);
 // Solve T X = B for block tridiagonal SPD T (K diagonal blocks Ad, K-1 off-diagonal
@@ -422,6 +430,8 @@ template <typename T>
 wl_status ensure_w(wl_op* op);
 template <typename T>
 wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw);
+template <typename T>
+wl_status phi_arnoldi(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* Xw);
 template <typename T>
 wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* const* Y, int outer_dim,
                     double* err_est);
