@@ -5,8 +5,9 @@
 // When beta rho(Z) is large the truncated series needs a degree of order e beta rho(Z);
 // a Krylov space of Z reaches the same accuracy with fewer products because it adapts
 // to the spectrum.  Z is not symmetric, so the basis is built by block Arnoldi with
-// full classical Gram-Schmidt orthogonalisation (repeated where it cancelled).  A block of 2n rows is
-// stored as one (2n) x b row-major array, its top half (rows 0..n-1) followed by its
+// full classical Gram-Schmidt orthogonalisation (repeated where it cancelled).  A
+// block of 2n rows is stored as one (2n) x b row-major array, its top half (rows
+// 0..n-1) followed by its
 // bottom half, so the Gram and update kernels treat it as a tall block unchanged, and
 //   Z V = [V_bot; A V_bot + (mu^2 - mu d) (.) V_top]
 // is one copy and one sparse product whose epilogue adds the diagonal term.  The
@@ -56,8 +57,8 @@ wl_status arn_update(ArnWork<T>& W, const T* X, int nblk, const std::vector<doub
 }
 
 // Orthogonalise Wb against basis blocks [0, nb) (classical Gram-Schmidt, a second pass
-// when the first cancelled most of a column) and
-// store it as block nb by CholQR2 with deflation.  H (host, (nb + 1) b x b) receives
+// when the first cancelled most of a column) and store it as block nb by CholQR2 with
+// deflation.  H (host, (nb + 1) b x b) receives
 // the coefficients: Wb = sum_i V_i H_i + V_nb H_nb.
 template <typename T>
 wl_status arn_append(ArnWork<T>& W, int nb, T* Wb, std::vector<double>& H) {
