@@ -1,0 +1,131 @@
+"""Parity at full size, in the launch configurations the benchmark times.
+
+Barabasi-Albert n = 10^6, m = 5 (the benchmark graph, 1e7 nonzeros), FP32 blocks of 16
+Rademacher columns with Krylov dimension 30, against the sparse FP64 oracle (truncated
+series and CG on A_mu(alpha)) on the columns it can afford; the road-network stand-in
+(n = 1.96e6) for the rational Krylov estimate, by properties that hold at any size
+(its oracle is dense).
+Tolerances as for the FP32 path elsewhere: phi X 2e-5, w 1e-5 relative."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sparse
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+@pytest.fixture(scope="module")
+def ba1m():
+    n = 1_000_000
+    rp, ci = synth.barabasi_albert(n, 5, seed=2026)
+    return n, rp, ci, sparse.adjacency(n, rp, ci)
+
+
+def dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.5, 1.0])
+def test_series_block16_full_size(ctx, lib, ba1m, mu):
+    n, rp, ci, As = ba1m
+    print(f"[gpu] full size BA 1e6 exp mu={mu}", flush=True)
+    g = lib.Graph(ctx, rp, ci)
+    g.autotune(torch.float32, 16)
+    lam = g.lambda_max()
+    op = lib.Operator(g, mu, "exp", 1.0 / lam, dtype=torch.float32, krylov_dim=30)
+    X = synth.rademacher_block(n, 16, 3)
+    PX = host(op.apply_phi(dev(X, torch.float32)))
+    coeffs = np.array([lam ** -k / np.prod(np.arange(1, k + 1, dtype=np.float64)) for k in range(31)])
+    cols = [0, 7, 15]
+    ref = sparse.series_apply(As, mu, coeffs, X[:, cols])
+    assert rel(PX[:, cols], ref) < 2e-5
+    # L 1 = 0 at full size
+    ones = torch.ones((n, 1), dtype=torch.float32, device="cuda")
+    w = host(op.fdeg())
+    L1 = host(op.apply_L(ones))
+    assert np.abs(L1).max() < 1e-5 * np.abs(w).max()
+
+
+def test_resolvent_lanczos_block16_full_size(ctx, lib, ba1m):
+    n, rp, ci, As = ba1m
+    print("[gpu] full size BA 1e6 res mu=0.5 Lanczos", flush=True)
+    g = lib.Graph(ctx, rp, ci)
+    g.autotune(torch.float32, 16)
+    rho = g.spectral_radius(0.5)
+    alpha = 0.5 / rho
+    op = lib.Operator(g, 0.5, "res", alpha, dtype=torch.float32, krylov_dim=30, rho_hint=rho)
+    X = synth.rademacher_block(n, 16, 3)
+    PX = host(op.apply_phi(dev(X, torch.float32)))
+    cols = [2, 11]
+    ref = sparse.phi_res_apply(As, 0.5, alpha, X[:, cols], rtol=1e-12)
+    assert rel(PX[:, cols], ref) < 2e-5
+
+
+def test_markov_chain_full_size(ctx, lib, ba1m):
+    n, rp, ci, As = ba1m
+    print("[gpu] full size BA 1e6 markov chain", flush=True)
+    g = lib.Graph(ctx, rp, ci)
+    lam = g.lambda_max()
+    op = lib.Operator(g, 1.0, "exp", 1.0 / lam, dtype=torch.float32, tol=1e-9)
+    K = op.info()[0]
+    starts = np.random.default_rng(590).choice(n, size=4, replace=False)
+    P0 = synth.spike_block(n, starts)
+    P1 = host(op.markov_step(dev(P0, torch.float32), steps=1))
+    coeffs = np.array([lam ** -k / np.prod(np.arange(1, k + 1, dtype=np.float64)) for k in range(K + 1)])
+    w = sparse.series_apply(As, 1.0, coeffs, np.ones((n, 1)))
+    ref = sparse.series_apply(As, 1.0, coeffs, P0 / w)
+    assert rel(P1, ref) < 2e-5
+    P20 = host(op.markov_step(dev(P0, torch.float32), steps=20))
+    np.testing.assert_allclose(P20.sum(0), 1.0, atol=1e-5)
+    pi = host(op.markov_stationary())
+    assert rel(pi, w[:, 0] / w.sum()) < 1e-5
+
+
+def test_arnoldi_full_size(ctx, lib, ba1m):
+    n, rp, ci, As = ba1m
+    print("[gpu] full size BA 1e6 Arnoldi on the linearisation", flush=True)
+    g = lib.Graph(ctx, rp, ci)
+    mu = 0.5
+    rhoZ = g.spectral_radius(mu)
+    beta = 20.0 / rhoZ
+    op = lib.Operator(g, mu, "exp", beta, dtype=torch.float32, krylov_dim=20, method="arnoldi")
+    X = synth.rademacher_block(n, 16, 3)
+    PX = host(op.apply_phi(dev(X, torch.float32)))
+    cols = [1, 9]
+    ref = sparse.phi_exp_apply(As, mu, beta, X[:, cols], tol=1e-12)
+    assert rel(PX[:, cols], ref) < 2e-5
+
+
+def test_return_probability_road_full_size(ctx, lib):
+    """At t = 0, Y(0) = Omega / n exactly: p_hat(0) estimates tr(I) / n = 1 within its
+    statistical error; p_hat stays in (0, 1] and decreases from there, with error
+    estimates below p_hat."""
+    print("[gpu] full size road stand-in return probability", flush=True)
+    rp, ci = synth.road_grid(1400, 1400, 0.7, seed=7)
+    n = len(rp) - 1
+    g = lib.Graph(ctx, rp, ci)
+    rhoZ = g.spectral_radius(1.0)
+    op = lib.Operator(g, 1.0, "res", 1.0 / (1.0 + rhoZ), dtype=torch.float32, tol=1e-7, rho_hint=rhoZ)
+    Om = lib.probes(ctx, n, 30, seed=2026, law="gauss", dtype=torch.float32)
+    ts = np.linspace(0.0, 100.0, 12)
+    p, e, poles, info = op.return_prob(Om, ts, 100.0, solve_tol=1e-6, max_iters=1000)
+    assert abs(p[0] - 1.0) < 5 * e[0] + 1e-3
+    assert np.all(p > 0) and np.all(p <= 1.0 + 1e-3) and p[-1] < 0.1 * p[0]
+    assert np.all(e < p)
+    assert info["solve_res"] <= 1e-6 and info["npoles"] >= 8
