@@ -361,7 +361,8 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
  *     kernels cover FP32 with b = 16 and b = 1 (nops <= 8, any precision); other
  *     shapes, and Krylov spaces so small that full reorthogonalisation is needed
  *     ((steps + 1) 2 b > n), are evaluated operator by operator into the same layout.
- * wl_multi_create: 1 <= nops <= 64 operators (WL_EUNSUPPORTED for mixed methods); the
+ * wl_multi_create: 1 <= nops <= 64 operators (WL_EUNSUPPORTED for mixed methods and for
+ * WL_M_ARNOLDI operators, which are evaluated alone); the
  * handle keeps the graph alive (not the operators, whose descriptors it copies).
  * wl_multi_apply: d_X n x b (the same block for every operator), d_Y n x (nops b)
  * row-major, laplacian != 0: L_g X in group g, else phi_g X.  nops b <= 4096.  Rows of

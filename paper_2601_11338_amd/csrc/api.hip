@@ -951,7 +951,11 @@ wl_status markov_gap_impl(wl_op* op, int outer_dim, uint64_t seed, double* lambd
   WL_TRY(op->outer_basis.ensure((size_t)(K + 2) * n * sizeof(T)));
   WL_TRY(op->outer_w.ensure((size_t)n * sizeof(T)));
   T* vptr = op->outer_basis.as<T>();
-  DevBuf rw, x0, t1, t2, dd;
+  DevBuf& rw = op->mk_rw;
+  DevBuf& x0 = op->mk_x0;
+  DevBuf& t1 = op->mk_t1;
+  DevBuf& t2 = op->mk_t2;
+  DevBuf& dd = op->mk_dd;
   WL_TRY(rw.ensure((size_t)n * sizeof(T)));
   WL_TRY(x0.ensure((size_t)n * sizeof(T)));
   WL_TRY(t1.ensure((size_t)n * sizeof(T)));

@@ -60,7 +60,9 @@ wl_status markov_step_impl(wl_op* op, const T* X, int b, int steps, T* Y) {
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
   WL_TRY(ensure_w<T>(op));
-  DevBuf rw, tmp, alt;
+  DevBuf& rw = op->mk_rw;
+  DevBuf& tmp = op->mk_tmp;
+  DevBuf& alt = op->mk_alt;
   WL_TRY(rw.ensure((size_t)n * sizeof(T)));
   WL_TRY(tmp.ensure((size_t)n * b * sizeof(T)));
   if (steps > 1) WL_TRY(alt.ensure((size_t)n * b * sizeof(T)));
@@ -74,7 +76,7 @@ wl_status markov_step_impl(wl_op* op, const T* X, int b, int steps, T* Y) {
     WL_TRY(phi_apply_impl<T>(op, tmp.as<T>(), out, b, nullptr, nullptr));
     cur = out;
   }
-  WL_HIP(hipStreamSynchronize(ctx->stream));  // the scratch blocks are freed on return
+  WL_HIP(hipStreamSynchronize(ctx->stream));
   return WL_OK;
 }
 
@@ -84,7 +86,8 @@ wl_status markov_stationary_impl(wl_op* op, T* pi) {
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
   WL_TRY(ensure_w<T>(op));
-  DevBuf s, sum;
+  DevBuf& s = op->mk_x0;
+  DevBuf& sum = op->mk_dd;
   WL_TRY(s.ensure((size_t)n * sizeof(T)));
   WL_TRY(sum.ensure(sizeof(double)));
   WL_TRY(launch_wpow<T>(ctx, n, op->w.as<T>(), 2, s.as<T>()));  // sqrt(w): sum(w) = ||sqrt(w)||^2

@@ -156,6 +156,9 @@ struct wl_op {
   DevBuf coef;            // device copy of recombination coefficients
   DevBuf small;           // device FP64 small matrices (T blocks etc.)
   DevBuf outer_basis, outer_w, outer_small, outer_coef, inner_tmp;
+  // discrete-time diffusion scratch, kept between calls (freeing a buffer waits for the
+  // whole device, which would serialise work on other streams)
+  DevBuf mk_rw, mk_tmp, mk_alt, mk_x0, mk_t1, mk_t2, mk_dd;
 };
 
 // ------------------------------------------------------------------ launch interfaces
