@@ -6,7 +6,8 @@
 // most; the weights w are the right singular vector of the smallest singular value of
 // the Loewner matrix (F_i - f_k) / (Z_i - z_k) over the points not yet chosen.  With
 // real points and values the Loewner matrix is real; its smallest singular pair comes
-// from a one-sided Jacobi SVD (accurate for the small singular values AAA needs).
+// from a one-sided Jacobi SVD (accurate for the small singular values AAA needs) of
+// the triangular factor of its Householder QR.
 // The poles are the zeros of the denominator sum_j w_j / (x - z_j), i.e. of the
 // polynomial sum_j w_j prod_{i != j} (x - z_i), found by the Aberth-Ehrlich
 // simultaneous iteration on that product form.
@@ -71,6 +72,35 @@ void jacobi_min_right_vector(int64_t rows, int m, std::vector<double>& A, std::v
   v.assign(V.begin() + (size_t)kmin * m, V.begin() + (size_t)(kmin + 1) * m);
 }
 
+// R (m x m, column-major) of a Householder QR of the rows x m column-major A: A and R
+// share their right singular vectors, and the Jacobi sweeps then run on m rows only.
+void householder_r(int64_t rows, int m, std::vector<double>& A, std::vector<double>& R) {
+  std::vector<double> v(rows);
+  for (int k = 0; k < m && k < rows; ++k) {
+    double* a = &A[(size_t)k * rows];
+    double nx = 0.0;
+    for (int64_t i = k; i < rows; ++i) nx += a[i] * a[i];
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double alpha = a[k] >= 0 ? -nx : nx;
+    for (int64_t i = k; i < rows; ++i) v[i] = a[i];
+    v[k] -= alpha;
+    double vv = 0.0;
+    for (int64_t i = k; i < rows; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    for (int c = k; c < m; ++c) {
+      double* col = &A[(size_t)c * rows];
+      double s = 0.0;
+      for (int64_t i = k; i < rows; ++i) s += v[i] * col[i];
+      s = 2.0 * s / vv;
+      for (int64_t i = k; i < rows; ++i) col[i] -= s * v[i];
+    }
+  }
+  R.assign((size_t)m * m, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int r = 0; r <= c && r < rows; ++r) R[(size_t)c * m + r] = A[(size_t)c * rows + r];
+}
+
 }  // namespace
 
 int aaa_real(int64_t N, const double* Z, const double* F, double tol, int mmax, std::vector<double>& z,
@@ -112,7 +142,13 @@ int aaa_real(int64_t N, const double* Z, const double* F, double tol, int mmax, 
         const int64_t i = rows[r];
         A[(size_t)k * nr + r] = (F[i] - f[k]) / (Z[i] - z[k]);
       }
-    jacobi_min_right_vector(nr, m, A, v);
+    if (nr > 2 * m) {
+      std::vector<double> Rm;
+      householder_r(nr, m, A, Rm);
+      jacobi_min_right_vector(m, m, Rm, v);
+    } else {
+      jacobi_min_right_vector(nr, m, A, v);
+    }
     w = v;
     err = 0.0;
     for (int64_t i = 0; i < N; ++i) {
@@ -156,20 +192,28 @@ int aaa_poles(const std::vector<double>& z, const std::vector<double>& w, std::v
   const double ctr = 0.5 * (zlo + zhi), rad = std::max(0.5 * (zhi - zlo), 1e-300);
   std::vector<double> zs(m);
   for (int i = 0; i < m; ++i) zs[i] = (z[i] - ctr) / rad;
+  // p(x) = sum_j w_j prod_{i != j} f_i and p'(x), f_i = x - z_i, in O(m) from prefix
+  // and suffix products of the f_i and their derivatives (product rule, f_i' = 1)
+  std::vector<cd> pre(m + 1), pred(m + 1), suf(m + 1), sufd(m + 1);
   auto p_and_dp = [&](cd x, cd* p, cd* dp) {
+    pre[0] = 1.0;
+    pred[0] = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const cd f = x - zs[i];
+      pred[i + 1] = pred[i] * f + pre[i];
+      pre[i + 1] = pre[i] * f;
+    }
+    suf[m] = 1.0;
+    sufd[m] = 0.0;
+    for (int i = m - 1; i >= 0; --i) {
+      const cd f = x - zs[i];
+      sufd[i] = sufd[i + 1] * f + suf[i + 1];
+      suf[i] = suf[i + 1] * f;
+    }
     cd P(0.0), D(0.0);
     for (int j = 0; j < m; ++j) {
-      cd prod(1.0);
-      for (int i = 0; i < m; ++i)
-        if (i != j) prod *= (x - zs[i]);
-      P += w[j] * prod;
-      for (int k = 0; k < m; ++k) {
-        if (k == j) continue;
-        cd q(1.0);
-        for (int i = 0; i < m; ++i)
-          if (i != j && i != k) q *= (x - zs[i]);
-        D += w[j] * q;
-      }
+      P += w[j] * (pre[j] * suf[j + 1]);
+      D += w[j] * (pred[j] * suf[j + 1] + pre[j] * sufd[j + 1]);
     }
     *p = P;
     *dp = D;
@@ -179,7 +223,8 @@ int aaa_poles(const std::vector<double>& z, const std::vector<double>& w, std::v
     const double th = 2.0 * M_PI * (k + 0.25) / deg + 0.4;
     r[k] = 1.3 * cd(std::cos(th), std::sin(th));
   }
-  // Aberth-Ehrlich: r_k -= N / (1 - N sum_{j != k} 1 / (r_k - r_j)), N = p / p'
+  // Aberth-Ehrlich: r_k -= N / (1 - N sum_{j != k} 1 / (r_k - r_j)), N = p / p';
+  // stop once every correction is at the rounding level of its root
   for (int it = 0; it < 500; ++it) {
     double mx = 0.0;
     for (int k = 0; k < deg; ++k) {
@@ -192,9 +237,9 @@ int aaa_poles(const std::vector<double>& z, const std::vector<double>& w, std::v
         if (j != k) s += 1.0 / (r[k] - r[j]);
       const cd delta = nwt / (1.0 - nwt * s);
       r[k] -= delta;
-      mx = std::max(mx, std::abs(delta));
+      mx = std::max(mx, std::abs(delta) / (1.0 + std::abs(r[k])));
     }
-    if (mx <= 1e-14) break;
+    if (mx <= 1e-15) break;
   }
   for (const cd& x : r) {
     const cd y = x * rad + ctr;
