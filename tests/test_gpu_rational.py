@@ -5,9 +5,10 @@ The library returns the poles it used; the oracle builds its (complex, exactly s
 block rational Arnoldi basis from the same poles, so both estimate from the same space
 and the same probes.  Differences come from the shifted solves (COCG to solve_tol), the
 projection (Rayleigh quotient V^T L V against the reduced pencil, equal with exact
-solves) and the vector precision.  Tolerances on p_hat, relative: FP64 1e-7 (solves to
-1e-12), FP32 2e-4 (basis orthogonal to ~1e-6, solves to 1e-6); on e_hat, absolute in
-units of p_hat: FP64 1e-6, FP32 2e-3.  At t = 0, Y(0) = Omega / n exactly, so p_hat(0)
+solves) and the vector precision.  Tolerances on p_hat: FP64 1e-7 relative (solves to
+1e-12); FP32 2e-4 relative plus 1e-6 of the largest estimate (the basis is orthogonal
+to ~1e-6, solves reach 1e-6, so a small p_hat at late t carries an absolute error of
+that order); on e_hat, absolute in units of p_hat: FP64 1e-6, FP32 2e-3.  At t = 0, Y(0) = Omega / n exactly, so p_hat(0)
 is the Nystrom estimate of the identity from Omega alone, to rounding at any size."""
 
 import numpy as np
@@ -42,7 +43,8 @@ def compare(lib, op, Lap, Om, ts, t_max, dtype, rtol_p, atol_e, pole_time=1.0, s
     assert info["npoles"] == poles.size and info["rho"] == rho
     assert info["solve_res"] <= solve_tol
     po, eo, _ = rational.return_probability_estimate(Lap, Om, ts, t_max, rho, poles=poles)
-    np.testing.assert_allclose(p, po, rtol=rtol_p, atol=0)
+    atol_p = 1e-6 * np.abs(po).max() if dtype == torch.float32 else 0.0
+    np.testing.assert_allclose(p, po, rtol=rtol_p, atol=atol_p)
     np.testing.assert_allclose(e, eo, rtol=0, atol=atol_e * np.abs(po).max())
     tr0, te0, _, _ = estimators.xnys(Om, Om / n)
     if ts[0] == 0.0:
