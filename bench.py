@@ -813,18 +813,16 @@ def run_arnoldi_ba1m(args):
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline_exp_large(rp, ci, n, mu, beta, X_h)
+        out["cpu_baseline"] = cpu_baseline_exp_large(rp, ci, n, mu, beta, X_h, Ks)
     return out
 
 
-def cpu_baseline_exp_large(rp, ci, n, mu, beta, X):
-    """The oracle's sparse truncated series (FP64, its own degree for 1e-9) on 2 of the
-    16 columns; counted as series products x nnz x columns."""
+def cpu_baseline_exp_large(rp, ci, n, mu, beta, X, K):
+    """The oracle's sparse truncated series (FP64) of the GPU series' degree K on 2 of
+    the 16 columns; counted as series products x nnz x columns."""
     from oracle import sparse
 
     A = sparse.adjacency(n, rp, ci)
-    lam = sparse.lambda_max(A)
-    K = sparse.exp_degree_for(beta, lam, 1e-9)
     t0 = time.perf_counter()
     sparse.phi_exp_apply(A, mu, beta, X[:, :2].astype("float64"), K=K)
     dt = time.perf_counter() - t0
