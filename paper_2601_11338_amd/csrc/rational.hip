@@ -609,7 +609,10 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   }
   std::vector<cd> poles;
   double aaa_err = 0.0;
-  if (exp_poles(t_max * rho, aaa_tol, 100, poles, &aaa_err)) {
+  // with t_max rho <= aaa_tol, 1 - e^{-x} <= x keeps exp(-x) within the tolerance of the
+  // constant 1 on the whole interval: no poles (L = 0, a graph without edges, included),
+  // the space is Omega's alone
+  if (t_max * rho > aaa_tol && exp_poles(t_max * rho, aaa_tol, 100, poles, &aaa_err)) {
     wl_set_error("wl_return_prob: AAA failed");
     return WL_ENOCONV;
   }

@@ -134,3 +134,13 @@ def test_fp32_series_large_beta(ctx, lib):
     Ym = host(lib.Multi([op, other]).apply_phi(dev(X, torch.float32)))
     assert rel(Ym[:, :16], ref) < 1e-4
     assert rel(Ym[:, 16:], sparse.phi_exp_apply(As, mu, 0.5 * beta, X, tol=1e-14)) < 1e-4
+
+
+def test_edgeless_graph(ctx, lib):
+    """No edges: A = D = 0, the start block [q_1 X; q_2 X] vanishes and phi = c_0 I."""
+    print("[gpu] arnoldi edgeless graph", flush=True)
+    n = 20
+    g = lib.Graph(ctx, np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), validate=True)
+    op = lib.Operator(g, 0.5, "exp", 0.7, dtype=torch.float64, krylov_dim=4, method="arnoldi")
+    X = synth.gaussian_block(n, 3, seed=2)
+    np.testing.assert_allclose(host(op.apply_phi(dev(X, torch.float64))), X, atol=1e-15)

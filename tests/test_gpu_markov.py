@@ -117,3 +117,17 @@ def test_markov_rejects_bad_arguments(ctx, lib):
         op.markov_step(X, steps=0)
     with pytest.raises(lib.WLError, match="EINVAL"):
         op.markov_gap(outer_dim=1)
+
+
+def test_markov_edgeless_graph(ctx, lib):
+    """No edges: phi = I, P = I: distributions stay put, pi is uniform, and every
+    eigenvalue of P is 1 (gap 0)."""
+    print("[gpu] markov edgeless graph", flush=True)
+    n = 30
+    g = lib.Graph(ctx, np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), validate=True)
+    op = lib.Operator(g, 0.5, "exp", 0.4, dtype=torch.float64, krylov_dim=5)
+    P0 = distributions(n, 3, 4)
+    np.testing.assert_allclose(host(op.markov_step(dev(P0, torch.float64), steps=5)), P0, atol=1e-14)
+    np.testing.assert_allclose(host(op.markov_stationary()), np.full(n, 1.0 / n), atol=1e-15)
+    l2, lmin, gap = op.markov_gap(outer_dim=10)
+    assert abs(l2 - 1.0) < 1e-12 and abs(lmin - 1.0) < 1e-12 and abs(gap) < 1e-12

@@ -173,3 +173,19 @@ def test_bad_arguments(ctx, lib):
     # an unreachable iteration budget is reported, not hidden
     with pytest.raises(lib.WLError):
         op.return_prob(Om, [1.0], 1.0, solve_tol=1e-14, max_iters=1)
+
+
+def test_edgeless_graph(ctx, lib):
+    """No edges: L = 0, rho(L) = 0, no poles; exp(-t L) = I, so every p_hat(t) is the
+    Nystrom estimate of I / n from the probes."""
+    print("[gpu] return_prob edgeless graph", flush=True)
+    n = 40
+    g = lib.Graph(ctx, np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32), validate=True)
+    Om = synth.gaussian_block(n, 5, seed=7)
+    tr0, te0, _, _ = estimators.xnys(Om, Om / n)
+    for kind in ("exp", "res"):
+        op = lib.Operator(g, 0.5, kind, 0.3, dtype=torch.float64, krylov_dim=5)
+        p, e, poles, info = op.return_prob(dev(Om, torch.float64), [0.0, 1.0, 50.0], 50.0, rho=0.0)
+        assert poles.size == 0 and info["nblocks"] == 1 and info["rho"] < 1e-12
+        np.testing.assert_allclose(p, tr0, rtol=1e-10)
+        np.testing.assert_allclose(e, te0, rtol=1e-8, atol=1e-14)
