@@ -681,6 +681,22 @@ def run_arp_road2m(args):
                                                  "aaa_err", "solve_res", "products")},
         "p_hat": {f"{ts[k]:.3g}": [float(p[k]), float(e[k])] for k in (0, 1, 9, 45, nt - 1)},
     }
+    # the standard Laplacian L = D - A on the same probes and times (the paper's
+    # reference in its return-probability figures), outside the timed region
+    opL = wl.Operator(g, 0.0, "linear", 1.0, dtype=torch.float32)
+    opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
+    torch.cuda.synchronize()
+    tL = time.perf_counter()
+    pL, eL, _, infoL = opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
+    torch.cuda.synchronize()
+    msL = (time.perf_counter() - tL) * 1e3
+    log(f"standard Laplacian: {msL:.0f} ms, poles {infoL['npoles']}, COCG iterations {infoL['iters_total']}, "
+        f"p(1)={pL[1]:.5f} p(100)={pL[-1]:.3e}")
+    out["standard_laplacian"] = {
+        "ms": msL,
+        "rational_krylov": {k: infoL[k] for k in ("npoles", "solves", "iters_total", "iters_max", "rho")},
+        "p_hat": {f"{ts[k]:.3g}": [float(pL[k]), float(eL[k])] for k in (0, 1, 9, 45, nt - 1)},
+    }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline_arp(rp, ci, n, alpha, K)

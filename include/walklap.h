@@ -59,7 +59,7 @@ typedef enum {
   WL_EINTERNAL = 9
 } wl_status;
 
-typedef enum { WL_F_RESOLVENT = 0, WL_F_EXP = 1 } wl_func;
+typedef enum { WL_F_RESOLVENT = 0, WL_F_EXP = 1, WL_F_LINEAR = 2 } wl_func;
 typedef enum { WL_FP32 = 4, WL_FP64 = 8 } wl_prec;
 typedef enum {
   WL_M_AUTO = 0,        /* exponential: recurrence; resolvent: block Lanczos on A_mu */
@@ -90,7 +90,10 @@ typedef struct wl_mlp wl_mlp;
 /* Operator description.
  *   mu          backtrack downweighting in [0, 1]; each backtracking step of a walk is
  *               weighted by theta = 1 - mu (Sec. 3.2).  mu = 0 all walks, mu = 1 NBT.
- *   func        WL_F_RESOLVENT (c_k = param^k) or WL_F_EXP (c_k = param^k / k!).
+ *   func        WL_F_RESOLVENT (c_k = param^k) or WL_F_EXP (c_k = param^k / k!), or
+ *               WL_F_LINEAR: f(x) = x (c_1 = 1, c_k = 0 for k >= 2; c_0 = 1 as always),
+ *               so phi = I + A, w = 1 + d and L = D - A, the standard graph Laplacian
+ *               that the paper's Laplacians reduce to (param ignored; recurrence only).
  *   param       alpha (resolvent; must satisfy alpha * rho(Z_mu) < 1, Prop. "whe-we-converge"
  *               and its remark) or beta (exponential; inverse temperature, Sec. 4.1.2).
  *   prec        WL_FP32 or WL_FP64: element type of vectors; all Krylov / recurrence

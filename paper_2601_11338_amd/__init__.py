@@ -15,6 +15,7 @@ from ._lib import (  # noqa: F401
     WL_EST_SURROGATE,
     WL_EST_XNYS,
     WL_F_EXP,
+    WL_F_LINEAR,
     WL_F_RESOLVENT,
     WL_FP32,
     WL_FP64,
@@ -30,7 +31,8 @@ from ._lib import (  # noqa: F401
     load,
 )
 
-FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP}
+FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP,
+         "linear": WL_F_LINEAR}
 METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS, "arnoldi": WL_M_ARNOLDI}
 ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS,
               "surrogate": WL_EST_SURROGATE}

@@ -6,7 +6,7 @@ import os
 LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwalklap.so")
 
 WL_OK, WL_EINVAL, WL_ERANGE, WL_ENOMEM, WL_EDEVICE, WL_ENOTSPD, WL_ENOCONV, WL_ENUMERIC, WL_EUNSUPPORTED = range(9)
-WL_F_RESOLVENT, WL_F_EXP = 0, 1
+WL_F_RESOLVENT, WL_F_EXP, WL_F_LINEAR = 0, 1, 2
 WL_FP32, WL_FP64 = 4, 8
 WL_M_AUTO, WL_M_RECURRENCE, WL_M_LANCZOS, WL_M_ARNOLDI = 0, 1, 2, 3
 WL_PROBE_GAUSS, WL_PROBE_RADEMACHER = 0, 1

@@ -1179,7 +1179,10 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   WL_CHECK(g && d && out, WL_EINVAL, "wl_op_create: null argument");
   *out = nullptr;
   WL_CHECK(d->mu >= 0.0 && d->mu <= 1.0, WL_EINVAL, "wl_op_create: mu must lie in [0, 1]");
-  WL_CHECK(d->func == WL_F_RESOLVENT || d->func == WL_F_EXP, WL_EINVAL, "wl_op_create: unknown func");
+  WL_CHECK(d->func == WL_F_RESOLVENT || d->func == WL_F_EXP || d->func == WL_F_LINEAR, WL_EINVAL,
+           "wl_op_create: unknown func");
+  WL_CHECK(d->func != WL_F_LINEAR || d->method == WL_M_AUTO || d->method == WL_M_RECURRENCE, WL_EUNSUPPORTED,
+           "wl_op_create: the linear weights (standard Laplacian) are evaluated by their one-step series");
   WL_CHECK(is_finite(d->param) && d->param > 0.0, WL_EINVAL, "wl_op_create: param (alpha or beta) must be > 0");
   WL_CHECK(d->prec == WL_FP32 || d->prec == WL_FP64, WL_EINVAL, "wl_op_create: prec must be WL_FP32 or WL_FP64");
   WL_CHECK(d->krylov_dim >= 0 && d->krylov_dim <= 2000, WL_EINVAL, "wl_op_create: krylov_dim out of range");
@@ -1191,7 +1194,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
            "wl_op_create: the Arnoldi method needs an explicit krylov_dim");
   WL_CHECK(d->reorth >= 0 && d->reorth <= 2, WL_EINVAL, "wl_op_create: reorth must be 0, 1 or 2");
   int method = d->method;
-  if (method == WL_M_AUTO) method = d->func == WL_F_EXP ? WL_M_RECURRENCE : WL_M_LANCZOS;
+  if (method == WL_M_AUTO) method = d->func == WL_F_RESOLVENT ? WL_M_LANCZOS : WL_M_RECURRENCE;
   WL_CHECK(!(method == WL_M_LANCZOS && d->func == WL_F_EXP && d->mu != 0.0), WL_EUNSUPPORTED,
            "wl_op_create: exponential weights with mu > 0 are not a function of one symmetric n x n matrix; "
            "use the recurrence");
@@ -1209,7 +1212,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   }
   double lam_exp = 0.0;  // lambda_max(A) for exponential weights (series scaling, degree)
   if (d->func == WL_F_EXP) WL_TRY(wl_lambda_max(g, 1e-10, &lam_exp));
-  int K = d->krylov_dim;
+  int K = d->func == WL_F_LINEAR ? 1 : d->krylov_dim;
   if (K == 0) {
     const double tol = d->tol > 0 ? d->tol : 1e-12;
     if (d->func == WL_F_EXP) {
@@ -1240,6 +1243,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   ++g->refs;
   op->d = *d;
   op->d.method = method;
+  if (d->func == WL_F_LINEAR) op->d.param = 1.0;  // phi = I + A: one step of scale 1
   op->rho = rho;
   op->lam = lam_exp;
   op->K = K;

@@ -391,6 +391,10 @@ __global__ void k_affine(int64_t n, const float* __restrict__ base, const float*
 void surrogate_coeffs(const wl_op* op, double* c2m, double* c3, double* c4) {
   const double p = op->d.param;
   const bool ex = op->d.func == WL_F_EXP;
+  if (op->d.func == WL_F_LINEAR) {  // c_k = 0 for k >= 2
+    *c2m = *c3 = *c4 = 0.0;
+    return;
+  }
   *c2m = (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
   *c3 = ex ? p * p * p / 6.0 : p * p * p;
   *c4 = ex ? p * p * p * p / 24.0 : p * p * p * p;

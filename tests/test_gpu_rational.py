@@ -30,6 +30,10 @@ def dev(x, dtype):
     return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
 
 
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
 def ba(n, m, seed):
     rp, ci = synth.barabasi_albert(n, m, seed)
     return rp, ci, walks.adjacency(n, rp, ci)
@@ -189,3 +193,24 @@ def test_edgeless_graph(ctx, lib):
         assert poles.size == 0 and info["nblocks"] == 1 and info["rho"] < 1e-12
         np.testing.assert_allclose(p, tr0, rtol=1e-10)
         np.testing.assert_allclose(e, te0, rtol=1e-8, atol=1e-14)
+
+
+def test_standard_laplacian(ctx, lib):
+    """Linear weights f(x) = x give phi = I + A and L = D - A, the standard Laplacian
+    Alg. 1 also takes (the paper's reference Laplacian in its return-probability
+    figures)."""
+    print("[gpu] return_prob standard Laplacian", flush=True)
+    n = 300
+    rp, ci, A = ba(n, 2, 19)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.0, "linear", 1.0, dtype=torch.float64)
+    assert op.info() == (1, lib.WL_M_RECURRENCE)
+    d = A.sum(1)
+    X = synth.gaussian_block(n, 3, seed=4)
+    np.testing.assert_allclose(host(op.fdeg()), 1.0 + d, rtol=1e-14)
+    Lap = np.diag(d) - A
+    np.testing.assert_allclose(host(op.apply_L(dev(X, torch.float64))), Lap @ X, atol=1e-12)
+    Om = synth.gaussian_block(n, 4, seed=5)
+    compare(lib, op, Lap, Om, [0.0, 0.2, 2.0, 20.0], 20.0, torch.float64, 1e-7, 1e-6)
+    with pytest.raises(lib.WLError):
+        lib.Operator(g, 0.0, "linear", 1.0, dtype=torch.float64, method="lanczos")
