@@ -100,3 +100,14 @@ def test_diag_est_rejects_bad_arguments(setup, lib):
         op.diag_est(0, 1)
     with pytest.raises(lib.WLError):
         op.diag_est(16, 1, target="L", estimator="surrogate")
+
+
+def test_surrogate_exact_for_linear_weights(setup, lib):
+    """Linear weights (phi = I + A): the degree-3 surrogate G = c_0 I + c_1 A is phi
+    itself, so the surrogate estimator's probe noise vanishes and diag phi = 1, tr phi = n
+    come out exactly."""
+    ctx, g, _, _, n, A, _ = setup
+    op = lib.Operator(g, 0.0, "linear", 1.0, dtype=torch.float64)
+    d, tr, te = op.diag_est(16, 3, target="phi", estimator="surrogate")
+    np.testing.assert_allclose(d.cpu().numpy(), 1.0, atol=1e-13)
+    assert abs(tr - n) < 1e-10 * n and abs(te) < 1e-10
