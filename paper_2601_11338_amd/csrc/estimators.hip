@@ -255,11 +255,13 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
     gop.g = g;
     gop.d = op->d;
     gop.d.method = WL_M_RECURRENCE;
-    gop.K = 3;
+    gop.K = std::min(3, op->K);  // linear weights: the series stops after one step
     const double p = op->d.param;
+    // weights of G's terms that exist (the series may stop before degree 3: linear
+    // weights after one step)
     const bool ex = op->d.func == WL_F_EXP, lin = op->d.func == WL_F_LINEAR;
-    c2m = lin ? 0.0 : (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
-    c3 = lin ? 0.0 : (ex ? p * p * p / 6.0 : p * p * p);
+    c2m = lin || gop.K < 2 ? 0.0 : (ex ? p * p / 2.0 : p * p) * (1.0 - op->d.mu);
+    c3 = lin || gop.K < 3 ? 0.0 : (ex ? p * p * p / 6.0 : p * p * p);
     WL_TRY(Z.ensure((size_t)n * mc * es));
     WL_TRY(graph_tri2(g, &tri));
     std::vector<unsigned long long> ht(n);
