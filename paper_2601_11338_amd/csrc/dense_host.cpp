@@ -384,9 +384,15 @@ void matmul(int m, const double* A, const double* B, double* C) {
   };
   std::vector<std::thread> pool;
   const int per = (m + nth - 1) / nth;
-  for (int t = 1; t < nth; ++t) pool.emplace_back(rows, std::min(m, t * per), std::min(m, (t + 1) * per));
+  int started = 1;
+  try {
+    for (; started < nth; ++started)
+      pool.emplace_back(rows, std::min(m, started * per), std::min(m, (started + 1) * per));
+  } catch (...) {  // no thread to be had: the caller's thread takes the rest
+  }
   rows(0, std::min(m, per));
   for (auto& th : pool) th.join();
+  if (started < nth) rows(std::min(m, started * per), m);
 }
 
 // X = V^{-1} B (m x m) by LU with partial pivoting; nonzero if singular

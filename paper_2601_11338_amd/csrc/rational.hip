@@ -760,9 +760,14 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     }
   };
   std::vector<std::thread> pool;
-  for (int tid = 1; tid < nth; ++tid) pool.emplace_back(estimate_times, tid);
+  int started = 1;
+  try {
+    for (; started < nth; ++started) pool.emplace_back(estimate_times, started);
+  } catch (...) {  // no thread to be had: the caller's thread takes the rest
+  }
   estimate_times(0);
   for (auto& th : pool) th.join();
+  for (int tid = started; tid < nth; ++tid) estimate_times(tid);
   for (char f : failed)
     if (f) {
       wl_set_error("wl_return_prob: eigendecomposition of a Nystrom core failed");
