@@ -49,7 +49,7 @@ typedef enum {
   WL_OK = 0,
   WL_EINVAL = 1,        /* invalid argument (null pointer, bad size, malformed graph) */
   WL_ERANGE = 2,        /* parameter outside the convergence region (alpha * rho(Z_mu) >= 1),
-                           or a size beyond the supported range (nnz >= 2^31) */
+                           or a size beyond the supported range (wl_graph_check_size) */
   WL_ENOMEM = 3,        /* device allocation failed */
   WL_EDEVICE = 4,       /* HIP runtime error, or no usable device */
   WL_ENOTSPD = 5,       /* an operator that must be positive definite is not */
@@ -147,10 +147,21 @@ wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launch
  * A simple undirected unweighted graph as symmetric CSR: d_rowptr (n+1 int32),
  * d_colidx (nnz int32), columns strictly increasing within a row, no self loops,
  * every edge stored in both directions (Definition "adjacency"; simple graphs,
- * Sec. 2).  nnz must be < 2^31 (WL_ERANGE).  With WL_GRAPH_VALIDATE the structure
- * is checked on the device (WL_EINVAL with the first violation).  Degrees
- * d = A 1 are computed on the device.  The row split used by the SpMM kernels
- * (rows above a degree threshold handled by whole workgroups) is built here.    */
+ * Sec. 2).  Sizes as wl_graph_check_size (WL_ERANGE beyond them).  With
+ * WL_GRAPH_VALIDATE the structure is checked on the device (WL_EINVAL with the
+ * first violation).  Degrees d = A 1 are computed on the device.  The row split
+ * used by the SpMM kernels (rows above a degree threshold handled by whole
+ * workgroups) is built here.
+ *
+ * Largest supported sizes of one CSR (a graph, or the concatenation of a batch):
+ * n <= WL_MAX_ROWS and nnz <= WL_MAX_NNZ = 2^31 - 1 - 2^16 (int32 column indices; the
+ * sparse-product kernels step a row's 32-bit index up to 2^16 past its end before the
+ * loop test).  wl_graph_check_size returns WL_OK, WL_EINVAL (negative) or WL_ERANGE;
+ * it is host only and runs without a device.  wl_graph_create and wl_batch_create
+ * apply it before touching the device.                                           */
+#define WL_MAX_ROWS 2147483646LL
+#define WL_MAX_NNZ 2147418111LL
+wl_status wl_graph_check_size(int64_t n, int64_t nnz);
 wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_rowptr,
                           const int32_t* d_colidx, uint32_t flags, wl_graph** out);
 wl_status wl_graph_info(const wl_graph* g, int64_t* n, int64_t* nnz, int32_t* max_degree);

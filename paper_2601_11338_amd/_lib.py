@@ -62,6 +62,7 @@ SIGNATURES = {
     "wl_ctx_destroy": (C.c_int, [vp]),
     "wl_ctx_set_profiling": (C.c_int, [vp, i32]),
     "wl_ctx_kernel_stats": (C.c_int, [vp, i32, C.POINTER(i64), pd, pd]),
+    "wl_graph_check_size": (C.c_int, [i64, i64]),
     "wl_graph_create": (C.c_int, [vp, i64, i64, vp, vp, u32, C.POINTER(vp)]),
     "wl_graph_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
     "wl_graph_destroy": (C.c_int, [vp]),

@@ -201,13 +201,22 @@ void graph_release(wl_graph* g) {
 extern "C" {
 
 // ------------------------------------------------------------------ graph
+wl_status wl_graph_check_size(int64_t n, int64_t nnz) {
+  WL_CHECK(n >= 0 && nnz >= 0, WL_EINVAL, "graph size: negative n or nnz");
+  WL_CHECK(n <= WL_MAX_ROWS, WL_ERANGE, "graph size: n = %lld exceeds %lld", (long long)n, (long long)WL_MAX_ROWS);
+  // the sparse-product kernels walk a row's column list with 32-bit indices that run
+  // up to 2^16 past the row's end before the loop test: nnz must leave that headroom
+  WL_CHECK(nnz <= WL_MAX_NNZ, WL_ERANGE, "graph size: nnz = %lld exceeds %lld (int32 CSR with index headroom)",
+           (long long)nnz, (long long)WL_MAX_NNZ);
+  return WL_OK;
+}
+
 wl_status wl_graph_create(wl_ctx* ctx, int64_t n, int64_t nnz, const int32_t* d_rowptr, const int32_t* d_colidx,
                           uint32_t flags, wl_graph** out) {
   WL_CHECK(ctx && out, WL_EINVAL, "wl_graph_create: null ctx or out");
   *out = nullptr;
   WL_CHECK(n >= 0 && nnz >= 0, WL_EINVAL, "wl_graph_create: negative size");
-  WL_CHECK(n < (1ll << 31) - 1, WL_ERANGE, "wl_graph_create: n must be < 2^31 - 1");
-  WL_CHECK(nnz < (1ll << 31), WL_ERANGE, "wl_graph_create: nnz must be < 2^31 (int32 CSR)");
+  WL_TRY(wl_graph_check_size(n, nnz));
   WL_CHECK(d_rowptr != nullptr, WL_EINVAL, "wl_graph_create: rowptr is null");
   WL_CHECK(nnz == 0 || d_colidx != nullptr, WL_EINVAL, "wl_graph_create: colidx is null");
   WL_CHECK((flags & ~(WL_GRAPH_COPY | WL_GRAPH_VALIDATE)) == 0, WL_EINVAL, "wl_graph_create: unknown flags");

@@ -515,6 +515,15 @@ wl_status expv_prepare(wl_batch* bt, BatchWork& wk, int b, int K) {
     wk.cap_at[kcap[g] - 1] = 1;
   }
   WL_HIP(hipMemcpyAsync(wk.kcap.p, kcap.data(), (size_t)ng * 4, hipMemcpyHostToDevice, ctx->stream));
+  if (bt->use_xmap) {
+    // the XCD tile map of the sparse products' shape is built (allocated, uploaded) now,
+    // not on first use inside a captured sequence; every product of the diffusion runs
+    // on library buffers of width b, so one shape covers them all
+    EpiArgs<float> ep;
+    ep.xmap = &bt->xmap;
+    ep.prepare_only = 1;
+    WL_TRY(launch_spmm<float>(bt->G, wk.bufA.as<float>(), wk.bufB.as<float>(), b, ep, shape_for(bt->G, WL_FP32, b)));
+  }
   const size_t lds = (size_t)5 * K * b * b * sizeof(double);
   WL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_expT_batched),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -735,7 +744,7 @@ wl_status wl_batch_create(wl_ctx* ctx, int32_t ngraphs, wl_graph* const* graphs,
     bt->K[gi] = std::max(1, K);
     bt->Kmax = std::max(bt->Kmax, bt->K[gi]);
   }
-  WL_CHECK(nnz_tot < (1ll << 31) && bt->N < (1ll << 31) - 1, WL_ERANGE, "wl_batch_create: batch too large");
+  WL_TRY(wl_graph_check_size(bt->N, nnz_tot));
   // concatenated CSR on the host
   std::vector<int32_t> hrp(bt->N + 1), hgid(bt->N);
   std::vector<int32_t> hci((size_t)std::max<int64_t>(nnz_tot, 1));

@@ -348,6 +348,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     WL_TRY(const_cast<XcdTileMap*>(ep.xmap)->get(RPB, n_long, &epx.tile_map, &blocks));
     nshort = blocks;
   }
+  if (ep.prepare_only) return WL_OK;
   const int64_t gx = nshort + n_long;
   WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
   const size_t lds = ep.C ? (size_t)b * TILE * sizeof(T) : 0;

@@ -201,6 +201,9 @@ struct EpiArgs {
   // gather from the same rows can be placed on one XCD.  Null: tile s = block s.
   const struct XcdTileMap* xmap = nullptr;
   const int32_t* tile_map = nullptr;  // device map, filled in by the launcher
+  // Host-side preparation only (resolve the tile map for this shape), no launch: makes
+  // a later launch of the same shape free of allocation and host copies (capture).
+  int prepare_only = 0;
 };
 
 // Tiles of a block-diagonal graph (consecutive row ranges that only touch their own

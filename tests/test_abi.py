@@ -47,6 +47,25 @@ def test_null_arguments_rejected(lib):
     assert b"null" in lib.wl_last_error()
 
 
+def test_graph_size_bound(lib):
+    """The int32 CSR bound leaves the sparse-product kernels' index headroom: nnz up to
+    2^31 - 1 - 2^16 is accepted, anything above is WL_ERANGE, negative sizes WL_EINVAL
+    (host-only check, no device touched; the boundary sizes never reach a GPU)."""
+    import paper_2601_11338_amd as wl
+    max_nnz = 2**31 - 1 - 2**16
+    assert lib.wl_graph_check_size(1000, max_nnz) == wl._lib.WL_OK
+    assert lib.wl_graph_check_size(1000, max_nnz + 1) == wl._lib.WL_ERANGE
+    assert b"nnz" in lib.wl_last_error()
+    assert lib.wl_graph_check_size(1000, 2**31 - 4000) == wl._lib.WL_ERANGE
+    assert lib.wl_graph_check_size(2**31 - 2, 0) == wl._lib.WL_OK
+    assert lib.wl_graph_check_size(2**31 - 1, 0) == wl._lib.WL_ERANGE
+    assert lib.wl_graph_check_size(-1, 0) == wl._lib.WL_EINVAL
+    assert lib.wl_graph_check_size(5, -1) == wl._lib.WL_EINVAL
+    # the graph constructor applies it before it looks at the context's device
+    h = C.c_void_p(1)
+    assert lib.wl_graph_create(C.c_void_p(1), 10, max_nnz + 1, None, None, 0, C.byref(h)) == wl._lib.WL_ERANGE
+
+
 def test_no_device_reports_edevice_or_works(lib):
     """Without a GPU the context call fails cleanly with WL_EDEVICE."""
     import torch

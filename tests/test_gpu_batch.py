@@ -127,6 +127,43 @@ def test_batch_graph_replays_match_eager(setup, lib):
     gr.close()
 
 
+def test_batch_graph_xcd_grouped_capture_first(ctx, lib):
+    """A fresh batch switched to the XCD-grouped tile order and captured before any eager
+    run at that width: the tile map is built before capture starts, and every replay
+    equals the eager call in the same tile order bit for bit."""
+    print("[gpu] batch graph xcd-grouped capture", flush=True)
+    gs, variants, ts = mixed_graphs()
+    graphs, descs, phis = [], [], []
+    for (n, rp, ci), (mu, kind) in zip(gs, variants):
+        param, ph = dense_phi(n, rp, ci, mu, kind)
+        graphs.append(lib.Graph(ctx, rp, ci))
+        descs.append({"mu": mu, "func": kind, "param": param})
+        phis.append(ph)
+    batch = lib.Batch(ctx, graphs, descs, tol=1e-12)
+    batch.xcd_grouped = True
+    b = 8
+    U0 = batch.pack([torch.tensor(philox.gaussian(ph.shape[0], b, 500 + i), dtype=torch.float32, device="cuda")
+                     for i, ph in enumerate(phis)])
+    Y = torch.empty_like(U0)
+    gr = batch.graph(U0, Y, outer_dim=30)
+    Ye = torch.empty_like(U0)
+    for r in range(3):
+        tr = [t * (1.0 + 0.25 * r) for t in ts]
+        gr.launch(tr)
+        torch.cuda.synchronize()
+        Yg = Y.clone()
+        batch.expv(U0, tr, outer_dim=30, out=Ye, want_trace=False)
+        torch.cuda.synchronize()
+        assert torch.equal(Yg, Ye), r
+    for i, (ph, y, t) in enumerate(zip(phis, batch.unpack(Y), [t * 1.5 for t in ts])):
+        om = batch.unpack(U0)[i].cpu().numpy().astype(np.float64)
+        (ref,) = laplacian.expv(laplacian.walk_laplacian(ph), om, [t])
+        err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref)
+        assert err < 1e-4, (i, err)
+    gr.close()
+    batch.close()
+
+
 def test_batch_diffusion_on_hub_graphs(lib):
     """Power-law graphs with hubs (a few large, fast-converging Ritz values of L) and a
     block model in one batch: exp(-t L) U0 against the dense oracle at t = 1 and 10."""
