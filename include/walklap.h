@@ -33,7 +33,8 @@
  *    alive, so handles may be destroyed in any order (each exactly once).
  *  - Workspace (Krylov bases, recurrence buffers, reduction partials) is
  *    allocated by the library on the device and kept in the operator or graph
- *    for reuse; WL_ENOMEM if it cannot be allocated.
+ *    for reuse; WL_ENOMEM if it cannot be allocated.  The _ws variants of the
+ *    evaluation calls take caller-provided workspace instead (wl_workspace_size).
  */
 #ifndef WALKLAP_H
 #define WALKLAP_H
@@ -223,6 +224,33 @@ wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b);
  * may be NULL): a-posteriori estimate || B_K E_K^T exp(-t T) E_1 R_0 ||_F.        */
 wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt,
                   void* const* d_Y, int32_t outer_dim, double* err_est);
+
+/* ---------------------------------------------------------------- caller workspace
+ * The evaluation is matrix-vector products only (Sec. 4.1), so its memory is a fixed
+ * set of blocks known before the call: Krylov bases ((K + 1) blocks of n x b),
+ * recurrence buffers (two n x b blocks), small FP64 matrices and reduction partials.
+ * A caller that plans its own device memory asks for that size and passes one region:
+ *
+ * wl_workspace_size: *bytes = device workspace one call of kind `call`
+ * (WL_CALL_APPLY_PHI, WL_CALL_APPLY_L or WL_CALL_EXPV with outer_dim) on op with
+ * block width b needs.  It depends on the operator's state: when op has not cached its
+ * walk degrees w (wl_fdeg, wl_apply_L or wl_expv did not run), the Laplacian calls
+ * include room to compute w (n values + one work vector + the b = 1 evaluation), and
+ * they compute w again on every such call; call wl_fdeg once first to avoid that.
+ * WL_EUNSUPPORTED for WL_M_ARNOLDI operators.  Host only, nothing enqueued.
+ * wl_apply_phi_ws / wl_apply_L_ws / wl_expv_ws: as wl_apply_phi / wl_apply_L / wl_expv,
+ * with every device buffer the call uses carved from d_work (device memory on the
+ * context's device, 256-byte aligned, at least the wl_workspace_size bytes for the same
+ * call, b and outer_dim; WL_EINVAL otherwise).  These calls allocate no device memory
+ * and record no kernel timing.  The region must stay valid until the call's work has
+ * completed on the stream; its contents need no initialisation and are undefined
+ * afterwards.  Calls sharing one region must be ordered (one stream).              */
+typedef enum { WL_CALL_APPLY_PHI = 0, WL_CALL_APPLY_L = 1, WL_CALL_EXPV = 2 } wl_call;
+wl_status wl_workspace_size(const wl_op* op, int32_t call, int32_t b, int32_t outer_dim, size_t* bytes);
+wl_status wl_apply_phi_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes);
+wl_status wl_apply_L_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes);
+wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
+                     int32_t outer_dim, double* err_est, void* d_work, size_t work_bytes);
 
 /* ---------------------------------------------------------------- discrete-time diffusion
  * The Markov chain of a walk Laplacian (Sec. "Simulating discrete-time diffusion",

@@ -272,6 +272,50 @@ class Operator:
         check(load().wl_expv(self.handle, _ptr(U0), U0.shape[1], tarr, len(ts), parr, int(outer_dim), err))
         return outs, list(err)
 
+    # ---- caller workspace (no device allocation inside the call)
+    CALLS = {"apply_phi": _lib.WL_CALL_APPLY_PHI, "apply_L": _lib.WL_CALL_APPLY_L, "expv": _lib.WL_CALL_EXPV}
+
+    def workspace_size(self, call, b, outer_dim=0):
+        """Bytes of device workspace one call ("apply_phi", "apply_L", "expv") needs."""
+        v = C.c_size_t()
+        check(load().wl_workspace_size(self.handle, self.CALLS[call], int(b), int(outer_dim), C.byref(v)))
+        return v.value
+
+    def _work(self, work):
+        torch = _torch()
+        if not (isinstance(work, torch.Tensor) and work.is_cuda and work.is_contiguous()):
+            raise ValueError("work must be a contiguous device tensor")
+        return _ptr(work), work.numel() * work.element_size()
+
+    def apply_phi_ws(self, X, work, out=None):
+        X = self._block(X)
+        out = self._out(out, X)
+        wp, wb = self._work(work)
+        check(load().wl_apply_phi_ws(self.handle, _ptr(X), _ptr(out), X.shape[1], wp, wb))
+        return out
+
+    def apply_L_ws(self, X, work, out=None):
+        X = self._block(X)
+        out = self._out(out, X)
+        wp, wb = self._work(work)
+        check(load().wl_apply_L_ws(self.handle, _ptr(X), _ptr(out), X.shape[1], wp, wb))
+        return out
+
+    def expv_ws(self, U0, ts, work, outer_dim=30, outs=None):
+        U0 = self._block(U0)
+        ts = [float(t) for t in ts]
+        torch = _torch()
+        outs = [torch.empty_like(U0) for _ in ts] if outs is None else outs
+        if len(outs) != len(ts):
+            raise ValueError("one output block per time is needed")
+        outs = [self._out(o, U0) for o in outs]
+        tarr = (C.c_double * len(ts))(*ts)
+        parr = (C.c_void_p * len(ts))(*[o.data_ptr() for o in outs])
+        err = (C.c_double * len(ts))()
+        wp, wb = self._work(work)
+        check(load().wl_expv_ws(self.handle, _ptr(U0), U0.shape[1], tarr, len(ts), parr, int(outer_dim), err, wp, wb))
+        return outs, list(err)
+
     def markov_step(self, X, steps=1, out=None):
         """Distributions held as the columns of X (n x b) after `steps` steps of the
         chain P = diag(w)^{-1} phi (p_{k+1} = p_k P)."""

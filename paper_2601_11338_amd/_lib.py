@@ -12,6 +12,7 @@ WL_M_AUTO, WL_M_RECURRENCE, WL_M_LANCZOS, WL_M_ARNOLDI = 0, 1, 2, 3
 WL_PROBE_GAUSS, WL_PROBE_RADEMACHER = 0, 1
 WL_EST_HUTCHINSON, WL_EST_BKS, WL_EST_XNYS, WL_EST_SURROGATE = 0, 1, 2, 3
 WL_GRAPH_COPY, WL_GRAPH_VALIDATE = 1, 2
+WL_CALL_APPLY_PHI, WL_CALL_APPLY_L, WL_CALL_EXPV = 0, 1, 2
 
 STATUS_NAMES = {
     WL_OK: "WL_OK", WL_EINVAL: "WL_EINVAL", WL_ERANGE: "WL_ERANGE", WL_ENOMEM: "WL_ENOMEM",
@@ -63,6 +64,10 @@ SIGNATURES = {
     "wl_ctx_set_profiling": (C.c_int, [vp, i32]),
     "wl_ctx_kernel_stats": (C.c_int, [vp, i32, C.POINTER(i64), pd, pd]),
     "wl_graph_check_size": (C.c_int, [i64, i64]),
+    "wl_workspace_size": (C.c_int, [vp, i32, i32, i32, C.POINTER(C.c_size_t)]),
+    "wl_apply_phi_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
+    "wl_apply_L_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
+    "wl_expv_ws": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd, vp, C.c_size_t]),
     "wl_graph_create": (C.c_int, [vp, i64, i64, vp, vp, u32, C.POINTER(vp)]),
     "wl_graph_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),
     "wl_graph_destroy": (C.c_int, [vp]),

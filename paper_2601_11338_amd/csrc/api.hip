@@ -29,6 +29,7 @@
 
 // ------------------------------------------------------------------ errors
 static thread_local char g_err[1024] = "";
+thread_local int wl_no_alloc = 0;
 
 void wl_set_error(const char* fmt, ...) {
   va_list ap;
@@ -1287,11 +1288,10 @@ wl_status ensure_w(wl_op* op) {
   wl_graph* g = op->g;
   const int64_t n = g->n;
   WL_TRY(op->w.ensure(std::max<int64_t>(n, 1) * sizeof(T)));
-  DevBuf ones;
+  DevBuf& ones = op->inner_tmp;
   WL_TRY(ones.ensure(std::max<int64_t>(n, 1) * sizeof(T)));
   WL_TRY(launch_fill<T>(g->ctx, n, T(1), ones.as<T>()));
   WL_TRY(phi_apply_impl<T>(op, ones.as<T>(), op->w.as<T>(), 1, nullptr, nullptr));
-  WL_HIP(hipStreamSynchronize(g->ctx->stream));  // ones is freed on return
   op->w_valid = true;
   return WL_OK;
 }
@@ -1429,6 +1429,207 @@ wl_status wl_probes(wl_ctx* ctx, int32_t prec, int32_t law, uint64_t seed, uint3
   DeviceGuard dg(ctx->device);
   if (prec == WL_FP32) return launch_probes<float>(ctx, law, seed, stream, n, M, (float*)d_out);
   return launch_probes<double>(ctx, law, seed, stream, n, M, (double*)d_out);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ caller workspace
+// Every device buffer a call of wl_apply_phi / wl_apply_L / wl_expv touches, with its
+// size, so that the call can run on one caller-provided region instead of library
+// allocations: the plan lists the operator's (and context's) buffers; the scope points
+// them into the region for the duration of the call and restores them afterwards.
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct WsPlan {
+  struct Item {
+    DevBuf* buf;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  bool uses_w = false;
+  void need(DevBuf& b, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    for (auto& it : items)
+      if (it.buf == &b) {
+        it.bytes = std::max(it.bytes, bytes);
+        return;
+      }
+    items.push_back({&b, bytes});
+  }
+  size_t total() const {
+    size_t s = 0;
+    for (const auto& it : items) s += align256(it.bytes);
+    return s;
+  }
+};
+
+size_t elem_size(const wl_op* op) { return op->d.prec == WL_FP32 ? 4 : 8; }
+
+// phi X on a block of width b (phi_apply_impl)
+wl_status plan_phi(wl_op* op, int b, WsPlan& pl) {
+  const int64_t n = op->g->n;
+  if (n == 0) return WL_OK;
+  const size_t s = elem_size(op), blk = (size_t)n * b * s;
+  if (op->d.method == WL_M_ARNOLDI) {
+    wl_set_error("caller workspace: Arnoldi operators are not covered");
+    return WL_EUNSUPPORTED;
+  }
+  if (op->d.method == WL_M_LANCZOS) {
+    const int K = lanczos_steps(op, n, b);
+    pl.need(op->basis, (size_t)(K + 1) * blk);
+    pl.need(op->wbuf, blk);
+    pl.need(op->small, SmallLayout{b, K, (size_t)b * b}.total() * sizeof(double));
+    pl.need(op->coef, (size_t)K * b * b * sizeof(double));
+    // fused steps take Grams of three blocks; full reorthogonalisation of up to K + 1
+    const int nblk = (op->d.reorth > 1 || (int64_t)(K + 1) * b * 2 > n) ? K + 1 : 3;
+    pl.need(op->g->ctx->partials, std::max(gram_partials_bound(n, op->d.prec, b, nblk),
+                                           update_partials_bound(n, op->d.prec, b)));
+    return WL_OK;
+  }
+  if (op->K >= 1) {
+    pl.need(op->bufA, blk);
+    pl.need(op->bufB, blk);
+  }
+  return WL_OK;
+}
+
+// the walk degrees, when the operator has not cached them
+wl_status plan_w(wl_op* op, WsPlan& pl) {
+  if (op->w_valid) return WL_OK;
+  const size_t nb = (size_t)std::max<int64_t>(op->g->n, 1) * elem_size(op);
+  pl.need(op->w, nb);
+  pl.need(op->inner_tmp, nb);
+  pl.uses_w = true;
+  return plan_phi(op, 1, pl);
+}
+
+wl_status plan_call(wl_op* op, int call, int b, int outer_dim, WsPlan& pl) {
+  const int64_t n = op->g->n;
+  switch (call) {
+    case WL_CALL_APPLY_PHI:
+      return plan_phi(op, b, pl);
+    case WL_CALL_APPLY_L:
+      WL_TRY(plan_w(op, pl));
+      return plan_phi(op, b, pl);
+    case WL_CALL_EXPV: {
+      WL_TRY(plan_w(op, pl));
+      if (n == 0) return WL_OK;
+      const int K = (int)std::max<int64_t>(1, std::min<int64_t>(outer_dim, std::max<int64_t>(1, (n + b - 1) / b)));
+      const size_t blk = (size_t)n * b * elem_size(op);
+      pl.need(op->outer_basis, (size_t)(K + 1) * blk);
+      pl.need(op->outer_w, blk);
+      pl.need(op->outer_small, SmallLayout{b, K, (size_t)b * b}.total() * sizeof(double));
+      pl.need(op->outer_coef, (size_t)K * b * b * sizeof(double));
+      pl.need(op->g->ctx->partials, std::max(gram_partials_bound(n, op->d.prec, b, K + 1),
+                                             update_partials_bound(n, op->d.prec, b)));
+      return plan_phi(op, b, pl);  // the inner phi products
+    }
+    default:
+      wl_set_error("wl_workspace_size: unknown call %d", call);
+      return WL_EINVAL;
+  }
+}
+
+// Points the planned buffers into [base, base + total) for its lifetime; allocation is
+// refused meanwhile (a missing plan entry becomes WL_EINTERNAL, never a hipMalloc) and
+// kernel timing is off (it would create events).
+class WsScope {
+ public:
+  WsScope(wl_op* op, const WsPlan& pl, void* base) : op_(op), uses_w_(pl.uses_w) {
+    char* p = static_cast<char*>(base);
+    for (const auto& it : pl.items) {
+      saved_.push_back({it.buf, it.buf->p, it.buf->bytes, it.buf->borrowed});
+      it.buf->p = p;
+      it.buf->bytes = it.bytes;
+      it.buf->borrowed = true;
+      p += align256(it.bytes);
+    }
+    prof_ = op->g->ctx->profiling;
+    op->g->ctx->profiling = false;
+    ++wl_no_alloc;
+  }
+  ~WsScope() {
+    for (auto it = saved_.rbegin(); it != saved_.rend(); ++it) {
+      it->buf->p = it->p;
+      it->buf->bytes = it->bytes;
+      it->buf->borrowed = it->borrowed;
+    }
+    --wl_no_alloc;
+    op_->g->ctx->profiling = prof_;
+    if (uses_w_) op_->w_valid = false;  // the walk degrees lived in the caller's region
+  }
+
+ private:
+  struct Saved {
+    DevBuf* buf;
+    void* p;
+    size_t bytes;
+    bool borrowed;
+  };
+  wl_op* op_;
+  bool uses_w_;
+  bool prof_ = false;
+  std::vector<Saved> saved_;
+};
+
+wl_status ws_check(wl_op* op, int call, int b, int outer_dim, void* d_work, size_t work_bytes, WsPlan& pl,
+                   const char* who) {
+  WL_TRY(plan_call(op, call, b, outer_dim, pl));
+  const size_t need = pl.total();
+  WL_CHECK(need == 0 || d_work, WL_EINVAL, "%s: workspace is null", who);
+  WL_CHECK((reinterpret_cast<uintptr_t>(d_work) & 255u) == 0, WL_EINVAL, "%s: workspace must be 256-byte aligned",
+           who);
+  WL_CHECK(work_bytes >= need, WL_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu bytes needed", who,
+           work_bytes, need);
+  return WL_OK;
+}
+
+}  // namespace
+
+static wl_status phi_ws_call(wl_op* op, const void* d_X, void* d_Y, int32_t b, bool laplacian, void* d_work,
+                             size_t work_bytes) {
+  const char* who = laplacian ? "wl_apply_L_ws" : "wl_apply_phi_ws";
+  WL_TRY(check_block(op, d_X, d_Y, b, who));
+  DeviceGuard dg(op->g->ctx->device);
+  WsPlan pl;
+  WL_TRY(ws_check(op, laplacian ? WL_CALL_APPLY_L : WL_CALL_APPLY_PHI, b, 0, d_work, work_bytes, pl, who));
+  WsScope scope(op, pl, d_work);
+  return laplacian ? wl_apply_L(op, d_X, d_Y, b) : wl_apply_phi(op, d_X, d_Y, b);
+}
+
+extern "C" {
+
+wl_status wl_workspace_size(const wl_op* op, int32_t call, int32_t b, int32_t outer_dim, size_t* bytes) {
+  WL_CHECK(op && bytes, WL_EINVAL, "wl_workspace_size: null argument");
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_workspace_size: b must lie in [1, 64]");
+  WL_CHECK(call != WL_CALL_EXPV || (outer_dim >= 1 && outer_dim <= 1000), WL_EINVAL,
+           "wl_workspace_size: outer_dim out of range");
+  WsPlan pl;
+  WL_TRY(plan_call(const_cast<wl_op*>(op), call, b, outer_dim, pl));
+  *bytes = pl.total();
+  return WL_OK;
+}
+
+wl_status wl_apply_phi_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes) {
+  return phi_ws_call(op, d_X, d_Y, b, false, d_work, work_bytes);
+}
+
+wl_status wl_apply_L_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes) {
+  return phi_ws_call(op, d_X, d_Y, b, true, d_work, work_bytes);
+}
+
+wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
+                     int32_t outer_dim, double* err_est, void* d_work, size_t work_bytes) {
+  WL_CHECK(op, WL_EINVAL, "wl_expv_ws: op is null");
+  WL_CHECK(b >= 1 && b <= 64, WL_EINVAL, "wl_expv_ws: b must lie in [1, 64]");
+  WL_CHECK(outer_dim >= 1 && outer_dim <= 1000, WL_EINVAL, "wl_expv_ws: outer_dim out of range");
+  DeviceGuard dg(op->g->ctx->device);
+  WsPlan pl;
+  WL_TRY(ws_check(op, WL_CALL_EXPV, b, outer_dim, d_work, work_bytes, pl, "wl_expv_ws"));
+  WsScope scope(op, pl, d_work);
+  return wl_expv(op, d_U0, b, t, nt, d_Y, outer_dim, err_est);
 }
 
 }  // extern "C"

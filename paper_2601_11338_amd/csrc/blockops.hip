@@ -1527,6 +1527,27 @@ wl_status launch_nys_diag(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* Y
   return WL_OK;
 }
 
+size_t gram_partials_bound(int64_t n, int prec, int b, int nblk) {
+  const int64_t B = pick_B(b), E = B * B;
+  nblk = std::max(nblk, 1);
+  int64_t doubles = 0;
+  // matrix-core Gram (FP32, B >= 16): one partial per workgroup, at most 1024
+  const int64_t mfma_parts = std::min<int64_t>(1024, std::max<int64_t>(1, ((n + 15) / 16 + 15) / 16));
+  if (prec == WL_FP32 && B >= 16) doubles = std::max(doubles, mfma_parts * nblk * E);
+  // single-column dot products: at most 1024 partials per block
+  if (B == 1) doubles = std::max<int64_t>(doubles, 1024 * nblk);
+  // general tiles: parts * nblk * E <= max(2^22, 32 nblk E)
+  doubles = std::max<int64_t>(doubles, std::max<int64_t>((int64_t)1 << 22, 32 * nblk * E));
+  return (size_t)doubles * sizeof(double);
+}
+
+size_t update_partials_bound(int64_t n, int prec, int b) {
+  const int64_t B = pick_B(b), E = B * B;
+  int64_t doubles = std::max<int64_t>(1024 * 256, 512 * E);  // matrix-core update / general tiles
+  doubles = std::max<int64_t>(doubles, (int64_t)gram_partials_bound(n, prec, b, 1) / (int64_t)sizeof(double));
+  return (size_t)doubles * sizeof(double);
+}
+
 #define WL_INST(T)                                                                                                   \
   template wl_status launch_gram<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const T*, int, double*);        \
   template wl_status launch_update<T>(wl_ctx*, int64_t, const T*, int, int64_t, int, const double*, const T*,      \

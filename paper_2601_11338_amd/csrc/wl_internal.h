@@ -53,25 +53,35 @@ struct DeviceGuard {
 };
 
 // ------------------------------------------------------------------ device buffer
+// Nonzero while a call runs on caller-provided workspace: no buffer may then grow (a
+// growth would be a device allocation the caller asked not to happen).
+extern thread_local int wl_no_alloc;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // p points into caller workspace (never freed here)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
     // work still queued may read the old allocation: drain the device first
-    if (p) {
+    if (p && !borrowed) {
       (void)hipDeviceSynchronize();
       (void)hipFree(p);
     }
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   // Grow to at least nbytes (contents not preserved).
   wl_status ensure(size_t nbytes) {
     if (nbytes <= bytes && p) return WL_OK;
+    if (borrowed || wl_no_alloc) {
+      wl_set_error("workspace plan too small: a buffer of %zu bytes was needed (internal)", nbytes);
+      return WL_EINTERNAL;
+    }
     release();
     size_t want = nbytes < 256 ? 256 : nbytes;
     hipError_t e = hipMalloc(&p, want);
@@ -430,6 +440,12 @@ wl_status launch_wpow(wl_ctx* ctx, int64_t n, const T* x, int mode, T* out);
 // out = x / *den with den one device double
 template <typename T>
 wl_status launch_div_by(wl_ctx* ctx, int64_t n, const T* x, const double* den, T* out);
+
+// Upper bounds (bytes) of the reduction partials one Gram of nblk blocks of width b
+// against a block of width b, or one block update of width b with its Gram, may use
+// in ctx->partials (they follow the launch shapes of launch_gram / launch_update).
+size_t gram_partials_bound(int64_t n, int prec, int b, int nblk);
+size_t update_partials_bound(int64_t n, int prec, int b);
 
 // ------------------------------------------------------------------ drivers
 template <typename T>

@@ -41,6 +41,12 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def node_rel(a, b, mag):
+    """Largest error of any node against that node's magnitude (phi >= 0 entrywise, so
+    for Rademacher columns |(phi X)_ij| <= (phi 1)_i = w_i)."""
+    return float(np.max(np.abs(a - b) / np.asarray(mag)[:, None]))
+
+
 @pytest.mark.parametrize("mu", [0.0, 0.5, 1.0])
 def test_series_block16_full_size(ctx, lib, ba1m, mu):
     n, rp, ci, As = ba1m
@@ -55,9 +61,13 @@ def test_series_block16_full_size(ctx, lib, ba1m, mu):
     cols = [0, 7, 15]
     ref = sparse.series_apply(As, mu, coeffs, X[:, cols])
     assert rel(PX[:, cols], ref) < 2e-5
+    w = host(op.fdeg())
+    wr = sparse.series_apply(As, mu, coeffs, np.ones((n, 1)))[:, 0]
+    ew, ep = float(np.max(np.abs(w - wr) / wr)), node_rel(PX[:, cols], ref, wr)
+    print(f"[gpu] per-node errors: w {ew:.1e}, phi X {ep:.1e}", flush=True)
+    assert ew < 2e-5 and ep < 1e-4
     # L 1 = 0 at full size
     ones = torch.ones((n, 1), dtype=torch.float32, device="cuda")
-    w = host(op.fdeg())
     L1 = host(op.apply_L(ones))
     assert np.abs(L1).max() < 1e-5 * np.abs(w).max()
 
@@ -75,6 +85,11 @@ def test_resolvent_lanczos_block16_full_size(ctx, lib, ba1m):
     cols = [2, 11]
     ref = sparse.phi_res_apply(As, 0.5, alpha, X[:, cols], rtol=1e-12)
     assert rel(PX[:, cols], ref) < 2e-5
+    w = host(op.fdeg())
+    wr = sparse.phi_res_apply(As, 0.5, alpha, np.ones((n, 1)), rtol=1e-12)[:, 0]
+    ew, ep = float(np.max(np.abs(w - wr) / wr)), node_rel(PX[:, cols], ref, wr)
+    print(f"[gpu] per-node errors: w {ew:.1e}, phi X {ep:.1e}", flush=True)
+    assert ew < 2e-5 and ep < 1e-4
 
 
 def test_markov_chain_full_size(ctx, lib, ba1m):

@@ -43,6 +43,16 @@ def rel(a, b, scale=None):
     return np.linalg.norm(a - b) / max(s, 1e-300)
 
 
+def node_rel(a, b, mag):
+    """Largest error of any node (and column) against that node's magnitude mag (n, or
+    n x b): the norm-wise checks alone would let hub rows hide errors on the many
+    low-degree nodes."""
+    mag = np.asarray(mag, dtype=np.float64)
+    if mag.ndim == 1 and np.ndim(a) == 2:
+        mag = mag[:, None]
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(mag, 1e-300)))
+
+
 # ------------------------------------------------------------------ SpMM
 def spmm_graphs():
     star_iso = synth.csr_from_edges(3000, np.zeros(2500, dtype=np.int64), np.arange(1, 2501))  # hub + isolated
@@ -118,6 +128,11 @@ def test_fp64_variants_match_dense(ctx, wl, mu, kind):
     assert rel(PX, ph @ X) < 1e-8
     scale = np.linalg.norm(wr[:, None] * X) + np.linalg.norm(ph @ X)
     assert rel(LX, laplacian.apply_laplacian(ph, X), scale) < 1e-8
+    # per node: w against itself, phi X against |phi| |X| (the size of the sum it is)
+    mag = np.abs(ph) @ np.abs(X)
+    assert node_rel(w, wr, wr) < 1e-8
+    assert node_rel(PX, ph @ X, mag) < 1e-8
+    assert node_rel(LX, laplacian.apply_laplacian(ph, X), np.abs(wr)[:, None] * np.abs(X) + mag) < 1e-8
 
 
 def test_mu0_exponential_lanczos_matches_dense(ctx, wl):
@@ -183,6 +198,12 @@ def test_fp32_block16_k30_matches_oracle(ctx, wl, ba_mid, mu, kind):
     assert rel(PX, pr) < 2e-5
     scale = np.linalg.norm(wr[:, None] * X) + np.linalg.norm(pr)
     assert rel(LX, wr[:, None] * X - pr, scale) < 2e-5
+    # per node: phi >= 0 entrywise (weights and walk counts are nonnegative), so for
+    # Rademacher X the size of (phi X)_ij is at most (phi |X|)_i = w_i, and of (L X)_ij
+    # at most 2 w_i
+    ew, ep, el = node_rel(w, wr, wr), node_rel(PX, pr, wr), node_rel(LX, wr[:, None] * X - pr, 2 * wr)
+    print(f"[gpu] per-node errors: w {ew:.1e}, phi X {ep:.1e}, L X {el:.1e}", flush=True)
+    assert ew < 2e-5 and ep < 1e-4 and el < 1e-4
 
 
 # ------------------------------------------------------------------ spectral scale
