@@ -66,10 +66,16 @@ typedef enum {
   WL_M_AUTO = 0,        /* exponential: recurrence; resolvent: block Lanczos on A_mu */
   WL_M_RECURRENCE = 1,  /* truncated series by the fused three-term recurrence (exponential) */
   WL_M_LANCZOS = 2,     /* block Lanczos (mu = 0: on A; resolvent: on A_mu(alpha)) */
-  WL_M_ARNOLDI = 3      /* exponential, any mu: block Arnoldi on the 2n x 2n linearisation Z
+  WL_M_ARNOLDI = 3,     /* exponential, any mu: block Arnoldi on the 2n x 2n linearisation Z
                            (eq. Zdef), phi X = X + [I O] beta phi_1(beta Z) [q_1 X; q_2 X]
                            (Prop. "whe-we-converge"); krylov_dim Arnoldi steps (required).
                            For beta rho(Z) large, where the series degree grows with it. */
+  WL_M_AMG_CG = 4       /* resolvent, WL_FP64: phi X = (1 - mu^2 alpha^2) A_mu(alpha)^{-1} X by
+                           conjugate gradients on the deformed Laplacian (eq. deformed, an
+                           M-matrix) preconditioned with an aggregation multigrid V-cycle
+                           (Sec. 4.2; see wl_amg_info); tol = relative residual of every
+                           column (0: 1e-9, Sec. 5.3), krylov_dim = iteration limit (0: 1000;
+                           WL_ENOCONV beyond it). */
 } wl_method;
 typedef enum { WL_PROBE_GAUSS = 0, WL_PROBE_RADEMACHER = 1 } wl_probe_law;
 typedef enum {
@@ -139,7 +145,8 @@ wl_status wl_ctx_destroy(wl_ctx* ctx);
  * profiling on or off clears the statistics.  Classes: 0 fused recurrence step of one
  * operator (degree >= 2, b >= 4), 1 block Lanczos operator product (b >= 4), 2 other
  * sparse products, 3 side-by-side series step (wl_multi_*, width >= 32), 4 side-by-side
- * Lanczos operator product (wl_multi_*, width >= 32).  Batched steps count as class 0. */
+ * Lanczos operator product (wl_multi_*, width >= 32), 5 finest-level products of the
+ * multigrid-preconditioned CG (WL_M_AMG_CG).  Batched steps count as class 0.           */
 wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on);
 wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launches, double* total_ms,
                               double* alg_bytes);
@@ -251,6 +258,44 @@ wl_status wl_apply_phi_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void
 wl_status wl_apply_L_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes);
 wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
                      int32_t outer_dim, double* err_est, void* d_work, size_t work_bytes);
+
+/* ---------------------------------------------------------------- multigrid-preconditioned CG
+ * The hierarchy of a WL_M_AMG_CG operator (Sec. 4.2), built on the host when the
+ * operator is created:
+ *  - strong couplings j != i with |a_ij| >= theta sqrt(a_ii a_jj), theta = 0.01;
+ *  - Vanek-Mandel-Brezina aggregation over the nodes that have a strong neighbour:
+ *    roots whose strong neighbourhoods are wholly free (in node order), then every free
+ *    node joins the aggregate of its most strongly coupled aggregated neighbour, then
+ *    leftovers group with their free strong neighbours;
+ *  - smoothed prolongator P = (I - omega D^-1 A) P_t, P_t the unit-norm piecewise
+ *    constants, omega = 4 / (3 ||D^-1 A||_inf); Galerkin coarse matrix P^T A P;
+ *  - levels while the coarse size stays below 0.9 of the fine one and the fine level
+ *    has more than 256 rows (at most 20);
+ *  - V-cycle: one l1-Jacobi sweep (M = diag(sum_j |a_ij|)) before and after the coarse
+ *    correction, 30 sweeps on the coarsest level; CG on every column from zero, stopped
+ *    when every column's residual is within tol of its right-hand side's norm.
+ * wl_amg_info: the hierarchy (rows and stored entries per level; level 0 counts the
+ * graph's nonzeros plus the diagonal), operator complexity (entries over all levels /
+ * level 0), setup time, and for the last solve its iterations and largest relative
+ * residual; products: sum of entries x columns over every sparse product so far.
+ * wl_amg_describe (host only, no device): the same hierarchy for a host CSR graph and
+ * (mu, alpha): level count, rows and entries per level (arrays of max_levels), and the
+ * aggregate of every node on the finest level (n int32, -1: no strong neighbour; may be
+ * NULL), for inspection and tests.                                                    */
+#define WL_AMG_MAX_LEVELS 20
+typedef struct {
+  int32_t levels;
+  int64_t rows[WL_AMG_MAX_LEVELS];
+  int64_t nnz[WL_AMG_MAX_LEVELS];
+  double operator_complexity;
+  double setup_ms;
+  int32_t iterations;
+  double rel_residual;
+  double products;
+} wl_amg_stats;
+wl_status wl_amg_info(const wl_op* op, wl_amg_stats* out);
+wl_status wl_amg_describe(int64_t n, const int32_t* rowptr, const int32_t* colidx, double mu, double alpha,
+                          int32_t max_levels, int32_t* levels, int64_t* rows, int64_t* nnz, int32_t* agg0);
 
 /* ---------------------------------------------------------------- discrete-time diffusion
  * The Markov chain of a walk Laplacian (Sec. "Simulating discrete-time diffusion",

@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     WL_F_RESOLVENT,
     WL_FP32,
     WL_FP64,
+    WL_M_AMG_CG,
     WL_M_ARNOLDI,
     WL_M_AUTO,
     WL_M_LANCZOS,
@@ -33,7 +34,8 @@ from ._lib import (  # noqa: F401
 
 FUNCS = {"res": WL_F_RESOLVENT, "resolvent": WL_F_RESOLVENT, "exp": WL_F_EXP, "exponential": WL_F_EXP,
          "linear": WL_F_LINEAR}
-METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS, "arnoldi": WL_M_ARNOLDI}
+METHODS = {"auto": WL_M_AUTO, "recurrence": WL_M_RECURRENCE, "lanczos": WL_M_LANCZOS, "arnoldi": WL_M_ARNOLDI,
+           "amg": WL_M_AMG_CG}
 ESTIMATORS = {"hutchinson": WL_EST_HUTCHINSON, "bks": WL_EST_BKS, "xnys": WL_EST_XNYS,
               "surrogate": WL_EST_SURROGATE}
 LAWS = {"gauss": WL_PROBE_GAUSS, "gaussian": WL_PROBE_GAUSS, "rademacher": WL_PROBE_RADEMACHER}
@@ -272,6 +274,15 @@ class Operator:
         check(load().wl_expv(self.handle, _ptr(U0), U0.shape[1], tarr, len(ts), parr, int(outer_dim), err))
         return outs, list(err)
 
+    def amg_info(self):
+        """Hierarchy and last-solve figures of a multigrid-preconditioned CG operator."""
+        st = _lib.AmgStats()
+        check(load().wl_amg_info(self.handle, C.byref(st)))
+        L = st.levels
+        return {"levels": L, "rows": list(st.rows[:L]), "nnz": list(st.nnz[:L]),
+                "operator_complexity": st.operator_complexity, "setup_ms": st.setup_ms,
+                "iterations": st.iterations, "rel_residual": st.rel_residual, "products": st.products}
+
     # ---- caller workspace (no device allocation inside the call)
     CALLS = {"apply_phi": _lib.WL_CALL_APPLY_PHI, "apply_L": _lib.WL_CALL_APPLY_L, "expv": _lib.WL_CALL_EXPV}
 
@@ -466,6 +477,21 @@ def exp_poles(xmax, tol=1e-13, mmax=100):
     npoles, err = C.c_int32(), C.c_double()
     st = load().wl_exp_poles(float(xmax), float(tol), int(mmax), _dptr(pol), cap, C.byref(npoles), C.byref(err))
     return _poles_out(st, pol, npoles, cap), err.value
+
+
+def amg_describe(n, rowptr, colidx, mu, alpha, max_levels=20):
+    """Host-only view of the multigrid hierarchy for a CSR graph (numpy int32 arrays):
+    (rows per level, entries per level, finest-level aggregates)."""
+    import numpy as np
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(colidx, dtype=np.int32)
+    lv = C.c_int32()
+    rows = (C.c_int64 * max_levels)()
+    nnz = (C.c_int64 * max_levels)()
+    agg = np.empty(int(n), dtype=np.int32)
+    check(load().wl_amg_describe(int(n), rp.ctypes.data, ci.ctypes.data, float(mu), float(alpha), int(max_levels),
+                                 C.byref(lv), rows, nnz, agg.ctypes.data))
+    return list(rows[:lv.value]), list(nnz[:lv.value]), agg
 
 
 def probes(ctx, n, M, seed, law="gauss", dtype=None, stream=0):

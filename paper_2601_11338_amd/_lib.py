@@ -8,7 +8,8 @@ LIBPATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwalklap.s
 WL_OK, WL_EINVAL, WL_ERANGE, WL_ENOMEM, WL_EDEVICE, WL_ENOTSPD, WL_ENOCONV, WL_ENUMERIC, WL_EUNSUPPORTED = range(9)
 WL_F_RESOLVENT, WL_F_EXP, WL_F_LINEAR = 0, 1, 2
 WL_FP32, WL_FP64 = 4, 8
-WL_M_AUTO, WL_M_RECURRENCE, WL_M_LANCZOS, WL_M_ARNOLDI = 0, 1, 2, 3
+WL_M_AUTO, WL_M_RECURRENCE, WL_M_LANCZOS, WL_M_ARNOLDI, WL_M_AMG_CG = 0, 1, 2, 3, 4
+WL_AMG_MAX_LEVELS = 20
 WL_PROBE_GAUSS, WL_PROBE_RADEMACHER = 0, 1
 WL_EST_HUTCHINSON, WL_EST_BKS, WL_EST_XNYS, WL_EST_SURROGATE = 0, 1, 2, 3
 WL_GRAPH_COPY, WL_GRAPH_VALIDATE = 1, 2
@@ -31,6 +32,19 @@ class RkInfo(C.Structure):
         ("rho", C.c_double),
         ("aaa_err", C.c_double),
         ("solve_res", C.c_double),
+        ("products", C.c_double),
+    ]
+
+
+class AmgStats(C.Structure):
+    _fields_ = [
+        ("levels", C.c_int32),
+        ("rows", C.c_int64 * WL_AMG_MAX_LEVELS),
+        ("nnz", C.c_int64 * WL_AMG_MAX_LEVELS),
+        ("operator_complexity", C.c_double),
+        ("setup_ms", C.c_double),
+        ("iterations", C.c_int32),
+        ("rel_residual", C.c_double),
         ("products", C.c_double),
     ]
 
@@ -67,6 +81,8 @@ SIGNATURES = {
     "wl_workspace_size": (C.c_int, [vp, i32, i32, i32, C.POINTER(C.c_size_t)]),
     "wl_apply_phi_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
     "wl_apply_L_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
+    "wl_amg_info": (C.c_int, [vp, C.POINTER(AmgStats)]),
+    "wl_amg_describe": (C.c_int, [i64, vp, vp, f64, f64, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), vp]),
     "wl_expv_ws": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd, vp, C.c_size_t]),
     "wl_graph_create": (C.c_int, [vp, i64, i64, vp, vp, u32, C.POINTER(vp)]),
     "wl_graph_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32)]),

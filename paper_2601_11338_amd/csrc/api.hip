@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "wl_internal.h"
+#include "wl_amg.h"
 
 // ------------------------------------------------------------------ errors
 static thread_local char g_err[1024] = "";
@@ -866,6 +867,7 @@ wl_status phi_apply_impl(wl_op* op, const T* X, T* Y, int b, const T* wv, const 
   if (op->g->n == 0) return WL_OK;
   if (op->d.method == WL_M_LANCZOS) return phi_lanczos<T>(op, X, Y, b, wv, Xw);
   if (op->d.method == WL_M_ARNOLDI) return phi_arnoldi<T>(op, X, Y, b, wv, Xw);
+  if (op->d.method == WL_M_AMG_CG) return phi_amg<T>(op, X, Y, b, wv, Xw);
   return phi_recurrence<T>(op, X, Y, b, wv, Xw);
 }
 
@@ -1197,7 +1199,9 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   WL_CHECK(d->prec == WL_FP32 || d->prec == WL_FP64, WL_EINVAL, "wl_op_create: prec must be WL_FP32 or WL_FP64");
   WL_CHECK(d->krylov_dim >= 0 && d->krylov_dim <= 2000, WL_EINVAL, "wl_op_create: krylov_dim out of range");
   WL_CHECK(is_finite(d->tol) && d->tol >= 0.0, WL_EINVAL, "wl_op_create: bad tol");
-  WL_CHECK(d->method >= WL_M_AUTO && d->method <= WL_M_ARNOLDI, WL_EINVAL, "wl_op_create: unknown method");
+  WL_CHECK(d->method >= WL_M_AUTO && d->method <= WL_M_AMG_CG, WL_EINVAL, "wl_op_create: unknown method");
+  WL_CHECK(d->method != WL_M_AMG_CG || (d->func == WL_F_RESOLVENT && d->prec == WL_FP64), WL_EUNSUPPORTED,
+           "wl_op_create: the multigrid-preconditioned CG solves resolvent systems in double precision");
   WL_CHECK(d->method != WL_M_ARNOLDI || d->func == WL_F_EXP, WL_EUNSUPPORTED,
            "wl_op_create: the Arnoldi method evaluates exponential weights only");
   WL_CHECK(d->method != WL_M_ARNOLDI || d->krylov_dim > 0, WL_EINVAL,
@@ -1223,6 +1227,7 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   double lam_exp = 0.0;  // lambda_max(A) for exponential weights (series scaling, degree)
   if (d->func == WL_F_EXP) WL_TRY(wl_lambda_max(g, 1e-10, &lam_exp));
   int K = d->func == WL_F_LINEAR ? 1 : d->krylov_dim;
+  if (method == WL_M_AMG_CG && K == 0) K = 1000;  // iteration limit
   if (K == 0) {
     const double tol = d->tol > 0 ? d->tol : 1e-12;
     if (d->func == WL_F_EXP) {
@@ -1257,6 +1262,15 @@ wl_status wl_op_create(wl_graph* g, const wl_op_desc* d, wl_op** out) {
   op->rho = rho;
   op->lam = lam_exp;
   op->K = K;
+  if (method == WL_M_AMG_CG) {
+    const wl_status s = amg_setup(op);
+    if (s != WL_OK) {
+      amg_destroy(op);
+      delete op;
+      graph_release(g);
+      return s;
+    }
+  }
   *out = op;
   return WL_OK;
 }
@@ -1274,6 +1288,7 @@ wl_status wl_op_destroy(wl_op* op) {
   {
     DeviceGuard dg(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
+    amg_destroy(op);
     delete op;
   }
   graph_release(g);
@@ -1472,8 +1487,8 @@ wl_status plan_phi(wl_op* op, int b, WsPlan& pl) {
   const int64_t n = op->g->n;
   if (n == 0) return WL_OK;
   const size_t s = elem_size(op), blk = (size_t)n * b * s;
-  if (op->d.method == WL_M_ARNOLDI) {
-    wl_set_error("caller workspace: Arnoldi operators are not covered");
+  if (op->d.method == WL_M_ARNOLDI || op->d.method == WL_M_AMG_CG) {
+    wl_set_error("caller workspace: Arnoldi and multigrid operators are not covered");
     return WL_EUNSUPPORTED;
   }
   if (op->d.method == WL_M_LANCZOS) {

@@ -1536,14 +1536,22 @@ size_t gram_partials_bound(int64_t n, int prec, int b, int nblk) {
   if (prec == WL_FP32 && B >= 16) doubles = std::max(doubles, mfma_parts * nblk * E);
   // single-column dot products: at most 1024 partials per block
   if (B == 1) doubles = std::max<int64_t>(doubles, 1024 * nblk);
-  // general tiles: parts * nblk * E <= max(2^22, 32 nblk E)
-  doubles = std::max<int64_t>(doubles, std::max<int64_t>((int64_t)1 << 22, 32 * nblk * E));
+  // general tiles: one partial per 32-row tile, at most clamp(2^22 / (E nblk), 32, 512)
+  const int64_t ntiles = std::max<int64_t>(1, (n + GRAM_TR - 1) / GRAM_TR);
+  const int64_t cap = std::min<int64_t>(512, std::max<int64_t>(32, ((int64_t)1 << 22) / (E * nblk)));
+  doubles = std::max<int64_t>(doubles, std::min(ntiles, cap) * nblk * E);
   return (size_t)doubles * sizeof(double);
 }
 
 size_t update_partials_bound(int64_t n, int prec, int b) {
   const int64_t B = pick_B(b), E = B * B;
-  int64_t doubles = std::max<int64_t>(1024 * 256, 512 * E);  // matrix-core update / general tiles
+  // matrix-core update with its Gram (FP32, 16 wide): one 256-value partial per workgroup
+  const int64_t mfma_grid = std::min<int64_t>(1024, std::max<int64_t>(1, ((n + 15) / 16 + 15) / 16));
+  int64_t doubles = (prec == WL_FP32 && B == 16) ? mfma_grid * 256 : 0;
+  doubles = std::max<int64_t>(doubles, 512);  // single-column updates
+  // general tiles with the Gram: one partial per 256-row tile, at most 512
+  doubles = std::max<int64_t>(doubles, std::min<int64_t>(512, std::max<int64_t>(1, (n + 255) / 256)) * E);
+  // updates that take a separate Gram of their output
   doubles = std::max<int64_t>(doubles, (int64_t)gram_partials_bound(n, prec, b, 1) / (int64_t)sizeof(double));
   return (size_t)doubles * sizeof(double);
 }

@@ -361,7 +361,8 @@ wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out) {
   wl_graph* g = ops[0]->g;
   const int prec = ops[0]->d.prec;
   const int method = ops[0]->d.method;
-  WL_CHECK(method != WL_M_ARNOLDI, WL_EUNSUPPORTED, "wl_multi_create: Arnoldi operators are evaluated alone");
+  WL_CHECK(method != WL_M_ARNOLDI && method != WL_M_AMG_CG, WL_EUNSUPPORTED,
+           "wl_multi_create: Arnoldi and multigrid operators are evaluated alone");
   for (int i = 0; i < nops; ++i) {
     WL_CHECK(ops[i]->g == g, WL_EINVAL, "wl_multi_create: operators must share one graph");
     WL_CHECK(ops[i]->d.prec == prec, WL_EINVAL, "wl_multi_create: operators must share one precision");

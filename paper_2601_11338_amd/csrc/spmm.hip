@@ -193,6 +193,11 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
       Frag<T, VW> xw = (MASK && VW == 1) ? ldf_m<T, VW, MASK>(ep.Xw + off, true) : ldf_nt<T, VW>(ep.Xw + off);
 #pragma unroll
       for (int i = 0; i < VW; ++i) s.v[i] = wr * xw.v[i] - s.v[i];
+    } else if (ep.jw) {
+      const T jr = ep.jw[r];
+      Frag<T, VW> xj = (MASK && VW == 1) ? ldf_m<T, VW, MASK>(ep.jx + off, true) : ldf_nt<T, VW>(ep.jx + off);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) s.v[i] = xj.v[i] + jr * s.v[i];
     }
     if constexpr (MASK && VW == 1) {
       ep.Sout[off] = s.v[0];
@@ -375,8 +380,9 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     // algorithmic bytes: CSR once, the gathered block once (compulsory), every row stream once
     const double s = sizeof(T), nb = (double)g->n * b;
     int streams = 1 + (Y ? 1 : 0) + (ep.Z ? 1 : 0) + (ep.C ? 1 : 0) + (ep.Sin ? 1 : 0) + (ep.Sout ? 1 : 0) +
-                  (ep.Xw ? 1 : 0);
-    ks->bytes += 4.0 * g->nnz + 4.0 * (g->n + 1) + s * nb * streams + (ep.wv ? s * g->n : 0.0);
+                  (ep.Xw ? 1 : 0) + (ep.jx ? 1 : 0);
+    ks->bytes += 4.0 * g->nnz + 4.0 * (g->n + 1) + s * nb * streams + (ep.wv ? s * g->n : 0.0) +
+                 (ep.jw ? s * g->n : 0.0);
   }
   return WL_OK;
 }
@@ -412,7 +418,8 @@ wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep
   if (g->n == 0) return WL_OK;
   constexpr int VW = vec_width<T>();
   const bool vec_ok = (b % VW == 0) && (!ep.ctab || ep.cgw % VW == 0) && aligned16(X) && aligned16(Y) &&
-                      aligned16(ep.Z) && aligned16(ep.Sin) && aligned16(ep.Sout) && aligned16(ep.Xw);
+                      aligned16(ep.Z) && aligned16(ep.Sin) && aligned16(ep.Sout) && aligned16(ep.Xw) &&
+                      aligned16(ep.jx);
   if (vec_ok) {
     const int lanes = b / VW;  // lanes needed for the whole row segment
     if (lanes == 1) return run_g<T, VW, 1, false>(g, X, Y, b, ep, sh.G, sh.long_thr);

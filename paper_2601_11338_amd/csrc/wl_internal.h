@@ -108,7 +108,7 @@ struct SpmmShape {
 // Timing classes of sparse products: single-operator series steps (b >= 4), Lanczos
 // operator products (b >= 4), side-by-side operator steps (width >= 32), the rest.
 enum { WL_KC_RECURRENCE = 0, WL_KC_LANCZOS_OP = 1, WL_KC_OTHER_SPMM = 2, WL_KC_MULTI = 3, WL_KC_MULTI_LANCZOS = 4,
-       WL_KC_COUNT = 5 };
+       WL_KC_AMG = 5, WL_KC_COUNT = 6 };
 struct KernelStats {
   int64_t launches = 0;
   double bytes = 0.0;
@@ -169,6 +169,7 @@ struct wl_op {
   // discrete-time diffusion scratch, kept between calls (freeing a buffer waits for the
   // whole device, which would serialise work on other streams)
   DevBuf mk_rw, mk_tmp, mk_alt, mk_x0, mk_t1, mk_t2, mk_dd;
+  struct AmgState* amg = nullptr;  // WL_M_AMG_CG: multigrid hierarchy and CG work blocks
 };
 
 // ------------------------------------------------------------------ launch interfaces
@@ -177,6 +178,7 @@ struct wl_op {
 //   Y[r]     = y                                                       (if Y)
 //   Sout[r]  = s0 * Sin[r] + sc * y                                    (if Sout; Sin optional)
 //   if wv:     Sout[r] = wv[r] * Xw[r] - Sout[r]                       (walk-Laplacian finish)
+//   if jw:     Sout[r] = jx[r] + jw[r] * Sout[r]                       (Jacobi sweep finish)
 // C is b x b row-major double on the device (transC: use C^T).
 template <typename T>
 struct EpiArgs {
@@ -191,6 +193,9 @@ struct EpiArgs {
   double s0 = 0.0, sc = 0.0;
   const T* wv = nullptr;
   const T* Xw = nullptr;
+  // Jacobi finish (instead of the walk-Laplacian one): Sout[r] = jx[r] + jw[r] * Sout[r]
+  const T* jw = nullptr;
+  const T* jx = nullptr;
   int kclass = WL_KC_OTHER_SPMM;  // timing class when profiling is on
   // Batched graphs: row r belongs to graph gid[r]; gtab holds, per graph, the five
   // coefficients {a, b0, b1, sc, fin} of this launch (replacing a, b0, b1, sc; fin != 0

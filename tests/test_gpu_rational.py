@@ -214,3 +214,44 @@ def test_standard_laplacian(ctx, lib):
     compare(lib, op, Lap, Om, [0.0, 0.2, 2.0, 20.0], 20.0, torch.float64, 1e-7, 1e-6)
     with pytest.raises(lib.WLError):
         lib.Operator(g, 0.0, "linear", 1.0, dtype=torch.float64, method="lanczos")
+
+
+@pytest.mark.parametrize("mu,kind,dtype", [(0.5, "exp", "f64"), (1.0, "res", "f64"), (0.5, "exp", "f32"),
+                                          (1.0, "res", "f32")])
+def test_pole_independent_estimates(ctx, lib, mu, kind, dtype):
+    """Each side builds its own AAA poles (the library on the device path, the oracle
+    with LAPACK), so the check does not depend on the library's poles:
+      * each p_hat(t) lies within 5 e_hat(t) of the exact tr exp(-t L) / n (Alg. 1
+        returns the estimate with its error estimate);
+      * the two estimates agree with each other: both spaces reproduce exp(-t L) Omega
+        to ~1e-10 on these graphs (measured with the oracle against the exact
+        exp(-t L) Omega), so the bound is that of the shifted solves and the vector
+        precision: FP64 1e-8 relative, FP32 2e-4 relative plus 1e-6 of the largest."""
+    print(f"[gpu] return_prob pole-independent mu={mu} {kind} {dtype}", flush=True)
+    n = 400
+    rp, ci, A = ba(n, 3, 5)
+    if kind == "exp":
+        param = 1.0 / np.linalg.eigvalsh(A)[-1]
+        method, kd = "auto", 0
+    else:
+        param = 1.0 / (1.0 + walks.spectral_radius(walks.linearisation(A, mu)))
+        method, kd = "lanczos", 60
+    td = torch.float64 if dtype == "f64" else torch.float32
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, mu, kind, param, dtype=td, krylov_dim=kd, method=method,
+                      tol=1e-15 if dtype == "f64" else 1e-9)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, mu, kind, param))
+    Om = synth.gaussian_block(n, 8, seed=3)
+    ts = [0.0, 0.1, 1.0, 5.0, 10.0]
+    rho = np.linalg.eigvalsh(Lap).max()
+    solve_tol = 1e-12 if dtype == "f64" else 1e-6
+    p, e, poles_lib, info = op.return_prob(dev(Om, td), ts, 10.0, rho=rho, solve_tol=solve_tol, max_iters=2000)
+    po, eo, poles_orc = rational.return_probability_estimate(Lap, Om, ts, 10.0, rho)
+    exact = rational.exact_return_probability(Lap, ts)
+    print(f"[gpu] poles: library {poles_lib.size}, oracle {poles_orc.size}; "
+          f"|p - exact| / e_hat: {np.round(np.abs(p - exact) / e, 2)}", flush=True)
+    assert np.all(np.abs(p - exact) <= 5 * e) and np.all(np.abs(po - exact) <= 5 * eo)
+    if dtype == "f64":
+        np.testing.assert_allclose(p, po, rtol=1e-8, atol=0)
+    else:
+        np.testing.assert_allclose(p, po, rtol=2e-4, atol=1e-6 * np.abs(po).max())
