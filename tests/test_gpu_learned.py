@@ -94,9 +94,19 @@ def test_mlp_save_load_roundtrip(ctx, lib, tmp_path):
 
 
 def test_training_reduces_loss_and_cv_helps(ctx, lib):
-    """Train on exact diagonals of a few small graphs; the control variate then lowers
-    the Gaussian-probe diagonal error on a held-out graph (the pass criterion of the
-    learned part at a small scale)."""
+    """Train on exact diagonals of a few small graphs, then estimate diag phi on a
+    held-out graph with 16 Gaussian probes (mean error over 10 seeds, normalised by
+    ||diag phi - 1||) with: plain Hutchinson, the learned control variate, the trivial
+    control variate g = 1, the exact diagonal as control variate (the best any diagonal
+    predictor can do), BKS and Rademacher probes.
+      * Against plain Gaussian Hutchinson the learned control variate gains more than 2x
+        in error (4x in probes: the pass criterion of the learned part).
+      * That gain is the trivial one: g = 1 removes the same omega_i^2 fluctuation.  A
+        diagonal control variate leaves the off-diagonal noise sum_k F_ik^2, which
+        dominates here, so even the exact diagonal is within 10 % of g = 1, and the
+        learned network is no worse than g = 1 (within 5 %).  At these weights no learned
+        gain exists over the best estimator without it (BKS and Rademacher are at the
+        level of g = 1; the errors are printed)."""
     feats, targs = [], []
     for seed in range(6):
         n = 1500
@@ -125,13 +135,23 @@ def test_training_reduces_loss_and_cv_helps(ctx, lib):
     ph = genfun.phi(A, 0.0, "res", alpha)
     d = np.diag(ph)
     ghat = net.forward(g.features(alpha)).cpu().numpy().astype(np.float64) + 1.0
-    errs_plain, errs_cv = [], []
+    errs = {k: [] for k in ("plain", "learned", "const", "exact", "bks", "rademacher")}
+    den = np.linalg.norm(d - 1)
     for s in range(10):
         Om = philox.gaussian(n, 16, 500 + s)
         Y = ph @ Om
-        errs_plain.append(np.linalg.norm(estimators.hutchinson_diag(Om, Y) - d) / np.linalg.norm(d - 1))
-        errs_cv.append(np.linalg.norm(estimators.cv_diag(Om, Y, ghat) - d) / np.linalg.norm(d - 1))
-    assert np.mean(errs_cv) < 0.5 * np.mean(errs_plain)
+        errs["plain"].append(np.linalg.norm(estimators.hutchinson_diag(Om, Y) - d) / den)
+        errs["learned"].append(np.linalg.norm(estimators.cv_diag(Om, Y, ghat) - d) / den)
+        errs["const"].append(np.linalg.norm(estimators.cv_diag(Om, Y, np.ones(n)) - d) / den)
+        errs["exact"].append(np.linalg.norm(estimators.cv_diag(Om, Y, d) - d) / den)
+        errs["bks"].append(np.linalg.norm(estimators.bks_diag(Om, Y) - d) / den)
+        R = philox.rademacher(n, 16, 500 + s)
+        errs["rademacher"].append(np.linalg.norm(estimators.hutchinson_diag(R, ph @ R) - d) / den)
+    e = {k: float(np.mean(v)) for k, v in errs.items()}
+    print("[gpu] held-out diagonal errors, M = 16: " + ", ".join(f"{k} {v:.3g}" for k, v in e.items()), flush=True)
+    assert e["learned"] < 0.5 * e["plain"]
+    assert e["exact"] > 0.9 * e["const"]
+    assert e["learned"] < 1.05 * e["const"]
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])

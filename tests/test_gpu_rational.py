@@ -250,7 +250,11 @@ def test_pole_independent_estimates(ctx, lib, mu, kind, dtype):
     exact = rational.exact_return_probability(Lap, ts)
     print(f"[gpu] poles: library {poles_lib.size}, oracle {poles_orc.size}; "
           f"|p - exact| / e_hat: {np.round(np.abs(p - exact) / e, 2)}", flush=True)
-    assert np.all(np.abs(p - exact) <= 5 * e) and np.all(np.abs(po - exact) <= 5 * eo)
+    # where e_hat vanishes (at late t exp(-t L) Omega is nearly the rank-one projection
+    # on the constant vector, which Nystrom recovers exactly) the FP32 estimate keeps
+    # its rounding: 1e-6 of the largest estimate, as in the parity tests above
+    floor = 1e-6 * np.abs(po).max() if dtype == "f32" else 1e-10 * np.abs(po).max()
+    assert np.all(np.abs(p - exact) <= 5 * e + floor) and np.all(np.abs(po - exact) <= 5 * eo + 1e-12)
     if dtype == "f64":
         np.testing.assert_allclose(p, po, rtol=1e-8, atol=0)
     else:
