@@ -141,23 +141,30 @@ def cpu_baseline(rp, ci, n, lam, X, K):
     """The oracle (sparse FP64 series, eq. qrec) on a bounded sample of the step:
     one of the ten operators (mu = 0.5, exponential), degree K, on 1 + b columns."""
     import numpy as np
-    from oracle import sparse
+    from oracle import krylov, sparse
 
     A = sparse.adjacency(n, rp, ci)
     beta = 1.0 / lam
-    coeffs = np.array([beta ** k / math.factorial(k) for k in range(K + 1)])
+    coeffs = krylov.exp_coefficients(beta, K)
+    nt = krylov.threads()
     t0 = time.perf_counter()
-    sparse.series_apply(A, 0.5, coeffs, np.ones((n, 1)))
-    sparse.series_apply(A, 0.5, coeffs, X.astype(np.float64))
+    reps = 0
+    while True:  # whole operator evaluations until about 10 s of host time
+        krylov.series_apply(A, 0.5, coeffs, np.ones((n, 1)))
+        krylov.series_apply(A, 0.5, coeffs, X.astype(np.float64))
+        reps += 1
+        if time.perf_counter() - t0 > 10.0 or reps == 8:
+            break
     dt = time.perf_counter() - t0
-    ev = K * A.nnz * (1 + X.shape[1])
+    ev = reps * K * A.nnz * (1 + X.shape[1])
     return {
         "value": ev / dt / 1e9,
         "unit": "GEdge·vec/s",
-        "cores": 1,
+        "cores": nt,
+        "nproc": os.cpu_count(),
         "kind": "oracle",
-        "sample": f"1 of 10 operators (mu=0.5, exp, degree {K}) on 1+{X.shape[1]} columns, "
-                  f"scipy.sparse single-threaded FP64, {dt:.1f} s",
+        "sample": f"{reps} evaluation(s) of 1 of the 10 operators (mu=0.5, exp, degree {K}) on 1+{X.shape[1]} "
+                  f"columns, FP64 series with scipy.sparse products split over {nt} host threads, {dt:.1f} s",
     }
 
 

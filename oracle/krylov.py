@@ -36,11 +36,17 @@ _POOL = None
 
 
 def threads():
-    """Host threads used for the row-chunked sparse products (all the process may use)."""
+    """Host threads used for the row-chunked sparse products: the CPUs the process may
+    run on, capped by OMP_NUM_THREADS when that is set (the host's share of a shared
+    machine)."""
     try:
-        return max(1, len(os.sched_getaffinity(0)))
+        nt = max(1, len(os.sched_getaffinity(0)))
     except AttributeError:
-        return max(1, os.cpu_count() or 1)
+        nt = max(1, os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    if cap.isdigit() and int(cap) > 0:
+        nt = min(nt, int(cap))
+    return nt
 
 
 def spmm(A, X):

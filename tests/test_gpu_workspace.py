@@ -59,14 +59,16 @@ def test_ws_calls_equal_allocating_calls(lib, ba20k, kind, mu, dtype, method):
     wL, nL = work_for(op, "apply_L", b)
     wE, nE = work_for(op, "expv", b, 12)
     assert nL > nP > 0 and nE > nL
+    # outputs from torch before the calls (its caching allocator takes 20 MiB segments)
+    P, L, E = torch.empty_like(X), torch.empty_like(X), torch.empty_like(X)
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info()[0]
-    P = op.apply_phi_ws(X, wP)
-    L = op.apply_L_ws(X, wL)
-    (E,), e = op.expv_ws(X, [1.0], wE, outer_dim=12)
+    op.apply_phi_ws(X, wP, out=P)
+    op.apply_L_ws(X, wL, out=L)
+    (E,), e = op.expv_ws(X, [1.0], wE, outer_dim=12, outs=[E])
     torch.cuda.synchronize()
     free1 = torch.cuda.mem_get_info()[0]
-    assert free0 - free1 < (4 << 20), (free0, free1, nE)  # outputs were allocated by torch before
+    assert free0 - free1 < (4 << 20), (free0, free1, nE)
     assert torch.equal(P, P_ref) and torch.equal(L, L_ref) and torch.equal(E, E_ref)
     assert e == e_ref
     # after the walk degrees are cached the Laplacian calls need less and still agree
