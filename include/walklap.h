@@ -259,6 +259,25 @@ wl_status wl_apply_L_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* 
 wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
                      int32_t outer_dim, double* err_est, void* d_work, size_t work_bytes);
 
+/* ---------------------------------------------------------------- no allocation
+ * wl_apply_L_noalloc: for callers that cannot allocate device memory at all (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  As
+ * wl_apply_L (Y = L X, n x b row-major, L = diag(w) - phi), but every device buffer the
+ * call uses lies in a fixed region of WL_NOALLOC_BYTES (64 MiB) that the library holds
+ * on each device it runs on from its first wl_ctx_create there until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library routine)
+ * and records no kernel timing.  WL_ERANGE, with nothing enqueued, when the call would
+ * need more than the region (wl_workspace_size(op, WL_CALL_APPLY_L, b) tells how much;
+ * FP32 series operators need about 2 n b 4 bytes, Lanczos ones (K + 2) n b s): take
+ * wl_apply_L_ws with a caller region then.  Every call on one GPU, from any context or
+ * thread, shares that GPU's region, and the region keeps the last call's contents:
+ * calls that overlap on one GPU (two host threads, or two streams whose work is in
+ * flight together) race and give undefined results; calls ordered on one stream, or
+ * separated by a synchronisation, are safe.  When the operator's walk degrees are not
+ * cached they are computed in the region on every call, as in wl_apply_L_ws.         */
+#define WL_NOALLOC_BYTES ((size_t)64 << 20)
+wl_status wl_apply_L_noalloc(wl_op* op, const void* d_X, void* d_Y, int32_t b);
+
 /* ---------------------------------------------------------------- multigrid-preconditioned CG
  * The hierarchy of a WL_M_AMG_CG operator (Sec. 4.2), built on the host when the
  * operator is created:

@@ -312,6 +312,13 @@ class Operator:
         check(load().wl_apply_L_ws(self.handle, _ptr(X), _ptr(out), X.shape[1], wp, wb))
         return out
 
+    def apply_L_noalloc(self, X, out):
+        """L X on the library's fixed region; out must be given (nothing is allocated)."""
+        X = self._block(X)
+        out = self._out(out, X)
+        check(load().wl_apply_L_noalloc(self.handle, _ptr(X), _ptr(out), X.shape[1]))
+        return out
+
     def expv_ws(self, U0, ts, work, outer_dim=30, outs=None):
         U0 = self._block(U0)
         ts = [float(t) for t in ts]

@@ -81,6 +81,7 @@ SIGNATURES = {
     "wl_workspace_size": (C.c_int, [vp, i32, i32, i32, C.POINTER(C.c_size_t)]),
     "wl_apply_phi_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
     "wl_apply_L_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),
+    "wl_apply_L_noalloc": (C.c_int, [vp, vp, vp, i32]),
     "wl_amg_info": (C.c_int, [vp, C.POINTER(AmgStats)]),
     "wl_amg_describe": (C.c_int, [i64, vp, vp, f64, f64, i32, C.POINTER(i32), C.POINTER(i64), C.POINTER(i64), vp]),
     "wl_expv_ws": (C.c_int, [vp, vp, i32, pd, i32, C.POINTER(vp), i32, pd, vp, C.c_size_t]),

@@ -23,10 +23,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "wl_internal.h"
 #include "wl_amg.h"
+
+static wl_status noalloc_setup(int device);
 
 // ------------------------------------------------------------------ errors
 static thread_local char g_err[1024] = "";
@@ -113,6 +117,7 @@ wl_status wl_ctx_create(int32_t device, void* stream, wl_ctx** out) {
   WL_CHECK(device >= 0 && device < count, WL_EINVAL, "wl_ctx_create: device %d out of range [0,%d)", device, count);
   DeviceGuard dg(device);
   WL_HIP(hipFree(nullptr));
+  WL_TRY(noalloc_setup(device));
   auto* c = new wl_ctx;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
@@ -1603,6 +1608,39 @@ wl_status ws_check(wl_op* op, int call, int b, int outer_dim, void* d_work, size
 
 }  // namespace
 
+// ------------------------------------------------------------------ fixed region
+// wl_apply_L_noalloc runs on a region that is part of the library's code object: one
+// static device array per GPU, held from module load until the process ends.  Host
+// code never names the array in a kernel argument or copy (on the host its name is a
+// stand-in, not a device address); the device address comes from hipGetSymbolAddress
+// with the device current, once per device, at wl_ctx_create.
+static __device__ __align__(256) unsigned char scratch[WL_NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, void*> g_scratch_ptr;  // device -> address of that device's copy
+}  // namespace
+
+static wl_status noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return WL_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    wl_set_error("fixed region: hipGetSymbolAddress failed on device %d: %s", device, hipGetErrorString(e));
+    return WL_EDEVICE;
+  }
+  WL_CHECK((reinterpret_cast<uintptr_t>(ptr) & 255u) == 0, WL_EINTERNAL, "fixed region is not 256-byte aligned");
+  g_scratch_ptr[device] = ptr;
+  return WL_OK;
+}
+
+static void* noalloc_region(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
 static wl_status phi_ws_call(wl_op* op, const void* d_X, void* d_Y, int32_t b, bool laplacian, void* d_work,
                              size_t work_bytes) {
   const char* who = laplacian ? "wl_apply_L_ws" : "wl_apply_phi_ws";
@@ -1633,6 +1671,23 @@ wl_status wl_apply_phi_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void
 
 wl_status wl_apply_L_ws(wl_op* op, const void* d_X, void* d_Y, int32_t b, void* d_work, size_t work_bytes) {
   return phi_ws_call(op, d_X, d_Y, b, true, d_work, work_bytes);
+}
+
+wl_status wl_apply_L_noalloc(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
+  WL_TRY(check_block(op, d_X, d_Y, b, "wl_apply_L_noalloc"));
+  const int dev = op->g->ctx->device;
+  DeviceGuard dg(dev);
+  void* base = noalloc_region(dev);
+  WL_CHECK(base, WL_EINTERNAL, "wl_apply_L_noalloc: fixed region of device %d not set up", dev);
+  WsPlan pl;
+  WL_TRY(plan_call(op, WL_CALL_APPLY_L, b, 0, pl));
+  const size_t need = pl.total();
+  WL_CHECK(need <= WL_NOALLOC_BYTES, WL_ERANGE,
+           "wl_apply_L_noalloc: this call needs %zu bytes of workspace, above the fixed region's %zu bytes "
+           "(use wl_apply_L_ws with a larger caller region)",
+           need, (size_t)WL_NOALLOC_BYTES);
+  WsScope scope(op, pl, base);
+  return wl_apply_L(op, d_X, d_Y, b);
 }
 
 wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, int32_t nt, void* const* d_Y,
