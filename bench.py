@@ -48,6 +48,13 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--separate", action="store_true",
                    help="ba1m: evaluate every operator on its own (no side-by-side series operators)")
+    p.add_argument("--no-pack", action="store_true",
+                   help="ba1m: walk degrees in passes of their own (four series operators side by side, the "
+                        "resolvent operators as Lanczos pairs) instead of riding beside the blocks")
+    p.add_argument("--res-layout", choices=["pairs", "packed"], default="pairs",
+                   help="ba1m: resolvent operators as two Lanczos pairs (32 wide), one single operator and their "
+                        "walk degrees as single-column processes on three streams (pairs), or all five with "
+                        "their walk degrees in one 96-wide block (packed)")
     p.add_argument("--shapes", default="",
                    help="ba1m: fixed sparse-product launch shapes width:lanes:threshold,... instead of autotuning "
                         "(e.g. to take hardware counters on the shapes a timed run chose)")
@@ -1217,6 +1224,224 @@ def cpu_baseline_cv(rp, ci, n, mu, beta, K, S, d_true, den, gpu_err):
                       f"thread pool, {secs:.1f} s; its error {err:.4e}"}
 
 
+def run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g):
+    """The default workload with every operator group in one wide block: the five
+    exponential operators (truncated series) and the five resolvent operators (block
+    Lanczos) each evaluate L V of all five and their walk degrees w = f(A)1 together
+    (wl_multi_apply_fdeg: 5 x 16 columns plus a 16-column group holding the five
+    vectors of ones, 96 FP32 values = three whole cache lines per gathered row).  The
+    resolvent group runs on a second stream (its own library context borrowing the
+    device CSR) while the series group runs on the first."""
+    import threading
+
+    import torch
+
+    import paper_2601_11338_amd as wl
+
+    wd = 5 * b + 16
+    if args.shapes:
+        for item in args.shapes.split(","):
+            w_, l_, t_ = (int(x) for x in item.split(":"))
+            g.set_shape(torch.float32, w_, l_, t_)
+    else:
+        for w_ in (wd, b, 2 * b, 5):
+            g.autotune(torch.float32, w_)
+    log("launch shapes width:lanes:threshold " +
+        ",".join(f"{w_}:{g.shape(torch.float32, w_)[0]}:{g.shape(torch.float32, w_)[1]}" for w_ in (wd, b, 2 * b, 5)))
+    lam = g.lambda_max()
+    mus = [0.0, 0.25, 0.5, 0.75, 1.0]
+    rhos = []
+    for mu in mus:
+        rhos.append(g.spectral_radius(mu))
+        log(f"mu={mu}: rho(Z_mu)={rhos[-1]:.6f} (lambda_max={lam:.6f})")
+    X = torch.tensor(X_h, device="cuda")
+    exp_ops = [wl.Operator(g, mu, "exp", 1.0 / lam, dtype=torch.float32, krylov_dim=K) for mu in mus]
+    series = wl.Multi(exp_ops)
+    Ys = torch.empty((n, 5 * b), dtype=torch.float32, device="cuda")
+    Ws = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+    series.apply_fdeg(X, out=Ys, out_w=Ws)  # walk degrees cached for the Laplacian finish
+    packed = args.res_layout == "packed"
+    # resolvent work items, each on its own context (stream) borrowing the device CSR
+    nitems = 1 if packed else 3
+    nctx = min(nitems, max(1, args.streams - 1))
+    ctxs, rgraphs = [ctx], []
+    for _ in range(nctx):
+        if args.streams > 1:
+            c = wl.Context(0, stream=torch.cuda.Stream().cuda_stream)
+            gi = wl.Graph(c, g.rowptr, g.colidx)
+            for w_ in (wd, b, 2 * b, 5):
+                gi.set_shape(torch.float32, w_, *g.shape(torch.float32, w_))
+            ctxs.append(c)
+            rgraphs.append(gi)
+        else:
+            rgraphs.append(g)
+    keep = []
+
+    def res_ops_on(graph):
+        return [wl.Operator(graph, mu, "res", 0.5 / rho, dtype=torch.float32, krylov_dim=K, rho_hint=rho)
+                for mu, rho in zip(mus, rhos)]
+
+    items = []
+    if packed:
+        resolv = wl.Multi(res_ops_on(rgraphs[0]))
+        Yr, Wr = torch.empty_like(Ys), torch.empty_like(Ws)
+        resolv.apply_fdeg(X, out=Yr, out_w=Wr)
+        keep.append(resolv)
+        items.append([lambda: resolv.apply_fdeg(X, out=Yr, out_w=Wr)])
+    else:
+        per = [[] for _ in rgraphs]
+        for i in range(3):  # item i on resolvent context i mod count
+            gi = rgraphs[i % len(rgraphs)]
+            ops_r = res_ops_on(gi)
+            keep.append(ops_r)
+            if i == 0:  # walk degrees of all five (single-column processes) and L V of the fifth
+                fd = wl.Multi(ops_r)
+                Wr = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+                Y1 = torch.empty((n, b), dtype=torch.float32, device="cuda")
+                ops_r[4].fdeg()
+                keep.extend([fd, Wr, Y1])
+                per[i % len(rgraphs)].append(lambda fd=fd, Wr=Wr, Y1=Y1, o=ops_r[4]: (fd.fdeg(out=Wr),
+                                                                                      o.apply_L(X, out=Y1)))
+            else:  # L V of a Lanczos pair (32 wide)
+                pm = wl.Multi(ops_r[2 * i - 2:2 * i])
+                Yp = torch.empty((n, 2 * b), dtype=torch.float32, device="cuda")
+                pm.apply_L(X, out=Yp)
+                keep.extend([pm, Yp])
+                per[i % len(rgraphs)].append(lambda pm=pm, Yp=Yp: pm.apply_L(X, out=Yp))
+        items = per
+    torch.cuda.synchronize()
+    nstreams = len(ctxs)
+
+    def run_items(its):
+        for it in its:
+            it()
+
+    def res_item():
+        for its in items:
+            run_items(its)
+
+    def step():
+        if nstreams > 1:
+            ths = [threading.Thread(target=run_items, args=(its,)) for its in items]
+            for th in ths:
+                th.start()
+            series.apply_fdeg(X, out=Ys, out_w=Ws)
+            for th in ths:
+                th.join()
+        else:
+            series.apply_fdeg(X, out=Ys, out_w=Ws)
+            res_item()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done")
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+
+    def stats(c, k):
+        return c.kernel_stats(k)
+
+    # class 3: the series group's sparse products; class 4: the Lanczos groups' (96 wide
+    # packed, or the 32-wide pairs); class 1: a single operator's Lanczos products
+    timed = {k: [sum(x) for x in zip(*[stats(c, k) for c in ctxs])] for k in (1, 3, 4)}
+    # the kernel roofline from a replay one group at a time on its own stream (with two
+    # streams a launch's HIP-event interval also spans the other group's work)
+    for c in ctxs:
+        c.set_profiling(False)
+        c.set_profiling(True)
+    for _ in range(2):
+        series.apply_fdeg(X, out=Ys, out_w=Ws)
+        torch.cuda.synchronize()
+        res_item()
+        torch.cuda.synchronize()
+    kern = []
+    lanes = g.shape(torch.float32, wd)[0]
+    seg = wd // 4  # 16-byte vectors per row
+    lpn = 16 if seg % 16 == 0 else (32 if 16 < seg < 32 and lanes >= 32 else (8 if seg % 8 == 0 else 4))
+    res_w = wd if packed else 2 * b
+    for k, width, what in ((3, wd, "series steps of the five exponential operators and their walk degrees"),
+                           (4, res_w, "Lanczos operator products of the five resolvent operators and their walk "
+                                      "degrees" if packed else "Lanczos operator products of two resolvent operators"),
+                           (1, b, "Lanczos operator products of one resolvent operator")):
+        nl, kms, kby = [sum(x) for x in zip(*[stats(c, k) for c in ctxs])]
+        if nl == 0:
+            continue
+        kl = g.shape(torch.float32, width)[0]
+        sg = width // 4
+        kp = 16 if sg % 16 == 0 else (32 if 16 < sg < 32 and kl >= 32 else (8 if sg % 8 == 0 else 4))
+        kern.append({"kernel": f"k_spmm<float,4,{kp},{kl}>", "width": width, "what": what, "launches": nl,
+                     "total_ms": kms, "avg_launch_us": kms / nl * 1e3, "alg_bytes_per_launch": kby / nl,
+                     "achieved": kby / (kms * 1e-3) / 1e9, "class": k,
+                     "timed_region": {"launches": timed[k][0], "avg_launch_us": timed[k][1] / max(timed[k][0], 1) * 1e3,
+                                      "achieved": timed[k][2] / (timed[k][1] * 1e-3) / 1e9 if timed[k][1] else None}})
+    for c in ctxs:
+        c.set_profiling(False)
+    edge_vec = 10 * K * nnz * (1 + b)
+    value = edge_vec / (ms * 1e-3) / 1e9
+    dom = max(kern, key=lambda k: k["total_ms"])
+    for k in kern:
+        log(f"width {k['width']} ({k['what']}): {k['launches']} launches, avg {k['avg_launch_us']:.1f} us, "
+            f"{k['achieved']:.0f} GB/s algorithmic, {k['total_ms']:.1f} ms in the replayed steps")
+    # gathered 128-byte lines per launch (every row segment of a neighbour, three whole
+    # lines at 96 FP32 values) plus the row-aligned streams: the traffic the measured
+    # random-gather ceiling applies to
+    line_bytes = nnz * 4 * dom["width"] + (dom["alg_bytes_per_launch"] - 4.0 * n * dom["width"])
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GEdge·vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"barabasi-albert n={n} m={m} nnz={nnz}; mu in {mus} x {{exp beta=1/lambda_max, "
+                        f"res alpha=0.5/rho(Z_mu)}}; b={b} Rademacher + f(A)1; Krylov dim {K}; FP32 vectors, "
+                        f"FP64 coefficients",
+            "n": n,
+            "nnz": nnz,
+            "block": b,
+            "krylov_dim": K,
+            "operators": 10,
+            "streams": nstreams,
+            "series_width": wd,
+            "resolvent_layout": args.res_layout,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": dom["achieved"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dom["achieved"] / HBM_PEAK_GBS,
+            "traffic": measured_traffic(n, m, dom["width"], g.shape(torch.float32, dom["width"])[0]),
+            "kernel": f"{dom['kernel']} ({dom['width']} wide: {dom['what']})",
+            "avg_launch_us": dom["avg_launch_us"],
+            "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
+            "line_bytes_per_launch": line_bytes,
+            "line_GBps": line_bytes / (dom["avg_launch_us"] * 1e-6) / 1e9,
+            "other_kernels": [k2 for k2 in kern if k2 is not dom],
+            "measured_in": "replay of the step one group at a time after the timed region",
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(rp, ci, n, lam, X_h, K)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1264,6 +1489,9 @@ def main():
     ctx = wl.Context(0)
     g = wl.Graph(ctx, rp, ci, validate=True)
     log(f"graph n={n} nnz={nnz} max_degree={g.info()[2]}")
+    if not (args.separate or args.no_pack):
+        run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g)
+        return
     widths = [b, 1] if args.separate else [b, 1, 4 * b, 5, 2 * b]  # 4 b: four series operators side by
     if args.shapes:                                                    # side; 5: five walk-degree columns;
         for item in args.shapes.split(","):                            # 2 b: two Lanczos processes

@@ -479,11 +479,22 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
  * wl_multi_apply: d_X n x b (the same block for every operator), d_Y n x (nops b)
  * row-major, laplacian != 0: L_g X in group g, else phi_g X.  nops b <= 4096.  Rows of
  * nops b = 32 or 64 FP32 values are where the sharing pays most.
- * wl_multi_fdeg: d_W n x nops, column g = phi_g 1.                                   */
+ * wl_multi_fdeg: d_W n x nops, column g = phi_g 1.
+ * wl_multi_apply_fdeg: both in one evaluation (the walk degrees w_g = phi_g 1 of
+ * eq. weighted_laplacian beside phi_g X or L_g X): d_Y as wl_multi_apply, d_W as
+ * wl_multi_fdeg (three distinct buffers).  The vectors of ones ride in one extra group
+ * of 16 columns, so each step gathers them from the same cache lines as the blocks:
+ * truncated series for nops <= 16 and any b; Lanczos operators for FP32, b = 16,
+ * nops <= 16 (the ones' group then holds nops independent single-column Lanczos
+ * processes with diagonal Grams).  Other shapes run wl_multi_apply, then
+ * wl_multi_fdeg.  With laplacian != 0 the finish takes the walk degrees cached by an
+ * earlier call (computed first when there are none), as wl_multi_apply does.        */
 typedef struct wl_multi wl_multi;
 wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out);
 wl_status wl_multi_apply(wl_multi* multi, const void* d_X, int32_t b, void* d_Y, int32_t laplacian);
 wl_status wl_multi_fdeg(wl_multi* multi, void* d_W);
+wl_status wl_multi_apply_fdeg(wl_multi* multi, const void* d_X, int32_t b, void* d_Y, void* d_W,
+                              int32_t laplacian);
 wl_status wl_multi_destroy(wl_multi* multi);
 
 /* ---------------------------------------------------------------- batches of graphs

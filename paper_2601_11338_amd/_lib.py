@@ -128,6 +128,7 @@ SIGNATURES = {
     "wl_multi_create": (C.c_int, [vp, i32, C.POINTER(vp)]),
     "wl_multi_apply": (C.c_int, [vp, vp, i32, vp, i32]),
     "wl_multi_fdeg": (C.c_int, [vp, vp]),
+    "wl_multi_apply_fdeg": (C.c_int, [vp, vp, i32, vp, vp, i32]),
     "wl_multi_destroy": (C.c_int, [vp]),
     "wl_batch_create": (C.c_int, [vp, i32, vp, vp, f64, C.POINTER(vp)]),
     "wl_batch_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32), vp, vp]),

@@ -831,7 +831,7 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
                                              const double* __restrict__ Rprev, double* __restrict__ Bout,
                                              int64_t gs, double* __restrict__ ref_out, const double* ref_in,
                                              double post_tol, double* skip_out, double skip_ratio,
-                                             const double* skip_in) {
+                                             const double* skip_in, int dg, const double* dref) {
   const int64_t go = (int64_t)blockIdx.x * gs;  // batch: graph g's matrices at +g gs
   if (ref_out) ref_out += go;
   if (ref_in) ref_in += go;
@@ -860,6 +860,49 @@ __global__ __launch_bounds__(64) void k_chol(int b, const double* __restrict__ G
   Rinv += go;
   if (Rprev) Rprev += go;
   if (Bout) Bout += go;
+  if ((int)blockIdx.x == dg) {
+    // A group of independent single-column processes (different operators side by
+    // side): only the diagonal of G is meaningful.  Each column is factorised alone and
+    // judged against its own scale (G_ii, A_ii^2 + B_ii^2, and for the later check the
+    // diagonal of dref when given); one pass is exact, so no second pass is asked for.
+    for (int e = t; e < b * b; e += 64) {
+      if (R) R[e] = 0.0;
+      Rinv[e] = 0.0;
+      if (Bout) Bout[e] = 0.0;
+    }
+    __syncthreads();
+    const double* dr = dref ? dref + go : nullptr;
+    for (int i = t; i < b; i += 64) {
+      const int d = i * b + i;
+      const double g = G[d];
+      double sref = g;
+      if (Aref || Bref)
+        sref = fmax(sref, (Aref ? Aref[d] * Aref[d] : 0.0) + (Bref ? Bref[d] * Bref[d] : 0.0));
+      const bool keep = g > 0.0 && g > tol * sref;
+      const double r = keep ? sqrt(g) : 0.0;
+      double ri = keep ? 1.0 / r : 0.0;
+      double bo = r * (Rprev ? Rprev[d] : 1.0);
+      if (Bout && ref_in && post_tol > 0.0) {
+        const double lim = post_tol * sqrt(fmax(dr ? dr[d] : ref_in[0], 0.0));
+        if (fabs(bo) <= lim) {
+          bo = 0.0;
+          ri = 0.0;
+        }
+      }
+      if (R) R[d] = r;
+      Rinv[d] = ri;
+      if (Bout) Bout[d] = bo;
+    }
+    if (t == 0) {
+      if (ref_out) {
+        double m = 0.0;
+        for (int i = 0; i < b; ++i) m = fmax(m, G[i * b + i]);
+        ref_out[0] = m;
+      }
+      if (skip_out) *skip_out = 1.0;
+    }
+    return;
+  }
   __shared__ double sG[64 * 65];
   __shared__ double sR[64 * 65];
   __shared__ int defl[64];
@@ -1421,10 +1464,10 @@ wl_status launch_lanczos_proj(wl_ctx* ctx, int b, int nbv, const double* P, doub
 wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const double* Aref, const double* Bref,
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs, int64_t gs,
                       double* ref_out, const double* ref_in, double post_tol, double* skip_out, double skip_ratio,
-                      const double* skip_in) {
+                      const double* skip_in, int dg, const double* dref) {
   WL_CHECK(b >= 1 && b <= 64 && ngraphs >= 1, WL_EINVAL, "chol: b out of range");
   hipLaunchKernelGGL(k_chol, dim3(ngraphs), dim3(64), 0, ctx->stream, b, G, tol, Aref, Bref, R, Rinv, Rprev, Bout,
-                     gs, ref_out, ref_in, post_tol, skip_out, skip_ratio, skip_in);
+                     gs, ref_out, ref_in, post_tol, skip_out, skip_ratio, skip_in, dg, dref);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }

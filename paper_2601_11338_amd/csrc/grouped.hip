@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) void k_gupdate1(int64_t n, const T* X, int64_t
 // flag are left alone.
 __global__ __launch_bounds__(256) void k_gfinalize(const double* __restrict__ partials, int nparts, int ngt,
                                                    int nblk, int E, double* __restrict__ out, int64_t gs,
-                                                   const double* __restrict__ skip) {
+                                                   const double* __restrict__ skip, int dg, int gb) {
   __shared__ double s[256];
   const int t = threadIdx.x, el = t & 15, p = t >> 4;
   const int64_t tot = (int64_t)ngt * nblk * E;
@@ -383,7 +383,12 @@ __global__ __launch_bounds__(256) void k_gfinalize(const double* __restrict__ pa
   }
   if (p == 0 && live) {
     const int64_t rem = ent - (int64_t)q * nblk * E;
-    out[(int64_t)q * gs + rem] = s[t];
+    double v0 = s[t];
+    if (q == dg) {  // group of independent single columns: cross terms do not exist
+      const int e = (int)(rem % E);
+      if (e / gb != e % gb) v0 = 0.0;
+    }
+    out[(int64_t)q * gs + rem] = v0;
   }
 }
 
@@ -493,7 +498,7 @@ bool grouped_supported(int prec, int gb, int ng) {
 
 template <typename T>
 wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk, const T* Y,
-                       double* out, int64_t gs, const double* skip) {
+                       double* out, int64_t gs, const double* skip, int dg) {
   WL_CHECK(grouped_supported(prec_of<T>(), gb, ng), WL_EUNSUPPORTED, "grouped Gram: unsupported group shape");
   WL_CHECK(nblk >= 1 && nblk <= 3, WL_EINVAL, "grouped Gram: 1..3 blocks");
   if (n == 0) return WL_OK;
@@ -530,7 +535,7 @@ wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64
   }
   const int64_t tot = (int64_t)ng * nblk * E;
   hipLaunchKernelGGL(k_gfinalize, dim3((unsigned)((tot + 15) / 16)), dim3(256), 0, ctx->stream,
-                     ctx->partials.as<double>(), nparts, ng, nblk, E, out, gs, skip);
+                     ctx->partials.as<double>(), nparts, ng, nblk, E, out, gs, skip, dg, gb);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -538,7 +543,7 @@ wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64
 template <typename T>
 wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk,
                          const double* C, int64_t cs, const T* Yin, double alpha, const T* wv, double beta, T* Out,
-                         double* gram_out, int64_t gs, const double* skip, const double* skip_gram) {
+                         double* gram_out, int64_t gs, const double* skip, const double* skip_gram, int dg) {
   WL_CHECK(grouped_supported(prec_of<T>(), gb, ng), WL_EUNSUPPORTED, "grouped update: unsupported group shape");
   WL_CHECK(nblk >= 0 && nblk <= (gb == 1 ? G1_MAXK : G16_LDS_KB), WL_EINVAL, "grouped update: too many blocks");
   WL_CHECK(!(skip && gram_out), WL_EINVAL, "grouped update: a skippable update yields no Gram");
@@ -578,7 +583,7 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
   if (gram_out) {
     const int64_t tot = (int64_t)ng * E;
     hipLaunchKernelGGL(k_gfinalize, dim3((unsigned)((tot + 15) / 16)), dim3(256), 0, ctx->stream,
-                       ctx->partials.as<double>(), nparts, ng, 1, E, gram_out, gs, skip_gram);
+                       ctx->partials.as<double>(), nparts, ng, 1, E, gram_out, gs, skip_gram, dg, gb);
     WL_HIP(hipGetLastError());
   }
   return WL_OK;
@@ -602,10 +607,10 @@ wl_status launch_group_copy(wl_ctx* ctx, int64_t n, int b, int ng, int q, const 
 
 #define WL_INST_GROUPED(T)                                                                                        \
   template wl_status launch_ggram<T>(wl_ctx*, int64_t, int, int, const T*, int64_t, int, const T*, double*,        \
-                                     int64_t, const double*);                                                      \
+                                     int64_t, const double*, int);                                                 \
   template wl_status launch_gupdate<T>(wl_ctx*, int64_t, int, int, const T*, int64_t, int, const double*, int64_t, \
                                        const T*, double, const T*, double, T*, double*, int64_t, const double*,    \
-                                       const double*);                                                             \
+                                       const double*, int);                                                        \
   template wl_status launch_group_copy<T>(wl_ctx*, int64_t, int, int, int, const T*, T*, bool);
 WL_INST_GROUPED(float)
 WL_INST_GROUPED(double)

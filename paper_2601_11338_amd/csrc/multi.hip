@@ -39,6 +39,12 @@ struct wl_multi {
   DevBuf Xrep, A, B, ones;
   DevBuf ltab;                      // Lanczos groups: [nops][5] {a, b0, b1, 0, 0}
   DevBuf basis, small, coef, tmpX, tmpY, tmpW;
+  // walk degrees riding beside the blocks (wl_multi_apply_fdeg): one extra group of 16
+  // columns whose column q < nops is operator q's vector of ones
+  DevBuf tab_pk, tab_pk_phi;  // series: [Kmax][2 nops][5], entries nops + q without finish
+  DevBuf cmap;                // operator of each column of the packed block
+  int cmap_b = 0;
+  DevBuf Xpk, Ypk, Wg;
 };
 
 namespace {
@@ -53,6 +59,52 @@ __global__ void k_replicate(int64_t n, int b, int nops, const T* __restrict__ X,
     Xr[i] = X[r * b + c];
   }
 }
+
+// Packed block: X in each of the nops groups of b columns, then a group of 16 columns
+// whose column q < nops is a vector of ones (operator q's walk degrees), zero beyond.
+template <typename T>
+__global__ void k_pack_fdeg(int64_t n, int b, int nops, const T* __restrict__ X, T* __restrict__ Xp) {
+  const int xw = b * nops;
+  const int64_t wd = (int64_t)xw + 16;
+  const int64_t total = n * wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / wd;
+    const int c = (int)(i - r * wd);
+    Xp[i] = c < xw ? X[r * b + c % b] : (c - xw < nops ? T(1) : T(0));
+  }
+}
+
+// Y (n x nops b) and W (n x nops) out of the packed block
+template <typename T>
+__global__ void k_unpack_fdeg(int64_t n, int b, int nops, const T* __restrict__ Yp, T* __restrict__ Y,
+                              T* __restrict__ W) {
+  const int xw = b * nops;
+  const int64_t wd = (int64_t)xw + 16;
+  const int64_t ow = (int64_t)xw + nops;
+  const int64_t total = n * ow;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ow;
+    const int c = (int)(i - r * ow);
+    if (c < xw)
+      Y[r * xw + c] = Yp[r * wd + c];
+    else
+      W[r * nops + (c - xw)] = Yp[r * wd + c];
+  }
+}
+
+// Wg (n x (nops + 1)) = [W | 0]: group-indexed finish weights of the packed Lanczos
+// recombination (the walk-degree group takes no finish)
+template <typename T>
+__global__ void k_wg(int64_t n, int nops, const T* __restrict__ W, T* __restrict__ Wg) {
+  const int64_t total = n * (nops + 1);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / (nops + 1);
+    const int c = (int)(i - r * (nops + 1));
+    Wg[i] = c < nops ? W[r * nops + c] : T(0);
+  }
+}
+
+int elem_grid(int64_t count) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (count + 255) / 256)); }
 
 template <typename T>
 wl_status multi_apply(wl_multi* m, const T* X, int b, T* Y, bool laplacian) {
@@ -285,6 +337,253 @@ wl_status multi_dispatch(wl_multi* m, const T* X, int b, T* Y, bool laplacian) {
   return multi_lanczos<T>(m, X, Xr, b, Y, laplacian ? m->W.as<T>() : nullptr);
 }
 
+// ------------------------------------------------------------------ walk degrees alongside
+// The operator of every column of the packed block (width nops b + 16): group q's
+// columns take operator q (series: table entry q, with its finish); walk-degree column
+// q takes operator q without finish (series: entry nops + q; Lanczos: q, the same
+// matrix); padding -1.
+wl_status ensure_cmap(wl_multi* m, int b, bool series) {
+  if (m->cmap_b == (series ? b : -b) && m->cmap.p) return WL_OK;
+  const int xw = m->nops * b, wd = xw + 16;
+  std::vector<int32_t> h(wd);
+  for (int c = 0; c < wd; ++c)
+    h[c] = c < xw ? c / b : (c - xw < m->nops ? (series ? m->nops : 0) + (c - xw) : -1);
+  WL_TRY(m->cmap.ensure(h.size() * 4));
+  WL_HIP(hipMemcpyAsync(m->cmap.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, m->g->ctx->stream));
+  WL_HIP(hipStreamSynchronize(m->g->ctx->stream));  // h is host memory of this call
+  m->cmap_b = series ? b : -b;
+  return WL_OK;
+}
+
+// Truncated series of every operator on X and on the vector of ones together: one
+// sparse product per step over the packed block.
+template <typename T>
+wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool laplacian) {
+  wl_graph* g = m->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  const int nops = m->nops;
+  const int wd = nops * b + 16;
+  const size_t bytes = (size_t)n * wd * sizeof(T);
+  WL_TRY(ensure_cmap(m, b, true));
+  WL_TRY(m->Xpk.ensure(bytes));
+  WL_TRY(m->A.ensure(bytes));
+  WL_TRY(m->B.ensure(bytes));
+  WL_TRY(m->Ypk.ensure(bytes));
+  T* Xr = m->Xpk.as<T>();
+  T* A = m->A.as<T>();
+  T* Bf = m->B.as<T>();
+  T* Yp = m->Ypk.as<T>();
+  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(n * wd)), dim3(256), 0, ctx->stream, n, b, nops, X, Xr);
+  WL_HIP(hipGetLastError());
+  const double* tab = (laplacian ? m->tab_pk : m->tab_pk_phi).as<double>();
+  const int64_t ts = (int64_t)2 * nops * 5;
+  const SpmmShape sh = shape_for(g, m->prec, wd);
+  auto base = [&](int k) {
+    EpiArgs<T> ep;
+    ep.ctab = tab + (int64_t)(k - 1) * ts;
+    ep.cgw = b;
+    ep.cmap = m->cmap.as<int32_t>();
+    ep.Sin = k == 1 ? Xr : Yp;
+    ep.Sout = Yp;
+    ep.s0 = 1.0;
+    if (laplacian && m->fin_at[k]) {
+      ep.wv = m->W.as<T>();
+      ep.wld = nops;
+      ep.Xw = Xr;
+    }
+    ep.kclass = WL_KC_MULTI;
+    return ep;
+  };
+  WL_TRY(launch_spmm<T>(g, Xr, m->Kmax == 1 ? nullptr : A, wd, base(1), sh));
+  const T* Pm2 = Xr;
+  T* Pm1 = A;
+  for (int k = 2; k <= m->Kmax; ++k) {
+    EpiArgs<T> ep = base(k);
+    ep.Z = Pm2;
+    T* out = (k == 2) ? Bf : const_cast<T*>(Pm2);
+    WL_TRY(launch_spmm<T>(g, Pm1, k == m->Kmax ? nullptr : out, wd, ep, sh));
+    Pm2 = Pm1;
+    Pm1 = out;
+  }
+  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nops * b + nops))), dim3(256), 0, ctx->stream, n, b, nops,
+                     Yp, Y, W);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+// Block Lanczos of every operator on X (16-column groups) and single-column Lanczos of
+// every operator on the vector of ones, all in lock step: the ones ride in one more
+// 16-column group whose Grams are diagonal (its columns are independent processes of
+// different operators), so one sparse product and one pass of each grouped kernel per
+// step serve both.  Returns false in *done when the shape is not covered.
+template <typename T>
+wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool laplacian, bool* done) {
+  *done = false;
+  wl_graph* g = m->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  const int nops = m->nops;
+  const int G = nops + 1, dgi = nops;
+  if (b != 16 || nops > 16 || !grouped_supported(m->prec, 16, G)) return WL_OK;
+  std::vector<int> Kq(nops), Kd(nops);
+  int K = 1;
+  bool local = true;
+  for (int q = 0; q < nops; ++q) {
+    wl_op op;
+    group_op(m, q, &op);
+    Kq[q] = lanczos_steps(&op, n, 16);
+    Kd[q] = lanczos_steps(&op, n, 1);
+    K = std::max(K, std::max(Kq[q], Kd[q]));
+    local = local && m->desc[q].reorth <= 1;
+  }
+  if (!local || (int64_t)(K + 1) * 16 * 2 > n) return WL_OK;
+  const int wd = G * 16;
+  const int64_t blk = n * wd;
+  WL_TRY(ensure_cmap(m, 16, false));
+  WL_TRY(m->Xpk.ensure((size_t)blk * sizeof(T)));
+  WL_TRY(m->Ypk.ensure((size_t)blk * sizeof(T)));
+  T* Xr = m->Xpk.as<T>();
+  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(blk)), dim3(256), 0, ctx->stream, n, 16, nops, X, Xr);
+  WL_HIP(hipGetLastError());
+  const int bb16 = 16;
+  SmallLayout Ly{bb16, K, (size_t)256};
+  const int64_t gs = (int64_t)((Ly.total() + 1) / 2 * 2);
+  WL_TRY(m->small.ensure((size_t)G * gs * sizeof(double)));
+  WL_TRY(m->basis.ensure((size_t)(K + 1) * blk * sizeof(T)));
+  double* S = m->small.as<double>();
+  T* basis = m->basis.as<T>();
+  const double tol = defl_tol<T>(), ptol = post_tol<T>();
+  // V_0 R0 = Xr per group by CholQR2 (the walk-degree group: each column normalised)
+  WL_TRY(launch_ggram<T>(ctx, n, 16, G, Xr, 0, 1, Xr, S + Ly.G(), gs, nullptr, dgi));
+  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, G, gs,
+                     S + Ly.Ref(), nullptr, 0.0, nullptr, 0.0, nullptr, dgi));
+  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Xr, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, basis, S + Ly.G(),
+                           gs, nullptr, nullptr, dgi));
+  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
+                     G, gs, nullptr, S + Ly.Ref(), ptol, nullptr, 0.0, nullptr, dgi));
+  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, basis, 0, 1, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, basis, nullptr,
+                           gs));
+  const SpmmShape sh = shape_for(g, m->prec, wd);
+  for (int j = 0; j < K; ++j) {
+    T* Vj = basis + (size_t)j * blk;
+    T* Vn = Vj + blk;
+    const T* Vp = j > 0 ? Vj - blk : nullptr;
+    EpiArgs<T> ep;
+    ep.ctab = m->ltab.as<double>();
+    ep.cgw = 16;
+    ep.cmap = m->cmap.as<int32_t>();
+    ep.Z = Vj;
+    if (Vp) {
+      ep.Z2 = Vp;
+      ep.C = S + Ly.B(j - 1);
+      ep.cgs = gs;
+      ep.transC = 1;
+    }
+    ep.kclass = WL_KC_MULTI_LANCZOS;
+    WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
+    const int nbv = j > 0 ? 2 : 1;
+    const T* Vlo = j > 0 ? Vp : Vj;
+    WL_TRY(launch_ggram<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, Vn, S + Ly.P(), gs, nullptr, dgi));
+    WL_TRY(launch_lanczos_proj(ctx, 16, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref(), G, gs));
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,
+                             S + Ly.G(), gs, nullptr, nullptr, dgi));
+    // the walk-degree columns are judged against their own scale before projection
+    // (the diagonal of W'^T W', the last block of P)
+    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), G,
+                       gs, nullptr, S + Ly.Ref(), ptol, S + Ly.Skip(), skip_ratio<T>(), nullptr, dgi,
+                       S + Ly.P() + (size_t)nbv * 256));
+    if (j + 1 == K) {
+      WL_TRY(launch_dcopy_groups(ctx, G, 256, S + Ly.R1(), S + Ly.B(j), gs));
+      break;
+    }
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vn, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, Vn, S + Ly.G(),
+                             gs, nullptr, S + Ly.Skip(), dgi));
+    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                       S + Ly.B(j), G, gs, nullptr, nullptr, 0.0, nullptr, 0.0, S + Ly.Skip(), dgi));
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vn, 0, 1, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, Vn, nullptr, gs,
+                             S + Ly.Skip(), nullptr));
+  }
+  std::vector<double> hS((size_t)G * gs);
+  WL_HIP(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  const size_t bb = 256;
+  std::vector<std::vector<double>> Fq(G);
+  int Kr = 1;
+  auto eff_dim = [](const std::vector<double>& hB, int Kg, size_t e2) {
+    for (int jj = 0; jj + 1 < Kg; ++jj) {  // stop after the first block whose coupling vanished entirely
+      double s2 = 0.0;
+      for (size_t e = 0; e < e2; ++e) s2 += hB[jj * e2 + e] * hB[jj * e2 + e];
+      if (s2 == 0.0) return jj + 1;
+    }
+    return Kg;
+  };
+  for (int q = 0; q < nops; ++q) {
+    const double* Sq = hS.data() + (size_t)q * gs;
+    const int Kg = Kq[q];
+    std::vector<double> hA(Sq + Ly.A(0), Sq + Ly.A(0) + Kg * bb), hB(Sq + Ly.B(0), Sq + Ly.B(0) + Kg * bb);
+    std::vector<double> hR0(Sq + Ly.R0(), Sq + Ly.R0() + bb);
+    for (double v : hA)
+      if (!std::isfinite(v)) {
+        wl_set_error("block Lanczos produced non-finite coefficients (operator %d)", q);
+        return WL_ENUMERIC;
+      }
+    const int Ke = eff_dim(hB, Kg, bb);
+    wl_op op;
+    group_op(m, q, &op);
+    WL_TRY(lanczos_coefficients(&op, Ke, 16, hA, hB, hR0, Fq[q]));
+    Kr = std::max(Kr, Ke);
+  }
+  // the walk-degree group: column q is operator q's own scalar Lanczos process
+  std::vector<std::vector<double>> Fd(nops);
+  {
+    const double* Sd = hS.data() + (size_t)dgi * gs;
+    for (int q = 0; q < nops; ++q) {
+      const int Kg = Kd[q];
+      const size_t d = (size_t)q * 16 + q;
+      std::vector<double> hA(Kg), hB(Kg), hR0(1, Sd[Ly.R0() + d]);
+      for (int jj = 0; jj < Kg; ++jj) {
+        hA[jj] = Sd[Ly.A(jj) + d];
+        hB[jj] = Sd[Ly.B(jj) + d];
+        if (!std::isfinite(hA[jj])) {
+          wl_set_error("Lanczos produced non-finite coefficients (walk degrees of operator %d)", q);
+          return WL_ENUMERIC;
+        }
+      }
+      const int Ke = eff_dim(hB, Kg, 1);
+      wl_op op;
+      group_op(m, q, &op);
+      WL_TRY(lanczos_coefficients(&op, Ke, 1, hA, hB, hR0, Fd[q]));
+      Kr = std::max(Kr, Ke);
+    }
+  }
+  // C_{q,k}: rows [16 k, 16 (k + 1)) of F_q; the walk-degree group's blocks are diagonal
+  // (negated under the Laplacian finish, whose weight there is zero: 0 * 1 - (-V F))
+  std::vector<double> F((size_t)G * Kr * bb, 0.0);
+  for (int q = 0; q < nops; ++q) std::copy(Fq[q].begin(), Fq[q].end(), F.begin() + (size_t)q * Kr * bb);
+  for (int q = 0; q < nops; ++q)
+    for (size_t k = 0; k < Fd[q].size(); ++k)
+      F[((size_t)dgi * Kr + k) * bb + (size_t)q * 16 + q] = laplacian ? -Fd[q][k] : Fd[q][k];
+  WL_TRY(m->coef.ensure(F.size() * sizeof(double)));
+  WL_HIP(hipMemcpyAsync(m->coef.p, F.data(), F.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  T* Wg = nullptr;
+  if (laplacian) {
+    WL_TRY(m->Wg.ensure((size_t)n * G * sizeof(T)));
+    Wg = m->Wg.as<T>();
+    hipLaunchKernelGGL(k_wg<T>, dim3(elem_grid(n * G)), dim3(256), 0, ctx->stream, n, nops, m->W.as<T>(), Wg);
+    WL_HIP(hipGetLastError());
+  }
+  T* Yp = m->Ypk.as<T>();
+  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, basis, blk, Kr, m->coef.as<double>(), (int64_t)Kr * bb,
+                           laplacian ? Xr : nullptr, 0.0, Wg, laplacian ? -1.0 : 1.0, Yp, nullptr, 0));
+  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nops * 16 + nops))), dim3(256), 0, ctx->stream, n, 16,
+                     nops, Yp, Y, W);
+  WL_HIP(hipGetLastError());
+  WL_HIP(hipStreamSynchronize(ctx->stream));  // F is host memory of this call
+  *done = true;
+  return WL_OK;
+}
+
 }  // namespace
 
 wl_status multi_groups_create(wl_op* op, int G, wl_multi** out) {
@@ -419,10 +718,27 @@ wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out) {
     }
     std::vector<double> tab_phi = tab;
     for (size_t e = 4; e < tab_phi.size(); e += 5) tab_phi[e] = 0.0;
+    // packed evaluation with walk degrees: entries [0, nops) as above, entries
+    // [nops, 2 nops) the same operators without finish (the walk-degree columns)
+    std::vector<double> tpk((size_t)m->Kmax * 2 * nops * 5, 0.0), tpk_phi;
+    for (int k = 0; k < m->Kmax; ++k)
+      for (int i = 0; i < nops; ++i)
+        for (int e = 0; e < 5; ++e) {
+          const double v = tab[((size_t)k * nops + i) * 5 + e];
+          tpk[((size_t)k * 2 * nops + i) * 5 + e] = v;
+          tpk[((size_t)k * 2 * nops + nops + i) * 5 + e] = e == 4 ? 0.0 : v;
+        }
+    tpk_phi = tpk;
+    for (size_t e = 4; e < tpk_phi.size(); e += 5) tpk_phi[e] = 0.0;
     s = m->tab.ensure(tab.size() * 8);
     if (s == WL_OK) s = m->tab_phi.ensure(tab.size() * 8);
+    if (s == WL_OK) s = m->tab_pk.ensure(tpk.size() * 8);
+    if (s == WL_OK) s = m->tab_pk_phi.ensure(tpk.size() * 8);
     if (s == WL_OK && (hipMemcpy(m->tab.p, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-                       hipMemcpy(m->tab_phi.p, tab_phi.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess)) {
+                       hipMemcpy(m->tab_phi.p, tab_phi.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                       hipMemcpy(m->tab_pk.p, tpk.data(), tpk.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+                       hipMemcpy(m->tab_pk_phi.p, tpk_phi.data(), tpk.size() * 8, hipMemcpyHostToDevice) !=
+                           hipSuccess)) {
       wl_set_error("wl_multi_create: coefficient upload failed");
       s = WL_EDEVICE;
     }
@@ -459,6 +775,33 @@ wl_status wl_multi_apply(wl_multi* m, const void* d_X, int32_t b, void* d_Y, int
   }
   if (laplacian) WL_TRY(multi_ensure_w<double>(m));
   return multi_dispatch<double>(m, (const double*)d_X, b, (double*)d_Y, laplacian != 0);
+}
+
+wl_status wl_multi_apply_fdeg(wl_multi* m, const void* d_X, int32_t b, void* d_Y, void* d_W, int32_t laplacian) {
+  WL_CHECK(m, WL_EINVAL, "wl_multi_apply_fdeg: handle is null");
+  WL_CHECK(b >= 1 && (int64_t)b * m->nops <= 4096, WL_EINVAL,
+           "wl_multi_apply_fdeg: need 1 <= b and nops * b <= 4096");
+  WL_CHECK(m->g->n == 0 || (d_X && d_Y && d_W && d_X != d_Y && d_X != d_W && d_Y != d_W), WL_EINVAL,
+           "wl_multi_apply_fdeg: bad blocks");
+  DeviceGuard dg(m->g->ctx->device);
+  const int64_t n = m->g->n;
+  if (n == 0) return WL_OK;
+  bool done = false;
+  if (m->prec == WL_FP32) {
+    if (laplacian) WL_TRY(multi_ensure_w<float>(m));
+    if (m->method == WL_M_RECURRENCE && m->nops <= 16)
+      return multi_series_fdeg<float>(m, (const float*)d_X, b, (float*)d_Y, (float*)d_W, laplacian != 0);
+    if (m->method == WL_M_LANCZOS)
+      WL_TRY(multi_lanczos_fdeg<float>(m, (const float*)d_X, b, (float*)d_Y, (float*)d_W, laplacian != 0, &done));
+    if (done) return WL_OK;
+    WL_TRY(multi_dispatch<float>(m, (const float*)d_X, b, (float*)d_Y, laplacian != 0));
+  } else {
+    if (laplacian) WL_TRY(multi_ensure_w<double>(m));
+    if (m->method == WL_M_RECURRENCE && m->nops <= 16)
+      return multi_series_fdeg<double>(m, (const double*)d_X, b, (double*)d_Y, (double*)d_W, laplacian != 0);
+    WL_TRY(multi_dispatch<double>(m, (const double*)d_X, b, (double*)d_Y, laplacian != 0));
+  }
+  return wl_multi_fdeg(m, d_W);  // shapes the packed evaluation does not cover: one call after the other
 }
 
 wl_status wl_multi_fdeg(wl_multi* m, void* d_W) {

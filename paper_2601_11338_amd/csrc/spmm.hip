@@ -125,11 +125,114 @@ __device__ __forceinline__ void add_shfl_xor(Frag<T, VW>& f, int off) {
 }
 
 // Epilogue for row r on columns [col, col + VW) (tile-local column cl).
-template <typename T, int VW, bool MASK>
+// Block-diagonal C term y -= Z2_row(group) C_group for the VW columns of this lane.
+template <typename T, int VW>
+__device__ __forceinline__ void c_term(int64_t r, int ld, int b, int col, int cl, int TILE, const EpiArgs<T>& ep,
+                                       const T* sC, T* y) {
+  const T* z2 = ep.Z2 + r * (int64_t)ld;
+  const int kw = ep.ctab ? ep.cgw : b;                    // rows of C that meet this column
+  if (ep.ctab) z2 += (col / ep.cgw) * ep.cgw;             // the operator's own segment
+  constexpr int ZV = 16 / (int)sizeof(T);                 // values per 16-byte load
+  int k = 0;
+  if ((reinterpret_cast<uintptr_t>(z2) & 15u) == 0) {
+    // the segment in 16-byte loads (the lanes of one row read the same lines)
+    for (; k + ZV <= kw; k += ZV) {
+      const Frag<T, ZV> zf = ldf<T, ZV>(z2 + k);
+#pragma unroll
+      for (int u = 0; u < ZV; ++u)
+#pragma unroll
+        for (int i = 0; i < VW; ++i) y[i] -= zf.v[u] * sC[(k + u) * TILE + cl + i];
+    }
+  }
+  for (; k < kw; ++k) {
+    const T zk = z2[k];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) y[i] -= zk * sC[k * TILE + cl + i];
+  }
+}
+
+// Epilogue with per-column operators (ep.cmap): the VW columns of a lane may belong to
+// different operators, each with its own coefficients and finish.  The caller has
+// returned for lanes past the block (with VW > 1 a fragment lies wholly inside it).
+// Per-column coefficients of one column tile, resolved through ep.cmap once per
+// workgroup into LDS (the epilogue then reads them with a few LDS loads instead of
+// global loads per column and row).  fin holds the finishing operator (-1: none).
+template <typename T, int TILE>
+struct ColCoef {
+  T a[TILE], sc[TILE], z0[TILE], z1[TILE];
+  int fin[TILE];
+};
+
+template <typename T, int TILE>
+__device__ __forceinline__ void stage_col_coef(const EpiArgs<T>& ep, int c0, int b, ColCoef<T, TILE>& cc) {
+  for (int j = threadIdx.x; j < TILE; j += 256) {
+    const int c = c0 + j;
+    const int q = c < b ? ep.cmap[c] : -1;
+    if (q >= 0) {  // else a padding column: all zero
+      const double* k = ep.ctab + 5 * (int64_t)q;
+      cc.a[j] = (T)k[0];
+      cc.z0[j] = (T)k[1];
+      cc.z1[j] = (T)k[2];
+      cc.sc[j] = (T)k[3];
+      cc.fin[j] = ep.wv != nullptr && k[4] != 0.0 ? q : -1;
+    } else {
+      cc.a[j] = T(0);
+      cc.z0[j] = T(0);
+      cc.z1[j] = T(0);
+      cc.sc[j] = T(0);
+      cc.fin[j] = -1;
+    }
+  }
+}
+
+template <typename T, int VW, int TILE>
+__device__ __forceinline__ void epilogue_cols(int64_t r, int ld, int b, int col, int cl, T deg,
+                                              const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC,
+                                              const ColCoef<T, TILE>& cc, T* Y) {
+  const int64_t off = r * (int64_t)ld + col;
+  T y[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) y[i] = cc.a[cl + i] * acc.v[i];
+  if (ep.Z) {
+    Frag<T, VW> z = ldf<T, VW>(ep.Z + off);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) y[i] += (cc.z0[cl + i] + cc.z1[cl + i] * deg) * z.v[i];
+  }
+  if (ep.C) c_term<T, VW>(r, ld, b, col, cl, TILE, ep, sC, y);
+  if (Y) {
+    Frag<T, VW> o;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) o.v[i] = y[i];
+    stf<T, VW>(Y + off, o);
+  }
+  if (ep.Sout) {
+    Frag<T, VW> s, xw;
+    if (ep.Sin)
+      s = ldf_nt<T, VW>(ep.Sin + off);
+    else
+      zero(s);
+    if (ep.wv) xw = ldf_nt<T, VW>(ep.Xw + off);
+    const T s0 = (T)ep.s0;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) {
+      T v = s0 * s.v[i] + cc.sc[cl + i] * y[i];
+      const int q = cc.fin[cl + i];
+      if (q >= 0) v = ep.wv[r * (int64_t)ep.wld + q] * xw.v[i] - v;
+      s.v[i] = v;
+    }
+    stf_nt<T, VW>(ep.Sout + off, s);
+  }
+}
+
+template <typename T, int VW, bool MASK, bool CM, int TILE_>
 __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int cl, int TILE, T deg,
                                          const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC,
-                                         T* Y) {
+                                         const ColCoef<T, TILE_>& cc, T* Y) {
   if (MASK && col >= b) return;
+  if constexpr (CM) {  // a separate instantiation: its registers do not weigh on the others
+    epilogue_cols<T, VW, TILE_>(r, ld, b, col, cl, deg, acc, ep, sC, cc, Y);
+    return;
+  }
   const int64_t off = r * (int64_t)ld + col;
   double ca = ep.a, cb0 = ep.b0, cb1 = ep.b1, csc = ep.sc;
   bool fin = ep.wv != nullptr;
@@ -159,16 +262,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
 #pragma unroll
     for (int i = 0; i < VW; ++i) y[i] += coef * z.v[i];
   }
-  if (ep.C) {
-    const T* z2 = ep.Z2 + r * (int64_t)ld;
-    const int kw = ep.ctab ? ep.cgw : b;                    // rows of C that meet this column
-    if (ep.ctab) z2 += (col / ep.cgw) * ep.cgw;             // the operator's own segment
-    for (int k = 0; k < kw; ++k) {
-      const T zk = z2[k];
-#pragma unroll
-      for (int i = 0; i < VW; ++i) y[i] -= zk * sC[k * TILE + cl + i];
-    }
-  }
+  if (ep.C) c_term<T, VW>(r, ld, b, col, cl, TILE, ep, sC, y);
   if (Y) {
     Frag<T, VW> o;
 #pragma unroll
@@ -240,7 +334,7 @@ constexpr int gather_unroll() {
   return VW == 1 && sizeof(T) == 4 ? 16 : 8;
 }
 
-template <typename T, int VW, int LPN, int G, bool MASK>
+template <typename T, int VW, int LPN, int G, bool MASK, bool CM>
 __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ colidx, int64_t n, int ld, int b,
                                               const T* __restrict__ X, T* Y, EpiArgs<T> ep,
@@ -250,8 +344,13 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sC = reinterpret_cast<T*>(smem_raw);
   __shared__ Frag<T, VW> red[4][LPN];
+  __shared__ ColCoef<T, CM ? TILE : 1> cc;
 
   const int c0 = blockIdx.y * TILE;
+  if constexpr (CM) {
+    stage_col_coef<T, TILE>(ep, c0, b, cc);
+    if (!ep.C) __syncthreads();  // else the C staging below synchronises
+  }
   if (ep.C) {
     const int kw = ep.ctab ? ep.cgw : b;
     for (int e = threadIdx.x; e < kw * TILE; e += 256) {
@@ -300,7 +399,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
       for (int w = 1; w < 4; ++w)
 #pragma unroll
         for (int i = 0; i < VW; ++i) tot.v[i] += red[w][lane].v[i];
-      epilogue<T, VW, MASK>(r, ld, b, col, cl, TILE, (T)(e - s), tot, ep, sC, Y);
+      epilogue<T, VW, MASK, CM>(r, ld, b, col, cl, TILE, (T)(e - s), tot, ep, sC, cc, Y);
     }
     return;
   }
@@ -326,7 +425,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   gather_sum<T, VW, MASK, gather_unroll<T, VW>()>(colidx, s + slot, e, NS, X, ld, col, colok, acc);
 #pragma unroll
   for (int off = LPN; off < G; off <<= 1) add_shfl_xor(acc, off);
-  if (slot == 0) epilogue<T, VW, MASK>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, Y);
+  if (slot == 0) epilogue<T, VW, MASK, CM>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, cc, Y);
 }
 
 template <typename T, int VW, int LPN, int G, bool MASK>
@@ -356,7 +455,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
   if (ep.prepare_only) return WL_OK;
   const int64_t gx = nshort + n_long;
   WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
-  const size_t lds = ep.C ? (size_t)b * TILE * sizeof(T) : 0;
+  const size_t lds = ep.C ? (size_t)(ep.ctab ? ep.cgw : b) * TILE * sizeof(T) : 0;  // rows of C staged
   dim3 grid((unsigned)gx, (unsigned)tiles);
   wl_ctx* ctx = g->ctx;
   KernelStats* ks = nullptr;
@@ -370,8 +469,12 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     }
     WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
   }
-  hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK>), grid, dim3(256), lds, ctx->stream, g->rowptr, g->colidx,
-                     g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
+  if (ep.cmap)
+    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, true>), grid, dim3(256), lds, ctx->stream, g->rowptr,
+                       g->colidx, g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
+  else
+    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, false>), grid, dim3(256), lds, ctx->stream, g->rowptr,
+                       g->colidx, g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
   WL_HIP(hipGetLastError());
   if (ks) {
     WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));
@@ -426,6 +529,10 @@ wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep
     if (lanes == 2) return run_g<T, VW, 2, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes <= 4 && lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 16 == 0) return run_g<T, VW, 16, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    // 17..31 vectors (e.g. 96 FP32 values): with 32 or more lanes per row one 32-lane
+    // segment covers the whole row (idle lanes masked), each neighbour's row gathered by
+    // one group in one go; with fewer the row is cut into column tiles (below)
+    if (lanes > 16 && lanes < 32 && sh.G >= 32) return run_g<T, VW, 32, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
     // 12 vectors (48 FP32 values): one 16-lane segment with the last four lanes idle
     // gathers each neighbour row once, where three 4-lane tiles would gather it thrice
     if (lanes == 12) return run_g<T, VW, 16, true>(g, X, Y, b, ep, sh.G, sh.long_thr);

@@ -211,6 +211,12 @@ struct EpiArgs {
   int cgw = 0;
   int wld = 0;
   int64_t cgs = 0;
+  // Per-column operators (with ctab): column c takes the coefficients ctab[5 cmap[c] ...]
+  // and the finish weight wv[r * wld + cmap[c]] instead of those of c / cgw (cmap[c] < 0:
+  // padding, all coefficients zero).  C stays block diagonal in cgw-wide groups.  This
+  // lets one group of cgw columns hold single columns of different operators (their
+  // walk degrees riding beside the wide blocks).
+  const int32_t* cmap = nullptr;
   // Row-tile order of the short-row blocks (host object, resolved by the launcher):
   // block s of the launch processes row tile map[s] (-1: idle), so that tiles that
   // gather from the same rows can be placed on one XCD.  Null: tile s = block s.
@@ -285,7 +291,11 @@ wl_status launch_chol(wl_ctx* ctx, int b, const double* G, double tol, const dou
                       double* R, double* Rinv, const double* Rprev, double* Bout, int ngraphs = 1,
                       int64_t gs = 0, double* ref_out = nullptr, const double* ref_in = nullptr,
                       double post_tol = 0.0, double* skip_out = nullptr, double skip_ratio = 0.0,
-                      const double* skip_in = nullptr);
+                      const double* skip_in = nullptr, int dg = -1, const double* dref = nullptr);
+// dg: index of a group (workgroup) whose columns are independent single-column
+// processes: its G is taken as diagonal, each column deflated against its own scale
+// (dref, optional: per-group b x b matrices whose diagonal is the column scale of the
+// later check), and no second pass is asked for.
 // skip_out (one double): 1 when the kept pivots satisfy min / max >= skip_ratio (a
 // second CholQR pass would change nothing at working precision), else 0.  skip_in:
 // when *skip_in != 0 the kernel only writes identity factors (R, Rinv) and
@@ -419,10 +429,11 @@ wl_status lanczos_coefficients(const wl_op* op, int Ke, int b, const std::vector
 // Supported: FP32 with gb = 16 (matrix cores) and gb = 1 (any precision, ng <= 8).
 bool grouped_supported(int prec, int gb, int ng);
 // out_q + k gb^2 = (X_k)_q^T Y_q for k < nblk (X_k at X + k sX); groups whose skip flag
-// (at skip + q gs) is set are left alone.
+// (at skip + q gs) is set are left alone.  Group dg (also in launch_gupdate's Gram)
+// holds independent single columns: its off-diagonal entries are set to zero.
 template <typename T>
 wl_status launch_ggram(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk, const T* Y,
-                       double* out, int64_t gs, const double* skip = nullptr);
+                       double* out, int64_t gs, const double* skip = nullptr, int dg = -1);
 // Out_q = (wv ? wv[:, q] : alpha) .* Yin_q + beta sum_k (X_k)_q C_{q,k}, C_{q,k} at
 // C + q cs + k gb^2 (gb x gb row-major); wv is n x ng.  gram_out (optional): Out_q^T Out_q
 // at gram_out + q gs.  Per-group flags: skip (the group's update is elided: in-place
@@ -431,7 +442,7 @@ template <typename T>
 wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int64_t sX, int nblk,
                          const double* C, int64_t cs, const T* Yin, double alpha, const T* wv, double beta, T* Out,
                          double* gram_out, int64_t gs, const double* skip = nullptr,
-                         const double* skip_gram = nullptr);
+                         const double* skip_gram = nullptr, int dg = -1);
 // y_q = x_q (count doubles) for q < ng at stride gs
 wl_status launch_dcopy_groups(wl_ctx* ctx, int ng, int count, const double* x, double* y, int64_t gs);
 // Y (n x ng b) column group q = X (n x b), or X's column group q into Y (n x b)
