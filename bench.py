@@ -64,6 +64,9 @@ def parse():
     p.add_argument("--krylov", type=int, default=30)
     p.add_argument("--arnoldi-steps", type=int, default=60, help="Krylov dimension of the arnoldi-ba1m workload")
     p.add_argument("--block", type=int, default=16)
+    p.add_argument("--gather-ceiling", action="store_true",
+                   help="only measure the machine ceilings: random whole-row gathers from a 10^6-row table "
+                        "(wl_gather_probe) at several row sizes, a plain device copy and a plain read")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device-to-device copy 5 times (reference for HBM counters)")
     p.add_argument("--summarize", metavar="DIR",
@@ -123,6 +126,68 @@ def copy_calibration():
     dt = time.perf_counter() - t0
     print(json.dumps({"copy_bytes_each": 2 * src.numel() * 4, "copies": 5, "seconds": dt,
                       "GBps": 5 * 2 * src.numel() * 4 / dt / 1e9}), flush=True)
+
+
+def gather_ceiling():
+    """The machine ceilings the sparse products are set against: random gathers of whole
+    rows (16 to 512 bytes) of a 10^6-row table, 10^7 gathers per launch with uniformly
+    drawn rows (wl_gather_probe), the same probe reading the table in order, and a plain
+    copy and sum of 2 GiB (torch kernels)."""
+    import ctypes as C
+
+    import torch
+
+    import paper_2601_11338_amd as wl
+
+    ctx = wl.Context(0)
+    rows, count = 1_000_000, 10_000_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    idx = torch.randint(0, rows, (count,), dtype=torch.int32, device="cuda", generator=gen)
+    table = torch.rand(rows * 128, dtype=torch.float32, device="cuda", generator=gen)  # rows of up to 512 B
+    blocks_max = 32768
+    out = torch.empty(blocks_max * 256 * 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    res = {"rows": rows, "gathers_per_launch": count, "gather": []}
+    for rb in (16, 64, 128, 256, 512):
+        for blocks in (8192, blocks_max):
+            ms = C.c_double()
+            wl._lib.check(wl.load().wl_gather_probe(ctx.handle, wl._ptr(table), rows, rb, wl._ptr(idx), count,
+                                                    wl._ptr(out), blocks, 10, C.byref(ms)))
+            t = ms.value * 1e-3
+            lines = -(-rb // 128)
+            res["gather"].append({"row_bytes": rb, "blocks": blocks, "us": t * 1e6,
+                                  "useful_GBps": count * rb / t / 1e9,
+                                  "line_GBps": count * lines * 128 / t / 1e9})
+            log(f"gather {rb:4d} B rows, {blocks} blocks: {t * 1e6:8.1f} us, useful {count * rb / t / 1e9:6.0f} GB/s, "
+                f"128-byte lines {count * lines * 128 / t / 1e9:6.0f} GB/s")
+    # the same probe with rows in order: a plain coalesced read of the table
+    seq = torch.arange(rows, dtype=torch.int32, device="cuda")
+    ms = C.c_double()
+    wl._lib.check(wl.load().wl_gather_probe(ctx.handle, wl._ptr(table), rows, 512, wl._ptr(seq), rows, wl._ptr(out),
+                                            8192, 10, C.byref(ms)))
+    res["read_in_order_GBps"] = rows * 512 / (ms.value * 1e-3) / 1e9
+    log(f"the table's rows in order (512 MB read): {res['read_in_order_GBps']:.0f} GB/s")
+    del table, out, seq
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    a.record()
+    for _ in range(5):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    res["copy_GBps"] = 5 * 2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9
+    s_ = src.sum()
+    a.record()
+    for _ in range(5):
+        s_ = src.sum()
+    b.record()
+    torch.cuda.synchronize()
+    res["sum_GBps"] = 5 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9
+    log(f"copy (read + write of 2 GiB) {res['copy_GBps']:.0f} GB/s, sum of 2 GiB {res['sum_GBps']:.0f} GB/s")
+    print(json.dumps(res), flush=True)
 
 
 def measured_traffic(n, m, width, lanes):
@@ -406,6 +471,12 @@ def run_expv_rmat25(args):
     mass = [float(o.sum()) / float(U0.sum()) for o in outs]
     log(f"recurrence kernel: {launches} launches, avg {avg_ms * 1e3:.1f} us, {achieved:.0f} GB/s algorithmic; "
         f"first-step kernel: {oth[0]} launches; mass ratio {mass}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        u0 = U0[:, 0].double().cpu().numpy()[:, None]
+        del outs
+        cpu = cpu_baseline_expv(rp.cpu().numpy(), ci.cpu().numpy(), n, 0.5, 1.0 / lam, K_in, K_out, b, u0)
     return {
         "metric": METRIC,
         "value": value,
@@ -441,7 +512,30 @@ def run_expv_rmat25(args):
             "alg_bytes_per_launch": kbytes / max(launches, 1),
         },
         "mass_ratio": mass,
+        "cpu_baseline": cpu,
     }
+
+
+def cpu_baseline_expv(rp, ci, n, mu, beta, K_in, K_out, b, u0, degree=4):
+    """The oracle's sparse FP64 series (eq. qrec, row-chunked threaded products) on one
+    of the 32 columns, cut to its first few products: the GPU step applies the degree
+    K_in series K_out times to 32 columns; the rate per edge-vector is taken as what one
+    full step would see on the host (the products dominate; the outer Lanczos' vector
+    work is not timed)."""
+    from oracle import krylov, sparse
+
+    A = sparse.adjacency(n, rp, ci)
+    nt = krylov.threads()
+    coeffs = krylov.exp_coefficients(beta, degree)
+    t0 = time.perf_counter()
+    krylov.series_apply(A, mu, coeffs, u0)
+    dt = time.perf_counter() - t0
+    ev = degree * float(A.nnz)
+    full = K_out * K_in * float(A.nnz) * b / (ev / dt)
+    return {"value": ev / dt / 1e9, "unit": "GEdge·vec/s", "cores": nt, "nproc": os.cpu_count(), "kind": "oracle",
+            "sample": f"FP64 series of degree {degree} (of the GPU's {K_in}) on 1 of the {b} columns, scipy.sparse "
+                      f"products split over {nt} host threads, {dt:.1f} s; at this rate one step ({K_out} outer "
+                      f"products x {K_in} inner x {b} columns) would take {full / 3600:.1f} h"}
 
 
 MLP_SHAPES = [(64, 8), (64,), (64, 64), (64,), (1, 64), (1,)]
@@ -1294,14 +1388,14 @@ def run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g):
             gi = rgraphs[i % len(rgraphs)]
             ops_r = res_ops_on(gi)
             keep.append(ops_r)
-            if i == 0:  # walk degrees of all five (single-column processes) and L V of the fifth
-                fd = wl.Multi(ops_r)
+            if i == 0:  # L V of the fifth operator with the walk degrees of all five beside it:
+                # [16 columns | 5 single-column processes + 11 padding] = one line per row
+                fd = wl.Multi(ops_r[4:] + ops_r[:4])
                 Wr = torch.empty((n, 5), dtype=torch.float32, device="cuda")
                 Y1 = torch.empty((n, b), dtype=torch.float32, device="cuda")
-                ops_r[4].fdeg()
+                fd.apply_fdeg(X, nx=1, out=Y1, out_w=Wr)
                 keep.extend([fd, Wr, Y1])
-                per[i % len(rgraphs)].append(lambda fd=fd, Wr=Wr, Y1=Y1, o=ops_r[4]: (fd.fdeg(out=Wr),
-                                                                                      o.apply_L(X, out=Y1)))
+                per[i % len(rgraphs)].append(lambda fd=fd, Wr=Wr, Y1=Y1: fd.apply_fdeg(X, nx=1, out=Y1, out_w=Wr))
             else:  # L V of a Lanczos pair (32 wide)
                 pm = wl.Multi(ops_r[2 * i - 2:2 * i])
                 Yp = torch.empty((n, 2 * b), dtype=torch.float32, device="cuda")
@@ -1369,7 +1463,8 @@ def run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g):
     res_w = wd if packed else 2 * b
     for k, width, what in ((3, wd, "series steps of the five exponential operators and their walk degrees"),
                            (4, res_w, "Lanczos operator products of the five resolvent operators and their walk "
-                                      "degrees" if packed else "Lanczos operator products of two resolvent operators"),
+                                      "degrees" if packed else "Lanczos operator products of two resolvent operators, "
+                                      "or of one with the five walk-degree processes"),
                            (1, b, "Lanczos operator products of one resolvent operator")):
         nl, kms, kby = [sum(x) for x in zip(*[stats(c, k) for c in ctxs])]
         if nl == 0:
@@ -1453,6 +1548,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.gather_ceiling:
+        gather_ceiling()
         return
     if args.workload == "batch512":
         print(json.dumps(run_batch512(args)), flush=True)

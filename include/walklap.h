@@ -278,6 +278,17 @@ wl_status wl_expv_ws(wl_op* op, const void* d_U0, int32_t b, const double* t, in
 #define WL_NOALLOC_BYTES ((size_t)64 << 20)
 wl_status wl_apply_L_noalloc(wl_op* op, const void* d_X, void* d_Y, int32_t b);
 
+/* ---------------------------------------------------------------- machine ceiling (diagnostic)
+ * wl_gather_probe: the rate at which the device gathers whole table rows at random,
+ * the access pattern of every neighbour gather of a sparse product (Sec. 4.1: the
+ * evaluation is matrix-vector products only).  d_table: rows x row_bytes (row_bytes =
+ * 16 x 1, 2, 4, 8, 16 or 32; 16-byte aligned); d_idx: count int32 row numbers (entries
+ * outside [0, rows) are skipped); d_out: blocks x 256 x 16 bytes of scratch output.
+ * One warm launch, then reps launches of `blocks` workgroups on the context's stream;
+ * *ms = mean time per launch (HIP events).  Nothing is allocated but two events.   */
+wl_status wl_gather_probe(wl_ctx* ctx, const void* d_table, int64_t rows, int32_t row_bytes, const int32_t* d_idx,
+                          int64_t count, void* d_out, int32_t blocks, int32_t reps, double* ms);
+
 /* ---------------------------------------------------------------- multigrid-preconditioned CG
  * The hierarchy of a WL_M_AMG_CG operator (Sec. 4.2), built on the host when the
  * operator is created:
@@ -481,19 +492,22 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
  * nops b = 32 or 64 FP32 values are where the sharing pays most.
  * wl_multi_fdeg: d_W n x nops, column g = phi_g 1.
  * wl_multi_apply_fdeg: both in one evaluation (the walk degrees w_g = phi_g 1 of
- * eq. weighted_laplacian beside phi_g X or L_g X): d_Y as wl_multi_apply, d_W as
- * wl_multi_fdeg (three distinct buffers).  The vectors of ones ride in one extra group
- * of 16 columns, so each step gathers them from the same cache lines as the blocks:
- * truncated series for nops <= 16 and any b; Lanczos operators for FP32, b = 16,
- * nops <= 16 (the ones' group then holds nops independent single-column Lanczos
- * processes with diagonal Grams).  Other shapes run wl_multi_apply, then
- * wl_multi_fdeg.  With laplacian != 0 the finish takes the walk degrees cached by an
- * earlier call (computed first when there are none), as wl_multi_apply does.        */
+ * eq. weighted_laplacian beside phi_g X or L_g X) for the first nx operators
+ * (1 <= nx <= nops) on X and the walk degrees of all nops: d_Y n x (nx b) row-major
+ * (group g < nx as wl_multi_apply), d_W n x nops as wl_multi_fdeg (three distinct
+ * buffers).  The vectors of ones ride in one extra group of 16 columns, so each step
+ * gathers them from the same cache lines as the blocks: truncated series for
+ * nops <= 16 and any b; Lanczos operators for FP32, b = 16, nops <= 16 (the ones'
+ * group then holds nops independent single-column Lanczos processes with diagonal
+ * Grams).  Other shapes run wl_multi_apply, then wl_multi_fdeg (nx = nops only;
+ * WL_EUNSUPPORTED otherwise).  With laplacian != 0 the finish takes the walk degrees
+ * cached by an earlier call (computed first when there are none), as wl_multi_apply
+ * does.                                                                              */
 typedef struct wl_multi wl_multi;
 wl_status wl_multi_create(wl_op* const* ops, int32_t nops, wl_multi** out);
 wl_status wl_multi_apply(wl_multi* multi, const void* d_X, int32_t b, void* d_Y, int32_t laplacian);
 wl_status wl_multi_fdeg(wl_multi* multi, void* d_W);
-wl_status wl_multi_apply_fdeg(wl_multi* multi, const void* d_X, int32_t b, void* d_Y, void* d_W,
+wl_status wl_multi_apply_fdeg(wl_multi* multi, const void* d_X, int32_t b, int32_t nx, void* d_Y, void* d_W,
                               int32_t laplacian);
 wl_status wl_multi_destroy(wl_multi* multi);
 

@@ -649,21 +649,22 @@ class Multi:
         check(load().wl_multi_fdeg(self.handle, _ptr(out)))
         return out
 
-    def apply_fdeg(self, X, laplacian=True, out=None, out_w=None):
-        """(Y, W) in one evaluation: Y n x (nops b) with group g = L_g X (or phi_g X),
-        W n x nops with column g = phi_g 1."""
+    def apply_fdeg(self, X, laplacian=True, out=None, out_w=None, nx=None):
+        """(Y, W) in one evaluation: Y n x (nx b) with group g = L_g X (or phi_g X) for
+        the first nx operators (all by default), W n x nops with column g = phi_g 1."""
         torch = _torch()
         X = X.to(self.dtype).contiguous()
         if X.dim() == 1:
             X = X.view(-1, 1)
         _need(X, "X", self.dtype, (self.graph.n, None))
-        shape = (self.graph.n, X.shape[1] * len(self.ops))
+        nx = len(self.ops) if nx is None else int(nx)
+        shape = (self.graph.n, X.shape[1] * nx)
         out = torch.empty(shape, dtype=self.dtype, device=X.device) if out is None else out
         _need(out, "out", self.dtype, shape)
         wshape = (self.graph.n, len(self.ops))
         out_w = torch.empty(wshape, dtype=self.dtype, device=X.device) if out_w is None else out_w
         _need(out_w, "out_w", self.dtype, wshape)
-        check(load().wl_multi_apply_fdeg(self.handle, _ptr(X), X.shape[1], _ptr(out), _ptr(out_w),
+        check(load().wl_multi_apply_fdeg(self.handle, _ptr(X), X.shape[1], nx, _ptr(out), _ptr(out_w),
                                          1 if laplacian else 0))
         return out, out_w
 

@@ -128,7 +128,8 @@ SIGNATURES = {
     "wl_multi_create": (C.c_int, [vp, i32, C.POINTER(vp)]),
     "wl_multi_apply": (C.c_int, [vp, vp, i32, vp, i32]),
     "wl_multi_fdeg": (C.c_int, [vp, vp]),
-    "wl_multi_apply_fdeg": (C.c_int, [vp, vp, i32, vp, vp, i32]),
+    "wl_multi_apply_fdeg": (C.c_int, [vp, vp, i32, i32, vp, vp, i32]),
+    "wl_gather_probe": (C.c_int, [vp, vp, C.c_int64, i32, vp, C.c_int64, vp, i32, i32, pd]),
     "wl_multi_destroy": (C.c_int, [vp]),
     "wl_batch_create": (C.c_int, [vp, i32, vp, vp, f64, C.POINTER(vp)]),
     "wl_batch_info": (C.c_int, [vp, C.POINTER(i64), C.POINTER(i32), vp, vp]),

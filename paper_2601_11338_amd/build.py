@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwalklap.so")
 
-SOURCES = ["spmm.hip", "blockops.hip", "dense_host.cpp", "api.hip", "estimators.hip", "learned.hip", "batch.hip", "multi.hip", "grouped.hip", "markov.hip", "aaa_host.cpp", "rational.hip", "arnoldi.hip", "amg_host.cpp", "amg.hip"]
+SOURCES = ["spmm.hip", "blockops.hip", "dense_host.cpp", "api.hip", "estimators.hip", "learned.hip", "batch.hip", "multi.hip", "grouped.hip", "markov.hip", "aaa_host.cpp", "rational.hip", "arnoldi.hip", "amg_host.cpp", "amg.hip", "diag.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -32,6 +32,7 @@ constexpr int G1_MAXG = 8;   // groups of single columns
 constexpr int G1_MAXK = 64;  // blocks combined by one single-column update
 constexpr int G16_MAXG = 4;  // 16-wide groups per workgroup (accumulator registers)
 constexpr int G16_LDS_KB = 120;  // gfx950: up to 160 KiB of LDS per workgroup
+constexpr int G16_SPLIT = 12;    // blocks per slice of a long combination (see launch_gupdate)
 
 // ------------------------------------------------------------------ gb = 16 (FP32)
 
@@ -551,6 +552,20 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
   const int E = gb * gb;
   int nparts = 1;
   if constexpr (sizeof(T) == 4) {
+    const bool out_apart = Out + (int64_t)n * ng * 16 <= X || Out >= X + (int64_t)(nblk - 1) * sX + n * ng * 16;
+    if (gb == 16 && nblk > G16_SPLIT && !gram_out && !skip && out_apart) {
+      // a long combination (a recombination over the whole basis): in slices of
+      // G16_SPLIT blocks, each slice adding onto Out, so that a workgroup's staged
+      // coefficients stay small enough for several workgroups per CU
+      for (int k0 = 0; k0 < nblk; k0 += G16_SPLIT) {
+        const int kb = std::min(G16_SPLIT, nblk - k0);
+        const bool first = k0 == 0;
+        WL_TRY(launch_gupdate<T>(ctx, n, gb, ng, X + (int64_t)k0 * sX, sX, kb, C + (int64_t)k0 * E, cs,
+                                 first ? Yin : Out, first ? alpha : 1.0, first ? wv : nullptr, beta, Out, nullptr,
+                                 gs, nullptr, nullptr, dg));
+      }
+      return WL_OK;
+    }
     if (gb == 16) {
       const int ngc = group_chunk(ng, std::max(nblk, 1));
       nparts = gparts(((n + 15) / 16 + 15) / 16, 1024);

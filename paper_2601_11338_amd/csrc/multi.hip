@@ -63,8 +63,8 @@ __global__ void k_replicate(int64_t n, int b, int nops, const T* __restrict__ X,
 // Packed block: X in each of the nops groups of b columns, then a group of 16 columns
 // whose column q < nops is a vector of ones (operator q's walk degrees), zero beyond.
 template <typename T>
-__global__ void k_pack_fdeg(int64_t n, int b, int nops, const T* __restrict__ X, T* __restrict__ Xp) {
-  const int xw = b * nops;
+__global__ void k_pack_fdeg(int64_t n, int b, int nx, int nops, const T* __restrict__ X, T* __restrict__ Xp) {
+  const int xw = b * nx;
   const int64_t wd = (int64_t)xw + 16;
   const int64_t total = n * wd;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
@@ -74,11 +74,11 @@ __global__ void k_pack_fdeg(int64_t n, int b, int nops, const T* __restrict__ X,
   }
 }
 
-// Y (n x nops b) and W (n x nops) out of the packed block
+// Y (n x nx b) and W (n x nops) out of the packed block
 template <typename T>
-__global__ void k_unpack_fdeg(int64_t n, int b, int nops, const T* __restrict__ Yp, T* __restrict__ Y,
+__global__ void k_unpack_fdeg(int64_t n, int b, int nx, int nops, const T* __restrict__ Yp, T* __restrict__ Y,
                               T* __restrict__ W) {
-  const int xw = b * nops;
+  const int xw = b * nx;
   const int64_t wd = (int64_t)xw + 16;
   const int64_t ow = (int64_t)xw + nops;
   const int64_t total = n * ow;
@@ -92,15 +92,15 @@ __global__ void k_unpack_fdeg(int64_t n, int b, int nops, const T* __restrict__ 
   }
 }
 
-// Wg (n x (nops + 1)) = [W | 0]: group-indexed finish weights of the packed Lanczos
-// recombination (the walk-degree group takes no finish)
+// Wg (n x (nx + 1)) = [W_0 .. W_{nx-1} | 0]: group-indexed finish weights of the packed
+// Lanczos recombination (W is n x nops; the walk-degree group takes no finish)
 template <typename T>
-__global__ void k_wg(int64_t n, int nops, const T* __restrict__ W, T* __restrict__ Wg) {
-  const int64_t total = n * (nops + 1);
+__global__ void k_wg(int64_t n, int nx, int nops, const T* __restrict__ W, T* __restrict__ Wg) {
+  const int64_t total = n * (nx + 1);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / (nops + 1);
-    const int c = (int)(i - r * (nops + 1));
-    Wg[i] = c < nops ? W[r * nops + c] : T(0);
+    const int64_t r = i / (nx + 1);
+    const int c = (int)(i - r * (nx + 1));
+    Wg[i] = c < nx ? W[r * nops + c] : T(0);
   }
 }
 
@@ -342,30 +342,31 @@ wl_status multi_dispatch(wl_multi* m, const T* X, int b, T* Y, bool laplacian) {
 // columns take operator q (series: table entry q, with its finish); walk-degree column
 // q takes operator q without finish (series: entry nops + q; Lanczos: q, the same
 // matrix); padding -1.
-wl_status ensure_cmap(wl_multi* m, int b, bool series) {
-  if (m->cmap_b == (series ? b : -b) && m->cmap.p) return WL_OK;
-  const int xw = m->nops * b, wd = xw + 16;
+wl_status ensure_cmap(wl_multi* m, int b, int nx, bool series) {
+  const int key = (series ? 1 : -1) * (b * 128 + nx);
+  if (m->cmap_b == key && m->cmap.p) return WL_OK;
+  const int xw = nx * b, wd = xw + 16;
   std::vector<int32_t> h(wd);
   for (int c = 0; c < wd; ++c)
     h[c] = c < xw ? c / b : (c - xw < m->nops ? (series ? m->nops : 0) + (c - xw) : -1);
   WL_TRY(m->cmap.ensure(h.size() * 4));
   WL_HIP(hipMemcpyAsync(m->cmap.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, m->g->ctx->stream));
   WL_HIP(hipStreamSynchronize(m->g->ctx->stream));  // h is host memory of this call
-  m->cmap_b = series ? b : -b;
+  m->cmap_b = key;
   return WL_OK;
 }
 
 // Truncated series of every operator on X and on the vector of ones together: one
 // sparse product per step over the packed block.
 template <typename T>
-wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool laplacian) {
+wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, int nx, T* Y, T* W, bool laplacian) {
   wl_graph* g = m->g;
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
   const int nops = m->nops;
-  const int wd = nops * b + 16;
+  const int wd = nx * b + 16;
   const size_t bytes = (size_t)n * wd * sizeof(T);
-  WL_TRY(ensure_cmap(m, b, true));
+  WL_TRY(ensure_cmap(m, b, nx, true));
   WL_TRY(m->Xpk.ensure(bytes));
   WL_TRY(m->A.ensure(bytes));
   WL_TRY(m->B.ensure(bytes));
@@ -374,7 +375,7 @@ wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool lap
   T* A = m->A.as<T>();
   T* Bf = m->B.as<T>();
   T* Yp = m->Ypk.as<T>();
-  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(n * wd)), dim3(256), 0, ctx->stream, n, b, nops, X, Xr);
+  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(n * wd)), dim3(256), 0, ctx->stream, n, b, nx, nops, X, Xr);
   WL_HIP(hipGetLastError());
   const double* tab = (laplacian ? m->tab_pk : m->tab_pk_phi).as<double>();
   const int64_t ts = (int64_t)2 * nops * 5;
@@ -406,8 +407,8 @@ wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool lap
     Pm2 = Pm1;
     Pm1 = out;
   }
-  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nops * b + nops))), dim3(256), 0, ctx->stream, n, b, nops,
-                     Yp, Y, W);
+  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nx * b + nops))), dim3(256), 0, ctx->stream, n, b, nx,
+                     nops, Yp, Y, W);
   WL_HIP(hipGetLastError());
   return WL_OK;
 }
@@ -418,33 +419,33 @@ wl_status multi_series_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool lap
 // different operators), so one sparse product and one pass of each grouped kernel per
 // step serve both.  Returns false in *done when the shape is not covered.
 template <typename T>
-wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool laplacian, bool* done) {
+wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, int nx, T* Y, T* W, bool laplacian, bool* done) {
   *done = false;
   wl_graph* g = m->g;
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
   const int nops = m->nops;
-  const int G = nops + 1, dgi = nops;
+  const int G = nx + 1, dgi = nx;
   if (b != 16 || nops > 16 || !grouped_supported(m->prec, 16, G)) return WL_OK;
-  std::vector<int> Kq(nops), Kd(nops);
+  std::vector<int> Kq(nx), Kd(nops);
   int K = 1;
   bool local = true;
   for (int q = 0; q < nops; ++q) {
     wl_op op;
     group_op(m, q, &op);
-    Kq[q] = lanczos_steps(&op, n, 16);
+    if (q < nx) Kq[q] = lanczos_steps(&op, n, 16);
     Kd[q] = lanczos_steps(&op, n, 1);
-    K = std::max(K, std::max(Kq[q], Kd[q]));
+    K = std::max(K, std::max(q < nx ? Kq[q] : 1, Kd[q]));
     local = local && m->desc[q].reorth <= 1;
   }
   if (!local || (int64_t)(K + 1) * 16 * 2 > n) return WL_OK;
   const int wd = G * 16;
   const int64_t blk = n * wd;
-  WL_TRY(ensure_cmap(m, 16, false));
+  WL_TRY(ensure_cmap(m, 16, nx, false));
   WL_TRY(m->Xpk.ensure((size_t)blk * sizeof(T)));
   WL_TRY(m->Ypk.ensure((size_t)blk * sizeof(T)));
   T* Xr = m->Xpk.as<T>();
-  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(blk)), dim3(256), 0, ctx->stream, n, 16, nops, X, Xr);
+  hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(blk)), dim3(256), 0, ctx->stream, n, 16, nx, nops, X, Xr);
   WL_HIP(hipGetLastError());
   const int bb16 = 16;
   SmallLayout Ly{bb16, K, (size_t)256};
@@ -518,7 +519,7 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool la
     }
     return Kg;
   };
-  for (int q = 0; q < nops; ++q) {
+  for (int q = 0; q < nx; ++q) {
     const double* Sq = hS.data() + (size_t)q * gs;
     const int Kg = Kq[q];
     std::vector<double> hA(Sq + Ly.A(0), Sq + Ly.A(0) + Kg * bb), hB(Sq + Ly.B(0), Sq + Ly.B(0) + Kg * bb);
@@ -560,7 +561,7 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool la
   // C_{q,k}: rows [16 k, 16 (k + 1)) of F_q; the walk-degree group's blocks are diagonal
   // (negated under the Laplacian finish, whose weight there is zero: 0 * 1 - (-V F))
   std::vector<double> F((size_t)G * Kr * bb, 0.0);
-  for (int q = 0; q < nops; ++q) std::copy(Fq[q].begin(), Fq[q].end(), F.begin() + (size_t)q * Kr * bb);
+  for (int q = 0; q < nx; ++q) std::copy(Fq[q].begin(), Fq[q].end(), F.begin() + (size_t)q * Kr * bb);
   for (int q = 0; q < nops; ++q)
     for (size_t k = 0; k < Fd[q].size(); ++k)
       F[((size_t)dgi * Kr + k) * bb + (size_t)q * 16 + q] = laplacian ? -Fd[q][k] : Fd[q][k];
@@ -570,14 +571,14 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, T* Y, T* W, bool la
   if (laplacian) {
     WL_TRY(m->Wg.ensure((size_t)n * G * sizeof(T)));
     Wg = m->Wg.as<T>();
-    hipLaunchKernelGGL(k_wg<T>, dim3(elem_grid(n * G)), dim3(256), 0, ctx->stream, n, nops, m->W.as<T>(), Wg);
+    hipLaunchKernelGGL(k_wg<T>, dim3(elem_grid(n * G)), dim3(256), 0, ctx->stream, n, nx, nops, m->W.as<T>(), Wg);
     WL_HIP(hipGetLastError());
   }
   T* Yp = m->Ypk.as<T>();
   WL_TRY(launch_gupdate<T>(ctx, n, 16, G, basis, blk, Kr, m->coef.as<double>(), (int64_t)Kr * bb,
                            laplacian ? Xr : nullptr, 0.0, Wg, laplacian ? -1.0 : 1.0, Yp, nullptr, 0));
-  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nops * 16 + nops))), dim3(256), 0, ctx->stream, n, 16,
-                     nops, Yp, Y, W);
+  hipLaunchKernelGGL(k_unpack_fdeg<T>, dim3(elem_grid(n * (nx * 16 + nops))), dim3(256), 0, ctx->stream, n, 16,
+                     nx, nops, Yp, Y, W);
   WL_HIP(hipGetLastError());
   WL_HIP(hipStreamSynchronize(ctx->stream));  // F is host memory of this call
   *done = true;
@@ -777,10 +778,12 @@ wl_status wl_multi_apply(wl_multi* m, const void* d_X, int32_t b, void* d_Y, int
   return multi_dispatch<double>(m, (const double*)d_X, b, (double*)d_Y, laplacian != 0);
 }
 
-wl_status wl_multi_apply_fdeg(wl_multi* m, const void* d_X, int32_t b, void* d_Y, void* d_W, int32_t laplacian) {
+wl_status wl_multi_apply_fdeg(wl_multi* m, const void* d_X, int32_t b, int32_t nx, void* d_Y, void* d_W,
+                              int32_t laplacian) {
   WL_CHECK(m, WL_EINVAL, "wl_multi_apply_fdeg: handle is null");
   WL_CHECK(b >= 1 && (int64_t)b * m->nops <= 4096, WL_EINVAL,
            "wl_multi_apply_fdeg: need 1 <= b and nops * b <= 4096");
+  WL_CHECK(nx >= 1 && nx <= m->nops, WL_EINVAL, "wl_multi_apply_fdeg: nx must lie in [1, nops]");
   WL_CHECK(m->g->n == 0 || (d_X && d_Y && d_W && d_X != d_Y && d_X != d_W && d_Y != d_W), WL_EINVAL,
            "wl_multi_apply_fdeg: bad blocks");
   DeviceGuard dg(m->g->ctx->device);
@@ -790,18 +793,24 @@ wl_status wl_multi_apply_fdeg(wl_multi* m, const void* d_X, int32_t b, void* d_Y
   if (m->prec == WL_FP32) {
     if (laplacian) WL_TRY(multi_ensure_w<float>(m));
     if (m->method == WL_M_RECURRENCE && m->nops <= 16)
-      return multi_series_fdeg<float>(m, (const float*)d_X, b, (float*)d_Y, (float*)d_W, laplacian != 0);
+      return multi_series_fdeg<float>(m, (const float*)d_X, b, nx, (float*)d_Y, (float*)d_W, laplacian != 0);
     if (m->method == WL_M_LANCZOS)
-      WL_TRY(multi_lanczos_fdeg<float>(m, (const float*)d_X, b, (float*)d_Y, (float*)d_W, laplacian != 0, &done));
+      WL_TRY(multi_lanczos_fdeg<float>(m, (const float*)d_X, b, nx, (float*)d_Y, (float*)d_W, laplacian != 0,
+                                       &done));
     if (done) return WL_OK;
-    WL_TRY(multi_dispatch<float>(m, (const float*)d_X, b, (float*)d_Y, laplacian != 0));
   } else {
     if (laplacian) WL_TRY(multi_ensure_w<double>(m));
     if (m->method == WL_M_RECURRENCE && m->nops <= 16)
-      return multi_series_fdeg<double>(m, (const double*)d_X, b, (double*)d_Y, (double*)d_W, laplacian != 0);
-    WL_TRY(multi_dispatch<double>(m, (const double*)d_X, b, (double*)d_Y, laplacian != 0));
+      return multi_series_fdeg<double>(m, (const double*)d_X, b, nx, (double*)d_Y, (double*)d_W, laplacian != 0);
   }
-  return wl_multi_fdeg(m, d_W);  // shapes the packed evaluation does not cover: one call after the other
+  // shapes the packed evaluation does not cover: one call after the other
+  WL_CHECK(nx == m->nops, WL_EUNSUPPORTED,
+           "wl_multi_apply_fdeg: nx < nops needs the packed evaluation (series, or FP32 Lanczos with b = 16)");
+  if (m->prec == WL_FP32)
+    WL_TRY(multi_dispatch<float>(m, (const float*)d_X, b, (float*)d_Y, laplacian != 0));
+  else
+    WL_TRY(multi_dispatch<double>(m, (const double*)d_X, b, (double*)d_Y, laplacian != 0));
+  return wl_multi_fdeg(m, d_W);
 }
 
 wl_status wl_multi_fdeg(wl_multi* m, void* d_W) {

@@ -144,4 +144,35 @@ def test_argument_checks(ba20k, lib):
     X = torch.zeros((n, 16), dtype=torch.float32, device="cuda")
     Y = torch.empty((n, 16), dtype=torch.float32, device="cuda")
     with pytest.raises(lib.WLError, match="EINVAL"):
-        lib._lib.check(lib.load().wl_multi_apply_fdeg(multi.handle, lib._ptr(X), 16, lib._ptr(Y), lib._ptr(Y), 1))
+        lib._lib.check(lib.load().wl_multi_apply_fdeg(multi.handle, lib._ptr(X), 16, 1, lib._ptr(Y), lib._ptr(Y), 1))
+    with pytest.raises(lib.WLError, match="EINVAL"):
+        lib._lib.check(lib.load().wl_multi_apply_fdeg(multi.handle, lib._ptr(X), 16, 2, lib._ptr(Y), lib._ptr(X), 1))
+
+
+@pytest.mark.parametrize("kind", ["exp", "res"])
+def test_fewer_blocks_than_walk_degrees(ba20k, lib, kind):
+    """nx < nops: L_g X for the first nx operators, walk degrees of all of them (the
+    resolvent layout of the default workload: one operator's block beside all five
+    walk-degree processes, 32 FP32 values per row)."""
+    n, As, g, lam = ba20k
+    print(f"[gpu] multi fdeg nx<nops {kind}", flush=True)
+    mus = [1.0, 0.0, 0.25, 0.5, 0.75]
+    params = [1.0 / lam if kind == "exp" else 0.5 / sparse.rho_Z(As, mu) for mu in mus]
+    ops = [lib.Operator(g, mu, kind, p, dtype=torch.float32, krylov_dim=30) for mu, p in zip(mus, params)]
+    multi = lib.Multi(ops)
+    X = synth.rademacher_block(n, 16, 4)
+    Xd = dev(X, torch.float32)
+    for nx in (1, 2):
+        Y, W = multi.apply_fdeg(Xd, nx=nx)
+        Y, W = host(Y), host(W)
+        assert Y.shape == (n, 16 * nx) and W.shape == (n, 5)
+        for i, (mu, p) in enumerate(zip(mus, params)):
+            wr = sparse.fdeg(As, mu, kind, p)
+            assert np.linalg.norm(W[:, i] - wr) < 1e-5 * np.linalg.norm(wr), (nx, mu)
+            assert float(np.max(np.abs(W[:, i] - wr) / np.abs(wr))) < 1e-5, (nx, mu)
+            if i < nx:
+                pr = sparse.phi_apply(As, mu, kind, p, X)
+                scale = np.linalg.norm(wr[:, None] * X) + np.linalg.norm(pr)
+                single = host(ops[i].apply_L(Xd))
+                assert np.linalg.norm(Y[:, 16 * i:16 * (i + 1)] - (wr[:, None] * X - pr)) < 2e-5 * scale, (nx, mu)
+                assert np.linalg.norm(Y[:, 16 * i:16 * (i + 1)] - single) < 2e-5 * scale, (nx, mu)
