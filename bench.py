@@ -62,7 +62,7 @@ def parse():
                    help="ba1m: independent operator groups run concurrently on this many streams (one library "
                         "context per stream, all borrowing one device CSR)")
     p.add_argument("--krylov", type=int, default=30)
-    p.add_argument("--arnoldi-steps", type=int, default=60, help="Krylov dimension of the arnoldi-ba1m workload")
+    p.add_argument("--arnoldi-steps", type=int, default=20, help="Krylov dimension of the arnoldi-ba1m workload")
     p.add_argument("--block", type=int, default=16)
     p.add_argument("--gather-ceiling", action="store_true",
                    help="only measure the machine ceilings: random whole-row gathers from a 10^6-row table "

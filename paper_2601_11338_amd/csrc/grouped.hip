@@ -547,7 +547,8 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
                          double* gram_out, int64_t gs, const double* skip, const double* skip_gram, int dg) {
   WL_CHECK(grouped_supported(prec_of<T>(), gb, ng), WL_EUNSUPPORTED, "grouped update: unsupported group shape");
   WL_CHECK(nblk >= 0 && nblk <= (gb == 1 ? G1_MAXK : G16_LDS_KB), WL_EINVAL, "grouped update: too many blocks");
-  WL_CHECK(!(skip && gram_out), WL_EINVAL, "grouped update: a skippable update yields no Gram");
+  WL_CHECK(!(skip && gram_out && skip_gram != skip), WL_EINVAL,
+           "grouped update: a skippable update yields a Gram only where it runs (skip_gram = skip)");
   if (n == 0) return WL_OK;
   const int E = gb * gb;
   int nparts = 1;
@@ -601,6 +602,110 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
                        ctx->partials.as<double>(), nparts, ng, 1, E, gram_out, gs, skip_gram, dg, gb);
     WL_HIP(hipGetLastError());
   }
+  return WL_OK;
+}
+
+// ------------------------------------------------------------------ deferred normalisation
+namespace {
+
+// The basis blocks of the lock-step Lanczos are kept as stored blocks W_j with a factor
+// N_j (16 x 16 per group) such that V_j = W_j N_j is orthonormal: the CholQR
+// normalisation is folded into the products that read the block instead of a pass over
+// it.  All small matrices of a group sit gs doubles apart; N_j at Nb + j 256.
+
+// Identity in every group's N_0.
+__global__ void k_eye_groups(double* __restrict__ N0, int64_t gs) {
+  const int64_t o = (int64_t)blockIdx.x * gs;
+  for (int e = threadIdx.x; e < 256; e += blockDim.x) N0[o + e] = (e >> 4) == (e & 15) ? 1.0 : 0.0;
+}
+
+// From the Gram Pt = [W_{j-1} W_j W']^T W' (nbv + 1 blocks of 16 x 16) of the stored blocks:
+// P1 = N_{j-1}^T Pt_1, A = sym(N_j^T Pt_2) (the true projections), and the update
+// coefficients for the stored blocks Cc = [-N_{j-1} P1; -N_j A; I]; ref = max diag of
+// W'^T W' (the block's scale before projection).  One workgroup of 256 per group.
+__global__ __launch_bounds__(256) void k_lanczos_proj_deferred(int nbv, const double* __restrict__ P,
+                                                               const double* __restrict__ Nprev,
+                                                               const double* __restrict__ Ncur,
+                                                               double* __restrict__ Aout, double* __restrict__ Cc,
+                                                               int64_t gs, double* __restrict__ ref_out) {
+  const int64_t go = (int64_t)blockIdx.x * gs;
+  P += go;
+  Aout += go;
+  Cc += go;
+  const double* Np = nbv == 2 ? Nprev + go : nullptr;
+  const double* Nc = Ncur + go;
+  __shared__ double sP1[256], sA[256];
+  const int t = threadIdx.x, i = t >> 4, j = t & 15;
+  const double* Pt1 = P;                       // [W_{j-1}]^T W' (nbv = 2)
+  const double* Pt2 = P + (nbv - 1) * 256;     // W_j^T W'
+  // true projections: rows of N^T Pt
+  double a = 0.0, p1 = 0.0;
+  for (int k = 0; k < 16; ++k) {
+    a += Nc[k * 16 + i] * Pt2[k * 16 + j];
+    if (Np) p1 += Np[k * 16 + i] * Pt1[k * 16 + j];
+  }
+  sA[t] = a;
+  sP1[t] = p1;
+  __syncthreads();
+  const double as = 0.5 * (sA[i * 16 + j] + sA[j * 16 + i]);
+  __syncthreads();
+  sA[t] = as;
+  Aout[t] = as;
+  __syncthreads();
+  // Cc blocks for the stored blocks
+  double c1 = 0.0, c2 = 0.0;
+  for (int k = 0; k < 16; ++k) {
+    if (Np) c1 += Np[i * 16 + k] * sP1[k * 16 + j];
+    c2 += Nc[i * 16 + k] * sA[k * 16 + j];
+  }
+  if (nbv == 2) Cc[t] = -c1;
+  Cc[(nbv - 1) * 256 + t] = -c2;
+  Cc[nbv * 256 + t] = i == j ? 1.0 : 0.0;
+  if (t == 0 && ref_out) {
+    const double* Gp = P + nbv * 256;
+    double m = 0.0;
+    for (int d = 0; d < 16; ++d) m = fmax(m, Gp[d * 16 + d]);
+    ref_out[go] = m;
+  }
+}
+
+// After the step's CholQR: N_{j+1} = skip ? Ri1 : Ri2 (the block was normalised
+// explicitly by Ri1 only where a second pass was needed), and the three-term
+// coefficient of the next product for the stored W_j: Ct = N_j B_j^T (16 x 16).
+__global__ __launch_bounds__(256) void k_lanczos_next(const double* __restrict__ skip, const double* __restrict__ Ri1,
+                                                      const double* __restrict__ Ri2, const double* __restrict__ Ncur,
+                                                      const double* __restrict__ B, double* __restrict__ Nnext,
+                                                      double* __restrict__ Ct, int64_t gs) {
+  const int64_t go = (int64_t)blockIdx.x * gs;
+  const int t = threadIdx.x, i = t >> 4, j = t & 15;
+  const bool sk = skip[go] != 0.0;
+  Nnext[go + t] = sk ? Ri1[go + t] : Ri2[go + t];
+  double c = 0.0;
+  for (int k = 0; k < 16; ++k) c += Ncur[go + i * 16 + k] * B[go + j * 16 + k];
+  Ct[go + t] = c;
+}
+
+}  // namespace
+
+wl_status launch_eye_groups(wl_ctx* ctx, int ng, double* N0, int64_t gs) {
+  hipLaunchKernelGGL(k_eye_groups, dim3(ng), dim3(256), 0, ctx->stream, N0, gs);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status launch_lanczos_proj_deferred(wl_ctx* ctx, int ng, int nbv, const double* P, const double* Nprev,
+                                       const double* Ncur, double* Aout, double* Cc, int64_t gs, double* ref_out) {
+  WL_CHECK(nbv == 1 || nbv == 2, WL_EINVAL, "lanczos projection: bad sizes");
+  hipLaunchKernelGGL(k_lanczos_proj_deferred, dim3(ng), dim3(256), 0, ctx->stream, nbv, P, Nprev, Ncur, Aout, Cc, gs,
+                     ref_out);
+  WL_HIP(hipGetLastError());
+  return WL_OK;
+}
+
+wl_status launch_lanczos_next(wl_ctx* ctx, int ng, const double* skip, const double* Ri1, const double* Ri2,
+                              const double* Ncur, const double* B, double* Nnext, double* Ct, int64_t gs) {
+  hipLaunchKernelGGL(k_lanczos_next, dim3(ng), dim3(256), 0, ctx->stream, skip, Ri1, Ri2, Ncur, B, Nnext, Ct, gs);
+  WL_HIP(hipGetLastError());
   return WL_OK;
 }
 

@@ -165,6 +165,115 @@ void group_op(const wl_multi* m, int q, wl_op* op) {
   op->K = m->K[q];
 }
 
+// Where a group's small matrices sit: SmallLayout Ly from the group's base (groups gs
+// doubles apart), then the deferred-normalisation factors N_j (j = 0..K) and the
+// three-term coefficient of the next product.
+struct LockLayout {
+  SmallLayout Ly;
+  int64_t noff, ctoff, gs;
+  explicit LockLayout(int K) : Ly{16, K, (size_t)256} {
+    noff = (int64_t)((Ly.total() + 1) / 2 * 2);
+    ctoff = noff + (int64_t)(K + 1) * 256;
+    gs = ctoff + 256;
+  }
+  int64_t N(int j) const { return noff + (int64_t)j * 256; }
+};
+
+// K steps of G block Lanczos processes of 16 columns in lock step on Xr (n x 16 G), one
+// sparse product per step for all (Sec. 4.1), with local reorthogonalisation against
+// the two previous blocks and CholQR with deflation.  Deferred normalisation: slot j of
+// the basis holds W_j with V_j = W_j N_j orthonormal (N_j from the step's CholQR), and
+// the products, Grams and updates that read W_j apply N_j on the small side, so the
+// normalising pass over the block is made only where a second CholQR pass is needed.
+// Group dg (or -1) holds independent single-column processes (diagonal Grams); cmap
+// (or null) maps columns to the operators of ltab.
+template <typename T>
+wl_status lockstep_lanczos(wl_multi* m, const T* Xr, int G, int dg, int K, const LockLayout& L, T* basis,
+                           double* S, const int32_t* cmap) {
+  wl_graph* g = m->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  const SmallLayout& Ly = L.Ly;
+  const int64_t gs = L.gs;
+  const int wd = G * 16;
+  const int64_t blk = n * wd;
+  const double tol = defl_tol<T>(), ptol = post_tol<T>();
+  // V_0 R0 = Xr per group by CholQR2 (the walk-degree group: each column normalised)
+  WL_TRY(launch_ggram<T>(ctx, n, 16, G, Xr, 0, 1, Xr, S + Ly.G(), gs, nullptr, dg));
+  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, G, gs,
+                     S + Ly.Ref(), nullptr, 0.0, nullptr, 0.0, nullptr, dg));
+  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Xr, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, basis, S + Ly.G(),
+                           gs, nullptr, nullptr, dg));
+  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
+                     G, gs, nullptr, S + Ly.Ref(), ptol, nullptr, 0.0, nullptr, dg));
+  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, basis, 0, 1, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, basis, nullptr,
+                           gs));
+  WL_TRY(launch_eye_groups(ctx, G, S + L.N(0), gs));
+  const SpmmShape sh = shape_for(g, m->prec, wd);
+  for (int j = 0; j < K; ++j) {
+    T* Vj = basis + (size_t)j * blk;
+    T* Vn = Vj + blk;
+    const T* Vp = j > 0 ? Vj - blk : nullptr;
+    // W' = Op_q(V_j) - V_{j-1} B_{j-1,q}^T = Op_q(W_j) N_j - W_{j-1} (N_{j-1} B_{j-1}^T)
+    EpiArgs<T> ep;
+    ep.ctab = m->ltab.as<double>();
+    ep.cgw = 16;
+    ep.cmap = cmap;
+    ep.cgs = gs;
+    ep.Z = Vj;
+    if (j > 0) ep.Nm = S + L.N(j);  // N_0 = I: V_0 is stored normalised
+    if (Vp) {
+      ep.Z2 = Vp;
+      ep.C = S + L.ctoff;
+      ep.transC = 0;
+    }
+    ep.kclass = wd >= 32 ? WL_KC_MULTI_LANCZOS : WL_KC_OTHER_SPMM;
+    WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
+    const int nbv = j > 0 ? 2 : 1;
+    const T* Vlo = j > 0 ? Vp : Vj;
+    WL_TRY(launch_ggram<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, Vn, S + Ly.P(), gs, nullptr, dg));
+    WL_TRY(launch_lanczos_proj_deferred(ctx, G, nbv, S + Ly.P(), j > 0 ? S + L.N(j - 1) : nullptr, S + L.N(j),
+                                        S + Ly.A(j), S + Ly.Cc(), gs, S + Ly.Ref()));
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,
+                             S + Ly.G(), gs, nullptr, nullptr, dg));
+    // the walk-degree columns are judged against their own scale before projection
+    // (the diagonal of W'^T W', the last block of P)
+    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), G,
+                       gs, nullptr, S + Ly.Ref(), ptol, S + Ly.Skip(), skip_ratio<T>(), nullptr, dg,
+                       S + Ly.P() + (size_t)nbv * 256));
+    if (j + 1 == K) {
+      WL_TRY(launch_dcopy_groups(ctx, G, 256, S + Ly.R1(), S + Ly.B(j), gs));
+      break;
+    }
+    // only groups whose first factor was ill conditioned normalise the block now (and
+    // take a second CholQR pass); the others keep W with N_{j+1} = R1^{-1}
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vn, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, Vn, S + Ly.G(),
+                             gs, S + Ly.Skip(), S + Ly.Skip(), dg));
+    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
+                       S + Ly.B(j), G, gs, nullptr, nullptr, 0.0, nullptr, 0.0, S + Ly.Skip(), dg));
+    WL_TRY(launch_lanczos_next(ctx, G, S + Ly.Skip(), S + Ly.Ri1(), S + Ly.Ri2(), S + L.N(j), S + Ly.B(j),
+                               S + L.N(j + 1), S + L.ctoff, gs));
+  }
+  return WL_OK;
+}
+
+// Coefficients of the stored blocks from a group's true ones: C_j <- N_j C_j (16 x 16
+// blocks, j < Ke; hS the group's small matrices on the host).
+void apply_deferred(const double* hSq, const LockLayout& L, int Ke, std::vector<double>& F) {
+  std::vector<double> t(256);
+  for (int j = 0; j < Ke; ++j) {
+    const double* N = hSq + L.N(j);
+    double* C = F.data() + (size_t)j * 256;
+    for (int r = 0; r < 16; ++r)
+      for (int c = 0; c < 16; ++c) {
+        double a = 0.0;
+        for (int k = 0; k < 16; ++k) a += N[r * 16 + k] * C[k * 16 + c];
+        t[r * 16 + c] = a;
+      }
+    std::copy(t.begin(), t.end(), C);
+  }
+}
+
 // Per-operator evaluation into the wide output (shapes the grouped kernels do not
 // cover, or a Krylov space small enough to need full reorthogonalisation).
 template <typename T>
@@ -186,9 +295,10 @@ wl_status multi_lanczos_each(wl_multi* m, const T* X, int b, T* Y, const T* wv) 
 
 // All groups' block Lanczos in lock step on the wide block Xr (n x nops b, every group
 // holding the same X), then Y = V F per group (with the Laplacian finish
-// Y_q = wv_q .* Xr_q - V F_q when wv is given).
+// Y_q = wv_q .* Xr_q - V F_q when wv is given); groups of single columns (any
+// precision), each basis block normalised in place.
 template <typename T>
-wl_status multi_lanczos(wl_multi* m, const T* X, const T* Xr, int b, T* Y, const T* wv) {
+wl_status multi_lanczos_plain(wl_multi* m, const T* X, const T* Xr, int b, T* Y, const T* wv) {
   wl_graph* g = m->g;
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
@@ -291,6 +401,83 @@ wl_status multi_lanczos(wl_multi* m, const T* X, const T* Xr, int b, T* Y, const
     wl_op op;
     group_op(m, q, &op);
     WL_TRY(lanczos_coefficients(&op, Ke, b, hA, hB, hR0, Fq[q]));
+    Keq[q] = Ke;
+    Kr = std::max(Kr, Ke);
+  }
+  // C_{q,k} = rows [k b, (k+1) b) of F_q (zero past the group's own dimension)
+  std::vector<double> F((size_t)G * Kr * bb, 0.0);
+  for (int q = 0; q < G; ++q)
+    std::copy(Fq[q].begin(), Fq[q].end(), F.begin() + (size_t)q * Kr * bb);
+  WL_TRY(m->coef.ensure(F.size() * sizeof(double)));
+  WL_HIP(hipMemcpyAsync(m->coef.p, F.data(), F.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  WL_TRY(launch_gupdate<T>(ctx, n, b, G, basis, blk, Kr, m->coef.as<double>(), (int64_t)Kr * bb, wv ? Xr : nullptr,
+                           0.0, wv, wv ? -1.0 : 1.0, Y, nullptr, 0));
+  WL_HIP(hipStreamSynchronize(ctx->stream));  // F is host memory of this call
+  return WL_OK;
+}
+
+// All groups' block Lanczos in lock step on the wide block Xr (n x nops b, every group
+// holding the same X), then Y = V F per group (with the Laplacian finish
+// Y_q = wv_q .* Xr_q - V F_q when wv is given).
+template <typename T>
+wl_status multi_lanczos(wl_multi* m, const T* X, const T* Xr, int b, T* Y, const T* wv) {
+  wl_graph* g = m->g;
+  wl_ctx* ctx = g->ctx;
+  const int64_t n = g->n;
+  const int G = m->nops;
+  std::vector<int> Kq(G);
+  int K = 1;
+  for (int q = 0; q < G; ++q) {
+    wl_op op;
+    group_op(m, q, &op);
+    Kq[q] = lanczos_steps(&op, n, b);
+    K = std::max(K, Kq[q]);
+  }
+  bool local = true;
+  for (int q = 0; q < G; ++q) local = local && m->desc[q].reorth <= 1;
+  if (!grouped_supported(m->prec, b, G) || (int64_t)(K + 1) * b * 2 > n || !local)
+    return multi_lanczos_each<T>(m, X, b, Y, wv);
+  if (b != 16) return multi_lanczos_plain<T>(m, X, Xr, b, Y, wv);
+  const int wd = G * b;
+  const int64_t blk = n * wd;
+  const LockLayout L(K);
+  const SmallLayout& Ly = L.Ly;
+  const int64_t gs = L.gs;
+  WL_TRY(m->small.ensure((size_t)G * gs * sizeof(double)));
+  WL_TRY(m->basis.ensure((size_t)(K + 1) * blk * sizeof(T)));
+  double* S = m->small.as<double>();
+  T* basis = m->basis.as<T>();
+  WL_TRY(lockstep_lanczos<T>(m, Xr, G, -1, K, L, basis, S, nullptr));
+  std::vector<double> hS((size_t)G * gs);
+  WL_HIP(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  const size_t bb = (size_t)b * b;
+  std::vector<std::vector<double>> Fq(G);
+  std::vector<int> Keq(G);
+  int Kr = 1;
+  for (int q = 0; q < G; ++q) {
+    const double* Sq = hS.data() + (size_t)q * gs;
+    const int Kg = Kq[q];
+    std::vector<double> hA(Sq + Ly.A(0), Sq + Ly.A(0) + Kg * bb), hB(Sq + Ly.B(0), Sq + Ly.B(0) + Kg * bb);
+    std::vector<double> hR0(Sq + Ly.R0(), Sq + Ly.R0() + bb);
+    int Ke = Kg;  // stop after the first block whose coupling vanished entirely
+    for (int jj = 0; jj + 1 < Kg; ++jj) {
+      double s2 = 0.0;
+      for (size_t e = 0; e < bb; ++e) s2 += hB[jj * bb + e] * hB[jj * bb + e];
+      if (s2 == 0.0) {
+        Ke = jj + 1;
+        break;
+      }
+    }
+    for (double v : hA)
+      if (!std::isfinite(v)) {
+        wl_set_error("block Lanczos produced non-finite coefficients (operator %d)", q);
+        return WL_ENUMERIC;
+      }
+    wl_op op;
+    group_op(m, q, &op);
+    WL_TRY(lanczos_coefficients(&op, Ke, b, hA, hB, hR0, Fq[q]));
+    apply_deferred(Sq, L, Ke, Fq[q]);  // for the stored blocks W_j = V_j N_j^{-1}
     Keq[q] = Ke;
     Kr = std::max(Kr, Ke);
   }
@@ -447,64 +634,14 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, int nx, T* Y, T* W,
   T* Xr = m->Xpk.as<T>();
   hipLaunchKernelGGL(k_pack_fdeg<T>, dim3(elem_grid(blk)), dim3(256), 0, ctx->stream, n, 16, nx, nops, X, Xr);
   WL_HIP(hipGetLastError());
-  const int bb16 = 16;
-  SmallLayout Ly{bb16, K, (size_t)256};
-  const int64_t gs = (int64_t)((Ly.total() + 1) / 2 * 2);
+  const LockLayout L(K);
+  const SmallLayout& Ly = L.Ly;
+  const int64_t gs = L.gs;
   WL_TRY(m->small.ensure((size_t)G * gs * sizeof(double)));
   WL_TRY(m->basis.ensure((size_t)(K + 1) * blk * sizeof(T)));
   double* S = m->small.as<double>();
   T* basis = m->basis.as<T>();
-  const double tol = defl_tol<T>(), ptol = post_tol<T>();
-  // V_0 R0 = Xr per group by CholQR2 (the walk-degree group: each column normalised)
-  WL_TRY(launch_ggram<T>(ctx, n, 16, G, Xr, 0, 1, Xr, S + Ly.G(), gs, nullptr, dgi));
-  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, G, gs,
-                     S + Ly.Ref(), nullptr, 0.0, nullptr, 0.0, nullptr, dgi));
-  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Xr, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, basis, S + Ly.G(),
-                           gs, nullptr, nullptr, dgi));
-  WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(), S + Ly.R0(),
-                     G, gs, nullptr, S + Ly.Ref(), ptol, nullptr, 0.0, nullptr, dgi));
-  WL_TRY(launch_gupdate<T>(ctx, n, 16, G, basis, 0, 1, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, basis, nullptr,
-                           gs));
-  const SpmmShape sh = shape_for(g, m->prec, wd);
-  for (int j = 0; j < K; ++j) {
-    T* Vj = basis + (size_t)j * blk;
-    T* Vn = Vj + blk;
-    const T* Vp = j > 0 ? Vj - blk : nullptr;
-    EpiArgs<T> ep;
-    ep.ctab = m->ltab.as<double>();
-    ep.cgw = 16;
-    ep.cmap = m->cmap.as<int32_t>();
-    ep.Z = Vj;
-    if (Vp) {
-      ep.Z2 = Vp;
-      ep.C = S + Ly.B(j - 1);
-      ep.cgs = gs;
-      ep.transC = 1;
-    }
-    ep.kclass = WL_KC_MULTI_LANCZOS;
-    WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
-    const int nbv = j > 0 ? 2 : 1;
-    const T* Vlo = j > 0 ? Vp : Vj;
-    WL_TRY(launch_ggram<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, Vn, S + Ly.P(), gs, nullptr, dgi));
-    WL_TRY(launch_lanczos_proj(ctx, 16, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref(), G, gs));
-    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,
-                             S + Ly.G(), gs, nullptr, nullptr, dgi));
-    // the walk-degree columns are judged against their own scale before projection
-    // (the diagonal of W'^T W', the last block of P)
-    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, nullptr, S + Ly.Ri1(), nullptr, S + Ly.R1(), G,
-                       gs, nullptr, S + Ly.Ref(), ptol, S + Ly.Skip(), skip_ratio<T>(), nullptr, dgi,
-                       S + Ly.P() + (size_t)nbv * 256));
-    if (j + 1 == K) {
-      WL_TRY(launch_dcopy_groups(ctx, G, 256, S + Ly.R1(), S + Ly.B(j), gs));
-      break;
-    }
-    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vn, 0, 1, S + Ly.Ri1(), gs, nullptr, 0.0, nullptr, 1.0, Vn, S + Ly.G(),
-                             gs, nullptr, S + Ly.Skip(), dgi));
-    WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R2(), S + Ly.Ri2(), S + Ly.R1(),
-                       S + Ly.B(j), G, gs, nullptr, nullptr, 0.0, nullptr, 0.0, S + Ly.Skip(), dgi));
-    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vn, 0, 1, S + Ly.Ri2(), gs, nullptr, 0.0, nullptr, 1.0, Vn, nullptr, gs,
-                             S + Ly.Skip(), nullptr));
-  }
+  WL_TRY(lockstep_lanczos<T>(m, Xr, G, dgi, K, L, basis, S, m->cmap.as<int32_t>()));
   std::vector<double> hS((size_t)G * gs);
   WL_HIP(hipMemcpyAsync(hS.data(), S, hS.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
   WL_HIP(hipStreamSynchronize(ctx->stream));
@@ -533,6 +670,7 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, int nx, T* Y, T* W,
     wl_op op;
     group_op(m, q, &op);
     WL_TRY(lanczos_coefficients(&op, Ke, 16, hA, hB, hR0, Fq[q]));
+    apply_deferred(Sq, L, Ke, Fq[q]);  // for the stored blocks W_j = V_j N_j^{-1}
     Kr = std::max(Kr, Ke);
   }
   // the walk-degree group: column q is operator q's own scalar Lanczos process
@@ -562,9 +700,12 @@ wl_status multi_lanczos_fdeg(wl_multi* m, const T* X, int b, int nx, T* Y, T* W,
   // (negated under the Laplacian finish, whose weight there is zero: 0 * 1 - (-V F))
   std::vector<double> F((size_t)G * Kr * bb, 0.0);
   for (int q = 0; q < nx; ++q) std::copy(Fq[q].begin(), Fq[q].end(), F.begin() + (size_t)q * Kr * bb);
+  const double* Sd = hS.data() + (size_t)dgi * gs;
   for (int q = 0; q < nops; ++q)
-    for (size_t k = 0; k < Fd[q].size(); ++k)
-      F[((size_t)dgi * Kr + k) * bb + (size_t)q * 16 + q] = laplacian ? -Fd[q][k] : Fd[q][k];
+    for (size_t k = 0; k < Fd[q].size(); ++k) {
+      const double f = Sd[L.N((int)k) + q * 16 + q] * Fd[q][k];  // stored block: diagonal N_k
+      F[((size_t)dgi * Kr + k) * bb + (size_t)q * 16 + q] = laplacian ? -f : f;
+    }
   WL_TRY(m->coef.ensure(F.size() * sizeof(double)));
   WL_HIP(hipMemcpyAsync(m->coef.p, F.data(), F.size() * 8, hipMemcpyHostToDevice, ctx->stream));
   T* Wg = nullptr;

@@ -154,6 +154,35 @@ __device__ __forceinline__ void c_term(int64_t r, int ld, int b, int col, int cl
 // Epilogue with per-column operators (ep.cmap): the VW columns of a lane may belong to
 // different operators, each with its own coefficients and finish.  The caller has
 // returned for lanes past the block (with VW > 1 a fragment lies wholly inside it).
+// Deferred normalisation: y (this lane's VW columns of a 16-column group) <- u N with u
+// the group's 16 values (its 16 / VW consecutive lanes exchange theirs) and N the
+// group's block staged in LDS as sN[k * TILE + tile column].
+template <typename T, int VW>
+__device__ __forceinline__ void right_factor(T* y, int cl, int TILE, const T* sN) {
+  constexpr int LG = 16 / VW;  // lanes holding one group's row segment
+  const int lane = threadIdx.x & 63;
+  const int base = lane & ~(LG - 1);
+  T out[VW];
+#pragma unroll
+  for (int i = 0; i < VW; ++i) out[i] = T(0);
+#pragma unroll
+  for (int t = 0; t < LG; ++t) {  // lane base + t's VW values, rows t VW .. of N
+    T ut[VW];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) ut[k] = __shfl(y[k], base + t, 64);
+#pragma unroll
+    for (int k = 0; k < VW; ++k)
+#pragma unroll
+      for (int i = 0; i < VW; ++i) out[i] += ut[k] * sN[(t * VW + k) * TILE + cl + i];
+  }
+#pragma unroll
+  for (int i = 0; i < VW; ++i) y[i] = out[i];
+}
+
+// Epilogue variants (template bits of the kernel): per-column operators (ep.cmap) and
+// the deferred-normalisation right factor (ep.Nm).
+constexpr int EPI_COLS = 1, EPI_NFAC = 2;
+
 // Per-column coefficients of one column tile, resolved through ep.cmap once per
 // workgroup into LDS (the epilogue then reads them with a few LDS loads instead of
 // global loads per column and row).  fin holds the finishing operator (-1: none).
@@ -185,10 +214,10 @@ __device__ __forceinline__ void stage_col_coef(const EpiArgs<T>& ep, int c0, int
   }
 }
 
-template <typename T, int VW, int TILE>
+template <typename T, int VW, int TILE, bool NF>
 __device__ __forceinline__ void epilogue_cols(int64_t r, int ld, int b, int col, int cl, T deg,
                                               const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC,
-                                              const ColCoef<T, TILE>& cc, T* Y) {
+                                              const T* sN, const ColCoef<T, TILE>& cc, T* Y) {
   const int64_t off = r * (int64_t)ld + col;
   T y[VW];
 #pragma unroll
@@ -198,6 +227,7 @@ __device__ __forceinline__ void epilogue_cols(int64_t r, int ld, int b, int col,
 #pragma unroll
     for (int i = 0; i < VW; ++i) y[i] += (cc.z0[cl + i] + cc.z1[cl + i] * deg) * z.v[i];
   }
+  if constexpr (NF && VW > 1) right_factor<T, VW>(y, cl, TILE, sN);
   if (ep.C) c_term<T, VW>(r, ld, b, col, cl, TILE, ep, sC, y);
   if (Y) {
     Frag<T, VW> o;
@@ -224,13 +254,13 @@ __device__ __forceinline__ void epilogue_cols(int64_t r, int ld, int b, int col,
   }
 }
 
-template <typename T, int VW, bool MASK, bool CM, int TILE_>
+template <typename T, int VW, bool MASK, int E, int TILE_>
 __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int cl, int TILE, T deg,
-                                         const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC,
+                                         const Frag<T, VW>& acc, const EpiArgs<T>& ep, const T* sC, const T* sN,
                                          const ColCoef<T, TILE_>& cc, T* Y) {
   if (MASK && col >= b) return;
-  if constexpr (CM) {  // a separate instantiation: its registers do not weigh on the others
-    epilogue_cols<T, VW, TILE_>(r, ld, b, col, cl, deg, acc, ep, sC, cc, Y);
+  if constexpr ((E & EPI_COLS) != 0) {  // separate instantiations: their registers do not weigh on the others
+    epilogue_cols<T, VW, TILE_, (E & EPI_NFAC) != 0>(r, ld, b, col, cl, deg, acc, ep, sC, sN, cc, Y);
     return;
   }
   const int64_t off = r * (int64_t)ld + col;
@@ -262,6 +292,7 @@ __device__ __forceinline__ void epilogue(int64_t r, int ld, int b, int col, int 
 #pragma unroll
     for (int i = 0; i < VW; ++i) y[i] += coef * z.v[i];
   }
+  if constexpr ((E & EPI_NFAC) != 0 && VW > 1) right_factor<T, VW>(y, cl, TILE, sN);
   if (ep.C) c_term<T, VW>(r, ld, b, col, cl, TILE, ep, sC, y);
   if (Y) {
     Frag<T, VW> o;
@@ -334,7 +365,7 @@ constexpr int gather_unroll() {
   return VW == 1 && sizeof(T) == 4 ? 16 : 8;
 }
 
-template <typename T, int VW, int LPN, int G, bool MASK, bool CM>
+template <typename T, int VW, int LPN, int G, bool MASK, int E>
 __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ colidx, int64_t n, int ld, int b,
                                               const T* __restrict__ X, T* Y, EpiArgs<T> ep,
@@ -344,6 +375,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sC = reinterpret_cast<T*>(smem_raw);
   __shared__ Frag<T, VW> red[4][LPN];
+  constexpr bool CM = (E & EPI_COLS) != 0;
   __shared__ ColCoef<T, CM ? TILE : 1> cc;
 
   const int c0 = blockIdx.y * TILE;
@@ -368,8 +400,22 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
       }
       sC[e] = (T)v;
     }
-    __syncthreads();
   }
+  // deferred normalisation factor: group q's block of Nm, row k, tile column j
+  T* sN = sC + (ep.C ? (ep.ctab ? ep.cgw : b) * TILE : 0);
+  if (ep.Nm) {
+    for (int e = threadIdx.x; e < 16 * TILE; e += 256) {
+      const int k = e / TILE, j = e - (e / TILE) * TILE;
+      const int c = c0 + j;
+      double v = 0.0;
+      if (c < b) {
+        const int q = c / 16, jc = c - q * 16;
+        v = ep.Nm[q * ep.cgs + k * 16 + jc];
+      }
+      sN[e] = (T)v;
+    }
+  }
+  if (ep.C || ep.Nm) __syncthreads();
   const int lane = threadIdx.x & 63;
   const int v = lane % LPN;
   const int cl = v * VW;
@@ -399,7 +445,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
       for (int w = 1; w < 4; ++w)
 #pragma unroll
         for (int i = 0; i < VW; ++i) tot.v[i] += red[w][lane].v[i];
-      epilogue<T, VW, MASK, CM>(r, ld, b, col, cl, TILE, (T)(e - s), tot, ep, sC, cc, Y);
+      epilogue<T, VW, MASK, E>(r, ld, b, col, cl, TILE, (T)(e - s), tot, ep, sC, sN, cc, Y);
     }
     return;
   }
@@ -425,7 +471,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int32_t* __restrict__ rowptr
   gather_sum<T, VW, MASK, gather_unroll<T, VW>()>(colidx, s + slot, e, NS, X, ld, col, colok, acc);
 #pragma unroll
   for (int off = LPN; off < G; off <<= 1) add_shfl_xor(acc, off);
-  if (slot == 0) epilogue<T, VW, MASK, CM>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, cc, Y);
+  if (slot == 0) epilogue<T, VW, MASK, E>(r, ld, b, col, cl, TILE, (T)(e - s), acc, ep, sC, sN, cc, Y);
 }
 
 template <typename T, int VW, int LPN, int G, bool MASK>
@@ -455,7 +501,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
   if (ep.prepare_only) return WL_OK;
   const int64_t gx = nshort + n_long;
   WL_CHECK(gx < (1ll << 31) && tiles < 65536, WL_ERANGE, "spmm grid too large");
-  const size_t lds = ep.C ? (size_t)(ep.ctab ? ep.cgw : b) * TILE * sizeof(T) : 0;  // rows of C staged
+  const size_t lds = ((ep.C ? (size_t)(ep.ctab ? ep.cgw : b) : 0) + (ep.Nm ? 16 : 0)) * TILE * sizeof(T);  // C, N
   dim3 grid((unsigned)gx, (unsigned)tiles);
   wl_ctx* ctx = g->ctx;
   KernelStats* ks = nullptr;
@@ -469,12 +515,25 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
     }
     WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
   }
-  if (ep.cmap)
-    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, true>), grid, dim3(256), lds, ctx->stream, g->rowptr,
-                       g->colidx, g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
-  else
-    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, false>), grid, dim3(256), lds, ctx->stream, g->rowptr,
-                       g->colidx, g->n, b, b, X, Y, epx, g->long_rows.as<int32_t>(), n_long, long_thr);
+  const int32_t* lr = g->long_rows.as<int32_t>();
+  if constexpr (VW == 4) {  // the right factor exists for 16-byte vectors of FP32 only
+    if (ep.Nm && ep.cmap)
+      hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, EPI_COLS | EPI_NFAC>), grid, dim3(256), lds, ctx->stream,
+                         g->rowptr, g->colidx, g->n, b, b, X, Y, epx, lr, n_long, long_thr);
+    else if (ep.Nm)
+      hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, EPI_NFAC>), grid, dim3(256), lds, ctx->stream, g->rowptr,
+                         g->colidx, g->n, b, b, X, Y, epx, lr, n_long, long_thr);
+  }
+  if (ep.Nm && VW != 4) {
+    wl_set_error("spmm: the deferred-normalisation factor needs FP32 16-byte vectors");
+    return WL_EINTERNAL;
+  }
+  if (!ep.Nm && ep.cmap)
+    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, EPI_COLS>), grid, dim3(256), lds, ctx->stream, g->rowptr,
+                       g->colidx, g->n, b, b, X, Y, epx, lr, n_long, long_thr);
+  else if (!ep.Nm)
+    hipLaunchKernelGGL((k_spmm<T, VW, LPN, G, MASK, 0>), grid, dim3(256), lds, ctx->stream, g->rowptr,
+                       g->colidx, g->n, b, b, X, Y, epx, lr, n_long, long_thr);
   WL_HIP(hipGetLastError());
   if (ks) {
     WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));

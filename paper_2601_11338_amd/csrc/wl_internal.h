@@ -217,6 +217,11 @@ struct EpiArgs {
   // lets one group of cgw columns hold single columns of different operators (their
   // walk degrees riding beside the wide blocks).
   const int32_t* cmap = nullptr;
+  // Deferred normalisation (with ctab): the gathered-plus-diagonal part u of a row is
+  // multiplied from the right by its cgw x cgw group block of Nm (row-major, group q's
+  // at Nm + q * cgs) before the C term: y = u N_q - Z2 C_q.  Needs 16-byte vectors and
+  // cgw = 16.
+  const double* Nm = nullptr;
   // Row-tile order of the short-row blocks (host object, resolved by the launcher):
   // block s of the launch processes row tile map[s] (-1: idle), so that tiles that
   // gather from the same rows can be placed on one XCD.  Null: tile s = block s.
@@ -445,6 +450,14 @@ wl_status launch_gupdate(wl_ctx* ctx, int64_t n, int gb, int ng, const T* X, int
                          const double* skip_gram = nullptr, int dg = -1);
 // y_q = x_q (count doubles) for q < ng at stride gs
 wl_status launch_dcopy_groups(wl_ctx* ctx, int ng, int count, const double* x, double* y, int64_t gs);
+// Deferred normalisation of the lock-step Lanczos (16-wide groups): stored blocks W_j
+// with factors N_j (V_j = W_j N_j).  N_0 = I; the projection from the stored blocks'
+// Gram; the next factor and three-term coefficient N_j B_j^T after each CholQR.
+wl_status launch_eye_groups(wl_ctx* ctx, int ng, double* N0, int64_t gs);
+wl_status launch_lanczos_proj_deferred(wl_ctx* ctx, int ng, int nbv, const double* P, const double* Nprev,
+                                       const double* Ncur, double* Aout, double* Cc, int64_t gs, double* ref_out);
+wl_status launch_lanczos_next(wl_ctx* ctx, int ng, const double* skip, const double* Ri1, const double* Ri2,
+                              const double* Ncur, const double* B, double* Nnext, double* Ct, int64_t gs);
 // Y (n x ng b) column group q = X (n x b), or X's column group q into Y (n x b)
 template <typename T>
 wl_status launch_group_copy(wl_ctx* ctx, int64_t n, int b, int ng, int q, const T* X, T* Y, bool into_group);
