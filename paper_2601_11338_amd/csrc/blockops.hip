@@ -460,6 +460,131 @@ __global__ __launch_bounds__(256) void k_update_mfma16(int64_t n, const float* X
   partials[(int64_t)blockIdx.x * 256 + threadIdx.x] = red[threadIdx.x];
 }
 
+// The same for n x 32 FP32 blocks: the 32 x 32 product as 2 x 2 tiles of 16 on
+// v_mfma_f32_16x16x4f32.  Lane l loads the 16 bytes at columns 16 h + 4 (l / 16)
+// (h = 0, 1) of chunk row l % 16; product step (h, s) takes component s of half h as
+// the A operand (the columns {16 h + 4 g + s : g = 0..3}) against the B operand
+// C_k[16 h + 4 (l / 16) + s][16 t + l % 16] of output tile t, lane-ordered in LDS
+// (4 KiB per block, at most UPD32_MAXK blocks per launch: longer combinations are
+// chained launches that accumulate into Out).  Lane l holds result rows
+// 4 (l / 16) + v of the columns l % 16 and 16 + l % 16; the optional Gram Out^T Out
+// (FP64 matrix cores) takes its three distinct 16 x 16 tiles from the same registers.
+// Each workgroup writes one full 32 x 32 partial.
+constexpr int UPD32_MAXK = 12;
+
+template <bool GRAM>
+__global__ __launch_bounds__(256) void k_update_mfma32(int64_t n, const float* X, int64_t sX, int nblk,
+                                                       const double* __restrict__ C, const float* Yin, double alpha,
+                                                       const float* __restrict__ wv, double beta, float* Out,
+                                                       double* __restrict__ partials,
+                                                       const double* __restrict__ skip,
+                                                       const double* __restrict__ skip_gram) {
+  if (skip && *skip != 0.0) return;  // identity update the caller elides
+  extern __shared__ float4 sCl[];     // [block][tile t][half h][lane], nblk x 4 KiB
+  __shared__ double red[3][256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, c = lane & 15;
+  for (int e = threadIdx.x; e < nblk * 256; e += 256) {
+    const int k = e >> 8, th = (e >> 6) & 3, l = e & 63;
+    const int t = th >> 1, h = th & 1, gg = l >> 4, cc = l & 15;
+    const double* Ck = C + (int64_t)k * 1024 + (16 * h + 4 * gg) * 32 + 16 * t + cc;
+    sCl[e] = make_float4((float)Ck[0], (float)Ck[32], (float)Ck[64], (float)Ck[96]);
+  }
+  __syncthreads();
+  const bool gram = GRAM && !(skip_gram && *skip_gram != 0.0);
+  const float tb = (float)beta, ta = (float)alpha;
+  v4d g00 = {0.0, 0.0, 0.0, 0.0}, g01 = g00, g11 = g00;
+  const int64_t nchunks = (n + 15) / 16;
+  const int64_t cstride = (int64_t)gridDim.x * 4;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
+    const int64_t r0 = ch * 16;
+    const bool okA = r0 + c < n;
+    const float* xa = X + (r0 + c) * 32 + 4 * g;
+    v4f d0 = {0.f, 0.f, 0.f, 0.f}, d1 = d0;
+    for (int k0 = 0; k0 < nblk; k0 += 4) {
+      float4 x[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          x[u][h] = (okA && k0 + u < nblk) ? *reinterpret_cast<const float4*>(xa + (int64_t)(k0 + u) * sX + 16 * h)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (k0 + u >= nblk) break;
+        const float4* bk = sCl + (k0 + u) * 256 + lane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float4 b0 = bk[h * 64], b1 = bk[128 + h * 64];
+          d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].x, b0.x, d0, 0, 0, 0);
+          d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].x, b1.x, d1, 0, 0, 0);
+          d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].y, b0.y, d0, 0, 0, 0);
+          d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].y, b1.y, d1, 0, 0, 0);
+          d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].z, b0.z, d0, 0, 0, 0);
+          d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].z, b1.z, d1, 0, 0, 0);
+          d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].w, b0.w, d0, 0, 0, 0);
+          d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u][h].w, b1.w, d1, 0, 0, 0);
+        }
+      }
+    }
+    float o0[4], o1[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      o0[v] = tb * d0[v];
+      o1[v] = tb * d1[v];
+    }
+    if (Yin) {  // clamped loads, zero weight past n
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = min(r0 + 4 * g + v, n - 1);
+        const float y0 = Yin[row * 32 + c], y1 = Yin[row * 32 + 16 + c];
+        const float wq = wv ? wv[row] : ta;
+        if (r0 + 4 * g + v < n) {
+          o0[v] += wq * y0;
+          o1[v] += wq * y1;
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 4 * g + v;
+      if (row < n) {
+        Out[row * 32 + c] = o0[v];
+        Out[row * 32 + 16 + c] = o1[v];
+      }
+    }
+    if (gram) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double a = (double)o0[v], b = (double)o1[v];
+        g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, g00, 0, 0, 0);
+        g01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, g01, 0, 0, 0);
+        g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, g11, 0, 0, 0);
+      }
+    }
+  }
+  if (!gram) return;  // uniform over the workgroup
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int idx = (4 * v + g) * 16 + c;  // FP64 16x16x4 output layout
+        red[0][idx] = (w == 0 ? 0.0 : red[0][idx]) + g00[v];
+        red[1][idx] = (w == 0 ? 0.0 : red[1][idx]) + g01[v];
+        red[2][idx] = (w == 0 ? 0.0 : red[2][idx]) + g11[v];
+      }
+    }
+    __syncthreads();
+  }
+  // the 32 x 32 partial: [[G00, G01], [G01^T, G11]]
+  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+  double* P = partials + (int64_t)blockIdx.x * 1024;
+  P[i * 32 + j] = red[0][threadIdx.x];
+  P[i * 32 + 16 + j] = red[1][threadIdx.x];
+  P[(16 + j) * 32 + i] = red[1][threadIdx.x];
+  P[(16 + i) * 32 + 16 + j] = red[2][threadIdx.x];
+}
+
 template <typename T, int B>
 struct RowVec {
   T v[B];
@@ -1336,6 +1461,44 @@ wl_status update_B(wl_ctx* ctx, int64_t n, const T* X, int ldx, int64_t sX, int 
         hipLaunchKernelGGL(k_update_mfma16<false>, dim3((unsigned)grid), dim3(256), lds, ctx->stream, n,
                            (const float*)X, sX, nblk, C, (const float*)Yin, alpha, (const float*)wv, beta,
                            (float*)Out, nullptr, skip, nullptr);
+        WL_HIP(hipGetLastError());
+      }
+      return WL_OK;
+    }
+  }
+  if constexpr (sizeof(T) == 4 && B == 32) {
+    const bool al = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Out) |
+                      reinterpret_cast<uintptr_t>(Yin)) & 15u) == 0 && (sX % 4) == 0;
+    // chained launches overwrite Out before the later blocks are read: Out must not
+    // be one of them
+    const uintptr_t xo = reinterpret_cast<uintptr_t>(X), oo = reinterpret_cast<uintptr_t>(Out);
+    const bool chain_alias = nblk > UPD32_MAXK && oo >= xo &&
+                             oo < xo + ((uintptr_t)(nblk - 1) * (uintptr_t)sX + (uintptr_t)n * 32) * sizeof(float);
+    if (bx == 32 && by == 32 && ldx == 32 && ldy == 32 && al && !(skip && gram_out) && !chain_alias) {
+      const int64_t nchunks = (n + 15) / 16;
+      int64_t grid = (nchunks + 15) / 16;  // about four chunks per wave
+      if (grid > 1024) grid = 1024;
+      if (grid < 1) grid = 1;
+      if (gram_out) WL_TRY(ctx->partials.ensure((size_t)grid * 1024 * sizeof(double)));
+      for (int k0 = 0; k0 < nblk; k0 += UPD32_MAXK) {
+        const int kb = std::min(UPD32_MAXK, nblk - k0);
+        const bool first = k0 == 0, last = k0 + kb == nblk;
+        const float* Xk = (const float*)X + (int64_t)k0 * sX;
+        const float* Yk = first ? (const float*)Yin : (const float*)Out;
+        const double ak = first ? alpha : 1.0;
+        const float* wk = first ? (const float*)wv : nullptr;
+        const size_t lds = (size_t)kb * 256 * sizeof(float4);
+        if (last && gram_out) {
+          hipLaunchKernelGGL(k_update_mfma32<true>, dim3((unsigned)grid), dim3(256), lds, ctx->stream, n, Xk, sX, kb,
+                             C + (int64_t)k0 * 1024, Yk, ak, wk, beta, (float*)Out, ctx->partials.as<double>(), skip,
+                             skip_gram);
+          WL_HIP(hipGetLastError());
+          hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(1024), 1), dim3(256), 0, ctx->stream,
+                             ctx->partials.as<double>(), (int)grid, 32, 32, 32, gram_out, skip_gram);
+        } else {
+          hipLaunchKernelGGL(k_update_mfma32<false>, dim3((unsigned)grid), dim3(256), lds, ctx->stream, n, Xk, sX, kb,
+                             C + (int64_t)k0 * 1024, Yk, ak, wk, beta, (float*)Out, nullptr, skip, nullptr);
+        }
         WL_HIP(hipGetLastError());
       }
       return WL_OK;

@@ -33,10 +33,6 @@ constexpr int RK_MAXM = 32;       // columns of Omega (2M <= 64, the block-width
 constexpr int RK_THREADS = 256;   // 8 rows x 32 columns per pass
 constexpr int RK_BLOCKS = 1024;   // grid of the row reductions (partials per block)
 
-struct ColCoef {
-  double re[RK_MAXM];
-  double im[RK_MAXM];
-};
 
 // Sum of per-block partials (nblk x K, row-major) into out[K], one workgroup per value,
 // fixed summation order.
@@ -118,13 +114,14 @@ __global__ void k_rk_shift_dot(int64_t n, int M, double a, double b, const T* __
 // With dre/dim given the third sum is ||d (.) r||^2 (the residual of the original system
 // when r is that of the symmetrised one).
 template <typename T>
-__global__ void k_rk_xr(int64_t n, int M, ColCoef al, const T* __restrict__ P, const T* __restrict__ Q,
+__global__ void k_rk_xr(int64_t n, int M, const double* __restrict__ al, const T* __restrict__ P,
+                        const T* __restrict__ Q,
                         T* __restrict__ X, T* __restrict__ R, const T* __restrict__ dre, const T* __restrict__ dim,
                         double* __restrict__ part) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   double v[3] = {0.0, 0.0, 0.0};
   if (c < M) {
-    const double ar = al.re[c], ai = al.im[c];
+    const double ar = al[c], ai = al[RK_MAXM + c];
     for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
       const int64_t o = r * 2 * M + c;
       const double pr = P[o], pi = P[o + M], qr = Q[o], qi = Q[o + M];
@@ -207,11 +204,12 @@ __global__ void k_fl_scale(int64_t n, int M, const T* __restrict__ dre, const T*
 
 // p = r + beta p and V = d (.) p in one pass
 template <typename T>
-__global__ void k_fl_dir(int64_t n, int M, ColCoef be, const T* __restrict__ dre, const T* __restrict__ dim,
+__global__ void k_fl_dir(int64_t n, int M, const double* __restrict__ be, const T* __restrict__ dre,
+                         const T* __restrict__ dim,
                          const T* __restrict__ R, T* __restrict__ P, T* __restrict__ V) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   if (c >= M) return;
-  const double br = be.re[c], bi = be.im[c];
+  const double br = be[c], bi = be[RK_MAXM + c];
   for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
     const int64_t o = r * 2 * M + c;
     const double pr0 = P[o], pi0 = P[o + M];
@@ -247,10 +245,11 @@ __global__ void k_fl_shift_dot(int64_t n, int M, const T* __restrict__ dre, cons
 
 // p = r + beta p (complex beta per column)
 template <typename T>
-__global__ void k_rk_dir(int64_t n, int M, ColCoef be, const T* __restrict__ R, T* __restrict__ P) {
+__global__ void k_rk_dir(int64_t n, int M, const double* __restrict__ be, const T* __restrict__ R,
+                         T* __restrict__ P) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   if (c >= M) return;
-  const double br = be.re[c], bi = be.im[c];
+  const double br = be[c], bi = be[RK_MAXM + c];
   for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
     const int64_t o = r * 2 * M + c;
     const double pr = P[o], pi = P[o + M];
@@ -281,6 +280,105 @@ __global__ void k_rk_pad(int64_t n, int M, int Mp, const T* __restrict__ src, T*
   }
 }
 
+// ---- COCG recurrence coefficients on the device.  Per column c < M (one thread each)
+// the state holds rho (complex), the initial norm, the active flag and the step
+// coefficients alpha, beta, so that no iteration waits for the host; the host reads
+// the summary (columns still open, worst open residual, worst converged residual,
+// breakdown flag) one iteration behind, while the next iteration runs.
+struct CgState {
+  double al[2 * RK_MAXM], be[2 * RK_MAXM];  // [re | im]
+  double rho_re[RK_MAXM], rho_im[RK_MAXM], nrm0[RK_MAXM], active[RK_MAXM];
+  double res_open, res_done, open, err;       // summary of the last update
+};
+
+__device__ double block_max64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// From the initial sums: flat (symmetrised systems) s = [r^T r (complex) | ||u||^2],
+// else s = [||u||^2]; rho = r^T r, nrm0 = ||u||.
+__global__ __launch_bounds__(64) void k_cg_setup(int M, int flat, const double* __restrict__ s, CgState* st) {
+  const int c = threadIdx.x;
+  double open = 0.0;
+  if (c < M) {
+    const double re = s[c], im = flat ? s[M + c] : 0.0, u2 = flat ? s[2 * M + c] : s[c];
+    st->rho_re[c] = re;
+    st->rho_im[c] = im;
+    st->nrm0[c] = sqrt(u2);
+    st->active[c] = u2 > 0.0 ? 1.0 : 0.0;
+    st->al[c] = st->al[RK_MAXM + c] = st->be[c] = st->be[RK_MAXM + c] = 0.0;
+    open = st->active[c];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) open += __shfl_xor(open, off, 64);
+  if (c == 0) {
+    st->open = open;
+    st->res_open = st->res_done = st->err = 0.0;
+  }
+}
+
+// alpha = rho / p^T (K - xi) p from s = [p^T q (complex)]; breakdown (p^T q = 0 in an
+// open column) sets err = 1 and leaves that column's step at zero
+__global__ __launch_bounds__(64) void k_cg_alpha(int M, const double* __restrict__ s, CgState* st) {
+  const int c = threadIdx.x;
+  if (c >= M) return;
+  double ar = 0.0, ai = 0.0;
+  if (st->active[c] != 0.0) {
+    const double pr = s[c], pi = s[M + c], den = pr * pr + pi * pi;
+    if (den == 0.0) {
+      st->err = 1.0;
+    } else {  // (rho_re + i rho_im) / (pr + i pi)
+      ar = (st->rho_re[c] * pr + st->rho_im[c] * pi) / den;
+      ai = (st->rho_im[c] * pr - st->rho_re[c] * pi) / den;
+    }
+  }
+  st->al[c] = ar;
+  st->al[RK_MAXM + c] = ai;
+}
+
+// From s = [r^T r (complex) | residual norm^2]: columns at or below tol close (their
+// later steps are zero); open ones take beta = r^T r / rho and rho = r^T r.
+__global__ __launch_bounds__(64) void k_cg_beta(int M, double tol, const double* __restrict__ s, CgState* st) {
+  const int c = threadIdx.x;
+  double worst = 0.0, done = 0.0, open = 0.0, bad = 0.0;
+  if (c < M) {
+    double br = 0.0, bi = 0.0;
+    if (st->active[c] != 0.0) {
+      const double res = sqrt(s[2 * M + c]) / st->nrm0[c];
+      if (!isfinite(res)) {
+        bad = 1.0;
+      } else if (res <= tol) {
+        st->active[c] = 0.0;
+        done = res;
+      } else {
+        const double rr = s[c], ri = s[M + c];
+        const double den = st->rho_re[c] * st->rho_re[c] + st->rho_im[c] * st->rho_im[c];
+        br = (rr * st->rho_re[c] + ri * st->rho_im[c]) / den;
+        bi = (ri * st->rho_re[c] - rr * st->rho_im[c]) / den;
+        st->rho_re[c] = rr;
+        st->rho_im[c] = ri;
+        worst = res;
+        open = 1.0;
+      }
+    }
+    st->be[c] = br;
+    st->be[RK_MAXM + c] = bi;
+  }
+  worst = block_max64(worst);
+  done = block_max64(done);
+  bad = block_max64(bad);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) open += __shfl_xor(open, off, 64);
+  if (c == 0) {
+    st->res_open = worst;
+    st->res_done = fmax(st->res_done, done);
+    st->open = open;
+    if (bad != 0.0) st->err = 2.0;
+  }
+}
+
 int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RK_BLOCKS, (n + 7) / 8)); }
 
 template <typename T>
@@ -293,13 +391,47 @@ struct RkWork {
   int nb = 0;        // blocks in the basis
   DevBuf dsmall;     // device doubles: Grams, coefficients
   DevBuf part, sums;  // row-reduction partials and their sums
+  DevBuf cg;          // COCG state (CgState)
+  double* hsum = nullptr;      // pinned host: two slots of the COCG summary (4 doubles each)
+  hipEvent_t ev[2] = {nullptr, nullptr};
   wl_multi* groups_wide = nullptr;  // the operator on 2M columns as 16-column groups
   wl_multi* groups_narrow = nullptr;  // ... on M columns
   ~RkWork() {
     multi_groups_destroy(groups_wide);
     multi_groups_destroy(groups_narrow);
+    if (hsum) (void)hipHostFree(hsum);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
+
+// Device sums of K values from the row-reduction partials (no host copy).
+template <typename T>
+void rk_finish(RkWork<T>& W, int K) {
+  k_rk_finish<<<K, RK_THREADS, 0, W.ctx->stream>>>(grid_rows(W.n), K, W.part.template as<double>(),
+                                                   W.sums.template as<double>());
+}
+
+// The COCG summary of the last coefficient update into pinned slot k (asynchronous,
+// event recorded); rk_cg_read waits for slot k and returns {res_open, res_done, open, err}.
+template <typename T>
+wl_status rk_cg_post(RkWork<T>& W, int k) {
+  if (!W.hsum) {
+    WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&W.hsum), 8 * sizeof(double), hipHostMallocDefault));
+    for (auto& e : W.ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  const CgState* st = W.cg.template as<CgState>();
+  WL_HIP(hipMemcpyAsync(W.hsum + 4 * k, &st->res_open, 4 * sizeof(double), hipMemcpyDeviceToHost, W.ctx->stream));
+  WL_HIP(hipEventRecord(W.ev[k], W.ctx->stream));
+  return WL_OK;
+}
+
+template <typename T>
+wl_status rk_cg_read(RkWork<T>& W, int k, double* out) {
+  WL_HIP(hipEventSynchronize(W.ev[k]));
+  for (int i = 0; i < 4; ++i) out[i] = W.hsum[4 * k + i];
+  return WL_OK;
+}
 
 // Y = L X on cols columns: the column-group runner when it covers the shape (16-column
 // groups of a Lanczos operator), else the operator's own product on the whole block.
@@ -314,16 +446,6 @@ wl_status rk_apply(RkWork<T>& W, const T* X, int cols, T* Y) {
   return phi_apply_impl<T>(W.op, X, Y, cols, W.op->w.template as<T>(), X);
 }
 
-template <typename T>
-wl_status rk_sums(RkWork<T>& W, int K, std::vector<double>& out) {
-  k_rk_finish<<<K, RK_THREADS, 0, W.ctx->stream>>>(grid_rows(W.n), K, W.part.template as<double>(),
-                                                   W.sums.template as<double>());
-  WL_HIP(hipGetLastError());
-  out.resize(K);
-  WL_HIP(hipMemcpyAsync(out.data(), W.sums.p, (size_t)K * 8, hipMemcpyDeviceToHost, W.ctx->stream));
-  WL_HIP(hipStreamSynchronize(W.ctx->stream));
-  return WL_OK;
-}
 
 // Host copy of the nb*bx x by Gram of the basis blocks [0, nblk) against Y.
 template <typename T>
@@ -402,6 +524,10 @@ wl_status rk_append(RkWork<T>& W, T* Wb, std::vector<double>* Rout) {
 }
 
 // COCG on (L - xi I) X = U, U real n x M, X complex as an n x 2M block [Re | Im].
+// The recurrence coefficients live on the device (k_cg_*); the host learns that every
+// column has converged one iteration late (the summary of iteration it - 1 is read while
+// iteration it runs), so at most one extra iteration is made, a no-op for the closed
+// columns (their steps are zero).
 template <typename T>
 wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R, T* P, T* Q, double tol,
                    int max_iters, int* iters, double* res_out) {
@@ -409,78 +535,56 @@ wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R
   const int64_t n = W.n;
   wl_ctx* ctx = W.ctx;
   const int grid = grid_rows(n);
-  using cd = std::complex<double>;
-  std::vector<double> s;
+  CgState* st = W.cg.template as<CgState>();
+  const double* sums = W.sums.template as<double>();
   k_rk_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, X, R, P, W.part.template as<double>());
   WL_HIP(hipGetLastError());
-  WL_TRY(rk_sums<T>(W, M, s));
-  std::vector<cd> rho(M);
-  std::vector<double> nrm0(M);
-  std::vector<char> active(M);
-  int nact = 0;
-  for (int c = 0; c < M; ++c) {
-    rho[c] = cd(s[c], 0.0);
-    nrm0[c] = std::sqrt(s[c]);
-    active[c] = nrm0[c] > 0.0;
-    nact += active[c];
-  }
-  double worst = 0.0, final_res = 0.0;  // largest residual of an open / a converged column
-  int it = 0;
-  for (; it < max_iters && nact > 0; ++it) {
+  rk_finish<T>(W, M);
+  k_cg_setup<<<1, 64, 0, ctx->stream>>>(M, 0, sums, st);
+  WL_HIP(hipGetLastError());
+  WL_TRY(rk_cg_post<T>(W, 0));
+  double sm[4];
+  WL_TRY(rk_cg_read<T>(W, 0, sm));
+  int it = 0, useful = 0;
+  bool open = sm[2] > 0.0;
+  for (; it < max_iters && open; ++it) {
     WL_TRY(rk_apply<T>(W, P, 2 * M, Q));  // Q = L P
     k_rk_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, xi.real(), xi.imag(), P, Q,
                                                             W.part.template as<double>());
-    WL_HIP(hipGetLastError());
-    WL_TRY(rk_sums<T>(W, 2 * M, s));
-    ColCoef al{}, be{};
-    for (int c = 0; c < M; ++c) {
-      if (!active[c]) continue;
-      const cd pq(s[c], s[M + c]);
-      if (pq == cd(0.0)) {
-        wl_set_error("rational Krylov: COCG broke down (p^T (L - xi) p = 0)");
-        return WL_ENUMERIC;
-      }
-      const cd a = rho[c] / pq;
-      al.re[c] = a.real();
-      al.im[c] = a.imag();
-    }
-    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, nullptr, nullptr,
+    rk_finish<T>(W, 2 * M);
+    k_cg_alpha<<<1, 64, 0, ctx->stream>>>(M, sums, st);
+    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, P, Q, X, R, nullptr, nullptr,
                                                      W.part.template as<double>());
+    rk_finish<T>(W, 3 * M);
+    k_cg_beta<<<1, 64, 0, ctx->stream>>>(M, tol, sums, st);
+    k_rk_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->be, R, P);
     WL_HIP(hipGetLastError());
-    WL_TRY(rk_sums<T>(W, 3 * M, s));
-    worst = 0.0;
-    for (int c = 0; c < M; ++c) {
-      if (!active[c]) continue;
-      const double res = std::sqrt(s[2 * M + c]) / nrm0[c];
-      if (!std::isfinite(res)) {
-        wl_set_error("rational Krylov: non-finite residual in the shifted solve");
-        return WL_ENUMERIC;
+    WL_TRY(rk_cg_post<T>(W, it & 1));
+    if (it > 0) {  // the previous iteration's summary, read while this one runs
+      WL_TRY(rk_cg_read<T>(W, (it - 1) & 1, sm));
+      WL_CHECK(sm[3] == 0.0, WL_ENUMERIC, sm[3] == 1.0 ? "rational Krylov: COCG broke down (p^T (L - xi) p = 0)"
+                                                       : "rational Krylov: non-finite residual in the shifted solve");
+      if (sm[2] == 0.0) {
+        useful = it;
+        open = false;
+        break;
       }
-      const cd rn(s[c], s[M + c]);
-      if (res <= tol) {
-        active[c] = 0;
-        --nact;
-        final_res = std::max(final_res, res);
-        continue;
-      }
-      worst = std::max(worst, res);
-      const cd b = rn / rho[c];
-      be.re[c] = b.real();
-      be.im[c] = b.imag();
-      rho[c] = rn;
     }
-    if (nact == 0) {
-      ++it;
-      break;
-    }
-    k_rk_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, R, P);
-    WL_HIP(hipGetLastError());
   }
-  *iters = it;
-  *res_out = nact > 0 ? worst : final_res;
-  if (nact > 0) {
+  if (open && it > 0) {  // the last iteration's summary
+    WL_TRY(rk_cg_read<T>(W, (it - 1) & 1, sm));
+    WL_CHECK(sm[3] == 0.0, WL_ENUMERIC, sm[3] == 1.0 ? "rational Krylov: COCG broke down (p^T (L - xi) p = 0)"
+                                                     : "rational Krylov: non-finite residual in the shifted solve");
+    useful = it;
+    open = sm[2] > 0.0;
+  } else if (useful == 0) {
+    useful = it;
+  }
+  *iters = useful;
+  *res_out = open ? sm[0] : sm[1];
+  if (open) {
     wl_set_error("rational Krylov: shifted solve did not reach %g in %d iterations (residual %g)", tol, max_iters,
-                 worst);
+                 sm[0]);
     return WL_ENOCONV;
   }
   return WL_OK;
@@ -511,76 +615,56 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   const int eg = (int)std::min<int64_t>(4096, (n + 255) / 256);
   k_fl_sqrt<T><<<eg, 256, 0, ctx->stream>>>(n, W.op->w.template as<T>(), xi.real(), xi.imag(), dre, dim);
   WL_HIP(hipGetLastError());
-  std::vector<double> sm;
+  CgState* st = W.cg.template as<CgState>();
+  const double* sums = W.sums.template as<double>();
   k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, P, V, W.part.template as<double>());
   WL_HIP(hipGetLastError());
-  WL_TRY(rk_sums<T>(W, 3 * M, sm));
-  std::vector<cd> rho(M);
-  std::vector<double> nrm0(M);
-  std::vector<char> active(M);
-  int nact = 0;
-  for (int c = 0; c < M; ++c) {
-    rho[c] = cd(sm[c], sm[M + c]);
-    nrm0[c] = std::sqrt(sm[2 * M + c]);
-    active[c] = nrm0[c] > 0.0;
-    nact += active[c];
-  }
-  double worst = 0.0, final_res = 0.0;
-  int it = 0;
-  for (; it < max_iters && nact > 0; ++it) {
+  rk_finish<T>(W, 3 * M);
+  k_cg_setup<<<1, 64, 0, ctx->stream>>>(M, 1, sums, st);
+  WL_HIP(hipGetLastError());
+  WL_TRY(rk_cg_post<T>(W, 0));
+  double sm[4];
+  WL_TRY(rk_cg_read<T>(W, 0, sm));
+  int it = 0, useful = 0;
+  bool open = sm[2] > 0.0;
+  for (; it < max_iters && open; ++it) {
     ep.Z = V;
     WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) P
     k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, P, Q, W.part.template as<double>());
+    rk_finish<T>(W, 2 * M);
+    k_cg_alpha<<<1, 64, 0, ctx->stream>>>(M, sums, st);
+    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, P, Q, X, R, dre, dim,
+                                                     W.part.template as<double>());
+    rk_finish<T>(W, 3 * M);
+    k_cg_beta<<<1, 64, 0, ctx->stream>>>(M, tol, sums, st);
+    k_fl_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->be, dre, dim, R, P, V);
     WL_HIP(hipGetLastError());
-    WL_TRY(rk_sums<T>(W, 2 * M, sm));
-    ColCoef al{}, be{};
-    for (int c = 0; c < M; ++c) {
-      if (!active[c]) continue;
-      const cd pq(sm[c], sm[M + c]);
-      if (pq == cd(0.0)) {
-        wl_set_error("rational Krylov: COCG broke down (p^T K p = 0)");
-        return WL_ENUMERIC;
+    WL_TRY(rk_cg_post<T>(W, it & 1));
+    if (it > 0) {  // the previous iteration's summary, read while this one runs
+      WL_TRY(rk_cg_read<T>(W, (it - 1) & 1, sm));
+      WL_CHECK(sm[3] == 0.0, WL_ENUMERIC, sm[3] == 1.0 ? "rational Krylov: COCG broke down (p^T K p = 0)"
+                                                       : "rational Krylov: non-finite residual in the shifted solve");
+      if (sm[2] == 0.0) {
+        useful = it;
+        open = false;
+        break;
       }
-      const cd al_c = rho[c] / pq;
-      al.re[c] = al_c.real();
-      al.im[c] = al_c.imag();
     }
-    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, al, P, Q, X, R, dre, dim, W.part.template as<double>());
-    WL_HIP(hipGetLastError());
-    WL_TRY(rk_sums<T>(W, 3 * M, sm));
-    worst = 0.0;
-    for (int c = 0; c < M; ++c) {
-      if (!active[c]) continue;
-      const double res = std::sqrt(sm[2 * M + c]) / nrm0[c];
-      if (!std::isfinite(res)) {
-        wl_set_error("rational Krylov: non-finite residual in the shifted solve");
-        return WL_ENUMERIC;
-      }
-      const cd rn(sm[c], sm[M + c]);
-      if (res <= tol) {
-        active[c] = 0;
-        --nact;
-        final_res = std::max(final_res, res);
-        continue;
-      }
-      worst = std::max(worst, res);
-      const cd bc = rn / rho[c];
-      be.re[c] = bc.real();
-      be.im[c] = bc.imag();
-      rho[c] = rn;
-    }
-    if (nact == 0) {
-      ++it;
-      break;
-    }
-    k_fl_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, be, dre, dim, R, P, V);
-    WL_HIP(hipGetLastError());
   }
-  *iters = it;
-  *res_out = nact > 0 ? worst : final_res;
-  if (nact > 0) {
+  if (open && it > 0) {  // the last iteration's summary
+    WL_TRY(rk_cg_read<T>(W, (it - 1) & 1, sm));
+    WL_CHECK(sm[3] == 0.0, WL_ENUMERIC, sm[3] == 1.0 ? "rational Krylov: COCG broke down (p^T K p = 0)"
+                                                     : "rational Krylov: non-finite residual in the shifted solve");
+    useful = it;
+    open = sm[2] > 0.0;
+  } else if (useful == 0) {
+    useful = it;
+  }
+  *iters = useful;
+  *res_out = open ? sm[0] : sm[1];
+  if (open) {
     wl_set_error("rational Krylov: shifted solve did not reach %g in %d iterations (residual %g)", tol, max_iters,
-                 worst);
+                 sm[0]);
     return WL_ENOCONV;
   }
   // x = A_mu (d (.) z)
@@ -670,6 +754,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   WL_TRY(W.dsmall.ensure((size_t)nb_max * Mp * Mp * 8));
   WL_TRY(W.part.ensure((size_t)RK_BLOCKS * 3 * Mp * 8));
   WL_TRY(W.sums.ensure((size_t)3 * Mp * 8));
+  WL_TRY(W.cg.ensure(sizeof(CgState)));
   W.basis = basis.as<T>();
   const int eg = (int)std::min<int64_t>(4096, (2 * (int64_t)blk + 255) / 256);
   // V_0 R0 = Omega (padded)
@@ -694,16 +779,13 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     iters_total += its;
     iters_max = std::max(iters_max, its);
     worst = std::max(worst, res);
-    k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, sol, 0, wb.as<T>());
-    WL_HIP(hipGetLastError());
-    WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
-    if (xi.imag() != 0.0) {
-      k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, sol, 1, wb.as<T>());
+    for (int part = 0; part < (xi.imag() != 0.0 ? 2 : 1); ++part) {
+      k_rk_part<T><<<eg, 256, 0, ctx->stream>>>(n, Mp, sol, part, wb.as<T>());
       WL_HIP(hipGetLastError());
       WL_TRY(rk_append<T>(W, wb.as<T>(), nullptr));
     }
   }
-  // T = V^T L V, one column block per basis block
+  // T = V^T L V, one column block per basis block, symmetrised
   const int nb = W.nb, m = nb * Mp;
   std::vector<double> Tm((size_t)m * m), col;
   for (int j = 0; j < nb; ++j) {
@@ -713,6 +795,11 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     for (int r = 0; r < m; ++r)
       for (int c = 0; c < Mp; ++c) Tm[(size_t)r * m + j * Mp + c] = col[(size_t)r * Mp + c];
   }
+  for (int r = 0; r < m; ++r)
+    for (int c = r + 1; c < m; ++c) {
+      const double v = 0.5 * (Tm[(size_t)r * m + c] + Tm[(size_t)c * m + r]);
+      Tm[(size_t)r * m + c] = Tm[(size_t)c * m + r] = v;
+    }
   products += (double)nb * M * op->K;
   // only the first Mp components of the eigenvectors enter: Z = S^T E_1 R0
   std::vector<double> lam(m), S1((size_t)Mp * m);

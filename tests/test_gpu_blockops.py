@@ -34,7 +34,7 @@ def test_block_gram(ctx, lib, dtype, bx, by, n, nblk):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("b", [1, 3, 4, 8, 16, 32, 64])
-@pytest.mark.parametrize("nblk", [1, 3])
+@pytest.mark.parametrize("nblk", [1, 3, 13, 25])
 @pytest.mark.parametrize("with_y", [False, True])
 def test_block_update(ctx, lib, dtype, b, nblk, with_y):
     n = 4099
@@ -65,3 +65,19 @@ def test_block_update_in_place(ctx, lib, b):
     Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
     lib.block_update(ctx, Xd, Cm, out=Xd)
     np.testing.assert_allclose(Xd.cpu().numpy(), X @ Cm, rtol=2e-5, atol=2e-5 * np.abs(X @ Cm).max())
+
+
+@pytest.mark.parametrize("nblk", [5, 13, 30])
+def test_block_update_out_is_an_input_block(ctx, lib, nblk):
+    """Out aliasing the first of many input blocks (32-wide FP32: combinations longer
+    than one launch holds run on the general kernel then) and the last one."""
+    n, b = 2500, 32
+    rng = np.random.default_rng(nblk)
+    X = f32(rng.standard_normal((nblk * n, b)))
+    Cm = rng.standard_normal((nblk * b, b))
+    ref = sum(X[k * n:(k + 1) * n] @ Cm[k * b:(k + 1) * b] for k in range(nblk))
+    for k_out in (0, nblk - 1):
+        Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+        out = Xd[k_out * n:(k_out + 1) * n]
+        lib.block_update(ctx, Xd, Cm, nblk=nblk, out=out)
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-5, atol=2e-5 * np.abs(ref).max())
