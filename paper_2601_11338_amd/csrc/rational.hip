@@ -160,11 +160,12 @@ __global__ void k_fl_sqrt(int64_t n, const T* __restrict__ w, double a, double b
   }
 }
 
-// z = 0, r = p = u / d, V = d (.) p; partials of r^T r (complex) and ||u||^2
+// z = 0, r = p = u / d, V = d (.) p = u (the direction is kept as V alone: p = V / d);
+// partials of r^T r (complex) and ||u||^2
 template <typename T>
 __global__ void k_fl_init(int64_t n, int M, const T* __restrict__ U, const T* __restrict__ dre,
-                          const T* __restrict__ dim, T* __restrict__ X, T* __restrict__ R, T* __restrict__ P,
-                          T* __restrict__ V, double* __restrict__ part) {
+                          const T* __restrict__ dim, T* __restrict__ X, T* __restrict__ R, T* __restrict__ V,
+                          double* __restrict__ part) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   double v[3] = {0.0, 0.0, 0.0};
   if (c < M)
@@ -177,8 +178,6 @@ __global__ void k_fl_init(int64_t n, int M, const T* __restrict__ U, const T* __
       X[o + M] = T(0);
       R[o] = (T)rr;
       R[o + M] = (T)ri;
-      P[o] = (T)rr;
-      P[o + M] = (T)ri;
       V[o] = (T)u;  // d (.) (u / d)
       V[o + M] = T(0);
       v[0] += rr * rr - ri * ri;
@@ -202,37 +201,64 @@ __global__ void k_fl_scale(int64_t n, int M, const T* __restrict__ dre, const T*
   }
 }
 
-// p = r + beta p and V = d (.) p in one pass
+// With V = d (.) p: x += alpha p (p = V / d) and the next direction
+// V = d (.) (r + beta p) = d (.) r + beta V, in one pass
 template <typename T>
-__global__ void k_fl_dir(int64_t n, int M, const double* __restrict__ be, const T* __restrict__ dre,
-                         const T* __restrict__ dim,
-                         const T* __restrict__ R, T* __restrict__ P, T* __restrict__ V) {
+__global__ void k_fl_dir(int64_t n, int M, const double* __restrict__ al, const double* __restrict__ be,
+                         const T* __restrict__ dre, const T* __restrict__ dim, const T* __restrict__ R,
+                         T* __restrict__ X, T* __restrict__ V) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   if (c >= M) return;
-  const double br = be[c], bi = be[RK_MAXM + c];
+  const double ar = al[c], ai = al[RK_MAXM + c], br = be[c], bi = be[RK_MAXM + c];
   for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
     const int64_t o = r * 2 * M + c;
-    const double pr0 = P[o], pi0 = P[o + M];
-    const T pr = (T)((double)R[o] + br * pr0 - bi * pi0);
-    const T pi = (T)((double)R[o + M] + br * pi0 + bi * pr0);
-    P[o] = pr;
-    P[o + M] = pi;
-    const double dr = dre[r], di = dim[r];
-    V[o] = (T)(dr * (double)pr - di * (double)pi);
-    V[o + M] = (T)(dr * (double)pi + di * (double)pr);
+    const double dr = dre[r], di = dim[r], m2 = dr * dr + di * di;
+    const double vr = V[o], vi = V[o + M];
+    const double pr = (vr * dr + vi * di) / m2, pi = (vi * dr - vr * di) / m2;
+    X[o] = (T)((double)X[o] + ar * pr - ai * pi);
+    X[o + M] = (T)((double)X[o + M] + ar * pi + ai * pr);
+    const double rr = R[o], ri = R[o + M];
+    V[o] = (T)(dr * rr - di * ri + br * vr - bi * vi);
+    V[o + M] = (T)(dr * ri + di * rr + br * vi + bi * vr);
   }
 }
 
-// Q <- d (.) Q - s P (Q holds A (d (.) P) on entry); partials of p^T q
+// r -= alpha q (complex alpha per column); partials of r^T r (complex) and ||d (.) r||^2
+// (the residual of the original system)
+template <typename T>
+__global__ void k_fl_xr(int64_t n, int M, const double* __restrict__ al, const T* __restrict__ Q,
+                        T* __restrict__ R, const T* __restrict__ dre, const T* __restrict__ dim,
+                        double* __restrict__ part) {
+  const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (c < M) {
+    const double ar = al[c], ai = al[RK_MAXM + c];
+    for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
+      const int64_t o = r * 2 * M + c;
+      const double qr = Q[o], qi = Q[o + M];
+      const double rr = (double)R[o] - (ar * qr - ai * qi);
+      const double ri = (double)R[o + M] - (ar * qi + ai * qr);
+      R[o] = (T)rr;
+      R[o + M] = (T)ri;
+      v[0] += rr * rr - ri * ri;
+      v[1] += 2.0 * rr * ri;
+      v[2] += ((double)dre[r] * dre[r] + (double)dim[r] * dim[r]) * (rr * rr + ri * ri);
+    }
+  }
+  block_colsum<3>(v, M, part);
+}
+
+// Q <- d (.) Q - s p with p = V / d (Q holds A V on entry); partials of p^T q
 template <typename T>
 __global__ void k_fl_shift_dot(int64_t n, int M, const T* __restrict__ dre, const T* __restrict__ dim, double s,
-                               const T* __restrict__ P, T* __restrict__ Q, double* __restrict__ part) {
+                               const T* __restrict__ V, T* __restrict__ Q, double* __restrict__ part) {
   const int c = threadIdx.x & 31, ry = threadIdx.x >> 5;
   double v[2] = {0.0, 0.0};
   if (c < M)
     for (int64_t r = (int64_t)blockIdx.x * 8 + ry; r < n; r += (int64_t)gridDim.x * 8) {
       const int64_t o = r * 2 * M + c;
-      const double dr = dre[r], di = dim[r], pr = P[o], pi = P[o + M], ar = Q[o], ai = Q[o + M];
+      const double dr = dre[r], di = dim[r], m2 = dr * dr + di * di, vr = V[o], vi = V[o + M];
+      const double pr = (vr * dr + vi * di) / m2, pi = (vi * dr - vr * di) / m2, ar = Q[o], ai = Q[o + M];
       const double qr = dr * ar - di * ai - s * pr;
       const double qi = dr * ai + di * ar - s * pi;
       Q[o] = (T)qr;
@@ -593,9 +619,10 @@ wl_status rk_solve(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R
 // COCG on the symmetrised system of a resolvent operator (see k_fl_sqrt): the same
 // solution x of (L - xi I) x = u as rk_solve, with one sparse product per iteration
 // instead of a Lanczos run.  Convergence is judged on the original residual d (.) r_z.
-// The solution lands in Q; V is scratch.
+// The direction is kept as V = d (.) p alone (p = V / d where needed); the solution
+// lands in Q.
 template <typename T>
-wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R, T* P, T* Q, T* V, T* dre,
+wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X, T* R, T* Q, T* V, T* dre,
                         T* dim, double tol, int max_iters, int* iters, double* res_out) {
   const int M = W.M;
   const int64_t n = W.n;
@@ -617,7 +644,7 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   WL_HIP(hipGetLastError());
   CgState* st = W.cg.template as<CgState>();
   const double* sums = W.sums.template as<double>();
-  k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, P, V, W.part.template as<double>());
+  k_fl_init<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, U, dre, dim, X, R, V, W.part.template as<double>());
   WL_HIP(hipGetLastError());
   rk_finish<T>(W, 3 * M);
   k_cg_setup<<<1, 64, 0, ctx->stream>>>(M, 1, sums, st);
@@ -629,15 +656,15 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   bool open = sm[2] > 0.0;
   for (; it < max_iters && open; ++it) {
     ep.Z = V;
-    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) P
-    k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, P, Q, W.part.template as<double>());
+    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) p
+    k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, V, Q, W.part.template as<double>());
     rk_finish<T>(W, 2 * M);
     k_cg_alpha<<<1, 64, 0, ctx->stream>>>(M, sums, st);
-    k_rk_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, P, Q, X, R, dre, dim,
+    k_fl_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, Q, R, dre, dim,
                                                      W.part.template as<double>());
     rk_finish<T>(W, 3 * M);
     k_cg_beta<<<1, 64, 0, ctx->stream>>>(M, tol, sums, st);
-    k_fl_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->be, dre, dim, R, P, V);
+    k_fl_dir<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, st->be, dre, dim, R, X, V);
     WL_HIP(hipGetLastError());
     WL_TRY(rk_cg_post<T>(W, it & 1));
     if (it > 0) {  // the previous iteration's summary, read while this one runs
@@ -745,7 +772,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   WL_TRY(wb.ensure(blk * sizeof(T)));
   WL_TRY(X.ensure(2 * blk * sizeof(T)));
   WL_TRY(R.ensure(2 * blk * sizeof(T)));
-  WL_TRY(P.ensure(2 * blk * sizeof(T)));
+  if (!flat) WL_TRY(P.ensure(2 * blk * sizeof(T)));
   WL_TRY(Q.ensure(2 * blk * sizeof(T)));
   if (flat) {
     WL_TRY(V.ensure(2 * blk * sizeof(T)));
@@ -769,7 +796,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     int its = 0;
     double res = 0.0;
     if (flat)
-      WL_TRY(rk_solve_flat<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), V.as<T>(), dd.as<T>(),
+      WL_TRY(rk_solve_flat<T>(W, xi, U, X.as<T>(), R.as<T>(), Q.as<T>(), V.as<T>(), dd.as<T>(),
                               dd.as<T>() + n, solve_tol, max_iters, &its, &res));
     else
       WL_TRY(rk_solve<T>(W, xi, U, X.as<T>(), R.as<T>(), P.as<T>(), Q.as<T>(), solve_tol, max_iters, &its, &res));
