@@ -190,6 +190,45 @@ def gather_ceiling():
     print(json.dumps(res), flush=True)
 
 
+def machine_ceilings(ctx, row_bytes):
+    """This box's ceilings beside the 8 TB/s specification, measured in the run (outside
+    the timed region, well under a second): a device-to-device copy of 2 GiB (read +
+    write) and random whole-line gathers of row_bytes-byte rows (10^7 uniformly drawn rows
+    of a 10^6-row table, wl_gather_probe), as 128-byte lines per second."""
+    import ctypes as C
+
+    import torch
+
+    import paper_2601_11338_amd as wl
+
+    rows, count = 1_000_000, 10_000_000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7)
+    idx = torch.randint(0, rows, (count,), dtype=torch.int32, device="cuda", generator=gen)
+    table = torch.rand(rows * row_bytes // 4, dtype=torch.float32, device="cuda", generator=gen)
+    out = torch.empty(8192 * 256 * 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ms = C.c_double()
+    wl._lib.check(wl.load().wl_gather_probe(ctx.handle, wl._ptr(table), rows, row_bytes, wl._ptr(idx), count,
+                                            wl._ptr(out), 8192, 5, C.byref(ms)))
+    lines = -(-row_bytes // 128)
+    gather = count * lines * 128 / (ms.value * 1e-3) / 1e9
+    del table, out, idx
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    a.record()
+    for _ in range(3):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    copy = 3 * 2 * src.numel() * 4 / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_GBps": copy, "gather_row_bytes": row_bytes, "gather_line_GBps": gather}
+
+
 def measured_traffic(n, m, width, lanes):
     """HBM bytes per launch of the dominant kernel (the sparse product at this block
     width) from the committed FETCH_SIZE / WRITE_SIZE counter runs, scaled by the
@@ -1533,6 +1572,13 @@ def run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g):
             "measured_in": "replay of the step one group at a time after the timed region",
         },
     }
+    # the dominant kernel gathers rows of width x 4 bytes: the same row size for the probe
+    ceil = machine_ceilings(ctx, min(512, 4 * dom["width"]))
+    out["roofline"]["measured_ceilings"] = ceil
+    out["roofline"]["frac_of_gather_ceiling"] = out["roofline"]["line_GBps"] / ceil["gather_line_GBps"]
+    log(f"this box: copy {ceil['copy_GBps']:.0f} GB/s, random {ceil['gather_row_bytes']}-byte row gathers "
+        f"{ceil['gather_line_GBps']:.0f} GB/s of 128-byte lines; the dominant kernel moves "
+        f"{out['roofline']['line_GBps']:.0f} GB/s of lines ({out['roofline']['frac_of_gather_ceiling']:.2f} of that)")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(rp, ci, n, lam, X_h, K)

@@ -597,6 +597,12 @@ wl_status launch_spmm(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep
     if (lanes == 12) return run_g<T, VW, 16, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 8 == 0) return run_g<T, VW, 8, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
     if (lanes % 4 == 0) return run_g<T, VW, 4, false>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    // other segments below 16 vectors (e.g. 20, 28 or 60 FP32 values): one masked
+    // segment of the next power of two, so each neighbour row is still gathered once
+    // with 16-byte loads
+    if (lanes < 4) return run_g<T, VW, 4, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes < 8) return run_g<T, VW, 8, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
+    if (lanes < 16) return run_g<T, VW, 16, true>(g, X, Y, b, ep, sh.G, sh.long_thr);
   }
   // scalar path with column masking for any b
   if (b == 1) return run_g<T, 1, 1, false>(g, X, Y, b, ep, sh.G, sh.long_thr);

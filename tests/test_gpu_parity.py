@@ -65,7 +65,7 @@ def spmm_graphs():
 
 
 @pytest.mark.parametrize("gname", ["er", "ba", "star_iso", "cycle"])
-@pytest.mark.parametrize("b", [1, 2, 3, 5, 7, 8, 16, 24, 32, 48, 64, 96])
+@pytest.mark.parametrize("b", [1, 2, 3, 5, 7, 8, 12, 16, 20, 24, 28, 32, 40, 48, 60, 64, 96])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_spmm_matches_sparse_product(ctx, wl, gname, b, dtype):
     n, rp, ci = spmm_graphs()[gname]
