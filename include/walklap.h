@@ -150,6 +150,25 @@ wl_status wl_ctx_destroy(wl_ctx* ctx);
 wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on);
 wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kernel_class, int64_t* launches, double* total_ms,
                               double* alg_bytes);
+/* With the environment variable WL_TRACE set (and not "0") when a context is created,
+ * profiling stays on for the context's life and wl_ctx_destroy prints every class's
+ * launches, time and algorithmic GB/s to stderr.                                      */
+
+/* wl_ctx_set_checks: result checks of the context's calls.  WL_CHECK_FINITE scans the
+ * outputs of wl_fdeg, wl_apply_phi, wl_apply_L and wl_expv (and their _ws / _noalloc
+ * forms) for NaN or Inf once the call's work is done: WL_ENUMERIC names the count.  The
+ * scan reads every output once and synchronises the stream (not for code under graph
+ * capture).  Enabling it allocates a small counter; flags = 0 turns checks off.        */
+#define WL_CHECK_FINITE 1u
+wl_status wl_ctx_set_checks(wl_ctx* ctx, uint32_t flags);
+
+/* wl_test_fail_alloc: test hook for the failure paths.  The k-th device allocation the
+ * library makes from now on (k = 0: the next one) fails as an out-of-memory would
+ * (the call returns WL_ENOMEM, the handles stay usable); one allocation fails, then
+ * the hook is off again.  k < 0 turns it off.  The environment variable
+ * WL_TEST_FAIL_ALLOC=k sets the same when the library first allocates.  Process-wide;
+ * for tests only.                                                                       */
+wl_status wl_test_fail_alloc(int64_t k);
 
 /* ---------------------------------------------------------------- graph (Sec. 2)
  * A simple undirected unweighted graph as symmetric CSR: d_rowptr (n+1 int32),

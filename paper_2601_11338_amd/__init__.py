@@ -110,6 +110,11 @@ class Context:
         check(load().wl_ctx_kernel_stats(self.handle, int(kernel_class), C.byref(n), C.byref(ms), C.byref(by)))
         return n.value, ms.value, by.value
 
+    def set_checks(self, finite=True):
+        """Scan the outputs of fdeg / apply_phi / apply_L / expv for NaN or Inf
+        (WL_ENUMERIC); synchronises after each such call."""
+        check(load().wl_ctx_set_checks(self.handle, WL_CHECK_FINITE if finite else 0))
+
     def close(self):
         if getattr(self, "handle", None) and self.handle.value:
             load().wl_ctx_destroy(self.handle)
@@ -124,6 +129,15 @@ class Context:
     @property
     def torch_device(self):
         return _torch().device("cuda", self.device)
+
+
+WL_CHECK_FINITE = 1
+
+
+def inject_alloc_failure(k):
+    """Test hook: the k-th device allocation of the library from now on fails as an
+    out-of-memory would (k < 0: off)."""
+    check(load().wl_test_fail_alloc(int(k)))
 
 
 class Graph:

@@ -77,6 +77,8 @@ SIGNATURES = {
     "wl_ctx_destroy": (C.c_int, [vp]),
     "wl_ctx_set_profiling": (C.c_int, [vp, i32]),
     "wl_ctx_kernel_stats": (C.c_int, [vp, i32, C.POINTER(i64), pd, pd]),
+    "wl_ctx_set_checks": (C.c_int, [vp, C.c_uint32]),
+    "wl_test_fail_alloc": (C.c_int, [i64]),
     "wl_graph_check_size": (C.c_int, [i64, i64]),
     "wl_workspace_size": (C.c_int, [vp, i32, i32, i32, C.POINTER(C.c_size_t)]),
     "wl_apply_phi_ws": (C.c_int, [vp, vp, vp, i32, vp, C.c_size_t]),

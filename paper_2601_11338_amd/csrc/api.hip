@@ -19,9 +19,11 @@
 //    exp(-t T) from one eigendecomposition for every t (Alg. 1 shares one basis
 //    across its parfor over t).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <unordered_map>
@@ -41,6 +43,67 @@ void wl_set_error(const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
+}
+
+// ------------------------------------------------------------------ allocation-failure hook
+// Allocations left before the injected failure: -1 off, -2 the environment not read yet.
+static std::atomic<int64_t> g_fail_alloc{-2};
+
+static void wl_fail_alloc_set(int64_t k) { g_fail_alloc.store(k < 0 ? -1 : k); }
+
+bool wl_alloc_injected() {
+  int64_t k = g_fail_alloc.load();
+  if (k == -2) {
+    const char* e = std::getenv("WL_TEST_FAIL_ALLOC");
+    int64_t v = -1;
+    if (e && e[0]) {
+      char* end = nullptr;
+      const long long x = std::strtoll(e, &end, 10);
+      if (end && *end == '\0' && x >= 0) v = x;
+    }
+    g_fail_alloc.compare_exchange_strong(k, v);
+    k = g_fail_alloc.load();
+  }
+  while (k >= 0)
+    if (g_fail_alloc.compare_exchange_weak(k, k == 0 ? -1 : k - 1)) return k == 0;
+  return false;
+}
+
+// ------------------------------------------------------------------ output scan
+namespace {
+
+template <typename T>
+__global__ void k_count_nonfinite(const T* __restrict__ p, int64_t count, unsigned long long* __restrict__ out) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    c += isfinite(p[i]) ? 0ull : 1ull;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0; }
+
+}  // namespace
+
+// WL_CHECK_FINITE: WL_ENUMERIC when any of the count values at p (an output of the
+// call `who`, already enqueued) is NaN or Inf; waits for the call's work.
+static wl_status scan_output(wl_ctx* ctx, int prec, const void* p, int64_t count, const char* who) {
+  if (!(ctx->checks & WL_CHECK_FINITE) || count <= 0) return WL_OK;
+  unsigned long long* d = ctx->check_count.as<unsigned long long>();
+  WL_CHECK(d, WL_EINTERNAL, "%s: output scan without its counter", who);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (count + 255) / 256));
+  k_zero_u64<<<1, 1, 0, ctx->stream>>>(d);
+  if (prec == WL_FP32)
+    k_count_nonfinite<float><<<grid, 256, 0, ctx->stream>>>((const float*)p, count, d);
+  else
+    k_count_nonfinite<double><<<grid, 256, 0, ctx->stream>>>((const double*)p, count, d);
+  WL_HIP(hipGetLastError());
+  unsigned long long bad = 0;
+  WL_HIP(hipMemcpyAsync(&bad, d, sizeof(bad), hipMemcpyDeviceToHost, ctx->stream));
+  WL_HIP(hipStreamSynchronize(ctx->stream));
+  WL_CHECK(bad == 0, WL_ENUMERIC, "%s: %llu of the %lld output values are NaN or Inf", who, bad, (long long)count);
+  return WL_OK;
 }
 
 namespace {
@@ -108,6 +171,11 @@ const char* wl_status_string(wl_status s) {
 int32_t wl_version(void) { return 100; }
 
 // ------------------------------------------------------------------ context
+wl_status wl_test_fail_alloc(int64_t k) {
+  wl_fail_alloc_set(k);
+  return WL_OK;
+}
+
 wl_status wl_ctx_create(int32_t device, void* stream, wl_ctx** out) {
   WL_CHECK(out != nullptr, WL_EINVAL, "wl_ctx_create: out is null");
   *out = nullptr;
@@ -121,7 +189,20 @@ wl_status wl_ctx_create(int32_t device, void* stream, wl_ctx** out) {
   auto* c = new wl_ctx;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  const char* tr = std::getenv("WL_TRACE");
+  if (tr && tr[0] && std::strcmp(tr, "0") != 0) c->trace = c->profiling = true;
   *out = c;
+  return WL_OK;
+}
+
+wl_status wl_ctx_set_checks(wl_ctx* ctx, uint32_t flags) {
+  WL_CHECK(ctx, WL_EINVAL, "wl_ctx_set_checks: ctx is null");
+  WL_CHECK((flags & ~WL_CHECK_FINITE) == 0, WL_EINVAL, "wl_ctx_set_checks: unknown flags");
+  if (flags & WL_CHECK_FINITE) {
+    DeviceGuard dg(ctx->device);
+    WL_TRY(ctx->check_count.ensure(sizeof(unsigned long long)));
+  }
+  ctx->checks = flags;
   return WL_OK;
 }
 
@@ -146,6 +227,7 @@ wl_status wl_ctx_set_profiling(wl_ctx* ctx, int32_t on) {
     k.launches = 0;
     k.bytes = 0.0;
     k.used = 0;
+    k.folded_ms = 0.0;
   }
   ctx->profiling = on != 0;
   return WL_OK;
@@ -157,7 +239,7 @@ wl_status wl_ctx_kernel_stats(wl_ctx* ctx, int32_t kclass, int64_t* launches, do
   DeviceGuard dg(ctx->device);
   WL_HIP(hipStreamSynchronize(ctx->stream));
   KernelStats& k = ctx->kstats[kclass];
-  double ms = 0.0;
+  double ms = k.folded_ms;
   for (size_t i = 0; i < k.used; ++i) {
     float e = 0.f;
     WL_HIP(hipEventElapsedTime(&e, k.events[i].first, k.events[i].second));
@@ -183,6 +265,18 @@ void ctx_release(wl_ctx* ctx) {
   {
     DeviceGuard dg(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->trace) {
+      static const char* names[WL_KC_COUNT] = {"recurrence step", "Lanczos operator product", "other sparse product",
+                                               "side-by-side series step", "side-by-side Lanczos product",
+                                               "multigrid finest level"};
+      for (int c = 0; c < WL_KC_COUNT; ++c) {
+        KernelStats& k = ctx->kstats[c];
+        if (!k.launches || kstats_fold(k) != WL_OK) continue;
+        std::fprintf(stderr, "[walklap trace] device %d, %s: %lld launches, %.3f ms, %.1f GB/s algorithmic\n",
+                     ctx->device, names[c], (long long)k.launches, k.folded_ms,
+                     k.folded_ms > 0 ? k.bytes / (k.folded_ms * 1e-3) / 1e9 : 0.0);
+      }
+    }
     for (auto& k : ctx->kstats)
       for (auto& e : k.events) {
         (void)hipEventDestroy(e.first);
@@ -190,8 +284,23 @@ void ctx_release(wl_ctx* ctx) {
       }
     ctx->partials.release();
     ctx->scratch.release();
+    ctx->check_count.release();
   }
   delete ctx;
+}
+
+// Reads back the timed event pairs of a kernel class into folded_ms and frees them for
+// reuse (waits for the last one).
+wl_status kstats_fold(KernelStats& k) {
+  if (!k.used) return WL_OK;
+  WL_HIP(hipEventSynchronize(k.events[k.used - 1].second));
+  for (size_t i = 0; i < k.used; ++i) {
+    float e = 0.f;
+    WL_HIP(hipEventElapsedTime(&e, k.events[i].first, k.events[i].second));
+    k.folded_ms += e;
+  }
+  k.used = 0;
+  return WL_OK;
 }
 
 void graph_release(wl_graph* g) {
@@ -1331,7 +1440,7 @@ wl_status wl_fdeg(wl_op* op, void* d_w) {
     WL_TRY(ensure_w<double>(op));
   if (op->g->n > 0)
     WL_HIP(hipMemcpyAsync(d_w, op->w.p, (size_t)op->g->n * es, hipMemcpyDeviceToDevice, op->g->ctx->stream));
-  return WL_OK;
+  return scan_output(op->g->ctx, op->d.prec, d_w, op->g->n, "wl_fdeg");
 }
 
 static wl_status check_block(wl_op* op, const void* X, const void* Y, int32_t b, const char* who) {
@@ -1348,8 +1457,11 @@ static wl_status check_block(wl_op* op, const void* X, const void* Y, int32_t b,
 wl_status wl_apply_phi(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
   WL_TRY(check_block(op, d_X, d_Y, b, "wl_apply_phi"));
   DeviceGuard dg(op->g->ctx->device);
-  if (op->d.prec == WL_FP32) return phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, nullptr, nullptr);
-  return phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, nullptr, nullptr);
+  if (op->d.prec == WL_FP32)
+    WL_TRY(phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, nullptr, nullptr));
+  else
+    WL_TRY(phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, nullptr, nullptr));
+  return scan_output(op->g->ctx, op->d.prec, d_Y, op->g->n * b, "wl_apply_phi");
 }
 
 wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
@@ -1357,10 +1469,13 @@ wl_status wl_apply_L(wl_op* op, const void* d_X, void* d_Y, int32_t b) {
   DeviceGuard dg(op->g->ctx->device);
   if (op->d.prec == WL_FP32) {
     WL_TRY(ensure_w<float>(op));
-    return phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, op->w.as<float>(), (const float*)d_X);
+    WL_TRY(phi_apply_impl<float>(op, (const float*)d_X, (float*)d_Y, b, op->w.as<float>(), (const float*)d_X));
+  } else {
+    WL_TRY(ensure_w<double>(op));
+    WL_TRY(
+        phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, op->w.as<double>(), (const double*)d_X));
   }
-  WL_TRY(ensure_w<double>(op));
-  return phi_apply_impl<double>(op, (const double*)d_X, (double*)d_Y, b, op->w.as<double>(), (const double*)d_X);
+  return scan_output(op->g->ctx, op->d.prec, d_Y, op->g->n * b, "wl_apply_L");
 }
 
 wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lambda2, double* lambda_min,
@@ -1387,10 +1502,13 @@ wl_status wl_expv(wl_op* op, const void* d_U0, int32_t b, const double* t, int32
   DeviceGuard dg(op->g->ctx->device);
   if (op->d.prec == WL_FP32) {
     WL_TRY(ensure_w<float>(op));
-    return expv_impl<float>(op, (const float*)d_U0, b, t, nt, (float* const*)d_Y, outer_dim, err_est);
+    WL_TRY(expv_impl<float>(op, (const float*)d_U0, b, t, nt, (float* const*)d_Y, outer_dim, err_est));
+  } else {
+    WL_TRY(ensure_w<double>(op));
+    WL_TRY(expv_impl<double>(op, (const double*)d_U0, b, t, nt, (double* const*)d_Y, outer_dim, err_est));
   }
-  WL_TRY(ensure_w<double>(op));
-  return expv_impl<double>(op, (const double*)d_U0, b, t, nt, (double* const*)d_Y, outer_dim, err_est);
+  for (int i = 0; i < nt; ++i) WL_TRY(scan_output(op->g->ctx, op->d.prec, d_Y[i], op->g->n * b, "wl_expv"));
+  return WL_OK;
 }
 
 wl_status wl_block_gram(wl_ctx* ctx, int32_t prec, int64_t n, int32_t nblk, int32_t bx, const void* d_X,

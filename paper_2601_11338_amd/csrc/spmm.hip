@@ -507,6 +507,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
   KernelStats* ks = nullptr;
   if (ctx->profiling && ep.kclass >= 0 && ep.kclass < WL_KC_COUNT) {
     ks = &ctx->kstats[ep.kclass];
+    if (ctx->trace && ks->used == WL_TRACE_FOLD) WL_TRY(kstats_fold(*ks));
     if (ks->used == ks->events.size()) {
       hipEvent_t a, c;
       WL_HIP(hipEventCreate(&a));

@@ -57,6 +57,11 @@ struct DeviceGuard {
 // growth would be a device allocation the caller asked not to happen).
 extern thread_local int wl_no_alloc;
 
+// Test hook for the failure paths: true when this device allocation is the one
+// WL_TEST_FAIL_ALLOC=k (read at the first allocation) or wl_test_fail_alloc(k) selected,
+// the k-th from then on (counting from 0); it then fails as an out-of-memory would.
+bool wl_alloc_injected();
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -84,6 +89,10 @@ struct DevBuf {
     }
     release();
     size_t want = nbytes < 256 ? 256 : nbytes;
+    if (wl_alloc_injected()) {
+      wl_set_error("hipMalloc(%zu) failed: out of memory (injected by the allocation-failure test hook)", want);
+      return WL_ENOMEM;
+    }
     hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
       p = nullptr;
@@ -114,14 +123,23 @@ struct KernelStats {
   double bytes = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t used = 0;
+  double folded_ms = 0.0;  // time of event pairs already read back and reused
 };
+// Trace mode (WL_TRACE set at context creation) keeps profiling on for the context's
+// life: every WL_TRACE_FOLD launches of a class its event pairs are read back (one wait
+// for the last) and reused.
+constexpr size_t WL_TRACE_FOLD = 16384;
+wl_status kstats_fold(KernelStats& k);
 
 struct wl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   DevBuf partials;  // reduction partials
   DevBuf scratch;   // small device-side matrices
+  DevBuf check_count;  // counter of the output scan (allocated when checks are enabled)
+  uint32_t checks = 0;  // WL_CHECK_* flags
   bool profiling = false;
+  bool trace = false;
   KernelStats kstats[WL_KC_COUNT];
   int refs = 1;  // the caller's handle + every graph / network made from it
 };
