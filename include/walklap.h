@@ -384,9 +384,12 @@ wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lam
  *
  * wl_return_prob: d_Omega n x M (row-major, operator precision, device; e.g. Gaussian
  * probes from wl_probes), 2 <= M <= 32, n > M.  t (host, nt values >= 0); t_max > 0 the
- * end of the time window; rho > 0 the spectral radius of L to use (<= 0: estimated by
- * 40 Lanczos steps: the largest Ritz value plus its residual norm; t_max rho <= aaa_tol,
- * as for L = 0, leaves no poles).  Poles: the wl_exp_poles
+ * end of the time window; rho > 0 the spectral radius of L to use (<= 0: for a
+ * resolvent operator the bound max w - s / (s + (mu alpha^2 + alpha) d_max), s = 1 -
+ * mu^2 alpha^2, which holds since phi = s A_mu(alpha)^{-1} is positive definite and
+ * bounds lambda_max(A_mu(alpha)) by Gershgorin; for
+ * other operators 40 Lanczos steps, the largest Ritz value plus its residual norm;
+ * t_max rho <= aaa_tol, as for L = 0, leaves no poles).  Poles: the wl_exp_poles
  * poles for xmax = t_max rho, divided by pole_time (1: as the algorithm states; t_max:
  * the poles of r(t_max lambda) ~ exp(-t_max lambda), accurate for t near t_max).  Each
  * real pole adds one basis block, each conjugate pair two (the real and imaginary parts

@@ -1,6 +1,7 @@
 // Rational Krylov estimate of the average return probability (Alg. 1, Sec. 4.4).
 //
-//   1. rho(L): Lanczos on the walk Laplacian (or the caller's value);
+//   1. rho(L): the caller's value; else for a resolvent the bound max w - s / lambda(A_mu)
+//      (phi positive definite, Gershgorin on A_mu), for other operators Lanczos on L;
 //   2. poles: AAA on exp(-x) over [0, t* rho] (host), divided by pole_time;
 //   3. basis: block rational Krylov space of L and Omega (eq. block-rational-Krylov),
 //      built in real arithmetic: a real pole xi adds (L - xi)^{-1} U, a conjugate pair
@@ -282,6 +283,20 @@ __global__ void k_rk_dir(int64_t n, int M, const double* __restrict__ be, const 
     P[o] = (T)((double)R[o] + br * pr - bi * pi);
     P[o + M] = (T)((double)R[o + M] + br * pi + bi * pr);
   }
+}
+
+// part[block] = the largest value of v over the rows the block visits
+template <typename T>
+__global__ __launch_bounds__(256) void k_rk_vmax(int64_t n, const T* __restrict__ v, double* __restrict__ part) {
+  __shared__ double s[4];
+  double m = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, (double)v[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(s[0], s[1]), fmax(s[2], s[3]));
 }
 
 // out (n x M) = real (part 0) or imaginary (part 1) half of X (n x 2M)
@@ -714,7 +729,26 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   // work: sparse products times the probe columns they act on (a walk-Laplacian
   // product on b columns is op->K products: Lanczos steps or series degree)
   double products = 0.0;
-  if (!(rho > 0.0)) {
+  if (!(rho > 0.0) && op->d.func == WL_F_RESOLVENT) {
+    // A resolvent's phi = s A_mu^{-1} is positive definite, so L = diag(w) - phi <= diag(w)
+    // and rho(L) <= max w - s / lambda_max(A_mu), with lambda_max(A_mu) <= b0 + (b1 + |a|)
+    // d_max (Gershgorin on A_mu = a A + b0 I + b1 D): an upper bound of the spectrum for
+    // the AAA interval without a product
+    double a, b0, b1;
+    lanczos_params(op, &a, &b0, &b1);
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
+    DevBuf part;
+    WL_TRY(part.ensure((size_t)nb * sizeof(double)));
+    k_rk_vmax<T><<<nb, 256, 0, ctx->stream>>>(n, op->w.template as<T>(), part.as<double>());
+    WL_HIP(hipGetLastError());
+    std::vector<double> hp(nb);
+    WL_HIP(hipMemcpyAsync(hp.data(), part.p, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    WL_HIP(hipStreamSynchronize(ctx->stream));
+    const double wmax = *std::max_element(hp.begin(), hp.end());
+    const double lam_a = b0 + (b1 + std::fabs(a)) * (double)g->max_deg;
+    WL_CHECK(std::isfinite(wmax) && lam_a > 0.0, WL_ENUMERIC, "wl_return_prob: bad walk degrees for the bound of rho");
+    rho = std::max(0.0, wmax - b0 / lam_a);
+  } else if (!(rho > 0.0)) {
     WL_TRY(laplacian_rho_impl<T>(op, 40, 0x5eed, &rho));
     products += 40.0 * op->K;
   }

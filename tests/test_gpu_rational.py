@@ -259,3 +259,31 @@ def test_pole_independent_estimates(ctx, lib, mu, kind, dtype):
         np.testing.assert_allclose(p, po, rtol=1e-8, atol=0)
     else:
         np.testing.assert_allclose(p, po, rtol=2e-4, atol=1e-6 * np.abs(po).max())
+
+
+@pytest.mark.parametrize("mu,frac", [(1.0, 0.5), (0.0, 0.3)])
+def test_resolvent_rho_bound(ctx, lib, mu, frac):
+    """Without a caller's rho, a resolvent takes the bound max w - s / (s + (mu alpha^2 +
+    alpha) d_max): phi = s A_mu^{-1} is positive definite, so L <= diag(w), and
+    lambda_max(A_mu) is bounded by its largest Gershgorin row.  It must lie above
+    lambda_max(L) (and within 50% of it on these graphs: 13% and 31% above, measured with
+    the oracle; 3% on the road stand-in of the bench),
+    cost no sparse product, and the estimate on the wider interval must still match the
+    exact tr exp(-t L) / n within its error estimate."""
+    print(f"[gpu] return_prob resolvent rho bound mu={mu}", flush=True)
+    n = 300
+    rp, ci, A = ba(n, 3, 5)
+    rz = walks.spectral_radius(walks.linearisation(A, mu)) if mu > 0 else np.linalg.eigvalsh(A)[-1]
+    alpha = frac / rz
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, mu, "res", alpha, dtype=torch.float64, krylov_dim=60, method="lanczos", tol=1e-14)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, mu, "res", alpha))
+    lmax = np.linalg.eigvalsh(Lap).max()
+    Om = synth.gaussian_block(n, 6, seed=12)
+    ts = [0.0, 0.5, 2.0, 10.0]
+    p, e, poles, info = op.return_prob(dev(Om, torch.float64), ts, 10.0, rho=0.0, solve_tol=1e-12, max_iters=2000)
+    assert lmax * (1 - 1e-9) <= info["rho"] <= 1.5 * lmax, (info["rho"], lmax)
+    K, M = op.info()[0], Om.shape[1]
+    assert info["products"] == 2 * M * (info["iters_total"] + info["solves"]) + info["nblocks"] * M * K
+    exact = rational.exact_return_probability(Lap, ts)
+    assert np.all(np.abs(p - exact) <= 5 * e + 1e-10 * np.abs(exact).max()), (p, exact, e)
