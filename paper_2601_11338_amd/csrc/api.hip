@@ -1010,27 +1010,29 @@ wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* c
                           op->outer_small, hA, hB, hR0, &Ke));
   const int m = Ke * b;
   std::vector<double> Tm = assemble_T(Ke, b, hA, hB);
-  std::vector<double> lam(m), U((size_t)m * m);
-  if (dense_syev(m, Tm.data(), lam.data(), U.data())) {
+  // T = U diag(lam) U^T in factored form (U is applied to blocks, never formed)
+  SymEig E;
+  if (sym_eig_factor(m, Tm.data(), E)) {
     wl_set_error("eigendecomposition of the projected Laplacian failed");
     return WL_ENOCONV;
   }
-  // U^T E_1 R0
+  // W0 = U^T E_1 R0, then F_t = U exp(-t lam) W0 for all times at once (m x nt b)
   std::vector<double> W0((size_t)m * b, 0.0);
+  for (int k = 0; k < b; ++k)
+    for (int c = 0; c < b; ++c) W0[(size_t)k * b + c] = hR0[(size_t)k * b + c];
+  sym_eig_apply_ut(E, b, W0.data());
+  const int nb = nt * b;
+  std::vector<double> Fall((size_t)m * nb);
   for (int i = 0; i < m; ++i)
-    for (int c = 0; c < b; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < b; ++k) s += U[(size_t)k * m + i] * hR0[(size_t)k * b + c];
-      W0[(size_t)i * b + c] = s;
+    for (int it = 0; it < nt; ++it) {
+      const double f = std::exp(-t[it] * E.lam[i]);
+      for (int c = 0; c < b; ++c) Fall[(size_t)i * nb + it * b + c] = f * W0[(size_t)i * b + c];
     }
+  sym_eig_apply_u(E, nb, Fall.data());
   for (int it = 0; it < nt; ++it) {
-    std::vector<double> F((size_t)m * b, 0.0);
+    std::vector<double> F((size_t)m * b);
     for (int r = 0; r < m; ++r)
-      for (int i = 0; i < m; ++i) {
-        const double u = U[(size_t)r * m + i] * std::exp(-t[it] * lam[i]);
-        if (u == 0.0) continue;
-        for (int c = 0; c < b; ++c) F[(size_t)r * b + c] += u * W0[(size_t)i * b + c];
-      }
+      for (int c = 0; c < b; ++c) F[(size_t)r * b + c] = Fall[(size_t)r * nb + it * b + c];
     if (err_est) {
       // || B_{K-1} F_last ||_F with F_last the last block row of F
       double e2 = 0.0;

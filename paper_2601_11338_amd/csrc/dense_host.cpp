@@ -4,7 +4,9 @@
 // Wilkinson-type shifts, tridiagonal eigenvalues, and a block Cholesky solve for
 // block tridiagonal SPD matrices.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 #include <vector>
@@ -13,11 +15,68 @@
 
 namespace {
 
+// Host threads for the dense work: the hardware's, at most 16 and at most
+// OMP_NUM_THREADS when that is set, and at most cap.
+int host_threads(int cap) {
+  int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v > 0) hw = std::min(hw, v);
+  }
+  return std::max(1, std::min({cap, 16, hw}));
+}
+
+// Barrier of a fixed team of threads (generation counter; spins, then yields).
+class SpinBarrier {
+ public:
+  void reset(int n) { n_ = n; }
+  void wait() {
+    if (n_ == 1) return;
+    const int g = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) + 1 == n_) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_release);
+      return;
+    }
+    int spins = 0;
+    while (gen_.load(std::memory_order_acquire) == g)
+      if (++spins > 512) std::this_thread::yield();
+  }
+
+ private:
+  int n_ = 1;
+  std::atomic<int> count_{0};
+  std::atomic<int> gen_{0};
+};
+
+// Runs f(tid, team) on a team of up to nth threads (the caller's is tid 0).  The
+// threads wait until the team is complete; if one cannot be started the team is
+// smaller, and bar is sized for the team that runs.
+template <typename F>
+void run_team(int nth, SpinBarrier& bar, F f) {
+  std::atomic<int> go{0};
+  int team = nth;
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nth; ++t)
+      pool.emplace_back([&, t] {
+        while (!go.load(std::memory_order_acquire)) std::this_thread::yield();
+        f(t, team);
+      });
+  } catch (...) {
+    team = 1 + (int)pool.size();
+  }
+  bar.reset(team);
+  go.store(1, std::memory_order_release);
+  f(0, team);
+  for (auto& th : pool) th.join();
+}
+
 // Implicit QL on a symmetric tridiagonal matrix (diagonal d[0..m), off-diagonal
 // e[0..m-1) with e[i] = T[i][i+1]).  If Zt is given (m x cols row-major, rows are the
 // current basis vectors, or their first cols components), every plane rotation is
 // applied to rows i, i+1 of Zt.
-int tql(int m, double* d, double* e_in, double* Zt, int cols = -1) {
+int tql(int m, double* d, double* e_in, double* Zt, int cols = -1, SymEig* log = nullptr) {
   if (cols < 0) cols = m;
   std::vector<double> e(m, 0.0);
   for (int i = 0; i + 1 < m; ++i) e[i] = e_in[i];
@@ -61,6 +120,11 @@ int tql(int m, double* d, double* e_in, double* Zt, int cols = -1) {
         p = s * r;
         d[i + 1] = g + p;
         g = c * r - bq;
+        if (log) {
+          log->ri.push_back(i);
+          log->rc.push_back(c);
+          log->rs.push_back(s);
+        }
         if (Zt) {
           double* zi = Zt + (size_t)i * cols;
           double* zj = Zt + (size_t)(i + 1) * cols;
@@ -104,55 +168,73 @@ void householder_tridiag(int m, const double* A_in, std::vector<double>& d, std:
       const double v = 0.5 * (A[(size_t)i * m + j] + A[(size_t)j * m + i]);
       A[(size_t)i * m + j] = A[(size_t)j * m + i] = v;
     }
-  // Householder reduction: for column k, reflect x = A[k+1:, k] onto alpha e_1.
-  vs.clear();
+  // Householder reduction: for column k, reflect x = A[k+1:, k] onto alpha e_1.  The
+  // two O(len^2) passes of a step (p = A22 v and the rank-2 update) split the rows of
+  // A22 over a team of threads; every row is computed exactly as by one thread.
+  const int steps = std::max(0, m - 2);
+  vs.assign(steps, std::vector<double>());
   d.assign(m, 0.0);
   e.assign(m, 0.0);
-  std::vector<double> p(m), q(m);
-  for (int k = 0; k + 2 < m; ++k) {
-    const int len = m - k - 1;
-    std::vector<double> v(len);
-    double nx = 0.0;
-    for (int i = 0; i < len; ++i) {
-      v[i] = A[(size_t)(k + 1 + i) * m + k];
-      nx += v[i] * v[i];
+  std::vector<double> p(m), q(m), v(m);
+  std::vector<char> skip(std::max(steps, 1), 0);
+  double K = 0.0;
+  SpinBarrier bar;
+  auto work = [&](int tid, int nth) {
+    for (int k = 0; k < steps; ++k) {
+      const int len = m - k - 1;
+      if (tid == 0) {
+        double nx = 0.0, tail = 0.0;
+        for (int i = 0; i < len; ++i) {
+          v[i] = A[(size_t)(k + 1 + i) * m + k];
+          nx += v[i] * v[i];
+          if (i > 0) tail += v[i] * v[i];
+        }
+        nx = std::sqrt(nx);
+        skip[k] = nx == 0.0 || tail == 0.0;  // identity reflector
+        if (!skip[k]) {
+          const double alpha = v[0] >= 0 ? -nx : nx;
+          v[0] -= alpha;
+          double nv = 0.0;
+          for (int i = 0; i < len; ++i) nv += v[i] * v[i];
+          nv = std::sqrt(nv);
+          for (int i = 0; i < len; ++i) v[i] /= nv;
+          // column / row k become alpha e_1 (A22 is not touched by this)
+          A[(size_t)(k + 1) * m + k] = alpha;
+          A[(size_t)k * m + k + 1] = alpha;
+          for (int i = 1; i < len; ++i) {
+            A[(size_t)(k + 1 + i) * m + k] = 0.0;
+            A[(size_t)k * m + k + 1 + i] = 0.0;
+          }
+        }
+      }
+      bar.wait();
+      if (skip[k]) continue;
+      const int r0 = (int)((int64_t)len * tid / nth), r1 = (int)((int64_t)len * (tid + 1) / nth);
+      // p = A22 v
+      for (int i = r0; i < r1; ++i) {
+        const double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
+        double sum = 0.0;
+        for (int j = 0; j < len; ++j) sum += row[j] * v[j];
+        p[i] = sum;
+      }
+      bar.wait();
+      if (tid == 0) {  // K = v^T p, q = p - K v
+        K = 0.0;
+        for (int i = 0; i < len; ++i) K += v[i] * p[i];
+        for (int i = 0; i < len; ++i) q[i] = p[i] - K * v[i];
+        vs[k].assign(v.begin(), v.begin() + len);
+      }
+      bar.wait();
+      // A22 <- A22 - 2 (v q^T + q v^T)
+      for (int i = r0; i < r1; ++i) {
+        double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
+        const double vi = v[i], qi = q[i];
+        for (int j = 0; j < len; ++j) row[j] -= 2.0 * (vi * q[j] + qi * v[j]);
+      }
+      bar.wait();
     }
-    nx = std::sqrt(nx);
-    double tail = 0.0;
-    for (int i = 1; i < len; ++i) tail += v[i] * v[i];
-    if (nx == 0.0 || tail == 0.0) {
-      vs.emplace_back();  // identity reflector
-      continue;
-    }
-    const double alpha = v[0] >= 0 ? -nx : nx;
-    v[0] -= alpha;
-    double nv = 0.0;
-    for (int i = 0; i < len; ++i) nv += v[i] * v[i];
-    nv = std::sqrt(nv);
-    for (int i = 0; i < len; ++i) v[i] /= nv;
-    // p = A22 v, K = v^T p, q = p - K v;  A22 <- A22 - 2 (v q^T + q v^T)
-    double K = 0.0;
-    for (int i = 0; i < len; ++i) {
-      const double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
-      double s = 0.0;
-      for (int j = 0; j < len; ++j) s += row[j] * v[j];
-      p[i] = s;
-    }
-    for (int i = 0; i < len; ++i) K += v[i] * p[i];
-    for (int i = 0; i < len; ++i) q[i] = p[i] - K * v[i];
-    for (int i = 0; i < len; ++i) {
-      double* row = &A[(size_t)(k + 1 + i) * m + k + 1];
-      const double vi = v[i], qi = q[i];
-      for (int j = 0; j < len; ++j) row[j] -= 2.0 * (vi * q[j] + qi * v[j]);
-    }
-    A[(size_t)(k + 1) * m + k] = alpha;
-    A[(size_t)k * m + k + 1] = alpha;
-    for (int i = 1; i < len; ++i) {
-      A[(size_t)(k + 1 + i) * m + k] = 0.0;
-      A[(size_t)k * m + k + 1 + i] = 0.0;
-    }
-    vs.push_back(std::move(v));
-  }
+  };
+  run_team(m >= 160 ? host_threads(m / 32) : 1, bar, work);
   for (int i = 0; i < m; ++i) d[i] = A[(size_t)i * m + i];
   for (int i = 0; i + 1 < m; ++i) e[i] = A[(size_t)i * m + i + 1];
 }
@@ -231,6 +313,108 @@ int dense_syev_rows(int m, const double* A_in, int kr, double* lam, double* Ur) 
     for (int r = 0; r < kr; ++r) Ur[(size_t)r * m + c] = Zt[(size_t)s * kr + r];
   }
   return 0;
+}
+
+int sym_eig_factor(int m, const double* A_in, SymEig& E) {
+  E = SymEig();
+  E.m = m;
+  if (m <= 0) return 0;
+  std::vector<double> d, e;
+  householder_tridiag(m, A_in, d, e, E.vs);
+  if (tql(m, d.data(), e.data(), nullptr, -1, &E)) return 1;
+  E.lam = std::move(d);
+  return 0;
+}
+
+namespace {
+
+constexpr int SYM_COLS = 8;  // columns moved through the reflectors and rotations together
+
+// Applies f(x) to the m x b block X in groups of SYM_COLS columns: x holds the group
+// row-major (m x SYM_COLS, missing columns zero), so a reflector or rotation updates
+// SYM_COLS independent values per row; the groups are split over host threads.
+template <typename F>
+void per_column_group(int m, int b, double* X, F f) {
+  const int ng = (b + SYM_COLS - 1) / SYM_COLS;
+  auto groups = [&](int g0, int g1) {
+    std::vector<double> x((size_t)m * SYM_COLS);
+    for (int gi = g0; gi < g1; ++gi) {
+      const int c0 = gi * SYM_COLS, nc = std::min(SYM_COLS, b - c0);
+      for (int i = 0; i < m; ++i)
+        for (int c = 0; c < SYM_COLS; ++c) x[(size_t)i * SYM_COLS + c] = c < nc ? X[(size_t)i * b + c0 + c] : 0.0;
+      f(x.data());
+      for (int i = 0; i < m; ++i)
+        for (int c = 0; c < nc; ++c) X[(size_t)i * b + c0 + c] = x[(size_t)i * SYM_COLS + c];
+    }
+  };
+  const int nth = (int64_t)m * m * b < (1 << 22) ? 1 : host_threads(ng);
+  std::vector<std::thread> pool;
+  int started = 1;
+  try {
+    for (; started < nth; ++started) pool.emplace_back(groups, ng * started / nth, ng * (started + 1) / nth);
+  } catch (...) {  // no thread to be had: the caller's thread takes the rest
+  }
+  groups(0, ng / nth);
+  for (auto& th : pool) th.join();
+  if (started < nth) groups(ng * started / nth, ng);
+}
+
+// x (rows of SYM_COLS values) <- H x for the reflector v acting on rows off..
+inline void reflect_rows(double* x, int off, const std::vector<double>& v) {
+  double s[SYM_COLS] = {};
+  for (size_t i = 0; i < v.size(); ++i) {
+    const double* r = x + (size_t)(off + i) * SYM_COLS;
+    for (int c = 0; c < SYM_COLS; ++c) s[c] += r[c] * v[i];
+  }
+  for (int c = 0; c < SYM_COLS; ++c) s[c] *= 2.0;
+  for (size_t i = 0; i < v.size(); ++i) {
+    double* r = x + (size_t)(off + i) * SYM_COLS;
+    for (int c = 0; c < SYM_COLS; ++c) r[c] -= s[c] * v[i];
+  }
+}
+
+}  // namespace
+
+void sym_eig_apply_ut(const SymEig& E, int b, double* X) {
+  const int m = E.m;
+  if (m <= 0 || b <= 0) return;
+  per_column_group(m, b, X, [&](double* x) {
+    // Q^T = H_last ... H_0: reflectors in order
+    for (size_t k = 0; k < E.vs.size(); ++k)
+      if (!E.vs[k].empty()) reflect_rows(x, (int)k + 1, E.vs[k]);
+    // then the QL rotations in the order they were made
+    for (size_t r = 0; r < E.ri.size(); ++r) {
+      double* xi = x + (size_t)E.ri[r] * SYM_COLS;
+      double* xj = xi + SYM_COLS;
+      const double c = E.rc[r], s = E.rs[r];
+      for (int q = 0; q < SYM_COLS; ++q) {
+        const double a = xi[q], bq = xj[q];
+        xj[q] = s * a + c * bq;
+        xi[q] = c * a - s * bq;
+      }
+    }
+  });
+}
+
+void sym_eig_apply_u(const SymEig& E, int b, double* X) {
+  const int m = E.m;
+  if (m <= 0 || b <= 0) return;
+  per_column_group(m, b, X, [&](double* x) {
+    // the transposed rotations in reverse order
+    for (size_t r = E.ri.size(); r-- > 0;) {
+      double* xi = x + (size_t)E.ri[r] * SYM_COLS;
+      double* xj = xi + SYM_COLS;
+      const double c = E.rc[r], s = E.rs[r];
+      for (int q = 0; q < SYM_COLS; ++q) {
+        const double a = xi[q], bq = xj[q];
+        xi[q] = c * a + s * bq;
+        xj[q] = c * bq - s * a;
+      }
+    }
+    // Q = H_0 ... H_last: reflectors in reverse order
+    for (size_t k = E.vs.size(); k-- > 0;)
+      if (!E.vs[k].empty()) reflect_rows(x, (int)k + 1, E.vs[k]);
+  });
 }
 
 namespace {

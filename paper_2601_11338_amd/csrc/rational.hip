@@ -862,20 +862,18 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
       Tm[(size_t)r * m + c] = Tm[(size_t)c * m + r] = v;
     }
   products += (double)nb * M * op->K;
-  // only the first Mp components of the eigenvectors enter: Z = S^T E_1 R0
-  std::vector<double> lam(m), S1((size_t)Mp * m);
-  if (dense_syev_rows(m, Tm.data(), Mp, lam.data(), S1.data())) {
+  // T = S diag(lam) S^T in factored form; only Z = S^T E_1 R0 enters (m x M: the probe
+  // columns, not the padding)
+  SymEig E;
+  if (sym_eig_factor(m, Tm.data(), E)) {
     wl_set_error("wl_return_prob: eigendecomposition of the projected matrix failed");
     return WL_ENOCONV;
   }
-  // Z (m x M: the probe columns, not the padding)
+  const std::vector<double>& lam = E.lam;
   std::vector<double> Z((size_t)m * M, 0.0);
-  for (int e = 0; e < m; ++e)
-    for (int c = 0; c < M; ++c) {
-      double s = 0.0;
-      for (int r = 0; r < Mp; ++r) s += S1[(size_t)r * m + e] * R0[(size_t)r * Mp + c];
-      Z[(size_t)e * M + c] = s;
-    }
+  for (int r = 0; r < Mp; ++r)
+    for (int c = 0; c < M; ++c) Z[(size_t)r * M + c] = R0[(size_t)r * Mp + c];
+  sym_eig_apply_ut(E, M, Z.data());
   // the times are independent (Alg. 1 runs them as a parallel loop): host threads
   const double inv_n = 1.0 / (double)n;
   const int nth = std::max(1, std::min({nt, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));

@@ -372,6 +372,21 @@ wl_status launch_cv_finish(wl_ctx* ctx, int64_t n, int M, const T* Om, const T* 
 int dense_syev(int m, const double* A, double* lam, double* U);
 // The same with only the first kr rows of U (kr x m row-major).
 int dense_syev_rows(int m, const double* A, int kr, double* lam, double* Ur);
+// A = U diag(lam) U^T kept in factored form: the Householder reflectors of the
+// tridiagonalisation and the plane rotations of the QL iteration, in the order they
+// were made.  U is never formed; applying it or its transpose to an m x b block costs
+// O(m^2 b) instead of the O(m^3) of accumulating U.  lam is in the QL order (unsorted).
+struct SymEig {
+  int m = 0;
+  std::vector<double> lam;
+  std::vector<std::vector<double>> vs;  // reflector k acts on indices k + 1.. (empty: none)
+  std::vector<int32_t> ri;              // rotation r acts on indices ri[r], ri[r] + 1
+  std::vector<double> rc, rs;
+};
+int sym_eig_factor(int m, const double* A, SymEig& E);
+// X (m x b row-major) <- U^T X, resp. U X; columns split over host threads.
+void sym_eig_apply_ut(const SymEig& E, int b, double* X);
+void sym_eig_apply_u(const SymEig& E, int b, double* X);
 // out (m x k) = phi_1(M) B, phi_1(x) = (e^x - 1) / x, for a general m x m M (row-major),
 // from exp([[M, B], [0, 0]]) by Pade scaling and squaring.  Nonzero on failure.
 int dense_phi1_times(int m, const double* M, int k, const double* B, double* out);

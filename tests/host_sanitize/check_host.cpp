@@ -90,6 +90,43 @@ void check_dense(std::mt19937_64& rng) {
   }
 }
 
+// the factored eigendecomposition: U (U^T X) = X and U diag(lam) U^T X = A X, on a dense
+// matrix and on a block tridiagonal one (the shape of the projected Krylov matrices)
+void check_sym_eig(std::mt19937_64& rng) {
+  std::normal_distribution<double> nd;
+  for (int m : {1, 3, 150, 400, 1280}) {
+    const int b = m >= 1000 ? 8 : 5;
+    std::vector<double> A((size_t)m * m, 0.0);
+    const int band = m >= 400 ? 32 : m;  // block tridiagonal bandwidth for the large cases
+    for (int i = 0; i < m; ++i)
+      for (int j = std::max(0, i - band); j <= i; ++j) A[(size_t)i * m + j] = A[(size_t)j * m + i] = nd(rng);
+    SymEig E;
+    const int st = sym_eig_factor(m, A.data(), E);
+    std::vector<double> X((size_t)m * b), Y, Z;
+    for (double& v : X) v = nd(rng);
+    Y = X;
+    sym_eig_apply_ut(E, b, Y.data());
+    Z = Y;
+    sym_eig_apply_u(E, b, Z.data());
+    double orth = 0.0;
+    for (size_t i = 0; i < X.size(); ++i) orth = std::max(orth, std::fabs(Z[i] - X[i]));
+    for (int i = 0; i < m; ++i)
+      for (int c = 0; c < b; ++c) Y[(size_t)i * b + c] *= E.lam[i];
+    sym_eig_apply_u(E, b, Y.data());
+    double res = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int c = 0; c < b; ++c) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += A[(size_t)i * m + j] * X[(size_t)j * b + c];
+        res = std::max(res, std::fabs(s - Y[(size_t)i * b + c]));
+      }
+    char what[96];
+    std::snprintf(what, sizeof(what), "sym_eig factored m=%d b=%d", m, b);
+    expect(st == 0 && (int)E.lam.size() == m && orth < 1e-11 && res < 1e-10 * std::sqrt((double)m), what,
+           std::max(orth, res));
+  }
+}
+
 void check_block_tridiag(std::mt19937_64& rng) {
   std::normal_distribution<double> nd;
   for (int K : {1, 3, 9}) {
@@ -306,6 +343,7 @@ void wl_set_error(const char*, ...) {}
 int main() {
   std::mt19937_64 rng(20260111);
   check_dense(rng);
+  check_sym_eig(rng);
   check_block_tridiag(rng);
   check_chol_deflate(rng);
   check_phi1(rng);
