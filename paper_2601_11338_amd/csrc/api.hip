@@ -759,32 +759,24 @@ std::vector<double> assemble_T(int K, int b, const std::vector<double>& hA, cons
   return T;
 }
 
-// F = f(T) E_1 R0 via the eigendecomposition of T (m = K b), f applied to eigenvalues.
+// F = f(T) E_1 R0 via the eigendecomposition of T (m = K b), f applied to eigenvalues;
+// T = U diag(lam) U^T kept in factored form (U applied to the b-column block only).
 template <typename Fn>
 int coeffs_by_eig(int K, int b, const std::vector<double>& hA, const std::vector<double>& hB,
-                  const std::vector<double>& hR0, Fn f, std::vector<double>& F, std::vector<double>* lam_out,
-                  std::vector<double>* U_out) {
+                  const std::vector<double>& hR0, Fn f, std::vector<double>& F) {
   const int m = K * b;
   std::vector<double> T = assemble_T(K, b, hA, hB);
-  std::vector<double> lam(m), U((size_t)m * m);
-  if (dense_syev(m, T.data(), lam.data(), U.data())) return 1;
-  // W = U^T E_1 R0  (m x b): rows of U restricted to the first b
-  std::vector<double> Wt((size_t)m * b, 0.0);
-  for (int i = 0; i < m; ++i)
-    for (int c = 0; c < b; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < b; ++k) s += U[(size_t)k * m + i] * hR0[(size_t)k * b + c];
-      Wt[(size_t)i * b + c] = s * f(lam[i]);
-    }
+  SymEig E;
+  if (sym_eig_factor(m, T.data(), E)) return 1;
   F.assign((size_t)m * b, 0.0);
-  for (int r = 0; r < m; ++r)
-    for (int i = 0; i < m; ++i) {
-      const double u = U[(size_t)r * m + i];
-      if (u == 0.0) continue;
-      for (int c = 0; c < b; ++c) F[(size_t)r * b + c] += u * Wt[(size_t)i * b + c];
-    }
-  if (lam_out) *lam_out = lam;
-  if (U_out) *U_out = U;
+  for (int k = 0; k < b; ++k)
+    for (int c = 0; c < b; ++c) F[(size_t)k * b + c] = hR0[(size_t)k * b + c];
+  sym_eig_apply_ut(E, b, F.data());
+  for (int i = 0; i < m; ++i) {
+    const double fi = f(E.lam[i]);
+    for (int c = 0; c < b; ++c) F[(size_t)i * b + c] *= fi;
+  }
+  sym_eig_apply_u(E, b, F.data());
   return 0;
 }
 
@@ -939,14 +931,13 @@ wl_status lanczos_coefficients(const wl_op* op, int Ke, int b, const std::vector
         }
       }
       const double cut = 1e-12 * lmax;
-      if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return x > cut ? scale / x : 0.0; }, F, nullptr,
-                        nullptr)) {
+      if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return x > cut ? scale / x : 0.0; }, F)) {
         wl_set_error("eigendecomposition of the projected matrix failed");
         return WL_ENOCONV;
       }
     }
   } else {
-    if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return std::exp(p * x); }, F, nullptr, nullptr)) {
+    if (coeffs_by_eig(Ke, b, hA, hB, hR0, [&](double x) { return std::exp(p * x); }, F)) {
       wl_set_error("eigendecomposition of the projected matrix failed");
       return WL_ENOCONV;
     }
