@@ -500,8 +500,11 @@ wl_status wl_diag_est(wl_op* op, int32_t target, double t, int32_t M, uint64_t s
  *   * WL_M_LANCZOS (Sec. 4.1): one block Lanczos process per operator, in lock step:
  *     the sparse product applies every group's own symmetric matrix and three-term
  *     subtraction, and the projections, CholQR factorisations and basis updates of all
- *     groups run as single passes over the wide block.  Each group's result uses its
- *     own number of steps; it agrees with the single operator's to the rounding level
+ *     groups run as single passes over the wide block (with the second local pass
+ *     against the previous block when any operator has reorth >= 1; with reorth 0
+ *     each new block is projected against the current one only).  Each group's
+ *     result uses its own number of steps; it agrees with the single operator's to the
+ *     rounding level
  *     of the Krylov recurrence (the grouped kernels sum in another order).  Grouped
  *     kernels cover FP32 with b = 16 and b = 1 (nops <= 8, any precision); other
  *     shapes, and Krylov spaces so small that full reorthogonalisation is needed

@@ -653,17 +653,19 @@ wl_status block_lanczos(wl_graph* g, const LanczosOp<T>& L, const T* X, int b, i
   if (!ring && (int64_t)(K + 1) * b * 2 > n) reorth = std::max(reorth, 2);
   auto slot = [&](int j) { return basis + (size_t)(ring ? j % 3 : j) * blk; };
   if (!ring && reorth <= 1) {
-    // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] against W'
-    // gives the projection; W = [V_{j-1} V_j W'] Cc is formed in place together with
-    // its own Gram; CholQR2 on that true Gram (with the deflation check of the first
-    // factor against W's scale before projection) orthonormalises it in place.
+    // Fused step: W' lands in basis slot j+1; one Gram of [V_{j-1} V_j W'] (reorth 1;
+    // [V_j W'] with reorth 0) against W' gives the projection; W = [.. W'] Cc is
+    // formed in place together with its own Gram; CholQR2 on that true Gram (with the
+    // deflation check of the first factor against W's scale before projection)
+    // orthonormalises it in place.
     for (int j = 0; j < K; ++j) {
       T* Vj = slot(j);
       T* Vn = slot(j + 1);
       const T* Vp = j > 0 ? slot(j - 1) : nullptr;
       WL_TRY(apply_lanczos_op<T>(g, L, Vj, Vn, b, Vp, j > 0 ? S + Ly.B(j - 1) : nullptr, S + Ly.P()));
-      const int nbv = j > 0 ? 2 : 1;
-      const T* Vlo = j > 0 ? Vp : Vj;
+      // projection against V_j (reorth 0), or a second local pass against V_{j-1} too
+      const int nbv = j > 0 && reorth >= 1 ? 2 : 1;
+      const T* Vlo = nbv == 2 ? Vp : Vj;
       WL_TRY(launch_gram<T>(ctx, n, Vlo, b, blk, nbv + 1, Vn, b, S + Ly.P()));
       WL_TRY(launch_lanczos_proj(ctx, b, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref()));
       WL_TRY(launch_update<T>(ctx, n, Vlo, b, blk, nbv + 1, S + Ly.Cc(), nullptr, 0.0, nullptr, 1.0, Vn, b,

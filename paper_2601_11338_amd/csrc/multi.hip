@@ -181,7 +181,9 @@ struct LockLayout {
 
 // K steps of G block Lanczos processes of 16 columns in lock step on Xr (n x 16 G), one
 // sparse product per step for all (Sec. 4.1): the three-term subtraction in the product's
-// epilogue, the projection against the current block and CholQR with deflation.
+// epilogue, the projection against the current block (with a second local pass
+// against the previous one when any operator asks for reorth >= 1) and CholQR with
+// deflation.
 // Deferred normalisation: slot j of
 // the basis holds W_j with V_j = W_j N_j orthonormal (N_j from the step's CholQR), and
 // the products, Grams and updates that read W_j apply N_j on the small side, so the
@@ -199,6 +201,8 @@ wl_status lockstep_lanczos(wl_multi* m, const T* Xr, int G, int dg, int K, const
   const int wd = G * 16;
   const int64_t blk = n * wd;
   const double tol = defl_tol<T>(), ptol = post_tol<T>();
+  bool local2 = false;
+  for (const auto& d : m->desc) local2 = local2 || d.reorth >= 1;
   // V_0 R0 = Xr per group by CholQR2 (the walk-degree group: each column normalised)
   WL_TRY(launch_ggram<T>(ctx, n, 16, G, Xr, 0, 1, Xr, S + Ly.G(), gs, nullptr, dg));
   WL_TRY(launch_chol(ctx, 16, S + Ly.G(), tol, nullptr, nullptr, S + Ly.R1(), S + Ly.Ri1(), nullptr, nullptr, G, gs,
@@ -230,15 +234,14 @@ wl_status lockstep_lanczos(wl_multi* m, const T* Xr, int G, int dg, int K, const
     }
     ep.kclass = wd >= 32 ? WL_KC_MULTI_LANCZOS : WL_KC_OTHER_SPMM;
     WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
-    // local projection against V_j alone: the epilogue's three-term subtraction has
-    // taken V_{j-1} out (a second pass against it left the FP32 results against the
-    // FP64 oracle unchanged, 3.3e-7 against 3.5e-7, and cost a third of the Gram and
-    // update traffic of the step)
-    const int nbv = 1;
-    WL_TRY(launch_ggram<T>(ctx, n, 16, G, Vj, blk, nbv + 1, Vn, S + Ly.P(), gs, nullptr, dg));
-    WL_TRY(launch_lanczos_proj_deferred(ctx, G, nbv, S + Ly.P(), nullptr, S + L.N(j), S + Ly.A(j), S + Ly.Cc(), gs,
-                                        S + Ly.Ref()));
-    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vj, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,
+    // projection against V_j (reorth 0: the epilogue's three-term subtraction has taken
+    // V_{j-1} out), or a second local pass against V_{j-1} too (reorth 1)
+    const int nbv = j > 0 && local2 ? 2 : 1;
+    const T* Vlo = nbv == 2 ? Vp : Vj;
+    WL_TRY(launch_ggram<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, Vn, S + Ly.P(), gs, nullptr, dg));
+    WL_TRY(launch_lanczos_proj_deferred(ctx, G, nbv, S + Ly.P(), nbv == 2 ? S + L.N(j - 1) : nullptr, S + L.N(j),
+                                        S + Ly.A(j), S + Ly.Cc(), gs, S + Ly.Ref()));
+    WL_TRY(launch_gupdate<T>(ctx, n, 16, G, Vlo, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,
                              S + Ly.G(), gs, nullptr, nullptr, dg));
     // the walk-degree columns are judged against their own scale before projection
     // (the diagonal of W'^T W', the last block of P)
@@ -327,6 +330,8 @@ wl_status multi_lanczos_plain(wl_multi* m, const T* X, const T* Xr, int b, T* Y,
   WL_TRY(m->basis.ensure((size_t)(K + 1) * blk * sizeof(T)));
   double* S = m->small.as<double>();
   T* basis = m->basis.as<T>();
+  bool local2 = false;
+  for (const auto& d : m->desc) local2 = local2 || d.reorth >= 1;
   const double tol = defl_tol<T>(), ptol = post_tol<T>();
   // V_0 R0 = Xr per group by CholQR2
   WL_TRY(launch_ggram<T>(ctx, n, b, G, Xr, 0, 1, Xr, S + Ly.G(), gs));
@@ -356,8 +361,8 @@ wl_status multi_lanczos_plain(wl_multi* m, const T* X, const T* Xr, int b, T* Y,
     }
     ep.kclass = wd >= 32 ? WL_KC_MULTI_LANCZOS : WL_KC_OTHER_SPMM;
     WL_TRY(launch_spmm<T>(g, Vj, Vn, wd, ep, sh));
-    const int nbv = j > 0 ? 2 : 1;
-    const T* Vlo = j > 0 ? Vp : Vj;
+    const int nbv = j > 0 && local2 ? 2 : 1;  // reorth 1: second local pass against V_{j-1}
+    const T* Vlo = nbv == 2 ? Vp : Vj;
     WL_TRY(launch_ggram<T>(ctx, n, b, G, Vlo, blk, nbv + 1, Vn, S + Ly.P(), gs));
     WL_TRY(launch_lanczos_proj(ctx, b, nbv, S + Ly.P(), S + Ly.A(j), S + Ly.Cc(), S + Ly.Ref(), G, gs));
     WL_TRY(launch_gupdate<T>(ctx, n, b, G, Vlo, blk, nbv + 1, S + Ly.Cc(), gs, nullptr, 0.0, nullptr, 1.0, Vn,

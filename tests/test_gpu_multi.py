@@ -135,11 +135,14 @@ def test_multi_lanczos_fp64_single_columns_and_fallback(ctx, lib):
         np.testing.assert_allclose(PX[:, cols], host(op.apply_phi(Xd)), rtol=0, atol=1e-12 * np.abs(PX).max())
 
 
+@pytest.mark.parametrize("reorth", [0, 1])
 @pytest.mark.parametrize("nops", [2, 3])
-def test_multi_lanczos_fp32_block16(ctx, lib, nops):
+def test_multi_lanczos_fp32_block16(ctx, lib, nops, reorth):
     """FP32 Lanczos groups of 16 columns (32 or 48 values per row; three groups take two
-    workgroup column chunks in the grouped kernels), Barabasi-Albert n = 3000."""
-    print(f"[gpu] multi lanczos fp32 b16 nops={nops}", flush=True)
+    workgroup column chunks in the grouped kernels), Barabasi-Albert n = 3000; reorth 0
+    (projection against the current block only) and 1 (second local pass against the
+    previous block too), grouped and single-operator paths alike."""
+    print(f"[gpu] multi lanczos fp32 b16 nops={nops} reorth={reorth}", flush=True)
     n = 3000
     rp, ci = synth.barabasi_albert(n, 5, 13)
     As = sparse.adjacency(n, rp, ci)
@@ -147,7 +150,8 @@ def test_multi_lanczos_fp32_block16(ctx, lib, nops):
     lam = g.lambda_max()
     specs = [(0.5, "res", _res_alpha(g, 0.5, lam)), (1.0, "res", _res_alpha(g, 1.0, lam)),
              (0.0, "exp", 1.0 / lam)][:nops]
-    ops = [lib.Operator(g, mu, f, p, dtype=torch.float32, krylov_dim=30, method="lanczos") for mu, f, p in specs]
+    ops = [lib.Operator(g, mu, f, p, dtype=torch.float32, krylov_dim=30, method="lanczos", reorth=reorth)
+           for mu, f, p in specs]
     multi = lib.Multi(ops)
     X = synth.rademacher_block(n, 16, 3)
     Xd = dev(X, torch.float32)
