@@ -1560,6 +1560,7 @@ def run_ba1m_packed(args, rp, ci, n, m, nnz, K, b, X_h, ctx, g):
             "streams": nstreams,
             "series_width": wd,
             "resolvent_layout": args.res_layout,
+            "lanczos_reorth": 0,
         },
         "roofline": {
             "bound": "hbm",

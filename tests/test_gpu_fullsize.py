@@ -92,6 +92,38 @@ def test_resolvent_lanczos_block16_full_size(ctx, lib, ba1m):
     assert ew < 2e-5 and ep < 1e-4
 
 
+def test_resolvent_groups_reorth0_full_size(ctx, lib, ba1m):
+    """The default workload's grouped Lanczos at full size: two resolvent operators side
+    by side (32-wide lock-step processes with deferred normalisation, reorth 0: each
+    new block projected against the current one only), and one operator's block beside
+    the walk-degree processes of three operators (apply_fdeg with nx = 1), K = 30."""
+    n, rp, ci, As = ba1m
+    print("[gpu] full size BA 1e6 grouped resolvents reorth 0", flush=True)
+    g = lib.Graph(ctx, rp, ci)
+    for w_ in (32, 16):
+        g.autotune(torch.float32, w_)
+    mus = [0.5, 1.0, 0.25]
+    rhos = [g.spectral_radius(mu) for mu in mus]
+    ops = [lib.Operator(g, mu, "res", 0.5 / rho, dtype=torch.float32, krylov_dim=30, rho_hint=rho, reorth=0)
+           for mu, rho in zip(mus, rhos)]
+    X = synth.rademacher_block(n, 16, 3)
+    Xd = dev(X, torch.float32)
+    PX = host(lib.Multi(ops[:2]).apply_phi(Xd))
+    Y, W = lib.Multi([ops[2], ops[0], ops[1]]).apply_fdeg(Xd, laplacian=False, nx=1)
+    Y, W = host(Y), host(W)
+    cols = [4, 13]
+    for i, (mu, rho) in enumerate(zip(mus, rhos)):
+        alpha = 0.5 / rho
+        wr = sparse.phi_res_apply(As, mu, alpha, np.ones((n, 1)), rtol=1e-12)[:, 0]
+        w = W[:, (i + 1) % 3]  # W's columns follow the second Multi's operator order
+        ew = float(np.max(np.abs(w - wr) / wr))
+        got = PX[:, [16 * i + c for c in cols]] if i < 2 else Y[:, cols]
+        ref = sparse.phi_res_apply(As, mu, alpha, X[:, cols], rtol=1e-12)
+        ep = node_rel(got, ref, wr)
+        print(f"[gpu] mu={mu}: phi X {rel(got, ref):.1e} (per node {ep:.1e}), w per node {ew:.1e}", flush=True)
+        assert rel(got, ref) < 2e-5 and ep < 1e-4 and ew < 2e-5
+
+
 def test_markov_chain_full_size(ctx, lib, ba1m):
     n, rp, ci, As = ba1m
     print("[gpu] full size BA 1e6 markov chain", flush=True)
