@@ -139,9 +139,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // kk = l / 16 and i = j = l % 16.  D[i][j] sits in lane l, element v with
 // i = 4 v + l / 16, j = l % 16 (layout measured on gfx950 with a probe whose inputs
 // make every output entry identify its (i, j)).
-// NB X blocks (block k at X + k sX) share one pass over Y (grid y walks chunks of NB
-// blocks).  Every wave walks 16-row chunks.  When every operand row is exactly
-// B = 16 NT floats (aligned), a chunk is loaded with 16-byte coalesced loads into
+// NB X blocks (block k at X + k sX) share one pass over Y; the ny groups of NB blocks
+// are separate workgroups over the same rows of Y.  Workgroups are dispatched to the 8
+// XCDs round-robin, so the 1-D grid of gx ny workgroups (gx row sets, a multiple of 8)
+// gives the ny workgroups of one row set ids 8 apart: they run on one XCD at about the
+// same time and Y's rows come from HBM once into its L2.  Every wave walks 16-row
+// chunks.  When every operand row is exactly B = 16 NT floats (aligned), a chunk is loaded with 16-byte coalesced loads into
 // registers one chunk ahead (the loads of chunk i + 1 are in flight while chunk i,
 // staged in the wave's own LDS slice, feeds the matrix cores); otherwise one element
 // per lane comes straight from memory.  The four waves' accumulators are summed in
@@ -149,8 +152,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <int NT, int NB>
 __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __restrict__ X, int ldx, int64_t sX,
                                                    int nblk, const float* __restrict__ Y, int ldy, int bx, int by,
-                                                   double* __restrict__ partials, const double* __restrict__ skip) {
+                                                   double* __restrict__ partials, const double* __restrict__ skip,
+                                                   int gx, int ny) {
   if (skip && *skip != 0.0) return;  // the caller does not need this Gram
+  const int wg_id = blockIdx.x;
+  const int grp = (wg_id >> 3) % ny;                     // group of NB X blocks
+  const int rset = ((wg_id >> 3) / ny) * 8 + (wg_id & 7);  // row set, < gx
   constexpr int B = 16 * NT;
   constexpr int TILE = 16 * B;  // floats per 16-row tile of one operand
   constexpr size_t TILE_BYTES = (size_t)4 * (NB + 1) * TILE * sizeof(float);
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
   __shared__ __align__(16) unsigned char smem[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
   float(*sm)[NB + 1][TILE] = reinterpret_cast<float(*)[NB + 1][TILE]>(smem);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kb0 = blockIdx.y * NB;
+  const int kb0 = grp * NB;
   const int nb = (nblk - kb0) < NB ? (nblk - kb0) : NB;
   v4d acc[NB][NT][NT];
 #pragma unroll
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
   const bool packed = ldx == B && ldy == B && bx == B && by == B && (sX % 4) == 0 &&
                       ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
   const int64_t nchunks = (n + 15) / 16;
-  const int64_t cstride = (int64_t)gridDim.x * 4;
+  const int64_t cstride = (int64_t)gx * 4;
   if (packed) {
     // 16 rows x B floats = 4 B float4 per operand, NT per lane
     float4 ry[NT], rx[NB][NT];
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
                                      : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     };
-    int64_t ch = (int64_t)blockIdx.x * 4 + wave;
+    int64_t ch = (int64_t)rset * 4 + wave;
     if (ch < nchunks) fetch(ch);
     for (; ch < nchunks; ch += cstride) {
 #pragma unroll
@@ -221,7 +228,7 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
       __builtin_amdgcn_wave_barrier();
     }
   } else {
-    for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunks; ch += cstride) {
+    for (int64_t ch = (int64_t)rset * 4 + wave; ch < nchunks; ch += cstride) {
       const int64_t r0 = ch * 16;
       // every operand element of the chunk is requested before the first product, at
       // addresses clamped into the blocks (a branch around each load would wait for it);
@@ -275,10 +282,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int64_t n, const float* __res
     }
     __syncthreads();
   }
-  const int nparts = gridDim.x;
   for (int e = threadIdx.x; e < nb * B * B; e += 256) {
     const int q = e / (B * B);
-    partials[((int64_t)(kb0 + q) * nparts + blockIdx.x) * (B * B) + (e - q * B * B)] = red[e];
+    partials[((int64_t)(kb0 + q) * gx + rset) * (B * B) + (e - q * B * B)] = red[e];
   }
 }
 
@@ -1365,20 +1371,23 @@ wl_status gram_B(wl_ctx* ctx, int64_t n, const void* X, bool isf, int ldx, int64
       int64_t blocks = (nchunks + 15) / 16;
       if (blocks > 1024) blocks = 1024;
       if (blocks < 1) blocks = 1;
-      const int nparts = (int)blocks;  // one partial per workgroup
+      blocks = (blocks + 7) / 8 * 8;  // row sets: a multiple of the 8 XCDs
+      const int nparts = (int)blocks;  // one partial per row set and block
       WL_TRY(ctx->partials.ensure((size_t)nparts * nblk * E * sizeof(double)));
       double* pp = ctx->partials.as<double>();
       const float* Xf = (const float*)X;
       const float* Yf = (const float*)Y;
       if (NT >= 4 || nblk == 1) {
-        hipLaunchKernelGGL((k_gram_mfma<NT, 1>), dim3((unsigned)blocks, nblk), dim3(256), 0, ctx->stream, n, Xf,
-                           ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
+        hipLaunchKernelGGL((k_gram_mfma<NT, 1>), dim3((unsigned)(blocks * nblk)), dim3(256), 0, ctx->stream, n, Xf,
+                           ldx, sX, nblk, Yf, ldy, bx, by, pp, skip, (int)blocks, nblk);
       } else if (nblk == 2 || NT == 2) {
-        hipLaunchKernelGGL((k_gram_mfma<NT, 2>), dim3((unsigned)blocks, (nblk + 1) / 2), dim3(256), 0, ctx->stream,
-                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
+        const int ny = (nblk + 1) / 2;
+        hipLaunchKernelGGL((k_gram_mfma<NT, 2>), dim3((unsigned)(blocks * ny)), dim3(256), 0, ctx->stream, n, Xf,
+                           ldx, sX, nblk, Yf, ldy, bx, by, pp, skip, (int)blocks, ny);
       } else {
-        hipLaunchKernelGGL((k_gram_mfma<NT, 3>), dim3((unsigned)blocks, (nblk + 2) / 3), dim3(256), 0, ctx->stream,
-                           n, Xf, ldx, sX, nblk, Yf, ldy, bx, by, pp, skip);
+        const int ny = (nblk + 2) / 3;
+        hipLaunchKernelGGL((k_gram_mfma<NT, 3>), dim3((unsigned)(blocks * ny)), dim3(256), 0, ctx->stream, n, Xf,
+                           ldx, sX, nblk, Yf, ldy, bx, by, pp, skip, (int)blocks, ny);
       }
       WL_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_gram_finalize, dim3(fin_grid(E), nblk), dim3(256), 0, ctx->stream,
