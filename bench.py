@@ -73,6 +73,12 @@ def parse():
                    help="only summarise a rocprofv3 output folder (kernel trace or counter CSVs): per kernel, the "
                         "number of dispatches, the mean over all and over the last --last dispatches")
     p.add_argument("--last", type=int, default=358, help="dispatches per kernel averaged by --summarize")
+    p.add_argument("--window-ms", type=float, default=0.0,
+                   help="--summarize of a kernel trace: only the dispatches of the trace's last WINDOW_MS "
+                        "milliseconds (the last step when nothing runs after it), with the time the GPU was "
+                        "busy and the longest idle gaps")
+    p.add_argument("--no-reference", action="store_true",
+                   help="arp-road2m: skip the standard-Laplacian estimate after the timed region")
     return p.parse_args()
 
 
@@ -108,6 +114,47 @@ def summarize(folder, last):
         rows.sort(reverse=True)
         for _, k, nv, avg, nt, avgt in rows[:30]:
             print(f"{nv:7d} x {avg:12.1f} | last {nt:5d}: {avgt:12.1f}  {k[:120]}")
+
+
+def summarize_window(folder, window_ms):
+    """The dispatches of a kernel trace that start within its last window_ms: per kernel
+    the total and mean duration, the union of the dispatch intervals (GPU busy) and the
+    longest gaps between them with the kernels on either side."""
+    import collections
+    import csv
+    import glob
+
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True)):
+        rows = []
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+        if not rows:
+            continue
+        rows.sort()
+        t0 = max(e for _, e, _ in rows) - window_ms * 1e6
+        rows = [x for x in rows if x[0] >= t0]
+        per = collections.defaultdict(lambda: [0, 0.0])
+        busy, last_end, gaps, prev = 0.0, None, [], None
+        for st, en, k in rows:
+            per[k][0] += 1
+            per[k][1] += (en - st) / 1e6
+            if last_end is None:
+                busy += (en - st) / 1e6
+            else:
+                if st > last_end:
+                    gaps.append(((st - last_end) / 1e6, prev, k))
+                busy += max(0, en - max(st, last_end)) / 1e6
+            last_end = en if last_end is None else max(last_end, en)
+            prev = k
+        print(f"# {os.path.relpath(f, folder)}: last {window_ms:.1f} ms, {len(rows)} dispatches, GPU busy "
+              f"{busy:.1f} ms, idle {window_ms - busy:.1f} ms")
+        for k, (c, ms) in sorted(per.items(), key=lambda x: -x[1][1])[:30]:
+            print(f"{ms:9.3f} ms {c:7d} x {ms / c * 1e3:10.1f} us  {k[:110]}")
+        gaps.sort(reverse=True)
+        print(f"# longest idle gaps (of {len(gaps)}, {sum(g for g, _, _ in gaps):.1f} ms in all)")
+        for g, a, b in gaps[:12]:
+            print(f"{g:8.3f} ms after {a[:60]}  before {b[:60]}")
 
 
 def copy_calibration():
@@ -762,10 +809,12 @@ def run_arp_road2m(args):
     ctx.set_profiling(True)
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts0 = time.perf_counter()
         p, e, poles, info = step()
         torch.cuda.synchronize()
-        log(f"step {i + 1}/{args.steps} done: poles {info['npoles']}, COCG iterations {info['iters_total']} "
-            f"(max {info['iters_max']}), rho {info['rho']:.4f}, p(1)={p[1]:.5f} p(100)={p[-1]:.3e}")
+        log(f"step {i + 1}/{args.steps} done in {(time.perf_counter() - ts0) * 1e3:.1f} ms: poles {info['npoles']}, "
+            f"COCG iterations {info['iters_total']} (max {info['iters_max']}), rho {info['rho']:.4f}, "
+            f"p(1)={p[1]:.5f} p(100)={p[-1]:.3e}")
     t1 = time.perf_counter()
     flat = ctx.kernel_stats(1)  # shifted-solve products with A_1(alpha), 64 wide (30 complex columns)
     lan = ctx.kernel_stats(4)   # Lanczos operator products as 16-column groups (projection, 32 wide)
@@ -830,22 +879,23 @@ def run_arp_road2m(args):
                                                  "aaa_err", "solve_res", "products")},
         "p_hat": {f"{ts[k]:.3g}": [float(p[k]), float(e[k])] for k in (0, 1, 9, 45, nt - 1)},
     }
-    # the standard Laplacian L = D - A on the same probes and times (the paper's
-    # reference in its return-probability figures), outside the timed region
-    opL = wl.Operator(g, 0.0, "linear", 1.0, dtype=torch.float32)
-    opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
-    torch.cuda.synchronize()
-    tL = time.perf_counter()
-    pL, eL, _, infoL = opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
-    torch.cuda.synchronize()
-    msL = (time.perf_counter() - tL) * 1e3
-    log(f"standard Laplacian: {msL:.0f} ms, poles {infoL['npoles']}, COCG iterations {infoL['iters_total']}, "
-        f"p(1)={pL[1]:.5f} p(100)={pL[-1]:.3e}")
-    out["standard_laplacian"] = {
-        "ms": msL,
-        "rational_krylov": {k: infoL[k] for k in ("npoles", "solves", "iters_total", "iters_max", "rho")},
-        "p_hat": {f"{ts[k]:.3g}": [float(pL[k]), float(eL[k])] for k in (0, 1, 9, 45, nt - 1)},
-    }
+    if not args.no_reference:
+        # the standard Laplacian L = D - A on the same probes and times (the paper's
+        # reference in its return-probability figures), outside the timed region
+        opL = wl.Operator(g, 0.0, "linear", 1.0, dtype=torch.float32)
+        opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
+        torch.cuda.synchronize()
+        tL = time.perf_counter()
+        pL, eL, _, infoL = opL.return_prob(Om, ts, t_max, solve_tol=1e-6, max_iters=1000)
+        torch.cuda.synchronize()
+        msL = (time.perf_counter() - tL) * 1e3
+        log(f"standard Laplacian: {msL:.0f} ms, poles {infoL['npoles']}, COCG iterations {infoL['iters_total']}, "
+            f"p(1)={pL[1]:.5f} p(100)={pL[-1]:.3e}")
+        out["standard_laplacian"] = {
+            "ms": msL,
+            "rational_krylov": {k: infoL[k] for k in ("npoles", "solves", "iters_total", "iters_max", "rho")},
+            "p_hat": {f"{ts[k]:.3g}": [float(pL[k]), float(eL[k])] for k in (0, 1, 9, 45, nt - 1)},
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline_arp(rp, ci, n, alpha, K)
@@ -1598,7 +1648,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.summarize:
-        summarize(args.summarize, args.last)
+        if args.window_ms > 0:
+            summarize_window(args.summarize, args.window_ms)
+        else:
+            summarize(args.summarize, args.last)
         return
     if args.copy_calibration:
         copy_calibration()

@@ -303,6 +303,31 @@ wl_status kstats_fold(KernelStats& k) {
   return WL_OK;
 }
 
+wl_status kstats_begin(wl_ctx* ctx, int kc, KernelStats** out) {
+  *out = nullptr;
+  if (!ctx->profiling || kc < 0 || kc >= WL_KC_COUNT) return WL_OK;
+  KernelStats* ks = &ctx->kstats[kc];
+  if (ctx->trace && ks->used == WL_TRACE_FOLD) WL_TRY(kstats_fold(*ks));
+  if (ks->used == ks->events.size()) {
+    hipEvent_t a, c;
+    WL_HIP(hipEventCreate(&a));
+    WL_HIP(hipEventCreate(&c));
+    ks->events.emplace_back(a, c);
+  }
+  WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
+  *out = ks;
+  return WL_OK;
+}
+
+wl_status kstats_end(wl_ctx* ctx, KernelStats* ks, double bytes) {
+  if (!ks) return WL_OK;
+  WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));
+  ++ks->used;
+  ++ks->launches;
+  ks->bytes += bytes;
+  return WL_OK;
+}
+
 void graph_release(wl_graph* g) {
   if (!g || --g->refs > 0) return;
   wl_ctx* ctx = g->ctx;

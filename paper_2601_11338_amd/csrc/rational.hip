@@ -270,6 +270,98 @@ __global__ void k_fl_shift_dot(int64_t n, int M, const T* __restrict__ dre, cons
   block_colsum<2>(v, M, part);
 }
 
+// Longest row the one-pass product below takes: each row is gathered by one lane group,
+// so a graph with longer rows runs the sparse-product kernel (whose long rows get whole
+// workgroups) followed by k_fl_shift_dot.
+constexpr int FL_FUSED_MAXDEG = 256;
+constexpr int FL_BLOCKS = 2048;  // workgroups of the one-pass product (a multiple of 8)
+
+// One iteration's operator product of the symmetrised shifted system in one pass, the
+// values of the sparse product (A_mu V = a A V + (b0 + b1 deg) V in FP32) followed by
+// k_fl_shift_dot: Q = d (.) (A_mu V) - s p with p = V / d, and per-workgroup partials of
+// p^T q (complex), laid out as block_colsum's.  M = 2 LPR complex columns: each row is
+// LPR lanes of four values, the first half Re and the second Im, so lane l and its
+// partner l ^ (LPR / 2) hold the two parts of the same four columns.  The rows are cut
+// into 8 contiguous ranges, one per XCD (workgroup w runs on XCD w mod 8), so a row and
+// the nearby rows its neighbours usually are go through one L2.
+template <int LPR>
+__global__ __launch_bounds__(256) void k_fl_product(const int32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ colidx, int64_t n,
+                                                    const float* __restrict__ V, const float* __restrict__ dre,
+                                                    const float* __restrict__ dim, float a, float b0, float b1,
+                                                    double s, float* __restrict__ Q, double* __restrict__ part) {
+  constexpr int M = 2 * LPR, W2 = 2 * M, H = LPR / 2, RG = 256 / LPR;
+  const int l = threadIdx.x % LPR, rg = threadIdx.x / LPR;
+  const bool re_half = l < H;
+  const int col = 4 * l;
+  const int64_t per = gridDim.x >> 3;                     // workgroups per XCD
+  const int64_t span = ((n + 7) / 8 + RG - 1) / RG * RG;  // rows per XCD range
+  const int64_t r0 = (int64_t)(blockIdx.x & 7) * span;
+  const int64_t r1 = r0 + span < n ? r0 + span : n;
+  double v0[4] = {0.0, 0.0, 0.0, 0.0}, v1[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0 + (int64_t)(blockIdx.x >> 3) * RG + rg; r < r1; r += per * RG) {
+    const int beg = rowptr[r], end = rowptr[r + 1];
+    const float4 z = *reinterpret_cast<const float4*>(V + r * W2 + col);
+    const double dr = dre[r], di = dim[r];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = beg; k < end; k += 4) {  // up to four neighbour rows in flight
+      int j[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = k + u < end ? colidx[k + u] : -1;
+      float4 x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        x[u] = j[u] >= 0 ? *reinterpret_cast<const float4*>(V + (int64_t)j[u] * W2 + col)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc.x += x[u].x;
+        acc.y += x[u].y;
+        acc.z += x[u].z;
+        acc.w += x[u].w;
+      }
+    }
+    const float cz = b0 + b1 * (float)(end - beg);
+    const float y[4] = {a * acc.x + cz * z.x, a * acc.y + cz * z.y, a * acc.z + cz * z.z, a * acc.w + cz * z.w};
+    const float zz[4] = {z.x, z.y, z.z, z.w};
+    // each lane computes its own part of p and q: with sdi = -di on the Re lanes and +di
+    // on the Im lanes, p_own = (z_own dr - sdi z_other) / |d|^2 and
+    // q_own = dr y_own + sdi y_other - s p_own
+    const double inv = 1.0 / (dr * dr + di * di);
+    const double sdi = re_half ? -di : di;
+    float out[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double yo = __shfl_xor(y[i], H, 64), zo = __shfl_xor(zz[i], H, 64);
+      const double po = ((double)zz[i] * dr - sdi * zo) * inv;
+      const double qo = dr * (double)y[i] + sdi * yo - s * po;
+      const double qp = __shfl_xor(qo, H, 64);  // the partner's part of q
+      out[i] = (float)qo;
+      v0[i] += po * qo;  // Re: pr qr, Im: pi qi
+      v1[i] += po * qp;  // Re: pr qi, Im: pi qr
+    }
+    *reinterpret_cast<float4*>(Q + r * W2 + col) = make_float4(out[0], out[1], out[2], out[3]);
+  }
+  // p^T q = sum (pr qr - pi qi) + i sum (pr qi + pi qr): the Re lane of each column pair
+  // takes its partner's sums
+  __shared__ double red[2][RG][M];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double o0 = __shfl_xor(v0[i], H, 64), o1 = __shfl_xor(v1[i], H, 64);
+    if (re_half) {
+      red[0][rg][col + i] = v0[i] - o0;
+      red[1][rg][col + i] = v1[i] + o1;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * M; e += 256) {
+    const int q = e / M, c = e - q * M;
+    double t = 0.0;
+    for (int y = 0; y < RG; ++y) t += red[q][y][c];
+    part[(size_t)blockIdx.x * 2 * M + e] = t;
+  }
+}
+
 // p = r + beta p (complex beta per column)
 template <typename T>
 __global__ void k_rk_dir(int64_t n, int M, const double* __restrict__ be, const T* __restrict__ R,
@@ -667,13 +759,37 @@ wl_status rk_solve_flat(RkWork<T>& W, std::complex<double> xi, const T* U, T* X,
   WL_TRY(rk_cg_post<T>(W, 0));
   double sm[4];
   WL_TRY(rk_cg_read<T>(W, 0, sm));
+  // the operator product and the shift in one pass where every row fits a lane group
+  const bool fused = sizeof(T) == 4 && (M == 16 || M == 32) && g->max_deg <= FL_FUSED_MAXDEG;
+  const int fgrid = (int)std::min<int64_t>(FL_BLOCKS, std::max<int64_t>(8, ((n + 15) / 16 + 7) / 8 * 8));
   int it = 0, useful = 0;
   bool open = sm[2] > 0.0;
   for (; it < max_iters && open; ++it) {
-    ep.Z = V;
-    WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) p
-    k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, V, Q, W.part.template as<double>());
-    rk_finish<T>(W, 2 * M);
+    if (fused) {
+      KernelStats* ks = nullptr;
+      WL_TRY(kstats_begin(ctx, WL_KC_LANCZOS_OP, &ks));
+      const float* Vf = reinterpret_cast<const float*>(V);
+      const float* drf = reinterpret_cast<const float*>(dre);
+      const float* dif = reinterpret_cast<const float*>(dim);
+      float* Qf = reinterpret_cast<float*>(Q);
+      if (M == 32)
+        k_fl_product<16><<<fgrid, 256, 0, ctx->stream>>>(g->rowptr, g->colidx, n, Vf, drf, dif, (float)a,
+                                                         (float)b0, (float)b1, s, Qf, W.part.template as<double>());
+      else
+        k_fl_product<8><<<fgrid, 256, 0, ctx->stream>>>(g->rowptr, g->colidx, n, Vf, drf, dif, (float)a,
+                                                        (float)b0, (float)b1, s, Qf, W.part.template as<double>());
+      WL_HIP(hipGetLastError());
+      // CSR once, V gathered once and read once as its own rows, Q written, d
+      WL_TRY(kstats_end(ctx, ks, 4.0 * g->nnz + 4.0 * (n + 1) + 3.0 * 4.0 * n * 2 * M + 8.0 * n));
+      k_rk_finish<<<2 * M, RK_THREADS, 0, ctx->stream>>>(fgrid, 2 * M, W.part.template as<double>(),
+                                                          W.sums.template as<double>());
+    } else {
+      ep.Z = V;
+      WL_TRY(launch_spmm<T>(g, V, Q, 2 * M, ep, sh));  // Q = A_mu V, V = d (.) p
+      k_fl_shift_dot<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, dre, dim, s, V, Q,
+                                                              W.part.template as<double>());
+      rk_finish<T>(W, 2 * M);
+    }
     k_cg_alpha<<<1, 64, 0, ctx->stream>>>(M, sums, st);
     k_fl_xr<T><<<grid, RK_THREADS, 0, ctx->stream>>>(n, M, st->al, Q, R, dre, dim,
                                                      W.part.template as<double>());
@@ -813,7 +929,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     WL_TRY(dd.ensure(2 * (size_t)n * sizeof(T)));
   }
   WL_TRY(W.dsmall.ensure((size_t)nb_max * Mp * Mp * 8));
-  WL_TRY(W.part.ensure((size_t)RK_BLOCKS * 3 * Mp * 8));
+  WL_TRY(W.part.ensure((size_t)std::max(RK_BLOCKS * 3, FL_BLOCKS * 2) * Mp * 8));
   WL_TRY(W.sums.ensure((size_t)3 * Mp * 8));
   WL_TRY(W.cg.ensure(sizeof(CgState)));
   W.basis = basis.as<T>();

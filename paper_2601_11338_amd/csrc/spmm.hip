@@ -505,17 +505,7 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
   dim3 grid((unsigned)gx, (unsigned)tiles);
   wl_ctx* ctx = g->ctx;
   KernelStats* ks = nullptr;
-  if (ctx->profiling && ep.kclass >= 0 && ep.kclass < WL_KC_COUNT) {
-    ks = &ctx->kstats[ep.kclass];
-    if (ctx->trace && ks->used == WL_TRACE_FOLD) WL_TRY(kstats_fold(*ks));
-    if (ks->used == ks->events.size()) {
-      hipEvent_t a, c;
-      WL_HIP(hipEventCreate(&a));
-      WL_HIP(hipEventCreate(&c));
-      ks->events.emplace_back(a, c);
-    }
-    WL_HIP(hipEventRecord(ks->events[ks->used].first, ctx->stream));
-  }
+  WL_TRY(kstats_begin(ctx, ep.kclass, &ks));
   const int32_t* lr = g->long_rows.as<int32_t>();
   if constexpr (VW == 4) {  // the right factor exists for 16-byte vectors of FP32 only
     if (ep.Nm && ep.cmap)
@@ -537,15 +527,12 @@ wl_status run(wl_graph* g, const T* X, T* Y, int b, const EpiArgs<T>& ep, int lo
                        g->colidx, g->n, b, b, X, Y, epx, lr, n_long, long_thr);
   WL_HIP(hipGetLastError());
   if (ks) {
-    WL_HIP(hipEventRecord(ks->events[ks->used].second, ctx->stream));
-    ++ks->used;
-    ++ks->launches;
     // algorithmic bytes: CSR once, the gathered block once (compulsory), every row stream once
     const double s = sizeof(T), nb = (double)g->n * b;
     int streams = 1 + (Y ? 1 : 0) + (ep.Z ? 1 : 0) + (ep.C ? 1 : 0) + (ep.Sin ? 1 : 0) + (ep.Sout ? 1 : 0) +
                   (ep.Xw ? 1 : 0) + (ep.jx ? 1 : 0);
-    ks->bytes += 4.0 * g->nnz + 4.0 * (g->n + 1) + s * nb * streams + (ep.wv ? s * g->n : 0.0) +
-                 (ep.jw ? s * g->n : 0.0);
+    WL_TRY(kstats_end(ctx, ks, 4.0 * g->nnz + 4.0 * (g->n + 1) + s * nb * streams + (ep.wv ? s * g->n : 0.0) +
+                                   (ep.jw ? s * g->n : 0.0)));
   }
   return WL_OK;
 }

@@ -130,6 +130,12 @@ struct KernelStats {
 // for the last) and reused.
 constexpr size_t WL_TRACE_FOLD = 16384;
 wl_status kstats_fold(KernelStats& k);
+struct wl_ctx;
+// Timing of one launch of class kc (profiling on): kstats_begin records the start event
+// on the context's stream and returns the class's record (null when profiling is off or
+// kc is not a class), kstats_end the end event and the launch's algorithmic bytes.
+wl_status kstats_begin(wl_ctx* ctx, int kc, KernelStats** ks);
+wl_status kstats_end(wl_ctx* ctx, KernelStats* ks, double bytes);
 
 struct wl_ctx {
   int device = 0;

@@ -118,6 +118,44 @@ def test_fp32_resolvent_column_groups(ctx, lib, M):
     compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
 
 
+def test_fp32_resolvent_road_one_pass(ctx, lib):
+    """A road-like lattice (every degree at most 4) with M = 30 probes (padded to 32
+    columns) at alpha = 1 / (1 + rho(Z_1)): the shifted solves take the one-pass product
+    (gather, shift and p^T q in one kernel), as on the road-network workload."""
+    print("[gpu] return_prob fp32 res mu=1 road lattice, one-pass solve product", flush=True)
+    rp, ci = synth.road_grid(50, 50, 0.7, seed=3)
+    n = len(rp) - 1
+    A = walks.adjacency(n, rp, ci)
+    assert np.diff(rp).max() <= 4
+    alpha = 1.0 / (1.0 + walks.spectral_radius(walks.linearisation(A, 1.0)))
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float32, krylov_dim=30, method="lanczos", tol=1e-7)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
+    Om = synth.gaussian_block(n, 30, seed=41)
+    compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
+
+
+@pytest.mark.parametrize("M", [8, 30])
+def test_fp32_resolvent_long_rows(ctx, lib, M):
+    """A node joined to 400 others (above the one-pass product's row limit of 256): the
+    shifted solves take the sparse-product kernel and the separate shift pass."""
+    print(f"[gpu] return_prob fp32 res mu=1 with a long row, M={M}", flush=True)
+    n = 2000
+    rp, ci = synth.barabasi_albert(n, 3, 29)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    extra = np.random.default_rng(5).choice(np.arange(1, n), 400, replace=False)
+    rp, ci = synth.csr_from_edges(n, np.concatenate([rows, np.zeros(400, dtype=np.int64)]),
+                                  np.concatenate([ci, extra]))
+    assert np.diff(rp).max() > 256
+    A = walks.adjacency(n, rp, ci)
+    alpha = 0.5 / walks.spectral_radius(walks.linearisation(A, 1.0))
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float32, krylov_dim=30, method="lanczos", tol=1e-7)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
+    Om = synth.gaussian_block(n, M, seed=43)
+    compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
+
+
 def test_estimated_rho_and_components_limit(ctx, lib):
     print("[gpu] return_prob components limit, estimated rho", flush=True)
     blocks = []
