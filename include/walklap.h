@@ -404,7 +404,10 @@ wl_status wl_markov_gap(wl_op* op, int32_t outer_dim, uint64_t seed, double* lam
  * with the residual checked on the original system; other operators apply L itself.
  * FP32 Lanczos operators pad the blocks to Mp = 16 ceil(M / 16) columns (zero columns)
  * and evaluate every product as 16-column groups.  Memory: (1 + poles) blocks of
- * n x Mp plus four n x 2 Mp blocks.                                                   */
+ * n x Mp plus four n x 2 Mp blocks, and for 16-column groups their Lanczos bases
+ * ((K + 1) blocks of n x Mp); all of it stays with the operator for the next call (the
+ * largest sizes seen) and is freed by wl_op_destroy.  Calls on one operator must not
+ * overlap.                                                                             */
 typedef struct {
   int32_t npoles;      /* finite poles used (a conjugate pair counts two) */
   int32_t nblocks;     /* basis blocks: Omega's, one per real pole, two per pair */

@@ -1423,6 +1423,7 @@ wl_status wl_op_destroy(wl_op* op) {
     DeviceGuard dg(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
     amg_destroy(op);
+    rk_cache_destroy(op);
     delete op;
   }
   graph_release(g);

@@ -28,6 +28,35 @@
 
 #include "wl_internal.h"
 
+// Work buffers of wl_return_prob kept with the operator between calls: the basis and the
+// solve blocks (freeing device memory waits for the whole device), the pinned summary
+// slots, and the column-group runners with their Lanczos bases.
+struct RkCache {
+  DevBuf basis, wb, X, R, P, Q, V, dd, dsmall, part, sums, cg;
+  double* hsum = nullptr;  // pinned host: two slots of the COCG summary (4 doubles each)
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  wl_multi* groups_wide = nullptr;    // the operator on 2 Mp columns as 16-column groups
+  wl_multi* groups_narrow = nullptr;  // ... on Mp columns
+  int groups_mp = 0;                  // the padded width the groups were made for
+  void drop_groups() {
+    multi_groups_destroy(groups_wide);
+    multi_groups_destroy(groups_narrow);
+    groups_wide = groups_narrow = nullptr;
+    groups_mp = 0;
+  }
+  ~RkCache() {
+    drop_groups();
+    if (hsum) (void)hipHostFree(hsum);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+void rk_cache_destroy(wl_op* op) {
+  delete op->rk;
+  op->rk = nullptr;
+}
+
 namespace {
 
 constexpr int RK_MAXM = 32;       // columns of Omega (2M <= 64, the block-width limit)
@@ -516,26 +545,23 @@ int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RK
 
 template <typename T>
 struct RkWork {
-  wl_op* op;
-  wl_ctx* ctx;
-  int64_t n;
-  int M;
-  T* basis;          // nb_max blocks of n x M
-  int nb = 0;        // blocks in the basis
-  DevBuf dsmall;     // device doubles: Grams, coefficients
-  DevBuf part, sums;  // row-reduction partials and their sums
-  DevBuf cg;          // COCG state (CgState)
-  double* hsum = nullptr;      // pinned host: two slots of the COCG summary (4 doubles each)
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  wl_multi* groups_wide = nullptr;  // the operator on 2M columns as 16-column groups
-  wl_multi* groups_narrow = nullptr;  // ... on M columns
-  ~RkWork() {
-    multi_groups_destroy(groups_wide);
-    multi_groups_destroy(groups_narrow);
-    if (hsum) (void)hipHostFree(hsum);
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
+  explicit RkWork(RkCache& c)
+      : dsmall(c.dsmall), part(c.part), sums(c.sums), cg(c.cg), hsum(c.hsum), ev(c.ev),
+        groups_wide(c.groups_wide), groups_narrow(c.groups_narrow) {}
+  wl_op* op = nullptr;
+  wl_ctx* ctx = nullptr;
+  int64_t n = 0;
+  int M = 0;
+  T* basis = nullptr;  // nb_max blocks of n x M
+  int nb = 0;          // blocks in the basis
+  // the operator's cached buffers (RkCache)
+  DevBuf& dsmall;      // device doubles: Grams, coefficients
+  DevBuf &part, &sums;  // row-reduction partials and their sums
+  DevBuf& cg;           // COCG state (CgState)
+  double*& hsum;        // pinned host: two slots of the COCG summary (4 doubles each)
+  hipEvent_t (&ev)[2];
+  wl_multi*& groups_wide;    // the operator on 2M columns as 16-column groups
+  wl_multi*& groups_narrow;  // ... on M columns
 };
 
 // Device sums of K values from the row-reduction partials (no host copy).
@@ -549,10 +575,9 @@ void rk_finish(RkWork<T>& W, int K) {
 // event recorded); rk_cg_read waits for slot k and returns {res_open, res_done, open, err}.
 template <typename T>
 wl_status rk_cg_post(RkWork<T>& W, int k) {
-  if (!W.hsum) {
-    WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&W.hsum), 8 * sizeof(double), hipHostMallocDefault));
-    for (auto& e : W.ev) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  }
+  if (!W.hsum) WL_HIP(hipHostMalloc(reinterpret_cast<void**>(&W.hsum), 8 * sizeof(double), hipHostMallocDefault));
+  for (auto& e : W.ev)
+    if (!e) WL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const CgState* st = W.cg.template as<CgState>();
   WL_HIP(hipMemcpyAsync(W.hsum + 4 * k, &st->res_open, 4 * sizeof(double), hipMemcpyDeviceToHost, W.ctx->stream));
   WL_HIP(hipEventRecord(W.ev[k], W.ctx->stream));
@@ -842,6 +867,8 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   const int64_t n = g->n;
   using cd = std::complex<double>;
   WL_TRY(ensure_w<T>(op));
+  if (!op->rk) op->rk = new RkCache;
+  RkCache& C = *op->rk;
   // work: sparse products times the probe columns they act on (a walk-Laplacian
   // product on b columns is op->K products: Lanczos steps or series degree)
   double products = 0.0;
@@ -853,7 +880,7 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
     double a, b0, b1;
     lanczos_params(op, &a, &b0, &b1);
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
-    DevBuf part;
+    DevBuf& part = C.sums;
     WL_TRY(part.ensure((size_t)nb * sizeof(double)));
     k_rk_vmax<T><<<nb, 256, 0, ctx->stream>>>(n, op->w.template as<T>(), part.as<double>());
     WL_HIP(hipGetLastError());
@@ -904,19 +931,21 @@ wl_status return_prob_impl(wl_op* op, const T* Om, int M, const double* ts, int 
   // with the square of the width)
   const bool grouped = op->d.prec == WL_FP32 && op->d.method == WL_M_LANCZOS;
   const int Mp = grouped ? (M + 15) / 16 * 16 : M;
-  RkWork<T> W;
+  RkWork<T> W(C);
   W.op = op;
   W.ctx = ctx;
   W.n = n;
   W.M = Mp;
-  if (grouped) {
-    WL_TRY(multi_groups_create(op, 2 * Mp / 16, &W.groups_wide));
-    WL_TRY(multi_groups_create(op, Mp / 16, &W.groups_narrow));
+  if (grouped && C.groups_mp != Mp) {  // made once per padded width, kept with the operator
+    C.drop_groups();
+    WL_TRY(multi_groups_create(op, 2 * Mp / 16, &C.groups_wide));
+    WL_TRY(multi_groups_create(op, Mp / 16, &C.groups_narrow));
+    C.groups_mp = Mp;
   }
   // resolvents: shifted solves on the symmetrised system (one sparse product per
   // iteration); other operators: COCG with the walk-Laplacian product itself
   const bool flat = op->d.func == WL_F_RESOLVENT;
-  DevBuf basis, wb, X, R, P, Q, V, dd;
+  DevBuf &basis = C.basis, &wb = C.wb, &X = C.X, &R = C.R, &P = C.P, &Q = C.Q, &V = C.V, &dd = C.dd;
   const size_t blk = (size_t)n * Mp;
   WL_TRY(basis.ensure((size_t)nb_max * blk * sizeof(T)));
   WL_TRY(wb.ensure(blk * sizeof(T)));

@@ -194,7 +194,10 @@ struct wl_op {
   // whole device, which would serialise work on other streams)
   DevBuf mk_rw, mk_tmp, mk_alt, mk_x0, mk_t1, mk_t2, mk_dd;
   struct AmgState* amg = nullptr;  // WL_M_AMG_CG: multigrid hierarchy and CG work blocks
+  struct RkCache* rk = nullptr;    // return-probability work buffers, kept between calls
 };
+// Frees the operator's return-probability work buffers (with the stream drained).
+void rk_cache_destroy(wl_op* op);
 
 // ------------------------------------------------------------------ launch interfaces
 // SpMM epilogue (per row r, on the b columns of the current tile):

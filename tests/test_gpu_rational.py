@@ -156,6 +156,33 @@ def test_fp32_resolvent_long_rows(ctx, lib, M):
     compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
 
 
+def test_buffers_kept_between_calls(ctx, lib):
+    """The work buffers and the column-group runners stay with the operator between
+    calls: calls of different widths in a row on one operator (Mp = 32, 16, 32, 16)
+    give what a fresh operator gives, bit for bit."""
+    print("[gpu] return_prob buffers kept between calls", flush=True)
+    n = 1500
+    rp, ci, A = ba(n, 3, 17)
+    alpha = 0.5 / walks.spectral_radius(walks.linearisation(A, 1.0))
+    g = lib.Graph(ctx, rp, ci)
+
+    def make():
+        return lib.Operator(g, 1.0, "res", alpha, dtype=torch.float32, krylov_dim=30, method="lanczos", tol=1e-7)
+
+    ts = [0.0, 0.5, 5.0]
+    op = make()
+    for M in (20, 5, 24, 8):
+        Om = dev(synth.gaussian_block(n, M, seed=M), torch.float32)
+        p1, e1, _, i1 = op.return_prob(Om, ts, 10.0, rho=0.0, solve_tol=1e-6, max_iters=2000)
+        fresh = make()
+        p2, e2, _, i2 = fresh.return_prob(Om, ts, 10.0, rho=0.0, solve_tol=1e-6, max_iters=2000)
+        fresh.close()
+        assert i1["iters_total"] == i2["iters_total"]
+        np.testing.assert_array_equal(p1, p2)
+        np.testing.assert_array_equal(e1, e2)
+    op.close()
+
+
 def test_estimated_rho_and_components_limit(ctx, lib):
     print("[gpu] return_prob components limit, estimated rho", flush=True)
     blocks = []
