@@ -551,70 +551,125 @@ void host_chol_deflate(int M, const std::vector<double>& G, double tol, double r
 // ------------------------------------------------------------------ phi_1 of a general matrix
 namespace {
 
-// C = A B for m x m row-major matrices, rows split over host threads
-void matmul(int m, const double* A, const double* B, double* C) {
-  const int nth = std::max(1, std::min({16, (m + 31) / 32, (int)std::max(1u, std::thread::hardware_concurrency())}));
-  auto rows = [&](int r0, int r1) {
-    for (int i = r0; i < r1; ++i) {
-      double* c = C + (size_t)i * m;
-      std::fill(c, c + m, 0.0);
-      for (int k = 0; k < m; ++k) {
-        const double a = A[(size_t)i * m + k];
-        if (a == 0.0) continue;
-        const double* b = B + (size_t)k * m;
-        for (int j = 0; j < m; ++j) c[j] += a * b[j];
-      }
-    }
-  };
-  std::vector<std::thread> pool;
-  const int per = (m + nth - 1) / nth;
-  int started = 1;
-  try {
-    for (; started < nth; ++started)
-      pool.emplace_back(rows, std::min(m, started * per), std::min(m, (started + 1) * per));
-  } catch (...) {  // no thread to be had: the caller's thread takes the rest
+typedef double wl_v4d __attribute__((vector_size(32)));  // four doubles (GCC / Clang vector extension)
+
+// C = A B for m x m row-major matrices on rows [r0, r1): 4 x 8 register tiles, k in
+// blocks of 128 rows of B (which stay in cache while a thread's rows pass over them).
+#define WL_MATMUL_ROWS_BODY                                                                              \
+  constexpr int KB = 128;                                                                                \
+  for (int i = r0; i < r1; ++i) std::fill(C + (size_t)i * m, C + (size_t)i * m + m, 0.0);                 \
+  for (int k0 = 0; k0 < m; k0 += KB) {                                                                   \
+    const int k1 = std::min(m, k0 + KB);                                                                 \
+    for (int i = r0; i < r1; i += 4) {                                                                   \
+      const int ni = std::min(4, r1 - i);                                                                \
+      for (int j = 0; j < m; j += 8) {                                                                   \
+        const int nj = std::min(8, m - j);                                                               \
+        if (ni == 4 && nj == 8) { /* eight 4-wide accumulators in registers */                            \
+          const double* a0 = A + (size_t)i * m;                                                          \
+          wl_v4d c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00, c20 = c00, c21 = c00, c30 = c00,      \
+                 c31 = c00;                                                                              \
+          for (int k = k0; k < k1; ++k) {                                                                \
+            const double* b = B + (size_t)k * m + j;                                                     \
+            wl_v4d b0, b1;                                                                               \
+            __builtin_memcpy(&b0, b, sizeof(b0));                                                        \
+            __builtin_memcpy(&b1, b + 4, sizeof(b1));                                                    \
+            const double x0 = a0[k], x1 = a0[m + k], x2 = a0[2 * (size_t)m + k], x3 = a0[3 * (size_t)m + k]; \
+            c00 += x0 * b0;                                                                              \
+            c01 += x0 * b1;                                                                              \
+            c10 += x1 * b0;                                                                              \
+            c11 += x1 * b1;                                                                              \
+            c20 += x2 * b0;                                                                              \
+            c21 += x2 * b1;                                                                              \
+            c30 += x3 * b0;                                                                              \
+            c31 += x3 * b1;                                                                              \
+          }                                                                                              \
+          const wl_v4d cs[4][2] = {{c00, c01}, {c10, c11}, {c20, c21}, {c30, c31}};                      \
+          for (int ii = 0; ii < 4; ++ii) {                                                               \
+            double* cr = C + (size_t)(i + ii) * m + j;                                                   \
+            for (int jj = 0; jj < 8; ++jj) cr[jj] += cs[ii][jj >> 2][jj & 3];                            \
+          }                                                                                              \
+        } else {                                                                                         \
+          for (int ii = 0; ii < ni; ++ii)                                                                \
+            for (int k = k0; k < k1; ++k) {                                                              \
+              const double x = A[(size_t)(i + ii) * m + k];                                              \
+              for (int jj = 0; jj < nj; ++jj) C[(size_t)(i + ii) * m + j + jj] += x * B[(size_t)k * m + j + jj]; \
+            }                                                                                            \
+        }                                                                                                \
+      }                                                                                                  \
+    }                                                                                                    \
   }
-  rows(0, std::min(m, per));
-  for (auto& th : pool) th.join();
-  if (started < nth) rows(std::min(m, started * per), m);
+
+// P <- (L U)^{-1} Pi P on columns [c0, c1) (P m x m row-major): the recorded row swaps,
+// then the unit lower triangle L and the upper triangle U of the factored Q, row by row
+// (each row of P takes the earlier rows' multiples, reading a row of Q at a time).
+#define WL_LU_SOLVE_COLS_BODY                                                                            \
+  for (int k = 0; k < m; ++k)                                                                            \
+    if (piv[k] != k)                                                                                     \
+      for (int j = c0; j < c1; ++j) std::swap(P[(size_t)piv[k] * m + j], P[(size_t)k * m + j]);          \
+  for (int i = 1; i < m; ++i) {                                                                          \
+    double* pi = P + (size_t)i * m;                                                                      \
+    const double* qi = Q + (size_t)i * m;                                                                \
+    for (int k = 0; k < i; ++k) {                                                                        \
+      const double f = qi[k];                                                                            \
+      if (f == 0.0) continue;                                                                            \
+      const double* pk = P + (size_t)k * m;                                                              \
+      for (int j = c0; j < c1; ++j) pi[j] -= f * pk[j];                                                  \
+    }                                                                                                    \
+  }                                                                                                      \
+  for (int i = m - 1; i >= 0; --i) {                                                                     \
+    double* pi = P + (size_t)i * m;                                                                      \
+    const double* qi = Q + (size_t)i * m;                                                                \
+    for (int k = i + 1; k < m; ++k) {                                                                    \
+      const double f = qi[k];                                                                            \
+      if (f == 0.0) continue;                                                                            \
+      const double* pk = P + (size_t)k * m;                                                              \
+      for (int j = c0; j < c1; ++j) pi[j] -= f * pk[j];                                                  \
+    }                                                                                                    \
+    const double inv = 1.0 / qi[i];                                                                      \
+    for (int j = c0; j < c1; ++j) pi[j] *= inv;                                                          \
+  }
+
+void matmul_rows_base(int m, const double* A, const double* B, double* C, int r0, int r1) { WL_MATMUL_ROWS_BODY }
+void lu_solve_cols_base(int m, const double* Q, const int* piv, double* P, int c0, int c1) {
+  WL_LU_SOLVE_COLS_BODY
+}
+#if !defined(__HIP_DEVICE_COMPILE__) && (defined(__x86_64__) || defined(_M_X64))
+// the same code compiled for AVX2 with FMA, taken when the host has them
+__attribute__((target("avx2,fma"))) void matmul_rows_avx2(int m, const double* A, const double* B, double* C, int r0,
+                                                          int r1) {
+  WL_MATMUL_ROWS_BODY
+}
+__attribute__((target("avx2,fma"))) void lu_solve_cols_avx2(int m, const double* Q, const int* piv, double* P,
+                                                            int c0, int c1) {
+  WL_LU_SOLVE_COLS_BODY
+}
+bool host_has_avx2() {
+  static const bool yes = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+  return yes;
+}
+#endif
+#undef WL_MATMUL_ROWS_BODY
+#undef WL_LU_SOLVE_COLS_BODY
+
+void matmul_rows(int m, const double* A, const double* B, double* C, int r0, int r1) {
+#if !defined(__HIP_DEVICE_COMPILE__) && (defined(__x86_64__) || defined(_M_X64))
+  if (host_has_avx2()) return matmul_rows_avx2(m, A, B, C, r0, r1);
+#endif
+  matmul_rows_base(m, A, B, C, r0, r1);
 }
 
-// X = V^{-1} B (m x m) by LU with partial pivoting; nonzero if singular
-int lu_solve(int m, std::vector<double> V, std::vector<double>& B) {
-  std::vector<int> piv(m);
-  for (int k = 0; k < m; ++k) {
-    int p = k;
-    for (int i = k + 1; i < m; ++i)
-      if (std::fabs(V[(size_t)i * m + k]) > std::fabs(V[(size_t)p * m + k])) p = i;
-    if (V[(size_t)p * m + k] == 0.0) return 1;
-    if (p != k) {
-      for (int j = 0; j < m; ++j) std::swap(V[(size_t)p * m + j], V[(size_t)k * m + j]);
-      for (int j = 0; j < m; ++j) std::swap(B[(size_t)p * m + j], B[(size_t)k * m + j]);
-    }
-    const double inv = 1.0 / V[(size_t)k * m + k];
-    for (int i = k + 1; i < m; ++i) {
-      const double f = V[(size_t)i * m + k] * inv;
-      if (f == 0.0) continue;
-      V[(size_t)i * m + k] = f;
-      for (int j = k + 1; j < m; ++j) V[(size_t)i * m + j] -= f * V[(size_t)k * m + j];
-      for (int j = 0; j < m; ++j) B[(size_t)i * m + j] -= f * B[(size_t)k * m + j];
-    }
-  }
-  for (int k = m - 1; k >= 0; --k) {
-    const double inv = 1.0 / V[(size_t)k * m + k];
-    for (int j = 0; j < m; ++j) B[(size_t)k * m + j] *= inv;
-    for (int i = 0; i < k; ++i) {
-      const double f = V[(size_t)i * m + k];
-      if (f == 0.0) continue;
-      for (int j = 0; j < m; ++j) B[(size_t)i * m + j] -= f * B[(size_t)k * m + j];
-    }
-  }
-  return 0;
+void lu_solve_cols(int m, const double* Q, const int* piv, double* P, int c0, int c1) {
+#if !defined(__HIP_DEVICE_COMPILE__) && (defined(__x86_64__) || defined(_M_X64))
+  if (host_has_avx2()) return lu_solve_cols_avx2(m, Q, piv, P, c0, c1);
+#endif
+  lu_solve_cols_base(m, Q, piv, P, c0, c1);
 }
 
 // exp(A) by scaling and squaring with the [13/13] Pade approximant (Higham, SIAM J.
 // Matrix Anal. Appl. 26, 2005): s with ||A / 2^s||_1 <= theta_13, r_13 = (V - U)^{-1}
-// (V + U) from the even and odd parts, then s squarings.
+// (V + U) from the even and odd parts, then s squarings.  One team of host threads does
+// it all: the products by row ranges, the LU factorisation of V - U (partial pivoting)
+// by rows below the pivot, the triangular solves by column ranges of V + U.
 int dense_expm(int m, std::vector<double>& A) {
   static const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0, 1187353796428800.0,
                                129060195264000.0,   10559470521600.0,    670442572800.0,     33522128640.0,
@@ -633,32 +688,89 @@ int dense_expm(int m, std::vector<double>& A) {
   const double sc = std::ldexp(1.0, -sq);
   for (double& x : A) x *= sc;
   const size_t mm = (size_t)m * m;
-  std::vector<double> A2(mm), A4(mm), A6(mm), T1(mm), U(mm), V(mm);
-  matmul(m, A.data(), A.data(), A2.data());
-  matmul(m, A2.data(), A2.data(), A4.data());
-  matmul(m, A4.data(), A2.data(), A6.data());
-  for (size_t e = 0; e < mm; ++e) T1[e] = b[13] * A6[e] + b[11] * A4[e] + b[9] * A2[e];
-  matmul(m, A6.data(), T1.data(), U.data());
-  for (size_t e = 0; e < mm; ++e) U[e] += b[7] * A6[e] + b[5] * A4[e] + b[3] * A2[e];
-  for (int i = 0; i < m; ++i) U[(size_t)i * m + i] += b[1];
-  matmul(m, A.data(), U.data(), T1.data());  // U = A (...)
-  std::swap(U, T1);
-  for (size_t e = 0; e < mm; ++e) T1[e] = b[12] * A6[e] + b[10] * A4[e] + b[8] * A2[e];
-  matmul(m, A6.data(), T1.data(), V.data());
-  for (size_t e = 0; e < mm; ++e) V[e] += b[6] * A6[e] + b[4] * A4[e] + b[2] * A2[e];
-  for (int i = 0; i < m; ++i) V[(size_t)i * m + i] += b[0];
-  std::vector<double> P(mm), Q(mm);
-  for (size_t e = 0; e < mm; ++e) {
-    P[e] = V[e] + U[e];
-    Q[e] = V[e] - U[e];
-  }
-  if (lu_solve(m, Q, P)) return 1;
-  for (int k = 0; k < sq; ++k) {
-    matmul(m, P.data(), P.data(), T1.data());
-    std::swap(P, T1);
-  }
-  A.swap(P);
-  return 0;
+  std::vector<double> A2(mm), A4(mm), A6(mm), T1(mm), U(mm), V(mm), W(mm);
+  std::vector<int> piv(m);
+  std::atomic<int> singular{0};
+  SpinBarrier bar;
+  const int nth = m >= 96 ? host_threads(m / 32) : 1;
+  run_team(nth, bar, [&](int tid, int team) {
+    const int per = (m + team - 1) / team;
+    const int r0 = std::min(m, tid * per), r1 = std::min(m, r0 + per);
+    auto mul = [&](const double* X, const double* Y, double* Z) {
+      matmul_rows(m, X, Y, Z, r0, r1);
+      bar.wait();
+    };
+    auto rows = [&](auto f) {  // elementwise work on this thread's rows, then the barrier
+      for (int i = r0; i < r1; ++i) f(i);
+      bar.wait();
+    };
+    mul(A.data(), A.data(), A2.data());
+    mul(A2.data(), A2.data(), A4.data());
+    mul(A4.data(), A2.data(), A6.data());
+    rows([&](int i) {
+      for (size_t e = (size_t)i * m; e < (size_t)(i + 1) * m; ++e) T1[e] = b[13] * A6[e] + b[11] * A4[e] + b[9] * A2[e];
+    });
+    mul(A6.data(), T1.data(), W.data());
+    rows([&](int i) {
+      for (size_t e = (size_t)i * m; e < (size_t)(i + 1) * m; ++e) W[e] += b[7] * A6[e] + b[5] * A4[e] + b[3] * A2[e];
+      W[(size_t)i * m + i] += b[1];
+    });
+    mul(A.data(), W.data(), U.data());  // the odd part U = A (...)
+    rows([&](int i) {
+      for (size_t e = (size_t)i * m; e < (size_t)(i + 1) * m; ++e) T1[e] = b[12] * A6[e] + b[10] * A4[e] + b[8] * A2[e];
+    });
+    mul(A6.data(), T1.data(), V.data());
+    // P = V + U (into A2), Q = V - U (into A4)
+    rows([&](int i) {
+      for (size_t e = (size_t)i * m; e < (size_t)(i + 1) * m; ++e) {
+        const double v = V[e] + b[6] * A6[e] + b[4] * A4[e] + b[2] * A2[e] + (e == (size_t)i * m + i ? b[0] : 0.0);
+        A2[e] = v + U[e];
+        A4[e] = v - U[e];
+      }
+    });
+    double* P = A2.data();
+    double* Q = A4.data();
+    // Q = L U with partial pivoting, the row swaps recorded (rows swapped whole, so the
+    // multipliers move with them)
+    for (int k = 0; k < m; ++k) {
+      if (tid == 0) {
+        int p = k;
+        for (int i = k + 1; i < m; ++i)
+          if (std::fabs(Q[(size_t)i * m + k]) > std::fabs(Q[(size_t)p * m + k])) p = i;
+        piv[k] = p;
+        if (Q[(size_t)p * m + k] == 0.0) {
+          singular.store(1);
+        } else if (p != k) {
+          for (int j = 0; j < m; ++j) std::swap(Q[(size_t)p * m + j], Q[(size_t)k * m + j]);
+        }
+      }
+      bar.wait();
+      if (singular.load()) return;
+      const double inv = 1.0 / Q[(size_t)k * m + k];
+      const int rem = m - k - 1, per2 = (rem + team - 1) / team;
+      const int i0 = k + 1 + std::min(rem, tid * per2), i1 = k + 1 + std::min(rem, (tid + 1) * per2);
+      for (int i = i0; i < i1; ++i) {
+        const double f = Q[(size_t)i * m + k] * inv;
+        Q[(size_t)i * m + k] = f;
+        if (f == 0.0) continue;
+        for (int j = k + 1; j < m; ++j) Q[(size_t)i * m + j] -= f * Q[(size_t)k * m + j];
+      }
+      bar.wait();
+    }
+    // P <- Q^{-1} P on this thread's columns: the swaps, then L, then U
+    const int cper = (m + team - 1) / team;
+    const int c0 = std::min(m, tid * cper), c1 = std::min(m, c0 + cper);
+    if (c0 < c1) lu_solve_cols(m, Q, piv.data(), P, c0, c1);
+    bar.wait();
+    double* cur = P;
+    double* nxt = T1.data();
+    for (int k = 0; k < sq; ++k) {
+      mul(cur, cur, nxt);
+      std::swap(cur, nxt);
+    }
+    if (tid == 0) std::copy(cur, cur + mm, A.begin());
+  });
+  return singular.load() ? 1 : 0;
 }
 
 }  // namespace
