@@ -895,9 +895,18 @@ wl_status phi_recurrence(wl_op* op, const T* X, T* Y, int b, const T* wv, const 
 
 }  // namespace
 
+int expv_outer_steps(int outer_dim, int64_t n) {
+  // n steps always reach an invariant space (a rank-deficient U0 grows by its rank)
+  return (int)std::max<int64_t>(1, std::min<int64_t>(outer_dim, n));
+}
+
 int lanczos_steps(const wl_op* op, int64_t n, int b) {
-  // the block Krylov space has dimension <= n: more steps only add deflated blocks
-  return (int)std::max<int64_t>(1, std::min<int64_t>(op->K, (n + b - 1) / b + 1));
+  // The block Krylov space has dimension <= n and grows by at least one per step until
+  // it is invariant, so n + 1 steps always suffice; fewer would not: a block with
+  // deflated (zero or dependent) columns grows by its rank, not by b.  Steps after the
+  // space is exhausted are zero blocks (the coupling vanishes and the process stops).
+  (void)b;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(op->K, n + 1));
 }
 
 void lanczos_params(const wl_op* op, double* a, double* b0, double* b1) {
@@ -1011,7 +1020,7 @@ wl_status expv_impl(wl_op* op, const T* U0, int b, const double* t, int nt, T* c
                     double* err_est) {
   wl_graph* g = op->g;
   const int64_t n = g->n;
-  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(outer_dim, std::max<int64_t>(1, (n + b - 1) / b)));
+  const int K = expv_outer_steps(outer_dim, n);
   WL_TRY(op->outer_basis.ensure((size_t)(K + 1) * n * b * sizeof(T)));
   WL_TRY(op->outer_w.ensure((size_t)n * b * sizeof(T)));
   LanczosOp<T> L;
@@ -1675,7 +1684,7 @@ wl_status plan_call(wl_op* op, int call, int b, int outer_dim, WsPlan& pl) {
     case WL_CALL_EXPV: {
       WL_TRY(plan_w(op, pl));
       if (n == 0) return WL_OK;
-      const int K = (int)std::max<int64_t>(1, std::min<int64_t>(outer_dim, std::max<int64_t>(1, (n + b - 1) / b)));
+      const int K = expv_outer_steps(outer_dim, n);
       const size_t blk = (size_t)n * b * elem_size(op);
       pl.need(op->outer_basis, (size_t)(K + 1) * blk);
       pl.need(op->outer_w, blk);

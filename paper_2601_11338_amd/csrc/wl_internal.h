@@ -461,6 +461,8 @@ struct SmallLayout {
 
 // Block Lanczos steps used for an operator's evaluation at block width b.
 int lanczos_steps(const wl_op* op, int64_t n, int b);
+// Outer Lanczos steps of the diffusion for outer_dim requested on n rows.
+int expv_outer_steps(int outer_dim, int64_t n);
 // The symmetric matrix Lanczos runs on, as a A + (b0 + b1 D): A_mu(alpha) for the
 // resolvent, A for the exponential (mu = 0).
 void lanczos_params(const wl_op* op, double* a, double* b0, double* b1);

@@ -86,3 +86,36 @@ def test_resolvent_lanczos_same_k_reference(lib, rmat16):
     print(f"[gpu] resolvent: FP32 vs same-K FP64 {err:.2e} (max node / w {node:.2e}); method error {meth:.2e}",
           flush=True)
     assert err < 2e-5 and node < 1e-4
+
+
+@pytest.mark.parametrize("K", [8, 16, 30])
+def test_rank_deficient_block_same_k(lib, K):
+    """A start block of rank 4 in 16 columns (12 zero columns) on a small graph with
+    many components (a 9 x 11 lattice with edges kept w.p. 0.35: isolated nodes and
+    small pieces, n = 99): the block Krylov space grows by 4 per step, so K steps are
+    K steps here too (the step count is capped by n + 1, not by n / b + 1, which would
+    stop at 8 and leave a 1e-2 error at any requested K).  phi X of the resolvent
+    (mu = 1) in FP64 against the oracle's same-K block Lanczos on the rank-4 block."""
+    print(f"[gpu] rank-deficient start block, same-K reference K={K}", flush=True)
+    rp, ci = synth.road_grid(9, 11, 0.35, seed=11)
+    n = len(rp) - 1
+    As = sparse.adjacency(n, rp, ci)
+    from oracle import genfun, walks
+    Ad = walks.adjacency(n, rp, ci)
+    alpha = 0.5 / walks.spectral_radius(walks.linearisation(Ad, 1.0))
+    X = synth.gaussian_block(n, 16, seed=5)
+    X[:, 4:] = 0.0
+    ctx = lib.Context(0)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float64, krylov_dim=K, method="lanczos", tol=1e-14)
+    Y = op.apply_phi(torch.tensor(X, dtype=torch.float64, device="cuda")).cpu().numpy()
+    ref = krylov.phi_resolvent_lanczos(As, 1.0, alpha, X[:, :4].copy(), K)
+    exact = genfun.phi(Ad, 1.0, "res", alpha) @ X[:, :4]
+    scale = np.abs(exact).max()
+    err_ref = np.abs(Y[:, :4] - ref).max() / scale
+    err_exact = np.abs(Y[:, :4] - exact).max() / scale
+    print(f"[gpu]   vs same-K {err_ref:.2e}, vs exact {err_exact:.2e}", flush=True)
+    assert err_ref < 1e-10, err_ref
+    assert np.abs(Y[:, 4:]).max() == 0.0
+    if K == 30:
+        assert err_exact < 1e-12, err_exact

@@ -135,6 +135,27 @@ def test_fp32_resolvent_road_one_pass(ctx, lib):
     compare(lib, op, Lap, Om, [0.0, 0.5, 5.0, 50.0], 50.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
 
 
+@pytest.mark.parametrize("nx,ny,keep,M", [(9, 11, 0.7, 4), (9, 11, 0.35, 4), (12, 12, 0.5, 6)])
+def test_fp32_resolvent_small_one_pass(ctx, lib, nx, ny, keep, M):
+    """The one-pass solve product on small lattices: fewer rows than the grid's row groups,
+    some XCD row ranges short or empty, isolated nodes (keep 0.35 and 0.5), against the
+    oracle from the library's poles.  The basis (10 blocks of M) stays below n, where the
+    oracle's basis (no deflation) is well defined.  The blocks are padded to 16 columns,
+    so the projection's Lanczos runs start from rank-deficient blocks: this case found
+    that the step count was capped for full-rank blocks (n / 16 + 1 steps, 8 here)."""
+    print(f"[gpu] return_prob fp32 res one-pass product, lattice {nx}x{ny} keep {keep} M={M}", flush=True)
+    rp, ci = synth.road_grid(nx, ny, keep, seed=11)
+    n = len(rp) - 1
+    A = walks.adjacency(n, rp, ci)
+    alpha = 0.5 / max(walks.spectral_radius(walks.linearisation(A, 1.0)), 1e-3)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 1.0, "res", alpha, dtype=torch.float32, krylov_dim=30, method="lanczos", tol=1e-7)
+    Lap = laplacian.walk_laplacian(genfun.phi(A, 1.0, "res", alpha))
+    Om = synth.gaussian_block(n, M, seed=5)
+    _, _, _, info = compare(lib, op, Lap, Om, [0.0, 0.5, 5.0], 5.0, torch.float32, 2e-4, 2e-3, solve_tol=1e-6)
+    assert info["nblocks"] * M < n
+
+
 @pytest.mark.parametrize("M", [8, 30])
 def test_fp32_resolvent_long_rows(ctx, lib, M):
     """A node joined to 400 others (above the one-pass product's row limit of 256): the
