@@ -188,3 +188,39 @@ def test_batch_diffusion_on_hub_graphs(lib):
             (ref,) = laplacian.expv(laplacian.walk_laplacian(ph), om, [t])
             err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref)
             assert err < 1e-4, (t, i, err)
+
+
+def test_batch_diffusion_on_disconnected_small_graphs(ctx, lib):
+    """Small graphs with many components (lattices with edges kept w.p. 0.35 or 0.5:
+    isolated nodes and small pieces) and one block with dependent columns: each graph's
+    Krylov space stops growing by b per step as its components fill up, so the step at
+    which the space is complete is not ceil(n / b).  exp(-t L) U0 against the dense
+    oracle."""
+    print("[gpu] batched diffusion on disconnected small graphs", flush=True)
+    specs = [(9, 11, 0.35, 11), (12, 12, 0.5, 12), (8, 8, 0.35, 13), (10, 10, 0.9, 14)]
+    graphs, descs, phis, Oms = [], [], [], []
+    for i, (nx, ny, keep, seed) in enumerate(specs):
+        rp, ci = synth.road_grid(nx, ny, keep, seed=seed)
+        n = len(rp) - 1
+        mu, kind = (1.0, "res") if i % 2 == 0 else (0.5, "exp")
+        A = walks.adjacency(n, rp, ci)
+        if kind == "exp":
+            param = 1.0 / max(np.linalg.eigvalsh(A)[-1], 1e-12)
+        else:
+            param = 0.5 / max(walks.spectral_radius(walks.linearisation(A, mu)), 1e-3)
+        graphs.append(lib.Graph(ctx, rp, ci, validate=True))
+        descs.append({"mu": mu, "func": kind, "param": param})
+        phis.append(genfun.phi(A, mu, kind, param))
+        om = philox.gaussian(n, 8, 200 + i).astype(np.float32).astype(np.float64)
+        if i == 3:
+            om[:, 4:] = om[:, :4]  # dependent columns: rank 4
+        Oms.append(om)
+    batch = lib.Batch(ctx, graphs, descs, tol=1e-12)
+    U0 = batch.pack([torch.tensor(o, dtype=torch.float32, device="cuda") for o in Oms])
+    ts = [1.0, 0.5, 5.0, 2.0]
+    Y, _, _ = batch.expv(U0, ts, outer_dim=30)
+    for i, (ph, om, y, t) in enumerate(zip(phis, Oms, batch.unpack(Y), ts)):
+        (ref,) = laplacian.expv(laplacian.walk_laplacian(ph), om, [t])
+        err = np.linalg.norm(y.cpu().numpy().astype(np.float64) - ref) / np.linalg.norm(ref)
+        print(f"[gpu]   graph {i} n={ph.shape[0]}: relative error {err:.2e}", flush=True)
+        assert err < 1e-4, (i, err)
