@@ -119,3 +119,30 @@ def test_rank_deficient_block_same_k(lib, K):
     assert np.abs(Y[:, 4:]).max() == 0.0
     if K == 30:
         assert err_exact < 1e-12, err_exact
+
+
+def test_rank_deficient_diffusion_outer_steps(lib):
+    """exp(-t L) U0 with U0 of rank 2 in 8 columns on the same 99-node lattice: the outer
+    Lanczos space grows by 2 per step, so 60 steps (120 > n) reach an invariant space and
+    the result is exact to rounding.  (Its former cap of ceil(n / b) = 13 steps held it
+    to 26 dimensions.)  FP64, against the dense exponential of the dense walk Laplacian."""
+    print("[gpu] rank-2 diffusion start block, outer steps", flush=True)
+    from oracle import genfun, laplacian, walks
+    import scipy.linalg as sla
+    rp, ci = synth.road_grid(9, 11, 0.35, seed=11)
+    n = len(rp) - 1
+    Ad = walks.adjacency(n, rp, ci)
+    beta = 1.0 / np.linalg.eigvalsh(Ad)[-1]
+    L = laplacian.walk_laplacian(genfun.phi(Ad, 0.5, "exp", beta))
+    G = synth.gaussian_block(n, 2, seed=7)
+    U0 = np.concatenate([G, G @ np.array([[1.0, 2.0, 0.5, 0.0, 1.0, -1.0], [1.0, -1.0, 3.0, 0.0, 0.0, 2.0]])], axis=1)
+    ctx = lib.Context(0)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.5, "exp", beta, dtype=torch.float64, tol=1e-14)
+    ts = [0.5, 5.0]
+    outs, _ = op.expv(torch.tensor(U0, dtype=torch.float64, device="cuda"), ts, outer_dim=60)
+    for t, y in zip(ts, outs):
+        ref = sla.expm(-t * L) @ U0
+        err = np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(f"[gpu]   t={t}: relative error {err:.2e}", flush=True)
+        assert err < 1e-9, (t, err)
