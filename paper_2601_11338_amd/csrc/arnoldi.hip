@@ -117,8 +117,10 @@ wl_status phi_arnoldi(wl_op* op, const T* X, T* Y, int b, const T* wv, const T* 
   wl_ctx* ctx = g->ctx;
   const int64_t n = g->n;
   const double mu = op->d.mu, beta = op->d.param;
-  // the Krylov space of Z has dimension <= 2n
-  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(op->K, (2 * n) / b - 1));
+  // the Krylov space of Z has dimension <= 2n and grows by at least one per step until
+  // it is invariant (a start block of lower rank grows by its rank, not by b); the loop
+  // stops at the first vanished coupling
+  const int K = (int)std::max<int64_t>(1, std::min<int64_t>(op->K, 2 * n));
   const int64_t blk2 = 2 * n * b;
   WL_TRY(op->basis.ensure((size_t)(K + 1) * blk2 * sizeof(T)));
   WL_TRY(op->wbuf.ensure((size_t)blk2 * sizeof(T)));

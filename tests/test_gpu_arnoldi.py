@@ -85,6 +85,22 @@ def test_full_space_is_exact(ctx, lib):
     assert rel(Y, genfun.phi(A, 1.0, "exp", 0.8) @ X) < 1e-11
 
 
+def test_rank_deficient_block_reaches_full_space(ctx, lib):
+    """A start block of rank 2 in 6 columns on a 40-node graph with several components: the
+    space of Z grows by 2 per step, so the step count may not stop at 2n / b (13 here);
+    with 50 steps it reaches an invariant space and phi X is exact to rounding."""
+    print("[gpu] arnoldi rank-deficient start block", flush=True)
+    rp, ci = synth.road_grid(5, 8, 0.5, seed=3)
+    n = len(rp) - 1
+    A = walks.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    op = lib.Operator(g, 0.5, "exp", 0.8, dtype=torch.float64, krylov_dim=50, method="arnoldi")
+    G = synth.gaussian_block(n, 2, seed=4)
+    X = np.concatenate([G, G @ np.array([[1.0, 0.5, -2.0, 0.0], [1.0, 3.0, 1.0, 0.0]])], axis=1)
+    Y = host(op.apply_phi(dev(X, torch.float64)))
+    assert rel(Y, genfun.phi(A, 0.5, "exp", 0.8) @ X) < 1e-11
+
+
 def test_fp32_ba_against_sparse_series(ctx, lib):
     print("[gpu] arnoldi fp32 BA n=4000 b=16", flush=True)
     n = 4000
