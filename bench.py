@@ -295,6 +295,27 @@ def measured_traffic(n, m, width, lanes):
     return rec["traffic_bytes_per_launch"]
 
 
+def traffic_record(name, lanes=None):
+    """HBM bytes per launch of a workload's dominant kernel from its committed counter
+    record (profiles/<name>_traffic.json: FETCH_SIZE / WRITE_SIZE of one run of the
+    workload, scaled by the copy-kernel calibration); None when there is no record, the
+    kernel source changed since the counters were taken, or (lanes given) the autotuner
+    picked another launch shape."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
+    src = os.path.join(ROOT, "paper_2601_11338_amd", "csrc", "spmm.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if sha != rec.get("source_sha1"):
+        return None
+    if lanes is not None and rec.get("lanes_per_row") is not None and rec["lanes_per_row"] != lanes:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(rp, ci, n, lam, X, K):
     """The oracle (sparse FP64 series, eq. qrec) on a bounded sample of the step:
     one of the ten operators (mu = 0.5, exponential), degree K, on 1 + b columns."""
@@ -444,7 +465,7 @@ def run_batch512(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_record("k_spmm_b8_batch512"),
             "kernel": "k_spmm batched recurrence step (b=8, per-graph coefficient table)",
             "avg_launch_us": kms / max(launches, 1) * 1e3,
             "alg_bytes_per_launch": alg / max(launches, 1),
@@ -592,7 +613,7 @@ def run_expv_rmat25(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_record("k_spmm_w32_expv_rmat25", g.shape(torch.float32, 32)[0]),
             "kernel": "k_spmm fused recurrence step (b=32)",
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
@@ -867,7 +888,8 @@ def run_arp_road2m(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom["achieved"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_record("k_spmm_w32_arp_road2m", g.shape(torch.float32, 32)[0])
+                       if dom["what"].startswith("grouped") else None,
             "kernel": dom["what"],
             "avg_launch_us": dom["avg_launch_us"],
             "alg_bytes_per_launch": dom["alg_bytes_per_launch"],
@@ -1315,7 +1337,7 @@ def run_amg_road2m(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_record("k_spmm_fp64_w16_amg_road2m", g.shape(torch.float64, b)[0]),
             "kernel": "k_spmm<double,2,8,*> finest-level products of the PCG (A_mu p, residual, l1-Jacobi sweep)",
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
