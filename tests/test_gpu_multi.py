@@ -256,3 +256,30 @@ def test_multi_lanczos_nine_single_columns_fall_back(ctx, lib):
         w = genfun.phi(A, mu, "res", _res_alpha(g, mu, lam)).sum(1)
         assert np.linalg.norm(W[:, i] - w) < 1e-8 * np.linalg.norm(w), mu
         np.testing.assert_allclose(W[:, i], host(op.fdeg()), rtol=0, atol=1e-13 * np.abs(w).max())
+
+
+def test_multi_lanczos_rank_deficient_block_small_graph(ctx, lib):
+    """A start block of rank 4 in 16 columns on a 99-node lattice with many components
+    (edges kept w.p. 0.35), FP64, resolvent (mu = 1) and exponential (mu = 0) side by side
+    with 30 steps:
+    the block Krylov space grows by 4 per step, so the runs must not stop at the full-rank
+    step count n / 16 + 1 (8); phi X against the dense phi to 1e-10."""
+    print("[gpu] multi lanczos rank-deficient block on a small disconnected graph", flush=True)
+    rp, ci = synth.road_grid(9, 11, 0.35, seed=11)
+    n = len(rp) - 1
+    As = sparse.adjacency(n, rp, ci)
+    g = lib.Graph(ctx, rp, ci)
+    lam = g.lambda_max()
+    specs = [(1.0, "res", 0.5 / g.spectral_radius(1.0)), (0.0, "exp", 1.0 / lam)]
+    ops = [lib.Operator(g, mu, f, p, dtype=torch.float64, krylov_dim=30, method="lanczos", tol=1e-14)
+           for mu, f, p in specs]
+    multi = lib.Multi(ops)
+    X = synth.gaussian_block(n, 16, 31)
+    X[:, 4:] = X[:, :4] @ np.random.default_rng(3).standard_normal((4, 12))
+    PX = host(multi.apply_phi(dev(X, torch.float64)))
+    for i, (mu, f, p) in enumerate(specs):
+        pr = sparse.phi_apply(As, mu, f, p, X)
+        cols = slice(16 * i, 16 * (i + 1))
+        err = np.linalg.norm(PX[:, cols] - pr) / np.linalg.norm(pr)
+        print(f"[gpu]   {f} mu={mu}: relative error {err:.2e}", flush=True)
+        assert err < 1e-10, (mu, f, err)
