@@ -260,10 +260,10 @@ def test_multi_lanczos_nine_single_columns_fall_back(ctx, lib):
 
 def test_multi_lanczos_rank_deficient_block_small_graph(ctx, lib):
     """A start block of rank 4 in 16 columns on a 99-node lattice with many components
-    (edges kept w.p. 0.35), FP64, resolvent (mu = 1) and exponential (mu = 0) side by side
-    with 30 steps:
-    the block Krylov space grows by 4 per step, so the runs must not stop at the full-rank
-    step count n / 16 + 1 (8); phi X against the dense phi to 1e-10."""
+    (edges kept w.p. 0.35), FP64, resolvent (mu = 1) and exponential (mu = 0) side by
+    side with 30 steps: the block Krylov space grows by 4 per step, so the runs must not
+    stop at the full-rank step count n / 16 + 1 (8); phi X against the dense phi to
+    1e-10."""
     print("[gpu] multi lanczos rank-deficient block on a small disconnected graph", flush=True)
     rp, ci = synth.road_grid(9, 11, 0.35, seed=11)
     n = len(rp) - 1
