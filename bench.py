@@ -56,7 +56,7 @@ def parse():
                         "walk degrees as single-column processes on three streams (pairs), or all five with "
                         "their walk degrees in one 96-wide block (packed)")
     p.add_argument("--shapes", default="",
-                   help="ba1m: fixed sparse-product launch shapes width:lanes:threshold,... instead of autotuning "
+                   help="ba1m, markov-ba1m: fixed sparse-product launch shapes width:lanes:threshold,... instead of autotuning "
                         "(e.g. to take hardware counters on the shapes a timed run chose)")
     p.add_argument("--streams", type=int, default=4,
                    help="ba1m: independent operator groups run concurrently on this many streams (one library "
@@ -669,8 +669,15 @@ def run_markov_ba1m(args):
     P0_h = synth.spike_block(n, starts, dtype=np.float32)
     ctx = wl.Context(0)
     g = wl.Graph(ctx, rp, ci, validate=True)
-    for w_ in (b, 1):
-        g.autotune(torch.float32, w_)
+    if args.shapes:
+        for item in args.shapes.split(","):
+            w_, l_, t_ = (int(x) for x in item.split(":"))
+            g.set_shape(torch.float32, w_, l_, t_)
+    else:
+        for w_ in (b, 1):
+            g.autotune(torch.float32, w_)
+    log("launch shapes width:lanes:threshold " +
+        ",".join(f"{w_}:{g.shape(torch.float32, w_)[0]}:{g.shape(torch.float32, w_)[1]}" for w_ in (b, 1)))
     lam = g.lambda_max()
     op = wl.Operator(g, 1.0, "exp", 1.0 / lam, dtype=torch.float32, tol=1e-9)
     K_in, _ = op.info()
@@ -743,7 +750,7 @@ def run_markov_ba1m(args):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_record("k_spmm_w16_markov_ba1m", g.shape(torch.float32, b)[0]),
             "kernel": f"k_spmm fused recurrence step (b={b})",
             "avg_launch_us": avg_ms * 1e3,
             "alg_bytes_per_launch": kbytes / max(launches, 1),
