@@ -11,8 +11,9 @@
 //   4. shifted solves: COCG (conjugate orthogonal CG for complex symmetric systems)
 //      column by column, the M complex columns held as one n x 2M real block
 //      [Re | Im]; for a resolvent operator on its symmetrised form, one sparse product
-//      with A_mu(alpha) per iteration (see k_fl_sqrt), otherwise one walk-Laplacian
-//      product on 2M columns per iteration;
+//      with A_mu(alpha) per iteration (see k_fl_sqrt; on graphs without long rows the
+//      product, the shift and the p^T q sums are one kernel, k_fl_product), otherwise
+//      one walk-Laplacian product on 2M columns per iteration;
 //   5. projection: T = V^T L V (the Rayleigh quotient; with exact solves it equals the
 //      reduced pencil Hhat Khat^{-1} of a pole sequence closed by infinity);
 //   6. per time t, on the host from T's eigendecomposition T = S diag(lam) S^T and
