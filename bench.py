@@ -316,6 +316,14 @@ def traffic_record(name, lanes=None):
     return rec["traffic_bytes_per_launch"]
 
 
+def with_nproc(out):
+    """The host's CPU count beside the CPU baseline's thread count (cores)."""
+    cb = out.get("cpu_baseline")
+    if isinstance(cb, dict):
+        cb.setdefault("nproc", os.cpu_count())
+    return out
+
+
 def cpu_baseline(rp, ci, n, lam, X, K):
     """The oracle (sparse FP64 series, eq. qrec) on a bounded sample of the step:
     one of the ten operators (mu = 0.5, exponential), degree K, on 1 + b columns."""
@@ -1689,25 +1697,25 @@ def main():
         gather_ceiling()
         return
     if args.workload == "batch512":
-        print(json.dumps(run_batch512(args)), flush=True)
+        print(json.dumps(with_nproc(run_batch512(args))), flush=True)
         return
     if args.workload == "cv-rmat22":
-        print(json.dumps(run_cv_rmat22(args)), flush=True)
+        print(json.dumps(with_nproc(run_cv_rmat22(args))), flush=True)
         return
     if args.workload == "expv-rmat25":
-        print(json.dumps(run_expv_rmat25(args)), flush=True)
+        print(json.dumps(with_nproc(run_expv_rmat25(args))), flush=True)
         return
     if args.workload == "markov-ba1m":
-        print(json.dumps(run_markov_ba1m(args)), flush=True)
+        print(json.dumps(with_nproc(run_markov_ba1m(args))), flush=True)
         return
     if args.workload == "arp-road2m":
-        print(json.dumps(run_arp_road2m(args)), flush=True)
+        print(json.dumps(with_nproc(run_arp_road2m(args))), flush=True)
         return
     if args.workload == "arnoldi-ba1m":
-        print(json.dumps(run_arnoldi_ba1m(args)), flush=True)
+        print(json.dumps(with_nproc(run_arnoldi_ba1m(args))), flush=True)
         return
     if args.workload == "amg-road2m":
-        print(json.dumps(run_amg_road2m(args)), flush=True)
+        print(json.dumps(with_nproc(run_amg_road2m(args))), flush=True)
         return
     import numpy as np
     import torch
